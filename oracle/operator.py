@@ -1,0 +1,79 @@
+"""The matrix-free operator and the quantities derived from X alone.
+
+The system is the paper's regularized normal equations
+(X^T X + lam I) w = X^T y; Krylov methods only need v -> A v (the
+introduction: only the matrix-vector product is required, X^T X is never
+formed).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+from .splitmix64 import SplitMix64
+
+
+def apply_A(X, lam: float, v: np.ndarray) -> np.ndarray:
+    """A v = X^T (X v) + lam v in FP64 (two sparse or dense products)."""
+    v = np.asarray(v, dtype=np.float64)
+    return np.asarray(X.T @ (X @ v), dtype=np.float64) + lam * v
+
+
+def rhs(X, y: np.ndarray) -> np.ndarray:
+    """b = X^T y."""
+    return np.asarray(X.T @ np.asarray(y, dtype=np.float64), dtype=np.float64)
+
+
+def column_sq_norms(X) -> np.ndarray:
+    """c_j = ||x_j||^2, the diagonal of X^T X."""
+    if sp.issparse(X):
+        Xc = X.tocsc()
+        return np.asarray(Xc.multiply(Xc).sum(axis=0), dtype=np.float64).ravel()
+    Xd = np.asarray(X, dtype=np.float64)
+    return np.einsum("ij,ij->j", Xd, Xd)
+
+
+def jacobi_diagonal(X, lam: float) -> np.ndarray:
+    """D = diag(A) = ||x_j||^2 + lam (the diagonal preconditioner of DCG)."""
+    return column_sq_norms(X) + lam
+
+
+def is_nonnegative(X) -> bool:
+    data = X.data if sp.issparse(X) else np.asarray(X)
+    return bool(data.size == 0 or data.min() >= 0)
+
+
+def gershgorin_row_sums(X) -> np.ndarray:
+    """g = X^T (X 1): the row sums of X^T X, which equal its absolute row
+    sums when X >= 0 entrywise."""
+    ones = np.ones(X.shape[1])
+    return np.asarray(X.T @ (X @ ones), dtype=np.float64)
+
+
+def omega_gershgorin(X, lam: float) -> float:
+    """Smoother weight for X >= 0: omega = 1 / rho_hat with
+    rho_hat = max_j (g_j + lam) / D_j >= rho(D^-1 A) (Gershgorin's theorem
+    applied to the rows of D^-1 A, all of whose entries are >= 0)."""
+    if not is_nonnegative(X):
+        raise ValueError("Gershgorin weight needs X >= 0; use omega_power")
+    g = gershgorin_row_sums(X)
+    D = jacobi_diagonal(X, lam)
+    return 1.0 / float(np.max((g + lam) / D))
+
+
+def omega_power(X, lam: float, seed: int, iters: int = 30, safety: float = 1.1) -> float:
+    """Smoother weight for general X: omega = 1 / (safety * rho_est), where
+    rho_est is the norm ratio after ``iters`` power iterations on
+    D^-1/2 A D^-1/2 from a SplitMix64(seed) start vector with entries in
+    [0.5, 1.5)."""
+    D = jacobi_diagonal(X, lam)
+    s = 1.0 / np.sqrt(D)
+    rng = SplitMix64(seed)
+    v = np.array([rng.next_unit() + 0.5 for _ in range(X.shape[1])])
+    v /= np.linalg.norm(v)
+    rho = 0.0
+    for _ in range(iters):
+        w = s * apply_A(X, lam, s * v)
+        rho = float(np.linalg.norm(w))
+        v = w / rho
+    return 1.0 / (safety * rho)

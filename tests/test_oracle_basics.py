@@ -1,0 +1,195 @@
+"""Pins for the oracle's generator, operator, smoother weight and coarse
+level: checked against published test vectors, brute force, closed forms and
+invariants, never against the oracle itself."""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+import datagen
+from oracle import SplitMix64, coarse, operator as op
+from tests.conftest import read_golden
+
+
+def test_splitmix64_published_vectors():
+    rows = read_golden("splitmix64.txt")
+    assert rows[0] == ["seed", "1234567"]
+    r = SplitMix64(1234567)
+    for tok in rows[1:6]:
+        assert r.next() == int(tok[0])
+    assert rows[6][0] == "buckets"
+    seed, n = int(rows[6][1]), int(rows[6][2])
+    r = SplitMix64(seed)
+    counts = [0] * 5
+    for _ in range(n):
+        counts[int(r.next_unit() * 5)] += 1
+    assert counts == [int(t) for t in rows[7]]
+
+
+def _tiny_binary(seed, n=40, f=17, m=4):
+    return datagen.zipf_binary_csr(n, f, m, 1.1, seed)
+
+
+def test_operator_exact_on_integers_brute_force():
+    """Binary X, integer v, integer lam: every intermediate is an integer,
+    so A v must equal a Python-int brute force exactly."""
+    X = _tiny_binary(1)
+    rng = np.random.default_rng(0)
+    v = rng.integers(-50, 50, size=X.shape[1]).astype(np.float64)
+    lam = 3.0
+    Xd = X.toarray().astype(int)
+    Xv = [sum(int(Xd[i, j]) * int(v[j]) for j in range(X.shape[1])) for i in range(X.shape[0])]
+    ref = [sum(int(Xd[i, j]) * Xv[i] for i in range(X.shape[0])) + 3 * int(v[j])
+           for j in range(X.shape[1])]
+    got = op.apply_A(X, lam, v)
+    assert [int(g) for g in got] == ref
+    assert np.all(got == np.asarray(ref, dtype=np.float64))
+
+
+def test_operator_random_vector_fsum():
+    X = _tiny_binary(2)
+    rng = np.random.default_rng(1)
+    v = rng.standard_normal(X.shape[1])
+    lam = 0.37
+    Xd = X.toarray()
+    u = [math.fsum(Xd[i, j] * v[j] for j in range(X.shape[1])) for i in range(X.shape[0])]
+    ref = np.array([math.fsum([Xd[i, j] * u[i] for i in range(X.shape[0])] + [lam * v[j]])
+                    for j in range(X.shape[1])])
+    got = op.apply_A(X, lam, v)
+    scale = np.abs(Xd).T @ (np.abs(Xd) @ np.abs(v)) + lam * np.abs(v)
+    assert np.all(np.abs(got - ref) <= 64 * np.finfo(float).eps * scale)
+
+
+def test_rhs_and_diagonal():
+    X = _tiny_binary(3)
+    Xd = X.toarray()
+    y = np.arange(X.shape[0], dtype=float) - 7
+    assert np.allclose(op.rhs(X, y), Xd.T @ y, rtol=0, atol=1e-12)
+    assert np.array_equal(op.jacobi_diagonal(X, 2.0), np.diag(Xd.T @ Xd) + 2.0)
+
+
+@pytest.mark.parametrize("lam", [1e-2, 1.0, 100.0])
+def test_gershgorin_weight_bounds_spectrum(lam):
+    X = _tiny_binary(4, n=60, f=25, m=6)
+    Xd = X.toarray()
+    A = Xd.T @ Xd + lam * np.eye(X.shape[1])
+    D = np.diag(A)
+    rho = sla.eigh(A, np.diag(D), eigvals_only=True).max()   # rho(D^-1 A)
+    w = op.omega_gershgorin(X, lam)
+    assert 1.0 / w >= rho * (1 - 1e-12)
+    assert w * rho < 2.0
+
+
+def test_power_weight_keeps_smoother_convergent():
+    rng = np.random.default_rng(5)
+    Xd = rng.standard_normal((50, 20))
+    lam = 0.1
+    A = Xd.T @ Xd + lam * np.eye(20)
+    rho = sla.eigh(A, np.diag(np.diag(A)), eigvals_only=True).max()
+    w = op.omega_power(Xd, lam, seed=9)
+    assert w * rho < 2.0
+    assert w * rho > 0.5          # not uselessly small: estimate within 2x
+    with pytest.raises(ValueError):
+        op.omega_gershgorin(Xd, lam)
+
+
+def test_prolongation_is_orthonormal():
+    labels = np.array([0, 2, 1, 2, 2, 0, 3, 1, 2])
+    P = coarse.prolongation(labels, 4)
+    PtP = (P.T @ P).toarray()
+    off = PtP - np.diag(np.diag(PtP))
+    assert np.all(off == 0)
+    assert np.all(np.abs(np.diag(PtP) - 1.0) <= 2 * np.finfo(float).eps)
+
+
+def test_averaging_restriction_gram_golden():
+    rows = read_golden("averaging_restriction.txt")
+    sizes = [int(t) for t in rows[0][1:]]
+    diag = [float(t) for t in rows[1][1:]]
+    labels = np.repeat(np.arange(len(sizes)), sizes)
+    Pt = coarse.averaging_restriction(labels, len(sizes))
+    G = (Pt @ Pt.T).toarray()
+    assert np.allclose(G, np.diag(diag), rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_galerkin_identity(seed):
+    """A_c = P^T (X^T X + lam I) P, formed densely from its definition."""
+    X = _tiny_binary(10 + seed, n=80, f=30, m=5)
+    labels = datagen.random_labels(30, 7, seed)
+    lam = 0.5
+    Xd = X.toarray()
+    P = coarse.prolongation(labels, 7).toarray()
+    ref = P.T @ (Xd.T @ Xd + lam * np.eye(30)) @ P
+    Ac = coarse.coarse_matrix(X, labels, 7, lam)
+    assert np.max(np.abs(Ac - ref)) <= 1e-13 * np.max(np.abs(ref))
+    # binary X: sqrt(n_s n_t) K_st is the integer S^T S with S = X P_u
+    n = coarse.cluster_sizes(labels, 7)
+    K = coarse.coarse_gram(X, labels, 7)
+    Pu = np.zeros((30, 7), dtype=np.int64)
+    Pu[np.arange(30), labels] = 1
+    S = X.toarray().astype(np.int64) @ Pu
+    StS = S.T @ S
+    assert np.allclose(K * np.sqrt(np.outer(n, n)), StS, rtol=1e-14, atol=0)
+
+
+def test_cholesky_factor():
+    X = _tiny_binary(20, n=90, f=40, m=5)
+    labels = datagen.random_labels(40, 9, 3)
+    Ac = coarse.coarse_matrix(X, labels, 9, 0.1)
+    L = coarse.cholesky(Ac)
+    assert np.allclose(L, np.tril(L))
+    assert np.linalg.norm(L @ L.T - Ac) <= 1e-14 * np.linalg.norm(Ac)
+    c = np.arange(9.0)
+    assert np.allclose(coarse.coarse_solve(L, c), np.linalg.solve(Ac, c), rtol=1e-12)
+
+
+def test_ideal_case_golden_spectrum():
+    """Duplicated columns: the nonzero eigenvalues of X^T X equal those of
+    K = P^T X^T X P, and match the hand-derived closed form 5 -/+ sqrt(7)."""
+    rows = read_golden("ideal_case.txt")
+    x1 = np.array([float(t) for t in rows[0][1:]])
+    x2 = np.array([float(t) for t in rows[1][1:]])
+    n1, n2 = (int(t) for t in rows[2][1:])
+    Kg = np.array([float(t) for t in rows[3][1:]]).reshape(2, 2)
+    eig = np.array([float(t) for t in rows[4][1:]])
+    Xd = np.column_stack([x1] * n1 + [x2] * n2)
+    labels = np.array([0] * n1 + [1] * n2)
+    K = coarse.coarse_gram(sp.csr_matrix(Xd), labels, 2)
+    assert np.allclose(K, Kg, rtol=1e-15, atol=1e-15)
+    ev = np.linalg.eigvalsh(Xd.T @ Xd)
+    nz = np.sort(ev[np.abs(ev) > 1e-9])
+    assert np.allclose(nz, eig, rtol=1e-14)
+    assert np.allclose(np.linalg.eigvalsh(K), eig, rtol=1e-14)
+    # the printed scaling x_s^T x_t / sqrt(n_s n_t) does not reproduce it
+    wrong = np.array([[x1 @ x1 / n1, x1 @ x2 / math.sqrt(n1 * n2)],
+                      [x1 @ x2 / math.sqrt(n1 * n2), x2 @ x2 / n2]])
+    assert not np.allclose(np.linalg.eigvalsh(wrong), eig)
+
+
+def test_exact_argmin_against_fractions():
+    from oracle.kmeans import exact_argmin
+    rng = np.random.default_rng(7)
+    for trial in range(20):
+        F, k = 30, 6
+        den = rng.integers(1, 6, size=k) ** 2
+        num = rng.integers(-40, 40, size=(F, k))
+        active = rng.random(k) > 0.2
+        active[rng.integers(k)] = True
+        got = exact_argmin(num, den, active)
+        for j in range(F):
+            best = None
+            for s in range(k):
+                if not active[s]:
+                    continue
+                v = Fraction(int(num[j, s]), int(den[s]))
+                if best is None or v < best[0]:
+                    best = (v, s)
+            assert got[j] == best[1]
+    # huge values take the Python-int path
+    num = np.array([[3 * 10**12, 3 * 10**12 - 1]], dtype=np.int64)
+    den = np.array([10**10, 10**10], dtype=np.int64)
+    assert exact_argmin(num, den, np.array([True, True]))[0] == 1

@@ -1,0 +1,201 @@
+"""Pins for the oracle's preconditioners and Krylov solvers: the ridge
+solution from an independent least-squares route, closed forms, the
+ideal-case one-step convergence, SPD-ness, monotone A-norm error and the
+flexible-CG / PCG equivalence."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+import datagen
+from oracle import coarse, kmeans, krylov, operator as op, precond
+
+
+def _lstsq_ridge(Xd, y, lam):
+    """argmin ||X w - y||^2 + lam ||w||^2 through the augmented system
+    [X; sqrt(lam) I] w = [y; 0] (QR/SVD least squares, no normal
+    equations)."""
+    F = Xd.shape[1]
+    Aug = np.vstack([Xd, np.sqrt(lam) * np.eye(F)])
+    rhs = np.concatenate([y, np.zeros(F)])
+    return sla.lstsq(Aug, rhs)[0]
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    P = datagen.tiny_sparse()
+    lab, fc, _, _ = kmeans.kmeans_features(P.X, 50, 42)
+    return P, lab, fc
+
+
+@pytest.mark.parametrize("method", ["none", "jacobi", "vcycle", "additive"])
+def test_solution_matches_least_squares(tiny, method):
+    P, lab, fc = tiny
+    lam = 1.0
+    w_ls = _lstsq_ridge(P.X.toarray(), P.y, lam)
+    Xd = P.X.toarray()
+    kappa = np.linalg.cond(Xd.T @ Xd + lam * np.eye(Xd.shape[1]))
+    w, info = krylov.solve(P.X, P.y, lam, method, lab, fc, tol=1e-10)
+    assert info.status == krylov.OK
+    assert info.relres <= 1e-10
+    assert np.linalg.norm(w - w_ls) / np.linalg.norm(w_ls) <= kappa * 1e-10
+    assert info.true_relres <= 2e-10
+
+
+def test_iteration_ordering(tiny):
+    """Two-level needs fewer iterations than CG (the paper's overview
+    table)."""
+    P, lab, fc = tiny
+    its = {m: krylov.solve(P.X, P.y, 1.0, m, lab, fc, tol=1e-10)[1].iters
+           for m in ["none", "jacobi", "vcycle"]}
+    assert its["vcycle"] < its["jacobi"] < its["none"]
+
+
+def test_disjoint_supports_closed_form():
+    """X^T X diagonal: w_j = x_j^T y / (c_j + lam); Jacobi-PCG is exact in
+    one step."""
+    rng = np.random.default_rng(3)
+    N, F = 40, 8
+    Xd = np.zeros((N, F))
+    rows = rng.permutation(N)
+    for j in range(F):
+        Xd[rows[5 * j:5 * j + 5], j] = 1.0
+    y = rng.standard_normal(N)
+    lam = 0.7
+    w_cf = (Xd.T @ y) / ((Xd ** 2).sum(axis=0) + lam)
+    w, info = krylov.solve(sp.csr_matrix(Xd), y, lam, "jacobi", tol=1e-14)
+    assert info.iters == 1
+    assert np.allclose(w, w_cf, rtol=1e-14, atol=0)
+
+
+def test_zero_matrix_gives_zero():
+    X = sp.csr_matrix((10, 6))
+    w, info = krylov.solve(X, np.ones(10), 1.0, "jacobi")
+    assert info.iters == 0 and np.all(w == 0)
+
+
+def test_ideal_case_one_iteration():
+    """Duplicated columns: range(P) holds b = X^T y and is invariant under A
+    and D, so the V-cycle is exact there and PCG stops after one step."""
+    X, group = datagen.duplicated_columns(40, [3, 4, 2, 5], 0.3, seed=8)
+    lab, fc, _, _ = kmeans.kmeans_features(X, 4, 3)
+    y = np.random.default_rng(1).standard_normal(40)
+    w, info = krylov.solve(X, y, 0.5, "vcycle", lab, fc, tol=1e-12)
+    assert info.iters == 1
+    w_ls = _lstsq_ridge(X.toarray(), y, 0.5)
+    assert np.linalg.norm(w - w_ls) <= 1e-11 * np.linalg.norm(w_ls)
+
+
+def test_singleton_clusters_one_iteration():
+    """labels = 0..F-1: P = I, A_c = A, the coarse correction is exact."""
+    P = datagen.tiny_sparse()
+    F = P.X.shape[1]
+    lab = np.arange(F, dtype=np.int32)
+    w, info = krylov.solve(P.X, P.y, 1.0, "vcycle", lab, F, tol=1e-12)
+    assert info.iters == 1
+
+
+def _dense_B(apply_B, F):
+    return np.column_stack([apply_B(e) for e in np.eye(F)])
+
+
+@pytest.mark.parametrize("kind", ["jacobi", "vcycle", "additive"])
+def test_preconditioner_spd(kind):
+    X = datagen.zipf_binary_csr(120, 40, 6, 1.1, 31)
+    lam = 0.3
+    lab = datagen.random_labels(40, 6, 2)
+    omega = op.omega_gershgorin(X, lam)
+    B, _ = precond.make(kind, X, lam, lab, 6, omega)
+    M = _dense_B(B, 40)
+    assert np.linalg.norm(M - M.T) <= 1e-12 * np.linalg.norm(M)
+    assert np.linalg.eigvalsh(0.5 * (M + M.T)).min() > 0
+
+
+def test_vcycle_error_propagation_matches_paper_form():
+    """I - B A = (I - S A)(I - P A_c^-1 P^T A)(I - S A) with S = omega D^-1."""
+    X = datagen.zipf_binary_csr(100, 30, 5, 1.1, 41)
+    lam = 0.8
+    lab = datagen.random_labels(30, 5, 4)
+    omega = op.omega_gershgorin(X, lam)
+    B, _ = precond.make("vcycle", X, lam, lab, 5, omega)
+    Xd = X.toarray()
+    A = Xd.T @ Xd + lam * np.eye(30)
+    S = omega * np.diag(1.0 / np.diag(A))
+    Pm = coarse.prolongation(lab, 5).toarray()
+    Ac = Pm.T @ A @ Pm
+    I = np.eye(30)
+    T = (I - S @ A) @ (I - Pm @ np.linalg.solve(Ac, Pm.T @ A)) @ (I - S @ A)
+    assert np.allclose(I - _dense_B(B, 30) @ A, T, atol=1e-12)
+
+
+def test_A_is_spd():
+    X = datagen.zipf_binary_csr(30, 50, 4, 1.1, 5)   # N < F: null space
+    lam = 0.25
+    Xd = X.toarray()
+    ev = np.linalg.eigvalsh(Xd.T @ Xd + lam * np.eye(50))
+    assert ev.min() >= lam * (1 - 1e-12)
+    assert np.isclose(ev.min(), lam)
+
+
+@pytest.mark.parametrize("kind", ["none", "jacobi", "vcycle"])
+def test_monotone_A_norm_error(kind):
+    X = datagen.zipf_binary_csr(200, 60, 6, 1.1, 51)
+    lam = 0.1
+    y = np.random.default_rng(2).standard_normal(200)
+    lab = datagen.random_labels(60, 8, 5)
+    Xd = X.toarray()
+    A = Xd.T @ Xd + lam * np.eye(60)
+    wst = np.linalg.solve(A, Xd.T @ y)
+    errs = []
+    for k in range(0, 25):
+        w, _ = krylov.solve(X, y, lam, kind, lab, 8, fixed_iters=k)
+        e = w - wst
+        errs.append(np.sqrt(e @ A @ e))
+    scale = np.sqrt(wst @ A @ wst)
+    assert all(b <= a + 1e-14 * scale for a, b in zip(errs, errs[1:]))
+
+
+def test_fcg1_reproduces_pcg():
+    P = datagen.tiny_sparse()
+    lam = 1.0
+    lab, fc, _, _ = kmeans.kmeans_features(P.X, 50, 42)
+    omega = op.omega_gershgorin(P.X, lam)
+    B, _ = precond.make("vcycle", P.X, lam, lab, fc, omega)
+    b = op.rhs(P.X, P.y)
+    A = lambda v: op.apply_A(P.X, lam, v)
+    # equal in exact arithmetic; in FP64 the rounding differences are
+    # amplified mid-solve (kappa ~ 5e3) and vanish again at convergence
+    for k in (1, 2, 3, 5, 8, 12, 16, 20, 24):
+        xp, _ = krylov.pcg(A, b, B, fixed_iters=k)
+        xf, _ = krylov.fcg(A, b, lambda r, i: B(r), m=1, fixed_iters=k)
+        rel = np.linalg.norm(xp - xf) / np.linalg.norm(xp)
+        assert rel <= (1e-13 if k <= 5 or k >= 20 else 1e-8)
+
+
+def test_fcg_truncation_schedule():
+    """m_i = max(1, i mod (m+1)) directions are kept: with m = 3 FCG stays
+    exact against a variable preconditioner on a tiny SPD system."""
+    rng = np.random.default_rng(4)
+    M = rng.standard_normal((12, 12))
+    A = M @ M.T + 12 * np.eye(12)
+    b = rng.standard_normal(12)
+    Bs = [np.diag(1.0 / (np.diag(A) * (1 + 0.1 * i))) for i in range(40)]
+    x, info = krylov.fcg(lambda v: A @ v, b, lambda r, i: Bs[i] @ r, m=3, tol=1e-12)
+    assert info.status == krylov.OK
+    assert np.allclose(A @ x, b, atol=1e-10)
+
+
+def test_stopping_rule_is_first_crossing(tiny):
+    P, lab, fc = tiny
+    w, info = krylov.solve(P.X, P.y, 1.0, "vcycle", lab, fc, tol=1e-8)
+    assert info.history[-1] <= 1e-8 < info.history[-2]
+
+
+def test_not_converged_and_breakdown():
+    P = datagen.tiny_sparse()
+    w, info = krylov.solve(P.X, P.y, 1.0, "none", tol=1e-10, max_iter=5)
+    assert info.status == krylov.NOT_CONVERGED and info.iters == 5
+    lab = datagen.random_labels(500, 50, 1)
+    # omega far above 2 / rho(D^-1 A): the V-cycle is indefinite
+    w, info = krylov.solve(P.X, P.y, 1.0, "vcycle", lab, 50, omega=50.0, tol=1e-10)
+    assert info.status == krylov.BREAKDOWN
