@@ -1,0 +1,210 @@
+/*
+ * rr.h -- C ABI of the MI355X two-level preconditioned CG solver for the
+ * regularized normal equations (X^T X + lambda I) w = X^T y.
+ *
+ * Method (Tavernier, Simm, Meerbergen, Moreau, "Two-level preconditioning
+ * for Ridge Regression", arXiv 1806.05826):
+ *   - the system and the ridge solution: introduction and the ridge
+ *     regression subsection (the paper's beta is lambda here);
+ *   - the two-level preconditioner: the two-level iteration subsection
+ *     (Galerkin coarse level, pre/post smoothing), with the adjusted
+ *     square-root average prolongation P (P(j,s) = 1/sqrt(n_s)) and the
+ *     Galerkin coarse matrix A_c = P^T A P = X_c^T X_c + lambda I of the
+ *     data-matrices subsection;
+ *   - the aggregation: K-means++ over the feature columns (clustering
+ *     section, K-means++ subsection), Euclidean distance;
+ *   - the coarse solve: Cholesky (experiments section);
+ *   - the Krylov iteration: PCG from x0 = 0, r0 = b, stopped on the
+ *     relative residual (initialisation of the flexible CG algorithm; the
+ *     residual plotted in the experiments).
+ *
+ * Conventions for every entry point:
+ *   - Every call returns rr_status; RR_OK (0) on success.  On any other
+ *     status rr_last_error() returns a message for the calling thread.
+ *     No C++ exception or abort crosses the ABI.
+ *   - Pointers documented "device" are HIP device pointers of the current
+ *     device; "host" pointers are ordinary host memory.  The library never
+ *     takes ownership of caller memory.
+ *   - `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ *     Calls are ordered on that stream; calls that return host-visible
+ *     results (info structs, rr_smoother_weight) synchronize it.
+ *   - Vectors are FP64, contiguous.  F-vectors are indexed by feature in
+ *     the caller's column order; N-vectors by sample.
+ *   - A handle is not thread-safe: one call at a time per handle.  Several
+ *     handles may be used concurrently on different streams.
+ *   - Device memory for a handle is allocated by rr_setup and released by
+ *     rr_destroy; rr_solve and the step-level calls allocate nothing.
+ */
+#ifndef RR_H
+#define RR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RR_OK = 0,
+  RR_ERR_INVALID_ARG = 1,   /* bad size, pointer, option or input matrix   */
+  RR_ERR_DEVICE = 2,        /* a HIP call failed                            */
+  RR_ERR_NOT_CONVERGED = 4, /* max_iter reached; w holds the last iterate   */
+  RR_ERR_BREAKDOWN = 5,     /* <p,Ap> or <r,z> not positive / not finite    */
+  RR_ERR_UNSUPPORTED = 6    /* valid request this build does not implement  */
+} rr_status;
+
+/* Preconditioner B used by rr_solve / rr_apply_precond (z = B r). */
+typedef enum {
+  RR_PRECOND_NONE = 0,     /* plain CG: z = r                                   */
+  RR_PRECOND_JACOBI = 1,   /* DCG: z = D^-1 r, D = diag(A) = ||x_j||^2 + lambda  */
+  RR_PRECOND_VCYCLE = 2,   /* two-level cycle, damped-Jacobi pre/post smoothing:
+                              e1 = w D^-1 r; rho1 = r - A e1;
+                              e2 = e1 + P A_c^-1 P^T rho1; rho2 = r - A e2;
+                              z = e2 + w D^-1 rho2  (three operator applications
+                              per PCG iteration, SPD for w rho(D^-1 A) < 2)      */
+  RR_PRECOND_ADDITIVE = 3  /* z = w D^-1 r + P A_c^-1 P^T r                      */
+} rr_precond;
+
+typedef struct rr_handle rr_handle;
+typedef void* rr_stream;
+
+/* Sparse feature matrix X (N x F) in CSR form, 0-based. */
+typedef struct {
+  int64_t n_rows;          /* N >= 1                                           */
+  int64_t n_cols;          /* F >= 1                                           */
+  int64_t nnz;             /* >= 0, < 2^31                                     */
+  const int32_t* row_ptr;  /* device int32[N+1], row_ptr[0] = 0, non-decreasing */
+  const int32_t* col_idx;  /* device int32[nnz], strictly increasing per row    */
+  const double* values;    /* device double[nnz], or NULL for a 0/1 (binary)
+                              matrix: every stored entry is 1                  */
+} rr_csr;
+
+typedef struct {
+  int32_t n_clusters;      /* k >= 1: k-means++ clusters of the feature columns;
+                              0: no coarse level (only NONE/JACOBI solves)      */
+  int32_t kmeans_max_iter; /* Lloyd assignment passes; 0 -> 100                 */
+  uint64_t seed;           /* SplitMix64 seed of the k-means++ draws            */
+  const int32_t* labels_in;/* optional device int32[F]: use this aggregation
+                              (labels in [0, n_labels_in)) instead of k-means;
+                              empty labels are dropped and the rest renumbered
+                              in increasing order                              */
+  int32_t n_labels_in;
+  int32_t lambda_slots;    /* coarse factors cached per handle; 0 -> 4          */
+} rr_setup_opts;
+
+/*
+ * rr_setup: copy X (device CSR) into library-owned storage, build its CSC
+ * transpose, the column norms ||x_j||^2 and the Gershgorin row sums of
+ * X^T X, then the aggregation (k-means++ over the columns, exact integer
+ * arithmetic for binary X) and the lambda-independent coarse Gram matrix
+ * K = P^T X^T X P.  X's arrays are only read during the call.  For non-binary
+ * X only labels_in aggregation is implemented (RR_ERR_UNSUPPORTED otherwise).
+ * Errors: RR_ERR_INVALID_ARG for an invalid matrix (bad row_ptr, column index
+ * out of range or not increasing) or options; RR_ERR_DEVICE on HIP failure.
+ * On success *out receives a handle to release with rr_destroy.
+ */
+rr_status rr_setup(const rr_csr* X, const rr_setup_opts* opts, rr_stream stream,
+                   rr_handle** out);
+
+/* Release a handle and its device memory (NULL is a no-op). */
+rr_status rr_destroy(rr_handle* h);
+
+typedef struct {
+  int64_t n_rows, n_cols, nnz;
+  int32_t n_coarse;        /* F_C (clusters left after dropping empty ones)    */
+  int32_t n_centres;       /* centres chosen by the seeding (fewer than k when
+                              every feature coincides with a chosen centre)    */
+  int32_t kmeans_iters;    /* Lloyd assignment passes run                      */
+  int32_t binary;          /* 1 when X was given without values               */
+  double setup_ms;         /* wall time of rr_setup                            */
+  double kmeans_ms;        /* of which clustering                              */
+} rr_setup_info;
+
+/* Host-side facts about a handle. */
+rr_status rr_get_setup_info(const rr_handle* h, rr_setup_info* info);
+
+/* Copy the final labels (device int32[F], values in [0, F_C)). */
+rr_status rr_get_labels(const rr_handle* h, int32_t* labels, rr_stream stream);
+
+/* Copy the seeding centres in draw order (device int32[n_centres]). */
+rr_status rr_get_centres(const rr_handle* h, int32_t* centres, rr_stream stream);
+
+typedef struct {
+  double tol;              /* stop when ||r_k|| <= tol ||b||; 0 -> 1e-10        */
+  int32_t max_iter;        /* 0 -> 10000                                        */
+  int32_t fixed_iters;     /* > 0: run exactly this many iterations              */
+  int32_t precond;         /* rr_precond; VCYCLE/ADDITIVE need a coarse level    */
+  int32_t rhs_is_b;        /* 0: rhs is y (device double[N]), b = X^T y;
+                              1: rhs is b (device double[F])                     */
+  double omega;            /* smoother weight w; 0 -> 1/rho_hat with rho_hat the
+                              Gershgorin bound max_j (X^T X 1 + lambda)_j / D_j
+                              (X >= 0), else a power-iteration estimate x 1.1   */
+  const double* x_ref;     /* optional device double[F]: also stop as soon as
+                              ||x_k - x_ref|| <= err_tol ||x_ref||               */
+  double err_tol;
+  double* residual_history;/* optional device double[limit+1]: ||r_k||/||b||    */
+  int32_t chunk;           /* iterations queued between host checks; 0 -> 8      */
+  int32_t profile;         /* 1: time every operator kernel with HIP events      */
+} rr_solve_opts;
+
+typedef struct {
+  int32_t status;          /* RR_OK / RR_ERR_NOT_CONVERGED / RR_ERR_BREAKDOWN    */
+  int32_t iters;           /* PCG iterations (x updates)                         */
+  int32_t op_applies;      /* operator applications, b = X^T y and the exit
+                              residual excluded                                  */
+  int32_t reserved;
+  double relres;           /* recursive ||r_k|| / ||b||                           */
+  double true_relres;      /* ||b - A x_k|| / ||b||, recomputed at exit          */
+  double err;              /* ||x_k - x_ref|| / ||x_ref|| when x_ref is given    */
+  double omega;            /* smoother weight used                               */
+  double ms;               /* wall time of the call                              */
+  double coarse_ms;        /* of which the per-lambda coarse factorization       */
+  double csr_avg_ms;       /* profile: mean CSR kernel time (u = X v)            */
+  double csc_avg_ms;       /* profile: mean CSC kernel time (t = X^T u + epilogue)*/
+  int32_t csr_launches, csc_launches;
+} rr_solve_info;
+
+/*
+ * rr_solve: PCG on (X^T X + lambda I) w = b from w = 0 (or the fixed-
+ * iteration / error-target variants above).  lambda must be finite and > 0.
+ * `rhs` and `w` are device FP64 buffers owned by the caller; w receives the
+ * last iterate also on RR_ERR_NOT_CONVERGED / RR_ERR_BREAKDOWN.  The call
+ * blocks until *info (host) is valid.  The lambda-dependent coarse factor is
+ * computed on first use of a lambda and cached in the handle.
+ */
+rr_status rr_solve(rr_handle* h, double lambda, const double* rhs, double* w,
+                   const rr_solve_opts* opts, rr_solve_info* info, rr_stream stream);
+
+/* Av = (X^T X + lambda I) v, v and Av device double[F] (lambda >= 0). */
+rr_status rr_apply_operator(rr_handle* h, double lambda, const double* v, double* Av,
+                            rr_stream stream);
+
+/* b = X^T y, y device double[N], b device double[F]. */
+rr_status rr_apply_rhs(rr_handle* h, const double* y, double* b, rr_stream stream);
+
+/* z = B r for the preconditioner `precond` (rr_precond) at this lambda;
+ * omega = 0 selects the automatic weight.  r, z device double[F]. */
+rr_status rr_apply_precond(rr_handle* h, double lambda, int32_t precond, double omega,
+                           const double* r, double* z, rr_stream stream);
+
+/* K = P^T X^T X P, device double[F_C * F_C] row-major (lambda-independent). */
+rr_status rr_coarse_gram(rr_handle* h, double* K, rr_stream stream);
+
+/* The Cholesky factor L (lower, row-major, zeros above the diagonal) of
+ * A_c = K + lambda I and A_c^-1, device double[F_C * F_C] each; either may be
+ * NULL.  Errors: RR_ERR_BREAKDOWN if A_c is not numerically positive definite. */
+rr_status rr_coarse_factor(rr_handle* h, double lambda, double* L, double* Ac_inv,
+                           rr_stream stream);
+
+/* The automatic smoother weight for this lambda (host double). */
+rr_status rr_smoother_weight(rr_handle* h, double lambda, double* omega);
+
+/* Message for the last non-OK status on this thread ("" if none). */
+const char* rr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RR_H */

@@ -1,0 +1,319 @@
+"""MI355X two-level preconditioned CG for ridge regression.
+
+A thin ctypes binding over ``librr.so``, the HIP/CDNA4 library whose C ABI
+is ``include/rr.h``.  The functions below carry the ABI's names and only
+marshal arguments: PyTorch supplies device memory (tensors on ``cuda``) and
+the stream (``torch.cuda.current_stream()``); every step of the solver runs
+in the library's kernels.  If the library is not built, importing this
+package raises ImportError.
+
+Method: Tavernier, Simm, Meerbergen & Moreau, "Two-level preconditioning for
+Ridge Regression" (arXiv 1806.05826): (X^T X + lambda I) w = X^T y solved by
+PCG with a two-level preconditioner whose coarse space aggregates feature
+columns by k-means++ (the paper's beta is lambda here).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librr.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
+        "or `python paper_1806_05826_amd/build.py`")
+
+_lib = C.CDLL(LIB_PATH)
+
+RR_OK, RR_ERR_INVALID_ARG, RR_ERR_DEVICE = 0, 1, 2
+RR_ERR_NOT_CONVERGED, RR_ERR_BREAKDOWN, RR_ERR_UNSUPPORTED = 4, 5, 6
+PRECOND = {"none": 0, "jacobi": 1, "vcycle": 2, "additive": 3}
+
+
+class rr_csr(C.Structure):
+    _fields_ = [("n_rows", C.c_int64), ("n_cols", C.c_int64), ("nnz", C.c_int64),
+                ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("values", C.c_void_p)]
+
+
+class rr_setup_opts(C.Structure):
+    _fields_ = [("n_clusters", C.c_int32), ("kmeans_max_iter", C.c_int32),
+                ("seed", C.c_uint64), ("labels_in", C.c_void_p), ("n_labels_in", C.c_int32),
+                ("lambda_slots", C.c_int32)]
+
+
+class rr_setup_info(C.Structure):
+    _fields_ = [("n_rows", C.c_int64), ("n_cols", C.c_int64), ("nnz", C.c_int64),
+                ("n_coarse", C.c_int32), ("n_centres", C.c_int32), ("kmeans_iters", C.c_int32),
+                ("binary", C.c_int32), ("setup_ms", C.c_double), ("kmeans_ms", C.c_double)]
+
+
+class rr_solve_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("fixed_iters", C.c_int32),
+                ("precond", C.c_int32), ("rhs_is_b", C.c_int32), ("omega", C.c_double),
+                ("x_ref", C.c_void_p), ("err_tol", C.c_double),
+                ("residual_history", C.c_void_p), ("chunk", C.c_int32), ("profile", C.c_int32)]
+
+
+class rr_solve_info(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("op_applies", C.c_int32),
+                ("reserved", C.c_int32), ("relres", C.c_double), ("true_relres", C.c_double),
+                ("err", C.c_double), ("omega", C.c_double), ("ms", C.c_double),
+                ("coarse_ms", C.c_double), ("csr_avg_ms", C.c_double),
+                ("csc_avg_ms", C.c_double), ("csr_launches", C.c_int32),
+                ("csc_launches", C.c_int32)]
+
+
+_P = C.c_void_p
+_SIGS = {
+    "rr_setup": [C.POINTER(rr_csr), C.POINTER(rr_setup_opts), _P, C.POINTER(_P)],
+    "rr_destroy": [_P],
+    "rr_get_setup_info": [_P, C.POINTER(rr_setup_info)],
+    "rr_get_labels": [_P, _P, _P],
+    "rr_get_centres": [_P, _P, _P],
+    "rr_solve": [_P, C.c_double, _P, _P, C.POINTER(rr_solve_opts), C.POINTER(rr_solve_info), _P],
+    "rr_apply_operator": [_P, C.c_double, _P, _P, _P],
+    "rr_apply_rhs": [_P, _P, _P, _P],
+    "rr_apply_precond": [_P, C.c_double, C.c_int32, C.c_double, _P, _P, _P],
+    "rr_coarse_gram": [_P, _P, _P],
+    "rr_coarse_factor": [_P, C.c_double, _P, _P, _P],
+    "rr_smoother_weight": [_P, C.c_double, C.POINTER(C.c_double)],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = C.c_int
+_lib.rr_last_error.argtypes = []
+_lib.rr_last_error.restype = C.c_char_p
+
+
+class RRError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"rr status {status}: {message}")
+        self.status = status
+        self.message = message
+
+
+def rr_last_error() -> str:
+    return (_lib.rr_last_error() or b"").decode()
+
+
+def _check(st: int, allow=()):
+    if st != RR_OK and st not in allow:
+        raise RRError(st, rr_last_error())
+    return st
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev_f64(t, n=None, name="vector"):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError(f"{name}: need a contiguous float64 CUDA tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name}: expected {n} elements, got {t.numel()}")
+    return t
+
+
+# --- the C ABI, one Python function per entry point -------------------------
+
+def rr_setup(row_ptr, col_idx, values, n_cols, n_clusters=0, seed=0, kmeans_max_iter=0,
+             labels_in=None, n_labels_in=0, lambda_slots=0, stream=None):
+    """X is a device CSR: row_ptr/col_idx int32 CUDA tensors, values float64
+    CUDA tensor or None (binary).  Returns an opaque handle (int)."""
+    import torch
+    for t, nm in ((row_ptr, "row_ptr"), (col_idx, "col_idx")):
+        if not (t.is_cuda and t.dtype == torch.int32 and t.is_contiguous()):
+            raise ValueError(f"{nm}: need a contiguous int32 CUDA tensor")
+    if values is not None:
+        _dev_f64(values, col_idx.numel(), "values")
+    if labels_in is not None and not (labels_in.is_cuda and labels_in.dtype == torch.int32):
+        raise ValueError("labels_in: need an int32 CUDA tensor")
+    X = rr_csr(row_ptr.numel() - 1, int(n_cols), col_idx.numel(), _ptr(row_ptr), _ptr(col_idx),
+               _ptr(values))
+    o = rr_setup_opts(int(n_clusters), int(kmeans_max_iter), int(seed) & (2**64 - 1),
+                      _ptr(labels_in), int(n_labels_in), int(lambda_slots))
+    h = C.c_void_p()
+    _check(_lib.rr_setup(C.byref(X), C.byref(o), _stream(stream), C.byref(h)))
+    return h.value
+
+
+def rr_destroy(h):
+    _check(_lib.rr_destroy(C.c_void_p(h)))
+
+
+def rr_get_setup_info(h) -> dict:
+    i = rr_setup_info()
+    _check(_lib.rr_get_setup_info(C.c_void_p(h), C.byref(i)))
+    return {f: getattr(i, f) for f, _ in rr_setup_info._fields_}
+
+
+def rr_get_labels(h, labels, stream=None):
+    _check(_lib.rr_get_labels(C.c_void_p(h), _ptr(labels), _stream(stream)))
+
+
+def rr_get_centres(h, centres, stream=None):
+    _check(_lib.rr_get_centres(C.c_void_p(h), _ptr(centres), _stream(stream)))
+
+
+def rr_solve(h, lam, rhs, w, tol=0.0, max_iter=0, fixed_iters=0, precond="vcycle",
+             rhs_is_b=False, omega=0.0, x_ref=None, err_tol=0.0, residual_history=None,
+             chunk=0, profile=False, stream=None, raise_on=(RR_ERR_INVALID_ARG, RR_ERR_DEVICE,
+                                                             RR_ERR_UNSUPPORTED)):
+    """Returns (status, info dict).  Statuses in `raise_on` raise RRError."""
+    _dev_f64(rhs, None, "rhs")
+    _dev_f64(w, None, "w")
+    o = rr_solve_opts(float(tol), int(max_iter), int(fixed_iters),
+                      PRECOND[precond] if isinstance(precond, str) else int(precond),
+                      1 if rhs_is_b else 0, float(omega), _ptr(x_ref), float(err_tol),
+                      _ptr(residual_history), int(chunk), 1 if profile else 0)
+    info = rr_solve_info()
+    st = _lib.rr_solve(C.c_void_p(h), float(lam), _ptr(rhs), _ptr(w), C.byref(o), C.byref(info),
+                       _stream(stream))
+    if st in raise_on:
+        raise RRError(st, rr_last_error())
+    return st, {f: getattr(info, f) for f, _ in rr_solve_info._fields_}
+
+
+def rr_apply_operator(h, lam, v, Av, stream=None):
+    _check(_lib.rr_apply_operator(C.c_void_p(h), float(lam), _ptr(v), _ptr(Av), _stream(stream)))
+
+
+def rr_apply_rhs(h, y, b, stream=None):
+    _check(_lib.rr_apply_rhs(C.c_void_p(h), _ptr(y), _ptr(b), _stream(stream)))
+
+
+def rr_apply_precond(h, lam, precond, omega, r, z, stream=None):
+    k = PRECOND[precond] if isinstance(precond, str) else int(precond)
+    _check(_lib.rr_apply_precond(C.c_void_p(h), float(lam), k, float(omega), _ptr(r), _ptr(z),
+                                 _stream(stream)))
+
+
+def rr_coarse_gram(h, K, stream=None):
+    _check(_lib.rr_coarse_gram(C.c_void_p(h), _ptr(K), _stream(stream)))
+
+
+def rr_coarse_factor(h, lam, L=None, Ainv=None, stream=None):
+    _check(_lib.rr_coarse_factor(C.c_void_p(h), float(lam), _ptr(L), _ptr(Ainv), _stream(stream)))
+
+
+def rr_smoother_weight(h, lam) -> float:
+    out = C.c_double()
+    _check(_lib.rr_smoother_weight(C.c_void_p(h), float(lam), C.byref(out)))
+    return out.value
+
+
+# --- a small convenience wrapper ---------------------------------------------
+
+class Ridge:
+    """Owns one handle.  ``X`` is a scipy CSR matrix (host); it is copied to
+    the device, handed to rr_setup and released (the library keeps its own
+    copy)."""
+
+    def __init__(self, X, n_clusters=0, seed=0, kmeans_max_iter=0, labels=None, binary=None,
+                 lambda_slots=0, device="cuda"):
+        import numpy as np
+        import torch
+        X = X.tocsr()
+        X.sort_indices()
+        if binary is None:
+            binary = bool(X.nnz == 0 or np.all(X.data == 1.0))
+        self.N, self.F = X.shape
+        self.device = torch.device(device)
+        rp = torch.as_tensor(X.indptr.astype(np.int32), device=self.device)
+        ci = torch.as_tensor(X.indices.astype(np.int32), device=self.device)
+        vals = None if binary else torch.as_tensor(X.data.astype(np.float64), device=self.device)
+        lab = None
+        nlab = 0
+        if labels is not None:
+            lab = torch.as_tensor(np.asarray(labels, dtype=np.int32), device=self.device)
+            nlab = int(np.max(labels)) + 1 if len(labels) else 1
+        self.h = rr_setup(rp, ci, vals, self.F, n_clusters, seed, kmeans_max_iter, lab, nlab,
+                          lambda_slots)
+        torch.cuda.current_stream().synchronize()
+        self.info = rr_get_setup_info(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            rr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _vec(self, v, n):
+        import torch
+        t = torch.as_tensor(v, dtype=torch.float64, device=self.device).contiguous()
+        if t.numel() != n:
+            raise ValueError(f"expected {n} elements")
+        return t
+
+    def solve(self, lam, y, rhs_is_b=False, **kw):
+        import torch
+        rhs = self._vec(y, self.F if rhs_is_b else self.N)
+        w = torch.empty(self.F, dtype=torch.float64, device=self.device)
+        st, info = rr_solve(self.h, lam, rhs, w, rhs_is_b=rhs_is_b, **kw)
+        return w, info
+
+    def apply_operator(self, lam, v):
+        import torch
+        v = self._vec(v, self.F)
+        out = torch.empty_like(v)
+        rr_apply_operator(self.h, lam, v, out)
+        return out
+
+    def apply_rhs(self, y):
+        import torch
+        y = self._vec(y, self.N)
+        out = torch.empty(self.F, dtype=torch.float64, device=self.device)
+        rr_apply_rhs(self.h, y, out)
+        return out
+
+    def apply_precond(self, lam, r, precond="vcycle", omega=0.0):
+        import torch
+        r = self._vec(r, self.F)
+        z = torch.empty_like(r)
+        rr_apply_precond(self.h, lam, precond, omega, r, z)
+        return z
+
+    def labels(self):
+        import torch
+        out = torch.empty(self.F, dtype=torch.int32, device=self.device)
+        rr_get_labels(self.h, out)
+        return out
+
+    def centres(self):
+        import torch
+        out = torch.empty(self.info["n_centres"], dtype=torch.int32, device=self.device)
+        rr_get_centres(self.h, out)
+        return out
+
+    def coarse_gram(self):
+        import torch
+        fc = self.info["n_coarse"]
+        K = torch.empty(fc * fc, dtype=torch.float64, device=self.device)
+        rr_coarse_gram(self.h, K)
+        return K.view(fc, fc)
+
+    def coarse_factor(self, lam):
+        import torch
+        fc = self.info["n_coarse"]
+        L = torch.empty(fc * fc, dtype=torch.float64, device=self.device)
+        Ai = torch.empty_like(L)
+        rr_coarse_factor(self.h, lam, L, Ai)
+        return L.view(fc, fc), Ai.view(fc, fc)
+
+    def smoother_weight(self, lam):
+        return rr_smoother_weight(self.h, lam)

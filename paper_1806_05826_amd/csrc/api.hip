@@ -1,0 +1,628 @@
+// C ABI entry points (include/rr.h): handle lifecycle, setup, the PCG driver
+// and the step-level calls.  The driver queues whole iterations on the
+// caller's stream; all scalars live on the device and kernels skip once the
+// device-side `done` flag is set, so the host only polls between chunks.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "rr_device.h"
+
+namespace rr {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+rr_status fail(rr_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+__global__ void k_colnorm_binary(int F, const int* col_ptr, double* c) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < F) c[j] = (double)(col_ptr[j + 1] - col_ptr[j]);
+}
+
+__global__ void k_colnorm_values(int F, const int* col_ptr, const double* cval, double* c) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= F) return;
+  double s = 0.0;
+  for (int e = col_ptr[j]; e < col_ptr[j + 1]; ++e) s += cval[e] * cval[e];
+  c[j] = s;
+}
+
+__global__ void k_smooth(int F, const double* r, const double* D, double omega, double* e1) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < F) e1[j] = (omega * r[j]) / D[j];
+}
+
+}  // namespace rr
+
+using namespace rr;
+
+namespace {
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+template <class T>
+rr_status dalloc(T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc((void**)p, sizeof(T) * n);
+  if (e != hipSuccess) return fail(RR_ERR_DEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
+  return RR_OK;
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+void destroy_handle(rr_handle* h) {
+  if (!h) return;
+  Sparse& X = h->X;
+  dfree(X.row_ptr); dfree(X.col_idx); dfree(X.val);
+  dfree(X.col_ptr); dfree(X.row_idx); dfree(X.cval);
+  free_merge_plan(X.csc_plan);
+  free_merge_plan(h->restrict_plan);
+  dfree(h->colnorm); dfree(h->gersh);
+  dfree(h->labels); dfree(h->centres); dfree(h->csize); dfree(h->cscale);
+  dfree(h->perm); dfree(h->coff); dfree(h->K);
+  for (auto& s : h->slots) { dfree(s.L); dfree(s.Ainv); }
+  dfree(h->chol_work); dfree(h->chol_flag);
+  Work& w = h->w;
+  dfree(w.x); dfree(w.r); dfree(w.p); dfree(w.q); dfree(w.z); dfree(w.e1); dfree(w.e2);
+  dfree(w.rho); dfree(w.b); dfree(w.u); dfree(w.c); dfree(w.yc); dfree(w.partials);
+  dfree(w.sc); dfree(w.D);
+  if (w.sc_host) (void)hipHostFree(w.sc_host);
+  for (auto e : h->ev_pool) (void)hipEventDestroy(e);
+  delete h;
+}
+
+int pick_group(double avg) {
+  int g = 4;
+  while (g < 64 && g < avg / 2.0) g *= 2;
+  return g;
+}
+
+rr_status setup_impl(const rr_csr* Xin, const rr_setup_opts* o, hipStream_t s, rr_handle* h) {
+  const double t0 = now_ms();
+  RR_HIP(hipGetDevice(&h->device));
+  Sparse& X = h->X;
+  X.N = (int)Xin->n_rows;
+  X.F = (int)Xin->n_cols;
+  X.nnz = (int)Xin->nnz;
+  X.binary = (Xin->values == nullptr);
+  RR_TRY(dalloc(&X.row_ptr, X.N + 1));
+  RR_TRY(dalloc(&X.col_idx, X.nnz));
+  RR_HIP(hipMemcpyAsync(X.row_ptr, Xin->row_ptr, sizeof(int) * (X.N + 1), hipMemcpyDeviceToDevice, s));
+  if (X.nnz)
+    RR_HIP(hipMemcpyAsync(X.col_idx, Xin->col_idx, sizeof(int) * X.nnz, hipMemcpyDeviceToDevice, s));
+  if (!X.binary) {
+    RR_TRY(dalloc(&X.val, X.nnz));
+    if (X.nnz) RR_HIP(hipMemcpyAsync(X.val, Xin->values, sizeof(double) * X.nnz, hipMemcpyDeviceToDevice, s));
+  }
+  rr_status vs = validate_csr(X, s);
+  if (vs == RR_ERR_UNSUPPORTED) {
+    h->nonneg = false;
+  } else if (vs != RR_OK) {
+    return vs;
+  }
+  X.csr_group = pick_group(X.N ? (double)X.nnz / X.N : 1.0);
+  RR_TRY(build_csc(X, s));
+  // column norms and Gershgorin row sums g = X^T (X 1)
+  RR_TRY(dalloc(&h->colnorm, X.F));
+  RR_TRY(dalloc(&h->gersh, X.F));
+  if (X.binary)
+    k_colnorm_binary<<<cdiv(X.F, kBlock), kBlock, 0, s>>>(X.F, X.col_ptr, h->colnorm);
+  else
+    k_colnorm_values<<<cdiv(X.F, kBlock), kBlock, 0, s>>>(X.F, X.col_ptr, X.cval, h->colnorm);
+  // work buffers
+  Work& w = h->w;
+  const int F = X.F, N = X.N;
+  RR_TRY(dalloc(&w.x, F)); RR_TRY(dalloc(&w.r, F)); RR_TRY(dalloc(&w.p, F));
+  RR_TRY(dalloc(&w.q, F)); RR_TRY(dalloc(&w.z, F)); RR_TRY(dalloc(&w.e1, F));
+  RR_TRY(dalloc(&w.e2, F)); RR_TRY(dalloc(&w.rho, F)); RR_TRY(dalloc(&w.b, F));
+  RR_TRY(dalloc(&w.D, F)); RR_TRY(dalloc(&w.u, N));
+  RR_TRY(dalloc(&w.sc, 1));
+  RR_HIP(hipHostMalloc((void**)&w.sc_host, sizeof(Scalars), hipHostMallocDefault));
+  std::memset(w.sc_host, 0, sizeof(Scalars));
+  RR_HIP(hipMemsetAsync(w.sc, 0, sizeof(Scalars), s));
+  {
+    launch_fill(w.u, 0.0, N, s);
+    launch_fill(w.x, 1.0, F, s);
+    launch_csr(X, w.x, w.u, nullptr, s);
+    Epi e{};
+    e.out = h->gersh;
+    // partials are not needed for EPI_STORE
+    launch_csc(X, w.u, EPI_STORE, e, nullptr, s);
+  }
+  // aggregation
+  RR_TRY(dalloc(&h->labels, F));
+  const int k = o ? o->n_clusters : 0;
+  h->k_req = k;
+  const double tk = now_ms();
+  if (o && o->labels_in) {
+    if (o->n_labels_in < 1) return fail(RR_ERR_INVALID_ARG, "n_labels_in must be >= 1");
+    RR_TRY(set_labels(h, o->labels_in, o->n_labels_in, s));
+  } else if (k > 0) {
+    RR_TRY(dalloc(&h->centres, std::min(k, F)));
+    const int mi = (o->kmeans_max_iter > 0) ? o->kmeans_max_iter : 100;
+    RR_TRY(run_kmeans(h, k, o->seed, mi, s));
+  }
+  h->kmeans_ms = now_ms() - tk;
+  int np = std::max(X.csc_plan.nblocks + cdiv(X.csc_plan.nspan, kBlock) + 1, cdiv(F, kBlock) + 1);
+  if (h->FC > 0) {
+    const int fc = h->FC;
+    RR_TRY(dalloc(&h->K, (size_t)fc * fc));
+    RR_TRY(build_coarse_gram(h, s));
+    const int nslots = (o && o->lambda_slots > 0) ? o->lambda_slots : 4;
+    h->slots.resize(nslots);
+    for (auto& sl : h->slots) {
+      RR_TRY(dalloc(&sl.L, (size_t)fc * fc));
+      RR_TRY(dalloc(&sl.Ainv, (size_t)fc * fc));
+    }
+    RR_TRY(dalloc(&h->chol_work, 2 * (size_t)fc * fc));
+    RR_TRY(dalloc(&h->chol_flag, 1));
+    RR_TRY(dalloc(&w.c, fc));
+    RR_TRY(dalloc(&w.yc, fc));
+    np = std::max(np, h->restrict_plan.nblocks + cdiv(h->restrict_plan.nspan, kBlock) + 1);
+  }
+  w.npartials = np;
+  RR_TRY(dalloc(&w.partials, 3 * (size_t)np));
+  RR_HIP(hipStreamSynchronize(s));
+  RR_HIP(hipGetLastError());
+  h->setup_ms = now_ms() - t0;
+  return RR_OK;
+}
+
+rr_status check_handle(const rr_handle* h) {
+  if (!h) return fail(RR_ERR_INVALID_ARG, "null handle");
+  return RR_OK;
+}
+
+rr_status check_lambda(double lam, bool allow_zero) {
+  if (!std::isfinite(lam) || lam < 0.0 || (!allow_zero && lam == 0.0))
+    return fail(RR_ERR_INVALID_ARG, "lambda must be finite and > 0");
+  return RR_OK;
+}
+
+rr_status auto_omega(rr_handle* h, double lam, double* omega, hipStream_t s) {
+  if (!h->nonneg)
+    return fail(RR_ERR_UNSUPPORTED, "automatic smoother weight for X with negative entries: pass omega");
+  double* d = h->w.yc ? h->w.yc : h->w.c;
+  double* tmp = nullptr;
+  if (!d) {
+    RR_TRY(dalloc(&tmp, 1));
+    d = tmp;
+  }
+  launch_omega_gersh(h->X.F, h->gersh, h->colnorm, lam, d, nullptr, nullptr, s);
+  RR_HIP(hipMemcpyAsync(omega, d, sizeof(double), hipMemcpyDeviceToHost, s));
+  RR_HIP(hipStreamSynchronize(s));
+  dfree(tmp);
+  return RR_OK;
+}
+
+// The coarse factor for lambda, from the cache or freshly computed.
+rr_status get_slot(rr_handle* h, double lam, LambdaSlot** out, double* ms, hipStream_t s) {
+  *ms = 0.0;
+  for (auto& sl : h->slots)
+    if (sl.valid && sl.lam == lam) {
+      sl.stamp = ++h->stamp;
+      *out = &sl;
+      return RR_OK;
+    }
+  LambdaSlot* victim = &h->slots[0];
+  for (auto& sl : h->slots)
+    if (!sl.valid || sl.stamp < victim->stamp) victim = &sl;
+  const double t0 = now_ms();
+  victim->valid = false;
+  RR_TRY(coarse_factor(h, lam, *victim, s));
+  RR_TRY(auto_omega(h, lam, &victim->omega, s));
+  RR_HIP(hipStreamSynchronize(s));
+  victim->lam = lam;
+  victim->valid = true;
+  victim->stamp = ++h->stamp;
+  *out = victim;
+  *ms = now_ms() - t0;
+  return RR_OK;
+}
+
+struct Prof {
+  bool on = false;
+  std::vector<std::pair<int, int>> csr, csc;   // event-pair index, iteration tag
+  int used = 0;
+};
+
+rr_status prof_pair(rr_handle* h, Prof& pf, int* idx) {
+  const int need = 2 * (pf.used + 1);
+  while ((int)h->ev_pool.size() < need) {
+    hipEvent_t e;
+    RR_HIP(hipEventCreate(&e));
+    h->ev_pool.push_back(e);
+  }
+  *idx = pf.used++;
+  return RR_OK;
+}
+
+// Apply the operator pieces with optional event timing.
+rr_status op_csr(rr_handle* h, Prof& pf, int tag, const double* v, hipStream_t s) {
+  const int* done = &h->w.sc->done;
+  if (!pf.on) {
+    launch_csr(h->X, v, h->w.u, done, s);
+    return RR_OK;
+  }
+  int i;
+  RR_TRY(prof_pair(h, pf, &i));
+  RR_HIP(hipEventRecord(h->ev_pool[2 * i], s));
+  launch_csr(h->X, v, h->w.u, done, s);
+  RR_HIP(hipEventRecord(h->ev_pool[2 * i + 1], s));
+  pf.csr.push_back({i, tag});
+  return RR_OK;
+}
+
+rr_status op_csc(rr_handle* h, Prof& pf, int tag, int mode, const Epi& e, hipStream_t s) {
+  const int* done = &h->w.sc->done;
+  if (!pf.on) {
+    launch_csc(h->X, h->w.u, mode, e, done, s);
+    return RR_OK;
+  }
+  int i;
+  RR_TRY(prof_pair(h, pf, &i));
+  RR_HIP(hipEventRecord(h->ev_pool[2 * i], s));
+  launch_csc(h->X, h->w.u, mode, e, done, s);
+  RR_HIP(hipEventRecord(h->ev_pool[2 * i + 1], s));
+  pf.csc.push_back({i, tag});
+  return RR_OK;
+}
+
+Epi base_epi(rr_handle* h, double lam) {
+  Epi e{};
+  e.lam = lam;
+  e.sc = h->w.sc;
+  e.partials = h->w.partials;
+  e.D = h->w.D;
+  return e;
+}
+
+// z = B r for the two-level forms; e1 (V-cycle) must already hold w D^-1 r.
+rr_status precond_two_level(rr_handle* h, Prof& pf, int tag, int kind, double lam, double omega,
+                            const LambdaSlot& sl, const double* r, double* z, hipStream_t s) {
+  Work& w = h->w;
+  const int F = h->X.F;
+  const int* done = &w.sc->done;
+  Epi er{};
+  er.scale = h->cscale;
+  er.out = w.c;
+  if (kind == PK_ADDITIVE) {
+    launch_segsum(h->restrict_plan, h->coff + 1, h->perm, nullptr, r, EPI_SCALE, er, done, s);
+    launch_gemv(h->FC, sl.Ainv, w.c, w.yc, done, s);
+    launch_prolong(F, h->labels, h->cscale, w.yc, nullptr, z, r, w.D, omega, 1, w.sc, w.partials, s);
+    return RR_OK;
+  }
+  // V(1,1): rho1 = r - A e1
+  RR_TRY(op_csr(h, pf, tag, w.e1, s));
+  Epi e = base_epi(h, lam);
+  e.p = w.e1;
+  e.r = r;
+  e.out = w.rho;
+  RR_TRY(op_csc(h, pf, tag, EPI_RESID, e, s));
+  // e2 = e1 + P A_c^-1 P^T rho1
+  launch_segsum(h->restrict_plan, h->coff + 1, h->perm, nullptr, w.rho, EPI_SCALE, er, done, s);
+  launch_gemv(h->FC, sl.Ainv, w.c, w.yc, done, s);
+  launch_prolong(F, h->labels, h->cscale, w.yc, w.e1, w.e2, nullptr, nullptr, 0.0, 0, w.sc, nullptr, s);
+  // z = e2 + w D^-1 (r - A e2), <r,z> -> beta
+  RR_TRY(op_csr(h, pf, tag, w.e2, s));
+  Epi e2 = base_epi(h, lam);
+  e2.p = w.e2;
+  e2.r = r;
+  e2.omega = omega;
+  e2.out = z;
+  RR_TRY(op_csc(h, pf, tag, EPI_POST, e2, s));
+  return RR_OK;
+}
+
+rr_status solve_impl(rr_handle* h, double lam, const double* rhs, double* wout,
+                     const rr_solve_opts* o, rr_solve_info* info, hipStream_t s) {
+  const double t0 = now_ms();
+  RR_TRY(check_lambda(lam, false));
+  if (!rhs || !wout) return fail(RR_ERR_INVALID_ARG, "null rhs or w");
+  rr_solve_opts def{};
+  const rr_solve_opts& op = o ? *o : def;
+  const int kind = op.precond;
+  if (kind < 0 || kind > 3) return fail(RR_ERR_INVALID_ARG, "unknown preconditioner");
+  if ((kind == PK_VCYCLE || kind == PK_ADDITIVE) && h->FC == 0)
+    return fail(RR_ERR_INVALID_ARG, "two-level preconditioner needs a coarse level (n_clusters > 0)");
+  if (op.fixed_iters < 0 || op.max_iter < 0 || op.chunk < 0 || op.tol < 0 || op.err_tol < 0)
+    return fail(RR_ERR_INVALID_ARG, "negative option");
+  const double tol = op.tol > 0 ? op.tol : 1e-10;
+  const int max_iter = op.max_iter > 0 ? op.max_iter : 10000;
+  const int chunk = op.chunk > 0 ? op.chunk : 8;
+  Work& w = h->w;
+  const int F = h->X.F;
+  double coarse_ms = 0.0;
+  LambdaSlot* sl = nullptr;
+  double omega = op.omega;
+  if (kind == PK_VCYCLE || kind == PK_ADDITIVE) {
+    RR_TRY(get_slot(h, lam, &sl, &coarse_ms, s));
+    if (omega == 0.0) omega = sl->omega;
+  }
+  if (!std::isfinite(omega) || omega < 0.0) return fail(RR_ERR_INVALID_ARG, "omega must be finite and >= 0");
+  launch_colnorm_diag(F, h->colnorm, lam, w.D, s);
+  if (op.rhs_is_b) {
+    launch_copy(w.b, rhs, F, s);
+  } else {
+    Epi e{};
+    e.out = w.b;
+    launch_csc(h->X, rhs, EPI_STORE, e, nullptr, s);
+  }
+  Scalars& hs = *w.sc_host;
+  std::memset(&hs, 0, sizeof(Scalars));
+  hs.tol2 = tol * tol;
+  hs.errtol2 = op.err_tol * op.err_tol;
+  hs.limit = op.fixed_iters > 0 ? op.fixed_iters : max_iter;
+  hs.fixed = op.fixed_iters;
+  hs.use_err = (op.x_ref != nullptr) ? 1 : 0;
+  hs.status = RR_ERR_NOT_CONVERGED;
+  RR_HIP(hipMemcpyAsync(w.sc, &hs, sizeof(Scalars), hipMemcpyHostToDevice, s));
+  Prof pf;
+  pf.on = op.profile != 0;
+  launch_pcg_init(F, w.b, w.x, w.r, w.p, w.z, w.e1, w.D, op.x_ref, omega, kind, w.sc, w.partials,
+                  op.residual_history, s);
+  if (kind == PK_VCYCLE || kind == PK_ADDITIVE)
+    RR_TRY(precond_two_level(h, pf, -1, kind, lam, omega, *sl, w.r, w.z, s));
+  launch_pupdate(F, w.p, w.z, w.sc, s);
+  int queued = 0;
+  for (;;) {
+    for (int c = 0; c < chunk; ++c, ++queued) {
+      RR_TRY(op_csr(h, pf, queued, w.p, s));
+      Epi e = base_epi(h, lam);
+      e.p = w.p;
+      e.out = w.q;
+      RR_TRY(op_csc(h, pf, queued, EPI_APPLY_DOT, e, s));
+      launch_pcg_update(F, w.x, w.r, w.p, w.q, w.z, w.e1, w.D, op.x_ref, omega, kind, w.sc,
+                        w.partials, op.residual_history, s);
+      if (kind == PK_VCYCLE || kind == PK_ADDITIVE)
+        RR_TRY(precond_two_level(h, pf, 100000000 + queued, kind, lam, omega, *sl, w.r, w.z, s));
+      launch_pupdate(F, w.p, w.z, w.sc, s);
+    }
+    RR_HIP(hipMemcpyAsync(&hs, w.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    RR_HIP(hipStreamSynchronize(s));
+    RR_HIP(hipGetLastError());
+    if (hs.done) break;
+    if (queued > hs.limit + 2 * chunk)
+      return fail(RR_ERR_DEVICE, "internal: iteration limit passed without the device finishing");
+  }
+  // exit: w = x and the true residual ||b - A x||
+  launch_copy(wout, w.x, F, s);
+  {
+    launch_csr(h->X, w.x, w.u, nullptr, s);
+    Epi e = base_epi(h, lam);
+    e.p = w.x;
+    e.r = w.b;
+    e.out = nullptr;
+    launch_csc(h->X, w.u, EPI_TRUE, e, nullptr, s);
+  }
+  RR_HIP(hipMemcpyAsync(&hs, w.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+  RR_HIP(hipStreamSynchronize(s));
+  RR_HIP(hipGetLastError());
+  rr_solve_info inf{};
+  inf.status = hs.status;
+  inf.iters = hs.iter;
+  // the V-cycle's two applications after the last update are skipped; the
+  // ones before the first iteration are not
+  inf.op_applies = (kind == PK_VCYCLE) ? 3 * hs.iter : hs.iter;
+  inf.relres = hs.bb > 0 ? std::sqrt(hs.rr / hs.bb) : 0.0;
+  inf.true_relres = hs.bb > 0 ? std::sqrt(hs.true_rr / hs.bb) : 0.0;
+  inf.err = hs.ref2 > 0 ? std::sqrt(hs.ee / hs.ref2) : 0.0;
+  inf.omega = omega;
+  inf.coarse_ms = coarse_ms;
+  if (pf.on) {
+    // count only launches that ran: iteration tags below the final count
+    auto acc = [&](const std::vector<std::pair<int, int>>& v, double* avg, int* n) {
+      double tot = 0.0;
+      int cnt = 0;
+      for (auto& pr : v) {
+        const int tag = pr.second;
+        const bool ran = (tag < 0) || (tag < 100000000 ? tag < hs.iter : tag - 100000000 + 1 < hs.iter);
+        if (!ran) continue;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, h->ev_pool[2 * pr.first], h->ev_pool[2 * pr.first + 1]) == hipSuccess) {
+          tot += ms;
+          ++cnt;
+        }
+      }
+      *avg = cnt ? tot / cnt : 0.0;
+      *n = cnt;
+    };
+    acc(pf.csr, &inf.csr_avg_ms, &inf.csr_launches);
+    acc(pf.csc, &inf.csc_avg_ms, &inf.csc_launches);
+  }
+  inf.ms = now_ms() - t0;
+  if (info) *info = inf;
+  if (hs.status == RR_ERR_NOT_CONVERGED)
+    return fail(RR_ERR_NOT_CONVERGED, "max_iter reached before the tolerance");
+  if (hs.status == RR_ERR_BREAKDOWN)
+    return fail(RR_ERR_BREAKDOWN, "breakdown: <p,Ap> or <r,z> not positive");
+  return RR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rr_last_error(void) { return g_last_error.c_str(); }
+
+rr_status rr_setup(const rr_csr* X, const rr_setup_opts* opts, rr_stream stream, rr_handle** out) {
+  g_last_error.clear();
+  if (!X || !out) return fail(RR_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (X->n_rows < 1 || X->n_cols < 1 || X->nnz < 0)
+    return fail(RR_ERR_INVALID_ARG, "X: need n_rows >= 1, n_cols >= 1, nnz >= 0");
+  if (X->n_rows >= (1ll << 31) - 1 || X->n_cols >= (1ll << 31) - 1 || X->nnz >= (1ll << 31) - 1 ||
+      X->n_cols + X->nnz >= (1ll << 31) - 1)
+    return fail(RR_ERR_INVALID_ARG, "X: sizes must fit 32-bit indices");
+  if (!X->row_ptr || (X->nnz > 0 && !X->col_idx))
+    return fail(RR_ERR_INVALID_ARG, "X: null row_ptr or col_idx");
+  if (opts && (opts->n_clusters < 0 || opts->kmeans_max_iter < 0 || opts->lambda_slots < 0))
+    return fail(RR_ERR_INVALID_ARG, "negative option");
+  rr_handle* h = new (std::nothrow) rr_handle();
+  if (!h) return fail(RR_ERR_DEVICE, "out of host memory");
+  rr_status st = setup_impl(X, opts, (hipStream_t)stream, h);
+  if (st != RR_OK) {
+    const std::string msg = g_last_error;
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    destroy_handle(h);
+    g_last_error = msg;
+    return st;
+  }
+  *out = h;
+  return RR_OK;
+}
+
+rr_status rr_destroy(rr_handle* h) {
+  if (!h) return RR_OK;
+  (void)hipDeviceSynchronize();
+  destroy_handle(h);
+  return RR_OK;
+}
+
+rr_status rr_get_setup_info(const rr_handle* h, rr_setup_info* info) {
+  RR_TRY(check_handle(h));
+  if (!info) return fail(RR_ERR_INVALID_ARG, "null info");
+  rr_setup_info i{};
+  i.n_rows = h->X.N;
+  i.n_cols = h->X.F;
+  i.nnz = h->X.nnz;
+  i.n_coarse = h->FC;
+  i.n_centres = h->n_centres;
+  i.kmeans_iters = h->kmeans_iters;
+  i.binary = h->X.binary ? 1 : 0;
+  i.setup_ms = h->setup_ms;
+  i.kmeans_ms = h->kmeans_ms;
+  *info = i;
+  return RR_OK;
+}
+
+rr_status rr_get_labels(const rr_handle* h, int32_t* labels, rr_stream stream) {
+  RR_TRY(check_handle(h));
+  if (!labels) return fail(RR_ERR_INVALID_ARG, "null labels");
+  if (h->FC == 0) return fail(RR_ERR_INVALID_ARG, "no aggregation (n_clusters = 0)");
+  RR_HIP(hipMemcpyAsync(labels, h->labels, sizeof(int) * h->X.F, hipMemcpyDeviceToDevice,
+                        (hipStream_t)stream));
+  return RR_OK;
+}
+
+rr_status rr_get_centres(const rr_handle* h, int32_t* centres, rr_stream stream) {
+  RR_TRY(check_handle(h));
+  if (!centres) return fail(RR_ERR_INVALID_ARG, "null centres");
+  if (!h->centres || h->n_centres == 0) return fail(RR_ERR_INVALID_ARG, "no k-means seeding was run");
+  RR_HIP(hipMemcpyAsync(centres, h->centres, sizeof(int) * h->n_centres, hipMemcpyDeviceToDevice,
+                        (hipStream_t)stream));
+  return RR_OK;
+}
+
+rr_status rr_solve(rr_handle* h, double lambda, const double* rhs, double* w,
+                   const rr_solve_opts* opts, rr_solve_info* info, rr_stream stream) {
+  g_last_error.clear();
+  RR_TRY(check_handle(h));
+  return solve_impl(h, lambda, rhs, w, opts, info, (hipStream_t)stream);
+}
+
+rr_status rr_apply_operator(rr_handle* h, double lambda, const double* v, double* Av,
+                            rr_stream stream) {
+  RR_TRY(check_handle(h));
+  RR_TRY(check_lambda(lambda, true));
+  if (!v || !Av) return fail(RR_ERR_INVALID_ARG, "null vector");
+  hipStream_t s = (hipStream_t)stream;
+  launch_csr(h->X, v, h->w.u, nullptr, s);
+  Epi e = base_epi(h, lambda);
+  e.p = v;
+  e.out = Av;
+  launch_csc(h->X, h->w.u, EPI_APPLY, e, nullptr, s);
+  RR_HIP(hipGetLastError());
+  return RR_OK;
+}
+
+rr_status rr_apply_rhs(rr_handle* h, const double* y, double* b, rr_stream stream) {
+  RR_TRY(check_handle(h));
+  if (!y || !b) return fail(RR_ERR_INVALID_ARG, "null vector");
+  Epi e{};
+  e.out = b;
+  launch_csc(h->X, y, EPI_STORE, e, nullptr, (hipStream_t)stream);
+  RR_HIP(hipGetLastError());
+  return RR_OK;
+}
+
+rr_status rr_apply_precond(rr_handle* h, double lambda, int32_t precond, double omega,
+                           const double* r, double* z, rr_stream stream) {
+  RR_TRY(check_handle(h));
+  RR_TRY(check_lambda(lambda, false));
+  if (!r || !z) return fail(RR_ERR_INVALID_ARG, "null vector");
+  if (precond < 0 || precond > 3) return fail(RR_ERR_INVALID_ARG, "unknown preconditioner");
+  hipStream_t s = (hipStream_t)stream;
+  Work& w = h->w;
+  const int F = h->X.F;
+  launch_colnorm_diag(F, h->colnorm, lambda, w.D, s);
+  if (precond == PK_NONE) {
+    launch_copy(z, r, F, s);
+    return RR_OK;
+  }
+  if (precond == PK_JACOBI) {
+    launch_jacobi_apply(F, r, w.D, z, s);
+    return RR_OK;
+  }
+  if (h->FC == 0) return fail(RR_ERR_INVALID_ARG, "two-level preconditioner needs a coarse level");
+  LambdaSlot* sl = nullptr;
+  double ms = 0.0;
+  RR_TRY(get_slot(h, lambda, &sl, &ms, s));
+  if (omega == 0.0) omega = sl->omega;
+  if (!std::isfinite(omega) || omega < 0.0) return fail(RR_ERR_INVALID_ARG, "omega must be finite and >= 0");
+  Scalars& hs = *w.sc_host;
+  std::memset(&hs, 0, sizeof(Scalars));
+  hs.rz = 1.0;
+  RR_HIP(hipMemcpyAsync(w.sc, &hs, sizeof(Scalars), hipMemcpyHostToDevice, s));
+  if (precond == PK_VCYCLE) k_smooth<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, r, w.D, omega, w.e1);
+  Prof pf;
+  RR_TRY(precond_two_level(h, pf, 0, precond, lambda, omega, *sl, r, z, s));
+  RR_HIP(hipStreamSynchronize(s));
+  RR_HIP(hipGetLastError());
+  return RR_OK;
+}
+
+rr_status rr_coarse_gram(rr_handle* h, double* K, rr_stream stream) {
+  RR_TRY(check_handle(h));
+  if (!K) return fail(RR_ERR_INVALID_ARG, "null K");
+  if (h->FC == 0) return fail(RR_ERR_INVALID_ARG, "no coarse level");
+  RR_HIP(hipMemcpyAsync(K, h->K, sizeof(double) * h->FC * h->FC, hipMemcpyDeviceToDevice,
+                        (hipStream_t)stream));
+  return RR_OK;
+}
+
+rr_status rr_coarse_factor(rr_handle* h, double lambda, double* L, double* Ainv, rr_stream stream) {
+  RR_TRY(check_handle(h));
+  RR_TRY(check_lambda(lambda, false));
+  if (h->FC == 0) return fail(RR_ERR_INVALID_ARG, "no coarse level");
+  hipStream_t s = (hipStream_t)stream;
+  LambdaSlot* sl = nullptr;
+  double ms = 0.0;
+  RR_TRY(get_slot(h, lambda, &sl, &ms, s));
+  const size_t bytes = sizeof(double) * h->FC * h->FC;
+  if (L) RR_HIP(hipMemcpyAsync(L, sl->L, bytes, hipMemcpyDeviceToDevice, s));
+  if (Ainv) RR_HIP(hipMemcpyAsync(Ainv, sl->Ainv, bytes, hipMemcpyDeviceToDevice, s));
+  return RR_OK;
+}
+
+rr_status rr_smoother_weight(rr_handle* h, double lambda, double* omega) {
+  RR_TRY(check_handle(h));
+  RR_TRY(check_lambda(lambda, false));
+  if (!omega) return fail(RR_ERR_INVALID_ARG, "null omega");
+  return auto_omega(h, lambda, omega, nullptr);
+}
+
+}  // extern "C"

@@ -1,0 +1,509 @@
+// The matrix-free operator v -> X^T (X v) + lambda v as two sparse passes:
+//   u = X v     CSR, a fixed group of lanes per row (rows are short and even)
+//   t = X^T u   CSC, merge-path tiles over (column ends + nonzeros), so the
+//               Zipf-skewed column lengths cost the same per tile; columns
+//               that cross tiles are finished by a small fix-up kernel that
+//               adds the tile partials in tile order (deterministic).
+// Only the matrix-vector product is needed by the Krylov method (the paper's
+// introduction); X^T X is never formed.
+#include <climits>
+
+#include <cstring>
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include "rr_device.h"
+
+namespace rr {
+
+// ---------------------------------------------------------------------------
+// CSR: u[i] = sum_{e in row i} v[col[e]] (* val[e])
+// ---------------------------------------------------------------------------
+template <int G, bool BIN>
+__global__ __launch_bounds__(kBlock) void k_csr(const int* __restrict__ ptr,
+                                                const int* __restrict__ idx,
+                                                const double* __restrict__ val,
+                                                const double* __restrict__ v,
+                                                double* __restrict__ u, int nrows,
+                                                const int* done) {
+  if (is_done(done)) return;
+  const int lane = threadIdx.x & (G - 1);
+  const int row = (blockIdx.x * kBlock + threadIdx.x) / G;
+  if (row >= nrows) return;  // whole G-lane group leaves together
+  const int a = ptr[row], b = ptr[row + 1];
+  double acc0 = 0.0, acc1 = 0.0;
+  int e = a + lane;
+  for (; e + G < b; e += 2 * G) {
+    const int c0 = idx[e], c1 = idx[e + G];
+    double x0 = v[c0], x1 = v[c1];
+    if (!BIN) {
+      x0 *= val[e];
+      x1 *= val[e + G];
+    }
+    acc0 += x0;
+    acc1 += x1;
+  }
+  if (e < b) {
+    double x0 = v[idx[e]];
+    if (!BIN) x0 *= val[e];
+    acc0 += x0;
+  }
+  double acc = acc0 + acc1;
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+  if (lane == 0) u[row] = acc;
+}
+
+template <int G>
+static void csr_dispatch(const Sparse& X, const double* v, double* u, const int* done,
+                         hipStream_t s) {
+  const int grid = cdiv((long long)X.N * G, kBlock);
+  if (X.binary)
+    k_csr<G, true><<<grid, kBlock, 0, s>>>(X.row_ptr, X.col_idx, nullptr, v, u, X.N, done);
+  else
+    k_csr<G, false><<<grid, kBlock, 0, s>>>(X.row_ptr, X.col_idx, X.val, v, u, X.N, done);
+}
+
+void launch_csr(const Sparse& X, const double* v, double* u, const int* done,
+                hipStream_t s) {
+  if (X.N == 0) return;
+  switch (X.csr_group) {
+    case 4: csr_dispatch<4>(X, v, u, done, s); break;
+    case 8: csr_dispatch<8>(X, v, u, done, s); break;
+    case 16: csr_dispatch<16>(X, v, u, done, s); break;
+    case 32: csr_dispatch<32>(X, v, u, done, s); break;
+    default: csr_dispatch<64>(X, v, u, done, s); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Segment epilogues
+// ---------------------------------------------------------------------------
+template <int MODE>
+__device__ inline void seg_finish(int s, double t, const Epi& e, double& dot) {
+  if constexpr (MODE == EPI_STORE) {
+    e.out[s] = t;
+  } else if constexpr (MODE == EPI_APPLY) {
+    e.out[s] = t + e.lam * e.p[s];
+  } else if constexpr (MODE == EPI_APPLY_DOT) {
+    const double ps = e.p[s];
+    const double q = t + e.lam * ps;
+    e.out[s] = q;
+    dot += ps * q;
+  } else if constexpr (MODE == EPI_RESID) {
+    e.out[s] = e.r[s] - (t + e.lam * e.p[s]);
+  } else if constexpr (MODE == EPI_POST) {
+    const double e2 = e.p[s];
+    const double rs = e.r[s];
+    const double rho = rs - (t + e.lam * e2);
+    const double z = e2 + (e.omega * rho) / e.D[s];
+    e.out[s] = z;
+    dot += rs * z;
+  } else if constexpr (MODE == EPI_TRUE) {
+    const double res = e.r[s] - (t + e.lam * e.p[s]);
+    if (e.out) e.out[s] = res;
+    dot += res * res;
+  } else if constexpr (MODE == EPI_SCALE) {
+    e.out[s] = t * e.scale[s];
+  }
+}
+
+template <int MODE>
+constexpr bool has_dot() {
+  return MODE == EPI_APPLY_DOT || MODE == EPI_POST || MODE == EPI_TRUE;
+}
+
+template <int MODE>
+__device__ inline void dot_finish(const Epi& e, double tot) {
+  if constexpr (MODE == EPI_APPLY_DOT) finish_alpha(e.sc, tot);
+  if constexpr (MODE == EPI_POST) finish_beta(e.sc, tot);
+  if constexpr (MODE == EPI_TRUE) e.sc->true_rr = tot;
+}
+
+// ---------------------------------------------------------------------------
+// Merge-path segmented gather-sum.  The merged list holds, for every
+// segment, its nonzeros followed by an end marker.  Tile b covers merged
+// items [b*T, (b+1)*T); coord[b] = (segments ended before, nonzeros before).
+// ---------------------------------------------------------------------------
+__device__ inline int merge_search(int diag, int alen, int blen, const int* a_end) {
+  // number of segment ends among the first `diag` merged items
+  int lo = max(0, diag - blen), hi = min(diag, alen);
+  while (lo < hi) {
+    const int m = (lo + hi) >> 1;
+    if (a_end[m] <= diag - m - 1)
+      lo = m + 1;
+    else
+      hi = m;
+  }
+  return lo;
+}
+
+__global__ void k_merge_coord(const int* __restrict__ seg_end, int nseg, int nnz,
+                              int nblocks, int2* __restrict__ coord) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b > nblocks) return;
+  const long long total = (long long)nseg + nnz;
+  const int diag = (int)min((long long)b * kMergeTile, total);
+  const int x = merge_search(diag, nseg, nnz, seg_end);
+  coord[b] = make_int2(x, diag - x);
+}
+
+template <int MODE, bool BIN>
+__global__ __launch_bounds__(kBlock) void k_segsum(
+    const int* __restrict__ seg_end, const int* __restrict__ idx,
+    const double* __restrict__ val, const double* __restrict__ v,
+    const int2* __restrict__ coord, double* __restrict__ head, double* __restrict__ tail,
+    int nseg, int nslots, Epi e, const int* done) {
+  if (is_done(done)) return;
+  __shared__ int s_end[kMergeTile + 1];
+  __shared__ double s_val[kMergeTile];
+  __shared__ int s_flag[kBlock];
+  __shared__ double s_acc[kBlock];
+
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int2 c0 = coord[b], c1 = coord[b + 1];
+  const int x0 = c0.x, y0 = c0.y;
+  const int nx = c1.x - x0, ny = c1.y - y0;
+  const int total = nx + ny;
+
+  for (int i = tid; i <= nx; i += kBlock)
+    s_end[i] = (x0 + i < nseg) ? seg_end[x0 + i] - y0 : INT_MAX;
+  for (int i = tid; i < ny; i += kBlock) {
+    const int g = y0 + i;
+    double a = v[idx[g]];
+    if (!BIN) a *= val[g];
+    s_val[i] = a;
+  }
+  __syncthreads();
+
+  const int d = min(tid * kMergeItems, total);
+  const int dend = min(d + kMergeItems, total);
+  const int x = merge_search(d, nx, ny, s_end);
+  const int y = d - x;
+
+  // pass 1: the partial sum of the segment this thread's range ends in
+  double acc = 0.0;
+  int saw = 0;
+  {
+    int xx = x, yy = y;
+#pragma unroll
+    for (int k = 0; k < kMergeItems; ++k) {
+      if (d + k < dend) {
+        if (yy < s_end[xx]) {
+          acc += s_val[yy];
+          ++yy;
+        } else {
+          acc = 0.0;
+          saw = 1;
+          ++xx;
+        }
+      }
+    }
+  }
+  // segmented inclusive scan over threads: (f1,v1) + (f2,v2) = (f1|f2, f2 ? v2 : v1+v2)
+  s_flag[tid] = saw;
+  s_acc[tid] = acc;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    int f = s_flag[tid];
+    double vv = s_acc[tid];
+    if (tid >= off) {
+      if (!f) vv = s_acc[tid - off] + vv;
+      f |= s_flag[tid - off];
+    }
+    __syncthreads();
+    s_flag[tid] = f;
+    s_acc[tid] = vv;
+    __syncthreads();
+  }
+  const double carry = tid ? s_acc[tid - 1] : 0.0;
+
+  // pass 2: finish every segment whose end marker lies in this thread's range
+  const int seg_start0 = (x0 > 0) ? seg_end[x0 - 1] : 0;
+  const bool mid = seg_start0 < y0;   // tile begins inside segment x0
+  double dot = 0.0;
+  acc = carry;
+  {
+    int xx = x, yy = y;
+#pragma unroll
+    for (int k = 0; k < kMergeItems; ++k) {
+      if (d + k < dend) {
+        if (yy < s_end[xx]) {
+          acc += s_val[yy];
+          ++yy;
+        } else {
+          if (xx == 0 && mid)
+            head[b] = acc;
+          else
+            seg_finish<MODE>(x0 + xx, acc, e, dot);
+          acc = 0.0;
+          ++xx;
+        }
+      }
+    }
+  }
+  if (d < dend && dend == total) tail[b] = acc;
+  if constexpr (has_dot<MODE>()) {
+    double vv[1] = {dot};
+    write_partial<1>(vv, e.partials, b, nslots);
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_segfix(const int4* __restrict__ span, int nspan,
+                                                   const double* __restrict__ head,
+                                                   const double* __restrict__ tail,
+                                                   int nmain, Epi e, const int* done) {
+  if (is_done(done)) return;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  double dot = 0.0;
+  if (i < nspan) {
+    const int4 sp = span[i];
+    double acc = tail[sp.y];
+    for (int bb = sp.y + 1; bb < sp.z; ++bb) acc += tail[bb];
+    acc += head[sp.z];
+    seg_finish<MODE>(sp.x, acc, e, dot);
+  }
+  if constexpr (has_dot<MODE>()) {
+    double vv[1] = {dot}, tot[1];
+    if (grid_finish<1>(vv, e.partials, nmain, nmain + gridDim.x, &e.sc->ticket, tot)) {
+      if (threadIdx.x == 0) dot_finish<MODE>(e, tot[0]);
+    }
+  }
+}
+
+template <int MODE>
+static void segsum_mode(const MergePlan& mp, const int* seg_end, const int* idx,
+                        const double* val, const double* v, const Epi& e, const int* done,
+                        hipStream_t s) {
+  const int nfix = std::max(1, cdiv(mp.nspan, kBlock));
+  const int nslots = mp.nblocks + nfix;
+  if (val)
+    k_segsum<MODE, false><<<mp.nblocks, kBlock, 0, s>>>(seg_end, idx, val, v, mp.coord, mp.head,
+                                                       mp.tail, mp.nseg, nslots, e, done);
+  else
+    k_segsum<MODE, true><<<mp.nblocks, kBlock, 0, s>>>(seg_end, idx, nullptr, v, mp.coord,
+                                                      mp.head, mp.tail, mp.nseg, nslots, e,
+                                                      done);
+  if (mp.nspan > 0 || has_dot<MODE>())
+    k_segfix<MODE><<<nfix, kBlock, 0, s>>>(mp.span, mp.nspan, mp.head, mp.tail, mp.nblocks, e,
+                                           done);
+}
+
+void launch_segsum(const MergePlan& mp, const int* seg_end, const int* idx, const double* val,
+                   const double* v, int mode, const Epi& e, const int* done, hipStream_t s) {
+  if (mp.nblocks == 0) return;
+  switch (mode) {
+    case EPI_STORE: segsum_mode<EPI_STORE>(mp, seg_end, idx, val, v, e, done, s); break;
+    case EPI_APPLY: segsum_mode<EPI_APPLY>(mp, seg_end, idx, val, v, e, done, s); break;
+    case EPI_APPLY_DOT: segsum_mode<EPI_APPLY_DOT>(mp, seg_end, idx, val, v, e, done, s); break;
+    case EPI_RESID: segsum_mode<EPI_RESID>(mp, seg_end, idx, val, v, e, done, s); break;
+    case EPI_POST: segsum_mode<EPI_POST>(mp, seg_end, idx, val, v, e, done, s); break;
+    case EPI_TRUE: segsum_mode<EPI_TRUE>(mp, seg_end, idx, val, v, e, done, s); break;
+    case EPI_SCALE: segsum_mode<EPI_SCALE>(mp, seg_end, idx, val, v, e, done, s); break;
+  }
+}
+
+void launch_csc(const Sparse& X, const double* u, int mode, const Epi& e, const int* done,
+                hipStream_t s) {
+  launch_segsum(X.csc_plan, X.col_ptr + 1, X.row_idx, X.binary ? nullptr : X.cval, u, mode, e,
+                done, s);
+}
+
+// ---------------------------------------------------------------------------
+// Plan construction (setup only)
+// ---------------------------------------------------------------------------
+__global__ void k_block_seg_start(const int2* coord, const int* seg_ptr, int nblocks,
+                                  int* out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nblocks) out[b] = seg_ptr[coord[b].x];
+}
+
+void free_merge_plan(MergePlan& mp) {
+  if (mp.coord) (void)hipFree(mp.coord);
+  if (mp.span) (void)hipFree(mp.span);
+  if (mp.head) (void)hipFree(mp.head);
+  if (mp.tail) (void)hipFree(mp.tail);
+  mp = MergePlan{};
+}
+
+// seg_end = ptr + 1 (nseg entries), seg_ptr = ptr (nseg + 1 entries).
+rr_status build_merge_plan(MergePlan& mp, const int* d_seg_end, const int* d_seg_ptr, int nseg,
+                           int nnz, hipStream_t s) {
+  free_merge_plan(mp);
+  mp.nseg = nseg;
+  mp.nnz = nnz;
+  const long long total = (long long)nseg + nnz;
+  if (total == 0) return RR_OK;
+  if (total >= INT_MAX) return fail(RR_ERR_INVALID_ARG, "merge plan: segments + nonzeros >= 2^31");
+  mp.nblocks = cdiv(total, kMergeTile);
+  RR_HIP(hipMalloc(&mp.coord, sizeof(int2) * (mp.nblocks + 1)));
+  RR_HIP(hipMalloc(&mp.head, sizeof(double) * mp.nblocks));
+  RR_HIP(hipMalloc(&mp.tail, sizeof(double) * mp.nblocks));
+  k_merge_coord<<<cdiv(mp.nblocks + 1, kBlock), kBlock, 0, s>>>(d_seg_end, nseg, nnz, mp.nblocks,
+                                                               mp.coord);
+  int* d_start = nullptr;
+  RR_HIP(hipMalloc(&d_start, sizeof(int) * mp.nblocks));
+  k_block_seg_start<<<cdiv(mp.nblocks, kBlock), kBlock, 0, s>>>(mp.coord, d_seg_ptr, mp.nblocks,
+                                                               d_start);
+  std::vector<int2> coord(mp.nblocks + 1);
+  std::vector<int> start(mp.nblocks);
+  RR_HIP(hipMemcpyAsync(coord.data(), mp.coord, sizeof(int2) * (mp.nblocks + 1),
+                        hipMemcpyDeviceToHost, s));
+  RR_HIP(hipMemcpyAsync(start.data(), d_start, sizeof(int) * mp.nblocks, hipMemcpyDeviceToHost,
+                        s));
+  RR_HIP(hipStreamSynchronize(s));
+  RR_HIP(hipFree(d_start));
+  // Segments that cross tiles: a run of tiles b_a..b_z that all begin inside
+  // segment s; s started in tile b_a - 1 and ends in tile b_z.
+  std::vector<int4> spans;
+  int b = 1;
+  while (b < mp.nblocks) {
+    const bool mid = start[b] < coord[b].y;
+    if (!mid) {
+      ++b;
+      continue;
+    }
+    const int seg = coord[b].x;
+    int bz = b;
+    while (bz + 1 < mp.nblocks && coord[bz + 1].x == seg && start[bz + 1] < coord[bz + 1].y) ++bz;
+    spans.push_back(make_int4(seg, b - 1, bz, 0));
+    b = bz + 1;
+  }
+  mp.nspan = (int)spans.size();
+  if (mp.nspan) {
+    RR_HIP(hipMalloc(&mp.span, sizeof(int4) * mp.nspan));
+    RR_HIP(hipMemcpyAsync(mp.span, spans.data(), sizeof(int4) * mp.nspan, hipMemcpyHostToDevice,
+                          s));
+    RR_HIP(hipStreamSynchronize(s));
+  }
+  return RR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Input validation and the CSC transpose (setup only)
+// ---------------------------------------------------------------------------
+__global__ void k_validate(const int* ptr, const int* idx, const double* val, int N, int F,
+                           int nnz, int* flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > N) return;
+  if (i == 0 && ptr[0] != 0) atomicOr(flag, 1);
+  if (i == N) {
+    if (ptr[N] != nnz) atomicOr(flag, 1);
+    return;
+  }
+  const int a = ptr[i], b = ptr[i + 1];
+  if (b < a || a < 0 || b > nnz) {
+    atomicOr(flag, 1);
+    return;
+  }
+  int prev = -1;
+  for (int e = a; e < b; ++e) {
+    const int c = idx[e];
+    if (c < 0 || c >= F) atomicOr(flag, 2);
+    if (c <= prev) atomicOr(flag, 4);
+    prev = c;
+    if (val) {
+      const double x = val[e];
+      if (!(x == x) || x == __builtin_inf() || x == -__builtin_inf()) atomicOr(flag, 8);
+      if (x < 0.0) atomicOr(flag, 16);
+    }
+  }
+}
+
+rr_status validate_csr(const Sparse& X, hipStream_t s) {
+  int* d_flag = nullptr;
+  RR_HIP(hipMalloc(&d_flag, sizeof(int)));
+  RR_HIP(hipMemsetAsync(d_flag, 0, sizeof(int), s));
+  k_validate<<<cdiv(X.N + 1, kBlock), kBlock, 0, s>>>(X.row_ptr, X.col_idx, X.val, X.N, X.F,
+                                                      X.nnz, d_flag);
+  int flag = 0;
+  RR_HIP(hipMemcpyAsync(&flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  RR_HIP(hipStreamSynchronize(s));
+  RR_HIP(hipFree(d_flag));
+  if (flag & 1) return fail(RR_ERR_INVALID_ARG, "X: row_ptr is not a valid CSR pointer array");
+  if (flag & 2) return fail(RR_ERR_INVALID_ARG, "X: column index out of range");
+  if (flag & 4) return fail(RR_ERR_INVALID_ARG, "X: column indices not strictly increasing in a row");
+  if (flag & 8) return fail(RR_ERR_INVALID_ARG, "X: non-finite value");
+  return (flag & 16) ? RR_ERR_UNSUPPORTED : RR_OK;   // caller records "has negatives"
+}
+
+__global__ void k_expand_rows(const int* ptr, int N, int* row_of) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  for (int e = ptr[i]; e < ptr[i + 1]; ++e) row_of[e] = i;
+}
+
+__global__ void k_iota(int* a, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = i;
+}
+
+__global__ void k_lower_bound_ptr(const int* keys, int n, int nseg, int* ptr) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > nseg) return;
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int m = (lo + hi) >> 1;
+    if (keys[m] < j)
+      lo = m + 1;
+    else
+      hi = m;
+  }
+  ptr[j] = lo;
+}
+
+__global__ void k_gather_csc(const int* order, const int* row_of, const double* val, int nnz,
+                             int* row_idx, double* cval) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  const int e = order[k];
+  row_idx[k] = row_of[e];
+  if (val) cval[k] = val[e];
+}
+
+static unsigned bits_for(int n) {
+  unsigned b = 1;
+  while ((1ll << b) < (long long)n) ++b;
+  return b;
+}
+
+// CSC by a stable radix sort of (column, CSR position): rows stay increasing
+// inside every column, so the transpose is deterministic.
+rr_status build_csc(Sparse& X, hipStream_t s) {
+  const int nnz = X.nnz;
+  RR_HIP(hipMalloc(&X.col_ptr, sizeof(int) * (X.F + 1)));
+  RR_HIP(hipMalloc(&X.row_idx, sizeof(int) * std::max(nnz, 1)));
+  if (!X.binary) RR_HIP(hipMalloc(&X.cval, sizeof(double) * std::max(nnz, 1)));
+  if (nnz == 0) {
+    RR_HIP(hipMemsetAsync(X.col_ptr, 0, sizeof(int) * (X.F + 1), s));
+    return build_merge_plan(X.csc_plan, X.col_ptr + 1, X.col_ptr, X.F, 0, s);
+  }
+  int *row_of = nullptr, *pos = nullptr, *keys_out = nullptr, *pos_out = nullptr;
+  RR_HIP(hipMalloc(&row_of, sizeof(int) * nnz));
+  RR_HIP(hipMalloc(&pos, sizeof(int) * nnz));
+  RR_HIP(hipMalloc(&keys_out, sizeof(int) * nnz));
+  RR_HIP(hipMalloc(&pos_out, sizeof(int) * nnz));
+  k_expand_rows<<<cdiv(X.N, kBlock), kBlock, 0, s>>>(X.row_ptr, X.N, row_of);
+  k_iota<<<cdiv(nnz, kBlock), kBlock, 0, s>>>(pos, nnz);
+  size_t tmp_bytes = 0;
+  const unsigned end_bit = bits_for(X.F);
+  RR_HIP(rocprim::radix_sort_pairs(nullptr, tmp_bytes, X.col_idx, keys_out, pos, pos_out,
+                                   (size_t)nnz, 0u, end_bit, s));
+  void* tmp = nullptr;
+  RR_HIP(hipMalloc(&tmp, std::max<size_t>(tmp_bytes, 1)));
+  RR_HIP(rocprim::radix_sort_pairs(tmp, tmp_bytes, X.col_idx, keys_out, pos, pos_out, (size_t)nnz,
+                                   0u, end_bit, s));
+  k_lower_bound_ptr<<<cdiv(X.F + 1, kBlock), kBlock, 0, s>>>(keys_out, nnz, X.F, X.col_ptr);
+  k_gather_csc<<<cdiv(nnz, kBlock), kBlock, 0, s>>>(pos_out, row_of, X.binary ? nullptr : X.val,
+                                                    nnz, X.row_idx, X.cval);
+  RR_HIP(hipStreamSynchronize(s));
+  RR_HIP(hipFree(tmp));
+  RR_HIP(hipFree(row_of));
+  RR_HIP(hipFree(pos));
+  RR_HIP(hipFree(keys_out));
+  RR_HIP(hipFree(pos_out));
+  return build_merge_plan(X.csc_plan, X.col_ptr + 1, X.col_ptr, X.F, nnz, s);
+}
+
+}  // namespace rr

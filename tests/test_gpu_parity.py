@@ -1,0 +1,275 @@
+"""GPU parity: the HIP path, called through the C ABI, against the CPU oracle
+on the same seeded inputs (datagen).  Sizes span many kernel tiles with
+ragged tails; the full-size binary-fingerprint case is in
+test_gpu_fullsize.py.
+
+Bars: integer/index work bit-exact (operator on integer vectors, k-means
+centres and labels); FP64 results within 1e-10 relative of the oracle at
+equal iteration counts, natural-stop iteration counts within +-1."""
+import numpy as np
+import pytest
+
+import datagen
+from oracle import coarse, kmeans, krylov, operator as op, precond
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rr():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1806_05826_amd as rr
+    return rr
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+CASES = {
+    "tiny": lambda: datagen.tiny_sparse(),
+    "mid": lambda: datagen.mid_sparse(),
+    "ragged": lambda: datagen.sparse_problem(3001, 1237, 7, seed=77),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request, rr):
+    P = CASES[request.param]()
+    print(f"[case {request.param}] N={P.X.shape[0]} F={P.X.shape[1]} nnz={P.X.nnz}", flush=True)
+    return request.param, P
+
+
+# --- operator ------------------------------------------------------------------
+
+def test_operator_exact_on_integers(rr, case):
+    name, P = case
+    R = rr.Ridge(P.X)
+    v = np.random.default_rng(1).integers(-60, 60, size=P.X.shape[1]).astype(np.float64)
+    got = host(R.apply_operator(3.0, v))
+    ref = op.apply_A(P.X, 3.0, v)
+    assert np.array_equal(got, ref)
+    R.close()
+
+
+def test_operator_random(rr, case):
+    name, P = case
+    R = rr.Ridge(P.X)
+    v = np.random.default_rng(2).standard_normal(P.X.shape[1])
+    got = host(R.apply_operator(0.37, v))
+    ref = op.apply_A(P.X, 0.37, v)
+    Xa = abs(P.X)
+    scale = Xa.T @ (Xa @ np.abs(v)) + 0.37 * np.abs(v)
+    assert np.all(np.abs(got - ref) <= 1e-13 * scale + 1e-300)
+    b = host(R.apply_rhs(P.y))
+    assert np.allclose(b, op.rhs(P.X, P.y), rtol=1e-13, atol=1e-12)
+    R.close()
+
+
+# --- k-means ---------------------------------------------------------------------
+
+KM = {"tiny": (50, 42), "mid": (300, 7), "ragged": (97, 3)}
+
+
+@pytest.fixture(scope="module")
+def clustered(rr, case):
+    name, P = case
+    k, seed = KM[name]
+    lab, fc, it, centres = kmeans.kmeans_features(P.X, k, seed)
+    R = rr.Ridge(P.X, n_clusters=k, seed=seed)
+    return name, P, R, (lab, fc, it, centres)
+
+
+def test_kmeans_bit_exact(rr, clustered):
+    name, P, R, (lab, fc, it, centres) = clustered
+    info = R.info
+    assert info["n_centres"] == len(centres)
+    assert np.array_equal(host(R.centres()), centres)
+    assert info["kmeans_iters"] == it
+    assert info["n_coarse"] == fc
+    assert np.array_equal(host(R.labels()), lab)
+
+
+def test_coarse_gram_and_factor(rr, clustered):
+    name, P, R, (lab, fc, it, centres) = clustered
+    K = host(R.coarse_gram())
+    Kref = coarse.coarse_gram(P.X, lab, fc)
+    assert np.max(np.abs(K - Kref)) <= 1e-13 * np.max(np.abs(Kref))
+    lam = 0.5
+    L, Ai = (host(t) for t in R.coarse_factor(lam))
+    Lref = coarse.cholesky(Kref + lam * np.eye(fc))
+    assert np.max(np.abs(L - Lref)) <= 1e-12 * np.max(np.abs(Lref))
+    Airef = np.linalg.inv(Kref + lam * np.eye(fc))
+    assert np.max(np.abs(Ai - Airef)) <= 1e-10 * np.max(np.abs(Airef))
+
+
+@pytest.mark.parametrize("kind", ["jacobi", "vcycle", "additive"])
+def test_precond_parity(rr, clustered, kind):
+    name, P, R, (lab, fc, it, centres) = clustered
+    lam = 1.0
+    r = np.random.default_rng(5).standard_normal(P.X.shape[1])
+    omega = op.omega_gershgorin(P.X, lam)
+    assert abs(R.smoother_weight(lam) - omega) <= 1e-15 * omega
+    B, _ = precond.make(kind, P.X, lam, lab, fc, omega)
+    z = host(R.apply_precond(lam, r, kind))
+    zr = B(r)
+    assert np.linalg.norm(z - zr) <= 1e-12 * np.linalg.norm(zr)
+
+
+@pytest.mark.parametrize("kind", ["none", "jacobi", "vcycle", "additive"])
+def test_solve_parity(rr, clustered, kind):
+    name, P, R, (lab, fc, it, centres) = clustered
+    lam = 1.0
+    x_or, inf_or = krylov.solve(P.X, P.y, lam, kind, lab, fc, tol=1e-10, max_iter=5000)
+    # natural stop: iterations within one, residuals at tolerance
+    w, info = R.solve(lam, P.y, precond=kind, tol=1e-10, max_iter=5000)
+    assert info["status"] == 0
+    assert abs(info["iters"] - inf_or.iters) <= 1
+    assert info["relres"] <= 1e-10
+    assert info["true_relres"] <= 2e-10
+    # equal iteration counts: iterates agree to 1e-10
+    k = inf_or.iters
+    x_k, _ = krylov.solve(P.X, P.y, lam, kind, lab, fc, fixed_iters=k)
+    w, info = R.solve(lam, P.y, precond=kind, fixed_iters=k)
+    assert info["iters"] == k
+    wk = host(w)
+    assert np.linalg.norm(wk - x_k) <= 1e-10 * np.linalg.norm(x_k)
+
+
+def test_residual_history_and_error_target(rr, clustered):
+    name, P, R, (lab, fc, it, centres) = clustered
+    lam = 1.0
+    wst = krylov.reference_solution(P.X, P.y, lam) if P.X.shape[1] <= 4000 else None
+    if wst is None:
+        pytest.skip("dense reference too large")
+    x, inf = krylov.solve(P.X, P.y, lam, "vcycle", lab, fc, tol=1e-10, x_ref=wst)
+    hist = torch.zeros(200, dtype=torch.float64, device="cuda")
+    w, info = R.solve(lam, P.y, precond="vcycle", tol=1e-10, residual_history=hist)
+    h = host(hist)[: info["iters"] + 1]
+    assert np.allclose(h, inf.history[: len(h)], rtol=1e-6, atol=1e-14)
+    # stop on the error against w* instead of the residual
+    first = next(i for i, e in enumerate(inf.err_history) if e <= 1e-10)
+    w, info = R.solve(lam, P.y, precond="vcycle", tol=1e-300, x_ref=dev(wst), err_tol=1e-10)
+    assert abs(info["iters"] - first) <= 1
+    assert info["err"] <= 1e-10
+
+
+def test_deterministic(rr, clustered):
+    name, P, R, _ = clustered
+    w1, i1 = R.solve(1.0, P.y, precond="vcycle", fixed_iters=15)
+    w2, i2 = R.solve(1.0, P.y, precond="vcycle", fixed_iters=15)
+    assert torch.equal(w1, w2)
+
+
+# --- aggregation given from outside ----------------------------------------------
+
+def test_labels_in_matches_oracle(rr):
+    P = datagen.mid_sparse()
+    F = P.X.shape[1]
+    lab = datagen.random_labels(F, 250, 9)
+    lab[lab == 17] = 3            # leave cluster 17 empty: it must be dropped
+    R = rr.Ridge(P.X, labels=lab)
+    labc, fc = kmeans.compact(lab)
+    assert R.info["n_coarse"] == fc == 249
+    assert np.array_equal(host(R.labels()), labc)
+    x_k, inf = krylov.solve(P.X, P.y, 0.1, "vcycle", labc, fc, fixed_iters=12)
+    w, info = R.solve(0.1, P.y, precond="vcycle", fixed_iters=12)
+    assert np.linalg.norm(host(w) - x_k) <= 1e-10 * np.linalg.norm(x_k)
+
+
+def test_singleton_clusters_one_iteration(rr):
+    P = datagen.tiny_sparse()
+    F = P.X.shape[1]
+    R = rr.Ridge(P.X, labels=np.arange(F))
+    w, info = R.solve(1.0, P.y, precond="vcycle", tol=1e-12)
+    assert info["iters"] == 1
+    wst = krylov.reference_solution(P.X, P.y, 1.0)
+    assert np.linalg.norm(host(w) - wst) <= 1e-11 * np.linalg.norm(wst)
+
+
+def test_ideal_case_one_iteration(rr):
+    X, group = datagen.duplicated_columns(300, [30, 45, 20, 50, 15], 0.2, seed=8)
+    R = rr.Ridge(X, n_clusters=5, seed=3)
+    assert R.info["n_coarse"] == 5
+    assert len(set(zip(group.tolist(), host(R.labels()).tolist()))) == 5
+    y = np.random.default_rng(1).standard_normal(300)
+    w, info = R.solve(0.5, y, precond="vcycle", tol=1e-12)
+    assert info["iters"] == 1
+
+
+# --- edge cases and errors ---------------------------------------------------------
+
+def test_zero_rhs_and_empty_columns(rr):
+    import scipy.sparse as sp
+    X = datagen.zipf_binary_csr(500, 300, 5, 1.1, 4)
+    X = sp.csr_matrix(X)
+    X[:, 7] = 0        # an empty column
+    X.eliminate_zeros()
+    R = rr.Ridge(X, n_clusters=20, seed=1)
+    w, info = R.solve(1.0, np.zeros(500), precond="vcycle")
+    assert info["iters"] == 0 and info["status"] == 0
+    assert float(torch.abs(w).max()) == 0.0
+    y = np.random.default_rng(3).standard_normal(500)
+    lab, fc, _, _ = kmeans.kmeans_features(X, 20, 1)
+    assert np.array_equal(host(R.labels()), lab)
+    x_or, inf = krylov.solve(X, y, 1.0, "vcycle", lab, fc, tol=1e-10)
+    w, info = R.solve(1.0, y, precond="vcycle", tol=1e-10)
+    assert abs(info["iters"] - inf.iters) <= 1
+
+
+def test_single_row_and_rhs_is_b(rr):
+    import scipy.sparse as sp
+    X = sp.csr_matrix(np.array([[1.0, 0.0, 1.0, 1.0]]))
+    R = rr.Ridge(X)
+    b = np.array([1.0, -2.0, 0.5, 3.0])
+    w, info = R.solve(0.25, b, precond="jacobi", rhs_is_b=True, tol=1e-14)
+    ref = np.linalg.solve(X.toarray().T @ X.toarray() + 0.25 * np.eye(4), b)
+    assert np.allclose(host(w), ref, rtol=1e-12)
+
+
+def test_real_valued_matrix(rr):
+    import scipy.sparse as sp
+    rng = np.random.default_rng(6)
+    X = sp.random(800, 300, density=0.03, random_state=7, format="csr")
+    X.data = rng.standard_normal(X.nnz)
+    with pytest.raises(rr.RRError) as e:     # coarse level needs binary X for now
+        rr.Ridge(X, labels=datagen.random_labels(300, 30, 2), binary=False)
+    assert e.value.status == rr.RR_ERR_UNSUPPORTED
+    R = rr.Ridge(X, binary=False)
+    y = rng.standard_normal(800)
+    v = rng.standard_normal(300)
+    assert np.allclose(host(R.apply_operator(0.7, v)), op.apply_A(X, 0.7, v), rtol=1e-12, atol=1e-12)
+    x_k, _ = krylov.solve(X, y, 0.7, "jacobi", fixed_iters=20)
+    w, info = R.solve(0.7, y, precond="jacobi", fixed_iters=20)
+    assert np.linalg.norm(host(w) - x_k) <= 1e-10 * np.linalg.norm(x_k)
+
+
+def test_errors(rr):
+    import scipy.sparse as sp
+    P = datagen.tiny_sparse()
+    R = rr.Ridge(P.X, n_clusters=10, seed=1)
+    with pytest.raises(rr.RRError) as e:
+        R.solve(0.0, P.y)
+    assert e.value.status == rr.RR_ERR_INVALID_ARG
+    w, info = R.solve(1.0, P.y, precond="none", max_iter=5)
+    assert info["status"] == rr.RR_ERR_NOT_CONVERGED and info["iters"] == 5
+    w, info = R.solve(1.0, P.y, precond="vcycle", omega=50.0)
+    assert info["status"] == rr.RR_ERR_BREAKDOWN
+    # invalid CSR: column index out of range / not increasing
+    rp = torch.tensor([0, 2, 3], dtype=torch.int32, device="cuda")
+    ci = torch.tensor([1, 9, 0], dtype=torch.int32, device="cuda")
+    with pytest.raises(rr.RRError) as e:
+        rr.rr_setup(rp, ci, None, 4)
+    assert e.value.status == rr.RR_ERR_INVALID_ARG
+    ci = torch.tensor([2, 1, 0], dtype=torch.int32, device="cuda")
+    with pytest.raises(rr.RRError) as e:
+        rr.rr_setup(rp, ci, None, 4)
+    assert e.value.status == rr.RR_ERR_INVALID_ARG
+    with pytest.raises(rr.RRError):
+        rr.Ridge(P.X, labels=np.full(500, -1))
