@@ -1,0 +1,205 @@
+"""Benchmark: time to 1e-10 relative error of the two-level PCG solve on the
+binary fingerprint workload (200,000 x 100,000, 60 nonzeros per row, Zipf(1.1)
+column popularity, 12.0 M nonzeros), lambda in {1e-2, 1, 100}, k-means
+aggregation with k = 1000, FP64 throughout.
+
+One step = the three solves, each run for the number of iterations at which
+its iterate first reaches relative error <= 1e-10 against a tightly converged
+reference (calibrated before the timed region).  Setup (transpose, k-means,
+coarse Gram) and the per-lambda coarse factorizations are timed separately
+and reported beside the step.
+
+Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-1e-10 rel. error (s) + SpMV HBM GB/s; batched/BF16/learned vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def csc_bytes(N, F, nnz, vec_streams):
+    """Algorithmic bytes of one CSC pass t = X^T u with an epilogue touching
+    `vec_streams` F-vectors: row indices, column pointers, u read once."""
+    return 4 * nnz + 4 * (F + 1) + 8 * N + 8 * F * vec_streams
+
+
+def csr_bytes(N, F, nnz):
+    """One CSR pass u = X v: column indices, row pointers, v read once, u written."""
+    return 4 * nnz + 4 * (N + 1) + 8 * F + 8 * N
+
+
+def cpu_baseline(X, y, lam, labels, fc, step_iters, budget_s=15.0):
+    """The oracle's two-level PCG (FP64 SciPy/NumPy) timed for whole
+    iterations until `budget_s` has passed; seconds per iteration times the
+    step's iteration count gives the CPU figure for one step."""
+    import numpy as np
+    from oracle import krylov, operator as op, precond
+    cores = len(os.sched_getaffinity(0))
+    omega = op.omega_gershgorin(X, lam)
+    B, _ = precond.make("vcycle", X, lam, labels, fc, omega)
+    b = op.rhs(X, y)
+    A = lambda v: op.apply_A(X, lam, v)
+    k = 2
+    t_iter = None
+    while True:
+        t0 = time.perf_counter()
+        krylov.pcg(A, b, B, fixed_iters=k)
+        dt = time.perf_counter() - t0
+        t_iter = dt / k
+        if dt > budget_s / 3 or k >= 64:
+            break
+        k *= 2
+    return {"value": t_iter * step_iters, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"{k} iterations of the oracle's V(1,1) two-level PCG at lambda=1 on the "
+                      f"same matrix (seeded random aggregation, F_C={fc}; SciPy sparse products "
+                      f"are single-threaded, {cores} cores visible), {t_iter * 1e3:.1f} ms per "
+                      f"iteration, scaled to the step's {step_iters} iterations"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--k", type=int, default=1000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU row-sharded design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_1806_05826_amd as rr
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    P = datagen.chembl_like()
+    N, F = P.X.shape
+    nnz = P.X.nnz
+    lams = [1e-2, 1.0, 100.0]
+    print(f"[bench] data {N}x{F} nnz={nnz}", file=sys.stderr, flush=True)
+
+    R = rr.Ridge(P.X, n_clusters=args.k, seed=5826, lambda_slots=4)
+    sinfo = R.info
+    print(f"[bench] setup {sinfo['setup_ms']:.0f} ms (k-means {sinfo['kmeans_ms']:.0f} ms, "
+          f"{sinfo['kmeans_iters']} Lloyd passes), F_C={sinfo['n_coarse']}", file=sys.stderr, flush=True)
+    y = torch.as_tensor(P.y, dtype=torch.float64, device=dev)
+    w = torch.empty(F, dtype=torch.float64, device=dev)
+
+    # calibration: reference solutions and the iteration reaching 1e-10 error
+    calib = {}
+    for lam in lams:
+        st, inf_ref = rr.rr_solve(R.h, lam, y, w, tol=1e-14, max_iter=3000, precond="vcycle",
+                                  raise_on=(1, 2, 6))
+        wref = w.clone()
+        st, inf = rr.rr_solve(R.h, lam, y, w, tol=1e-300, x_ref=wref, err_tol=1e-10,
+                              max_iter=3000, precond="vcycle", raise_on=(1, 2, 6))
+        calib[lam] = {"iters": inf["iters"], "err": inf["err"], "ref_iters": inf_ref["iters"],
+                      "ref_true_relres": inf_ref["true_relres"], "coarse_ms": inf_ref["coarse_ms"]}
+        print(f"[bench] lambda={lam}: {inf['iters']} iterations to rel. error {inf['err']:.2e} "
+              f"(reference: {inf_ref['iters']} its, true relres {inf_ref['true_relres']:.1e})",
+              file=sys.stderr, flush=True)
+
+    def step(profile=False):
+        out = {}
+        for lam in lams:
+            st, inf = rr.rr_solve(R.h, lam, y, w, fixed_iters=calib[lam]["iters"],
+                                  precond="vcycle", profile=profile, chunk=16, raise_on=(1, 2, 6))
+            out[lam] = inf
+        return out
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        last = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    # kernel timing with HIP events recorded by the library on its stream
+    prof = step(profile=True)
+    torch.cuda.synchronize()
+    csc_ms = np.mean([prof[l]["csc_avg_ms"] for l in lams])
+    csr_ms = np.mean([prof[l]["csr_avg_ms"] for l in lams])
+    b_csc = csc_bytes(N, F, nnz, 3)   # epilogues touch 2, 3 and 4 F-vectors in equal numbers
+    b_csr = csr_bytes(N, F, nnz)
+    gbs_csc = b_csc / (csc_ms * 1e-3) / 1e9
+    gbs_op = (b_csc + b_csr) / ((csc_ms + csr_ms) * 1e-3) / 1e9
+
+    # other forms for comparison (untimed calibration, one timed solve each)
+    compare = {}
+    for kind in ("jacobi", "additive"):
+        lam = 1.0
+        st, inf = rr.rr_solve(R.h, lam, y, w, tol=1e-14, max_iter=5000, precond=kind, raise_on=(1, 2, 6))
+        wref = w.clone()
+        st, inf = rr.rr_solve(R.h, lam, y, w, tol=1e-300, x_ref=wref, err_tol=1e-10,
+                              max_iter=5000, precond=kind, raise_on=(1, 2, 6))
+        k = inf["iters"]
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        rr.rr_solve(R.h, lam, y, w, fixed_iters=k, precond=kind, chunk=16, raise_on=(1, 2, 6))
+        torch.cuda.synchronize()
+        compare[kind] = {"lambda": lam, "iters": k, "ms": (time.perf_counter() - ta) * 1e3}
+    compare["vcycle"] = {"lambda": 1.0, "iters": calib[1.0]["iters"], "ms": last[1.0]["ms"]}
+
+    total_iters = sum(calib[l]["iters"] for l in lams)
+    cpu = None
+    if not args.no_cpu:
+        labels = datagen.random_labels(F, args.k, 11)
+        cpu = cpu_baseline(P.X, P.y, 1.0, labels, args.k, total_iters)
+
+    line = {
+        "metric": METRIC,
+        "value": ms_per_step / 1e3,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded Zipf(1.1) binary fingerprints, y = X w* + N(0, 0.1^2))",
+        "config": {
+            "workload": "binary 200000x100000 CSR+CSC, 60 nnz/row (12.0M nnz), Zipf(1.1) columns; "
+                        "k-means k=1000 feature aggregation; V(1,1) two-level PCG (damped Jacobi "
+                        "smoothing, FP64 coarse Cholesky); lambda in {1e-2,1,100}; each solve run "
+                        "to relative error <= 1e-10 vs a converged reference",
+            "lambdas": lams,
+            "n_clusters": args.k,
+            "n_coarse": sinfo["n_coarse"],
+        },
+        "per_lambda": {str(l): {"iters": calib[l]["iters"], "ms": last[l]["ms"],
+                                "err": calib[l]["err"], "coarse_factor_ms": calib[l]["coarse_ms"]}
+                       for l in lams},
+        "setup_ms": sinfo["setup_ms"],
+        "kmeans_ms": sinfo["kmeans_ms"],
+        "kmeans_passes": sinfo["kmeans_iters"],
+        "operator_gbs": gbs_op,
+        "csr_avg_ms": csr_ms,
+        "csc_avg_ms": csc_ms,
+        "compare_lambda1": compare,
+        "roofline": {"bound": "hbm", "achieved": gbs_csc, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs_csc / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "CSC pass t = X^T u + epilogue (merge-path main + fix-up)",
+                     "bytes_per_launch": b_csc},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,111 @@
+"""Full-size parity on the 200,000 x 100,000 binary fingerprint workload
+(12.0 M nonzeros, Zipf(1.1) column popularity), in the launch configuration
+the benchmark times.
+
+The oracle cannot run k-means at this size in seconds, so clustering is
+checked through a property that holds at any size: after Lloyd converges,
+every feature's label is the exact nearest cluster mean of the final
+clusters (checked with exact integers on a sample of features, including
+the most popular ones).  Solves use a seeded aggregation from datagen so the
+oracle can run them too."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import datagen
+from oracle import kmeans, krylov, operator as op
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rr():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1806_05826_amd as rr
+    return rr
+
+
+@pytest.fixture(scope="module")
+def big():
+    print("[fullsize] generating 200000 x 100000, 60 nnz/row", flush=True)
+    return datagen.chembl_like()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def test_fullsize_operator_exact(rr, big):
+    R = rr.Ridge(big.X)
+    v = np.random.default_rng(3).integers(-40, 40, size=big.X.shape[1]).astype(np.float64)
+    got = host(R.apply_operator(2.0, v))
+    assert np.array_equal(got, op.apply_A(big.X, 2.0, v))
+    b = host(R.apply_rhs(big.y))
+    assert np.allclose(b, op.rhs(big.X, big.y), rtol=1e-13, atol=1e-11)
+    R.close()
+
+
+def test_fullsize_kmeans_fixed_point(rr, big):
+    print("[fullsize] GPU k-means k=1000", flush=True)
+    R = rr.Ridge(big.X, n_clusters=1000, seed=5826)
+    info = R.info
+    print(f"[fullsize] setup {info['setup_ms']:.0f} ms (k-means {info['kmeans_ms']:.0f} ms), "
+          f"centres {info['n_centres']}, Lloyd passes {info['kmeans_iters']}, F_C {info['n_coarse']}",
+          flush=True)
+    assert info["kmeans_iters"] < 100, "Lloyd did not converge; fixed-point check needs convergence"
+    lab = host(R.labels()).astype(np.int64)
+    fc = info["n_coarse"]
+    assert lab.min() == 0 and lab.max() == fc - 1
+    n = np.bincount(lab, minlength=fc).astype(np.int64)
+    assert np.all(n > 0)
+    Xi = big.X.astype(np.int64).tocsr()
+    Pu = sp.csr_matrix((np.ones(lab.size, dtype=np.int64), (np.arange(lab.size), lab)),
+                       shape=(lab.size, fc))
+    S = (Xi @ Pu).tocsr()
+    Q = np.asarray(S.multiply(S).sum(axis=0)).ravel().astype(np.int64)
+    colnnz = np.diff(big.X.tocsc().indptr)
+    rng = np.random.default_rng(0)
+    sample = np.unique(np.concatenate([np.argsort(-colnnz)[:20], rng.choice(lab.size, 300, replace=False)]))
+    XcT = Xi.T.tocsr()[sample]
+    H = np.asarray((XcT @ S).todense(), dtype=np.int64)       # h_js for the sample
+    num = Q[None, :] - 2 * n[None, :] * H
+    best = kmeans.exact_argmin(num, n * n, np.ones(fc, dtype=bool))
+    assert np.array_equal(best, lab[sample])
+    # K = P^T X^T X P on the sampled rows
+    K = host(R.coarse_gram())
+    sel = lab[sample[:8]]
+    StS_rows = (S.tocsc()[:, sel].T @ S).toarray().astype(np.float64)
+    sc = 1.0 / np.sqrt(n.astype(np.float64))
+    Kref = StS_rows * sc[sel, None] * sc[None, :]
+    assert np.allclose(K[sel], Kref, rtol=1e-14, atol=0)
+    R.close()
+
+
+@pytest.fixture(scope="module")
+def solver_random_labels(rr, big):
+    lab = datagen.random_labels(big.X.shape[1], 1000, 11)
+    R = rr.Ridge(big.X, labels=lab)
+    return R, lab
+
+
+@pytest.mark.parametrize("lam", [1e-2, 1.0, 100.0])
+def test_fullsize_solve(rr, big, solver_random_labels, lam):
+    R, lab = solver_random_labels
+    fc = 1000
+    print(f"[fullsize] solve lambda={lam}", flush=True)
+    w, info = R.solve(lam, big.y, precond="vcycle", tol=1e-10, max_iter=2000)
+    assert info["status"] == 0 and info["relres"] <= 1e-10
+    # the true residual by the oracle's operator, a property at any size
+    b = op.rhs(big.X, big.y)
+    wn = host(w)
+    res = np.linalg.norm(b - op.apply_A(big.X, lam, wn)) / np.linalg.norm(b)
+    assert res <= 2e-10
+    assert abs(res - info["true_relres"]) <= 1e-12
+    # oracle at equal iteration count once converged (1e-13)
+    x_t, inf_t = krylov.solve(big.X, big.y, lam, "vcycle", lab, fc, tol=1e-13, max_iter=2000)
+    assert inf_t.status == krylov.OK
+    assert abs(info["iters"] - next(i for i, h in enumerate(inf_t.history) if h <= 1e-10)) <= 2
+    w, info = R.solve(lam, big.y, precond="vcycle", fixed_iters=inf_t.iters)
+    assert np.linalg.norm(host(w) - x_t) <= 1e-10 * np.linalg.norm(x_t)
