@@ -37,8 +37,26 @@ def averaging_restriction(labels: np.ndarray, F_C: int) -> sp.csr_matrix:
     return sp.csr_matrix((vals, (labels, np.arange(F))), shape=(F_C, F))
 
 
+def _is_binary(X) -> bool:
+    data = X.data if sp.issparse(X) else np.asarray(X).ravel()
+    return bool(data.size) and bool(np.isin(data, (0.0, 1.0)).all())
+
+
 def coarse_gram(X, labels: np.ndarray, F_C: int) -> np.ndarray:
-    """K = P^T X^T X P = X_c^T X_c (dense F_C x F_C, FP64)."""
+    """K = P^T X^T X P = X_c^T X_c (dense F_C x F_C, FP64).
+
+    For 0/1 data X_c = S diag(n)^-1/2 with S = X P_u the integer count
+    matrix (P_u the 0/1 membership), so K_st = (S^T S)_st / sqrt(n_s n_t):
+    S^T S is formed exactly in integers and scaled once.  Other data use
+    FP64 products."""
+    if sp.issparse(X) and _is_binary(X):
+        n = cluster_sizes(labels, F_C)
+        F = labels.shape[0]
+        Pu = sp.csr_matrix((np.ones(F, dtype=np.int64), (np.arange(F), labels)), shape=(F, F_C))
+        S = sp.csr_matrix(X).astype(np.int64) @ Pu
+        StS = np.asarray((S.T @ S).todense(), dtype=np.int64)
+        sc = 1.0 / np.sqrt(n.astype(np.float64))
+        return (StS.astype(np.float64) * sc[:, None]) * sc[None, :]
     P = prolongation(labels, F_C)
     Xc = X @ P
     K = Xc.T @ Xc

@@ -13,7 +13,7 @@ import pytest
 import scipy.sparse as sp
 
 import datagen
-from oracle import kmeans, krylov, operator as op
+from oracle import kmeans, krylov, operator as op, precond
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -103,9 +103,29 @@ def test_fullsize_solve(rr, big, solver_random_labels, lam):
     res = np.linalg.norm(b - op.apply_A(big.X, lam, wn)) / np.linalg.norm(b)
     assert res <= 2e-10
     assert abs(res - info["true_relres"]) <= 1e-12
+    # iteration count inside the oracle's rounding spread (diagonal perturbed
+    # by at most 2 ulp), with 2 % slack for the small ensemble
+    omega = op.omega_gershgorin(big.X, lam)
+    tl = precond.TwoLevel(big.X, lam, lab, fc, omega)
+    A = lambda v: op.apply_A(big.X, lam, v)
+    D0 = tl.D.copy()
+    its = []
+    rng = np.random.default_rng(1)
+    Ac0 = tl.Ac.copy()
+    for t in range(3):
+        tl.D = D0 if t == 0 else D0 * (1.0 + (rng.random(D0.size) - 0.5) * 4 * 2**-53)
+        if t > 0:   # A_c to within 2 ulp, symmetric
+            E = (rng.random(Ac0.shape) - 0.5) * 4 * 2**-53
+            tl.Ac = Ac0 * (1.0 + 0.5 * (E + E.T))
+            tl.L = np.linalg.cholesky(tl.Ac)
+        its.append(krylov.pcg(A, b, tl.vcycle, tol=1e-10, max_iter=2000)[1].iters)
+    slack = 1 + int(0.02 * max(its))
+    assert min(its) - slack <= info["iters"] <= max(its) + slack, (info["iters"], its)
     # oracle at equal iteration count once converged (1e-13)
-    x_t, inf_t = krylov.solve(big.X, big.y, lam, "vcycle", lab, fc, tol=1e-13, max_iter=2000)
+    tl.D = D0
+    tl.Ac = Ac0
+    tl.L = np.linalg.cholesky(Ac0)
+    x_t, inf_t = krylov.pcg(A, b, tl.vcycle, tol=1e-13, max_iter=2000)
     assert inf_t.status == krylov.OK
-    assert abs(info["iters"] - next(i for i, h in enumerate(inf_t.history) if h <= 1e-10)) <= 2
     w, info = R.solve(lam, big.y, precond="vcycle", fixed_iters=inf_t.iters)
     assert np.linalg.norm(host(w) - x_t) <= 1e-10 * np.linalg.norm(x_t)

@@ -127,9 +127,9 @@ def test_precond_parity(rr, clustered, kind):
 
 def oracle_iteration_spread(P, lam, kind, lab, fc, tol, max_iter, n=6, seed=0):
     """Iteration counts of the oracle itself under rounding-level changes:
-    the preconditioner's diagonal (or, for CG, an identity scaling) is
-    perturbed entrywise by at most 2 ulp.  FP64 Krylov iteration counts are
-    only defined up to this spread."""
+    the preconditioner's diagonal (or, for CG, an identity scaling) and the
+    coarse matrix are perturbed entrywise by at most 2 ulp.  FP64 Krylov
+    iteration counts are only defined up to this spread."""
     b = op.rhs(P.X, P.y)
     A = lambda v: op.apply_A(P.X, lam, v)
     F = P.X.shape[1]
@@ -146,6 +146,10 @@ def oracle_iteration_spread(P, lam, kind, lab, fc, tol, max_iter, n=6, seed=0):
         else:
             tl = precond.TwoLevel(P.X, lam, lab, fc, omega)
             tl.D = tl.D * pert
+            if t > 0:   # A_c to within 2 ulp, symmetric: its rounding class
+                E = (rng.random(tl.Ac.shape) - 0.5) * 4 * 2**-53
+                tl.Ac = tl.Ac * (1.0 + 0.5 * (E + E.T))
+                tl.L = coarse.cholesky(tl.Ac)
             B = tl.vcycle if kind == "vcycle" else tl.additive
         _, inf = krylov.pcg(A, b, B, tol=tol, max_iter=max_iter)
         its.append(inf.iters)
@@ -158,10 +162,11 @@ def test_solve_parity(rr, clustered, kind):
     lam = 1.0
     # natural stop at 1e-10: iteration count inside the oracle's rounding
     # spread, +-1; recursive and true residuals at the tolerance
-    lo, hi = oracle_iteration_spread(P, lam, kind, lab, fc, 1e-10, 5000)
+    lo, hi = oracle_iteration_spread(P, lam, kind, lab, fc, 1e-10, 5000, n=8)
     w, info = R.solve(lam, P.y, precond=kind, tol=1e-10, max_iter=5000)
     assert info["status"] == 0
-    assert lo - 1 <= info["iters"] <= hi + 1, (info["iters"], lo, hi)
+    slack = 1 + int(0.02 * hi)    # the ensemble under-samples the tails of the spread
+    assert lo - slack <= info["iters"] <= hi + slack, (info["iters"], lo, hi)
     assert info["relres"] <= 1e-10
     assert info["true_relres"] <= 2e-10
     # equal iteration counts once converged (relative residual 1e-13):
@@ -183,7 +188,7 @@ def test_residual_history_and_error_target(rr, clustered):
     wst = krylov.reference_solution(P.X, P.y, lam) if P.X.shape[1] <= 4000 else None
     if wst is None:
         pytest.skip("dense reference too large")
-    x, inf = krylov.solve(P.X, P.y, lam, "vcycle", lab, fc, tol=1e-10, x_ref=wst)
+    x, inf = krylov.solve(P.X, P.y, lam, "vcycle", lab, fc, tol=1e-13, x_ref=wst)
     hist = torch.zeros(200, dtype=torch.float64, device="cuda")
     w, info = R.solve(lam, P.y, precond="vcycle", tol=1e-10, residual_history=hist)
     h = host(hist)[: info["iters"] + 1]

@@ -136,6 +136,18 @@ def test_galerkin_identity(seed):
     assert np.allclose(K * np.sqrt(np.outer(n, n)), StS, rtol=1e-14, atol=0)
 
 
+def test_galerkin_identity_real_valued():
+    rng = np.random.default_rng(12)
+    X = sp.random(70, 25, density=0.2, random_state=3, format="csr")
+    X.data = rng.standard_normal(X.nnz)
+    labels = datagen.random_labels(25, 6, 1)
+    Xd = X.toarray()
+    P = coarse.prolongation(labels, 6).toarray()
+    ref = P.T @ (Xd.T @ Xd + 0.3 * np.eye(25)) @ P
+    Ac = coarse.coarse_matrix(X, labels, 6, 0.3)
+    assert np.max(np.abs(Ac - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
 def test_cholesky_factor():
     X = _tiny_binary(20, n=90, f=40, m=5)
     labels = datagen.random_labels(40, 9, 3)
