@@ -34,6 +34,11 @@ __global__ void k_colnorm_values(int F, const int* col_ptr, const double* cval, 
   c[j] = s;
 }
 
+__global__ void k_gather_int(int* dst, const int* src, const int* idx, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[idx[i]];
+}
+
 __global__ void k_smooth(int F, const double* r, const double* D, double omega, double* e1) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < F) e1[j] = (omega * r[j]) / D[j];
@@ -70,7 +75,7 @@ void destroy_handle(rr_handle* h) {
   dfree(X.col_ptr); dfree(X.row_idx); dfree(X.cval);
   free_merge_plan(X.csc_plan);
   free_merge_plan(h->restrict_plan);
-  dfree(h->colnorm); dfree(h->gersh);
+  dfree(h->colnorm); dfree(h->gersh); dfree(h->fperm); dfree(h->finv);
   dfree(h->labels); dfree(h->centres); dfree(h->csize); dfree(h->cscale);
   dfree(h->perm); dfree(h->coff); dfree(h->K);
   for (auto& s : h->slots) { dfree(s.L); dfree(s.Ainv); }
@@ -78,7 +83,7 @@ void destroy_handle(rr_handle* h) {
   Work& w = h->w;
   dfree(w.x); dfree(w.r); dfree(w.p); dfree(w.q); dfree(w.z); dfree(w.e1); dfree(w.e2);
   dfree(w.rho); dfree(w.b); dfree(w.u); dfree(w.c); dfree(w.yc); dfree(w.partials);
-  dfree(w.sc); dfree(w.D);
+  dfree(w.sc); dfree(w.D); dfree(w.vin); dfree(w.vout); dfree(w.xref);
   if (w.sc_host) (void)hipHostFree(w.sc_host);
   for (auto e : h->ev_pool) (void)hipEventDestroy(e);
   delete h;
@@ -114,6 +119,9 @@ rr_status setup_impl(const rr_csr* Xin, const rr_setup_opts* o, hipStream_t s, r
     return vs;
   }
   X.csr_group = pick_group(X.N ? (double)X.nnz / X.N : 1.0);
+  RR_TRY(dalloc(&h->fperm, X.F));
+  RR_TRY(dalloc(&h->finv, X.F));
+  RR_TRY(renumber_features(X, h->fperm, h->finv, s));
   RR_TRY(build_csc(X, s));
   // column norms and Gershgorin row sums g = X^T (X 1)
   RR_TRY(dalloc(&h->colnorm, X.F));
@@ -129,6 +137,7 @@ rr_status setup_impl(const rr_csr* Xin, const rr_setup_opts* o, hipStream_t s, r
   RR_TRY(dalloc(&w.q, F)); RR_TRY(dalloc(&w.z, F)); RR_TRY(dalloc(&w.e1, F));
   RR_TRY(dalloc(&w.e2, F)); RR_TRY(dalloc(&w.rho, F)); RR_TRY(dalloc(&w.b, F));
   RR_TRY(dalloc(&w.D, F)); RR_TRY(dalloc(&w.u, N));
+  RR_TRY(dalloc(&w.vin, F)); RR_TRY(dalloc(&w.vout, F)); RR_TRY(dalloc(&w.xref, F));
   RR_TRY(dalloc(&w.sc, 1));
   RR_HIP(hipHostMalloc((void**)&w.sc_host, sizeof(Scalars), hipHostMallocDefault));
   std::memset(w.sc_host, 0, sizeof(Scalars));
@@ -156,7 +165,7 @@ rr_status setup_impl(const rr_csr* Xin, const rr_setup_opts* o, hipStream_t s, r
     RR_TRY(run_kmeans(h, k, o->seed, mi, s));
   }
   h->kmeans_ms = now_ms() - tk;
-  int np = std::max(X.csc_plan.nblocks + cdiv(X.csc_plan.nspan, kBlock) + 1, cdiv(F, kBlock) + 1);
+  int np = std::max(X.csc_plan.nblocks + cdiv(X.csc_plan.nspan, kBlock / 64) + 1, cdiv(F, kBlock) + 1);
   if (h->FC > 0) {
     const int fc = h->FC;
     RR_TRY(dalloc(&h->K, (size_t)fc * fc));
@@ -171,7 +180,7 @@ rr_status setup_impl(const rr_csr* Xin, const rr_setup_opts* o, hipStream_t s, r
     RR_TRY(dalloc(&h->chol_flag, 1));
     RR_TRY(dalloc(&w.c, fc));
     RR_TRY(dalloc(&w.yc, fc));
-    np = std::max(np, h->restrict_plan.nblocks + cdiv(h->restrict_plan.nspan, kBlock) + 1);
+    np = std::max(np, h->restrict_plan.nblocks + cdiv(h->restrict_plan.nspan, kBlock / 64) + 1);
   }
   w.npartials = np;
   RR_TRY(dalloc(&w.partials, 3 * (size_t)np));
@@ -355,7 +364,7 @@ rr_status solve_impl(rr_handle* h, double lam, const double* rhs, double* wout,
   if (!std::isfinite(omega) || omega < 0.0) return fail(RR_ERR_INVALID_ARG, "omega must be finite and >= 0");
   launch_colnorm_diag(F, h->colnorm, lam, w.D, s);
   if (op.rhs_is_b) {
-    launch_copy(w.b, rhs, F, s);
+    launch_gather(w.b, rhs, h->fperm, F, s);
   } else {
     Epi e{};
     e.out = w.b;
@@ -372,7 +381,12 @@ rr_status solve_impl(rr_handle* h, double lam, const double* rhs, double* wout,
   RR_HIP(hipMemcpyAsync(w.sc, &hs, sizeof(Scalars), hipMemcpyHostToDevice, s));
   Prof pf;
   pf.on = op.profile != 0;
-  launch_pcg_init(F, w.b, w.x, w.r, w.p, w.z, w.e1, w.D, op.x_ref, omega, kind, w.sc, w.partials,
+  const double* xref = nullptr;
+  if (op.x_ref) {
+    launch_gather(w.xref, op.x_ref, h->fperm, F, s);
+    xref = w.xref;
+  }
+  launch_pcg_init(F, w.b, w.x, w.r, w.p, w.z, w.e1, w.D, xref, omega, kind, w.sc, w.partials,
                   op.residual_history, s);
   if (kind == PK_VCYCLE || kind == PK_ADDITIVE)
     RR_TRY(precond_two_level(h, pf, -1, kind, lam, omega, *sl, w.r, w.z, s));
@@ -385,7 +399,7 @@ rr_status solve_impl(rr_handle* h, double lam, const double* rhs, double* wout,
       e.p = w.p;
       e.out = w.q;
       RR_TRY(op_csc(h, pf, queued, EPI_APPLY_DOT, e, s));
-      launch_pcg_update(F, w.x, w.r, w.p, w.q, w.z, w.e1, w.D, op.x_ref, omega, kind, w.sc,
+      launch_pcg_update(F, w.x, w.r, w.p, w.q, w.z, w.e1, w.D, xref, omega, kind, w.sc,
                         w.partials, op.residual_history, s);
       if (kind == PK_VCYCLE || kind == PK_ADDITIVE)
         RR_TRY(precond_two_level(h, pf, 100000000 + queued, kind, lam, omega, *sl, w.r, w.z, s));
@@ -399,7 +413,7 @@ rr_status solve_impl(rr_handle* h, double lam, const double* rhs, double* wout,
       return fail(RR_ERR_DEVICE, "internal: iteration limit passed without the device finishing");
   }
   // exit: w = x and the true residual ||b - A x||
-  launch_copy(wout, w.x, F, s);
+  launch_gather(wout, w.x, h->finv, F, s);
   {
     launch_csr(h->X, w.x, w.u, nullptr, s);
     Epi e = base_epi(h, lam);
@@ -513,8 +527,9 @@ rr_status rr_get_labels(const rr_handle* h, int32_t* labels, rr_stream stream) {
   RR_TRY(check_handle(h));
   if (!labels) return fail(RR_ERR_INVALID_ARG, "null labels");
   if (h->FC == 0) return fail(RR_ERR_INVALID_ARG, "no aggregation (n_clusters = 0)");
-  RR_HIP(hipMemcpyAsync(labels, h->labels, sizeof(int) * h->X.F, hipMemcpyDeviceToDevice,
-                        (hipStream_t)stream));
+  k_gather_int<<<cdiv(h->X.F, kBlock), kBlock, 0, (hipStream_t)stream>>>(labels, h->labels, h->finv,
+                                                                        h->X.F);
+  RR_HIP(hipGetLastError());
   return RR_OK;
 }
 
@@ -540,11 +555,15 @@ rr_status rr_apply_operator(rr_handle* h, double lambda, const double* v, double
   RR_TRY(check_lambda(lambda, true));
   if (!v || !Av) return fail(RR_ERR_INVALID_ARG, "null vector");
   hipStream_t s = (hipStream_t)stream;
-  launch_csr(h->X, v, h->w.u, nullptr, s);
+  Work& w = h->w;
+  const int F = h->X.F;
+  launch_gather(w.vin, v, h->fperm, F, s);
+  launch_csr(h->X, w.vin, w.u, nullptr, s);
   Epi e = base_epi(h, lambda);
-  e.p = v;
-  e.out = Av;
-  launch_csc(h->X, h->w.u, EPI_APPLY, e, nullptr, s);
+  e.p = w.vin;
+  e.out = w.vout;
+  launch_csc(h->X, w.u, EPI_APPLY, e, nullptr, s);
+  launch_gather(Av, w.vout, h->finv, F, s);
   RR_HIP(hipGetLastError());
   return RR_OK;
 }
@@ -553,8 +572,9 @@ rr_status rr_apply_rhs(rr_handle* h, const double* y, double* b, rr_stream strea
   RR_TRY(check_handle(h));
   if (!y || !b) return fail(RR_ERR_INVALID_ARG, "null vector");
   Epi e{};
-  e.out = b;
+  e.out = h->w.vout;
   launch_csc(h->X, y, EPI_STORE, e, nullptr, (hipStream_t)stream);
+  launch_gather(b, h->w.vout, h->finv, h->X.F, (hipStream_t)stream);
   RR_HIP(hipGetLastError());
   return RR_OK;
 }
@@ -573,8 +593,10 @@ rr_status rr_apply_precond(rr_handle* h, double lambda, int32_t precond, double 
     launch_copy(z, r, F, s);
     return RR_OK;
   }
+  launch_gather(w.vin, r, h->fperm, F, s);
   if (precond == PK_JACOBI) {
-    launch_jacobi_apply(F, r, w.D, z, s);
+    launch_jacobi_apply(F, w.vin, w.D, w.vout, s);
+    launch_gather(z, w.vout, h->finv, F, s);
     return RR_OK;
   }
   if (h->FC == 0) return fail(RR_ERR_INVALID_ARG, "two-level preconditioner needs a coarse level");
@@ -587,9 +609,10 @@ rr_status rr_apply_precond(rr_handle* h, double lambda, int32_t precond, double 
   std::memset(&hs, 0, sizeof(Scalars));
   hs.rz = 1.0;
   RR_HIP(hipMemcpyAsync(w.sc, &hs, sizeof(Scalars), hipMemcpyHostToDevice, s));
-  if (precond == PK_VCYCLE) k_smooth<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, r, w.D, omega, w.e1);
+  if (precond == PK_VCYCLE) k_smooth<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, w.vin, w.D, omega, w.e1);
   Prof pf;
-  RR_TRY(precond_two_level(h, pf, 0, precond, lambda, omega, *sl, r, z, s));
+  RR_TRY(precond_two_level(h, pf, 0, precond, lambda, omega, *sl, w.vin, w.vout, s));
+  launch_gather(z, w.vout, h->finv, F, s);
   RR_HIP(hipStreamSynchronize(s));
   RR_HIP(hipGetLastError());
   return RR_OK;

@@ -190,6 +190,14 @@ void launch_fill(double* x, double v, long long n, hipStream_t s) {
   if (n > 0) k_fill<<<cdiv(n, kBlock), kBlock, 0, s>>>(x, v, n);
 }
 
+__global__ void k_gather(double* dst, const double* src, const int* idx, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[idx[i]];
+}
+void launch_gather(double* dst, const double* src, const int* idx, int n, hipStream_t s) {
+  if (n > 0) k_gather<<<cdiv(n, kBlock), kBlock, 0, s>>>(dst, src, idx, n);
+}
+
 __global__ void k_copy(double* dst, const double* src, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[i];

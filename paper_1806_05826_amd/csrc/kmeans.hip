@@ -46,10 +46,10 @@ __global__ void k_seed_first(const unsigned long long* draws, int F, int* centre
 
 // ind[rows of column centres[slot_prev]] = 0, then ind[rows of centres[slot]] = 1
 __global__ void k_indicator(const int* __restrict__ col_ptr, const int* __restrict__ row_idx,
-                            const int* centres, int slot, double value, double* ind,
-                            const SeedState* st) {
+                            const int* centres, const int* __restrict__ finv, int slot,
+                            double value, double* ind, const SeedState* st) {
   if (st->stop) return;
-  const int c = centres[slot];
+  const int c = finv[centres[slot]];
   const int a = col_ptr[c], b = col_ptr[c + 1];
   for (int e = a + blockIdx.x * blockDim.x + threadIdx.x; e < b; e += gridDim.x * blockDim.x)
     ind[row_idx[e]] = value;
@@ -60,6 +60,7 @@ __global__ void k_indicator(const int* __restrict__ col_ptr, const int* __restri
 // chunk whose prefix range holds r.
 __global__ __launch_bounds__(kBlock) void k_seed_update(int F, const double* __restrict__ colnorm,
                                                         const double* __restrict__ gram,
+                                                        const int* __restrict__ finv,
                                                         const int* centres, int slot, int first,
                                                         long long* __restrict__ d2,
                                                         long long* __restrict__ chunk_sum,
@@ -68,12 +69,14 @@ __global__ __launch_bounds__(kBlock) void k_seed_update(int F, const double* __r
   if (st->stop) return;
   __shared__ long long red[kBlock];
   __shared__ int is_last;
-  const int c = centres[slot];
-  const long long cc = (long long)colnorm[c];
+  // d2 and the draw run over features in the caller's order; colnorm and
+  // gram are held in the internal order
+  const long long cc = (long long)colnorm[finv[centres[slot]]];
   long long sum = 0;
   const int j0 = blockIdx.x * kSeedChunk;
   for (int j = j0 + threadIdx.x; j < min(F, j0 + kSeedChunk); j += kBlock) {
-    const long long dist = (long long)colnorm[j] + cc - 2 * (long long)gram[j];
+    const int jn = finv[j];
+    const long long dist = (long long)colnorm[jn] + cc - 2 * (long long)gram[jn];
     const long long v = first ? dist : min(d2[j], dist);
     d2[j] = v;
     sum += v;
@@ -86,14 +89,13 @@ __global__ __launch_bounds__(kBlock) void k_seed_update(int F, const double* __r
   }
   if (threadIdx.x == 0) {
     __hip_atomic_store(&chunk_sum[blockIdx.x], red[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    const unsigned prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    wait_stores();
+    const unsigned prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     is_last = (prev == gridDim.x - 1);
   }
   __syncthreads();
   if (!is_last || threadIdx.x != 0) return;
-  __threadfence();
-  *ticket = 0;
+  __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (next < 0) return;   // no further draw
   long long T = 0;
   for (int b = 0; b < (int)gridDim.x; ++b)
@@ -344,9 +346,9 @@ __global__ void k_init_labels(int F, int nc, const int* centres, int* lab) {
   if (j < F) lab[j] = -1;
   // centres are written by a second launch (ordering across blocks)
 }
-__global__ void k_set_centres(int nc, const int* centres, int* lab) {
+__global__ void k_set_centres(int nc, const int* centres, const int* finv, int* lab) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < nc) lab[centres[s]] = s;
+  if (s < nc) lab[finv[centres[s]]] = s;
 }
 
 // Compaction: remap[s] = rank of s among non-empty clusters.  One block.
@@ -383,10 +385,11 @@ __global__ void k_relabel(int F, const int* remap, int* lab, int* bad) {
   lab[j] = m;
 }
 
-__global__ void k_check_labels(int F, int nlab, const int* lab_in, int* lab, int* bad) {
+__global__ void k_check_labels(int F, int nlab, const int* lab_in, const int* fperm, int* lab,
+                               int* bad) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= F) return;
-  const int l = lab_in[j];
+  const int l = lab_in[fperm[j]];
   if (l < 0 || l >= nlab) atomicOr(bad, 1);
   lab[j] = l;
 }
@@ -518,11 +521,12 @@ rr_status run_kmeans(rr_handle* h, int k, uint64_t seed, int max_iter, hipStream
   e.out = gram;
   const int ind_grid = 64;
   for (int i = 0; i < k; ++i) {
-    if (i > 0) k_indicator<<<ind_grid, kBlock, 0, s>>>(X.col_ptr, X.row_idx, h->centres, i - 1, 0.0, ind, st);
-    k_indicator<<<ind_grid, kBlock, 0, s>>>(X.col_ptr, X.row_idx, h->centres, i, 1.0, ind, st);
+    if (i > 0)
+      k_indicator<<<ind_grid, kBlock, 0, s>>>(X.col_ptr, X.row_idx, h->centres, h->finv, i - 1, 0.0, ind, st);
+    k_indicator<<<ind_grid, kBlock, 0, s>>>(X.col_ptr, X.row_idx, h->centres, h->finv, i, 1.0, ind, st);
     launch_csc(X, ind, EPI_STORE, e, &st->stop, s);
     const int next = (i + 1 < k) ? i + 1 : -1;
-    k_seed_update<<<nchunks, kBlock, 0, s>>>(F, h->colnorm, gram, h->centres, i, i == 0, d2,
+    k_seed_update<<<nchunks, kBlock, 0, s>>>(F, h->colnorm, gram, h->finv, h->centres, i, i == 0, d2,
                                              chunk_sum, d_draws, next, st, ticket);
     if (next > 0) k_seed_pick<<<1, kSeedChunk, 0, s>>>(F, d2, h->centres, next, st);
   }
@@ -550,7 +554,7 @@ rr_status run_kmeans(rr_handle* h, int k, uint64_t seed, int max_iter, hipStream
   RR_HIP(hipMalloc(&s0, sizeof(int)));
   RR_HIP(hipMalloc(&changed, sizeof(int)));
   k_init_labels<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, nc, h->centres, lab);
-  k_set_centres<<<cdiv(nc, kBlock), kBlock, 0, s>>>(nc, h->centres, lab);
+  k_set_centres<<<cdiv(nc, kBlock), kBlock, 0, s>>>(nc, h->centres, h->finv, lab);
   const int rows_per_block = 64;
   const int cnt_grid = std::min(1024, cdiv(F, kBlock));
   int it = 0;
@@ -599,7 +603,8 @@ rr_status set_labels(rr_handle* h, const int* labels_in, int nlab, hipStream_t s
   int *n = nullptr, *remap = nullptr, *fc = nullptr;
   RR_HIP(hipMalloc(&bad, sizeof(int)));
   RR_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
-  if (labels_in) k_check_labels<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, nlab, labels_in, h->labels, bad);
+  if (labels_in)
+    k_check_labels<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, nlab, labels_in, h->fperm, h->labels, bad);
   RR_HIP(hipMalloc(&n, sizeof(int) * nlab));
   RR_HIP(hipMalloc(&remap, sizeof(int) * nlab));
   RR_HIP(hipMalloc(&fc, sizeof(int)));

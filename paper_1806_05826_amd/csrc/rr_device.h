@@ -37,10 +37,22 @@ __device__ inline void write_partial(const double (&v)[NV], double* partials, in
   }
 }
 
+// Wait until this thread's earlier memory operations have completed.  The
+// partials below are written with agent-scope (coherent) atomic stores, so
+// once they have completed every block can see them; no cache writeback of
+// the whole L2 is needed, unlike a full release fence.
+__device__ inline void wait_stores() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // Every block of the grid stores its partial in slot (slot0 + blockIdx.x);
 // the last block to arrive then adds all `nslots` partials (which may include
 // slots written by an earlier kernel) in slot order, and returns true with
-// the totals in `tot` (valid in every thread of that block).
+// the totals in `tot` (valid in every thread of that block).  Partials are
+// agent-scope atomic stores and loads; the arrival ticket is an agent-scope
+// atomic counter, reset by the last block.
 template <int NV>
 __device__ inline bool grid_finish(const double (&v)[NV], double* partials, int slot0,
                                    int nslots, unsigned int* ticket, double (&tot)[NV]) {
@@ -48,14 +60,13 @@ __device__ inline bool grid_finish(const double (&v)[NV], double* partials, int 
   __shared__ int is_last;
   write_partial<NV>(v, partials, slot0 + blockIdx.x, nslots);
   if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned int prev =
-        __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    wait_stores();
+    const unsigned int prev =
+        __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     is_last = (prev == (unsigned)gridDim.x - 1u);
   }
   __syncthreads();
   if (!is_last) return false;
-  __threadfence();
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     double s = 0.0;

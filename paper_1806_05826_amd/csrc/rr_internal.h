@@ -98,6 +98,7 @@ struct Work {
   double *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr;
   double *e1 = nullptr, *e2 = nullptr, *rho = nullptr, *b = nullptr;
   double *D = nullptr;            // Jacobi diagonal at the current lambda
+  double *vin = nullptr, *vout = nullptr, *xref = nullptr;  // boundary permutation buffers
   double *u = nullptr;            // [N]
   double *c = nullptr, *yc = nullptr;   // [FC]
   double *partials = nullptr;     // reduction partials
@@ -111,13 +112,15 @@ struct Work {
 struct rr_handle {
   int device = 0;
   rr::Sparse X;
+  int* fperm = nullptr;         // [F] internal feature -> caller's feature
+  int* finv = nullptr;          // [F] caller's feature -> internal feature
   double* colnorm = nullptr;    // [F] ||x_j||^2
   double* gersh = nullptr;      // [F] (X^T X 1)_j
   bool nonneg = true;
   // aggregation
   int k_req = 0, FC = 0, n_centres = 0, kmeans_iters = 0;
   int* labels = nullptr;        // [F] in [0, FC)
-  int* centres = nullptr;       // [k]
+  int* centres = nullptr;       // [k] caller's feature indices, draw order
   int* csize = nullptr;         // [FC]
   double* cscale = nullptr;     // [FC] 1/sqrt(n_s)
   int* perm = nullptr;          // [F] features sorted by cluster (stable)
@@ -168,6 +171,7 @@ void launch_segsum(const MergePlan& mp, const int* seg_end, const int* idx, cons
 void launch_csc(const Sparse& X, const double* u, int mode, const Epi& e, const int* done,
                 hipStream_t s);
 rr_status build_csc(Sparse& X, hipStream_t s);
+rr_status renumber_features(Sparse& X, int* fperm, int* finv, hipStream_t s);
 rr_status validate_csr(const Sparse& X, hipStream_t s);
 
 // ---- vector kernels (blas1.hip) ---------------------------------------------
@@ -184,6 +188,8 @@ void launch_prolong(int F, const int* labels, const double* cscale, const double
                     const double* e1, double* out, const double* r, const double* D,
                     double omega, int additive, Scalars* sc, double* partials, hipStream_t s);
 void launch_fill(double* x, double v, long long n, hipStream_t s);
+// dst[i] = src[idx[i]]
+void launch_gather(double* dst, const double* src, const int* idx, int n, hipStream_t s);
 void launch_copy(double* dst, const double* src, long long n, hipStream_t s);
 void launch_colnorm_diag(int F, const double* colnorm, double lam, double* D, hipStream_t s);
 void launch_jacobi_apply(int F, const double* r, const double* D, double* z, hipStream_t s);

@@ -249,20 +249,24 @@ __global__ __launch_bounds__(kBlock) void k_segsum(
   }
 }
 
+// One wave per tile-crossing segment: lanes add the tile partials in a fixed
+// strided pattern, then a fixed butterfly; head of the last tile added last.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_segfix(const int4* __restrict__ span, int nspan,
                                                    const double* __restrict__ head,
                                                    const double* __restrict__ tail,
                                                    int nmain, Epi e, const int* done) {
   if (is_done(done)) return;
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   double dot = 0.0;
-  if (i < nspan) {
-    const int4 sp = span[i];
-    double acc = tail[sp.y];
-    for (int bb = sp.y + 1; bb < sp.z; ++bb) acc += tail[bb];
+  if (wave < nspan) {
+    const int4 sp = span[wave];
+    double acc = 0.0;
+    for (int bb = sp.y + lane; bb < sp.z; bb += 64) acc += tail[bb];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
     acc += head[sp.z];
-    seg_finish<MODE>(sp.x, acc, e, dot);
+    if (lane == 0) seg_finish<MODE>(sp.x, acc, e, dot);
   }
   if constexpr (has_dot<MODE>()) {
     double vv[1] = {dot}, tot[1];
@@ -276,7 +280,7 @@ template <int MODE>
 static void segsum_mode(const MergePlan& mp, const int* seg_end, const int* idx,
                         const double* val, const double* v, const Epi& e, const int* done,
                         hipStream_t s) {
-  const int nfix = std::max(1, cdiv(mp.nspan, kBlock));
+  const int nfix = std::max(1, cdiv(mp.nspan, kBlock / 64));
   const int nslots = mp.nblocks + nfix;
   if (val)
     k_segsum<MODE, false><<<mp.nblocks, kBlock, 0, s>>>(seg_end, idx, val, v, mp.coord, mp.head,
@@ -466,6 +470,89 @@ static unsigned bits_for(int n) {
   unsigned b = 1;
   while ((1ll << b) < (long long)n) ++b;
   return b;
+}
+
+// ---------------------------------------------------------------------------
+// Feature renumbering (setup only): internal feature order = descending
+// column count, ties in the caller's order, so the most popular columns'
+// entries of every F-vector share cache lines and the CSR gathers of v hit
+// the L1.  fperm[new] = caller index, finv[caller] = new index.
+// ---------------------------------------------------------------------------
+__global__ void k_col_count(const int* col_idx, int nnz, int* cnt) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += gridDim.x * blockDim.x)
+    atomicAdd(&cnt[col_idx[e]], 1);
+}
+
+__global__ void k_invert(const int* fperm, int F, int* finv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < F) finv[fperm[i]] = i;
+}
+
+// key = row << 32 | new column, so a radix sort orders each row by new index
+__global__ void k_row_keys(const int* ptr, const int* col_idx, const int* finv, int N,
+                           unsigned long long* keys) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  for (int e = ptr[i]; e < ptr[i + 1]; ++e)
+    keys[e] = ((unsigned long long)i << 32) | (unsigned)finv[col_idx[e]];
+}
+
+__global__ void k_keys_to_cols(const unsigned long long* keys, int nnz, int* col_idx) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nnz) col_idx[e] = (int)(keys[e] & 0xffffffffull);
+}
+
+rr_status renumber_features(Sparse& X, int* fperm, int* finv, hipStream_t s) {
+  const int F = X.F, nnz = X.nnz, N = X.N;
+  int *cnt = nullptr, *cnt_out = nullptr, *iota = nullptr;
+  RR_HIP(hipMalloc(&cnt, sizeof(int) * F));
+  RR_HIP(hipMalloc(&cnt_out, sizeof(int) * F));
+  RR_HIP(hipMalloc(&iota, sizeof(int) * F));
+  RR_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * F, s));
+  if (nnz) k_col_count<<<std::min(4096, cdiv(nnz, kBlock)), kBlock, 0, s>>>(X.col_idx, nnz, cnt);
+  k_iota<<<cdiv(F, kBlock), kBlock, 0, s>>>(iota, F);
+  size_t tmp_bytes = 0;
+  RR_HIP(rocprim::radix_sort_pairs_desc(nullptr, tmp_bytes, cnt, cnt_out, iota, fperm, (size_t)F, 0u,
+                                        32u, s));
+  void* tmp = nullptr;
+  RR_HIP(hipMalloc(&tmp, std::max<size_t>(tmp_bytes, 1)));
+  RR_HIP(rocprim::radix_sort_pairs_desc(tmp, tmp_bytes, cnt, cnt_out, iota, fperm, (size_t)F, 0u, 32u,
+                                        s));
+  k_invert<<<cdiv(F, kBlock), kBlock, 0, s>>>(fperm, F, finv);
+  RR_HIP(hipStreamSynchronize(s));
+  RR_HIP(hipFree(tmp));
+  RR_HIP(hipFree(cnt));
+  RR_HIP(hipFree(cnt_out));
+  RR_HIP(hipFree(iota));
+  if (nnz == 0) return RR_OK;
+  unsigned long long *keys = nullptr, *keys_out = nullptr;
+  RR_HIP(hipMalloc(&keys, sizeof(unsigned long long) * nnz));
+  RR_HIP(hipMalloc(&keys_out, sizeof(unsigned long long) * nnz));
+  k_row_keys<<<cdiv(N, kBlock), kBlock, 0, s>>>(X.row_ptr, X.col_idx, finv, N, keys);
+  unsigned end_bit = 32 + bits_for(N);
+  tmp_bytes = 0;
+  if (X.binary) {
+    RR_HIP(rocprim::radix_sort_keys(nullptr, tmp_bytes, keys, keys_out, (size_t)nnz, 0u, end_bit, s));
+    RR_HIP(hipMalloc(&tmp, std::max<size_t>(tmp_bytes, 1)));
+    RR_HIP(rocprim::radix_sort_keys(tmp, tmp_bytes, keys, keys_out, (size_t)nnz, 0u, end_bit, s));
+  } else {
+    double* vout = nullptr;
+    RR_HIP(hipMalloc(&vout, sizeof(double) * nnz));
+    RR_HIP(rocprim::radix_sort_pairs(nullptr, tmp_bytes, keys, keys_out, X.val, vout, (size_t)nnz, 0u,
+                                     end_bit, s));
+    RR_HIP(hipMalloc(&tmp, std::max<size_t>(tmp_bytes, 1)));
+    RR_HIP(rocprim::radix_sort_pairs(tmp, tmp_bytes, keys, keys_out, X.val, vout, (size_t)nnz, 0u,
+                                     end_bit, s));
+    RR_HIP(hipMemcpyAsync(X.val, vout, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
+    RR_HIP(hipStreamSynchronize(s));
+    RR_HIP(hipFree(vout));
+  }
+  k_keys_to_cols<<<cdiv(nnz, kBlock), kBlock, 0, s>>>(keys_out, nnz, X.col_idx);
+  RR_HIP(hipStreamSynchronize(s));
+  RR_HIP(hipFree(tmp));
+  RR_HIP(hipFree(keys));
+  RR_HIP(hipFree(keys_out));
+  return RR_OK;
 }
 
 // CSC by a stable radix sort of (column, CSR position): rows stay increasing

@@ -112,13 +112,21 @@ def test_fullsize_solve(rr, big, solver_random_labels, lam):
     its = []
     rng = np.random.default_rng(1)
     Ac0 = tl.Ac.copy()
-    for t in range(3):
-        tl.D = D0 if t == 0 else D0 * (1.0 + (rng.random(D0.size) - 0.5) * 4 * 2**-53)
-        if t > 0:   # A_c to within 2 ulp, symmetric
+    plain = tl.coarse_correction
+    for t in range(4):
+        tl.D = D0
+        tl.coarse_correction = plain
+        if t in (1, 2):   # coarse solve through an explicit inverse
+            L0 = np.linalg.cholesky(Ac0)
+            Ai = np.linalg.inv(Ac0) if t == 1 else np.linalg.inv(L0).T @ np.linalg.inv(L0)
+            tl.coarse_correction = lambda r, Ai=Ai: tl.P @ (Ai @ (tl.P.T @ r))
+        elif t == 3:      # diagonal and A_c to within 2 ulp, A_c symmetric
+            tl.D = D0 * (1.0 + (rng.random(D0.size) - 0.5) * 4 * 2**-53)
             E = (rng.random(Ac0.shape) - 0.5) * 4 * 2**-53
             tl.Ac = Ac0 * (1.0 + 0.5 * (E + E.T))
             tl.L = np.linalg.cholesky(tl.Ac)
         its.append(krylov.pcg(A, b, tl.vcycle, tol=1e-10, max_iter=2000)[1].iters)
+    tl.coarse_correction = plain
     slack = 1 + int(0.02 * max(its))
     assert min(its) - slack <= info["iters"] <= max(its) + slack, (info["iters"], its)
     # oracle at equal iteration count once converged (1e-13)

@@ -127,9 +127,11 @@ def test_precond_parity(rr, clustered, kind):
 
 def oracle_iteration_spread(P, lam, kind, lab, fc, tol, max_iter, n=6, seed=0):
     """Iteration counts of the oracle itself under rounding-level changes:
-    the preconditioner's diagonal (or, for CG, an identity scaling) and the
-    coarse matrix are perturbed entrywise by at most 2 ulp.  FP64 Krylov
-    iteration counts are only defined up to this spread."""
+    the coarse solve done through an explicit inverse, and the
+    preconditioner's diagonal (or, for CG, an identity scaling) and the
+    coarse matrix perturbed entrywise by at most 2 ulp.  FP64 Krylov
+    iteration counts are only defined up to this spread (near a residual
+    plateau it spans several iterations)."""
     b = op.rhs(P.X, P.y)
     A = lambda v: op.apply_A(P.X, lam, v)
     F = P.X.shape[1]
@@ -145,8 +147,15 @@ def oracle_iteration_spread(P, lam, kind, lab, fc, tol, max_iter, n=6, seed=0):
             B = lambda r, D=D: r / D
         else:
             tl = precond.TwoLevel(P.X, lam, lab, fc, omega)
-            tl.D = tl.D * pert
-            if t > 0:   # A_c to within 2 ulp, symmetric: its rounding class
+            if t in (1, 2):
+                # the coarse solve through an explicit inverse (LU-based, or
+                # from the Cholesky factor): the same solve in another
+                # rounding order
+                Ai = np.linalg.inv(tl.Ac) if t == 1 else np.linalg.inv(tl.L).T @ np.linalg.inv(tl.L)
+                tl.coarse_correction = lambda r, tl=tl, Ai=Ai: tl.P @ (Ai @ (tl.P.T @ r))
+            elif t > 2:
+                # diagonal and A_c to within 2 ulp (A_c kept symmetric)
+                tl.D = tl.D * pert
                 E = (rng.random(tl.Ac.shape) - 0.5) * 4 * 2**-53
                 tl.Ac = tl.Ac * (1.0 + 0.5 * (E + E.T))
                 tl.L = coarse.cholesky(tl.Ac)
