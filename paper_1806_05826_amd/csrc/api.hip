@@ -74,6 +74,8 @@ void destroy_handle(rr_handle* h) {
   dfree(X.row_ptr); dfree(X.col_idx); dfree(X.val);
   dfree(X.col_ptr); dfree(X.row_idx); dfree(X.cval);
   free_merge_plan(X.csc_plan);
+  free_sell(X.sell_csr);
+  free_sell(X.sell_csc);
   free_merge_plan(h->restrict_plan);
   dfree(h->colnorm); dfree(h->gersh); dfree(h->fperm); dfree(h->finv);
   dfree(h->labels); dfree(h->centres); dfree(h->csize); dfree(h->cscale);
@@ -123,6 +125,13 @@ rr_status setup_impl(const rr_csr* Xin, const rr_setup_opts* o, hipStream_t s, r
   RR_TRY(dalloc(&h->finv, X.F));
   RR_TRY(renumber_features(X, h->fperm, h->finv, s));
   RR_TRY(build_csc(X, s));
+  {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess &&
+        ncu > 0)
+      X.num_cu = ncu;
+  }
+  RR_TRY(build_sell_plans(X, s));
   // column norms and Gershgorin row sums g = X^T (X 1)
   RR_TRY(dalloc(&h->colnorm, X.F));
   RR_TRY(dalloc(&h->gersh, X.F));
@@ -165,7 +174,8 @@ rr_status setup_impl(const rr_csr* Xin, const rr_setup_opts* o, hipStream_t s, r
     RR_TRY(run_kmeans(h, k, o->seed, mi, s));
   }
   h->kmeans_ms = now_ms() - tk;
-  int np = std::max(X.csc_plan.nblocks + cdiv(X.csc_plan.nspan, kBlock / 64) + 1, cdiv(F, kBlock) + 1);
+  int np = cdiv(F, kBlock) + 1;   // >= every reduction grid (the segment reduction uses <= 256)
+  if (!X.binary) np = std::max(np, X.csc_plan.nblocks + cdiv(X.csc_plan.nspan, kBlock / 64) + 1);
   if (h->FC > 0) {
     const int fc = h->FC;
     RR_TRY(dalloc(&h->K, (size_t)fc * fc));
@@ -182,8 +192,17 @@ rr_status setup_impl(const rr_csr* Xin, const rr_setup_opts* o, hipStream_t s, r
     RR_TRY(dalloc(&w.yc, fc));
     np = std::max(np, h->restrict_plan.nblocks + cdiv(h->restrict_plan.nspan, kBlock / 64) + 1);
   }
+  // five partial regions (pq, upd, rz, init, tr), each large enough for the
+  // widest producer grid
+  np = std::max(np, 3 * kMaxParts);
   w.npartials = np;
-  RR_TRY(dalloc(&w.partials, 3 * (size_t)np));
+  RR_TRY(dalloc(&w.partials, 5 * (size_t)np));
+  w.parts.pq = w.partials;
+  w.parts.upd = w.partials + (size_t)np;
+  w.parts.rz = w.partials + 2 * (size_t)np;
+  w.parts.init = w.partials + 3 * (size_t)np;
+  w.parts.tr = w.partials + 4 * (size_t)np;
+  w.parts.n_vec = vec_grid(F);
   RR_HIP(hipStreamSynchronize(s));
   RR_HIP(hipGetLastError());
   h->setup_ms = now_ms() - t0;
@@ -260,31 +279,36 @@ rr_status prof_pair(rr_handle* h, Prof& pf, int* idx) {
 }
 
 // Apply the operator pieces with optional event timing.
-rr_status op_csr(rr_handle* h, Prof& pf, int tag, const double* v, hipStream_t s) {
+rr_status op_csr(rr_handle* h, Prof& pf, int tag, const double* v, hipStream_t s,
+                 const StageArgs* stage = nullptr) {
   const int* done = &h->w.sc->done;
   if (!pf.on) {
-    launch_csr(h->X, v, h->w.u, done, s);
+    launch_csr(h->X, v, h->w.u, done, s, stage);
     return RR_OK;
   }
   int i;
   RR_TRY(prof_pair(h, pf, &i));
   RR_HIP(hipEventRecord(h->ev_pool[2 * i], s));
-  launch_csr(h->X, v, h->w.u, done, s);
+  launch_csr(h->X, v, h->w.u, done, s, stage);
   RR_HIP(hipEventRecord(h->ev_pool[2 * i + 1], s));
   pf.csr.push_back({i, tag});
   return RR_OK;
 }
 
-rr_status op_csc(rr_handle* h, Prof& pf, int tag, int mode, const Epi& e, hipStream_t s) {
+// *nparts receives the count of block partials a dot-product epilogue left.
+rr_status op_csc(rr_handle* h, Prof& pf, int tag, int mode, const Epi& e, hipStream_t s,
+                 int* nparts = nullptr) {
   const int* done = &h->w.sc->done;
   if (!pf.on) {
-    launch_csc(h->X, h->w.u, mode, e, done, s);
+    const int n = launch_csc(h->X, h->w.u, mode, e, done, s);
+    if (nparts) *nparts = n;
     return RR_OK;
   }
   int i;
   RR_TRY(prof_pair(h, pf, &i));
   RR_HIP(hipEventRecord(h->ev_pool[2 * i], s));
-  launch_csc(h->X, h->w.u, mode, e, done, s);
+  const int n = launch_csc(h->X, h->w.u, mode, e, done, s);
+  if (nparts) *nparts = n;
   RR_HIP(hipEventRecord(h->ev_pool[2 * i + 1], s));
   pf.csc.push_back({i, tag});
   return RR_OK;
@@ -294,14 +318,16 @@ Epi base_epi(rr_handle* h, double lam) {
   Epi e{};
   e.lam = lam;
   e.sc = h->w.sc;
-  e.partials = h->w.partials;
   e.D = h->w.D;
   return e;
 }
 
 // z = B r for the two-level forms; e1 (V-cycle) must already hold w D^-1 r.
+// The partials of <r, z> are left in parts.rz (*n_rz of them).  With a
+// stage, the convergence check of the preceding update runs first.
 rr_status precond_two_level(rr_handle* h, Prof& pf, int tag, int kind, double lam, double omega,
-                            const LambdaSlot& sl, const double* r, double* z, hipStream_t s) {
+                            const LambdaSlot& sl, const double* r, double* z,
+                            const StageArgs* stage, int* n_rz, hipStream_t s) {
   Work& w = h->w;
   const int F = h->X.F;
   const int* done = &w.sc->done;
@@ -309,13 +335,16 @@ rr_status precond_two_level(rr_handle* h, Prof& pf, int tag, int kind, double la
   er.scale = h->cscale;
   er.out = w.c;
   if (kind == PK_ADDITIVE) {
+    if (stage) launch_stage_update(*stage, s);
     launch_segsum(h->restrict_plan, h->coff + 1, h->perm, nullptr, r, EPI_SCALE, er, done, s);
     launch_gemv(h->FC, sl.Ainv, w.c, w.yc, done, s);
-    launch_prolong(F, h->labels, h->cscale, w.yc, nullptr, z, r, w.D, omega, 1, w.sc, w.partials, s);
+    launch_prolong(F, h->labels, h->cscale, w.yc, nullptr, z, r, w.D, omega, 1, w.sc,
+                   w.parts.rz, s);
+    *n_rz = w.parts.n_vec;
     return RR_OK;
   }
   // V(1,1): rho1 = r - A e1
-  RR_TRY(op_csr(h, pf, tag, w.e1, s));
+  RR_TRY(op_csr(h, pf, tag, w.e1, s, stage));
   Epi e = base_epi(h, lam);
   e.p = w.e1;
   e.r = r;
@@ -332,7 +361,8 @@ rr_status precond_two_level(rr_handle* h, Prof& pf, int tag, int kind, double la
   e2.r = r;
   e2.omega = omega;
   e2.out = z;
-  RR_TRY(op_csc(h, pf, tag, EPI_POST, e2, s));
+  e2.partials = w.parts.rz;
+  RR_TRY(op_csc(h, pf, tag, EPI_POST, e2, s, n_rz));
   return RR_OK;
 }
 
@@ -386,11 +416,19 @@ rr_status solve_impl(rr_handle* h, double lam, const double* rhs, double* wout,
     launch_gather(w.xref, op.x_ref, h->fperm, F, s);
     xref = w.xref;
   }
-  launch_pcg_init(F, w.b, w.x, w.r, w.p, w.z, w.e1, w.D, xref, omega, kind, w.sc, w.partials,
-                  op.residual_history, s);
-  if (kind == PK_VCYCLE || kind == PK_ADDITIVE)
-    RR_TRY(precond_two_level(h, pf, -1, kind, lam, omega, *sl, w.r, w.z, s));
-  launch_pupdate(F, w.p, w.z, w.sc, s);
+  const bool two_level = (kind == PK_VCYCLE || kind == PK_ADDITIVE);
+  const int nv = w.parts.n_vec;
+  launch_pcg_init(F, w.b, w.x, w.r, w.p, w.z, w.e1, w.D, xref, omega, kind, w.parts.init, s);
+  launch_finish_init(w.sc, w.parts.init, nv, op.residual_history, kind, s);
+  if (two_level) {
+    int nrz = 0;
+    RR_TRY(precond_two_level(h, pf, -1, kind, lam, omega, *sl, w.r, w.z, nullptr, &nrz, s));
+    launch_pupdate(F, w.p, w.z, w.sc, w.parts.rz, nrz, 1, nullptr, s);
+  } else {
+    launch_pupdate(F, w.p, w.z, w.sc, w.parts.init + 2 * nv, nv, 1, nullptr, s);
+  }
+  // the convergence check after each update runs in the kernel that follows it
+  StageArgs stage{w.sc, w.parts.upd, nv, op.residual_history, kind};
   int queued = 0;
   for (;;) {
     for (int c = 0; c < chunk; ++c, ++queued) {
@@ -398,12 +436,19 @@ rr_status solve_impl(rr_handle* h, double lam, const double* rhs, double* wout,
       Epi e = base_epi(h, lam);
       e.p = w.p;
       e.out = w.q;
-      RR_TRY(op_csc(h, pf, queued, EPI_APPLY_DOT, e, s));
+      e.partials = w.parts.pq;
+      int npq = 0;
+      RR_TRY(op_csc(h, pf, queued, EPI_APPLY_DOT, e, s, &npq));
       launch_pcg_update(F, w.x, w.r, w.p, w.q, w.z, w.e1, w.D, xref, omega, kind, w.sc,
-                        w.partials, op.residual_history, s);
-      if (kind == PK_VCYCLE || kind == PK_ADDITIVE)
-        RR_TRY(precond_two_level(h, pf, 100000000 + queued, kind, lam, omega, *sl, w.r, w.z, s));
-      launch_pupdate(F, w.p, w.z, w.sc, s);
+                        w.parts.pq, npq, w.parts.upd, s);
+      if (two_level) {
+        int nrz = 0;
+        RR_TRY(precond_two_level(h, pf, 100000000 + queued, kind, lam, omega, *sl, w.r, w.z,
+                                 &stage, &nrz, s));
+        launch_pupdate(F, w.p, w.z, w.sc, w.parts.rz, nrz, 0, nullptr, s);
+      } else {
+        launch_pupdate(F, w.p, w.z, w.sc, nullptr, 0, 0, &stage, s);
+      }
     }
     RR_HIP(hipMemcpyAsync(&hs, w.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
     RR_HIP(hipStreamSynchronize(s));
@@ -420,7 +465,9 @@ rr_status solve_impl(rr_handle* h, double lam, const double* rhs, double* wout,
     e.p = w.x;
     e.r = w.b;
     e.out = nullptr;
-    launch_csc(h->X, w.u, EPI_TRUE, e, nullptr, s);
+    e.partials = w.parts.tr;
+    const int ntr = launch_csc(h->X, w.u, EPI_TRUE, e, nullptr, s);
+    launch_finish_true(w.sc, w.parts.tr, ntr, s);
   }
   RR_HIP(hipMemcpyAsync(&hs, w.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
   RR_HIP(hipStreamSynchronize(s));
@@ -611,7 +658,8 @@ rr_status rr_apply_precond(rr_handle* h, double lambda, int32_t precond, double 
   RR_HIP(hipMemcpyAsync(w.sc, &hs, sizeof(Scalars), hipMemcpyHostToDevice, s));
   if (precond == PK_VCYCLE) k_smooth<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, w.vin, w.D, omega, w.e1);
   Prof pf;
-  RR_TRY(precond_two_level(h, pf, 0, precond, lambda, omega, *sl, w.vin, w.vout, s));
+  int nrz = 0;
+  RR_TRY(precond_two_level(h, pf, 0, precond, lambda, omega, *sl, w.vin, w.vout, nullptr, &nrz, s));
   launch_gather(z, w.vout, h->finv, F, s);
   RR_HIP(hipStreamSynchronize(s));
   RR_HIP(hipGetLastError());

@@ -1,13 +1,30 @@
 // Fused vector kernels of the PCG iteration (the x/r updates and the
 // scalars of the flexible-CG algorithm's update steps, specialised to a
-// fixed preconditioner).  Every reduction finishes in the last block to
-// arrive, in block order, so scalars stay on the device and results are
-// bitwise reproducible run to run.
+// fixed preconditioner).  A reduction leaves one partial per block; every
+// block of the kernel that needs the scalar adds the partials itself in slot
+// order, so scalars stay on the device, no block waits for another, and
+// results are bitwise reproducible run to run.
 #include "rr_device.h"
 
 namespace rr {
 
-// x = 0, r = b, p = 0, ||b||^2, ||x_ref||^2 and the first smoother step.
+int vec_grid(int F) { return std::max(1, std::min(kMaxParts, cdiv(F, kBlock))); }
+
+// Block partials of up to three sums, stored in parts[i * n + blockIdx.x].
+__device__ inline void store_parts3(double a, double b, double c, double* parts, int n) {
+  __shared__ double red[kBlock / 64];
+  const double ta = block_sum(a, red);
+  const double tb = block_sum(b, red);
+  const double tc = block_sum(c, red);
+  if (threadIdx.x == 0) {
+    parts[blockIdx.x] = ta;
+    parts[n + blockIdx.x] = tb;
+    parts[2 * n + blockIdx.x] = tc;
+  }
+}
+
+// x = 0, r = b, p = 0, the first smoother step, and the partials of ||b||^2,
+// ||x_ref||^2 and <r, z> (Jacobi / CG forms).
 __global__ __launch_bounds__(kBlock) void k_pcg_init(int F, const double* __restrict__ b,
                                                      double* __restrict__ x,
                                                      double* __restrict__ r,
@@ -16,134 +33,186 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(int F, const double* __rest
                                                      double* __restrict__ e1,
                                                      const double* __restrict__ D,
                                                      const double* __restrict__ xref,
-                                                     double omega, int kind, Scalars* sc,
-                                                     double* partials, double* history) {
-  const int j = blockIdx.x * kBlock + threadIdx.x;
-  double v[3] = {0.0, 0.0, 0.0};
-  if (j < F) {
+                                                     double omega, int kind, double* parts) {
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < F; j += gridDim.x * kBlock) {
     const double bj = b[j];
     x[j] = 0.0;
     r[j] = bj;
     p[j] = 0.0;
-    v[0] = bj * bj;
-    if (xref) v[1] = xref[j] * xref[j];
+    v0 += bj * bj;
+    if (xref) v1 += xref[j] * xref[j];
     if (kind == PK_JACOBI) {
       const double zj = bj / D[j];
       z[j] = zj;
-      v[2] = bj * zj;
+      v2 += bj * zj;
     } else if (kind == PK_NONE) {
       z[j] = bj;
-      v[2] = bj * bj;
+      v2 += bj * bj;
     } else if (kind == PK_VCYCLE) {
       e1[j] = (omega * bj) / D[j];
     }
   }
-  double tot[3];
-  if (grid_finish<3>(v, partials, 0, gridDim.x, &sc->ticket, tot) && threadIdx.x == 0) {
-    sc->bb = tot[0];
-    sc->ref2 = tot[1];
-    sc->tol2 *= tot[0];
-    sc->errtol2 *= tot[1];
-    sc->iter = 0;
-    if (history) history[0] = (tot[0] > 0.0) ? 1.0 : 0.0;
-    if (!(tot[0] > 0.0)) {
-      sc->done = 1;
-      sc->status = (tot[0] == 0.0) ? RR_OK : RR_ERR_BREAKDOWN;
-      sc->true_rr = 0.0;
-    } else if (kind == PK_JACOBI || kind == PK_NONE) {
-      finish_beta(sc, tot[2]);
-    }
-  }
+  store_parts3(v0, v1, v2, parts, gridDim.x);
 }
 
 void launch_pcg_init(int F, const double* b, double* x, double* r, double* p, double* z,
                      double* e1, const double* D, const double* xref, double omega, int kind,
-                     Scalars* sc, double* partials, double* history, hipStream_t s) {
-  k_pcg_init<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, b, x, r, p, z, e1, D, xref, omega, kind, sc,
-                                                partials, history);
+                     double* parts_init, hipStream_t s) {
+  k_pcg_init<<<vec_grid(F), kBlock, 0, s>>>(F, b, x, r, p, z, e1, D, xref, omega, kind,
+                                            parts_init);
 }
 
-// x += alpha p; r -= alpha q; ||r||^2; optional error; next smoother input.
+// ||b||^2 and ||x_ref||^2 from the init partials; scales the tolerances.
+__global__ __launch_bounds__(kBlock) void k_finish_init(Scalars* sc, const double* parts, int n,
+                                                        double* history) {
+  __shared__ double red[kBlock / 64];
+  const double bb = sum_parts<kBlock>(parts, n, red);
+  const double ref2 = sum_parts<kBlock>(parts + n, n, red);
+  if (threadIdx.x != 0) return;
+  sc->bb = bb;
+  sc->ref2 = ref2;
+  sc->tol2 *= bb;
+  sc->errtol2 *= ref2;
+  sc->iter = 0;
+  if (history) history[0] = (bb > 0.0) ? 1.0 : 0.0;
+  if (!(bb > 0.0)) {
+    sc->done = 1;
+    sc->status = (bb == 0.0) ? RR_OK : RR_ERR_BREAKDOWN;
+    sc->true_rr = 0.0;
+  }
+}
+
+void launch_finish_init(Scalars* sc, const double* parts_init, int n, double* history, int,
+                        hipStream_t s) {
+  k_finish_init<<<1, kBlock, 0, s>>>(sc, parts_init, n, history);
+}
+
+// alpha = <r,z> / <p,Ap> (every block adds the <p,Ap> partials itself), then
+// x += alpha p; r -= alpha q; the next smoother input; partials of ||r||^2,
+// the error and <r, z> (Jacobi / CG forms).  The convergence check runs in
+// the next kernel.
 __global__ __launch_bounds__(kBlock) void k_pcg_update(
     int F, double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
     const double* __restrict__ q, double* __restrict__ z, double* __restrict__ e1,
     const double* __restrict__ D, const double* __restrict__ xref, double omega, int kind,
-    Scalars* sc, double* partials, double* history) {
+    Scalars* sc, const double* __restrict__ parts_pq, int n_pq, double* parts_upd) {
   if (sc->done) return;
-  const double alpha = sc->alpha;
-  const int j = blockIdx.x * kBlock + threadIdx.x;
-  double v[3] = {0.0, 0.0, 0.0};
-  if (j < F) {
+  __shared__ double red[kBlock / 64];
+  const double pq = sum_parts<kBlock>(parts_pq, n_pq, red);
+  if (!finite_pos(pq)) {
+    if (is_block0_lead()) {
+      sc->pq = pq;
+      sc->status = RR_ERR_BREAKDOWN;
+      sc->done = 1;
+    }
+    return;
+  }
+  const double rz = sc->rz_next;
+  const double alpha = rz / pq;
+  if (is_block0_lead()) {
+    sc->pq = pq;
+    sc->alpha = alpha;
+    sc->rz = rz;
+    sc->iter = sc->iter + 1;
+  }
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < F; j += gridDim.x * kBlock) {
     const double xj = x[j] + alpha * p[j];
     const double rj = r[j] - alpha * q[j];
     x[j] = xj;
     r[j] = rj;
-    v[0] = rj * rj;
+    v0 += rj * rj;
     if (xref) {
       const double d = xj - xref[j];
-      v[1] = d * d;
+      v1 += d * d;
     }
     if (kind == PK_JACOBI) {
       const double zj = rj / D[j];
       z[j] = zj;
-      v[2] = rj * zj;
+      v2 += rj * zj;
     } else if (kind == PK_NONE) {
       z[j] = rj;
-      v[2] = rj * rj;
+      v2 += rj * rj;
     } else if (kind == PK_VCYCLE) {
       e1[j] = (omega * rj) / D[j];
     }
   }
-  double tot[3];
-  if (grid_finish<3>(v, partials, 0, gridDim.x, &sc->ticket, tot) && threadIdx.x == 0) {
-    const double rr = tot[0];
-    sc->rr = rr;
-    sc->ee = tot[1];
-    const int it = ++sc->iter;
-    if (history) history[it] = sqrt(rr / sc->bb);
-    if (!(rr == rr)) {
-      sc->status = RR_ERR_BREAKDOWN;
-      sc->done = 1;
-      return;
-    }
-    if (sc->fixed > 0) {
-      if (it >= sc->fixed) {
-        sc->status = RR_OK;
-        sc->done = 1;
-      }
-    } else if (rr <= sc->tol2 || (sc->use_err && tot[1] <= sc->errtol2)) {
-      sc->status = RR_OK;
-      sc->done = 1;
-    } else if (it >= sc->limit) {
-      sc->done = 1;
-    }
-    if (!sc->done && (kind == PK_JACOBI || kind == PK_NONE)) finish_beta(sc, tot[2]);
-  }
+  store_parts3(v0, v1, v2, parts_upd, gridDim.x);
 }
 
 void launch_pcg_update(int F, double* x, double* r, const double* p, const double* q,
                        double* z, double* e1, const double* D, const double* xref,
-                       double omega, int kind, Scalars* sc, double* partials, double* history,
-                       hipStream_t s) {
-  k_pcg_update<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, x, r, p, q, z, e1, D, xref, omega, kind,
-                                                  sc, partials, history);
+                       double omega, int kind, Scalars* sc, const double* parts_pq, int n_pq,
+                       double* parts_upd, hipStream_t s) {
+  k_pcg_update<<<vec_grid(F), kBlock, 0, s>>>(F, x, r, p, q, z, e1, D, xref, omega, kind, sc,
+                                              parts_pq, n_pq, parts_upd);
 }
 
+// p = z + beta p with beta = <r,z>_new / <r,z>_old (0 on the first call).
+// With a stage, the convergence check of the preceding update runs first and
+// <r,z> comes from the update's partials.
 __global__ __launch_bounds__(kBlock) void k_pupdate(int F, double* __restrict__ p,
-                                                    const double* __restrict__ z,
-                                                    const Scalars* sc) {
+                                                    const double* __restrict__ z, Scalars* sc,
+                                                    const double* __restrict__ parts_rz,
+                                                    int n_rz, int first, StageArgs stage) {
   if (sc->done) return;
-  const double beta = sc->beta;
-  const int j = blockIdx.x * kBlock + threadIdx.x;
-  if (j < F) p[j] = z[j] + beta * p[j];
+  __shared__ double red[kBlock / 64];
+  double rz_new;
+  if (stage.sc) {
+    if (stage_update<kBlock>(stage, red, rz_new)) return;
+  } else {
+    rz_new = sum_parts<kBlock>(parts_rz, n_rz, red);
+  }
+  if (!finite_pos(rz_new)) {
+    if (is_block0_lead()) {
+      sc->status = RR_ERR_BREAKDOWN;
+      sc->done = 1;
+    }
+    return;
+  }
+  const double beta = first ? 0.0 : rz_new / sc->rz;
+  if (is_block0_lead()) {
+    sc->rz_next = rz_new;
+    sc->beta = beta;
+  }
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < F; j += gridDim.x * kBlock)
+    p[j] = z[j] + beta * p[j];
 }
 
-void launch_pupdate(int F, double* p, const double* z, Scalars* sc, hipStream_t s) {
-  k_pupdate<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, p, z, sc);
+void launch_pupdate(int F, double* p, const double* z, Scalars* sc, const double* parts_rz,
+                    int n_rz, int first, const StageArgs* stage, hipStream_t s) {
+  StageArgs st{};
+  if (stage) st = *stage;
+  k_pupdate<<<vec_grid(F), kBlock, 0, s>>>(F, p, z, sc, parts_rz, n_rz, first, st);
+}
+
+// The convergence check alone (one block), where the next kernel cannot
+// host it.
+__global__ __launch_bounds__(kBlock) void k_stage_update(StageArgs st) {
+  if (st.sc->done) return;
+  __shared__ double red[kBlock / 64];
+  double rz_unused;
+  (void)stage_update<kBlock>(st, red, rz_unused);
+}
+
+void launch_stage_update(const StageArgs& st, hipStream_t s) {
+  k_stage_update<<<1, kBlock, 0, s>>>(st);
+}
+
+// ||b - A x||^2 from the partials of the true-residual pass.
+__global__ __launch_bounds__(kBlock) void k_finish_true(Scalars* sc, const double* parts, int n) {
+  __shared__ double red[kBlock / 64];
+  const double t = sum_parts<kBlock>(parts, n, red);
+  if (threadIdx.x == 0) sc->true_rr = t;
+}
+
+void launch_finish_true(Scalars* sc, const double* parts, int n, hipStream_t s) {
+  k_finish_true<<<1, kBlock, 0, s>>>(sc, parts, n);
 }
 
 // Prolongation: out = e1 + P yc (V-cycle), or the additive form
-// z = w D^-1 r + P yc with <r,z> -> beta.
+// z = w D^-1 r + P yc with partials of <r,z>.
 __global__ __launch_bounds__(kBlock) void k_prolong(int F, const int* __restrict__ labels,
                                                     const double* __restrict__ cscale,
                                                     const double* __restrict__ yc,
@@ -151,35 +220,31 @@ __global__ __launch_bounds__(kBlock) void k_prolong(int F, const int* __restrict
                                                     double* __restrict__ out,
                                                     const double* __restrict__ r,
                                                     const double* __restrict__ D, double omega,
-                                                    int additive, Scalars* sc,
-                                                    double* partials) {
+                                                    int additive, const Scalars* sc,
+                                                    double* parts_rz) {
   if (sc && sc->done) return;
-  const int j = blockIdx.x * kBlock + threadIdx.x;
-  double v[1] = {0.0};
-  if (j < F) {
+  double v = 0.0;
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < F; j += gridDim.x * kBlock) {
     const int s = labels[j];
     const double corr = cscale[s] * yc[s];
     if (additive) {
       const double rj = r[j];
       const double zj = (omega * rj) / D[j] + corr;
       out[j] = zj;
-      v[0] = rj * zj;
+      v += rj * zj;
     } else {
       out[j] = e1[j] + corr;
     }
   }
-  if (additive && sc) {
-    double tot[1];
-    if (grid_finish<1>(v, partials, 0, gridDim.x, &sc->ticket, tot) && threadIdx.x == 0)
-      finish_beta(sc, tot[0]);
-  }
+  if (parts_rz) store_block_partial<kBlock>(v, parts_rz, blockIdx.x);
 }
 
 void launch_prolong(int F, const int* labels, const double* cscale, const double* yc,
                     const double* e1, double* out, const double* r, const double* D,
-                    double omega, int additive, Scalars* sc, double* partials, hipStream_t s) {
-  k_prolong<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, labels, cscale, yc, e1, out, r, D, omega,
-                                               additive, sc, partials);
+                    double omega, int additive, const Scalars* sc, double* parts_rz,
+                    hipStream_t s) {
+  k_prolong<<<vec_grid(F), kBlock, 0, s>>>(F, labels, cscale, yc, e1, out, r, D, omega,
+                                           additive, sc, parts_rz);
 }
 
 __global__ void k_fill(double* x, double v, long long n) {
@@ -241,30 +306,6 @@ void launch_omega_gersh(int F, const double* g, const double* colnorm, double la
   k_omega_gersh<<<1, 1024, 0, s>>>(F, g, colnorm, lam, out);
 }
 
-__global__ void k_axpby(long long n, double a, const double* x, double b, double* y) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = a * x[i] + b * y[i];
-}
-void launch_axpby(long long n, double a, const double* x, double b, double* y, hipStream_t s) {
-  if (n > 0) k_axpby<<<cdiv(n, kBlock), kBlock, 0, s>>>(n, a, x, b, y);
-}
-
-__global__ __launch_bounds__(kBlock) void k_dot(long long n, const double* x, const double* y,
-                                                double* out, double* partials,
-                                                unsigned* ticket) {
-  double v[1] = {0.0};
-  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
-       i += (long long)gridDim.x * kBlock)
-    v[0] += x[i] * y[i];
-  double tot[1];
-  if (grid_finish<1>(v, partials, 0, gridDim.x, ticket, tot) && threadIdx.x == 0) *out = tot[0];
-}
-void launch_dot(long long n, const double* x, const double* y, double* out, double* partials,
-                unsigned* ticket, hipStream_t s) {
-  const int grid = std::max(1, std::min(1024, cdiv(n, kBlock)));
-  k_dot<<<grid, kBlock, 0, s>>>(n, x, y, out, partials, ticket);
-}
-
 // y = A x, A row-major n x n: one wave per row.
 __global__ __launch_bounds__(kBlock) void k_gemv(int n, const double* __restrict__ A,
                                                  const double* __restrict__ x,
@@ -274,10 +315,16 @@ __global__ __launch_bounds__(kBlock) void k_gemv(int n, const double* __restrict
   const int lane = threadIdx.x & 63;
   if (row >= n) return;
   const double* a = A + (size_t)row * n;
-  double acc = 0.0;
-  for (int c = lane; c < n; c += 64) acc += a[c] * x[c];
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if (lane == 0) y[row] = acc;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int c = lane;
+  for (; c + 192 < n; c += 256) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] += a[c + 64 * k] * x[c + 64 * k];
+  }
+  for (; c < n; c += 64) acc[0] += a[c] * x[c];
+  double t = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+  if (lane == 0) y[row] = t;
 }
 void launch_gemv(int n, const double* A, const double* x, double* y, const int* done,
                  hipStream_t s) {

@@ -1,5 +1,6 @@
-// Device helpers shared by the HIP kernels: block reductions and the
-// last-block ticket that finishes a grid-wide reduction in a fixed order.
+// Device helpers shared by the HIP kernels: block reductions, the sums of
+// block partials that every consumer block repeats in the same order, the
+// solver's convergence check, and the column epilogues.
 #pragma once
 
 #include "rr_internal.h"
@@ -20,89 +21,126 @@ __device__ inline double block_sum(double v, double* lds /* kBlock/64 */) {
   return t;
 }
 
-// Block-reduce NV values and store them in partial slot `slot` of
-// `partials` (layout partials[i * nslots + slot]).
-template <int NV>
-__device__ inline void write_partial(const double (&v)[NV], double* partials, int slot,
-                                     int nslots) {
-  __shared__ double red[kBlock / 64];
-  double bs[NV];
+// Sum over a block of NT threads; result in every thread; fixed tree.
+template <int NT>
+__device__ inline double block_sum_n(double v, double* lds /* NT/64 */) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int wid = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) lds[wid] = v;
+  __syncthreads();
+  double t = 0.0;
 #pragma unroll
-  for (int i = 0; i < NV; ++i) bs[i] = block_sum(v[i], red);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i)
-      __hip_atomic_store(&partials[i * nslots + slot], bs[i], __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-  }
+  for (int i = 0; i < NT / 64; ++i) t += lds[i];
+  __syncthreads();
+  return t;
 }
 
-// Wait until this thread's earlier memory operations have completed.  The
-// partials below are written with agent-scope (coherent) atomic stores, so
-// once they have completed every block can see them; no cache writeback of
-// the whole L2 is needed, unlike a full release fence.
+// Every block calls this with the same (p, n) and gets the same total: the
+// partials of a previous kernel added in one fixed order.
+template <int NT>
+__device__ inline double sum_parts(const double* p, int n, double* lds) {
+  double s = 0.0;
+  for (int j = threadIdx.x; j < n; j += NT) s += p[j];
+  return block_sum_n<NT>(s, lds);
+}
+
+// Wait until this thread's earlier memory operations have completed.  Used
+// after agent-scope (coherent) atomic stores that another block will read
+// once it has seen a later ticket; no cache writeback of the whole L2 is
+// needed, unlike a full release fence.
 __device__ inline void wait_stores() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __builtin_amdgcn_s_waitcnt(0);
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// Every block of the grid stores its partial in slot (slot0 + blockIdx.x);
-// the last block to arrive then adds all `nslots` partials (which may include
-// slots written by an earlier kernel) in slot order, and returns true with
-// the totals in `tot` (valid in every thread of that block).  Partials are
-// agent-scope atomic stores and loads; the arrival ticket is an agent-scope
-// atomic counter, reset by the last block.
-template <int NV>
-__device__ inline bool grid_finish(const double (&v)[NV], double* partials, int slot0,
-                                   int nslots, unsigned int* ticket, double (&tot)[NV]) {
-  __shared__ double red2[kBlock / 64];
-  __shared__ int is_last;
-  write_partial<NV>(v, partials, slot0 + blockIdx.x, nslots);
-  if (threadIdx.x == 0) {
-    wait_stores();
-    const unsigned int prev =
-        __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    is_last = (prev == (unsigned)gridDim.x - 1u);
-  }
-  __syncthreads();
-  if (!is_last) return false;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    double s = 0.0;
-    for (int j = threadIdx.x; j < nslots; j += kBlock)
-      s += __hip_atomic_load(&partials[i * nslots + j], __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-    tot[i] = block_sum(s, red2);
-  }
-  if (threadIdx.x == 0)
-    __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return true;
-}
-
 __device__ inline bool finite_pos(double v) { return v > 0.0 && v < __builtin_inf(); }
-
-// Scalar updates done by the finishing block (thread 0 only).
-__device__ inline void finish_alpha(Scalars* sc, double pq) {
-  sc->pq = pq;
-  if (!finite_pos(pq)) {
-    sc->status = RR_ERR_BREAKDOWN;
-    sc->done = 1;
-  } else {
-    sc->alpha = sc->rz / pq;
-  }
-}
-
-__device__ inline void finish_beta(Scalars* sc, double rz_new) {
-  if (!finite_pos(rz_new)) {
-    sc->status = RR_ERR_BREAKDOWN;
-    sc->done = 1;
-    return;
-  }
-  sc->beta = (sc->iter == 0) ? 0.0 : rz_new / sc->rz;
-  sc->rz = rz_new;
-}
 
 __device__ inline bool is_done(const int* done) { return done != nullptr && *done != 0; }
 
+__device__ inline bool is_block0_lead() { return blockIdx.x == 0 && threadIdx.x == 0; }
+
+// The convergence check after an x/r update, run by every block of the
+// kernel that follows the update (all blocks reach the same decision from
+// the same partials; block 0 records it).  The update kernel has already
+// advanced the iteration count.  Returns true when the solve is finished;
+// rz_new receives <r,z> of the new residual (Jacobi / CG forms).
+template <int NT>
+__device__ inline bool stage_update(const StageArgs& st, double* lds, double& rz_new) {
+  Scalars* sc = st.sc;
+  const double rr = sum_parts<NT>(st.upd, st.n, lds);
+  const double ee = sum_parts<NT>(st.upd + st.n, st.n, lds);
+  rz_new = sum_parts<NT>(st.upd + 2 * st.n, st.n, lds);
+  const int it = sc->iter;
+  bool fin = false;
+  int status = RR_ERR_NOT_CONVERGED;
+  if (!(rr == rr)) {
+    fin = true;
+    status = RR_ERR_BREAKDOWN;
+  } else if (sc->fixed > 0) {
+    if (it >= sc->fixed) {
+      fin = true;
+      status = RR_OK;
+    }
+  } else if (rr <= sc->tol2 || (sc->use_err && ee <= sc->errtol2)) {
+    fin = true;
+    status = RR_OK;
+  } else if (it >= sc->limit) {
+    fin = true;
+  }
+  if (is_block0_lead()) {
+    sc->rr = rr;
+    sc->ee = ee;
+    if (st.history) st.history[it] = sqrt(rr / sc->bb);
+    if (fin) {
+      sc->status = status;
+      sc->done = 1;
+    }
+  }
+  return fin;
+}
+
+// Segment epilogues: what happens to a finished column sum t of column s.
+template <int MODE>
+__device__ inline void seg_finish(int s, double t, const Epi& e, double& dot) {
+  if constexpr (MODE == EPI_STORE) {
+    e.out[s] = t;
+  } else if constexpr (MODE == EPI_APPLY) {
+    e.out[s] = t + e.lam * e.p[s];
+  } else if constexpr (MODE == EPI_APPLY_DOT) {
+    const double ps = e.p[s];
+    const double q = t + e.lam * ps;
+    e.out[s] = q;
+    dot += ps * q;
+  } else if constexpr (MODE == EPI_RESID) {
+    e.out[s] = e.r[s] - (t + e.lam * e.p[s]);
+  } else if constexpr (MODE == EPI_POST) {
+    const double e2 = e.p[s];
+    const double rs = e.r[s];
+    const double rho = rs - (t + e.lam * e2);
+    const double z = e2 + (e.omega * rho) / e.D[s];
+    e.out[s] = z;
+    dot += rs * z;
+  } else if constexpr (MODE == EPI_TRUE) {
+    const double res = e.r[s] - (t + e.lam * e.p[s]);
+    if (e.out) e.out[s] = res;
+    dot += res * res;
+  } else if constexpr (MODE == EPI_SCALE) {
+    e.out[s] = t * e.scale[s];
+  }
+}
+
+template <int MODE>
+constexpr bool has_dot() {
+  return MODE == EPI_APPLY_DOT || MODE == EPI_POST || MODE == EPI_TRUE;
+}
+
+// The epilogue's dot product leaves one partial per block (consumed by the
+// next solver kernel).
+template <int NT>
+__device__ inline void store_block_partial(double v, double* partials, int slot) {
+  __shared__ double red_p[NT / 64];
+  const double t = block_sum_n<NT>(v, red_p);
+  if (threadIdx.x == 0) partials[slot] = t;
+}
 }  // namespace rr

@@ -17,9 +17,9 @@ constexpr int kBlock = 256;          // threads per block for streaming kernels
 constexpr int kMergeItems = 8;       // merge-path items per thread
 constexpr int kMergeTile = kBlock * kMergeItems;
 
-// Device-resident Krylov state.  Reduction kernels finish their scalar in the
-// last block to arrive (integer ticket), so the host never reads a scalar
-// inside the iteration.
+// Device-resident Krylov state.  A scalar is written by block 0 of the kernel
+// that forms it and read by later kernels only, so the host never reads a
+// scalar inside the iteration.
 struct Scalars {
   double rz;        // <r, z> of the current iterate
   double pq;        // <p, A p>
@@ -32,10 +32,34 @@ struct Scalars {
   double errtol2;   // err_tol^2 ||x_ref||^2
   double true_rr;   // ||b - A x||^2 at exit
   double pad;
+  double rz_next;   // <r, z> of the newest residual, consumed by the next update
+  double pad3;
   int iter, done, status, limit;
   int fixed, use_err, pad0, pad1;
-  unsigned int ticket;
-  unsigned int pad2[15];
+  unsigned int pad2[16];
+};
+
+// Block partials of the solver's reductions.  A producer kernel stores one
+// value per block (plain stores); every block of the consuming kernel adds
+// them in the same order, so all blocks see the same scalar without atomics.
+constexpr int kMaxParts = 512;   // >= every producer grid
+struct Parts {
+  double* pq = nullptr;    // <p, Ap>            [n_red]
+  double* upd = nullptr;   // ||r||^2, err^2, <r,z> (Jacobi/CG)   [3 * n_vec]
+  double* rz = nullptr;    // <r, z> from the preconditioner      [n_red or n_vec]
+  double* init = nullptr;  // ||b||^2, ||x_ref||^2, <r,z>          [3 * n_vec]
+  double* tr = nullptr;    // ||b - Ax||^2                         [n_red]
+  int n_red = 0;           // blocks of the column reduction (CSC epilogue)
+  int n_vec = 0;           // blocks of the vector kernels
+};
+
+// What the kernel after the x/r update checks before doing its own work.
+struct StageArgs {
+  Scalars* sc;
+  const double* upd;       // update partials (3 * n)
+  int n;
+  double* history;
+  int kind;
 };
 
 // Epilogue arguments of the CSC (column-segment) reduction.
@@ -58,7 +82,7 @@ struct Epi {
   const double* scale;  // per-segment scale
   double* out;
   Scalars* sc;
-  double* partials;
+  double* partials;      // block partials of the epilogue's dot product
   double* history;
 };
 
@@ -69,6 +93,23 @@ struct MergePlan {
   int4* span = nullptr;    // device [nspan]: (segment, first block, last block, 0)
   double* head = nullptr;  // device [nblocks]
   double* tail = nullptr;  // device [nblocks]
+};
+
+// Sliced-ELL plan of a segmented gather-sum out_s = sum_{e in s} v[g_e]
+// (see sell.hip).  The gathered vector is cut into slices of W entries that
+// live in LDS.
+constexpr int kSliceRows = 16384;     // W: 128 KB of FP64 per slice in LDS
+constexpr int kSliceBlock = 1024;     // threads per sliced workgroup
+constexpr int kSliceWaves = kSliceBlock / 64;
+struct SellPlan {
+  int S = 0, gdim = 0, W = 0, R = 0, nblk = 0, ntask = 0, nslots = 0;
+  long long idx_bytes = 0;
+  uint16_t* idx = nullptr;    // packed local indices
+  int4* task = nullptr;       // [ntask]
+  int4* blk = nullptr;        // [nblk] (slice, first task, end task, 0)
+  int* lane_slot = nullptr;   // output slot of each lane of the lane tasks (-1: padding)
+  int* sbase = nullptr;       // [S+1] first slot of every segment
+  double* slots = nullptr;    // [nslots] per (segment, slice) sums
 };
 
 // Sparse matrix stored both ways.
@@ -82,7 +123,10 @@ struct Sparse {
   int* row_idx = nullptr;   // [nnz]
   double* cval = nullptr;   // [nnz] or null (CSC order)
   int csr_group = 16;       // lanes per row in the CSR kernel
-  MergePlan csc_plan;       // segments = columns
+  MergePlan csc_plan;       // segments = columns (merge-path form, valued X)
+  SellPlan sell_csr;        // u = X v   (0/1 X)
+  SellPlan sell_csc;        // t = X^T u (0/1 X)
+  int num_cu = 256;
 };
 
 struct LambdaSlot {
@@ -103,6 +147,7 @@ struct Work {
   double *c = nullptr, *yc = nullptr;   // [FC]
   double *partials = nullptr;     // reduction partials
   int npartials = 0;
+  Parts parts;
   Scalars* sc = nullptr;
   Scalars* sc_host = nullptr;     // pinned mirror
 };
@@ -163,30 +208,47 @@ rr_status build_merge_plan(MergePlan& mp, const int* d_seg_end, const int* d_seg
                            int nseg, int nnz, hipStream_t s);
 void free_merge_plan(MergePlan& mp);
 // u = X v (CSR).  done may be null.
-void launch_csr(const Sparse& X, const double* v, double* u, const int* done, hipStream_t s);
+void launch_csr(const Sparse& X, const double* v, double* u, const int* done, hipStream_t s,
+                const StageArgs* stage = nullptr);
 // Column-segment reduction t_s = sum_e v[idx[e]] (* val[e]) with epilogue `mode`.
-void launch_segsum(const MergePlan& mp, const int* seg_end, const int* idx, const double* val,
-                   const double* v, int mode, const Epi& e, const int* done, hipStream_t s);
-// X^T u with epilogue, using the CSC of X.
-void launch_csc(const Sparse& X, const double* u, int mode, const Epi& e, const int* done,
-                hipStream_t s);
+// Epilogues with a dot product leave block partials in e.partials; the
+// return value is their count (0 for the other modes).
+int launch_segsum(const MergePlan& mp, const int* seg_end, const int* idx, const double* val,
+                  const double* v, int mode, const Epi& e, const int* done, hipStream_t s);
+// X^T u with epilogue, using the CSC of X; returns the partial count.
+int launch_csc(const Sparse& X, const double* u, int mode, const Epi& e, const int* done,
+               hipStream_t s);
 rr_status build_csc(Sparse& X, hipStream_t s);
 rr_status renumber_features(Sparse& X, int* fperm, int* finv, hipStream_t s);
+rr_status build_sell_plans(Sparse& X, hipStream_t s);
+void free_sell(SellPlan& sp);
+int launch_sell(const SellPlan& sp, const double* v, int mode, const Epi& e, const int* done,
+                hipStream_t s, const StageArgs* stage = nullptr);
+int sell_reduce_grid(int S);
 rr_status validate_csr(const Sparse& X, hipStream_t s);
 
 // ---- vector kernels (blas1.hip) ---------------------------------------------
 enum PcgKind { PK_NONE = 0, PK_JACOBI = 1, PK_VCYCLE = 2, PK_ADDITIVE = 3 };
+int vec_grid(int F);   // blocks of the PCG vector kernels (<= kMaxParts)
 void launch_pcg_init(int F, const double* b, double* x, double* r, double* p, double* z,
                      double* e1, const double* D, const double* xref, double omega, int kind,
-                     Scalars* sc, double* partials, double* history, hipStream_t s);
+                     double* parts_init, hipStream_t s);
+void launch_finish_init(Scalars* sc, const double* parts_init, int n, double* history, int kind,
+                        hipStream_t s);
 void launch_pcg_update(int F, double* x, double* r, const double* p, const double* q,
                        double* z, double* e1, const double* D, const double* xref,
-                       double omega, int kind, Scalars* sc, double* partials, double* history,
-                       hipStream_t s);
-void launch_pupdate(int F, double* p, const double* z, Scalars* sc, hipStream_t s);
+                       double omega, int kind, Scalars* sc, const double* parts_pq, int n_pq,
+                       double* parts_upd, hipStream_t s);
+// p = z + beta p; beta from rz partials (first: beta = 0); with `stage` the
+// convergence check of the preceding update runs first
+void launch_pupdate(int F, double* p, const double* z, Scalars* sc, const double* parts_rz,
+                    int n_rz, int first, const StageArgs* stage, hipStream_t s);
+void launch_stage_update(const StageArgs& st, hipStream_t s);
+void launch_finish_true(Scalars* sc, const double* parts, int n, hipStream_t s);
 void launch_prolong(int F, const int* labels, const double* cscale, const double* yc,
                     const double* e1, double* out, const double* r, const double* D,
-                    double omega, int additive, Scalars* sc, double* partials, hipStream_t s);
+                    double omega, int additive, const Scalars* sc, double* parts_rz,
+                    hipStream_t s);
 void launch_fill(double* x, double v, long long n, hipStream_t s);
 // dst[i] = src[idx[i]]
 void launch_gather(double* dst, const double* src, const int* idx, int n, hipStream_t s);
@@ -195,10 +257,6 @@ void launch_colnorm_diag(int F, const double* colnorm, double lam, double* D, hi
 void launch_jacobi_apply(int F, const double* r, const double* D, double* z, hipStream_t s);
 void launch_omega_gersh(int F, const double* g, const double* colnorm, double lam,
                         double* out, double* partials, unsigned* ticket, hipStream_t s);
-void launch_axpby(long long n, double a, const double* x, double b, double* y,
-                  hipStream_t s);
-void launch_dot(long long n, const double* x, const double* y, double* out,
-                double* partials, unsigned* ticket, hipStream_t s);
 void launch_gemv(int n, const double* A, const double* x, double* y, const int* done,
                  hipStream_t s);
 

@@ -63,8 +63,15 @@ static void csr_dispatch(const Sparse& X, const double* v, double* u, const int*
     k_csr<G, false><<<grid, kBlock, 0, s>>>(X.row_ptr, X.col_idx, X.val, v, u, X.N, done);
 }
 
-void launch_csr(const Sparse& X, const double* v, double* u, const int* done,
-                hipStream_t s) {
+void launch_csr(const Sparse& X, const double* v, double* u, const int* done, hipStream_t s,
+                const StageArgs* stage) {
+  if (X.binary && X.N > 0) {
+    Epi e{};
+    e.out = u;
+    launch_sell(X.sell_csr, v, EPI_STORE, e, done, s, stage);
+    return;
+  }
+  if (stage) launch_stage_update(*stage, s);
   if (X.N == 0) return;
   switch (X.csr_group) {
     case 4: csr_dispatch<4>(X, v, u, done, s); break;
@@ -73,50 +80,6 @@ void launch_csr(const Sparse& X, const double* v, double* u, const int* done,
     case 32: csr_dispatch<32>(X, v, u, done, s); break;
     default: csr_dispatch<64>(X, v, u, done, s); break;
   }
-}
-
-// ---------------------------------------------------------------------------
-// Segment epilogues
-// ---------------------------------------------------------------------------
-template <int MODE>
-__device__ inline void seg_finish(int s, double t, const Epi& e, double& dot) {
-  if constexpr (MODE == EPI_STORE) {
-    e.out[s] = t;
-  } else if constexpr (MODE == EPI_APPLY) {
-    e.out[s] = t + e.lam * e.p[s];
-  } else if constexpr (MODE == EPI_APPLY_DOT) {
-    const double ps = e.p[s];
-    const double q = t + e.lam * ps;
-    e.out[s] = q;
-    dot += ps * q;
-  } else if constexpr (MODE == EPI_RESID) {
-    e.out[s] = e.r[s] - (t + e.lam * e.p[s]);
-  } else if constexpr (MODE == EPI_POST) {
-    const double e2 = e.p[s];
-    const double rs = e.r[s];
-    const double rho = rs - (t + e.lam * e2);
-    const double z = e2 + (e.omega * rho) / e.D[s];
-    e.out[s] = z;
-    dot += rs * z;
-  } else if constexpr (MODE == EPI_TRUE) {
-    const double res = e.r[s] - (t + e.lam * e.p[s]);
-    if (e.out) e.out[s] = res;
-    dot += res * res;
-  } else if constexpr (MODE == EPI_SCALE) {
-    e.out[s] = t * e.scale[s];
-  }
-}
-
-template <int MODE>
-constexpr bool has_dot() {
-  return MODE == EPI_APPLY_DOT || MODE == EPI_POST || MODE == EPI_TRUE;
-}
-
-template <int MODE>
-__device__ inline void dot_finish(const Epi& e, double tot) {
-  if constexpr (MODE == EPI_APPLY_DOT) finish_alpha(e.sc, tot);
-  if constexpr (MODE == EPI_POST) finish_beta(e.sc, tot);
-  if constexpr (MODE == EPI_TRUE) e.sc->true_rr = tot;
 }
 
 // ---------------------------------------------------------------------------
@@ -166,13 +129,41 @@ __global__ __launch_bounds__(kBlock) void k_segsum(
   const int nx = c1.x - x0, ny = c1.y - y0;
   const int total = nx + ny;
 
-  for (int i = tid; i <= nx; i += kBlock)
-    s_end[i] = (x0 + i < nseg) ? seg_end[x0 + i] - y0 : INT_MAX;
-  for (int i = tid; i < ny; i += kBlock) {
-    const int g = y0 + i;
-    double a = v[idx[g]];
-    if (!BIN) a *= val[g];
-    s_val[i] = a;
+  {
+    // issue all staging loads before the first LDS store
+    int te[kMergeItems + 1];
+    int ti[kMergeItems];
+#pragma unroll
+    for (int k = 0; k <= kMergeItems; ++k) {
+      const int i = tid + k * kBlock;
+      te[k] = (i <= nx && x0 + i < nseg) ? seg_end[x0 + i] - y0 : INT_MAX;
+    }
+#pragma unroll
+    for (int k = 0; k < kMergeItems; ++k) {
+      const int i = tid + k * kBlock;
+      ti[k] = (i < ny) ? idx[y0 + i] : 0;
+    }
+    double tv[kMergeItems];
+#pragma unroll
+    for (int k = 0; k < kMergeItems; ++k) {
+      const int i = tid + k * kBlock;
+      double a = 0.0;
+      if (i < ny) {
+        a = v[ti[k]];
+        if (!BIN) a *= val[y0 + i];
+      }
+      tv[k] = a;
+    }
+#pragma unroll
+    for (int k = 0; k <= kMergeItems; ++k) {
+      const int i = tid + k * kBlock;
+      if (i <= nx) s_end[i] = te[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kMergeItems; ++k) {
+      const int i = tid + k * kBlock;
+      if (i < ny) s_val[i] = tv[k];
+    }
   }
   __syncthreads();
 
@@ -245,7 +236,7 @@ __global__ __launch_bounds__(kBlock) void k_segsum(
   if (d < dend && dend == total) tail[b] = acc;
   if constexpr (has_dot<MODE>()) {
     double vv[1] = {dot};
-    write_partial<1>(vv, e.partials, b, nslots);
+    store_block_partial<kBlock>(vv[0], e.partials, b);
   }
 }
 
@@ -268,18 +259,21 @@ __global__ __launch_bounds__(kBlock) void k_segfix(const int4* __restrict__ span
     acc += head[sp.z];
     if (lane == 0) seg_finish<MODE>(sp.x, acc, e, dot);
   }
-  if constexpr (has_dot<MODE>()) {
-    double vv[1] = {dot}, tot[1];
-    if (grid_finish<1>(vv, e.partials, nmain, nmain + gridDim.x, &e.sc->ticket, tot)) {
-      if (threadIdx.x == 0) dot_finish<MODE>(e, tot[0]);
-    }
-  }
+  if constexpr (has_dot<MODE>()) store_block_partial<kBlock>(dot, e.partials, nmain + blockIdx.x);
+}
+
+// Collapse n block partials into partials[0] (one block, fixed order).
+__global__ __launch_bounds__(kBlock) void k_collapse(double* partials, int n, const int* done) {
+  if (is_done(done)) return;
+  __shared__ double red[kBlock / 64];
+  const double t = sum_parts<kBlock>(partials, n, red);
+  if (threadIdx.x == 0) partials[0] = t;
 }
 
 template <int MODE>
-static void segsum_mode(const MergePlan& mp, const int* seg_end, const int* idx,
-                        const double* val, const double* v, const Epi& e, const int* done,
-                        hipStream_t s) {
+static int segsum_mode(const MergePlan& mp, const int* seg_end, const int* idx,
+                       const double* val, const double* v, const Epi& e, const int* done,
+                       hipStream_t s) {
   const int nfix = std::max(1, cdiv(mp.nspan, kBlock / 64));
   const int nslots = mp.nblocks + nfix;
   if (val)
@@ -292,27 +286,33 @@ static void segsum_mode(const MergePlan& mp, const int* seg_end, const int* idx,
   if (mp.nspan > 0 || has_dot<MODE>())
     k_segfix<MODE><<<nfix, kBlock, 0, s>>>(mp.span, mp.nspan, mp.head, mp.tail, mp.nblocks, e,
                                            done);
+  if (!has_dot<MODE>()) return 0;
+  if (nslots <= kMaxParts) return nslots;
+  k_collapse<<<1, kBlock, 0, s>>>(e.partials, nslots, done);
+  return 1;
 }
 
-void launch_segsum(const MergePlan& mp, const int* seg_end, const int* idx, const double* val,
-                   const double* v, int mode, const Epi& e, const int* done, hipStream_t s) {
-  if (mp.nblocks == 0) return;
+int launch_csc(const Sparse& X, const double* u, int mode, const Epi& e, const int* done,
+               hipStream_t s) {
+  if (X.binary) return launch_sell(X.sell_csc, u, mode, e, done, s);
+  return launch_segsum(X.csc_plan, X.col_ptr + 1, X.row_idx, X.cval, u, mode, e, done, s);
+}
+
+int launch_segsum(const MergePlan& mp, const int* seg_end, const int* idx, const double* val,
+                  const double* v, int mode, const Epi& e, const int* done, hipStream_t s) {
+  if (mp.nblocks == 0) return 0;
   switch (mode) {
-    case EPI_STORE: segsum_mode<EPI_STORE>(mp, seg_end, idx, val, v, e, done, s); break;
-    case EPI_APPLY: segsum_mode<EPI_APPLY>(mp, seg_end, idx, val, v, e, done, s); break;
-    case EPI_APPLY_DOT: segsum_mode<EPI_APPLY_DOT>(mp, seg_end, idx, val, v, e, done, s); break;
-    case EPI_RESID: segsum_mode<EPI_RESID>(mp, seg_end, idx, val, v, e, done, s); break;
-    case EPI_POST: segsum_mode<EPI_POST>(mp, seg_end, idx, val, v, e, done, s); break;
-    case EPI_TRUE: segsum_mode<EPI_TRUE>(mp, seg_end, idx, val, v, e, done, s); break;
-    case EPI_SCALE: segsum_mode<EPI_SCALE>(mp, seg_end, idx, val, v, e, done, s); break;
+    case EPI_STORE: return segsum_mode<EPI_STORE>(mp, seg_end, idx, val, v, e, done, s);
+    case EPI_APPLY: return segsum_mode<EPI_APPLY>(mp, seg_end, idx, val, v, e, done, s);
+    case EPI_APPLY_DOT: return segsum_mode<EPI_APPLY_DOT>(mp, seg_end, idx, val, v, e, done, s);
+    case EPI_RESID: return segsum_mode<EPI_RESID>(mp, seg_end, idx, val, v, e, done, s);
+    case EPI_POST: return segsum_mode<EPI_POST>(mp, seg_end, idx, val, v, e, done, s);
+    case EPI_TRUE: return segsum_mode<EPI_TRUE>(mp, seg_end, idx, val, v, e, done, s);
+    case EPI_SCALE: return segsum_mode<EPI_SCALE>(mp, seg_end, idx, val, v, e, done, s);
   }
+  return 0;
 }
 
-void launch_csc(const Sparse& X, const double* u, int mode, const Epi& e, const int* done,
-                hipStream_t s) {
-  launch_segsum(X.csc_plan, X.col_ptr + 1, X.row_idx, X.binary ? nullptr : X.cval, u, mode, e,
-                done, s);
-}
 
 // ---------------------------------------------------------------------------
 // Plan construction (setup only)
@@ -564,7 +564,7 @@ rr_status build_csc(Sparse& X, hipStream_t s) {
   if (!X.binary) RR_HIP(hipMalloc(&X.cval, sizeof(double) * std::max(nnz, 1)));
   if (nnz == 0) {
     RR_HIP(hipMemsetAsync(X.col_ptr, 0, sizeof(int) * (X.F + 1), s));
-    return build_merge_plan(X.csc_plan, X.col_ptr + 1, X.col_ptr, X.F, 0, s);
+    return RR_OK;
   }
   int *row_of = nullptr, *pos = nullptr, *keys_out = nullptr, *pos_out = nullptr;
   RR_HIP(hipMalloc(&row_of, sizeof(int) * nnz));
@@ -590,6 +590,7 @@ rr_status build_csc(Sparse& X, hipStream_t s) {
   RR_HIP(hipFree(pos));
   RR_HIP(hipFree(keys_out));
   RR_HIP(hipFree(pos_out));
+  if (X.binary) return RR_OK;   // 0/1 matrices use the sliced-ELL plans
   return build_merge_plan(X.csc_plan, X.col_ptr + 1, X.col_ptr, X.F, nnz, s);
 }
 
