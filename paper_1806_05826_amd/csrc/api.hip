@@ -194,7 +194,7 @@ rr_status setup_impl(const rr_csr* Xin, const rr_setup_opts* o, hipStream_t s, r
   }
   // five partial regions (pq, upd, rz, init, tr), each large enough for the
   // widest producer grid
-  np = std::max(np, 3 * kMaxParts);
+  np = std::max(np, std::max(3 * kMaxParts, kMaxReduceBlocks + 1));
   w.npartials = np;
   RR_TRY(dalloc(&w.partials, 5 * (size_t)np));
   w.parts.pq = w.partials;

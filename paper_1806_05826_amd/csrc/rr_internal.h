@@ -42,7 +42,8 @@ struct Scalars {
 // Block partials of the solver's reductions.  A producer kernel stores one
 // value per block (plain stores); every block of the consuming kernel adds
 // them in the same order, so all blocks see the same scalar without atomics.
-constexpr int kMaxParts = 512;   // >= every producer grid
+constexpr int kMaxParts = 1024;         // partials a consumer block adds itself
+constexpr int kMaxReduceBlocks = 4096;  // grid cap of the SELL segment reduction
 struct Parts {
   double* pq = nullptr;    // <p, Ap>            [n_red]
   double* upd = nullptr;   // ||r||^2, err^2, <r,z> (Jacobi/CG)   [3 * n_vec]
@@ -102,14 +103,15 @@ constexpr int kSliceRows = 16384;     // W: 128 KB of FP64 per slice in LDS
 constexpr int kSliceBlock = 1024;     // threads per sliced workgroup
 constexpr int kSliceWaves = kSliceBlock / 64;
 struct SellPlan {
-  int S = 0, gdim = 0, W = 0, R = 0, nblk = 0, ntask = 0, nslots = 0;
+  int S = 0, gdim = 0, W = 0, R = 0, nblk = 0, ntask = 0, nslots = 0, nitems = 0, nout = 0;
   long long idx_bytes = 0;
-  uint16_t* idx = nullptr;    // packed local indices
+  uint16_t* idx = nullptr;    // packed local indexes (bit 15: last entry of a pair)
   int4* task = nullptr;       // [ntask]
-  int4* blk = nullptr;        // [nblk] (slice, first task, end task, 0)
-  int* lane_slot = nullptr;   // output slot of each lane of the lane tasks (-1: padding)
-  int* sbase = nullptr;       // [S+1] first slot of every segment
-  double* slots = nullptr;    // [nslots] per (segment, slice) sums
+  int* wrange = nullptr;      // [nblk * (kSliceWaves + 1)] task range of every wave
+  int* bslice = nullptr;      // [nblk] slice of every workgroup
+  int* pos = nullptr;         // [nitems] output position of every piece of a (segment, slice) pair
+  int* sbase = nullptr;       // [S+1] first piece of every segment
+  double* part = nullptr;     // [nout] partial sums
 };
 
 // Sparse matrix stored both ways.
@@ -225,6 +227,9 @@ void free_sell(SellPlan& sp);
 int launch_sell(const SellPlan& sp, const double* v, int mode, const Epi& e, const int* done,
                 hipStream_t s, const StageArgs* stage = nullptr);
 int sell_reduce_grid(int S);
+// More than kMaxParts block partials are first added into partials[0] by one
+// block; returns the count the consumer should add.
+int collapse_parts(double* partials, int n, const int* done, hipStream_t s);
 rr_status validate_csr(const Sparse& X, hipStream_t s);
 
 // ---- vector kernels (blas1.hip) ---------------------------------------------

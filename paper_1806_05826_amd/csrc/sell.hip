@@ -5,30 +5,37 @@
 // X for u = X v, columns of X for t = X^T u).  The gathered index range is cut
 // into slices of W entries whose part of v fits in LDS (W = 16384 FP64 =
 // 128 KB, plus one zero entry used for padding).  Every nonempty (segment,
-// slice) pair gets one output slot; slots of a segment are consecutive, in
-// slice order.  Pairs of one slice are processed by workgroups that first
-// copy the slice's part of v into LDS:
-//   * pairs with at most 512 entries are sorted by length and packed 64 to a
-//     wave task, lane l summing pair l; entry k of lane l is stored at
-//     base + 64 k + l (uint16, local index), padded with the zero entry to
-//     the task's longest pair, so every load instruction reads 128
-//     consecutive bytes;
-//   * longer pairs are one wave task each, stored contiguously and padded to
-//     a multiple of 512 entries; lane l reads 8 entries (16 bytes) per 512,
-//     then the wave adds its lanes in a fixed butterfly.
-// A reduction kernel then adds each segment's slots in slice order and
-// applies the epilogue.  Each sum's order is fixed by the plan, so results
-// are bitwise reproducible.
+// slice) pair produces one partial sum, or one per piece when it is cut into
+// pieces to keep lane streams short.  Workgroups own one slice each; they
+// copy its part of v into LDS and then work through wave tasks:
+//   * lane tasks: 64 lane streams of uint16 local indexes, entry k of lane l
+//     stored at base + 64 k + l (every load instruction reads 128
+//     consecutive bytes).  A lane stream holds one pair or, for short
+//     pairs, several pairs back to back; bit 15 marks the last entry of a
+//     pair, where the lane writes its running sum to the next of its output
+//     positions (base + 64 c + l) and restarts.  Streams are padded with the
+//     zero entry to the task's longest one;
+//   * wave tasks: one long pair, stored contiguously and padded to a
+//     multiple of 64 entries; lane l reads 8 entries (16 bytes) of every full
+//     512 and one entry (2 bytes) of every 64 of the rest, then the wave adds
+//     its lanes in a fixed butterfly.
+// Tasks are spread over the waves of a slice's workgroups by cost, and every
+// wave fetches its task descriptors in one load before the slice copy.  A
+// reduction kernel then adds each segment's partial sums in slice order
+// (reading them through a position index) and applies the epilogue.  Every
+// sum's order is fixed by the plan, so results are bitwise reproducible.
 #include <algorithm>
 #include <numeric>
+#include <queue>
 
 #include "rr_device.h"
 
 namespace rr {
 
-constexpr int kHeavyLen = 512;      // pairs longer than this get a whole wave
-constexpr int kLaneUnroll = 32;     // index loads in flight per lane (lane tasks)
+constexpr int kLaneUnroll = 16;     // index loads in flight per lane (lane tasks)
 constexpr int kWaveUnroll = 16;     // 16-byte loads in flight per lane (wave tasks)
+constexpr unsigned kEndFlag = 0x8000u;
+constexpr unsigned kLocalMask = 0x7fffu;
 
 template <int NTHREADS, int MAXN>
 __device__ inline void fill_slice(double* dst, const double* __restrict__ src, int n) {
@@ -46,14 +53,15 @@ __device__ inline void fill_slice(double* dst, const double* __restrict__ src, i
   }
 }
 
-// task.x: kind (0 lane task, 1 wave task); task.y: offset of its indices
-// (uint16 units for lane tasks, 16-byte units for wave tasks); task.z: length
-// (longest pair for lane tasks, 512-entry groups for wave tasks); task.w:
-// first lane-slot entry (lane tasks) or the output slot (wave tasks).
-__global__ __launch_bounds__(kSliceBlock) void k_sell(const int4* __restrict__ blk,
+// task.x: kind (0 lane task, 1 wave task); task.y: offset of its indexes
+// (uint16 units for lane tasks, 16-byte units for wave tasks); task.z:
+// length (longest lane stream; for wave tasks 16 x the 512-entry groups +
+// the 64-entry tail groups); task.w: first output position.  Wave w of workgroup b runs tasks [wrange[17 b + w],
+// wrange[17 b + w + 1]) of slice bslice[b].
+__global__ __launch_bounds__(kSliceBlock) void k_sell(const int* __restrict__ wrange,
+                                                     const int* __restrict__ bslice,
                                                      const int4* __restrict__ task,
                                                      const uint16_t* __restrict__ idx,
-                                                     const int* __restrict__ lane_slot,
                                                      const double* __restrict__ v, int gdim,
                                                      int W, double* __restrict__ out,
                                                      const int* done, StageArgs stage) {
@@ -64,40 +72,64 @@ __global__ __launch_bounds__(kSliceBlock) void k_sell(const int4* __restrict__ b
     if (stage_update<kSliceBlock>(stage, red_s, rz_unused)) return;
   }
   __shared__ double vs[kSliceRows + 1];
-  const int4 b = blk[blockIdx.x];
-  const int r = b.x;
-  const int g0 = r * W;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int t0 = wrange[blockIdx.x * (kSliceWaves + 1) + w];
+  const int t1 = wrange[blockIdx.x * (kSliceWaves + 1) + w + 1];
+  int4 my = make_int4(0, 0, 0, 0);
+  if (t0 + lane < t1) my = task[t0 + lane];
+  const int g0 = bslice[blockIdx.x] * W;
   fill_slice<kSliceBlock, kSliceRows + 1>(vs, v + g0, min(W, gdim - g0));
   __syncthreads();
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int t = b.y + w; t < b.z; t += kSliceWaves) {
-    const int4 tk = task[t];
-    if (tk.x == 0) {
-      const uint16_t* p = idx + tk.y + lane;
-      const int m = tk.z;
-      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int t = t0; t < t1; ++t) {
+    const int i = (t - t0) & 63;
+    if (i == 0 && t != t0) {
+      my = make_int4(0, 0, 0, 0);
+      if (t + lane < t1) my = task[t + lane];
+    }
+    const int kind = __builtin_amdgcn_readlane(my.x, i);
+    const int base = __builtin_amdgcn_readlane(my.y, i);
+    const int len = __builtin_amdgcn_readlane(my.z, i);
+    const int obase = __builtin_amdgcn_readlane(my.w, i);
+    if (kind == 0) {
+      const uint16_t* p = idx + base + lane;
+      double* o = out + obase + lane;
+      double acc = 0.0;
       int k = 0;
-      for (; k + kLaneUnroll <= m; k += kLaneUnroll) {
-        uint16_t q[kLaneUnroll];
+      for (; k + kLaneUnroll <= len; k += kLaneUnroll) {
+        unsigned q[kLaneUnroll];
 #pragma unroll
         for (int j = 0; j < kLaneUnroll; ++j) q[j] = p[(size_t)(k + j) * 64];
 #pragma unroll
-        for (int j = 0; j < kLaneUnroll; ++j) acc[j & 3] += vs[q[j]];
+        for (int j = 0; j < kLaneUnroll; ++j) {
+          acc += vs[q[j] & kLocalMask];
+          if (q[j] & kEndFlag) {
+            *o = acc;
+            o += 64;
+            acc = 0.0;
+          }
+        }
       }
-      if (k < m) {   // the rest, loads issued together
-        uint16_t q[kLaneUnroll];
-#pragma unroll
-        for (int j = 0; j < kLaneUnroll; ++j) q[j] = (k + j < m) ? p[(size_t)(k + j) * 64] : (uint16_t)0;
+      if (k < len) {   // the rest (len is the same in every lane): loads issued together
+        unsigned q[kLaneUnroll];
 #pragma unroll
         for (int j = 0; j < kLaneUnroll; ++j)
-          if (k + j < m) acc[j & 3] += vs[q[j]];
+          q[j] = (k + j < len) ? (unsigned)p[(size_t)(k + j) * 64] : (unsigned)W;
+#pragma unroll
+        for (int j = 0; j < kLaneUnroll; ++j) {
+          if (k + j < len) {
+            acc += vs[q[j] & kLocalMask];
+            if (q[j] & kEndFlag) {
+              *o = acc;
+              o += 64;
+              acc = 0.0;
+            }
+          }
+        }
       }
-      const double s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-      const int slot = lane_slot[tk.w + lane];
-      if (slot >= 0) out[slot] = s;
     } else {
-      const uint4* p = reinterpret_cast<const uint4*>(idx) + tk.y + lane;
-      const int ng = tk.z;
+      const uint4* p = reinterpret_cast<const uint4*>(idx) + base + lane;
+      const int ng = len >> 4, nt = len & 15;
       double acc[4] = {0.0, 0.0, 0.0, 0.0};
       int g = 0;
       for (; g + kWaveUnroll <= ng; g += kWaveUnroll) {
@@ -109,12 +141,12 @@ __global__ __launch_bounds__(kSliceBlock) void k_sell(const int4* __restrict__ b
           const unsigned wds[4] = {q[j].x, q[j].y, q[j].z, q[j].w};
 #pragma unroll
           for (int h = 0; h < 4; ++h) {
-            acc[(2 * h) & 3] += vs[wds[h] & 0xffffu];
-            acc[(2 * h + 1) & 3] += vs[wds[h] >> 16];
+            acc[(2 * h) & 3] += vs[wds[h] & kLocalMask];
+            acc[(2 * h + 1) & 3] += vs[(wds[h] >> 16) & kLocalMask];
           }
         }
       }
-      if (g < ng) {   // the rest, loads issued together
+      if (g < ng) {   // the rest (ng is the same in every lane): loads issued together
         uint4 q[kWaveUnroll];
 #pragma unroll
         for (int j = 0; j < kWaveUnroll; ++j)
@@ -125,23 +157,36 @@ __global__ __launch_bounds__(kSliceBlock) void k_sell(const int4* __restrict__ b
             const unsigned wds[4] = {q[j].x, q[j].y, q[j].z, q[j].w};
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
-              acc[(2 * h) & 3] += vs[wds[h] & 0xffffu];
-              acc[(2 * h + 1) & 3] += vs[wds[h] >> 16];
+              acc[(2 * h) & 3] += vs[wds[h] & kLocalMask];
+              acc[(2 * h + 1) & 3] += vs[(wds[h] >> 16) & kLocalMask];
             }
           }
         }
       }
+      if (nt > 0) {   // tail: up to 8 groups of 64 entries, one 2-byte load per lane each
+        const uint16_t* pt = idx + (size_t)base * 8 + (size_t)ng * 512 + lane;
+        unsigned q[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) q[j] = (j < nt) ? (unsigned)pt[j * 64] : (unsigned)W;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (j < nt) acc[j & 3] += vs[q[j] & kLocalMask];
+      }
       double s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-      if (lane == 0) out[tk.w] = s;
+      if (lane == 0) out[obase] = s;
     }
   }
 }
 
-// segment s: t = sum of its slots in slice order, then the epilogue
+// segment s: t = sum of its partial sums in slice order, then the epilogue.
+// One thread per segment; the positions and values of up to 16 pieces are
+// loaded together.
+constexpr int kReduceBatch = 16;
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_sell_reduce(const double* __restrict__ slots,
+__global__ __launch_bounds__(kBlock) void k_sell_reduce(const double* __restrict__ part,
+                                                       const int* __restrict__ pos,
                                                        const int* __restrict__ sbase, int S,
                                                        Epi e, const int* done) {
   if (is_done(done)) return;
@@ -149,12 +194,15 @@ __global__ __launch_bounds__(kBlock) void k_sell_reduce(const double* __restrict
   for (int s = blockIdx.x * kBlock + threadIdx.x; s < S; s += gridDim.x * kBlock) {
     const int a = sbase[s], z = sbase[s + 1];
     double t = 0.0;
-    for (int k0 = a; k0 < z; k0 += 8) {
-      double pv[8];
+    for (int k0 = a; k0 < z; k0 += kReduceBatch) {
+      int pi[kReduceBatch];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) pv[j] = (k0 + j < z) ? slots[k0 + j] : 0.0;
+      for (int j = 0; j < kReduceBatch; ++j) pi[j] = (k0 + j < z) ? pos[k0 + j] : -1;
+      double pv[kReduceBatch];
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
+      for (int j = 0; j < kReduceBatch; ++j) pv[j] = (pi[j] >= 0) ? part[pi[j]] : 0.0;
+#pragma unroll
+      for (int j = 0; j < kReduceBatch; ++j)
         if (k0 + j < z) t += pv[j];
     }
     seg_finish<MODE>(s, t, e, dot);
@@ -162,11 +210,12 @@ __global__ __launch_bounds__(kBlock) void k_sell_reduce(const double* __restrict
   if constexpr (has_dot<MODE>()) store_block_partial<kBlock>(dot, e.partials, blockIdx.x);
 }
 
-int sell_reduce_grid(int S) { return std::max(1, std::min(256, cdiv(S, kBlock))); }
+int sell_reduce_grid(int S) { return std::max(1, std::min(kMaxReduceBlocks, cdiv(S, kBlock))); }
 
 template <int MODE>
 static void sell_reduce_mode(const SellPlan& sp, const Epi& e, const int* done, hipStream_t s) {
-  k_sell_reduce<MODE><<<sell_reduce_grid(sp.S), kBlock, 0, s>>>(sp.slots, sp.sbase, sp.S, e, done);
+  k_sell_reduce<MODE><<<sell_reduce_grid(sp.S), kBlock, 0, s>>>(sp.part, sp.pos, sp.sbase, sp.S,
+                                                                e, done);
 }
 
 int launch_sell(const SellPlan& sp, const double* v, int mode, const Epi& e, const int* done,
@@ -174,8 +223,8 @@ int launch_sell(const SellPlan& sp, const double* v, int mode, const Epi& e, con
   StageArgs st{};
   if (stage) st = *stage;
   if (sp.nblk > 0)
-    k_sell<<<sp.nblk, kSliceBlock, 0, s>>>(sp.blk, sp.task, sp.idx, sp.lane_slot, v, sp.gdim,
-                                          sp.W, sp.slots, done, st);
+    k_sell<<<sp.nblk, kSliceBlock, 0, s>>>(sp.wrange, sp.bslice, sp.task, sp.idx, v, sp.gdim,
+                                          sp.W, sp.part, done, st);
   else if (stage)
     launch_stage_update(*stage, s);
   switch (mode) {
@@ -187,18 +236,71 @@ int launch_sell(const SellPlan& sp, const double* v, int mode, const Epi& e, con
     case EPI_TRUE: sell_reduce_mode<EPI_TRUE>(sp, e, done, s); break;
     case EPI_SCALE: sell_reduce_mode<EPI_SCALE>(sp, e, done, s); break;
   }
-  return sell_reduce_grid(sp.S);
+  if (mode != EPI_APPLY_DOT && mode != EPI_POST && mode != EPI_TRUE) return 0;
+  return collapse_parts(e.partials, sell_reduce_grid(sp.S), done, s);
 }
 
 void free_sell(SellPlan& sp) {
   if (sp.idx) (void)hipFree(sp.idx);
   if (sp.task) (void)hipFree(sp.task);
-  if (sp.blk) (void)hipFree(sp.blk);
-  if (sp.lane_slot) (void)hipFree(sp.lane_slot);
+  if (sp.wrange) (void)hipFree(sp.wrange);
+  if (sp.bslice) (void)hipFree(sp.bslice);
+  if (sp.pos) (void)hipFree(sp.pos);
   if (sp.sbase) (void)hipFree(sp.sbase);
-  if (sp.slots) (void)hipFree(sp.slots);
+  if (sp.part) (void)hipFree(sp.part);
   sp = SellPlan{};
 }
+
+namespace {
+
+struct Pair {
+  int start, len;
+};
+
+// Lane-task builder state: indexes, tasks, output positions.
+struct SellBuild {
+  std::vector<uint16_t> idx;
+  std::vector<int4> tasks;
+  std::vector<long long> tcost;
+  std::vector<int> tslice;
+  std::vector<int> pos;      // per pair: output position
+  int nout = 0;
+};
+
+// One lane task from up to 64 lane streams, each a list of pairs.
+void emit_lane_task(SellBuild& B, const std::vector<std::vector<int>>& lanes,
+                    const std::vector<Pair>& pairs, const std::vector<int>& gidx, int g0, int W,
+                    int r) {
+  int m = 0, J = 0;
+  for (const auto& ln : lanes) {
+    int len = 0;
+    for (int pi : ln) len += pairs[pi].len;
+    m = std::max(m, len);
+    J = std::max(J, (int)ln.size());
+  }
+  const int base = (int)B.idx.size();
+  B.idx.resize(B.idx.size() + (size_t)m * 64, (uint16_t)W);
+  const int obase = B.nout;
+  for (int l = 0; l < (int)lanes.size(); ++l) {
+    int k = 0, c = 0;
+    for (int pi : lanes[l]) {
+      const Pair& pa = pairs[pi];
+      for (int e = 0; e < pa.len; ++e, ++k) {
+        unsigned q = (unsigned)(gidx[pa.start + e] - g0);
+        if (e == pa.len - 1) q |= kEndFlag;
+        B.idx[base + (size_t)k * 64 + l] = (uint16_t)q;
+      }
+      B.pos[pi] = obase + c * 64 + l;
+      ++c;
+    }
+  }
+  B.nout += J * 64;
+  B.tasks.push_back(make_int4(0, base, m, obase));
+  B.tcost.push_back((long long)m + 4);
+  B.tslice.push_back(r);
+}
+
+}  // namespace
 
 // Host-side construction from a segment-major pattern (ptr[S+1], gidx sorted
 // inside every segment).  Setup only.
@@ -211,16 +313,12 @@ rr_status build_sell(SellPlan& sp, const std::vector<int>& ptr, const std::vecto
   sp.gdim = gdim;
   sp.W = W;
   sp.R = R;
-  // nonempty (segment, slice) pairs in (segment, slice) order = slot order
-  struct Pair {
-    int start, len;
-  };
+  // nonempty (segment, slice) pairs in (segment, slice) order
   std::vector<Pair> pairs;
   std::vector<int> pslice;
-  std::vector<int> sbase(S + 1, 0);
+  std::vector<int> pseg;
   pairs.reserve(ptr[S] / 2 + S);
   for (int q = 0; q < S; ++q) {
-    sbase[q] = (int)pairs.size();
     int e = ptr[q];
     const int z = ptr[q + 1];
     while (e < z) {
@@ -229,98 +327,205 @@ rr_status build_sell(SellPlan& sp, const std::vector<int>& ptr, const std::vecto
       while (f < z && gidx[f] / W == r) ++f;
       pairs.push_back({e, f - e});
       pslice.push_back(r);
+      pseg.push_back(q);
       e = f;
     }
   }
-  sbase[S] = (int)pairs.size();
   sp.nslots = (int)pairs.size();
-  // per slice: heavy pairs (own wave) and light pairs (64 per wave, by length)
-  std::vector<std::vector<int>> light(R), heavy(R);
-  for (int i = 0; i < (int)pairs.size(); ++i)
-    (pairs[i].len > kHeavyLen ? heavy : light)[pslice[i]].push_back(i);
-  std::vector<uint16_t> idx;
-  std::vector<int4> tasks;
-  std::vector<int> lane_slot;
-  std::vector<long long> tcost;
-  std::vector<int> tslice;
+  const long long nnz = ptr[S];
+  // lane streams of about `target` entries; pairs of (2, 4] target entries
+  // are cut in two halves, each with its own partial sum; longer pairs get a
+  // whole wave
+  const int target = (int)std::min<long long>(
+      64, std::max<long long>(8, nnz / std::max(1LL, (long long)num_cu * kSliceWaves * 64 * 2)));
+  const int cmax = 2 * target;
+  std::vector<Pair> items;
+  std::vector<int> islice;
+  std::vector<int> sbase(S + 1, 0);
+  items.reserve(pairs.size() + nnz / cmax + 1);
+  for (size_t i = 0, q = 0; q <= (size_t)S; ++q) {
+    sbase[q] = (int)items.size();
+    if (q == (size_t)S) break;
+    for (; i < pairs.size() && pseg[i] == (int)q; ++i) {
+      const Pair pa = pairs[i];
+      const int nc = (pa.len > cmax && pa.len <= 2 * cmax) ? 2 : 1;
+      for (int c = 0; c < nc; ++c) {
+        const int a = (int)((long long)pa.len * c / nc), b = (int)((long long)pa.len * (c + 1) / nc);
+        items.push_back({pa.start + a, b - a});
+        islice.push_back(pslice[i]);
+      }
+    }
+  }
+  pairs.swap(items);
+  pslice.swap(islice);
+  sp.nitems = (int)pairs.size();
+  std::vector<std::vector<int>> light(R), medium(R), heavy(R);
+  for (int i = 0; i < (int)pairs.size(); ++i) {
+    const int len = pairs[i].len;
+    (len > cmax ? heavy : (len > target ? medium : light))[pslice[i]].push_back(i);
+  }
+  SellBuild B;
+  B.pos.assign(pairs.size(), -1);
   const uint16_t pad = (uint16_t)W;   // index of the zero entry
+  auto by_len_desc = [&](int a, int b) {
+    return pairs[a].len != pairs[b].len ? pairs[a].len > pairs[b].len : a < b;
+  };
   for (int r = 0; r < R; ++r) {
     const int g0 = r * W;
     for (int i : heavy[r]) {
-      while (idx.size() % 8) idx.push_back(pad);
-      const int base16 = (int)(idx.size() / 8);
+      while (B.idx.size() % 8) B.idx.push_back(pad);
+      const int base16 = (int)(B.idx.size() / 8);
       const int len = pairs[i].len;
-      const int ng = cdiv(len, 512);
-      for (int k = 0; k < ng * 512; ++k)
-        idx.push_back(k < len ? (uint16_t)(gidx[pairs[i].start + k] - g0) : pad);
-      tasks.push_back(make_int4(1, base16, ng, i));
-      tcost.push_back((long long)ng * 8 + 8);
-      tslice.push_back(r);
+      const int ng = len / 512;                  // 512-entry groups (16-byte loads)
+      const int nt = cdiv(len - ng * 512, 64);   // 64-entry tail groups (2-byte loads)
+      for (int k = 0; k < ng * 512 + nt * 64; ++k)
+        B.idx.push_back(k < len ? (uint16_t)(gidx[pairs[i].start + k] - g0) : pad);
+      B.pos[i] = B.nout++;
+      B.tasks.push_back(make_int4(1, base16, ng * 16 + nt, B.pos[i]));
+      B.tcost.push_back((long long)ng * 8 + nt + 8);
+      B.tslice.push_back(r);
     }
+    // medium pairs: one per lane, 64 of similar length per task
+    std::vector<int>& md = medium[r];
+    std::sort(md.begin(), md.end(), by_len_desc);
+    for (size_t c = 0; c < md.size(); c += 64) {
+      std::vector<std::vector<int>> lanes;
+      for (size_t l = c; l < std::min(md.size(), c + 64); ++l) lanes.push_back({md[l]});
+      emit_lane_task(B, lanes, pairs, gidx, g0, W, r);
+    }
+    // short pairs: longest first onto the least loaded of nl lane streams
     std::vector<int>& lt = light[r];
-    std::stable_sort(lt.begin(), lt.end(),
-                     [&](int a, int b) { return pairs[a].len > pairs[b].len; });
-    for (size_t c = 0; c < lt.size(); c += 64) {
-      const int nv = (int)std::min<size_t>(64, lt.size() - c);
-      const int m = pairs[lt[c]].len;
-      const int base = (int)idx.size();
-      idx.resize(idx.size() + (size_t)m * 64, pad);
-      for (int l = 0; l < nv; ++l) {
-        const Pair& pa = pairs[lt[c + l]];
-        for (int k = 0; k < pa.len; ++k)
-          idx[base + (size_t)k * 64 + l] = (uint16_t)(gidx[pa.start + k] - g0);
+    if (!lt.empty()) {
+      std::sort(lt.begin(), lt.end(), by_len_desc);
+      long long tot = 0;
+      for (int i : lt) tot += pairs[i].len;
+      const int nl = 64 * std::max(1, cdiv(tot, 64LL * target));
+      std::vector<std::vector<int>> lanes(nl);
+      std::vector<int> load(nl, 0);
+      using Item = std::pair<int, int>;   // (load, lane)
+      std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
+      for (int l = 0; l < nl; ++l) heap.push({0, l});
+      for (int i : lt) {
+        const Item it = heap.top();
+        heap.pop();
+        lanes[it.second].push_back(i);
+        load[it.second] += pairs[i].len;
+        heap.push({load[it.second], it.second});
       }
-      const int ls = (int)lane_slot.size();
-      for (int l = 0; l < 64; ++l) lane_slot.push_back(l < nv ? lt[c + l] : -1);
-      tasks.push_back(make_int4(0, base, m, ls));
-      tcost.push_back((long long)m + 8);
-      tslice.push_back(r);
+      std::vector<int> order(nl);
+      std::iota(order.begin(), order.end(), 0);
+      std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return load[a] > load[b]; });
+      for (int c = 0; c < nl; c += 64) {
+        std::vector<std::vector<int>> tl;
+        for (int l = c; l < c + 64; ++l)
+          if (!lanes[order[l]].empty()) tl.push_back(lanes[order[l]]);
+        if (!tl.empty()) emit_lane_task(B, tl, pairs, gidx, g0, W, r);
+      }
     }
   }
-  // workgroups: tasks of one slice, balanced on cost, about num_cu in total
+  // workgroups: each slice gets a share of about num_cu workgroups by cost;
+  // its tasks go, heaviest first, to the least loaded wave of its workgroups
+  std::vector<long long> scost(R, 0);
   long long total = 0;
-  for (long long c : tcost) total += c;
-  std::vector<int4> blks;
-  std::vector<int4> tasks_sorted;
-  tasks_sorted.reserve(tasks.size());
-  const long long per_blk = std::max(1LL, total / std::max(1, num_cu));
-  size_t t = 0;
-  while (t < tasks.size()) {
-    const int r = tslice[t];
-    size_t u = t;
-    long long c = 0;
-    while (u < tasks.size() && tslice[u] == r && (c < per_blk || u == t)) c += tcost[u++];
-    // inside a workgroup, heaviest tasks first so the waves' round robin balances
-    std::vector<size_t> ord(u - t);
-    std::iota(ord.begin(), ord.end(), t);
-    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return tcost[a] > tcost[b]; });
-    const int first = (int)tasks_sorted.size();
-    for (size_t o : ord) tasks_sorted.push_back(tasks[o]);
-    blks.push_back(make_int4(r, first, (int)tasks_sorted.size(), 0));
-    t = u;
+  for (size_t t = 0; t < B.tasks.size(); ++t) {
+    scost[B.tslice[t]] += B.tcost[t];
+    total += B.tcost[t];
   }
-  sp.nblk = (int)blks.size();
+  std::vector<int> nb(R, 0);
+  {
+    std::vector<std::pair<double, int>> frac;
+    int used = 0;
+    for (int r = 0; r < R; ++r) {
+      if (scost[r] == 0) continue;
+      const double share = (double)scost[r] / (double)total * num_cu;
+      nb[r] = std::max(1, (int)share);
+      used += nb[r];
+      frac.push_back({share - (int)share, r});
+    }
+    std::sort(frac.begin(), frac.end(), [](auto& a, auto& b) { return a.first > b.first; });
+    for (size_t k = 0; k < frac.size() && used < num_cu; ++k, ++used) nb[frac[k].second]++;
+  }
+  std::vector<std::vector<int>> stasks(R);
+  for (size_t t = 0; t < B.tasks.size(); ++t) stasks[B.tslice[t]].push_back((int)t);
+  std::vector<int4> tasks_sorted;
+  std::vector<int> wrange, bslice;
+  tasks_sorted.reserve(B.tasks.size());
+  for (int r = 0; r < R; ++r) {
+    if (nb[r] == 0) continue;
+    const int nbin = nb[r] * kSliceWaves;
+    std::vector<int>& ts = stasks[r];
+    std::stable_sort(ts.begin(), ts.end(), [&](int a, int b) { return B.tcost[a] > B.tcost[b]; });
+    std::vector<std::vector<int>> bins(nbin);
+    using Item = std::pair<long long, int>;
+    std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
+    for (int k = 0; k < nbin; ++k) heap.push({0, k});
+    for (int t : ts) {
+      const Item it = heap.top();
+      heap.pop();
+      bins[it.second].push_back(t);
+      heap.push({it.first + B.tcost[t], it.second});
+    }
+    for (int b = 0; b < nb[r]; ++b) {
+      bslice.push_back(r);
+      for (int w = 0; w < kSliceWaves; ++w) {
+        wrange.push_back((int)tasks_sorted.size());
+        for (int t : bins[b * kSliceWaves + w]) tasks_sorted.push_back(B.tasks[t]);
+      }
+      wrange.push_back((int)tasks_sorted.size());
+    }
+  }
+  while (B.idx.size() % 8) B.idx.push_back(pad);
+  if (B.idx.empty()) B.idx.resize(8, pad);
+  // the kernel trusts the plan: check every access it will make
+  for (const int4& t : tasks_sorted) {
+    const size_t n16 = B.idx.size();
+    bool ok;
+    if (t.x == 0)
+      ok = t.z >= 1 && (size_t)t.y + (size_t)(t.z - 1) * 64 + 63 < n16 && t.w >= 0 &&
+           t.w + 63 < B.nout;
+    else
+      ok = t.z >= 1 && (t.z & 15) <= 8 &&
+           (size_t)t.y * 8 + (size_t)(t.z >> 4) * 512 + (size_t)(t.z & 15) * 64 <= n16 &&
+           t.w >= 0 && t.w < B.nout;
+    if (!ok) return fail(RR_ERR_DEVICE, "internal: SELL plan out of range");
+  }
+  for (uint16_t q : B.idx)
+    if ((q & kLocalMask) > (unsigned)W) return fail(RR_ERR_DEVICE, "internal: SELL index out of range");
+  for (const int4& t : tasks_sorted) {   // lane l's c-th output goes to t.w + 64 c + l
+    if (t.x != 0) continue;
+    for (int l = 0; l < 64; ++l) {
+      int c = 0;
+      for (int k = 0; k < t.z; ++k)
+        if (B.idx[t.y + (size_t)k * 64 + l] & kEndFlag) ++c;
+      if (c > 0 && t.w + 64 * (c - 1) + l >= B.nout)
+        return fail(RR_ERR_DEVICE, "internal: SELL output out of range");
+    }
+  }
+  for (int p : B.pos)
+    if (p < 0 || p >= B.nout) return fail(RR_ERR_DEVICE, "internal: SELL output position missing");
+  sp.nblk = (int)bslice.size();
   sp.ntask = (int)tasks_sorted.size();
-  while (idx.size() % 8) idx.push_back(pad);
-  if (idx.empty()) idx.resize(8, pad);
-  if (lane_slot.empty()) lane_slot.push_back(-1);
-  RR_HIP(hipMalloc(&sp.idx, sizeof(uint16_t) * idx.size()));
+  sp.nout = B.nout;
+  RR_HIP(hipMalloc(&sp.idx, sizeof(uint16_t) * B.idx.size()));
   RR_HIP(hipMalloc(&sp.task, sizeof(int4) * std::max<size_t>(1, tasks_sorted.size())));
-  RR_HIP(hipMalloc(&sp.blk, sizeof(int4) * std::max<size_t>(1, blks.size())));
-  RR_HIP(hipMalloc(&sp.lane_slot, sizeof(int) * lane_slot.size()));
+  RR_HIP(hipMalloc(&sp.wrange, sizeof(int) * std::max<size_t>(1, wrange.size())));
+  RR_HIP(hipMalloc(&sp.bslice, sizeof(int) * std::max<size_t>(1, bslice.size())));
+  RR_HIP(hipMalloc(&sp.pos, sizeof(int) * std::max<size_t>(1, B.pos.size())));
   RR_HIP(hipMalloc(&sp.sbase, sizeof(int) * sbase.size()));
-  RR_HIP(hipMalloc(&sp.slots, sizeof(double) * std::max(1, sp.nslots)));
-  RR_HIP(hipMemcpyAsync(sp.idx, idx.data(), sizeof(uint16_t) * idx.size(), hipMemcpyHostToDevice, s));
+  RR_HIP(hipMalloc(&sp.part, sizeof(double) * std::max(1, sp.nout)));
+  RR_HIP(hipMemcpyAsync(sp.idx, B.idx.data(), sizeof(uint16_t) * B.idx.size(), hipMemcpyHostToDevice, s));
   if (!tasks_sorted.empty())
     RR_HIP(hipMemcpyAsync(sp.task, tasks_sorted.data(), sizeof(int4) * tasks_sorted.size(),
                           hipMemcpyHostToDevice, s));
-  if (!blks.empty())
-    RR_HIP(hipMemcpyAsync(sp.blk, blks.data(), sizeof(int4) * blks.size(), hipMemcpyHostToDevice, s));
-  RR_HIP(hipMemcpyAsync(sp.lane_slot, lane_slot.data(), sizeof(int) * lane_slot.size(),
-                        hipMemcpyHostToDevice, s));
+  if (!wrange.empty())
+    RR_HIP(hipMemcpyAsync(sp.wrange, wrange.data(), sizeof(int) * wrange.size(), hipMemcpyHostToDevice, s));
+  if (!bslice.empty())
+    RR_HIP(hipMemcpyAsync(sp.bslice, bslice.data(), sizeof(int) * bslice.size(), hipMemcpyHostToDevice, s));
+  if (!B.pos.empty())
+    RR_HIP(hipMemcpyAsync(sp.pos, B.pos.data(), sizeof(int) * B.pos.size(), hipMemcpyHostToDevice, s));
   RR_HIP(hipMemcpyAsync(sp.sbase, sbase.data(), sizeof(int) * sbase.size(), hipMemcpyHostToDevice, s));
   RR_HIP(hipStreamSynchronize(s));
-  sp.idx_bytes = (long long)idx.size() * 2;
+  sp.idx_bytes = (long long)B.idx.size() * 2;
   return RR_OK;
 }
 

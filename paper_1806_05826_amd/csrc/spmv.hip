@@ -287,8 +287,12 @@ static int segsum_mode(const MergePlan& mp, const int* seg_end, const int* idx,
     k_segfix<MODE><<<nfix, kBlock, 0, s>>>(mp.span, mp.nspan, mp.head, mp.tail, mp.nblocks, e,
                                            done);
   if (!has_dot<MODE>()) return 0;
-  if (nslots <= kMaxParts) return nslots;
-  k_collapse<<<1, kBlock, 0, s>>>(e.partials, nslots, done);
+  return collapse_parts(e.partials, nslots, done, s);
+}
+
+int collapse_parts(double* partials, int n, const int* done, hipStream_t s) {
+  if (n <= kMaxParts) return n;
+  k_collapse<<<1, kBlock, 0, s>>>(partials, n, done);
   return 1;
 }
 
