@@ -37,20 +37,25 @@ constexpr int kWaveUnroll = 16;     // 16-byte loads in flight per lane (wave ta
 constexpr unsigned kEndFlag = 0x8000u;
 constexpr unsigned kLocalMask = 0x7fffu;
 
-template <int NTHREADS, int MAXN>
+// dst[0, W] = src[0, n) followed by zeros (n <= W = kSliceRows), with direct
+// global-to-LDS loads: at step k wave w moves the 128 entries starting at
+// (16 k + w) 128, 16 bytes per lane; the entries past the last whole pair
+// below n and the zero tail are written one by one.  The caller waits for
+// the loads (s_waitcnt) and synchronises the workgroup.
+static_assert(kSliceRows % (kSliceWaves * 128) == 0, "slice copy covers whole 1 KB rows");
 __device__ inline void fill_slice(double* dst, const double* __restrict__ src, int n) {
-  constexpr int PER = (MAXN + NTHREADS - 1) / NTHREADS;
-  double t[PER];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nfull = n & ~1;
 #pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    const int i = threadIdx.x + k * NTHREADS;
-    t[k] = (i < n) ? src[i] : 0.0;
+  for (int k = 0; k < kSliceRows / (kSliceWaves * 128); ++k) {
+    const int e0 = (k * kSliceWaves + w) * 128;
+    if (e0 + 2 * lane < nfull)
+      __builtin_amdgcn_global_load_lds(
+          (const __attribute__((address_space(1))) void*)(src + e0 + 2 * lane),
+          (__attribute__((address_space(3))) void*)(dst + e0), 16, 0, 0);
   }
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    const int i = threadIdx.x + k * NTHREADS;
-    if (i < MAXN) dst[i] = t[k];
-  }
+  for (int i = nfull + (int)threadIdx.x; i <= kSliceRows; i += kSliceBlock)
+    dst[i] = (i < n) ? src[i] : 0.0;
 }
 
 // task.x: kind (0 lane task, 1 wave task); task.y: offset of its indexes
@@ -79,7 +84,8 @@ __global__ __launch_bounds__(kSliceBlock) void k_sell(const int* __restrict__ wr
   int4 my = make_int4(0, 0, 0, 0);
   if (t0 + lane < t1) my = task[t0 + lane];
   const int g0 = bslice[blockIdx.x] * W;
-  fill_slice<kSliceBlock, kSliceRows + 1>(vs, v + g0, min(W, gdim - g0));
+  fill_slice(vs, v + g0, min(W, gdim - g0));
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   for (int t = t0; t < t1; ++t) {
     const int i = (t - t0) & 63;
