@@ -24,15 +24,46 @@ METRIC = "time-to-1e-10 rel. error (s) + SpMV HBM GB/s; batched/BF16/learned vs 
 HBM_PEAK_GBS = 8000.0
 
 
-def csc_bytes(N, F, nnz, vec_streams):
-    """Algorithmic bytes of one CSC pass t = X^T u with an epilogue touching
-    `vec_streams` F-vectors: row indices, column pointers, u read once."""
-    return 4 * nnz + 4 * (F + 1) + 8 * N + 8 * F * vec_streams
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sell_columns_binary_200kx100k_traffic.md")
+SELL_SOURCE = os.path.join(ROOT, "paper_1806_05826_amd", "csrc", "sell.hip")
 
 
-def csr_bytes(N, F, nnz):
-    """One CSR pass u = X v: column indices, row pointers, v read once, u written."""
-    return 4 * nnz + 4 * (N + 1) + 8 * F + 8 * N
+def column_gather_bytes(N, F, nnz):
+    """Algorithmic bytes of the column-pass gather t = X^T u (0/1 X): the CSC
+    pattern (4-byte row indexes, column pointers), u read once, t written."""
+    return 4 * nnz + 4 * (F + 1) + 8 * N + 8 * F
+
+
+def apply_bytes(N, F, nnz):
+    """One operator application q = X^T (X p) + lambda p with the pattern
+    stored both ways: both index arrays and pointer arrays, p read twice, u
+    written and read, q written."""
+    return 8 * nnz + 4 * (N + 1) + 4 * (F + 1) + 8 * F * 2 + 16 * N + 8 * F
+
+
+def measured_traffic():
+    """HBM bytes per launch of the column gather kernel from the committed
+    counter summary, or None when it is missing or was taken on a different
+    version of the kernel source."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    try:
+        src_hash = hashlib.sha256(open(SELL_SOURCE, "rb").read()).hexdigest()
+        if fields.get("sell.hip sha256") != src_hash:
+            return None
+        fetch = float(fields["FETCH_SIZE KiB per dispatch"]) * float(fields["FETCH_SIZE scale"])
+        write = float(fields["WRITE_SIZE KiB per dispatch"]) * float(fields["WRITE_SIZE scale"])
+    except (KeyError, ValueError, OSError):
+        return None
+    return (fetch + write) * 1024.0
 
 
 def cpu_baseline(X, y, lam, labels, fc, step_iters, budget_s=15.0):
@@ -70,6 +101,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--k", type=int, default=1000)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with a plain 256 MiB device copy (scale for memory counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -115,7 +148,8 @@ def main():
         out = {}
         for lam in lams:
             st, inf = rr.rr_solve(R.h, lam, y, w, fixed_iters=calib[lam]["iters"],
-                                  precond="vcycle", profile=profile, chunk=16, raise_on=(1, 2, 6))
+                                  precond="vcycle", profile=2 if profile else 0, chunk=16,
+                                  raise_on=(1, 2, 6))
             out[lam] = inf
         return out
 
@@ -133,10 +167,12 @@ def main():
     torch.cuda.synchronize()
     csc_ms = np.mean([prof[l]["csc_avg_ms"] for l in lams])
     csr_ms = np.mean([prof[l]["csr_avg_ms"] for l in lams])
-    b_csc = csc_bytes(N, F, nnz, 3)   # epilogues touch 2, 3 and 4 F-vectors in equal numbers
-    b_csr = csr_bytes(N, F, nnz)
-    gbs_csc = b_csc / (csc_ms * 1e-3) / 1e9
-    gbs_op = (b_csc + b_csr) / ((csc_ms + csr_ms) * 1e-3) / 1e9
+    gcsc_ms = np.mean([prof[l]["csc_gather_avg_ms"] for l in lams])
+    gcsr_ms = np.mean([prof[l]["csr_gather_avg_ms"] for l in lams])
+    b_gather = column_gather_bytes(N, F, nnz)
+    gbs_gather = b_gather / (gcsc_ms * 1e-3) / 1e9
+    b_apply = apply_bytes(N, F, nnz)
+    gbs_op = b_apply / ((csc_ms + csr_ms) * 1e-3) / 1e9
 
     # other forms for comparison (untimed calibration, one timed solve each)
     compare = {}
@@ -188,17 +224,22 @@ def main():
         "setup_ms": sinfo["setup_ms"],
         "kmeans_ms": sinfo["kmeans_ms"],
         "kmeans_passes": sinfo["kmeans_iters"],
-        "operator_gbs": gbs_op,
-        "csr_avg_ms": csr_ms,
-        "csc_avg_ms": csc_ms,
+        "operator": {"apply_bytes": b_apply, "apply_ms": csr_ms + csc_ms, "apply_gbs": gbs_op,
+                     "row_pass_ms": csr_ms, "row_gather_ms": gcsr_ms,
+                     "column_pass_ms": csc_ms, "column_gather_ms": gcsc_ms},
         "compare_lambda1": compare,
-        "roofline": {"bound": "hbm", "achieved": gbs_csc, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs_csc / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "CSC pass t = X^T u + epilogue (merge-path main + fix-up)",
-                     "bytes_per_launch": b_csc},
+        "roofline": {"bound": "hbm", "achieved": gbs_gather, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs_gather / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "kernel": "rr::k_sell<1> (column-pass gather of t = X^T u through LDS slices)",
+                     "bytes_per_launch": b_gather, "ms_per_launch": gcsc_ms},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+    if args.calibrate_copy:
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

@@ -145,7 +145,9 @@ typedef struct {
   double err_tol;
   double* residual_history;/* optional device double[limit+1]: ||r_k||/||b||    */
   int32_t chunk;           /* iterations queued between host checks; 0 -> 8      */
-  int32_t profile;         /* 1: time every operator kernel with HIP events      */
+  int32_t profile;         /* 1: time every operator pass with HIP events; 2: also
+                              time 20 back-to-back launches of each sliced gather
+                              kernel on the final vectors (0/1 X)                */
 } rr_solve_opts;
 
 typedef struct {
@@ -160,9 +162,14 @@ typedef struct {
   double omega;            /* smoother weight used                               */
   double ms;               /* wall time of the call                              */
   double coarse_ms;        /* of which the per-lambda coarse factorization       */
-  double csr_avg_ms;       /* profile: mean CSR kernel time (u = X v)            */
-  double csc_avg_ms;       /* profile: mean CSC kernel time (t = X^T u + epilogue)*/
+  double csr_avg_ms;       /* profile: mean time of a row pass u = X v           */
+  double csc_avg_ms;       /* profile: mean time of a column pass t = X^T u with
+                              its epilogue                                       */
   int32_t csr_launches, csc_launches;
+  double csr_gather_avg_ms;/* profile 1: of csr_avg_ms, the sliced gather kernel
+                              (0/1 X; the whole pass for valued X); profile 2:
+                              its back-to-back launch time                       */
+  double csc_gather_avg_ms;/* profile: the same for the column pass              */
 } rr_solve_info;
 
 /*

@@ -62,7 +62,8 @@ class rr_solve_info(C.Structure):
                 ("err", C.c_double), ("omega", C.c_double), ("ms", C.c_double),
                 ("coarse_ms", C.c_double), ("csr_avg_ms", C.c_double),
                 ("csc_avg_ms", C.c_double), ("csr_launches", C.c_int32),
-                ("csc_launches", C.c_int32)]
+                ("csc_launches", C.c_int32), ("csr_gather_avg_ms", C.c_double),
+                ("csc_gather_avg_ms", C.c_double)]
 
 
 _P = C.c_void_p
@@ -175,7 +176,7 @@ def rr_solve(h, lam, rhs, w, tol=0.0, max_iter=0, fixed_iters=0, precond="vcycle
     o = rr_solve_opts(float(tol), int(max_iter), int(fixed_iters),
                       PRECOND[precond] if isinstance(precond, str) else int(precond),
                       1 if rhs_is_b else 0, float(omega), _ptr(x_ref), float(err_tol),
-                      _ptr(residual_history), int(chunk), 1 if profile else 0)
+                      _ptr(residual_history), int(chunk), int(profile))
     info = rr_solve_info()
     st = _lib.rr_solve(C.c_void_p(h), float(lam), _ptr(rhs), _ptr(w), C.byref(o), C.byref(info),
                        _stream(stream))

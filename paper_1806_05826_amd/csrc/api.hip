@@ -263,12 +263,13 @@ rr_status get_slot(rr_handle* h, double lam, LambdaSlot** out, double* ms, hipSt
 
 struct Prof {
   bool on = false;
-  std::vector<std::pair<int, int>> csr, csc;   // event-pair index, iteration tag
+  std::vector<std::pair<int, int>> csr, csc;   // event-triple index, iteration tag
   int used = 0;
 };
 
+// Three events per timed pass: start, after the gather kernel, end.
 rr_status prof_pair(rr_handle* h, Prof& pf, int* idx) {
-  const int need = 2 * (pf.used + 1);
+  const int need = 3 * (pf.used + 1);
   while ((int)h->ev_pool.size() < need) {
     hipEvent_t e;
     RR_HIP(hipEventCreate(&e));
@@ -288,9 +289,9 @@ rr_status op_csr(rr_handle* h, Prof& pf, int tag, const double* v, hipStream_t s
   }
   int i;
   RR_TRY(prof_pair(h, pf, &i));
-  RR_HIP(hipEventRecord(h->ev_pool[2 * i], s));
-  launch_csr(h->X, v, h->w.u, done, s, stage);
-  RR_HIP(hipEventRecord(h->ev_pool[2 * i + 1], s));
+  RR_HIP(hipEventRecord(h->ev_pool[3 * i], s));
+  launch_csr(h->X, v, h->w.u, done, s, stage, h->ev_pool[3 * i + 1]);
+  RR_HIP(hipEventRecord(h->ev_pool[3 * i + 2], s));
   pf.csr.push_back({i, tag});
   return RR_OK;
 }
@@ -306,10 +307,10 @@ rr_status op_csc(rr_handle* h, Prof& pf, int tag, int mode, const Epi& e, hipStr
   }
   int i;
   RR_TRY(prof_pair(h, pf, &i));
-  RR_HIP(hipEventRecord(h->ev_pool[2 * i], s));
-  const int n = launch_csc(h->X, h->w.u, mode, e, done, s);
+  RR_HIP(hipEventRecord(h->ev_pool[3 * i], s));
+  const int n = launch_csc(h->X, h->w.u, mode, e, done, s, h->ev_pool[3 * i + 1]);
   if (nparts) *nparts = n;
-  RR_HIP(hipEventRecord(h->ev_pool[2 * i + 1], s));
+  RR_HIP(hipEventRecord(h->ev_pool[3 * i + 2], s));
   pf.csc.push_back({i, tag});
   return RR_OK;
 }
@@ -485,24 +486,46 @@ rr_status solve_impl(rr_handle* h, double lam, const double* rhs, double* wout,
   inf.coarse_ms = coarse_ms;
   if (pf.on) {
     // count only launches that ran: iteration tags below the final count
-    auto acc = [&](const std::vector<std::pair<int, int>>& v, double* avg, int* n) {
-      double tot = 0.0;
+    auto acc = [&](const std::vector<std::pair<int, int>>& v, double* avg, double* gavg, int* n) {
+      double tot = 0.0, gtot = 0.0;
       int cnt = 0;
       for (auto& pr : v) {
         const int tag = pr.second;
         const bool ran = (tag < 0) || (tag < 100000000 ? tag < hs.iter : tag - 100000000 + 1 < hs.iter);
         if (!ran) continue;
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, h->ev_pool[2 * pr.first], h->ev_pool[2 * pr.first + 1]) == hipSuccess) {
+        float ms = 0.f, gms = 0.f;
+        const hipEvent_t* ev = &h->ev_pool[3 * pr.first];
+        if (hipEventElapsedTime(&ms, ev[0], ev[2]) == hipSuccess &&
+            hipEventElapsedTime(&gms, ev[0], ev[1]) == hipSuccess) {
           tot += ms;
+          gtot += gms;
           ++cnt;
         }
       }
       *avg = cnt ? tot / cnt : 0.0;
+      *gavg = cnt ? gtot / cnt : 0.0;
       *n = cnt;
     };
-    acc(pf.csr, &inf.csr_avg_ms, &inf.csr_launches);
-    acc(pf.csc, &inf.csc_avg_ms, &inf.csc_launches);
+    acc(pf.csr, &inf.csr_avg_ms, &inf.csr_gather_avg_ms, &inf.csr_launches);
+    acc(pf.csc, &inf.csc_avg_ms, &inf.csc_gather_avg_ms, &inf.csc_launches);
+    if (op.profile == 2 && h->X.binary) {
+      // back-to-back launches of each gather kernel on the final x and u = X x
+      constexpr int kReps = 20;
+      int ti = 0;
+      RR_TRY(prof_pair(h, pf, &ti));
+      const hipEvent_t* ev = &h->ev_pool[3 * ti];
+      float ms = 0.f;
+      RR_HIP(hipEventRecord(ev[0], s));
+      for (int i = 0; i < kReps; ++i) launch_sell_gather(h->X.sell_csr, w.x, s);
+      RR_HIP(hipEventRecord(ev[1], s));
+      for (int i = 0; i < kReps; ++i) launch_sell_gather(h->X.sell_csc, w.u, s);
+      RR_HIP(hipEventRecord(ev[2], s));
+      RR_HIP(hipEventSynchronize(ev[2]));
+      RR_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+      inf.csr_gather_avg_ms = ms / kReps;
+      RR_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));
+      inf.csc_gather_avg_ms = ms / kReps;
+    }
   }
   inf.ms = now_ms() - t0;
   if (info) *info = inf;

@@ -104,6 +104,7 @@ constexpr int kSliceBlock = 1024;     // threads per sliced workgroup
 constexpr int kSliceWaves = kSliceBlock / 64;
 struct SellPlan {
   int S = 0, gdim = 0, W = 0, R = 0, nblk = 0, ntask = 0, nslots = 0, nitems = 0, nout = 0;
+  int pass = 0;               // 0: rows of X (u = X v), 1: columns (t = X^T u)
   long long idx_bytes = 0;
   uint16_t* idx = nullptr;    // packed local indexes (bit 15: last entry of a pair)
   int4* task = nullptr;       // [ntask]
@@ -210,8 +211,10 @@ rr_status build_merge_plan(MergePlan& mp, const int* d_seg_end, const int* d_seg
                            int nseg, int nnz, hipStream_t s);
 void free_merge_plan(MergePlan& mp);
 // u = X v (CSR).  done may be null.
+// With `mid`, an event is recorded after the gather kernel of a sliced pass
+// (before its segment reduction); elsewhere after the whole pass.
 void launch_csr(const Sparse& X, const double* v, double* u, const int* done, hipStream_t s,
-                const StageArgs* stage = nullptr);
+                const StageArgs* stage = nullptr, hipEvent_t mid = nullptr);
 // Column-segment reduction t_s = sum_e v[idx[e]] (* val[e]) with epilogue `mode`.
 // Epilogues with a dot product leave block partials in e.partials; the
 // return value is their count (0 for the other modes).
@@ -219,14 +222,16 @@ int launch_segsum(const MergePlan& mp, const int* seg_end, const int* idx, const
                   const double* v, int mode, const Epi& e, const int* done, hipStream_t s);
 // X^T u with epilogue, using the CSC of X; returns the partial count.
 int launch_csc(const Sparse& X, const double* u, int mode, const Epi& e, const int* done,
-               hipStream_t s);
+               hipStream_t s, hipEvent_t mid = nullptr);
 rr_status build_csc(Sparse& X, hipStream_t s);
 rr_status renumber_features(Sparse& X, int* fperm, int* finv, hipStream_t s);
 rr_status build_sell_plans(Sparse& X, hipStream_t s);
 void free_sell(SellPlan& sp);
 int launch_sell(const SellPlan& sp, const double* v, int mode, const Epi& e, const int* done,
-                hipStream_t s, const StageArgs* stage = nullptr);
+                hipStream_t s, const StageArgs* stage = nullptr, hipEvent_t mid = nullptr);
 int sell_reduce_grid(int S);
+// The gather kernel alone (partial sums only; no reduction, no epilogue).
+void launch_sell_gather(const SellPlan& sp, const double* v, hipStream_t s);
 // More than kMaxParts block partials are first added into partials[0] by one
 // block; returns the count the consumer should add.
 int collapse_parts(double* partials, int n, const int* done, hipStream_t s);

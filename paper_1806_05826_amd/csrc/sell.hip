@@ -63,6 +63,9 @@ __device__ inline void fill_slice(double* dst, const double* __restrict__ src, i
 // length (longest lane stream; for wave tasks 16 x the 512-entry groups +
 // the 64-entry tail groups); task.w: first output position.  Wave w of workgroup b runs tasks [wrange[17 b + w],
 // wrange[17 b + w + 1]) of slice bslice[b].
+// PASS only names the instantiation (0: rows of X, 1: columns of X), so a
+// profiler reports the two operator passes apart.
+template <int PASS>
 __global__ __launch_bounds__(kSliceBlock) void k_sell(const int* __restrict__ wrange,
                                                      const int* __restrict__ bslice,
                                                      const int4* __restrict__ task,
@@ -225,14 +228,20 @@ static void sell_reduce_mode(const SellPlan& sp, const Epi& e, const int* done, 
 }
 
 int launch_sell(const SellPlan& sp, const double* v, int mode, const Epi& e, const int* done,
-                hipStream_t s, const StageArgs* stage) {
+                hipStream_t s, const StageArgs* stage, hipEvent_t mid) {
   StageArgs st{};
   if (stage) st = *stage;
-  if (sp.nblk > 0)
-    k_sell<<<sp.nblk, kSliceBlock, 0, s>>>(sp.wrange, sp.bslice, sp.task, sp.idx, v, sp.gdim,
-                                          sp.W, sp.part, done, st);
-  else if (stage)
+  if (sp.nblk > 0) {
+    if (sp.pass == 0)
+      k_sell<0><<<sp.nblk, kSliceBlock, 0, s>>>(sp.wrange, sp.bslice, sp.task, sp.idx, v, sp.gdim,
+                                               sp.W, sp.part, done, st);
+    else
+      k_sell<1><<<sp.nblk, kSliceBlock, 0, s>>>(sp.wrange, sp.bslice, sp.task, sp.idx, v, sp.gdim,
+                                               sp.W, sp.part, done, st);
+  } else if (stage) {
     launch_stage_update(*stage, s);
+  }
+  if (mid) (void)hipEventRecord(mid, s);
   switch (mode) {
     case EPI_STORE: sell_reduce_mode<EPI_STORE>(sp, e, done, s); break;
     case EPI_APPLY: sell_reduce_mode<EPI_APPLY>(sp, e, done, s); break;
@@ -244,6 +253,17 @@ int launch_sell(const SellPlan& sp, const double* v, int mode, const Epi& e, con
   }
   if (mode != EPI_APPLY_DOT && mode != EPI_POST && mode != EPI_TRUE) return 0;
   return collapse_parts(e.partials, sell_reduce_grid(sp.S), done, s);
+}
+
+void launch_sell_gather(const SellPlan& sp, const double* v, hipStream_t s) {
+  if (sp.nblk == 0) return;
+  const StageArgs st{};
+  if (sp.pass == 0)
+    k_sell<0><<<sp.nblk, kSliceBlock, 0, s>>>(sp.wrange, sp.bslice, sp.task, sp.idx, v, sp.gdim,
+                                             sp.W, sp.part, nullptr, st);
+  else
+    k_sell<1><<<sp.nblk, kSliceBlock, 0, s>>>(sp.wrange, sp.bslice, sp.task, sp.idx, v, sp.gdim,
+                                             sp.W, sp.part, nullptr, st);
 }
 
 void free_sell(SellPlan& sp) {
@@ -547,6 +567,8 @@ rr_status build_sell_plans(Sparse& X, hipStream_t s) {
   RR_HIP(hipStreamSynchronize(s));
   RR_TRY(build_sell(X.sell_csr, rp, ci, X.N, X.F, X.num_cu, s));
   RR_TRY(build_sell(X.sell_csc, cp, ri, X.F, X.N, X.num_cu, s));
+  X.sell_csr.pass = 0;
+  X.sell_csc.pass = 1;
   return RR_OK;
 }
 

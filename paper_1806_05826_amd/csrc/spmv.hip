@@ -64,15 +64,18 @@ static void csr_dispatch(const Sparse& X, const double* v, double* u, const int*
 }
 
 void launch_csr(const Sparse& X, const double* v, double* u, const int* done, hipStream_t s,
-                const StageArgs* stage) {
+                const StageArgs* stage, hipEvent_t mid) {
   if (X.binary && X.N > 0) {
     Epi e{};
     e.out = u;
-    launch_sell(X.sell_csr, v, EPI_STORE, e, done, s, stage);
+    launch_sell(X.sell_csr, v, EPI_STORE, e, done, s, stage, mid);
     return;
   }
   if (stage) launch_stage_update(*stage, s);
-  if (X.N == 0) return;
+  if (X.N == 0) {
+    if (mid) (void)hipEventRecord(mid, s);
+    return;
+  }
   switch (X.csr_group) {
     case 4: csr_dispatch<4>(X, v, u, done, s); break;
     case 8: csr_dispatch<8>(X, v, u, done, s); break;
@@ -80,6 +83,7 @@ void launch_csr(const Sparse& X, const double* v, double* u, const int* done, hi
     case 32: csr_dispatch<32>(X, v, u, done, s); break;
     default: csr_dispatch<64>(X, v, u, done, s); break;
   }
+  if (mid) (void)hipEventRecord(mid, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -297,9 +301,11 @@ int collapse_parts(double* partials, int n, const int* done, hipStream_t s) {
 }
 
 int launch_csc(const Sparse& X, const double* u, int mode, const Epi& e, const int* done,
-               hipStream_t s) {
-  if (X.binary) return launch_sell(X.sell_csc, u, mode, e, done, s);
-  return launch_segsum(X.csc_plan, X.col_ptr + 1, X.row_idx, X.cval, u, mode, e, done, s);
+               hipStream_t s, hipEvent_t mid) {
+  if (X.binary) return launch_sell(X.sell_csc, u, mode, e, done, s, nullptr, mid);
+  const int n = launch_segsum(X.csc_plan, X.col_ptr + 1, X.row_idx, X.cval, u, mode, e, done, s);
+  if (mid) (void)hipEventRecord(mid, s);
+  return n;
 }
 
 int launch_segsum(const MergePlan& mp, const int* seg_end, const int* idx, const double* val,
