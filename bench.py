@@ -189,6 +189,20 @@ def main():
         torch.cuda.synchronize()
         compare[kind] = {"lambda": lam, "iters": k, "ms": (time.perf_counter() - ta) * 1e3}
     compare["vcycle"] = {"lambda": 1.0, "iters": calib[1.0]["iters"], "ms": last[1.0]["ms"]}
+    # flexible CG (truncation 1) with the same V(1,1) preconditioner
+    lam = 1.0
+    st, inf = rr.rr_solve(R.h, lam, y, w, tol=1e-14, max_iter=5000, precond="vcycle", krylov="fcg",
+                          fcg_m=1, raise_on=(1, 2, 6))
+    wref = w.clone()
+    st, inf = rr.rr_solve(R.h, lam, y, w, tol=1e-300, x_ref=wref, err_tol=1e-10, max_iter=5000,
+                          precond="vcycle", krylov="fcg", fcg_m=1, raise_on=(1, 2, 6))
+    k = inf["iters"]
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    rr.rr_solve(R.h, lam, y, w, fixed_iters=k, precond="vcycle", krylov="fcg", fcg_m=1, chunk=16,
+                raise_on=(1, 2, 6))
+    torch.cuda.synchronize()
+    compare["fcg1_vcycle"] = {"lambda": lam, "iters": k, "ms": (time.perf_counter() - ta) * 1e3}
 
     total_iters = sum(calib[l]["iters"] for l in lams)
     cpu = None

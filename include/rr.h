@@ -130,6 +130,13 @@ rr_status rr_get_labels(const rr_handle* h, int32_t* labels, rr_stream stream);
 /* Copy the seeding centres in draw order (device int32[n_centres]). */
 rr_status rr_get_centres(const rr_handle* h, int32_t* centres, rr_stream stream);
 
+/* Krylov method of rr_solve. */
+typedef enum {
+  RR_KRYLOV_PCG = 0,       /* preconditioned CG (needs a fixed SPD preconditioner) */
+  RR_KRYLOV_FCG = 1        /* flexible CG with truncation fcg_m (the paper's
+                              flexible-CG algorithm, Notay's FCG)                */
+} rr_krylov;
+
 typedef struct {
   double tol;              /* stop when ||r_k|| <= tol ||b||; 0 -> 1e-10        */
   int32_t max_iter;        /* 0 -> 10000                                        */
@@ -148,6 +155,11 @@ typedef struct {
   int32_t profile;         /* 1: time every operator pass with HIP events; 2: also
                               time 20 back-to-back launches of each sliced gather
                               kernel on the final vectors (0/1 X)                */
+  int32_t krylov;          /* rr_krylov: PCG (default) or flexible CG           */
+  int32_t fcg_m;           /* flexible CG: directions kept, 1..16; 0 -> 1.
+                              Direction i is orthogonalized against the
+                              m_i = max(1, i mod (m+1)) previous ones (the
+                              truncation of the paper's flexible-CG algorithm)  */
 } rr_solve_opts;
 
 typedef struct {

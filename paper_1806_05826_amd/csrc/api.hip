@@ -85,7 +85,9 @@ void destroy_handle(rr_handle* h) {
   Work& w = h->w;
   dfree(w.x); dfree(w.r); dfree(w.p); dfree(w.q); dfree(w.z); dfree(w.e1); dfree(w.e2);
   dfree(w.rho); dfree(w.b); dfree(w.u); dfree(w.c); dfree(w.yc); dfree(w.partials);
+  dfree(w.parts.dots);
   dfree(w.sc); dfree(w.D); dfree(w.vin); dfree(w.vout); dfree(w.xref);
+  dfree(w.fcg_p); dfree(w.fcg_ap); dfree(w.fcg_paps);
   if (w.sc_host) (void)hipHostFree(w.sc_host);
   for (auto e : h->ev_pool) (void)hipEventDestroy(e);
   delete h;
@@ -203,6 +205,7 @@ rr_status setup_impl(const rr_csr* Xin, const rr_setup_opts* o, hipStream_t s, r
   w.parts.init = w.partials + 3 * (size_t)np;
   w.parts.tr = w.partials + 4 * (size_t)np;
   w.parts.n_vec = vec_grid(F);
+  RR_TRY(dalloc(&w.parts.dots, (size_t)kMaxFcg * kMaxParts));
   RR_HIP(hipStreamSynchronize(s));
   RR_HIP(hipGetLastError());
   h->setup_ms = now_ms() - t0;
@@ -380,11 +383,28 @@ rr_status solve_impl(rr_handle* h, double lam, const double* rhs, double* wout,
     return fail(RR_ERR_INVALID_ARG, "two-level preconditioner needs a coarse level (n_clusters > 0)");
   if (op.fixed_iters < 0 || op.max_iter < 0 || op.chunk < 0 || op.tol < 0 || op.err_tol < 0)
     return fail(RR_ERR_INVALID_ARG, "negative option");
+  if (op.krylov != RR_KRYLOV_PCG && op.krylov != RR_KRYLOV_FCG)
+    return fail(RR_ERR_INVALID_ARG, "unknown Krylov method");
+  if (op.fcg_m < 0 || op.fcg_m > kMaxFcg)
+    return fail(RR_ERR_INVALID_ARG, "fcg_m must be in [0, 16]");
   const double tol = op.tol > 0 ? op.tol : 1e-10;
   const int max_iter = op.max_iter > 0 ? op.max_iter : 10000;
   const int chunk = op.chunk > 0 ? op.chunk : 8;
   Work& w = h->w;
   const int F = h->X.F;
+  const int fcg_m = op.fcg_m > 0 ? op.fcg_m : 1;
+  if (op.krylov == RR_KRYLOV_FCG && w.fcg_m < fcg_m) {
+    RR_HIP(hipStreamSynchronize(s));
+    dfree(w.fcg_p);
+    dfree(w.fcg_ap);
+    dfree(w.fcg_paps);
+    w.fcg_p = w.fcg_ap = w.fcg_paps = nullptr;
+    w.fcg_m = 0;
+    RR_TRY(dalloc(&w.fcg_p, (size_t)fcg_m * F));
+    RR_TRY(dalloc(&w.fcg_ap, (size_t)fcg_m * F));
+    RR_TRY(dalloc(&w.fcg_paps, kMaxFcg));
+    w.fcg_m = fcg_m;
+  }
   double coarse_ms = 0.0;
   LambdaSlot* sl = nullptr;
   double omega = op.omega;
@@ -421,6 +441,58 @@ rr_status solve_impl(rr_handle* h, double lam, const double* rhs, double* wout,
   const int nv = w.parts.n_vec;
   launch_pcg_init(F, w.b, w.x, w.r, w.p, w.z, w.e1, w.D, xref, omega, kind, w.parts.init, s);
   launch_finish_init(w.sc, w.parts.init, nv, op.residual_history, kind, s);
+  // the convergence check after each update runs in the kernel that follows it
+  StageArgs stage{w.sc, w.parts.upd, nv, op.residual_history, kind};
+  int queued = 0;
+  if (op.krylov == RR_KRYLOV_FCG) {
+    // flexible CG (the paper's flexible-CG algorithm): direction i is z_i
+    // orthogonalized against the m_i previous ones, m_i = max(1, i mod (m+1))
+    const int m = fcg_m;
+    if (two_level) {
+      int nrz = 0;
+      RR_TRY(precond_two_level(h, pf, -1, kind, lam, omega, *sl, w.r, w.z, nullptr, &nrz, s));
+    }
+    for (;;) {
+      for (int c = 0; c < chunk; ++c, ++queued) {
+        const int i = queued;
+        const int slot = i % m;
+        double* pi = w.fcg_p + (size_t)slot * F;
+        double* qi = w.fcg_ap + (size_t)slot * F;
+        FcgWindow win{};
+        if (i > 0) {
+          if (two_level) {
+            int nrz = 0;
+            RR_TRY(precond_two_level(h, pf, 100000000 + i - 1, kind, lam, omega, *sl, w.r, w.z,
+                                     &stage, &nrz, s));
+          }
+          const int mi = std::max(1, i % (m + 1));
+          for (int kk = i - mi; kk < i; ++kk) {
+            win.p[win.n] = w.fcg_p + (size_t)(kk % m) * F;
+            win.ap[win.n] = w.fcg_ap + (size_t)(kk % m) * F;
+            win.slot[win.n] = kk % m;
+            ++win.n;
+          }
+          launch_fcg_dots(F, w.z, win, w.parts.dots, w.sc, two_level ? nullptr : &stage, s);
+        }
+        launch_fcg_dir(F, w.z, w.r, pi, win, w.parts.dots, w.fcg_paps, w.parts.rz, w.sc, s);
+        RR_TRY(op_csr(h, pf, i, pi, s));
+        Epi e = base_epi(h, lam);
+        e.p = pi;
+        e.out = qi;
+        e.partials = w.parts.pq;
+        int npq = 0;
+        RR_TRY(op_csc(h, pf, i, EPI_APPLY_DOT, e, s, &npq));
+        launch_fcg_update(F, w.x, w.r, pi, qi, w.z, w.e1, w.D, xref, omega, kind, w.sc,
+                          w.parts.pq, npq, w.parts.rz, w.fcg_paps, slot, w.parts.upd, s);
+      }
+      RR_HIP(hipMemcpyAsync(&hs, w.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+      RR_HIP(hipStreamSynchronize(s));
+      RR_HIP(hipGetLastError());
+      if (hs.done) break;
+      if (queued > hs.limit + 2 * chunk)
+        return fail(RR_ERR_DEVICE, "internal: iteration limit passed without the device finishing");
+    }
+  } else {
   if (two_level) {
     int nrz = 0;
     RR_TRY(precond_two_level(h, pf, -1, kind, lam, omega, *sl, w.r, w.z, nullptr, &nrz, s));
@@ -428,9 +500,6 @@ rr_status solve_impl(rr_handle* h, double lam, const double* rhs, double* wout,
   } else {
     launch_pupdate(F, w.p, w.z, w.sc, w.parts.init + 2 * nv, nv, 1, nullptr, s);
   }
-  // the convergence check after each update runs in the kernel that follows it
-  StageArgs stage{w.sc, w.parts.upd, nv, op.residual_history, kind};
-  int queued = 0;
   for (;;) {
     for (int c = 0; c < chunk; ++c, ++queued) {
       RR_TRY(op_csr(h, pf, queued, w.p, s));
@@ -457,6 +526,7 @@ rr_status solve_impl(rr_handle* h, double lam, const double* rhs, double* wout,
     if (hs.done) break;
     if (queued > hs.limit + 2 * chunk)
       return fail(RR_ERR_DEVICE, "internal: iteration limit passed without the device finishing");
+  }
   }
   // exit: w = x and the true residual ||b - A x||
   launch_gather(wout, w.x, h->finv, F, s);

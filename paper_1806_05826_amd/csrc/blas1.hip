@@ -247,6 +247,134 @@ void launch_prolong(int F, const int* labels, const double* cscale, const double
                                            additive, sc, parts_rz);
 }
 
+// ---- flexible CG (truncated, m previous directions) -------------------------
+
+// <z, A p_k> for the window's directions: partials parts[k * gridDim + block].
+// With a stage, the convergence check of the preceding update runs first.
+__global__ __launch_bounds__(kBlock) void k_fcg_dots(int F, const double* z, FcgWindow win,
+                                                     double* parts, Scalars* sc, StageArgs stage) {
+  if (sc->done) return;
+  __shared__ double red[kBlock / 64];
+  if (stage.sc) {
+    double rz_unused;
+    if (stage_update<kBlock>(stage, red, rz_unused)) return;
+  }
+  double acc[kMaxFcg];
+#pragma unroll
+  for (int k = 0; k < kMaxFcg; ++k) acc[k] = 0.0;
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < F; j += gridDim.x * kBlock) {
+    const double zj = z[j];
+#pragma unroll
+    for (int k = 0; k < kMaxFcg; ++k)
+      if (k < win.n) acc[k] += zj * win.ap[k][j];
+  }
+#pragma unroll
+  for (int k = 0; k < kMaxFcg; ++k) {
+    if (k < win.n) {
+      const double t = block_sum(acc[k], red);
+      if (threadIdx.x == 0) parts[k * gridDim.x + blockIdx.x] = t;
+    }
+  }
+}
+
+void launch_fcg_dots(int F, const double* z, const FcgWindow& win, double* parts, Scalars* sc,
+                     const StageArgs* stage, hipStream_t s) {
+  StageArgs st{};
+  if (stage) st = *stage;
+  k_fcg_dots<<<vec_grid(F), kBlock, 0, s>>>(F, z, win, parts, sc, st);
+}
+
+// p = z - sum_k (<z, A p_k> / <p_k, A p_k>) p_k, oldest direction first, and
+// the partials of <p, r>.  p may be the storage of the window's oldest
+// direction: each element is read before it is overwritten by the same thread.
+__global__ __launch_bounds__(kBlock) void k_fcg_dir(int F, const double* z, const double* r,
+                                                    double* p, FcgWindow win,
+                                                    const double* dots, int n_dots,
+                                                    const double* paps, double* parts_pr,
+                                                    const Scalars* sc) {
+  if (sc->done) return;
+  __shared__ double red[kBlock / 64];
+  double c[kMaxFcg];
+#pragma unroll
+  for (int k = 0; k < kMaxFcg; ++k)
+    c[k] = (k < win.n) ? sum_parts<kBlock>(dots + k * n_dots, n_dots, red) / paps[win.slot[k]] : 0.0;
+  double v = 0.0;
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < F; j += gridDim.x * kBlock) {
+    double pj = z[j];
+#pragma unroll
+    for (int k = 0; k < kMaxFcg; ++k)
+      if (k < win.n) pj -= c[k] * win.p[k][j];
+    p[j] = pj;
+    v += pj * r[j];
+  }
+  store_block_partial<kBlock>(v, parts_pr, blockIdx.x);
+}
+
+void launch_fcg_dir(int F, const double* z, const double* r, double* p, const FcgWindow& win,
+                    const double* dots, const double* paps, double* parts_pr, const Scalars* sc,
+                    hipStream_t s) {
+  k_fcg_dir<<<vec_grid(F), kBlock, 0, s>>>(F, z, r, p, win, dots, vec_grid(F), paps, parts_pr, sc);
+}
+
+// alpha = <p, r> / <p, A p>; x += alpha p; r -= alpha q; <p, A p> kept for
+// the later orthogonalizations; the next smoother input and the partials of
+// ||r||^2 and the error, as in the PCG update.
+__global__ __launch_bounds__(kBlock) void k_fcg_update(
+    int F, double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+    const double* __restrict__ q, double* __restrict__ z, double* __restrict__ e1,
+    const double* __restrict__ D, const double* __restrict__ xref, double omega, int kind,
+    Scalars* sc, const double* __restrict__ parts_pq, int n_pq, const double* __restrict__ parts_pr,
+    int n_pr, double* paps, int slot, double* parts_upd) {
+  if (sc->done) return;
+  __shared__ double red[kBlock / 64];
+  const double pq = sum_parts<kBlock>(parts_pq, n_pq, red);
+  if (!finite_pos(pq)) {
+    if (is_block0_lead()) {
+      sc->pq = pq;
+      sc->status = RR_ERR_BREAKDOWN;
+      sc->done = 1;
+    }
+    return;
+  }
+  const double pr = sum_parts<kBlock>(parts_pr, n_pr, red);
+  const double alpha = pr / pq;
+  if (is_block0_lead()) {
+    sc->pq = pq;
+    sc->alpha = alpha;
+    paps[slot] = pq;
+    sc->iter = sc->iter + 1;
+  }
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < F; j += gridDim.x * kBlock) {
+    const double xj = x[j] + alpha * p[j];
+    const double rj = r[j] - alpha * q[j];
+    x[j] = xj;
+    r[j] = rj;
+    v0 += rj * rj;
+    if (xref) {
+      const double d = xj - xref[j];
+      v1 += d * d;
+    }
+    if (kind == PK_JACOBI) {
+      z[j] = rj / D[j];
+    } else if (kind == PK_NONE) {
+      z[j] = rj;
+    } else if (kind == PK_VCYCLE) {
+      e1[j] = (omega * rj) / D[j];
+    }
+  }
+  store_parts3(v0, v1, v2, parts_upd, gridDim.x);
+}
+
+void launch_fcg_update(int F, double* x, double* r, const double* p, const double* q, double* z,
+                       double* e1, const double* D, const double* xref, double omega, int kind,
+                       Scalars* sc, const double* parts_pq, int n_pq, const double* parts_pr,
+                       double* paps, int slot, double* parts_upd, hipStream_t s) {
+  k_fcg_update<<<vec_grid(F), kBlock, 0, s>>>(F, x, r, p, q, z, e1, D, xref, omega, kind, sc,
+                                              parts_pq, n_pq, parts_pr, vec_grid(F), paps, slot,
+                                              parts_upd);
+}
+
 __global__ void k_fill(double* x, double v, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = v;

@@ -50,6 +50,7 @@ struct Parts {
   double* rz = nullptr;    // <r, z> from the preconditioner      [n_red or n_vec]
   double* init = nullptr;  // ||b||^2, ||x_ref||^2, <r,z>          [3 * n_vec]
   double* tr = nullptr;    // ||b - Ax||^2                         [n_red]
+  double* dots = nullptr;  // flexible CG: <z, A p_k>               [kMaxFcg * n_vec]
   int n_red = 0;           // blocks of the column reduction (CSC epilogue)
   int n_vec = 0;           // blocks of the vector kernels
 };
@@ -61,6 +62,15 @@ struct StageArgs {
   int n;
   double* history;
   int kind;
+};
+
+// Window of previous directions of flexible CG (oldest first).
+constexpr int kMaxFcg = 16;
+struct FcgWindow {
+  const double* p[kMaxFcg];
+  const double* ap[kMaxFcg];
+  int slot[kMaxFcg];        // ring slot of each direction (its <p, Ap>)
+  int n;
 };
 
 // Epilogue arguments of the CSC (column-segment) reduction.
@@ -151,6 +161,8 @@ struct Work {
   double *partials = nullptr;     // reduction partials
   int npartials = 0;
   Parts parts;
+  int fcg_m = 0;                  // ring size of the flexible-CG directions
+  double *fcg_p = nullptr, *fcg_ap = nullptr, *fcg_paps = nullptr;   // [m F], [m F], [m]
   Scalars* sc = nullptr;
   Scalars* sc_host = nullptr;     // pinned mirror
 };
@@ -255,6 +267,15 @@ void launch_pupdate(int F, double* p, const double* z, Scalars* sc, const double
                     int n_rz, int first, const StageArgs* stage, hipStream_t s);
 void launch_stage_update(const StageArgs& st, hipStream_t s);
 void launch_finish_true(Scalars* sc, const double* parts, int n, hipStream_t s);
+void launch_fcg_dots(int F, const double* z, const FcgWindow& win, double* parts, Scalars* sc,
+                     const StageArgs* stage, hipStream_t s);
+void launch_fcg_dir(int F, const double* z, const double* r, double* p, const FcgWindow& win,
+                    const double* dots, const double* paps, double* parts_pr, const Scalars* sc,
+                    hipStream_t s);
+void launch_fcg_update(int F, double* x, double* r, const double* p, const double* q, double* z,
+                       double* e1, const double* D, const double* xref, double omega, int kind,
+                       Scalars* sc, const double* parts_pq, int n_pq, const double* parts_pr,
+                       double* paps, int slot, double* parts_upd, hipStream_t s);
 void launch_prolong(int F, const int* labels, const double* cscale, const double* yc,
                     const double* e1, double* out, const double* r, const double* D,
                     double omega, int additive, const Scalars* sc, double* parts_rz,

@@ -125,7 +125,7 @@ def test_precond_parity(rr, clustered, kind):
     assert np.linalg.norm(z - zr) <= 32 * kappa_c * 2**-52 * np.linalg.norm(zr)
 
 
-def oracle_iteration_spread(P, lam, kind, lab, fc, tol, max_iter, n=6, seed=0):
+def oracle_iteration_spread(P, lam, kind, lab, fc, tol, max_iter, n=6, seed=0, fcg_m=None):
     """Iteration counts of the oracle itself under rounding-level changes:
     the coarse solve done through an explicit inverse, and the
     preconditioner's diagonal (or, for CG, an identity scaling) and the
@@ -160,7 +160,10 @@ def oracle_iteration_spread(P, lam, kind, lab, fc, tol, max_iter, n=6, seed=0):
                 tl.Ac = tl.Ac * (1.0 + 0.5 * (E + E.T))
                 tl.L = coarse.cholesky(tl.Ac)
             B = tl.vcycle if kind == "vcycle" else tl.additive
-        _, inf = krylov.pcg(A, b, B, tol=tol, max_iter=max_iter)
+        if fcg_m is None:
+            _, inf = krylov.pcg(A, b, B, tol=tol, max_iter=max_iter)
+        else:
+            _, inf = krylov.fcg(A, b, lambda r, i, B=B: B(r), m=fcg_m, tol=tol, max_iter=max_iter)
         its.append(inf.iters)
     return min(its), max(its)
 
@@ -189,6 +192,51 @@ def test_solve_parity(rr, clustered, kind):
     x_1, _ = krylov.solve(P.X, P.y, lam, kind, lab, fc, fixed_iters=1)
     w, info = R.solve(lam, P.y, precond=kind, fixed_iters=1)
     assert np.linalg.norm(host(w) - x_1) <= 1e-10 * np.linalg.norm(x_1)
+
+
+def oracle_fcg(P, lam, kind, lab, fc, m, **kw):
+    b = op.rhs(P.X, P.y)
+    omega = op.omega_gershgorin(P.X, lam) if kind in ("vcycle", "additive") else None
+    B, _ = precond.make(kind, P.X, lam, lab, fc, omega)
+    return krylov.fcg(lambda v: op.apply_A(P.X, lam, v), b, lambda r, i: B(r), m=m, **kw)
+
+
+@pytest.mark.parametrize("kind", ["none", "jacobi", "vcycle", "additive"])
+@pytest.mark.parametrize("m", [1, 3])
+def test_fcg_parity(rr, clustered, kind, m):
+    """Flexible CG with truncation m against the oracle's flexible CG with the
+    same preconditioner: converged iterates at equal counts to 1e-10, the
+    first step to 1e-10, natural-stop counts inside the oracle's rounding
+    spread."""
+    name, P, R, (lab, fc, it, centres) = clustered
+    lam = 1.0
+    x_t, inf_t = oracle_fcg(P, lam, kind, lab, fc, m, tol=1e-13, max_iter=5000)
+    assert inf_t.status == krylov.OK
+    w, info = R.solve(lam, P.y, precond=kind, krylov="fcg", fcg_m=m, fixed_iters=inf_t.iters)
+    assert info["iters"] == inf_t.iters
+    assert np.linalg.norm(host(w) - x_t) <= 1e-10 * np.linalg.norm(x_t)
+    x_1, _ = oracle_fcg(P, lam, kind, lab, fc, m, fixed_iters=1)
+    w, info = R.solve(lam, P.y, precond=kind, krylov="fcg", fcg_m=m, fixed_iters=1)
+    assert np.linalg.norm(host(w) - x_1) <= 1e-10 * np.linalg.norm(x_1)
+    lo, hi = oracle_iteration_spread(P, lam, kind, lab, fc, 1e-10, 5000, n=6, fcg_m=m)
+    w, info = R.solve(lam, P.y, precond=kind, krylov="fcg", fcg_m=m, tol=1e-10, max_iter=5000)
+    assert info["status"] == 0
+    slack = 1 + int(0.02 * hi)
+    assert lo - slack <= info["iters"] <= hi + slack, (info["iters"], lo, hi)
+    assert info["true_relres"] <= 2e-10
+
+
+def test_fcg_options(rr, clustered):
+    name, P, R, _ = clustered
+    with pytest.raises(rr.RRError):
+        R.solve(1.0, P.y, krylov="fcg", fcg_m=17)
+    with pytest.raises(rr.RRError):
+        R.solve(1.0, P.y, krylov=7)
+    # the ring grows on demand and a smaller m afterwards still works
+    w1, i1 = R.solve(1.0, P.y, precond="vcycle", krylov="fcg", fcg_m=16, fixed_iters=20)
+    w2, i2 = R.solve(1.0, P.y, precond="vcycle", krylov="fcg", fcg_m=2, fixed_iters=20)
+    assert i1["iters"] == i2["iters"] == 20
+    assert np.all(np.isfinite(host(w1))) and np.all(np.isfinite(host(w2)))
 
 
 def test_residual_history_and_error_target(rr, clustered):
