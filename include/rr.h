@@ -195,6 +195,27 @@ typedef struct {
 rr_status rr_solve(rr_handle* h, double lambda, const double* rhs, double* w,
                    const rr_solve_opts* opts, rr_solve_info* info, rr_stream stream);
 
+/*
+ * rr_solve_batched: nprob independent solves (the paper solves one system
+ * per lambda, each with the two-level preconditioner of its own handle; its
+ * amortization argument is that X, the clustering and K serve many solves).
+ * Problem i solves (X_i^T X_i + lambdas[i] I) w = b_i on handles[i] with
+ * rhs[i], w[i] as in rr_solve.  Host arrays: handles, lambdas, rhs, w (device
+ * pointers), info[nprob] (may be NULL).  One options struct serves every
+ * problem; x_ref and residual_history must be NULL (per-problem buffers).
+ * Problems on distinct handles run concurrently on library-owned streams of
+ * their handles, with their iteration chunks queued round-robin; a handle
+ * that appears several times runs its problems in batch order.  The call
+ * orders after prior work on `stream`, later work on `stream` orders after
+ * it, and it blocks until info is valid.  Returns RR_OK when every problem
+ * succeeded, else the first failing status (info[i].status per problem).
+ * Errors: RR_ERR_INVALID_ARG for nprob < 0, null arrays or handles, or
+ * per-problem buffers in opts.
+ */
+rr_status rr_solve_batched(int32_t nprob, rr_handle* const* handles, const double* lambdas,
+                           const double* const* rhs, double* const* w, const rr_solve_opts* opts,
+                           rr_solve_info* info, rr_stream stream);
+
 /* Av = (X^T X + lambda I) v, v and Av device double[F] (lambda >= 0). */
 rr_status rr_apply_operator(rr_handle* h, double lambda, const double* v, double* Av,
                             rr_stream stream);

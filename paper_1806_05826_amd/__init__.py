@@ -76,6 +76,7 @@ _SIGS = {
     "rr_get_labels": [_P, _P, _P],
     "rr_get_centres": [_P, _P, _P],
     "rr_solve": [_P, C.c_double, _P, _P, C.POINTER(rr_solve_opts), C.POINTER(rr_solve_info), _P],
+    "rr_solve_batched": [C.c_int32, _P, _P, _P, _P, C.POINTER(rr_solve_opts), _P, _P],
     "rr_apply_operator": [_P, C.c_double, _P, _P, _P],
     "rr_apply_rhs": [_P, _P, _P, _P],
     "rr_apply_precond": [_P, C.c_double, C.c_int32, C.c_double, _P, _P, _P],
@@ -186,6 +187,32 @@ def rr_solve(h, lam, rhs, w, tol=0.0, max_iter=0, fixed_iters=0, precond="vcycle
     if st in raise_on:
         raise RRError(st, rr_last_error())
     return st, {f: getattr(info, f) for f, _ in rr_solve_info._fields_}
+
+
+def rr_solve_batched(handles, lams, rhs, ws, tol=0.0, max_iter=0, fixed_iters=0, precond="vcycle",
+                     rhs_is_b=False, omega=0.0, chunk=0, krylov="pcg", fcg_m=0, stream=None,
+                     raise_on=(RR_ERR_INVALID_ARG, RR_ERR_DEVICE, RR_ERR_UNSUPPORTED)):
+    """Batched solves; returns (status, [info dict per problem])."""
+    n = len(handles)
+    if not (len(lams) == len(rhs) == len(ws) == n):
+        raise ValueError("handles, lams, rhs and ws must have equal lengths")
+    for t in list(rhs) + list(ws):
+        _dev_f64(t, None, "vector")
+    H = (C.c_void_p * max(n, 1))(*[C.c_void_p(h) for h in handles])
+    L = (C.c_double * max(n, 1))(*[float(x) for x in lams])
+    Rp = (C.c_void_p * max(n, 1))(*[_ptr(t) for t in rhs])
+    Wp = (C.c_void_p * max(n, 1))(*[_ptr(t) for t in ws])
+    o = rr_solve_opts(float(tol), int(max_iter), int(fixed_iters),
+                      PRECOND[precond] if isinstance(precond, str) else int(precond),
+                      1 if rhs_is_b else 0, float(omega), None, 0.0, None, int(chunk), 0,
+                      KRYLOV[krylov] if isinstance(krylov, str) else int(krylov), int(fcg_m))
+    infos = (rr_solve_info * max(n, 1))()
+    st = _lib.rr_solve_batched(C.c_int32(n), C.cast(H, C.c_void_p), C.cast(L, C.c_void_p),
+                               C.cast(Rp, C.c_void_p), C.cast(Wp, C.c_void_p), C.byref(o),
+                               C.cast(infos, C.c_void_p), _stream(stream))
+    if st in raise_on:
+        raise RRError(st, rr_last_error())
+    return st, [{f: getattr(infos[i], f) for f, _ in rr_solve_info._fields_} for i in range(n)]
 
 
 def rr_apply_operator(h, lam, v, Av, stream=None):

@@ -90,6 +90,7 @@ void destroy_handle(rr_handle* h) {
   dfree(w.fcg_p); dfree(w.fcg_ap); dfree(w.fcg_paps);
   if (w.sc_host) (void)hipHostFree(w.sc_host);
   for (auto e : h->ev_pool) (void)hipEventDestroy(e);
+  if (h->bstream) (void)hipStreamDestroy(h->bstream);
   delete h;
 }
 
@@ -370,14 +371,36 @@ rr_status precond_two_level(rr_handle* h, Prof& pf, int tag, int kind, double la
   return RR_OK;
 }
 
-rr_status solve_impl(rr_handle* h, double lam, const double* rhs, double* wout,
-                     const rr_solve_opts* o, rr_solve_info* info, hipStream_t s) {
-  const double t0 = now_ms();
+// One solve, in phases so that several solves (distinct handles) can be
+// queued round-robin on their own streams: begin (checks, b, init, first
+// preconditioner application), queue_chunk (a chunk of iterations), poll
+// (read the device scalars), finish (w, the true residual, info).
+struct Solve {
+  rr_handle* h = nullptr;
+  double lam = 0.0;
+  const double* rhs = nullptr;
+  double* wout = nullptr;
+  rr_solve_opts op{};
+  hipStream_t s = nullptr;
+  double t0 = 0.0, coarse_ms = 0.0, omega = 0.0;
+  int kind = 0, chunk = 8, fcg_m = 1, queued = 0;
+  bool two_level = false, done = false;
+  LambdaSlot* sl = nullptr;
+  const double* xref = nullptr;
+  StageArgs stage{};
+  Prof pf;
+
+  rr_status begin();
+  rr_status queue_chunk();
+  rr_status poll();
+  rr_status finish(rr_solve_info* info);
+};
+
+rr_status Solve::begin() {
+  t0 = now_ms();
   RR_TRY(check_lambda(lam, false));
   if (!rhs || !wout) return fail(RR_ERR_INVALID_ARG, "null rhs or w");
-  rr_solve_opts def{};
-  const rr_solve_opts& op = o ? *o : def;
-  const int kind = op.precond;
+  kind = op.precond;
   if (kind < 0 || kind > 3) return fail(RR_ERR_INVALID_ARG, "unknown preconditioner");
   if ((kind == PK_VCYCLE || kind == PK_ADDITIVE) && h->FC == 0)
     return fail(RR_ERR_INVALID_ARG, "two-level preconditioner needs a coarse level (n_clusters > 0)");
@@ -389,10 +412,10 @@ rr_status solve_impl(rr_handle* h, double lam, const double* rhs, double* wout,
     return fail(RR_ERR_INVALID_ARG, "fcg_m must be in [0, 16]");
   const double tol = op.tol > 0 ? op.tol : 1e-10;
   const int max_iter = op.max_iter > 0 ? op.max_iter : 10000;
-  const int chunk = op.chunk > 0 ? op.chunk : 8;
+  chunk = op.chunk > 0 ? op.chunk : 8;
   Work& w = h->w;
   const int F = h->X.F;
-  const int fcg_m = op.fcg_m > 0 ? op.fcg_m : 1;
+  fcg_m = op.fcg_m > 0 ? op.fcg_m : 1;
   if (op.krylov == RR_KRYLOV_FCG && w.fcg_m < fcg_m) {
     RR_HIP(hipStreamSynchronize(s));
     dfree(w.fcg_p);
@@ -405,9 +428,7 @@ rr_status solve_impl(rr_handle* h, double lam, const double* rhs, double* wout,
     RR_TRY(dalloc(&w.fcg_paps, kMaxFcg));
     w.fcg_m = fcg_m;
   }
-  double coarse_ms = 0.0;
-  LambdaSlot* sl = nullptr;
-  double omega = op.omega;
+  omega = op.omega;
   if (kind == PK_VCYCLE || kind == PK_ADDITIVE) {
     RR_TRY(get_slot(h, lam, &sl, &coarse_ms, s));
     if (omega == 0.0) omega = sl->omega;
@@ -430,104 +451,114 @@ rr_status solve_impl(rr_handle* h, double lam, const double* rhs, double* wout,
   hs.use_err = (op.x_ref != nullptr) ? 1 : 0;
   hs.status = RR_ERR_NOT_CONVERGED;
   RR_HIP(hipMemcpyAsync(w.sc, &hs, sizeof(Scalars), hipMemcpyHostToDevice, s));
-  Prof pf;
   pf.on = op.profile != 0;
-  const double* xref = nullptr;
   if (op.x_ref) {
     launch_gather(w.xref, op.x_ref, h->fperm, F, s);
     xref = w.xref;
   }
-  const bool two_level = (kind == PK_VCYCLE || kind == PK_ADDITIVE);
+  two_level = (kind == PK_VCYCLE || kind == PK_ADDITIVE);
   const int nv = w.parts.n_vec;
   launch_pcg_init(F, w.b, w.x, w.r, w.p, w.z, w.e1, w.D, xref, omega, kind, w.parts.init, s);
   launch_finish_init(w.sc, w.parts.init, nv, op.residual_history, kind, s);
   // the convergence check after each update runs in the kernel that follows it
-  StageArgs stage{w.sc, w.parts.upd, nv, op.residual_history, kind};
-  int queued = 0;
+  stage = StageArgs{w.sc, w.parts.upd, nv, op.residual_history, kind};
+  queued = 0;
   if (op.krylov == RR_KRYLOV_FCG) {
-    // flexible CG (the paper's flexible-CG algorithm): direction i is z_i
-    // orthogonalized against the m_i previous ones, m_i = max(1, i mod (m+1))
-    const int m = fcg_m;
     if (two_level) {
       int nrz = 0;
       RR_TRY(precond_two_level(h, pf, -1, kind, lam, omega, *sl, w.r, w.z, nullptr, &nrz, s));
     }
-    for (;;) {
-      for (int c = 0; c < chunk; ++c, ++queued) {
-        const int i = queued;
-        const int slot = i % m;
-        double* pi = w.fcg_p + (size_t)slot * F;
-        double* qi = w.fcg_ap + (size_t)slot * F;
-        FcgWindow win{};
-        if (i > 0) {
-          if (two_level) {
-            int nrz = 0;
-            RR_TRY(precond_two_level(h, pf, 100000000 + i - 1, kind, lam, omega, *sl, w.r, w.z,
-                                     &stage, &nrz, s));
-          }
-          const int mi = std::max(1, i % (m + 1));
-          for (int kk = i - mi; kk < i; ++kk) {
-            win.p[win.n] = w.fcg_p + (size_t)(kk % m) * F;
-            win.ap[win.n] = w.fcg_ap + (size_t)(kk % m) * F;
-            win.slot[win.n] = kk % m;
-            ++win.n;
-          }
-          launch_fcg_dots(F, w.z, win, w.parts.dots, w.sc, two_level ? nullptr : &stage, s);
-        }
-        launch_fcg_dir(F, w.z, w.r, pi, win, w.parts.dots, w.fcg_paps, w.parts.rz, w.sc, s);
-        RR_TRY(op_csr(h, pf, i, pi, s));
-        Epi e = base_epi(h, lam);
-        e.p = pi;
-        e.out = qi;
-        e.partials = w.parts.pq;
-        int npq = 0;
-        RR_TRY(op_csc(h, pf, i, EPI_APPLY_DOT, e, s, &npq));
-        launch_fcg_update(F, w.x, w.r, pi, qi, w.z, w.e1, w.D, xref, omega, kind, w.sc,
-                          w.parts.pq, npq, w.parts.rz, w.fcg_paps, slot, w.parts.upd, s);
-      }
-      RR_HIP(hipMemcpyAsync(&hs, w.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
-      RR_HIP(hipStreamSynchronize(s));
-      RR_HIP(hipGetLastError());
-      if (hs.done) break;
-      if (queued > hs.limit + 2 * chunk)
-        return fail(RR_ERR_DEVICE, "internal: iteration limit passed without the device finishing");
-    }
-  } else {
-  if (two_level) {
+  } else if (two_level) {
     int nrz = 0;
     RR_TRY(precond_two_level(h, pf, -1, kind, lam, omega, *sl, w.r, w.z, nullptr, &nrz, s));
     launch_pupdate(F, w.p, w.z, w.sc, w.parts.rz, nrz, 1, nullptr, s);
   } else {
     launch_pupdate(F, w.p, w.z, w.sc, w.parts.init + 2 * nv, nv, 1, nullptr, s);
   }
-  for (;;) {
+  return RR_OK;
+}
+
+rr_status Solve::queue_chunk() {
+  Work& w = h->w;
+  const int F = h->X.F;
+  if (op.krylov == RR_KRYLOV_FCG) {
+    // flexible CG (the paper's flexible-CG algorithm): direction i is z_i
+    // orthogonalized against the m_i previous ones, m_i = max(1, i mod (m+1))
+    const int m = fcg_m;
     for (int c = 0; c < chunk; ++c, ++queued) {
-      RR_TRY(op_csr(h, pf, queued, w.p, s));
+      const int i = queued;
+      const int slot = i % m;
+      double* pi = w.fcg_p + (size_t)slot * F;
+      double* qi = w.fcg_ap + (size_t)slot * F;
+      FcgWindow win{};
+      if (i > 0) {
+        if (two_level) {
+          int nrz = 0;
+          RR_TRY(precond_two_level(h, pf, 100000000 + i - 1, kind, lam, omega, *sl, w.r, w.z,
+                                   &stage, &nrz, s));
+        }
+        const int mi = std::max(1, i % (m + 1));
+        for (int kk = i - mi; kk < i; ++kk) {
+          win.p[win.n] = w.fcg_p + (size_t)(kk % m) * F;
+          win.ap[win.n] = w.fcg_ap + (size_t)(kk % m) * F;
+          win.slot[win.n] = kk % m;
+          ++win.n;
+        }
+        launch_fcg_dots(F, w.z, win, w.parts.dots, w.sc, two_level ? nullptr : &stage, s);
+      }
+      launch_fcg_dir(F, w.z, w.r, pi, win, w.parts.dots, w.fcg_paps, w.parts.rz, w.sc, s);
+      RR_TRY(op_csr(h, pf, i, pi, s));
       Epi e = base_epi(h, lam);
-      e.p = w.p;
-      e.out = w.q;
+      e.p = pi;
+      e.out = qi;
       e.partials = w.parts.pq;
       int npq = 0;
-      RR_TRY(op_csc(h, pf, queued, EPI_APPLY_DOT, e, s, &npq));
-      launch_pcg_update(F, w.x, w.r, w.p, w.q, w.z, w.e1, w.D, xref, omega, kind, w.sc,
-                        w.parts.pq, npq, w.parts.upd, s);
-      if (two_level) {
-        int nrz = 0;
-        RR_TRY(precond_two_level(h, pf, 100000000 + queued, kind, lam, omega, *sl, w.r, w.z,
-                                 &stage, &nrz, s));
-        launch_pupdate(F, w.p, w.z, w.sc, w.parts.rz, nrz, 0, nullptr, s);
-      } else {
-        launch_pupdate(F, w.p, w.z, w.sc, nullptr, 0, 0, &stage, s);
-      }
+      RR_TRY(op_csc(h, pf, i, EPI_APPLY_DOT, e, s, &npq));
+      launch_fcg_update(F, w.x, w.r, pi, qi, w.z, w.e1, w.D, xref, omega, kind, w.sc,
+                        w.parts.pq, npq, w.parts.rz, w.fcg_paps, slot, w.parts.upd, s);
     }
-    RR_HIP(hipMemcpyAsync(&hs, w.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
-    RR_HIP(hipStreamSynchronize(s));
-    RR_HIP(hipGetLastError());
-    if (hs.done) break;
-    if (queued > hs.limit + 2 * chunk)
-      return fail(RR_ERR_DEVICE, "internal: iteration limit passed without the device finishing");
+    return RR_OK;
   }
+  for (int c = 0; c < chunk; ++c, ++queued) {
+    RR_TRY(op_csr(h, pf, queued, w.p, s));
+    Epi e = base_epi(h, lam);
+    e.p = w.p;
+    e.out = w.q;
+    e.partials = w.parts.pq;
+    int npq = 0;
+    RR_TRY(op_csc(h, pf, queued, EPI_APPLY_DOT, e, s, &npq));
+    launch_pcg_update(F, w.x, w.r, w.p, w.q, w.z, w.e1, w.D, xref, omega, kind, w.sc,
+                      w.parts.pq, npq, w.parts.upd, s);
+    if (two_level) {
+      int nrz = 0;
+      RR_TRY(precond_two_level(h, pf, 100000000 + queued, kind, lam, omega, *sl, w.r, w.z,
+                               &stage, &nrz, s));
+      launch_pupdate(F, w.p, w.z, w.sc, w.parts.rz, nrz, 0, nullptr, s);
+    } else {
+      launch_pupdate(F, w.p, w.z, w.sc, nullptr, 0, 0, &stage, s);
+    }
   }
+  return RR_OK;
+}
+
+rr_status Solve::poll() {
+  Scalars& hs = *h->w.sc_host;
+  RR_HIP(hipMemcpyAsync(&hs, h->w.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+  RR_HIP(hipStreamSynchronize(s));
+  RR_HIP(hipGetLastError());
+  if (hs.done) {
+    done = true;
+    return RR_OK;
+  }
+  if (queued > hs.limit + 2 * chunk)
+    return fail(RR_ERR_DEVICE, "internal: iteration limit passed without the device finishing");
+  return RR_OK;
+}
+
+rr_status Solve::finish(rr_solve_info* info) {
+  Work& w = h->w;
+  const int F = h->X.F;
+  Scalars& hs = *w.sc_host;
   // exit: w = x and the true residual ||b - A x||
   launch_gather(wout, w.x, h->finv, F, s);
   {
@@ -604,6 +635,105 @@ rr_status solve_impl(rr_handle* h, double lam, const double* rhs, double* wout,
   if (hs.status == RR_ERR_BREAKDOWN)
     return fail(RR_ERR_BREAKDOWN, "breakdown: <p,Ap> or <r,z> not positive");
   return RR_OK;
+}
+
+rr_status solve_impl(rr_handle* h, double lam, const double* rhs, double* wout,
+                     const rr_solve_opts* o, rr_solve_info* info, hipStream_t s) {
+  Solve sv;
+  sv.h = h;
+  sv.lam = lam;
+  sv.rhs = rhs;
+  sv.wout = wout;
+  if (o) sv.op = *o;
+  sv.s = s;
+  RR_TRY(sv.begin());
+  while (!sv.done) {
+    RR_TRY(sv.queue_chunk());
+    RR_TRY(sv.poll());
+  }
+  return sv.finish(info);
+}
+
+// Problems on distinct handles run concurrently, each on its handle's own
+// stream, with their chunks queued round-robin; a handle that appears again
+// starts its next problem once its previous one has finished.
+rr_status solve_batched_impl(int nprob, rr_handle* const* hs, const double* lams,
+                             const double* const* rhs, double* const* ws, const rr_solve_opts* o,
+                             rr_solve_info* infos, hipStream_t caller) {
+  if (nprob < 0) return fail(RR_ERR_INVALID_ARG, "nprob must be >= 0");
+  if (nprob == 0) return RR_OK;
+  if (!hs || !lams || !rhs || !ws) return fail(RR_ERR_INVALID_ARG, "null batch array");
+  rr_solve_opts op{};
+  if (o) op = *o;
+  if (op.x_ref || op.residual_history)
+    return fail(RR_ERR_INVALID_ARG, "x_ref and residual_history are per-problem buffers: use rr_solve");
+  for (int i = 0; i < nprob; ++i)
+    if (!hs[i]) return fail(RR_ERR_INVALID_ARG, "null handle in batch");
+  // waves: each handle at most once per wave, in batch order
+  std::vector<int> wave(nprob, 0);
+  int nwaves = 0;
+  for (int i = 0; i < nprob; ++i) {
+    int k = 0;
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) k = std::max(k, wave[j] + 1);
+    wave[i] = k;
+    nwaves = std::max(nwaves, k + 1);
+  }
+  hipEvent_t ev_in;
+  RR_HIP(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
+  RR_HIP(hipEventRecord(ev_in, caller));
+  rr_status first_bad = RR_OK;
+  for (int wv = 0; wv < nwaves; ++wv) {
+    std::vector<Solve> sv;
+    std::vector<int> idx;
+    for (int i = 0; i < nprob; ++i) {
+      if (wave[i] != wv) continue;
+      rr_handle* h = hs[i];
+      if (!h->bstream) RR_HIP(hipStreamCreateWithFlags(&h->bstream, hipStreamNonBlocking));
+      RR_HIP(hipStreamWaitEvent(h->bstream, ev_in, 0));
+      Solve x;
+      x.h = h;
+      x.lam = lams[i];
+      x.rhs = rhs[i];
+      x.wout = ws[i];
+      x.op = op;
+      x.s = h->bstream;
+      sv.push_back(x);
+      idx.push_back(i);
+    }
+    std::vector<rr_status> st(sv.size(), RR_OK);
+    for (size_t j = 0; j < sv.size(); ++j) st[j] = sv[j].begin();
+    for (;;) {
+      bool active = false;
+      for (size_t j = 0; j < sv.size(); ++j)
+        if (st[j] == RR_OK && !sv[j].done) {
+          st[j] = sv[j].queue_chunk();
+          active = true;
+        }
+      if (!active) break;
+      for (size_t j = 0; j < sv.size(); ++j)
+        if (st[j] == RR_OK && !sv[j].done) st[j] = sv[j].poll();
+    }
+    for (size_t j = 0; j < sv.size(); ++j) {
+      rr_solve_info inf{};
+      if (st[j] == RR_OK) {
+        st[j] = sv[j].finish(&inf);
+      } else {
+        (void)hipStreamSynchronize(sv[j].s);
+        inf.status = st[j];
+      }
+      if (infos) infos[idx[j]] = inf;
+      if (st[j] != RR_OK && first_bad == RR_OK) first_bad = st[j];
+    }
+    // the next wave's problems and the caller wait for this wave
+    for (size_t j = 0; j < sv.size(); ++j) {
+      RR_HIP(hipEventRecord(ev_in, sv[j].s));
+      RR_HIP(hipStreamWaitEvent(caller, ev_in, 0));
+    }
+    RR_HIP(hipEventRecord(ev_in, caller));
+  }
+  RR_HIP(hipEventDestroy(ev_in));
+  return first_bad;
 }
 
 }  // namespace
@@ -687,6 +817,13 @@ rr_status rr_solve(rr_handle* h, double lambda, const double* rhs, double* w,
   g_last_error.clear();
   RR_TRY(check_handle(h));
   return solve_impl(h, lambda, rhs, w, opts, info, (hipStream_t)stream);
+}
+
+rr_status rr_solve_batched(int32_t nprob, rr_handle* const* handles, const double* lambdas,
+                           const double* const* rhs, double* const* w, const rr_solve_opts* opts,
+                           rr_solve_info* info, rr_stream stream) {
+  g_last_error.clear();
+  return solve_batched_impl(nprob, handles, lambdas, rhs, w, opts, info, (hipStream_t)stream);
 }
 
 rr_status rr_apply_operator(rr_handle* h, double lambda, const double* v, double* Av,

@@ -194,6 +194,7 @@ struct rr_handle {
   rr::Work w;
   double setup_ms = 0, kmeans_ms = 0;
   std::vector<hipEvent_t> ev_pool;
+  hipStream_t bstream = nullptr;    // the handle's own stream for batched solves
 };
 
 namespace rr {
