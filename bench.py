@@ -204,6 +204,33 @@ def main():
     torch.cuda.synchronize()
     compare["fcg1_vcycle"] = {"lambda": lam, "iters": k, "ms": (time.perf_counter() - ta) * 1e3}
 
+    # batched form: the three lambdas as one rr_solve_batched call on the same
+    # handle (three work sets, concurrent) against three rr_solve calls, both
+    # stopping at relative residual 1e-10
+    def seq_solves():
+        out = []
+        for lam in lams:
+            st, inf = rr.rr_solve(R.h, lam, y, w, tol=1e-10, precond="vcycle", chunk=16,
+                                  raise_on=(1, 2, 6))
+            out.append(inf["iters"])
+        return out
+    wsb = [torch.empty(F, dtype=torch.float64, device=dev) for _ in lams]
+    def batched_solves():
+        st, infos = rr.rr_solve_batched([R.h] * len(lams), lams, [y] * len(lams), wsb, tol=1e-10,
+                                        precond="vcycle", chunk=16, raise_on=(1, 2, 6))
+        return [i["iters"] for i in infos]
+    batched = {}
+    for name, f in (("plain", seq_solves), ("batched", batched_solves)):
+        f()
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(3):
+            its = f()
+        torch.cuda.synchronize()
+        batched[name + "_ms"] = (time.perf_counter() - ta) * 1e3 / 3
+        batched[name + "_iters"] = its
+    batched["speedup"] = batched["plain_ms"] / batched["batched_ms"]
+
     total_iters = sum(calib[l]["iters"] for l in lams)
     cpu = None
     if not args.no_cpu:
@@ -242,6 +269,7 @@ def main():
                      "row_pass_ms": csr_ms, "row_gather_ms": gcsr_ms,
                      "column_pass_ms": csc_ms, "column_gather_ms": gcsc_ms},
         "compare_lambda1": compare,
+        "batched_lambdas": batched,
         "roofline": {"bound": "hbm", "achieved": gbs_gather, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs_gather / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "rr::k_sell<1> (column-pass gather of t = X^T u through LDS slices)",

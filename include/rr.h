@@ -202,10 +202,14 @@ rr_status rr_solve(rr_handle* h, double lambda, const double* rhs, double* w,
  * Problem i solves (X_i^T X_i + lambdas[i] I) w = b_i on handles[i] with
  * rhs[i], w[i] as in rr_solve.  Host arrays: handles, lambdas, rhs, w (device
  * pointers), info[nprob] (may be NULL).  One options struct serves every
- * problem; x_ref and residual_history must be NULL (per-problem buffers).
- * Problems on distinct handles run concurrently on library-owned streams of
- * their handles, with their iteration chunks queued round-robin; a handle
- * that appears several times runs its problems in batch order.  The call
+ * problem; x_ref and residual_history must be NULL (per-problem buffers) and
+ * profile is ignored.  Problems run concurrently, each in a work set of its
+ * handle (vectors, partial sums and a stream of its own; the k-th problem on
+ * a handle uses the handle's k-th set, created on first use), with their
+ * iteration chunks queued round-robin; beyond 8 problems per handle the rest
+ * run in later waves.  Cached coarse factors in use are never evicted (the
+ * cache grows instead).  Every problem's result is bitwise the result of
+ * rr_solve with the same arguments.  The call
  * orders after prior work on `stream`, later work on `stream` orders after
  * it, and it blocks until info is valid.  Returns RR_OK when every problem
  * succeeded, else the first failing status (info[i].status per problem).

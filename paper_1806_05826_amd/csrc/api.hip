@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <new>
 
 #include "rr_device.h"
@@ -68,6 +69,86 @@ void dfree(void* p) {
   if (p) (void)hipFree(p);
 }
 
+void free_work(Work& w) {
+  dfree(w.x); dfree(w.r); dfree(w.p); dfree(w.q); dfree(w.z); dfree(w.e1); dfree(w.e2);
+  dfree(w.rho); dfree(w.b); dfree(w.u); dfree(w.c); dfree(w.yc); dfree(w.partials);
+  dfree(w.parts.dots);
+  dfree(w.sc); dfree(w.D); dfree(w.vin); dfree(w.vout); dfree(w.xref);
+  dfree(w.fcg_p); dfree(w.fcg_ap); dfree(w.fcg_paps);
+  if (w.sc_host) (void)hipHostFree(w.sc_host);
+  if (w.extra) {
+    dfree(w.X.sell_csr.part); dfree(w.X.sell_csc.part);
+    dfree(w.X.csc_plan.head); dfree(w.X.csc_plan.tail);
+    dfree(w.rplan.head); dfree(w.rplan.tail);
+  }
+  if (w.stream) (void)hipStreamDestroy(w.stream);
+  w = Work{};
+}
+
+// The solve vectors and reduction partials of one work set (F features,
+// N samples, F_C coarse unknowns, np partials per region).
+rr_status alloc_work(Work& w, int F, int N, int FC, int np) {
+  RR_TRY(dalloc(&w.x, F)); RR_TRY(dalloc(&w.r, F)); RR_TRY(dalloc(&w.p, F));
+  RR_TRY(dalloc(&w.q, F)); RR_TRY(dalloc(&w.z, F)); RR_TRY(dalloc(&w.e1, F));
+  RR_TRY(dalloc(&w.e2, F)); RR_TRY(dalloc(&w.rho, F)); RR_TRY(dalloc(&w.b, F));
+  RR_TRY(dalloc(&w.D, F)); RR_TRY(dalloc(&w.u, N));
+  RR_TRY(dalloc(&w.vin, F)); RR_TRY(dalloc(&w.vout, F)); RR_TRY(dalloc(&w.xref, F));
+  RR_TRY(dalloc(&w.sc, 1));
+  RR_HIP(hipHostMalloc((void**)&w.sc_host, sizeof(Scalars), hipHostMallocDefault));
+  std::memset(w.sc_host, 0, sizeof(Scalars));
+  if (FC > 0) {
+    RR_TRY(dalloc(&w.c, FC));
+    RR_TRY(dalloc(&w.yc, FC));
+  }
+  // five partial regions (pq, upd, rz, init, tr), each large enough for the
+  // widest producer grid
+  w.npartials = np;
+  RR_TRY(dalloc(&w.partials, 5 * (size_t)np));
+  w.parts.pq = w.partials;
+  w.parts.upd = w.partials + (size_t)np;
+  w.parts.rz = w.partials + 2 * (size_t)np;
+  w.parts.init = w.partials + 3 * (size_t)np;
+  w.parts.tr = w.partials + 4 * (size_t)np;
+  w.parts.n_vec = vec_grid(F);
+  RR_TRY(dalloc(&w.parts.dots, (size_t)kMaxFcg * kMaxParts));
+  return RR_OK;
+}
+
+// Work set k (0: the handle's own); sets beyond the first are created on
+// first use with their own partial-sum buffers for the operator passes and
+// the restriction.
+rr_status get_work_set(rr_handle* h, int k, Work** out) {
+  if (k == 0) {
+    *out = &h->w;
+    return RR_OK;
+  }
+  while ((int)h->extra_sets.size() < k) {
+    Work* w = new (std::nothrow) Work();
+    if (!w) return fail(RR_ERR_DEVICE, "out of host memory");
+    h->extra_sets.push_back(w);
+    w->extra = true;
+    w->X = h->X;
+    w->rplan = h->restrict_plan;
+    w->X.sell_csr.part = w->X.sell_csc.part = nullptr;
+    w->X.csc_plan.head = w->X.csc_plan.tail = nullptr;
+    w->rplan.head = w->rplan.tail = nullptr;
+    RR_TRY(alloc_work(*w, h->X.F, h->X.N, h->FC, h->npartials));
+    if (h->X.binary) {
+      RR_TRY(dalloc(&w->X.sell_csr.part, h->X.sell_csr.nout));
+      RR_TRY(dalloc(&w->X.sell_csc.part, h->X.sell_csc.nout));
+    } else {
+      RR_TRY(dalloc(&w->X.csc_plan.head, h->X.csc_plan.nblocks));
+      RR_TRY(dalloc(&w->X.csc_plan.tail, h->X.csc_plan.nblocks));
+    }
+    if (h->restrict_plan.nblocks > 0) {
+      RR_TRY(dalloc(&w->rplan.head, h->restrict_plan.nblocks));
+      RR_TRY(dalloc(&w->rplan.tail, h->restrict_plan.nblocks));
+    }
+  }
+  *out = h->extra_sets[k - 1];
+  return RR_OK;
+}
+
 void destroy_handle(rr_handle* h) {
   if (!h) return;
   Sparse& X = h->X;
@@ -81,14 +162,12 @@ void destroy_handle(rr_handle* h) {
   dfree(h->labels); dfree(h->centres); dfree(h->csize); dfree(h->cscale);
   dfree(h->perm); dfree(h->coff); dfree(h->K);
   for (auto& s : h->slots) { dfree(s.L); dfree(s.Ainv); }
-  dfree(h->chol_work); dfree(h->chol_flag);
-  Work& w = h->w;
-  dfree(w.x); dfree(w.r); dfree(w.p); dfree(w.q); dfree(w.z); dfree(w.e1); dfree(w.e2);
-  dfree(w.rho); dfree(w.b); dfree(w.u); dfree(w.c); dfree(w.yc); dfree(w.partials);
-  dfree(w.parts.dots);
-  dfree(w.sc); dfree(w.D); dfree(w.vin); dfree(w.vout); dfree(w.xref);
-  dfree(w.fcg_p); dfree(w.fcg_ap); dfree(w.fcg_paps);
-  if (w.sc_host) (void)hipHostFree(w.sc_host);
+  dfree(h->chol_work); dfree(h->chol_flag); dfree(h->omega_tmp);
+  free_work(h->w);
+  for (Work* w : h->extra_sets) {
+    free_work(*w);
+    delete w;
+  }
   for (auto e : h->ev_pool) (void)hipEventDestroy(e);
   if (h->bstream) (void)hipStreamDestroy(h->bstream);
   delete h;
@@ -142,18 +221,12 @@ rr_status setup_impl(const rr_csr* Xin, const rr_setup_opts* o, hipStream_t s, r
     k_colnorm_binary<<<cdiv(X.F, kBlock), kBlock, 0, s>>>(X.F, X.col_ptr, h->colnorm);
   else
     k_colnorm_values<<<cdiv(X.F, kBlock), kBlock, 0, s>>>(X.F, X.col_ptr, X.cval, h->colnorm);
-  // work buffers
+  // work buffers for the Gershgorin pass (the full set is allocated below)
   Work& w = h->w;
   const int F = X.F, N = X.N;
-  RR_TRY(dalloc(&w.x, F)); RR_TRY(dalloc(&w.r, F)); RR_TRY(dalloc(&w.p, F));
-  RR_TRY(dalloc(&w.q, F)); RR_TRY(dalloc(&w.z, F)); RR_TRY(dalloc(&w.e1, F));
-  RR_TRY(dalloc(&w.e2, F)); RR_TRY(dalloc(&w.rho, F)); RR_TRY(dalloc(&w.b, F));
-  RR_TRY(dalloc(&w.D, F)); RR_TRY(dalloc(&w.u, N));
-  RR_TRY(dalloc(&w.vin, F)); RR_TRY(dalloc(&w.vout, F)); RR_TRY(dalloc(&w.xref, F));
-  RR_TRY(dalloc(&w.sc, 1));
-  RR_HIP(hipHostMalloc((void**)&w.sc_host, sizeof(Scalars), hipHostMallocDefault));
-  std::memset(w.sc_host, 0, sizeof(Scalars));
-  RR_HIP(hipMemsetAsync(w.sc, 0, sizeof(Scalars), s));
+  RR_TRY(dalloc(&w.x, F));
+  RR_TRY(dalloc(&w.u, N));
+  RR_TRY(dalloc(&h->omega_tmp, 1));
   {
     launch_fill(w.u, 0.0, N, s);
     launch_fill(w.x, 1.0, F, s);
@@ -191,22 +264,18 @@ rr_status setup_impl(const rr_csr* Xin, const rr_setup_opts* o, hipStream_t s, r
     }
     RR_TRY(dalloc(&h->chol_work, 2 * (size_t)fc * fc));
     RR_TRY(dalloc(&h->chol_flag, 1));
-    RR_TRY(dalloc(&w.c, fc));
-    RR_TRY(dalloc(&w.yc, fc));
     np = std::max(np, h->restrict_plan.nblocks + cdiv(h->restrict_plan.nspan, kBlock / 64) + 1);
   }
-  // five partial regions (pq, upd, rz, init, tr), each large enough for the
-  // widest producer grid
   np = std::max(np, std::max(3 * kMaxParts, kMaxReduceBlocks + 1));
-  w.npartials = np;
-  RR_TRY(dalloc(&w.partials, 5 * (size_t)np));
-  w.parts.pq = w.partials;
-  w.parts.upd = w.partials + (size_t)np;
-  w.parts.rz = w.partials + 2 * (size_t)np;
-  w.parts.init = w.partials + 3 * (size_t)np;
-  w.parts.tr = w.partials + 4 * (size_t)np;
-  w.parts.n_vec = vec_grid(F);
-  RR_TRY(dalloc(&w.parts.dots, (size_t)kMaxFcg * kMaxParts));
+  h->npartials = np;
+  RR_HIP(hipStreamSynchronize(s));
+  dfree(w.x);
+  dfree(w.u);
+  w.x = w.u = nullptr;
+  RR_TRY(alloc_work(w, F, N, h->FC, np));
+  RR_HIP(hipMemsetAsync(w.sc, 0, sizeof(Scalars), s));
+  w.X = h->X;
+  w.rplan = h->restrict_plan;
   RR_HIP(hipStreamSynchronize(s));
   RR_HIP(hipGetLastError());
   h->setup_ms = now_ms() - t0;
@@ -227,16 +296,9 @@ rr_status check_lambda(double lam, bool allow_zero) {
 rr_status auto_omega(rr_handle* h, double lam, double* omega, hipStream_t s) {
   if (!h->nonneg)
     return fail(RR_ERR_UNSUPPORTED, "automatic smoother weight for X with negative entries: pass omega");
-  double* d = h->w.yc ? h->w.yc : h->w.c;
-  double* tmp = nullptr;
-  if (!d) {
-    RR_TRY(dalloc(&tmp, 1));
-    d = tmp;
-  }
-  launch_omega_gersh(h->X.F, h->gersh, h->colnorm, lam, d, nullptr, nullptr, s);
-  RR_HIP(hipMemcpyAsync(omega, d, sizeof(double), hipMemcpyDeviceToHost, s));
+  launch_omega_gersh(h->X.F, h->gersh, h->colnorm, lam, h->omega_tmp, nullptr, nullptr, s);
+  RR_HIP(hipMemcpyAsync(omega, h->omega_tmp, sizeof(double), hipMemcpyDeviceToHost, s));
   RR_HIP(hipStreamSynchronize(s));
-  dfree(tmp);
   return RR_OK;
 }
 
@@ -249,9 +311,18 @@ rr_status get_slot(rr_handle* h, double lam, LambdaSlot** out, double* ms, hipSt
       *out = &sl;
       return RR_OK;
     }
-  LambdaSlot* victim = &h->slots[0];
+  LambdaSlot* victim = nullptr;
   for (auto& sl : h->slots)
-    if (!sl.valid || sl.stamp < victim->stamp) victim = &sl;
+    if (sl.in_use == 0 && (!victim || !sl.valid || (victim->valid && sl.stamp < victim->stamp)))
+      victim = &sl;
+  if (!victim) {   // every cached factor is in use by a running solve
+    LambdaSlot ns;
+    const int fc = h->FC;
+    RR_TRY(dalloc(&ns.L, (size_t)fc * fc));
+    RR_TRY(dalloc(&ns.Ainv, (size_t)fc * fc));
+    h->slots.push_back(ns);   // slots is a deque: pointers to other slots stay valid
+    victim = &h->slots.back();
+  }
   const double t0 = now_ms();
   victim->valid = false;
   RR_TRY(coarse_factor(h, lam, *victim, s));
@@ -284,56 +355,55 @@ rr_status prof_pair(rr_handle* h, Prof& pf, int* idx) {
 }
 
 // Apply the operator pieces with optional event timing.
-rr_status op_csr(rr_handle* h, Prof& pf, int tag, const double* v, hipStream_t s,
+rr_status op_csr(rr_handle* h, Work& w, Prof& pf, int tag, const double* v, hipStream_t s,
                  const StageArgs* stage = nullptr) {
-  const int* done = &h->w.sc->done;
+  const int* done = &w.sc->done;
   if (!pf.on) {
-    launch_csr(h->X, v, h->w.u, done, s, stage);
+    launch_csr(w.X, v, w.u, done, s, stage);
     return RR_OK;
   }
   int i;
   RR_TRY(prof_pair(h, pf, &i));
   RR_HIP(hipEventRecord(h->ev_pool[3 * i], s));
-  launch_csr(h->X, v, h->w.u, done, s, stage, h->ev_pool[3 * i + 1]);
+  launch_csr(w.X, v, w.u, done, s, stage, h->ev_pool[3 * i + 1]);
   RR_HIP(hipEventRecord(h->ev_pool[3 * i + 2], s));
   pf.csr.push_back({i, tag});
   return RR_OK;
 }
 
 // *nparts receives the count of block partials a dot-product epilogue left.
-rr_status op_csc(rr_handle* h, Prof& pf, int tag, int mode, const Epi& e, hipStream_t s,
+rr_status op_csc(rr_handle* h, Work& w, Prof& pf, int tag, int mode, const Epi& e, hipStream_t s,
                  int* nparts = nullptr) {
-  const int* done = &h->w.sc->done;
+  const int* done = &w.sc->done;
   if (!pf.on) {
-    const int n = launch_csc(h->X, h->w.u, mode, e, done, s);
+    const int n = launch_csc(w.X, w.u, mode, e, done, s);
     if (nparts) *nparts = n;
     return RR_OK;
   }
   int i;
   RR_TRY(prof_pair(h, pf, &i));
   RR_HIP(hipEventRecord(h->ev_pool[3 * i], s));
-  const int n = launch_csc(h->X, h->w.u, mode, e, done, s, h->ev_pool[3 * i + 1]);
+  const int n = launch_csc(w.X, w.u, mode, e, done, s, h->ev_pool[3 * i + 1]);
   if (nparts) *nparts = n;
   RR_HIP(hipEventRecord(h->ev_pool[3 * i + 2], s));
   pf.csc.push_back({i, tag});
   return RR_OK;
 }
 
-Epi base_epi(rr_handle* h, double lam) {
+Epi base_epi(const Work& w, double lam) {
   Epi e{};
   e.lam = lam;
-  e.sc = h->w.sc;
-  e.D = h->w.D;
+  e.sc = w.sc;
+  e.D = w.D;
   return e;
 }
 
 // z = B r for the two-level forms; e1 (V-cycle) must already hold w D^-1 r.
 // The partials of <r, z> are left in parts.rz (*n_rz of them).  With a
 // stage, the convergence check of the preceding update runs first.
-rr_status precond_two_level(rr_handle* h, Prof& pf, int tag, int kind, double lam, double omega,
-                            const LambdaSlot& sl, const double* r, double* z,
+rr_status precond_two_level(rr_handle* h, Work& w, Prof& pf, int tag, int kind, double lam,
+                            double omega, const LambdaSlot& sl, const double* r, double* z,
                             const StageArgs* stage, int* n_rz, hipStream_t s) {
-  Work& w = h->w;
   const int F = h->X.F;
   const int* done = &w.sc->done;
   Epi er{};
@@ -341,7 +411,7 @@ rr_status precond_two_level(rr_handle* h, Prof& pf, int tag, int kind, double la
   er.out = w.c;
   if (kind == PK_ADDITIVE) {
     if (stage) launch_stage_update(*stage, s);
-    launch_segsum(h->restrict_plan, h->coff + 1, h->perm, nullptr, r, EPI_SCALE, er, done, s);
+    launch_segsum(w.rplan, h->coff + 1, h->perm, nullptr, r, EPI_SCALE, er, done, s);
     launch_gemv(h->FC, sl.Ainv, w.c, w.yc, done, s);
     launch_prolong(F, h->labels, h->cscale, w.yc, nullptr, z, r, w.D, omega, 1, w.sc,
                    w.parts.rz, s);
@@ -349,25 +419,25 @@ rr_status precond_two_level(rr_handle* h, Prof& pf, int tag, int kind, double la
     return RR_OK;
   }
   // V(1,1): rho1 = r - A e1
-  RR_TRY(op_csr(h, pf, tag, w.e1, s, stage));
-  Epi e = base_epi(h, lam);
+  RR_TRY(op_csr(h, w, pf, tag, w.e1, s, stage));
+  Epi e = base_epi(w, lam);
   e.p = w.e1;
   e.r = r;
   e.out = w.rho;
-  RR_TRY(op_csc(h, pf, tag, EPI_RESID, e, s));
+  RR_TRY(op_csc(h, w, pf, tag, EPI_RESID, e, s));
   // e2 = e1 + P A_c^-1 P^T rho1
-  launch_segsum(h->restrict_plan, h->coff + 1, h->perm, nullptr, w.rho, EPI_SCALE, er, done, s);
+  launch_segsum(w.rplan, h->coff + 1, h->perm, nullptr, w.rho, EPI_SCALE, er, done, s);
   launch_gemv(h->FC, sl.Ainv, w.c, w.yc, done, s);
   launch_prolong(F, h->labels, h->cscale, w.yc, w.e1, w.e2, nullptr, nullptr, 0.0, 0, w.sc, nullptr, s);
   // z = e2 + w D^-1 (r - A e2), <r,z> -> beta
-  RR_TRY(op_csr(h, pf, tag, w.e2, s));
-  Epi e2 = base_epi(h, lam);
+  RR_TRY(op_csr(h, w, pf, tag, w.e2, s));
+  Epi e2 = base_epi(w, lam);
   e2.p = w.e2;
   e2.r = r;
   e2.omega = omega;
   e2.out = z;
   e2.partials = w.parts.rz;
-  RR_TRY(op_csc(h, pf, tag, EPI_POST, e2, s, n_rz));
+  RR_TRY(op_csc(h, w, pf, tag, EPI_POST, e2, s, n_rz));
   return RR_OK;
 }
 
@@ -377,6 +447,7 @@ rr_status precond_two_level(rr_handle* h, Prof& pf, int tag, int kind, double la
 // (read the device scalars), finish (w, the true residual, info).
 struct Solve {
   rr_handle* h = nullptr;
+  Work* ws = nullptr;      // the work set this solve runs in
   double lam = 0.0;
   const double* rhs = nullptr;
   double* wout = nullptr;
@@ -394,6 +465,10 @@ struct Solve {
   rr_status queue_chunk();
   rr_status poll();
   rr_status finish(rr_solve_info* info);
+  void release() {
+    if (sl) sl->in_use--;
+    sl = nullptr;
+  }
 };
 
 rr_status Solve::begin() {
@@ -413,7 +488,7 @@ rr_status Solve::begin() {
   const double tol = op.tol > 0 ? op.tol : 1e-10;
   const int max_iter = op.max_iter > 0 ? op.max_iter : 10000;
   chunk = op.chunk > 0 ? op.chunk : 8;
-  Work& w = h->w;
+  Work& w = *ws;
   const int F = h->X.F;
   fcg_m = op.fcg_m > 0 ? op.fcg_m : 1;
   if (op.krylov == RR_KRYLOV_FCG && w.fcg_m < fcg_m) {
@@ -431,6 +506,7 @@ rr_status Solve::begin() {
   omega = op.omega;
   if (kind == PK_VCYCLE || kind == PK_ADDITIVE) {
     RR_TRY(get_slot(h, lam, &sl, &coarse_ms, s));
+    sl->in_use++;
     if (omega == 0.0) omega = sl->omega;
   }
   if (!std::isfinite(omega) || omega < 0.0) return fail(RR_ERR_INVALID_ARG, "omega must be finite and >= 0");
@@ -440,7 +516,7 @@ rr_status Solve::begin() {
   } else {
     Epi e{};
     e.out = w.b;
-    launch_csc(h->X, rhs, EPI_STORE, e, nullptr, s);
+    launch_csc(w.X, rhs, EPI_STORE, e, nullptr, s);
   }
   Scalars& hs = *w.sc_host;
   std::memset(&hs, 0, sizeof(Scalars));
@@ -466,11 +542,11 @@ rr_status Solve::begin() {
   if (op.krylov == RR_KRYLOV_FCG) {
     if (two_level) {
       int nrz = 0;
-      RR_TRY(precond_two_level(h, pf, -1, kind, lam, omega, *sl, w.r, w.z, nullptr, &nrz, s));
+      RR_TRY(precond_two_level(h, w, pf, -1, kind, lam, omega, *sl, w.r, w.z, nullptr, &nrz, s));
     }
   } else if (two_level) {
     int nrz = 0;
-    RR_TRY(precond_two_level(h, pf, -1, kind, lam, omega, *sl, w.r, w.z, nullptr, &nrz, s));
+    RR_TRY(precond_two_level(h, w, pf, -1, kind, lam, omega, *sl, w.r, w.z, nullptr, &nrz, s));
     launch_pupdate(F, w.p, w.z, w.sc, w.parts.rz, nrz, 1, nullptr, s);
   } else {
     launch_pupdate(F, w.p, w.z, w.sc, w.parts.init + 2 * nv, nv, 1, nullptr, s);
@@ -479,7 +555,7 @@ rr_status Solve::begin() {
 }
 
 rr_status Solve::queue_chunk() {
-  Work& w = h->w;
+  Work& w = *ws;
   const int F = h->X.F;
   if (op.krylov == RR_KRYLOV_FCG) {
     // flexible CG (the paper's flexible-CG algorithm): direction i is z_i
@@ -494,7 +570,7 @@ rr_status Solve::queue_chunk() {
       if (i > 0) {
         if (two_level) {
           int nrz = 0;
-          RR_TRY(precond_two_level(h, pf, 100000000 + i - 1, kind, lam, omega, *sl, w.r, w.z,
+          RR_TRY(precond_two_level(h, w, pf, 100000000 + i - 1, kind, lam, omega, *sl, w.r, w.z,
                                    &stage, &nrz, s));
         }
         const int mi = std::max(1, i % (m + 1));
@@ -507,31 +583,31 @@ rr_status Solve::queue_chunk() {
         launch_fcg_dots(F, w.z, win, w.parts.dots, w.sc, two_level ? nullptr : &stage, s);
       }
       launch_fcg_dir(F, w.z, w.r, pi, win, w.parts.dots, w.fcg_paps, w.parts.rz, w.sc, s);
-      RR_TRY(op_csr(h, pf, i, pi, s));
-      Epi e = base_epi(h, lam);
+      RR_TRY(op_csr(h, w, pf, i, pi, s));
+      Epi e = base_epi(w, lam);
       e.p = pi;
       e.out = qi;
       e.partials = w.parts.pq;
       int npq = 0;
-      RR_TRY(op_csc(h, pf, i, EPI_APPLY_DOT, e, s, &npq));
+      RR_TRY(op_csc(h, w, pf, i, EPI_APPLY_DOT, e, s, &npq));
       launch_fcg_update(F, w.x, w.r, pi, qi, w.z, w.e1, w.D, xref, omega, kind, w.sc,
                         w.parts.pq, npq, w.parts.rz, w.fcg_paps, slot, w.parts.upd, s);
     }
     return RR_OK;
   }
   for (int c = 0; c < chunk; ++c, ++queued) {
-    RR_TRY(op_csr(h, pf, queued, w.p, s));
-    Epi e = base_epi(h, lam);
+    RR_TRY(op_csr(h, w, pf, queued, w.p, s));
+    Epi e = base_epi(w, lam);
     e.p = w.p;
     e.out = w.q;
     e.partials = w.parts.pq;
     int npq = 0;
-    RR_TRY(op_csc(h, pf, queued, EPI_APPLY_DOT, e, s, &npq));
+    RR_TRY(op_csc(h, w, pf, queued, EPI_APPLY_DOT, e, s, &npq));
     launch_pcg_update(F, w.x, w.r, w.p, w.q, w.z, w.e1, w.D, xref, omega, kind, w.sc,
                       w.parts.pq, npq, w.parts.upd, s);
     if (two_level) {
       int nrz = 0;
-      RR_TRY(precond_two_level(h, pf, 100000000 + queued, kind, lam, omega, *sl, w.r, w.z,
+      RR_TRY(precond_two_level(h, w, pf, 100000000 + queued, kind, lam, omega, *sl, w.r, w.z,
                                &stage, &nrz, s));
       launch_pupdate(F, w.p, w.z, w.sc, w.parts.rz, nrz, 0, nullptr, s);
     } else {
@@ -542,8 +618,8 @@ rr_status Solve::queue_chunk() {
 }
 
 rr_status Solve::poll() {
-  Scalars& hs = *h->w.sc_host;
-  RR_HIP(hipMemcpyAsync(&hs, h->w.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+  Scalars& hs = *ws->sc_host;
+  RR_HIP(hipMemcpyAsync(&hs, ws->sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
   RR_HIP(hipStreamSynchronize(s));
   RR_HIP(hipGetLastError());
   if (hs.done) {
@@ -556,19 +632,19 @@ rr_status Solve::poll() {
 }
 
 rr_status Solve::finish(rr_solve_info* info) {
-  Work& w = h->w;
+  Work& w = *ws;
   const int F = h->X.F;
   Scalars& hs = *w.sc_host;
   // exit: w = x and the true residual ||b - A x||
   launch_gather(wout, w.x, h->finv, F, s);
   {
-    launch_csr(h->X, w.x, w.u, nullptr, s);
-    Epi e = base_epi(h, lam);
+    launch_csr(w.X, w.x, w.u, nullptr, s);
+    Epi e = base_epi(w, lam);
     e.p = w.x;
     e.r = w.b;
     e.out = nullptr;
     e.partials = w.parts.tr;
-    const int ntr = launch_csc(h->X, w.u, EPI_TRUE, e, nullptr, s);
+    const int ntr = launch_csc(w.X, w.u, EPI_TRUE, e, nullptr, s);
     launch_finish_true(w.sc, w.parts.tr, ntr, s);
   }
   RR_HIP(hipMemcpyAsync(&hs, w.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
@@ -617,9 +693,9 @@ rr_status Solve::finish(rr_solve_info* info) {
       const hipEvent_t* ev = &h->ev_pool[3 * ti];
       float ms = 0.f;
       RR_HIP(hipEventRecord(ev[0], s));
-      for (int i = 0; i < kReps; ++i) launch_sell_gather(h->X.sell_csr, w.x, s);
+      for (int i = 0; i < kReps; ++i) launch_sell_gather(w.X.sell_csr, w.x, s);
       RR_HIP(hipEventRecord(ev[1], s));
-      for (int i = 0; i < kReps; ++i) launch_sell_gather(h->X.sell_csc, w.u, s);
+      for (int i = 0; i < kReps; ++i) launch_sell_gather(w.X.sell_csc, w.u, s);
       RR_HIP(hipEventRecord(ev[2], s));
       RR_HIP(hipEventSynchronize(ev[2]));
       RR_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
@@ -641,22 +717,28 @@ rr_status solve_impl(rr_handle* h, double lam, const double* rhs, double* wout,
                      const rr_solve_opts* o, rr_solve_info* info, hipStream_t s) {
   Solve sv;
   sv.h = h;
+  sv.ws = &h->w;
   sv.lam = lam;
   sv.rhs = rhs;
   sv.wout = wout;
   if (o) sv.op = *o;
   sv.s = s;
-  RR_TRY(sv.begin());
-  while (!sv.done) {
-    RR_TRY(sv.queue_chunk());
-    RR_TRY(sv.poll());
+  rr_status st = sv.begin();
+  while (st == RR_OK && !sv.done) {
+    st = sv.queue_chunk();
+    if (st == RR_OK) st = sv.poll();
   }
-  return sv.finish(info);
+  if (st == RR_OK) st = sv.finish(info);
+  sv.release();
+  return st;
 }
 
-// Problems on distinct handles run concurrently, each on its handle's own
-// stream, with their chunks queued round-robin; a handle that appears again
-// starts its next problem once its previous one has finished.
+// Problems run concurrently, each in its own work set (the k-th problem on
+// a handle in the k-th set) on that set's stream, with their iteration
+// chunks queued round-robin.  More than kMaxSets problems on one handle run
+// in later waves.
+constexpr int kMaxSets = 8;
+
 rr_status solve_batched_impl(int nprob, rr_handle* const* hs, const double* lams,
                              const double* const* rhs, double* const* ws, const rr_solve_opts* o,
                              rr_solve_info* infos, hipStream_t caller) {
@@ -667,72 +749,77 @@ rr_status solve_batched_impl(int nprob, rr_handle* const* hs, const double* lams
   if (o) op = *o;
   if (op.x_ref || op.residual_history)
     return fail(RR_ERR_INVALID_ARG, "x_ref and residual_history are per-problem buffers: use rr_solve");
+  op.profile = 0;
   for (int i = 0; i < nprob; ++i)
     if (!hs[i]) return fail(RR_ERR_INVALID_ARG, "null handle in batch");
-  // waves: each handle at most once per wave, in batch order
-  std::vector<int> wave(nprob, 0);
+  std::vector<int> wave(nprob, 0), set(nprob, 0);
   int nwaves = 0;
   for (int i = 0; i < nprob; ++i) {
     int k = 0;
-    for (int j = 0; j < i; ++j)
-      if (hs[j] == hs[i]) k = std::max(k, wave[j] + 1);
-    wave[i] = k;
-    nwaves = std::max(nwaves, k + 1);
+    for (int j = 0; j < i; ++j) k += (hs[j] == hs[i]);
+    wave[i] = k / kMaxSets;
+    set[i] = k % kMaxSets;
+    nwaves = std::max(nwaves, wave[i] + 1);
   }
-  hipEvent_t ev_in;
-  RR_HIP(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
-  RR_HIP(hipEventRecord(ev_in, caller));
+  hipEvent_t ev;
+  RR_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  RR_HIP(hipEventRecord(ev, caller));
   rr_status first_bad = RR_OK;
   for (int wv = 0; wv < nwaves; ++wv) {
-    std::vector<Solve> sv;
+    std::vector<std::unique_ptr<Solve>> sv;
     std::vector<int> idx;
     for (int i = 0; i < nprob; ++i) {
       if (wave[i] != wv) continue;
       rr_handle* h = hs[i];
-      if (!h->bstream) RR_HIP(hipStreamCreateWithFlags(&h->bstream, hipStreamNonBlocking));
-      RR_HIP(hipStreamWaitEvent(h->bstream, ev_in, 0));
-      Solve x;
-      x.h = h;
-      x.lam = lams[i];
-      x.rhs = rhs[i];
-      x.wout = ws[i];
-      x.op = op;
-      x.s = h->bstream;
-      sv.push_back(x);
+      Work* w = nullptr;
+      RR_TRY(get_work_set(h, set[i], &w));
+      hipStream_t* st = (set[i] == 0) ? &h->bstream : &w->stream;
+      if (!*st) RR_HIP(hipStreamCreateWithFlags(st, hipStreamNonBlocking));
+      RR_HIP(hipStreamWaitEvent(*st, ev, 0));
+      std::unique_ptr<Solve> x(new Solve());
+      x->h = h;
+      x->ws = w;
+      x->lam = lams[i];
+      x->rhs = rhs[i];
+      x->wout = ws[i];
+      x->op = op;
+      x->s = *st;
+      sv.push_back(std::move(x));
       idx.push_back(i);
     }
     std::vector<rr_status> st(sv.size(), RR_OK);
-    for (size_t j = 0; j < sv.size(); ++j) st[j] = sv[j].begin();
+    for (size_t j = 0; j < sv.size(); ++j) st[j] = sv[j]->begin();
     for (;;) {
       bool active = false;
       for (size_t j = 0; j < sv.size(); ++j)
-        if (st[j] == RR_OK && !sv[j].done) {
-          st[j] = sv[j].queue_chunk();
+        if (st[j] == RR_OK && !sv[j]->done) {
+          st[j] = sv[j]->queue_chunk();
           active = true;
         }
       if (!active) break;
       for (size_t j = 0; j < sv.size(); ++j)
-        if (st[j] == RR_OK && !sv[j].done) st[j] = sv[j].poll();
+        if (st[j] == RR_OK && !sv[j]->done) st[j] = sv[j]->poll();
     }
     for (size_t j = 0; j < sv.size(); ++j) {
       rr_solve_info inf{};
       if (st[j] == RR_OK) {
-        st[j] = sv[j].finish(&inf);
+        st[j] = sv[j]->finish(&inf);
       } else {
-        (void)hipStreamSynchronize(sv[j].s);
+        (void)hipStreamSynchronize(sv[j]->s);
         inf.status = st[j];
       }
+      sv[j]->release();
       if (infos) infos[idx[j]] = inf;
       if (st[j] != RR_OK && first_bad == RR_OK) first_bad = st[j];
     }
-    // the next wave's problems and the caller wait for this wave
+    // the next wave and the caller's later work wait for this wave
     for (size_t j = 0; j < sv.size(); ++j) {
-      RR_HIP(hipEventRecord(ev_in, sv[j].s));
-      RR_HIP(hipStreamWaitEvent(caller, ev_in, 0));
+      RR_HIP(hipEventRecord(ev, sv[j]->s));
+      RR_HIP(hipStreamWaitEvent(caller, ev, 0));
     }
-    RR_HIP(hipEventRecord(ev_in, caller));
+    RR_HIP(hipEventRecord(ev, caller));
   }
-  RR_HIP(hipEventDestroy(ev_in));
+  RR_HIP(hipEventDestroy(ev));
   return first_bad;
 }
 
@@ -836,7 +923,7 @@ rr_status rr_apply_operator(rr_handle* h, double lambda, const double* v, double
   const int F = h->X.F;
   launch_gather(w.vin, v, h->fperm, F, s);
   launch_csr(h->X, w.vin, w.u, nullptr, s);
-  Epi e = base_epi(h, lambda);
+  Epi e = base_epi(w, lambda);
   e.p = w.vin;
   e.out = w.vout;
   launch_csc(h->X, w.u, EPI_APPLY, e, nullptr, s);
@@ -889,7 +976,7 @@ rr_status rr_apply_precond(rr_handle* h, double lambda, int32_t precond, double 
   if (precond == PK_VCYCLE) k_smooth<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, w.vin, w.D, omega, w.e1);
   Prof pf;
   int nrz = 0;
-  RR_TRY(precond_two_level(h, pf, 0, precond, lambda, omega, *sl, w.vin, w.vout, nullptr, &nrz, s));
+  RR_TRY(precond_two_level(h, w, pf, 0, precond, lambda, omega, *sl, w.vin, w.vout, nullptr, &nrz, s));
   launch_gather(z, w.vout, h->finv, F, s);
   RR_HIP(hipStreamSynchronize(s));
   RR_HIP(hipGetLastError());

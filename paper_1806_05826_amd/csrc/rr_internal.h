@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <deque>
 #include <string>
 #include <vector>
 
@@ -149,6 +150,7 @@ struct LambdaSlot {
   double omega = 0.0;       // automatic smoother weight at this lambda
   bool valid = false;
   unsigned long long stamp = 0;
+  int in_use = 0;           // solves running with this factor (not evicted meanwhile)
 };
 
 struct Work {
@@ -165,6 +167,13 @@ struct Work {
   double *fcg_p = nullptr, *fcg_ap = nullptr, *fcg_paps = nullptr;   // [m F], [m F], [m]
   Scalars* sc = nullptr;
   Scalars* sc_host = nullptr;     // pinned mirror
+  // The matrix and restriction plans as this set sees them: the handle's
+  // plans with this set's own partial-sum buffers, so that solves on
+  // different sets of one handle can run at the same time.
+  Sparse X;
+  MergePlan rplan;
+  bool extra = false;             // an additional set (owns those buffers)
+  hipStream_t stream = nullptr;   // batched solves: this set's stream
 };
 
 }  // namespace rr
@@ -187,11 +196,14 @@ struct rr_handle {
   int* coff = nullptr;          // [FC+1] cluster offsets into perm
   rr::MergePlan restrict_plan;  // segments = clusters over perm
   double* K = nullptr;          // [FC*FC] coarse Gram
-  std::vector<rr::LambdaSlot> slots;
+  std::deque<rr::LambdaSlot> slots;
   unsigned long long stamp = 0;
   double* chol_work = nullptr;  // [FC*FC] scratch for the factorization
   int* chol_flag = nullptr;     // device int
-  rr::Work w;
+  rr::Work w;                     // work set 0
+  std::vector<rr::Work*> extra_sets;   // work sets 1, 2, ... for concurrent solves
+  int npartials = 0;
+  double* omega_tmp = nullptr;    // device scalar for the smoother weight
   double setup_ms = 0, kmeans_ms = 0;
   std::vector<hipEvent_t> ev_pool;
   hipStream_t bstream = nullptr;    // the handle's own stream for batched solves

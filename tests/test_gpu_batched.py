@@ -58,6 +58,23 @@ def test_batch_equals_single_solves(rr, handles, krylov_kind):
         assert infos[j]["true_relres"] == inf1["true_relres"]
 
 
+def test_many_lambdas_on_one_handle(rr, handles):
+    """Ten lambdas of one matrix: eight work sets in the first wave, two in
+    the second, each result bitwise its single solve."""
+    probs, Rs = handles
+    P, R = probs[1], Rs[1]
+    lams = list(np.logspace(-2, 2, 10))
+    y = dev(P.y)
+    ws = [torch.empty(P.X.shape[1], dtype=torch.float64, device="cuda") for _ in lams]
+    print("[batched] 10 lambdas on one handle", flush=True)
+    st, infos = rr.rr_solve_batched([R.h] * len(lams), lams, [y] * len(lams), ws, tol=1e-10,
+                                    precond="vcycle")
+    assert st == 0
+    for lam, w, inf in zip(lams, ws, infos):
+        w1, inf1 = R.solve(lam, P.y, precond="vcycle", tol=1e-10)
+        assert inf["iters"] == inf1["iters"] and np.array_equal(host(w), host(w1))
+
+
 def test_uneven_problems_match_oracle(rr):
     batch = datagen.batched_problems(6, seed=4, n_range=(500, 4000), d_range=(200, 1500))
     Rs, rhs, ws, lams = [], [], [], []
