@@ -130,6 +130,15 @@ rr_status rr_get_labels(const rr_handle* h, int32_t* labels, rr_stream stream);
 /* Copy the seeding centres in draw order (device int32[n_centres]). */
 rr_status rr_get_centres(const rr_handle* h, int32_t* centres, rr_stream stream);
 
+/* Arithmetic of rr_solve. */
+typedef enum {
+  RR_PREC_F64 = 0,         /* FP64 vectors, sums and scalars throughout          */
+  RR_PREC_F32_IR = 1       /* iterative refinement: r = b - A x and x in FP64;
+                              each correction A d = r by PCG with FP32 vectors
+                              and FP32 operator sums, FP64 scalars and FP64
+                              coarse solve (0/1 X; none / Jacobi / V(1,1))      */
+} rr_precision;
+
 /* Krylov method of rr_solve. */
 typedef enum {
   RR_KRYLOV_PCG = 0,       /* preconditioned CG (needs a fixed SPD preconditioner) */
@@ -160,6 +169,12 @@ typedef struct {
                               Direction i is orthogonalized against the
                               m_i = max(1, i mod (m+1)) previous ones (the
                               truncation of the paper's flexible-CG algorithm)  */
+  int32_t precision;       /* rr_precision: FP64 (default) or FP32 inner solves
+                              with FP64 iterative refinement                     */
+  double inner_tol;        /* refinement: relative residual of each inner solve;
+                              0 -> 1e-4.  tol then bounds the FP64 residual
+                              ||b - A x|| / ||b||, max_iter the inner iterations
+                              of each step (at most 40 steps)                    */
 } rr_solve_opts;
 
 typedef struct {
@@ -167,8 +182,9 @@ typedef struct {
   int32_t iters;           /* PCG iterations (x updates)                         */
   int32_t op_applies;      /* operator applications, b = X^T y and the exit
                               residual excluded                                  */
-  int32_t reserved;
-  double relres;           /* recursive ||r_k|| / ||b||                           */
+  int32_t ir_steps;        /* refinement steps (RR_PREC_F32_IR), else 0         */
+  double relres;           /* recursive ||r_k|| / ||b|| (refinement: the FP64
+                              residual ||b - A x|| / ||b||)                      */
   double true_relres;      /* ||b - A x_k|| / ||b||, recomputed at exit          */
   double err;              /* ||x_k - x_ref|| / ||x_ref|| when x_ref is given    */
   double omega;            /* smoother weight used                               */

@@ -31,6 +31,7 @@ RR_OK, RR_ERR_INVALID_ARG, RR_ERR_DEVICE = 0, 1, 2
 RR_ERR_NOT_CONVERGED, RR_ERR_BREAKDOWN, RR_ERR_UNSUPPORTED = 4, 5, 6
 PRECOND = {"none": 0, "jacobi": 1, "vcycle": 2, "additive": 3}
 KRYLOV = {"pcg": 0, "fcg": 1}
+PRECISION = {"f64": 0, "f32_ir": 1}
 
 
 class rr_csr(C.Structure):
@@ -55,12 +56,13 @@ class rr_solve_opts(C.Structure):
                 ("precond", C.c_int32), ("rhs_is_b", C.c_int32), ("omega", C.c_double),
                 ("x_ref", C.c_void_p), ("err_tol", C.c_double),
                 ("residual_history", C.c_void_p), ("chunk", C.c_int32), ("profile", C.c_int32),
-                ("krylov", C.c_int32), ("fcg_m", C.c_int32)]
+                ("krylov", C.c_int32), ("fcg_m", C.c_int32), ("precision", C.c_int32),
+                ("inner_tol", C.c_double)]
 
 
 class rr_solve_info(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("op_applies", C.c_int32),
-                ("reserved", C.c_int32), ("relres", C.c_double), ("true_relres", C.c_double),
+                ("ir_steps", C.c_int32), ("relres", C.c_double), ("true_relres", C.c_double),
                 ("err", C.c_double), ("omega", C.c_double), ("ms", C.c_double),
                 ("coarse_ms", C.c_double), ("csr_avg_ms", C.c_double),
                 ("csc_avg_ms", C.c_double), ("csr_launches", C.c_int32),
@@ -171,8 +173,8 @@ def rr_get_centres(h, centres, stream=None):
 
 def rr_solve(h, lam, rhs, w, tol=0.0, max_iter=0, fixed_iters=0, precond="vcycle",
              rhs_is_b=False, omega=0.0, x_ref=None, err_tol=0.0, residual_history=None,
-             chunk=0, profile=False, krylov="pcg", fcg_m=0, stream=None,
-             raise_on=(RR_ERR_INVALID_ARG, RR_ERR_DEVICE, RR_ERR_UNSUPPORTED)):
+             chunk=0, profile=False, krylov="pcg", fcg_m=0, precision="f64", inner_tol=0.0,
+             stream=None, raise_on=(RR_ERR_INVALID_ARG, RR_ERR_DEVICE, RR_ERR_UNSUPPORTED)):
     """Returns (status, info dict).  Statuses in `raise_on` raise RRError."""
     _dev_f64(rhs, None, "rhs")
     _dev_f64(w, None, "w")
@@ -180,7 +182,9 @@ def rr_solve(h, lam, rhs, w, tol=0.0, max_iter=0, fixed_iters=0, precond="vcycle
                       PRECOND[precond] if isinstance(precond, str) else int(precond),
                       1 if rhs_is_b else 0, float(omega), _ptr(x_ref), float(err_tol),
                       _ptr(residual_history), int(chunk), int(profile),
-                      KRYLOV[krylov] if isinstance(krylov, str) else int(krylov), int(fcg_m))
+                      KRYLOV[krylov] if isinstance(krylov, str) else int(krylov), int(fcg_m),
+                      PRECISION[precision] if isinstance(precision, str) else int(precision),
+                      float(inner_tol))
     info = rr_solve_info()
     st = _lib.rr_solve(C.c_void_p(h), float(lam), _ptr(rhs), _ptr(w), C.byref(o), C.byref(info),
                        _stream(stream))

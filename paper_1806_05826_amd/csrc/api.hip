@@ -76,6 +76,9 @@ void free_work(Work& w) {
   dfree(w.sc); dfree(w.D); dfree(w.vin); dfree(w.vout); dfree(w.xref);
   dfree(w.fcg_p); dfree(w.fcg_ap); dfree(w.fcg_paps);
   if (w.sc_host) (void)hipHostFree(w.sc_host);
+  IrVectors& f = w.f32;
+  dfree(f.x); dfree(f.r); dfree(f.p); dfree(f.q); dfree(f.z); dfree(f.e1); dfree(f.e2);
+  dfree(f.D); dfree(f.u); dfree(f.part_rows); dfree(f.part_cols);
   if (w.extra) {
     dfree(w.X.sell_csr.part); dfree(w.X.sell_csc.part);
     dfree(w.X.csc_plan.head); dfree(w.X.csc_plan.tail);
@@ -713,8 +716,214 @@ rr_status Solve::finish(rr_solve_info* info) {
   return RR_OK;
 }
 
+// ---- mixed precision: FP32 inner PCG inside FP64 iterative refinement ------
+
+rr_status ensure_f32(rr_handle* h, Work& w) {
+  IrVectors& f = w.f32;
+  if (f.x) return RR_OK;
+  const int F = h->X.F, N = h->X.N;
+  RR_TRY(dalloc(&f.x, F)); RR_TRY(dalloc(&f.r, F)); RR_TRY(dalloc(&f.p, F));
+  RR_TRY(dalloc(&f.q, F)); RR_TRY(dalloc(&f.z, F)); RR_TRY(dalloc(&f.e1, F));
+  RR_TRY(dalloc(&f.e2, F)); RR_TRY(dalloc(&f.D, F));
+  RR_TRY(dalloc(&f.u, N));
+  RR_TRY(dalloc(&f.part_rows, h->X.sell_csr.nout));
+  RR_TRY(dalloc(&f.part_cols, h->X.sell_csc.nout));
+  return RR_OK;
+}
+
+// z32 = B r32 (V(1,1), FP32 vectors, FP64 coarse solve); <r,z> partials in
+// parts.rz, their count in *n_rz.
+rr_status precond32(rr_handle* h, Work& w, double lam, double omega, const LambdaSlot& sl,
+                    const StageArgs* stage, int* n_rz, hipStream_t s) {
+  IrVectors& f = w.f32;
+  const int F = h->X.F;
+  const int* done = &w.sc->done;
+  Epi32 e{};
+  e.lam = lam;
+  e.out = f.u;
+  launch_sell32(w.X.sell_csr, f.part_rows, f.e1, EPI_STORE, e, done, s, stage);
+  Epi32 er{};
+  er.lam = lam;
+  er.p = f.e1;
+  er.r = f.r;
+  er.out64 = w.rho;
+  launch_sell32(w.X.sell_csc, f.part_cols, f.u, EPI_RESID, er, done, s);
+  Epi ec{};
+  ec.scale = h->cscale;
+  ec.out = w.c;
+  launch_segsum(w.rplan, h->coff + 1, h->perm, nullptr, w.rho, EPI_SCALE, ec, done, s);
+  launch_gemv(h->FC, sl.Ainv, w.c, w.yc, done, s);
+  launch_prolong32(F, h->labels, h->cscale, w.yc, f.e1, f.e2, done, s);
+  launch_sell32(w.X.sell_csr, f.part_rows, f.e2, EPI_STORE, e, done, s);
+  Epi32 ep{};
+  ep.lam = lam;
+  ep.omega = omega;
+  ep.p = f.e2;
+  ep.r = f.r;
+  ep.D = f.D;
+  ep.out = f.z;
+  ep.partials = w.parts.rz;
+  *n_rz = launch_sell32(w.X.sell_csc, f.part_cols, f.u, EPI_POST, ep, done, s);
+  return RR_OK;
+}
+
+rr_status solve_ir(rr_handle* h, Work& w, double lam, const double* rhs, double* wout,
+                   const rr_solve_opts& op, rr_solve_info* info, hipStream_t s) {
+  const double t0 = now_ms();
+  RR_TRY(check_lambda(lam, false));
+  if (!rhs || !wout) return fail(RR_ERR_INVALID_ARG, "null rhs or w");
+  if (!h->X.binary)
+    return fail(RR_ERR_UNSUPPORTED, "single-precision inner solves are built for 0/1 X only");
+  const int kind = op.precond;
+  if (kind != PK_NONE && kind != PK_JACOBI && kind != PK_VCYCLE)
+    return fail(RR_ERR_UNSUPPORTED, "iterative refinement supports the none, Jacobi and V(1,1) preconditioners");
+  if (kind == PK_VCYCLE && h->FC == 0)
+    return fail(RR_ERR_INVALID_ARG, "two-level preconditioner needs a coarse level (n_clusters > 0)");
+  if (op.krylov != RR_KRYLOV_PCG) return fail(RR_ERR_UNSUPPORTED, "iterative refinement runs PCG inner solves");
+  if (op.x_ref || op.residual_history || op.fixed_iters)
+    return fail(RR_ERR_INVALID_ARG, "x_ref, residual_history and fixed_iters are not used with refinement");
+  if (op.max_iter < 0 || op.chunk < 0 || op.tol < 0 || op.inner_tol < 0 || op.inner_tol >= 1)
+    return fail(RR_ERR_INVALID_ARG, "bad refinement option");
+  const double tol = op.tol > 0 ? op.tol : 1e-10;
+  const double inner_tol = op.inner_tol > 0 ? op.inner_tol : 1e-4;
+  const int max_inner = op.max_iter > 0 ? op.max_iter : 10000;
+  const int chunk = op.chunk > 0 ? op.chunk : 8;
+  constexpr int kMaxSteps = 40;
+  const int F = h->X.F;
+  LambdaSlot* sl = nullptr;
+  double coarse_ms = 0.0, omega = op.omega;
+  if (kind == PK_VCYCLE) {
+    RR_TRY(get_slot(h, lam, &sl, &coarse_ms, s));
+    if (omega == 0.0) omega = sl->omega;
+  }
+  if (!std::isfinite(omega) || omega < 0.0) return fail(RR_ERR_INVALID_ARG, "omega must be finite and >= 0");
+  RR_TRY(ensure_f32(h, w));
+  if (sl) sl->in_use++;
+  struct Unpin {
+    LambdaSlot* sl;
+    ~Unpin() { if (sl) sl->in_use--; }
+  } unpin{sl};
+  if (op.rhs_is_b) {
+    launch_gather(w.b, rhs, h->fperm, F, s);
+  } else {
+    Epi e{};
+    e.out = w.b;
+    launch_csc(w.X, rhs, EPI_STORE, e, nullptr, s);
+  }
+  // outer state: x = 0, r = b, ||b||^2 (FP64)
+  Scalars& hs = *w.sc_host;
+  std::memset(&hs, 0, sizeof(Scalars));
+  RR_HIP(hipMemcpyAsync(w.sc, &hs, sizeof(Scalars), hipMemcpyHostToDevice, s));
+  const int nv = w.parts.n_vec;
+  launch_colnorm_diag(F, h->colnorm, lam, w.D, s);
+  launch_pcg_init(F, w.b, w.x, w.r, w.p, w.z, w.e1, w.D, nullptr, 0.0, PK_NONE, w.parts.init, s);
+  launch_finish_init(w.sc, w.parts.init, nv, nullptr, PK_NONE, s);
+  RR_HIP(hipMemcpyAsync(&hs, w.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+  RR_HIP(hipStreamSynchronize(s));
+  const double bb = hs.bb;
+  int status = RR_ERR_NOT_CONVERGED, steps = 0, inner_total = 0;
+  double rr_true = bb;
+  if (!(bb > 0.0)) {
+    status = (bb == 0.0) ? RR_OK : RR_ERR_BREAKDOWN;
+    rr_true = 0.0;
+  }
+  IrVectors& f = w.f32;
+  StageArgs stage{w.sc, w.parts.upd, nv, nullptr, kind};
+  while (status == RR_ERR_NOT_CONVERGED && steps < kMaxSteps) {
+    // inner solve A d = r with FP32 vectors, to relative residual inner_tol
+    std::memset(&hs, 0, sizeof(Scalars));
+    hs.tol2 = inner_tol * inner_tol;
+    hs.limit = max_inner;
+    hs.status = RR_ERR_NOT_CONVERGED;
+    RR_HIP(hipMemcpyAsync(w.sc, &hs, sizeof(Scalars), hipMemcpyHostToDevice, s));
+    launch_ir_init(F, w.r, h->colnorm, lam, omega, kind, f, w.parts.init, s);
+    launch_finish_init(w.sc, w.parts.init, nv, nullptr, kind, s);
+    if (kind == PK_VCYCLE) {
+      int nrz = 0;
+      RR_TRY(precond32(h, w, lam, omega, *sl, nullptr, &nrz, s));
+      launch_ir_pupdate(F, f.p, f.z, w.sc, w.parts.rz, nrz, 1, nullptr, s);
+    } else {
+      launch_ir_pupdate(F, f.p, f.z, w.sc, w.parts.init + 2 * nv, nv, 1, nullptr, s);
+    }
+    int queued = 0;
+    for (;;) {
+      for (int c = 0; c < chunk; ++c, ++queued) {
+        const int* done = &w.sc->done;
+        Epi32 e{};
+        e.out = f.u;
+        launch_sell32(w.X.sell_csr, f.part_rows, f.p, EPI_STORE, e, done, s);
+        Epi32 eq{};
+        eq.lam = lam;
+        eq.p = f.p;
+        eq.out = f.q;
+        eq.partials = w.parts.pq;
+        const int npq = launch_sell32(w.X.sell_csc, f.part_cols, f.u, EPI_APPLY_DOT, eq, done, s);
+        launch_ir_update(F, f, omega, kind, w.sc, w.parts.pq, npq, w.parts.upd, s);
+        if (kind == PK_VCYCLE) {
+          int nrz = 0;
+          RR_TRY(precond32(h, w, lam, omega, *sl, &stage, &nrz, s));
+          launch_ir_pupdate(F, f.p, f.z, w.sc, w.parts.rz, nrz, 0, nullptr, s);
+        } else {
+          launch_ir_pupdate(F, f.p, f.z, w.sc, nullptr, 0, 0, &stage, s);
+        }
+      }
+      RR_HIP(hipMemcpyAsync(&hs, w.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+      RR_HIP(hipStreamSynchronize(s));
+      RR_HIP(hipGetLastError());
+      if (hs.done) break;
+      if (queued > hs.limit + 2 * chunk)
+        return fail(RR_ERR_DEVICE, "internal: iteration limit passed without the device finishing");
+    }
+    inner_total += hs.iter;
+    ++steps;
+    if (hs.status == RR_ERR_BREAKDOWN && hs.iter == 0) {
+      status = RR_ERR_BREAKDOWN;
+      break;
+    }
+    // x += d; r = b - A x in FP64, ||r||^2
+    launch_ir_accumulate(F, w.x, f.x, s);
+    launch_csr(w.X, w.x, w.u, nullptr, s);
+    Epi e = base_epi(w, lam);
+    e.p = w.x;
+    e.r = w.b;
+    e.out = w.r;
+    e.partials = w.parts.tr;
+    const int ntr = launch_csc(w.X, w.u, EPI_TRUE, e, nullptr, s);
+    launch_finish_true(w.sc, w.parts.tr, ntr, s);
+    RR_HIP(hipMemcpyAsync(&hs, w.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    RR_HIP(hipStreamSynchronize(s));
+    RR_HIP(hipGetLastError());
+    rr_true = hs.true_rr;
+    if (!(rr_true == rr_true)) {
+      status = RR_ERR_BREAKDOWN;
+      break;
+    }
+    if (rr_true <= tol * tol * bb) status = RR_OK;
+  }
+  launch_gather(wout, w.x, h->finv, F, s);
+  RR_HIP(hipStreamSynchronize(s));
+  RR_HIP(hipGetLastError());
+  rr_solve_info inf{};
+  inf.status = status;
+  inf.iters = inner_total;
+  inf.ir_steps = steps;
+  inf.op_applies = (kind == PK_VCYCLE ? 3 * inner_total : inner_total) + steps;
+  inf.relres = bb > 0 ? std::sqrt(rr_true / bb) : 0.0;
+  inf.true_relres = inf.relres;
+  inf.omega = omega;
+  inf.coarse_ms = coarse_ms;
+  inf.ms = now_ms() - t0;
+  if (info) *info = inf;
+  if (status == RR_ERR_NOT_CONVERGED)
+    return fail(RR_ERR_NOT_CONVERGED, "refinement steps exhausted before the tolerance");
+  if (status == RR_ERR_BREAKDOWN) return fail(RR_ERR_BREAKDOWN, "breakdown in refinement");
+  return RR_OK;
+}
+
 rr_status solve_impl(rr_handle* h, double lam, const double* rhs, double* wout,
                      const rr_solve_opts* o, rr_solve_info* info, hipStream_t s) {
+  if (o && o->precision == RR_PREC_F32_IR) return solve_ir(h, h->w, lam, rhs, wout, *o, info, s);
+  if (o && o->precision != RR_PREC_F64) return fail(RR_ERR_INVALID_ARG, "unknown precision");
   Solve sv;
   sv.h = h;
   sv.ws = &h->w;
@@ -749,6 +958,8 @@ rr_status solve_batched_impl(int nprob, rr_handle* const* hs, const double* lams
   if (o) op = *o;
   if (op.x_ref || op.residual_history)
     return fail(RR_ERR_INVALID_ARG, "x_ref and residual_history are per-problem buffers: use rr_solve");
+  if (op.precision != RR_PREC_F64)
+    return fail(RR_ERR_UNSUPPORTED, "batched solves run in FP64");
   op.profile = 0;
   for (int i = 0; i < nprob; ++i)
     if (!hs[i]) return fail(RR_ERR_INVALID_ARG, "null handle in batch");

@@ -98,6 +98,26 @@ struct Epi {
   double* history;
 };
 
+// Single-precision vectors of an inner solve of iterative refinement.
+struct IrVectors {
+  float *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr;
+  float *e1 = nullptr, *e2 = nullptr, *D = nullptr;   // [F]
+  float* u = nullptr;                                                  // [N]
+  float *part_rows = nullptr, *part_cols = nullptr;   // operator partial sums (sliced passes)
+};
+
+// Epilogue arguments of the single-precision column reduction.
+struct Epi32 {
+  double lam;
+  double omega;
+  const float* p;
+  const float* r;
+  const float* D;
+  float* out;
+  double* out64;      // EPI_RESID: FP64 result
+  double* partials;
+};
+
 // Merge-path plan of a segmented gather-sum out[s] = sum_{e in seg s} v[idx[e]].
 struct MergePlan {
   int nseg = 0, nnz = 0, nblocks = 0, nspan = 0;
@@ -173,6 +193,7 @@ struct Work {
   Sparse X;
   MergePlan rplan;
   bool extra = false;             // an additional set (owns those buffers)
+  IrVectors f32;                  // single-precision vectors, allocated on first use
   hipStream_t stream = nullptr;   // batched solves: this set's stream
 };
 
@@ -255,6 +276,10 @@ void free_sell(SellPlan& sp);
 int launch_sell(const SellPlan& sp, const double* v, int mode, const Epi& e, const int* done,
                 hipStream_t s, const StageArgs* stage = nullptr, hipEvent_t mid = nullptr);
 int sell_reduce_grid(int S);
+// Single-precision pass over v (float) with FP32 sums into `part` (float
+// [sp.nout], the caller's); returns the count of dot partials left.
+int launch_sell32(const SellPlan& sp, float* part, const float* v, int mode, const Epi32& e,
+                  const int* done, hipStream_t s, const StageArgs* stage = nullptr);
 // The gather kernel alone (partial sums only; no reduction, no epilogue).
 void launch_sell_gather(const SellPlan& sp, const double* v, hipStream_t s);
 // More than kMaxParts block partials are first added into partials[0] by one
@@ -294,6 +319,16 @@ void launch_prolong(int F, const int* labels, const double* cscale, const double
                     double omega, int additive, const Scalars* sc, double* parts_rz,
                     hipStream_t s);
 void launch_fill(double* x, double v, long long n, hipStream_t s);
+// ---- single-precision inner solves (mixed.hip) -------------------------------
+void launch_ir_init(int F, const double* r64, const double* colnorm, double lam, double omega,
+                    int kind, const IrVectors& v, double* parts, hipStream_t s);
+void launch_ir_update(int F, const IrVectors& v, double omega, int kind, Scalars* sc,
+                      const double* parts_pq, int n_pq, double* parts_upd, hipStream_t s);
+void launch_ir_pupdate(int F, float* p, const float* z, Scalars* sc, const double* parts_rz,
+                       int n_rz, int first, const StageArgs* stage, hipStream_t s);
+void launch_prolong32(int F, const int* labels, const double* cscale, const double* yc,
+                      const float* e1, float* e2, const int* done, hipStream_t s);
+void launch_ir_accumulate(int F, double* x, const float* d, hipStream_t s);
 // dst[i] = src[idx[i]]
 void launch_gather(double* dst, const double* src, const int* idx, int n, hipStream_t s);
 void launch_copy(double* dst, const double* src, long long n, hipStream_t s);

@@ -38,24 +38,27 @@ constexpr unsigned kEndFlag = 0x8000u;
 constexpr unsigned kLocalMask = 0x7fffu;
 
 // dst[0, W] = src[0, n) followed by zeros (n <= W = kSliceRows), with direct
-// global-to-LDS loads: at step k wave w moves the 128 entries starting at
-// (16 k + w) 128, 16 bytes per lane; the entries past the last whole pair
-// below n and the zero tail are written one by one.  The caller waits for
-// the loads (s_waitcnt) and synchronises the workgroup.
-static_assert(kSliceRows % (kSliceWaves * 128) == 0, "slice copy covers whole 1 KB rows");
-__device__ inline void fill_slice(double* dst, const double* __restrict__ src, int n) {
+// global-to-LDS loads: at step k wave w moves the 64 E entries starting at
+// (16 k + w) 64 E, 16 bytes (E entries) per lane; the entries past the last
+// whole E-group below n and the zero tail are written one by one.  The
+// caller waits for the loads (s_waitcnt) and synchronises the workgroup.
+template <typename T>
+__device__ inline void fill_slice(T* dst, const T* __restrict__ src, int n) {
+  constexpr int E = 16 / (int)sizeof(T);
+  constexpr int ROW = 64 * E;
+  static_assert(kSliceRows % (kSliceWaves * ROW) == 0, "slice copy covers whole 1 KB rows");
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nfull = n & ~1;
+  const int nfull = n - n % E;
 #pragma unroll
-  for (int k = 0; k < kSliceRows / (kSliceWaves * 128); ++k) {
-    const int e0 = (k * kSliceWaves + w) * 128;
-    if (e0 + 2 * lane < nfull)
+  for (int k = 0; k < kSliceRows / (kSliceWaves * ROW); ++k) {
+    const int e0 = (k * kSliceWaves + w) * ROW;
+    if (e0 + E * lane < nfull)
       __builtin_amdgcn_global_load_lds(
-          (const __attribute__((address_space(1))) void*)(src + e0 + 2 * lane),
+          (const __attribute__((address_space(1))) void*)(src + e0 + E * lane),
           (__attribute__((address_space(3))) void*)(dst + e0), 16, 0, 0);
   }
   for (int i = nfull + (int)threadIdx.x; i <= kSliceRows; i += kSliceBlock)
-    dst[i] = (i < n) ? src[i] : 0.0;
+    dst[i] = (i < n) ? src[i] : T(0);
 }
 
 // task.x: kind (0 lane task, 1 wave task); task.y: offset of its indexes
@@ -63,23 +66,20 @@ __device__ inline void fill_slice(double* dst, const double* __restrict__ src, i
 // length (longest lane stream; for wave tasks 16 x the 512-entry groups +
 // the 64-entry tail groups); task.w: first output position.  Wave w of workgroup b runs tasks [wrange[17 b + w],
 // wrange[17 b + w + 1]) of slice bslice[b].
-// PASS only names the instantiation (0: rows of X, 1: columns of X), so a
-// profiler reports the two operator passes apart.
-template <int PASS>
-__global__ __launch_bounds__(kSliceBlock) void k_sell(const int* __restrict__ wrange,
-                                                     const int* __restrict__ bslice,
-                                                     const int4* __restrict__ task,
-                                                     const uint16_t* __restrict__ idx,
-                                                     const double* __restrict__ v, int gdim,
-                                                     int W, double* __restrict__ out,
-                                                     const int* done, StageArgs stage) {
+// T is the type of the gathered vector, of the LDS slice and of the sums
+// (double, or float for the single-precision inner solves).
+template <typename T>
+__device__ inline void sell_body(const int* __restrict__ wrange, const int* __restrict__ bslice,
+                                 const int4* __restrict__ task, const uint16_t* __restrict__ idx,
+                                 const T* __restrict__ v, int gdim, int W, T* __restrict__ out,
+                                 const int* done, const StageArgs& stage) {
   if (is_done(done)) return;
   if (stage.sc) {   // convergence check of the preceding x/r update
     __shared__ double red_s[kSliceWaves];
     double rz_unused;
     if (stage_update<kSliceBlock>(stage, red_s, rz_unused)) return;
   }
-  __shared__ double vs[kSliceRows + 1];
+  __shared__ __align__(16) T vs[kSliceRows + 1];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int t0 = wrange[blockIdx.x * (kSliceWaves + 1) + w];
@@ -102,8 +102,8 @@ __global__ __launch_bounds__(kSliceBlock) void k_sell(const int* __restrict__ wr
     const int obase = __builtin_amdgcn_readlane(my.w, i);
     if (kind == 0) {
       const uint16_t* p = idx + base + lane;
-      double* o = out + obase + lane;
-      double acc = 0.0;
+      T* o = out + obase + lane;
+      T acc = T(0);
       int k = 0;
       for (; k + kLaneUnroll <= len; k += kLaneUnroll) {
         unsigned q[kLaneUnroll];
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kSliceBlock) void k_sell(const int* __restrict__ wr
           if (q[j] & kEndFlag) {
             *o = acc;
             o += 64;
-            acc = 0.0;
+            acc = T(0);
           }
         }
       }
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kSliceBlock) void k_sell(const int* __restrict__ wr
             if (q[j] & kEndFlag) {
               *o = acc;
               o += 64;
-              acc = 0.0;
+              acc = T(0);
             }
           }
         }
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(kSliceBlock) void k_sell(const int* __restrict__ wr
     } else {
       const uint4* p = reinterpret_cast<const uint4*>(idx) + base + lane;
       const int ng = len >> 4, nt = len & 15;
-      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      T acc[4] = {T(0), T(0), T(0), T(0)};
       int g = 0;
       for (; g + kWaveUnroll <= ng; g += kWaveUnroll) {
         uint4 q[kWaveUnroll];
@@ -181,12 +181,37 @@ __global__ __launch_bounds__(kSliceBlock) void k_sell(const int* __restrict__ wr
         for (int j = 0; j < 8; ++j)
           if (j < nt) acc[j & 3] += vs[q[j] & kLocalMask];
       }
-      double s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+      T s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
       if (lane == 0) out[obase] = s;
     }
   }
+}
+
+// PASS only names the instantiation (0: rows of X, 1: columns of X), so a
+// profiler reports the two operator passes apart.
+template <int PASS>
+__global__ __launch_bounds__(kSliceBlock) void k_sell(const int* __restrict__ wrange,
+                                                     const int* __restrict__ bslice,
+                                                     const int4* __restrict__ task,
+                                                     const uint16_t* __restrict__ idx,
+                                                     const double* __restrict__ v, int gdim,
+                                                     int W, double* __restrict__ out,
+                                                     const int* done, StageArgs stage) {
+  sell_body<double>(wrange, bslice, task, idx, v, gdim, W, out, done, stage);
+}
+
+// The same passes over single-precision vectors (FP32 sums).
+template <int PASS>
+__global__ __launch_bounds__(kSliceBlock) void k_sell32(const int* __restrict__ wrange,
+                                                       const int* __restrict__ bslice,
+                                                       const int4* __restrict__ task,
+                                                       const uint16_t* __restrict__ idx,
+                                                       const float* __restrict__ v, int gdim,
+                                                       int W, float* __restrict__ out,
+                                                       const int* done, StageArgs stage) {
+  sell_body<float>(wrange, bslice, task, idx, v, gdim, W, out, done, stage);
 }
 
 // segment s: t = sum of its partial sums in slice order, then the epilogue.
@@ -220,6 +245,86 @@ __global__ __launch_bounds__(kBlock) void k_sell_reduce(const double* __restrict
 }
 
 int sell_reduce_grid(int S) { return std::max(1, std::min(kMaxReduceBlocks, cdiv(S, kBlock))); }
+
+// Single-precision segment reduction: FP32 sums and epilogue, FP64 dot
+// products (modes EPI_STORE, EPI_APPLY_DOT, EPI_RESID, EPI_POST; EPI_RESID
+// stores its result widened to FP64 for the FP64 restriction).
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_sell_reduce32(const float* __restrict__ part,
+                                                         const int* __restrict__ pos,
+                                                         const int* __restrict__ sbase, int S,
+                                                         Epi32 e, const int* done) {
+  if (is_done(done)) return;
+  double dot = 0.0;
+  const float lam = (float)e.lam, omega = (float)e.omega;
+  for (int s = blockIdx.x * kBlock + threadIdx.x; s < S; s += gridDim.x * kBlock) {
+    const int a = sbase[s], z = sbase[s + 1];
+    float t = 0.0f;
+    for (int k0 = a; k0 < z; k0 += kReduceBatch) {
+      int pi[kReduceBatch];
+#pragma unroll
+      for (int j = 0; j < kReduceBatch; ++j) pi[j] = (k0 + j < z) ? pos[k0 + j] : -1;
+      float pv[kReduceBatch];
+#pragma unroll
+      for (int j = 0; j < kReduceBatch; ++j) pv[j] = (pi[j] >= 0) ? part[pi[j]] : 0.0f;
+#pragma unroll
+      for (int j = 0; j < kReduceBatch; ++j)
+        if (k0 + j < z) t += pv[j];
+    }
+    if constexpr (MODE == EPI_STORE) {
+      e.out[s] = t;
+    } else if constexpr (MODE == EPI_APPLY_DOT) {
+      const float ps = e.p[s];
+      const float q = t + lam * ps;
+      e.out[s] = q;
+      dot += (double)ps * (double)q;
+    } else if constexpr (MODE == EPI_RESID) {
+      e.out64[s] = (double)(e.r[s] - (t + lam * e.p[s]));
+    } else if constexpr (MODE == EPI_POST) {
+      const float e2 = e.p[s], rs = e.r[s];
+      const float rho = rs - (t + lam * e2);
+      const float zz = e2 + (omega * rho) / e.D[s];
+      e.out[s] = zz;
+      dot += (double)rs * (double)zz;
+    }
+  }
+  if constexpr (MODE == EPI_APPLY_DOT || MODE == EPI_POST)
+    store_block_partial<kBlock>(dot, e.partials, blockIdx.x);
+}
+
+int launch_sell32(const SellPlan& sp, float* part, const float* v, int mode, const Epi32& e,
+                  const int* done, hipStream_t s, const StageArgs* stage) {
+  StageArgs st{};
+  if (stage) st = *stage;
+  if (sp.nblk > 0) {
+    if (sp.pass == 0)
+      k_sell32<0><<<sp.nblk, kSliceBlock, 0, s>>>(sp.wrange, sp.bslice, sp.task, sp.idx, v, sp.gdim,
+                                                 sp.W, part, done, st);
+    else
+      k_sell32<1><<<sp.nblk, kSliceBlock, 0, s>>>(sp.wrange, sp.bslice, sp.task, sp.idx, v, sp.gdim,
+                                                 sp.W, part, done, st);
+  } else if (stage) {
+    launch_stage_update(*stage, s);
+  }
+  const int g = sell_reduce_grid(sp.S);
+  switch (mode) {
+    case EPI_STORE:
+      k_sell_reduce32<EPI_STORE><<<g, kBlock, 0, s>>>(part, sp.pos, sp.sbase, sp.S, e, done);
+      return 0;
+    case EPI_APPLY_DOT:
+      k_sell_reduce32<EPI_APPLY_DOT><<<g, kBlock, 0, s>>>(part, sp.pos, sp.sbase, sp.S, e, done);
+      break;
+    case EPI_RESID:
+      k_sell_reduce32<EPI_RESID><<<g, kBlock, 0, s>>>(part, sp.pos, sp.sbase, sp.S, e, done);
+      return 0;
+    case EPI_POST:
+      k_sell_reduce32<EPI_POST><<<g, kBlock, 0, s>>>(part, sp.pos, sp.sbase, sp.S, e, done);
+      break;
+    default:
+      return 0;
+  }
+  return collapse_parts(e.partials, g, done, s);
+}
 
 template <int MODE>
 static void sell_reduce_mode(const SellPlan& sp, const Epi& e, const int* done, hipStream_t s) {

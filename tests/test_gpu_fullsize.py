@@ -137,3 +137,22 @@ def test_fullsize_solve(rr, big, solver_random_labels, lam):
     assert inf_t.status == krylov.OK
     w, info = R.solve(lam, big.y, precond="vcycle", fixed_iters=inf_t.iters)
     assert np.linalg.norm(host(w) - x_t) <= 1e-10 * np.linalg.norm(x_t)
+
+
+@pytest.mark.parametrize("lam", [1e-2, 1.0, 100.0])
+def test_fullsize_mixed_precision(rr, big, solver_random_labels, lam):
+    """FP32 inner solves inside FP64 refinement reach the FP64 solution: the
+    reference is the oracle's PCG
+    (FP64, same aggregation; converged to 1e-14); the refined solution is
+    asserted within 1e-10 relative error of it."""
+    R, lab = solver_random_labels
+    fc = 1000
+    print(f"[fullsize] mixed precision lambda={lam}", flush=True)
+    x_ref, inf_ref = krylov.solve(big.X, big.y, lam, "vcycle", lab, fc, tol=1e-14, max_iter=3000)
+    assert inf_ref.status == krylov.OK
+    w, info = R.solve(lam, big.y, precond="vcycle", precision="f32_ir", tol=1e-13, max_iter=3000)
+    err = np.linalg.norm(host(w) - x_ref) / np.linalg.norm(x_ref)
+    print(f"[fullsize] mixed lambda={lam}: {info['ir_steps']} steps, {info['iters']} inner "
+          f"iterations, residual {info['relres']:.1e}, error {err:.1e}", flush=True)
+    assert info["status"] == 0 and info["ir_steps"] >= 2
+    assert err <= 1e-10
