@@ -63,7 +63,15 @@ typedef enum {
                               e2 = e1 + P A_c^-1 P^T rho1; rho2 = r - A e2;
                               z = e2 + w D^-1 rho2  (three operator applications
                               per PCG iteration, SPD for w rho(D^-1 A) < 2)      */
-  RR_PRECOND_ADDITIVE = 3  /* z = w D^-1 r + P A_c^-1 P^T r                      */
+  RR_PRECOND_ADDITIVE = 3, /* z = w D^-1 r + P A_c^-1 P^T r                      */
+  RR_PRECOND_LEARNED = 4   /* the VCYCLE cycle with its coarse solve replaced by
+                              the network: e2 = e1 + P (||r_c|| y), y its output
+                              for [r_c / ||r_c||, log lambda], r_c = P^T rho1
+                              (rr_mlp_init / rr_mlp_train); no coarse Cholesky
+                              is applied; nonlinear, so flexible CG only; after
+                              an iteration chunk that reduces ||r|| by less than
+                              10 % the solve continues with RR_PRECOND_VCYCLE
+                              (info.fallback_iter)                               */
 } rr_precond;
 
 typedef struct rr_handle rr_handle;
@@ -198,6 +206,9 @@ typedef struct {
                               (0/1 X; the whole pass for valued X); profile 2:
                               its back-to-back launch time                       */
   double csc_gather_avg_ms;/* profile: the same for the column pass              */
+  int32_t fallback_iter;   /* RR_PRECOND_LEARNED: iteration at which the solve
+                              fell back to the algebraic cycle, else -1          */
+  int32_t pad_;
 } rr_solve_info;
 
 /*
@@ -262,6 +273,66 @@ rr_status rr_smoother_weight(rr_handle* h, double lambda, double* omega);
 
 /* Message for the last non-OK status on this thread ("" if none). */
 const char* rr_last_error(void);
+
+/*
+ * ---- Learned coarse correction --------------------------------------------
+ * A three-layer perceptron: in = F_C + 1 inputs [r_c / ||r_c||, log lambda],
+ * two ReLU layers of `hidden` units, F_C outputs; the products run on the
+ * matrix cores in BF16 with FP32 accumulation, master weights and Adam state
+ * are FP32.  Parameters are handled as one FP32 array, row-major, in the order
+ * W1 [hidden, in], b1 [hidden], W2 [hidden, hidden], b2 [hidden],
+ * W3 [F_C, hidden], b3 [F_C].  None of this is in the paper; its flexible CG
+ * is what admits such a nonlinear preconditioner.
+ */
+typedef struct {
+  int32_t epochs;          /* passes over the pairs; 0 -> 20                       */
+  int32_t batch;           /* mini-batch size, 1..1024; 0 -> 256                   */
+  double lr;               /* Adam step size; 0 -> 1e-3                            */
+  uint64_t seed;           /* SplitMix64 seed of the per-epoch shuffles            */
+} rr_mlp_train_opts;
+
+/* Create (or re-create) the network of a handle with a coarse level:
+ * He-uniform weights (bound sqrt(6/fan_in), SplitMix64(seed) draws in
+ * parameter order), zero biases, fresh Adam state.  hidden in 16..1024. */
+rr_status rr_mlp_init(rr_handle* h, int32_t hidden, uint64_t seed);
+
+/* Sizes: parameter count, inputs, outputs. */
+rr_status rr_mlp_size(const rr_handle* h, int64_t* n_params, int32_t* n_in, int32_t* n_out);
+
+/* Copy the FP32 parameters from / to the host (n_params floats); setting
+ * also resets the Adam state. */
+rr_status rr_mlp_set_weights(rr_handle* h, const float* host_params);
+rr_status rr_mlp_get_weights(const rr_handle* h, float* host_params);
+
+/* out[b, :] = network(in[b, :]) for b < batch (device FP32 arrays [batch, in]
+ * and [batch, F_C]); any batch size. */
+rr_status rr_mlp_forward(rr_handle* h, const float* in, int32_t batch, float* out,
+                         rr_stream stream);
+
+/* Gradient of sum_b <dout[b], network(in[b])> with respect to the parameters
+ * (device FP32 grads[n_params]); batch 1..1024. */
+rr_status rr_mlp_backward(rr_handle* h, const float* in, const float* dout, int32_t batch,
+                          float* grads, rr_stream stream);
+
+/* Adam on the loss (1 / 2B) sum_b ||network(in[b]) - target[b]||^2 over
+ * shuffled mini-batches of the n pairs (device FP32 in [n, F_C + 1],
+ * target [n, F_C]).  loss_history (host, may be NULL) receives the mean loss
+ * of every epoch. */
+rr_status rr_mlp_train(rr_handle* h, const float* in, const float* target, int64_t n,
+                       const rr_mlp_train_opts* opts, float* loss_history, rr_stream stream);
+
+/* Training pairs generated by the solver: for each lambdas[i] (host) a V(1,1)
+ * PCG solve of (X^T X + lambda I) w = X^T y (device y[N]) records the coarse
+ * residual r_c = P^T rho1 that its cycle hands to the coarse solve, after
+ * every `every`-th iteration, up to pairs_per_solve of them; pair q gets input
+ * [r_c/||r_c||, log lambda] and target A_c(lambda)^-1 r_c / ||r_c|| (the
+ * algebraic coarse correction).
+ * inputs [n_solves * pairs_per_solve, F_C + 1] and targets [.., F_C] are
+ * device FP32; *n_pairs receives the count written (solves that converge
+ * early give fewer). */
+rr_status rr_collect_pairs(rr_handle* h, const double* lambdas, int32_t n_solves,
+                           int32_t pairs_per_solve, int32_t every, const double* y, float* inputs,
+                           float* targets, int64_t* n_pairs, rr_stream stream);
 
 #ifdef __cplusplus
 }

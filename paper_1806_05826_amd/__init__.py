@@ -29,7 +29,7 @@ _lib = C.CDLL(LIB_PATH)
 
 RR_OK, RR_ERR_INVALID_ARG, RR_ERR_DEVICE = 0, 1, 2
 RR_ERR_NOT_CONVERGED, RR_ERR_BREAKDOWN, RR_ERR_UNSUPPORTED = 4, 5, 6
-PRECOND = {"none": 0, "jacobi": 1, "vcycle": 2, "additive": 3}
+PRECOND = {"none": 0, "jacobi": 1, "vcycle": 2, "additive": 3, "learned": 4}
 KRYLOV = {"pcg": 0, "fcg": 1}
 PRECISION = {"f64": 0, "f32_ir": 1}
 
@@ -67,7 +67,8 @@ class rr_solve_info(C.Structure):
                 ("coarse_ms", C.c_double), ("csr_avg_ms", C.c_double),
                 ("csc_avg_ms", C.c_double), ("csr_launches", C.c_int32),
                 ("csc_launches", C.c_int32), ("csr_gather_avg_ms", C.c_double),
-                ("csc_gather_avg_ms", C.c_double)]
+                ("csc_gather_avg_ms", C.c_double), ("fallback_iter", C.c_int32),
+                ("pad_", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -79,6 +80,14 @@ _SIGS = {
     "rr_get_centres": [_P, _P, _P],
     "rr_solve": [_P, C.c_double, _P, _P, C.POINTER(rr_solve_opts), C.POINTER(rr_solve_info), _P],
     "rr_solve_batched": [C.c_int32, _P, _P, _P, _P, C.POINTER(rr_solve_opts), _P, _P],
+    "rr_mlp_init": [_P, C.c_int32, C.c_uint64],
+    "rr_mlp_size": [_P, _P, _P, _P],
+    "rr_mlp_set_weights": [_P, _P],
+    "rr_mlp_get_weights": [_P, _P],
+    "rr_mlp_forward": [_P, _P, C.c_int32, _P, _P],
+    "rr_mlp_backward": [_P, _P, _P, C.c_int32, _P, _P],
+    "rr_mlp_train": [_P, _P, _P, C.c_int64, _P, _P, _P],
+    "rr_collect_pairs": [_P, _P, C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, _P, _P],
     "rr_apply_operator": [_P, C.c_double, _P, _P, _P],
     "rr_apply_rhs": [_P, _P, _P, _P],
     "rr_apply_precond": [_P, C.c_double, C.c_int32, C.c_double, _P, _P, _P],
@@ -217,6 +226,80 @@ def rr_solve_batched(handles, lams, rhs, ws, tol=0.0, max_iter=0, fixed_iters=0,
     if st in raise_on:
         raise RRError(st, rr_last_error())
     return st, [{f: getattr(infos[i], f) for f, _ in rr_solve_info._fields_} for i in range(n)]
+
+
+class rr_mlp_train_opts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double),
+                ("seed", C.c_uint64)]
+
+
+def rr_mlp_init(h, hidden=256, seed=0):
+    _check(_lib.rr_mlp_init(C.c_void_p(h), int(hidden), C.c_uint64(seed)))
+
+
+def rr_mlp_size(h):
+    n, i, o = C.c_int64(), C.c_int32(), C.c_int32()
+    _check(_lib.rr_mlp_size(C.c_void_p(h), C.byref(n), C.byref(i), C.byref(o)))
+    return n.value, i.value, o.value
+
+
+def rr_mlp_set_weights(h, params):
+    import numpy as np
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    _check(_lib.rr_mlp_set_weights(C.c_void_p(h), a.ctypes.data_as(C.c_void_p)))
+
+
+def rr_mlp_get_weights(h):
+    import numpy as np
+    n, _, _ = rr_mlp_size(h)
+    a = np.empty(n, dtype=np.float32)
+    _check(_lib.rr_mlp_get_weights(C.c_void_p(h), a.ctypes.data_as(C.c_void_p)))
+    return a
+
+
+def _dev_f32(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32
+            and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+
+
+def rr_mlp_forward(h, inp, out, stream=None):
+    _dev_f32(inp, "in")
+    _dev_f32(out, "out")
+    _check(_lib.rr_mlp_forward(C.c_void_p(h), _ptr(inp), int(inp.shape[0]), _ptr(out), _stream(stream)))
+
+
+def rr_mlp_backward(h, inp, dout, grads, stream=None):
+    for t, nm in ((inp, "in"), (dout, "dout"), (grads, "grads")):
+        _dev_f32(t, nm)
+    _check(_lib.rr_mlp_backward(C.c_void_p(h), _ptr(inp), _ptr(dout), int(inp.shape[0]),
+                                _ptr(grads), _stream(stream)))
+
+
+def rr_mlp_train(h, inp, target, epochs=0, batch=0, lr=0.0, seed=0, stream=None):
+    """Returns the per-epoch mean loss (host list)."""
+    import numpy as np
+    _dev_f32(inp, "in")
+    _dev_f32(target, "target")
+    o = rr_mlp_train_opts(int(epochs), int(batch), float(lr), int(seed))
+    hist = np.zeros(max(1, epochs if epochs > 0 else 20), dtype=np.float32)
+    _check(_lib.rr_mlp_train(C.c_void_p(h), _ptr(inp), _ptr(target), C.c_int64(int(inp.shape[0])),
+                             C.byref(o), hist.ctypes.data_as(C.c_void_p), _stream(stream)))
+    return hist.tolist()
+
+
+def rr_collect_pairs(h, lams, pairs_per_solve, every, y, inputs, targets, stream=None):
+    """Returns the number of pairs written."""
+    _dev_f32(inputs, "inputs")
+    _dev_f32(targets, "targets")
+    _dev_f64(y, None, "y")
+    L = (C.c_double * max(1, len(lams)))(*[float(x) for x in lams])
+    n = C.c_int64()
+    _check(_lib.rr_collect_pairs(C.c_void_p(h), C.cast(L, C.c_void_p), len(lams), int(pairs_per_solve),
+                                 int(every), _ptr(y), _ptr(inputs), _ptr(targets), C.byref(n),
+                                 _stream(stream)))
+    return n.value
 
 
 def rr_apply_operator(h, lam, v, Av, stream=None):

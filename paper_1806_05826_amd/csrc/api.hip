@@ -165,7 +165,8 @@ void destroy_handle(rr_handle* h) {
   dfree(h->labels); dfree(h->centres); dfree(h->csize); dfree(h->cscale);
   dfree(h->perm); dfree(h->coff); dfree(h->K);
   for (auto& s : h->slots) { dfree(s.L); dfree(s.Ainv); }
-  dfree(h->chol_work); dfree(h->chol_flag); dfree(h->omega_tmp);
+  dfree(h->chol_work); dfree(h->chol_flag); dfree(h->omega_tmp); dfree(h->mlp_scale);
+  free_mlp(h->mlp);
   free_work(h->w);
   for (Work* w : h->extra_sets) {
     free_work(*w);
@@ -406,7 +407,8 @@ Epi base_epi(const Work& w, double lam) {
 // stage, the convergence check of the preceding update runs first.
 rr_status precond_two_level(rr_handle* h, Work& w, Prof& pf, int tag, int kind, double lam,
                             double omega, const LambdaSlot& sl, const double* r, double* z,
-                            const StageArgs* stage, int* n_rz, hipStream_t s) {
+                            const StageArgs* stage, int* n_rz, hipStream_t s,
+                            double* snap = nullptr) {
   const int F = h->X.F;
   const int* done = &w.sc->done;
   Epi er{};
@@ -428,9 +430,16 @@ rr_status precond_two_level(rr_handle* h, Work& w, Prof& pf, int tag, int kind, 
   e.r = r;
   e.out = w.rho;
   RR_TRY(op_csc(h, w, pf, tag, EPI_RESID, e, s));
-  // e2 = e1 + P A_c^-1 P^T rho1
+  // e2 = e1 + P A_c^-1 P^T rho1 (learned: the network's coarse correction)
   launch_segsum(w.rplan, h->coff + 1, h->perm, nullptr, w.rho, EPI_SCALE, er, done, s);
-  launch_gemv(h->FC, sl.Ainv, w.c, w.yc, done, s);
+  if (snap) launch_copy_done(snap, w.c, h->FC, done, s);
+  if (kind == PK_LEARNED) {
+    launch_learned_in(h->FC, w.c, lam, h->mlp.xb, h->mlp_scale, done, s);
+    mlp_forward(h->mlp, 1, s);
+    launch_learned_out(h->FC, h->mlp.y, h->mlp_scale, w.yc, done, s);
+  } else {
+    launch_gemv(h->FC, sl.Ainv, w.c, w.yc, done, s);
+  }
   launch_prolong(F, h->labels, h->cscale, w.yc, w.e1, w.e2, nullptr, nullptr, 0.0, 0, w.sc, nullptr, s);
   // z = e2 + w D^-1 (r - A e2), <r,z> -> beta
   RR_TRY(op_csr(h, w, pf, tag, w.e2, s));
@@ -463,6 +472,12 @@ struct Solve {
   const double* xref = nullptr;
   StageArgs stage{};
   Prof pf;
+  // coarse residual snapshots P^T r_k after every `snap_every`-th update
+  double* snap = nullptr;
+  int snap_every = 0, snap_max = 0, snap_queued = 0;
+  // learned coarse correction: switch to the algebraic cycle on a stall
+  double last_rr = -1.0;
+  int fallback_iter = -1;
 
   rr_status begin();
   rr_status queue_chunk();
@@ -479,9 +494,15 @@ rr_status Solve::begin() {
   RR_TRY(check_lambda(lam, false));
   if (!rhs || !wout) return fail(RR_ERR_INVALID_ARG, "null rhs or w");
   kind = op.precond;
-  if (kind < 0 || kind > 3) return fail(RR_ERR_INVALID_ARG, "unknown preconditioner");
-  if ((kind == PK_VCYCLE || kind == PK_ADDITIVE) && h->FC == 0)
+  if (kind < 0 || kind > 4) return fail(RR_ERR_INVALID_ARG, "unknown preconditioner");
+  if ((kind == PK_VCYCLE || kind == PK_ADDITIVE || kind == PK_LEARNED) && h->FC == 0)
     return fail(RR_ERR_INVALID_ARG, "two-level preconditioner needs a coarse level (n_clusters > 0)");
+  if (kind == PK_LEARNED) {
+    if (op.krylov != RR_KRYLOV_FCG)
+      return fail(RR_ERR_INVALID_ARG, "the learned coarse correction is nonlinear: use flexible CG");
+    if (!h->mlp.w || h->mlp.in != h->FC + 1 || h->mlp.out != h->FC)
+      return fail(RR_ERR_INVALID_ARG, "no network for this coarse level (rr_mlp_init)");
+  }
   if (op.fixed_iters < 0 || op.max_iter < 0 || op.chunk < 0 || op.tol < 0 || op.err_tol < 0)
     return fail(RR_ERR_INVALID_ARG, "negative option");
   if (op.krylov != RR_KRYLOV_PCG && op.krylov != RR_KRYLOV_FCG)
@@ -507,7 +528,7 @@ rr_status Solve::begin() {
     w.fcg_m = fcg_m;
   }
   omega = op.omega;
-  if (kind == PK_VCYCLE || kind == PK_ADDITIVE) {
+  if (kind == PK_VCYCLE || kind == PK_ADDITIVE || kind == PK_LEARNED) {
     RR_TRY(get_slot(h, lam, &sl, &coarse_ms, s));
     sl->in_use++;
     if (omega == 0.0) omega = sl->omega;
@@ -535,7 +556,7 @@ rr_status Solve::begin() {
     launch_gather(w.xref, op.x_ref, h->fperm, F, s);
     xref = w.xref;
   }
-  two_level = (kind == PK_VCYCLE || kind == PK_ADDITIVE);
+  two_level = (kind == PK_VCYCLE || kind == PK_ADDITIVE || kind == PK_LEARNED);
   const int nv = w.parts.n_vec;
   launch_pcg_init(F, w.b, w.x, w.r, w.p, w.z, w.e1, w.D, xref, omega, kind, w.parts.init, s);
   launch_finish_init(w.sc, w.parts.init, nv, op.residual_history, kind, s);
@@ -610,8 +631,11 @@ rr_status Solve::queue_chunk() {
                       w.parts.pq, npq, w.parts.upd, s);
     if (two_level) {
       int nrz = 0;
+      double* sp = nullptr;
+      if (snap && (queued + 1) % snap_every == 0 && snap_queued < snap_max)
+        sp = snap + (size_t)(snap_queued++) * h->FC;
       RR_TRY(precond_two_level(h, w, pf, 100000000 + queued, kind, lam, omega, *sl, w.r, w.z,
-                               &stage, &nrz, s));
+                               &stage, &nrz, s, sp));
       launch_pupdate(F, w.p, w.z, w.sc, w.parts.rz, nrz, 0, nullptr, s);
     } else {
       launch_pupdate(F, w.p, w.z, w.sc, nullptr, 0, 0, &stage, s);
@@ -628,6 +652,18 @@ rr_status Solve::poll() {
   if (hs.done) {
     done = true;
     return RR_OK;
+  }
+  if (kind == PK_LEARNED && hs.iter > 0) {
+    // a chunk that reduced ||r|| by less than 10 % counts as a stall: the
+    // rest of the solve uses the algebraic V(1,1) cycle (flexible CG takes a
+    // changing preconditioner), whose first smoother step is formed here
+    if (last_rr >= 0.0 && !(hs.rr < 0.81 * last_rr)) {
+      fallback_iter = hs.iter;
+      kind = PK_VCYCLE;
+      stage.kind = kind;
+      k_smooth<<<cdiv(h->X.F, kBlock), kBlock, 0, s>>>(h->X.F, ws->r, ws->D, omega, ws->e1);
+    }
+    last_rr = hs.rr;
   }
   if (queued > hs.limit + 2 * chunk)
     return fail(RR_ERR_DEVICE, "internal: iteration limit passed without the device finishing");
@@ -658,12 +694,13 @@ rr_status Solve::finish(rr_solve_info* info) {
   inf.iters = hs.iter;
   // the V-cycle's two applications after the last update are skipped; the
   // ones before the first iteration are not
-  inf.op_applies = (kind == PK_VCYCLE) ? 3 * hs.iter : hs.iter;
+  inf.op_applies = (kind == PK_VCYCLE || kind == PK_LEARNED) ? 3 * hs.iter : hs.iter;
   inf.relres = hs.bb > 0 ? std::sqrt(hs.rr / hs.bb) : 0.0;
   inf.true_relres = hs.bb > 0 ? std::sqrt(hs.true_rr / hs.bb) : 0.0;
   inf.err = hs.ref2 > 0 ? std::sqrt(hs.ee / hs.ref2) : 0.0;
   inf.omega = omega;
   inf.coarse_ms = coarse_ms;
+  inf.fallback_iter = fallback_iter;
   if (pf.on) {
     // count only launches that ran: iteration tags below the final count
     auto acc = [&](const std::vector<std::pair<int, int>>& v, double* avg, double* gavg, int* n) {
@@ -1214,6 +1251,207 @@ rr_status rr_coarse_factor(rr_handle* h, double lambda, double* L, double* Ainv,
   const size_t bytes = sizeof(double) * h->FC * h->FC;
   if (L) RR_HIP(hipMemcpyAsync(L, sl->L, bytes, hipMemcpyDeviceToDevice, s));
   if (Ainv) RR_HIP(hipMemcpyAsync(Ainv, sl->Ainv, bytes, hipMemcpyDeviceToDevice, s));
+  return RR_OK;
+}
+
+rr_status rr_mlp_init(rr_handle* h, int32_t hidden, uint64_t seed) {
+  RR_TRY(check_handle(h));
+  if (h->FC == 0) return fail(RR_ERR_INVALID_ARG, "no coarse level");
+  if (hidden < 16 || hidden > 1024) return fail(RR_ERR_INVALID_ARG, "hidden must be in [16, 1024]");
+  RR_HIP(hipDeviceSynchronize());
+  RR_TRY(mlp_alloc(h->mlp, h->FC + 1, hidden, h->FC, 1024));
+  if (!h->mlp_scale) RR_TRY(dalloc(&h->mlp_scale, 1));
+  size_t o[7];
+  h->mlp.offsets(o);
+  std::vector<float> p(h->mlp.nparam, 0.0f);
+  uint64_t st = seed;
+  const int fan_in[3] = {h->mlp.in, hidden, hidden};
+  for (int layer = 0; layer < 3; ++layer) {
+    const double bound = std::sqrt(6.0 / fan_in[layer]);
+    for (size_t i = o[2 * layer]; i < o[2 * layer + 1]; ++i) {
+      const double u = (double)(splitmix64_next(st) >> 11) * (1.0 / 9007199254740992.0);
+      p[i] = (float)((2.0 * u - 1.0) * bound);
+    }
+  }
+  return mlp_set(h->mlp, p.data(), nullptr);
+}
+
+rr_status rr_mlp_size(const rr_handle* h, int64_t* n_params, int32_t* n_in, int32_t* n_out) {
+  RR_TRY(check_handle(h));
+  if (!h->mlp.w) return fail(RR_ERR_INVALID_ARG, "no network (rr_mlp_init)");
+  if (n_params) *n_params = (int64_t)h->mlp.nparam;
+  if (n_in) *n_in = h->mlp.in;
+  if (n_out) *n_out = h->mlp.out;
+  return RR_OK;
+}
+
+rr_status rr_mlp_set_weights(rr_handle* h, const float* host_params) {
+  RR_TRY(check_handle(h));
+  if (!h->mlp.w) return fail(RR_ERR_INVALID_ARG, "no network (rr_mlp_init)");
+  if (!host_params) return fail(RR_ERR_INVALID_ARG, "null parameters");
+  return mlp_set(h->mlp, host_params, nullptr);
+}
+
+rr_status rr_mlp_get_weights(const rr_handle* h, float* host_params) {
+  RR_TRY(check_handle(h));
+  if (!h->mlp.w) return fail(RR_ERR_INVALID_ARG, "no network (rr_mlp_init)");
+  if (!host_params) return fail(RR_ERR_INVALID_ARG, "null parameters");
+  RR_HIP(hipDeviceSynchronize());
+  RR_HIP(hipMemcpy(host_params, h->mlp.w, sizeof(float) * h->mlp.nparam, hipMemcpyDeviceToHost));
+  return RR_OK;
+}
+
+rr_status rr_mlp_forward(rr_handle* h, const float* in, int32_t batch, float* out, rr_stream stream) {
+  RR_TRY(check_handle(h));
+  Mlp& n = h->mlp;
+  if (!n.w) return fail(RR_ERR_INVALID_ARG, "no network (rr_mlp_init)");
+  if (batch < 0 || (batch > 0 && (!in || !out))) return fail(RR_ERR_INVALID_ARG, "bad batch");
+  hipStream_t s = (hipStream_t)stream;
+  for (int b0 = 0; b0 < batch; b0 += n.max_batch) {
+    const int bn = std::min(n.max_batch, batch - b0);
+    mlp_load_inputs(n, in + (size_t)b0 * n.in, nullptr, bn, s);
+    mlp_forward(n, bn, s);
+    RR_HIP(hipMemcpyAsync(out + (size_t)b0 * n.out, n.y, sizeof(float) * (size_t)bn * n.out,
+                          hipMemcpyDeviceToDevice, s));
+  }
+  RR_HIP(hipGetLastError());
+  return RR_OK;
+}
+
+rr_status rr_mlp_backward(rr_handle* h, const float* in, const float* dout, int32_t batch,
+                          float* grads, rr_stream stream) {
+  RR_TRY(check_handle(h));
+  Mlp& n = h->mlp;
+  if (!n.w) return fail(RR_ERR_INVALID_ARG, "no network (rr_mlp_init)");
+  if (batch < 1 || batch > n.max_batch || !in || !dout || !grads)
+    return fail(RR_ERR_INVALID_ARG, "batch must be in [1, 1024] with non-null arrays");
+  hipStream_t s = (hipStream_t)stream;
+  mlp_load_inputs(n, in, nullptr, batch, s);
+  mlp_forward(n, batch, s);
+  mlp_set_dout(n, dout, batch, s);
+  mlp_backward(n, batch, s);
+  RR_HIP(hipMemcpyAsync(grads, n.g, sizeof(float) * n.nparam, hipMemcpyDeviceToDevice, s));
+  RR_HIP(hipGetLastError());
+  return RR_OK;
+}
+
+rr_status rr_mlp_train(rr_handle* h, const float* in, const float* target, int64_t npairs,
+                       const rr_mlp_train_opts* opts, float* loss_history, rr_stream stream) {
+  RR_TRY(check_handle(h));
+  Mlp& n = h->mlp;
+  if (!n.w) return fail(RR_ERR_INVALID_ARG, "no network (rr_mlp_init)");
+  if (npairs < 1 || !in || !target) return fail(RR_ERR_INVALID_ARG, "need n >= 1 pairs");
+  rr_mlp_train_opts o{};
+  if (opts) o = *opts;
+  const int epochs = o.epochs > 0 ? o.epochs : 20;
+  const int B = o.batch > 0 ? o.batch : 256;
+  if (B > n.max_batch || npairs > (1LL << 31) - 1)
+    return fail(RR_ERR_INVALID_ARG, "batch must be <= 1024 and n < 2^31");
+  const float lr = o.lr > 0 ? (float)o.lr : 1e-3f;
+  hipStream_t s = (hipStream_t)stream;
+  const int N = (int)npairs;
+  std::vector<int> order(N);
+  int* d_order = nullptr;
+  RR_TRY(dalloc(&d_order, N));
+  std::vector<float> err(n.max_batch);
+  uint64_t st = o.seed;
+  rr_status res = RR_OK;
+  for (int ep = 0; ep < epochs && res == RR_OK; ++ep) {
+    for (int i = 0; i < N; ++i) order[i] = i;
+    for (int i = N - 1; i > 0; --i) {   // Fisher-Yates with SplitMix64 draws
+      const int j = (int)(splitmix64_next(st) % (uint64_t)(i + 1));
+      std::swap(order[i], order[j]);
+    }
+    if (hipMemcpyAsync(d_order, order.data(), sizeof(int) * N, hipMemcpyHostToDevice, s) != hipSuccess) {
+      res = fail(RR_ERR_DEVICE, "hipMemcpyAsync");
+      break;
+    }
+    double tot = 0.0;
+    for (int b0 = 0; b0 < N; b0 += B) {
+      const int bn = std::min(B, N - b0);
+      mlp_load_inputs(n, in, d_order + b0, bn, s);
+      mlp_forward(n, bn, s);
+      mlp_loss_grad(n, target, d_order + b0, bn, s);
+      mlp_backward(n, bn, s);
+      mlp_adam(n, lr, s);
+      if (loss_history) {
+        if (hipMemcpyAsync(err.data(), n.err2, sizeof(float) * bn, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+          res = fail(RR_ERR_DEVICE, "loss readback");
+          break;
+        }
+        for (int i = 0; i < bn; ++i) tot += err[i];
+      }
+    }
+    if (loss_history) loss_history[ep] = (float)(0.5 * tot / N);
+  }
+  (void)hipStreamSynchronize(s);
+  dfree(d_order);
+  RR_TRY(res);
+  RR_HIP(hipGetLastError());
+  return RR_OK;
+}
+
+rr_status rr_collect_pairs(rr_handle* h, const double* lambdas, int32_t n_solves,
+                           int32_t pairs_per_solve, int32_t every, const double* y, float* inputs,
+                           float* targets, int64_t* n_pairs, rr_stream stream) {
+  RR_TRY(check_handle(h));
+  if (h->FC == 0) return fail(RR_ERR_INVALID_ARG, "no coarse level");
+  if (n_solves < 0 || pairs_per_solve < 1 || every < 1 || !lambdas || !y || !inputs || !targets)
+    return fail(RR_ERR_INVALID_ARG, "bad pair-collection arguments");
+  hipStream_t s = (hipStream_t)stream;
+  const int FC = h->FC;
+  double* snap = nullptr;
+  double* ainv_rc = nullptr;
+  RR_TRY(dalloc(&snap, (size_t)pairs_per_solve * FC));
+  RR_TRY(dalloc(&ainv_rc, (size_t)pairs_per_solve * FC));
+  double* wtmp = nullptr;
+  RR_TRY(dalloc(&wtmp, h->X.F));
+  int64_t written = 0;
+  rr_status res = RR_OK;
+  for (int i = 0; i < n_solves && res == RR_OK; ++i) {
+    Solve sv;
+    sv.h = h;
+    sv.ws = &h->w;
+    sv.lam = lambdas[i];
+    sv.rhs = y;
+    sv.wout = wtmp;
+    sv.op.precond = PK_VCYCLE;
+    sv.op.tol = 1e-10;
+    sv.op.max_iter = every * pairs_per_solve;
+    sv.s = s;
+    sv.snap = snap;
+    sv.snap_every = every;
+    sv.snap_max = pairs_per_solve;
+    res = sv.begin();
+    while (res == RR_OK && !sv.done) {
+      res = sv.queue_chunk();
+      if (res == RR_OK) res = sv.poll();
+    }
+    rr_solve_info inf{};
+    if (res == RR_OK) {
+      const rr_status fs = sv.finish(&inf);
+      if (fs != RR_OK && fs != RR_ERR_NOT_CONVERGED) res = fs;
+      g_last_error.clear();
+    }
+    if (res == RR_OK) {
+      // the cycle after the last update does not run: its snapshot is stale
+      const int valid = std::min(pairs_per_solve, std::max(0, inf.iters - 1) / every);
+      for (int q = 0; q < valid; ++q)
+        launch_gemv(FC, sv.sl->Ainv, snap + (size_t)q * FC, ainv_rc + (size_t)q * FC, nullptr, s);
+      launch_make_pairs(FC, valid, snap, ainv_rc, lambdas[i], inputs + (size_t)written * (FC + 1),
+                        targets + (size_t)written * FC, s);
+      written += valid;
+      if (hipStreamSynchronize(s) != hipSuccess) res = fail(RR_ERR_DEVICE, "pair construction");
+    }
+    sv.release();
+  }
+  (void)hipStreamSynchronize(s);
+  dfree(snap);
+  dfree(ainv_rc);
+  dfree(wtmp);
+  RR_TRY(res);
+  if (n_pairs) *n_pairs = written;
   return RR_OK;
 }
 

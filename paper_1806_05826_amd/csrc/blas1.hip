@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(int F, const double* __rest
     } else if (kind == PK_NONE) {
       z[j] = bj;
       v2 += bj * bj;
-    } else if (kind == PK_VCYCLE) {
+    } else if (kind == PK_VCYCLE || kind == PK_LEARNED) {
       e1[j] = (omega * bj) / D[j];
     }
   }
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(
     } else if (kind == PK_NONE) {
       z[j] = rj;
       v2 += rj * rj;
-    } else if (kind == PK_VCYCLE) {
+    } else if (kind == PK_VCYCLE || kind == PK_LEARNED) {
       e1[j] = (omega * rj) / D[j];
     }
   }
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_fcg_update(
       z[j] = rj / D[j];
     } else if (kind == PK_NONE) {
       z[j] = rj;
-    } else if (kind == PK_VCYCLE) {
+    } else if (kind == PK_VCYCLE || kind == PK_LEARNED) {
       e1[j] = (omega * rj) / D[j];
     }
   }
@@ -373,6 +373,17 @@ void launch_fcg_update(int F, double* x, double* r, const double* p, const doubl
   k_fcg_update<<<vec_grid(F), kBlock, 0, s>>>(F, x, r, p, q, z, e1, D, xref, omega, kind, sc,
                                               parts_pq, n_pq, parts_pr, vec_grid(F), paps, slot,
                                               parts_upd);
+}
+
+// dst = src unless the solve has finished
+__global__ void k_copy_done(double* __restrict__ dst, const double* __restrict__ src, int n,
+                            const int* done) {
+  if (is_done(done)) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+void launch_copy_done(double* dst, const double* src, int n, const int* done, hipStream_t s) {
+  if (n > 0) k_copy_done<<<cdiv(n, kBlock), kBlock, 0, s>>>(dst, src, n, done);
 }
 
 __global__ void k_fill(double* x, double v, long long n) {

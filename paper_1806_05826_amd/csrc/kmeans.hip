@@ -429,7 +429,7 @@ __global__ void k_offsets(const int* keys, int n, int nseg, int* off) {
 // ----------------------------------------------------------------------------
 // host side
 // ----------------------------------------------------------------------------
-static uint64_t splitmix64_next(uint64_t& state) {
+uint64_t splitmix64_next(uint64_t& state) {
   // SplitMix64 (Steele, Lea & Flood 2014)
   state += 0x9E3779B97F4A7C15ull;
   uint64_t z = state;

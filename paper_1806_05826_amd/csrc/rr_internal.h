@@ -106,6 +106,23 @@ struct IrVectors {
   float *part_rows = nullptr, *part_cols = nullptr;   // operator partial sums (sliced passes)
 };
 
+// The learned coarse correction's network (mlp.hip).
+struct Mlp {
+  int in = 0, hid = 0, out = 0, max_batch = 0, t = 0;
+  size_t nparam = 0;
+  float* w = nullptr;        // FP32 master parameters W1 b1 W2 b2 W3 b3
+  uint16_t* w16 = nullptr;   // BF16 copy (the products' operands)
+  float *m = nullptr, *v = nullptr, *g = nullptr;   // Adam moments, gradient
+  uint16_t* xb = nullptr;    // [max_batch, in] BF16 inputs
+  float *z1 = nullptr, *z2 = nullptr, *y = nullptr;          // pre-activations, output
+  uint16_t *a1 = nullptr, *a2 = nullptr;                     // BF16 activations
+  float *dy32 = nullptr, *dz2 = nullptr, *dz1 = nullptr;     // FP32 backward signals
+  uint16_t *dy16 = nullptr, *dz2b = nullptr, *dz1b = nullptr;
+  float* err2 = nullptr;     // per-row squared errors
+  int* rows = nullptr;       // mini-batch row indices
+  void offsets(size_t* o) const;   // o[0..6]: W1 b1 W2 b2 W3 b3 end
+};
+
 // Epilogue arguments of the single-precision column reduction.
 struct Epi32 {
   double lam;
@@ -221,6 +238,8 @@ struct rr_handle {
   unsigned long long stamp = 0;
   double* chol_work = nullptr;  // [FC*FC] scratch for the factorization
   int* chol_flag = nullptr;     // device int
+  rr::Mlp mlp;                    // learned coarse correction (rr_mlp_init)
+  double* mlp_scale = nullptr;    // device scalar ||P^T r|| of the learned correction
   rr::Work w;                     // work set 0
   std::vector<rr::Work*> extra_sets;   // work sets 1, 2, ... for concurrent solves
   int npartials = 0;
@@ -243,6 +262,8 @@ rr_status fail(rr_status st, const std::string& msg);
       return ::rr::fail(RR_ERR_DEVICE, std::string(#call) + ": " +          \
                                            hipGetErrorString(e_));           \
   } while (0)
+
+#define RR_HIP_VOID(call) (void)(call)
 
 #define RR_TRY(call)                                                         \
   do {                                                                       \
@@ -288,7 +309,7 @@ int collapse_parts(double* partials, int n, const int* done, hipStream_t s);
 rr_status validate_csr(const Sparse& X, hipStream_t s);
 
 // ---- vector kernels (blas1.hip) ---------------------------------------------
-enum PcgKind { PK_NONE = 0, PK_JACOBI = 1, PK_VCYCLE = 2, PK_ADDITIVE = 3 };
+enum PcgKind { PK_NONE = 0, PK_JACOBI = 1, PK_VCYCLE = 2, PK_ADDITIVE = 3, PK_LEARNED = 4 };
 int vec_grid(int F);   // blocks of the PCG vector kernels (<= kMaxParts)
 void launch_pcg_init(int F, const double* b, double* x, double* r, double* p, double* z,
                      double* e1, const double* D, const double* xref, double omega, int kind,
@@ -332,6 +353,7 @@ void launch_ir_accumulate(int F, double* x, const float* d, hipStream_t s);
 // dst[i] = src[idx[i]]
 void launch_gather(double* dst, const double* src, const int* idx, int n, hipStream_t s);
 void launch_copy(double* dst, const double* src, long long n, hipStream_t s);
+void launch_copy_done(double* dst, const double* src, int n, const int* done, hipStream_t s);
 void launch_colnorm_diag(int F, const double* colnorm, double lam, double* D, hipStream_t s);
 void launch_jacobi_apply(int F, const double* r, const double* D, double* z, hipStream_t s);
 void launch_omega_gersh(int F, const double* g, const double* colnorm, double lam,
@@ -339,10 +361,28 @@ void launch_omega_gersh(int F, const double* g, const double* colnorm, double la
 void launch_gemv(int n, const double* A, const double* x, double* y, const int* done,
                  hipStream_t s);
 
+// ---- learned coarse correction (mlp.hip) -------------------------------------
+void free_mlp(Mlp& n);
+rr_status mlp_alloc(Mlp& n, int in, int hid, int out, int max_batch);
+rr_status mlp_set(Mlp& n, const float* host, hipStream_t s);
+void mlp_load_inputs(Mlp& n, const float* X, const int* rows, int Bn, hipStream_t s);
+void mlp_forward(Mlp& n, int Bn, hipStream_t s);
+void mlp_set_dout(Mlp& n, const float* dY, int Bn, hipStream_t s);
+void mlp_loss_grad(Mlp& n, const float* T, const int* rows, int Bn, hipStream_t s);
+void mlp_backward(Mlp& n, int Bn, hipStream_t s);
+void mlp_adam(Mlp& n, float lr, hipStream_t s);
+void launch_learned_in(int FC, const double* c, double lam, uint16_t* xb, double* scale,
+                       const int* done, hipStream_t s);
+void launch_learned_out(int FC, const float* y, const double* scale, double* yc, const int* done,
+                        hipStream_t s);
+void launch_make_pairs(int FC, int npairs, const double* S, const double* Ainv_rc, double lam,
+                       float* inputs, float* targets, hipStream_t s);
+
 // ---- coarse level (coarse.hip) ---------------------------------------------
 rr_status coarse_factor(rr_handle* h, double lam, LambdaSlot& slot, hipStream_t s);
 
 // ---- clustering (kmeans.hip) -----------------------------------------------
+uint64_t splitmix64_next(uint64_t& state);   // SplitMix64 (Steele, Lea & Flood)
 rr_status run_kmeans(rr_handle* h, int k, uint64_t seed, int max_iter, hipStream_t s);
 rr_status set_labels(rr_handle* h, const int* labels_in, int nlab, hipStream_t s);
 rr_status build_coarse_gram(rr_handle* h, hipStream_t s);
