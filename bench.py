@@ -260,6 +260,38 @@ def main():
     mixed["ms_per_step"] = (time.perf_counter() - ta) * 1e3 / 3
     mixed["vs_plain"] = ms_per_step / mixed["ms_per_step"]
 
+    # learned coarse correction (lambda = 1): pairs from V(1,1) solves at
+    # lambda log-uniform in [0.3, 3], Adam on the BF16 network, then flexible
+    # CG with the network against V(1,1) PCG, both to relative residual 1e-10
+    learned = {}
+    fc = sinfo["n_coarse"]
+    llams = list(np.exp(np.random.default_rng(2).uniform(np.log(0.3), np.log(3.0), 64)))
+    per = 40
+    inp = torch.empty((len(llams) * per, fc + 1), dtype=torch.float32, device=dev)
+    tgt = torch.empty((len(llams) * per, fc), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    npairs = rr.rr_collect_pairs(R.h, llams, per, 1, y, inp, tgt)
+    torch.cuda.synchronize()
+    learned["collect_s"] = time.perf_counter() - ta
+    rr.rr_mlp_init(R.h, hidden=256, seed=11)
+    ta = time.perf_counter()
+    hist = rr.rr_mlp_train(R.h, inp[:npairs].contiguous(), tgt[:npairs].contiguous(), epochs=60,
+                           batch=256, lr=1e-3, seed=5)
+    torch.cuda.synchronize()
+    learned.update({"pairs": npairs, "train_s": time.perf_counter() - ta, "epochs": 60,
+                    "loss_first": hist[0], "loss_last": hist[-1]})
+    for name, kw in (("learned_fcg", dict(precond="learned", krylov="fcg", fcg_m=4)),
+                     ("vcycle_pcg", dict(precond="vcycle")),
+                     ("jacobi_fcg", dict(precond="jacobi", krylov="fcg", fcg_m=4))):
+        st, inf = rr.rr_solve(R.h, 1.0, y, w, tol=1e-10, max_iter=5000, chunk=8, raise_on=(1, 2, 6), **kw)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        st, inf = rr.rr_solve(R.h, 1.0, y, w, tol=1e-10, max_iter=5000, chunk=8, raise_on=(1, 2, 6), **kw)
+        torch.cuda.synchronize()
+        learned[name] = {"iters": inf["iters"], "ms": (time.perf_counter() - ta) * 1e3,
+                         "true_relres": inf["true_relres"], "fallback_iter": inf["fallback_iter"]}
+
     total_iters = sum(calib[l]["iters"] for l in lams)
     cpu = None
     if not args.no_cpu:
@@ -300,6 +332,7 @@ def main():
         "compare_lambda1": compare,
         "batched_lambdas": batched,
         "mixed_precision": mixed,
+        "learned": learned,
         "roofline": {"bound": "hbm", "achieved": gbs_gather, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs_gather / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "rr::k_sell<1> (column-pass gather of t = X^T u through LDS slices)",
