@@ -179,6 +179,10 @@ typedef struct {
                               truncation of the paper's flexible-CG algorithm)  */
   int32_t precision;       /* rr_precision: FP64 (default) or FP32 inner solves
                               with FP64 iterative refinement                     */
+  int32_t graph;           /* 1: PCG iterations are captured once per chunk
+                              signature into a HIP graph and replayed (the
+                              chunk's launches do not change between chunks);
+                              ignored with profile, flexible CG and refinement  */
   double inner_tol;        /* refinement: relative residual of each inner solve;
                               0 -> 1e-4.  tol then bounds the FP64 residual
                               ||b - A x|| / ||b||, max_iter the inner iterations

@@ -57,7 +57,7 @@ class rr_solve_opts(C.Structure):
                 ("x_ref", C.c_void_p), ("err_tol", C.c_double),
                 ("residual_history", C.c_void_p), ("chunk", C.c_int32), ("profile", C.c_int32),
                 ("krylov", C.c_int32), ("fcg_m", C.c_int32), ("precision", C.c_int32),
-                ("inner_tol", C.c_double)]
+                ("graph", C.c_int32), ("inner_tol", C.c_double)]
 
 
 class rr_solve_info(C.Structure):
@@ -183,7 +183,8 @@ def rr_get_centres(h, centres, stream=None):
 def rr_solve(h, lam, rhs, w, tol=0.0, max_iter=0, fixed_iters=0, precond="vcycle",
              rhs_is_b=False, omega=0.0, x_ref=None, err_tol=0.0, residual_history=None,
              chunk=0, profile=False, krylov="pcg", fcg_m=0, precision="f64", inner_tol=0.0,
-             stream=None, raise_on=(RR_ERR_INVALID_ARG, RR_ERR_DEVICE, RR_ERR_UNSUPPORTED)):
+             graph=False, stream=None,
+             raise_on=(RR_ERR_INVALID_ARG, RR_ERR_DEVICE, RR_ERR_UNSUPPORTED)):
     """Returns (status, info dict).  Statuses in `raise_on` raise RRError."""
     _dev_f64(rhs, None, "rhs")
     _dev_f64(w, None, "w")
@@ -193,7 +194,7 @@ def rr_solve(h, lam, rhs, w, tol=0.0, max_iter=0, fixed_iters=0, precond="vcycle
                       _ptr(residual_history), int(chunk), int(profile),
                       KRYLOV[krylov] if isinstance(krylov, str) else int(krylov), int(fcg_m),
                       PRECISION[precision] if isinstance(precision, str) else int(precision),
-                      float(inner_tol))
+                      1 if graph else 0, float(inner_tol))
     info = rr_solve_info()
     st = _lib.rr_solve(C.c_void_p(h), float(lam), _ptr(rhs), _ptr(w), C.byref(o), C.byref(info),
                        _stream(stream))
@@ -218,7 +219,8 @@ def rr_solve_batched(handles, lams, rhs, ws, tol=0.0, max_iter=0, fixed_iters=0,
     o = rr_solve_opts(float(tol), int(max_iter), int(fixed_iters),
                       PRECOND[precond] if isinstance(precond, str) else int(precond),
                       1 if rhs_is_b else 0, float(omega), None, 0.0, None, int(chunk), 0,
-                      KRYLOV[krylov] if isinstance(krylov, str) else int(krylov), int(fcg_m))
+                      KRYLOV[krylov] if isinstance(krylov, str) else int(krylov), int(fcg_m),
+                      0, 0, 0.0)
     infos = (rr_solve_info * max(n, 1))()
     st = _lib.rr_solve_batched(C.c_int32(n), C.cast(H, C.c_void_p), C.cast(L, C.c_void_p),
                                C.cast(Rp, C.c_void_p), C.cast(Wp, C.c_void_p), C.byref(o),

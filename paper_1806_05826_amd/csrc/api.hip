@@ -84,6 +84,8 @@ void free_work(Work& w) {
     dfree(w.X.csc_plan.head); dfree(w.X.csc_plan.tail);
     dfree(w.rplan.head); dfree(w.rplan.tail);
   }
+  w.graph.reset();
+  if (w.graph.ev) (void)hipEventDestroy(w.graph.ev);
   if (w.stream) (void)hipStreamDestroy(w.stream);
   w = Work{};
 }
@@ -481,6 +483,7 @@ struct Solve {
 
   rr_status begin();
   rr_status queue_chunk();
+  rr_status queue_chunk_eager(Work& w, int F);
   rr_status poll();
   rr_status finish(rr_solve_info* info);
   void release() {
@@ -619,6 +622,54 @@ rr_status Solve::queue_chunk() {
     }
     return RR_OK;
   }
+  if (op.graph && !pf.on && !snap) {
+    // the chunk's launches are the same for every chunk of this solve (all
+    // changing state lives in device memory): capture them once per
+    // signature, then replay
+    GraphKey key{kind, lam, omega, sl ? sl->Ainv : nullptr, xref, op.residual_history, chunk};
+    // the legacy default stream cannot be captured: use the set's own
+    // stream, ordered after and before the caller's with events
+    hipStream_t gs = s;
+    if (!s) {
+      if (!w.stream) RR_HIP(hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking));
+      if (!w.graph.ev) RR_HIP(hipEventCreateWithFlags(&w.graph.ev, hipEventDisableTiming));
+      gs = w.stream;
+    }
+    if (!w.graph.exec || !(w.graph.key == key)) {
+      w.graph.reset();
+      const hipStream_t saved = s;
+      s = gs;
+      RR_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+      rr_status cs = queue_chunk_eager(w, F);
+      s = saved;
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(gs, &g);
+      if (cs != RR_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return cs;
+      }
+      RR_HIP(e);
+      w.graph.graph = g;
+      RR_HIP(hipGraphInstantiate(&w.graph.exec, g, nullptr, nullptr, 0));
+      w.graph.key = key;
+      queued -= chunk;   // the captured launches did not run
+    }
+    if (gs != s) {
+      RR_HIP(hipEventRecord(w.graph.ev, s));
+      RR_HIP(hipStreamWaitEvent(gs, w.graph.ev, 0));
+    }
+    RR_HIP(hipGraphLaunch(w.graph.exec, gs));
+    if (gs != s) {
+      RR_HIP(hipEventRecord(w.graph.ev, gs));
+      RR_HIP(hipStreamWaitEvent(s, w.graph.ev, 0));
+    }
+    queued += chunk;
+    return RR_OK;
+  }
+  return queue_chunk_eager(w, F);
+}
+
+rr_status Solve::queue_chunk_eager(Work& w, int F) {
   for (int c = 0; c < chunk; ++c, ++queued) {
     RR_TRY(op_csr(h, w, pf, queued, w.p, s));
     Epi e = base_epi(w, lam);

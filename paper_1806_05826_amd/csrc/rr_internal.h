@@ -190,6 +190,33 @@ struct LambdaSlot {
   int in_use = 0;           // solves running with this factor (not evicted meanwhile)
 };
 
+// A captured chunk of PCG iterations and what its launches depend on.
+struct GraphKey {
+  int kind = -1;
+  double lam = 0.0, omega = 0.0;
+  const double* ainv = nullptr;
+  const double* xref = nullptr;
+  const double* history = nullptr;
+  int chunk = 0;
+  bool operator==(const GraphKey& o) const {
+    return kind == o.kind && lam == o.lam && omega == o.omega && ainv == o.ainv &&
+           xref == o.xref && history == o.history && chunk == o.chunk;
+  }
+};
+struct ChunkGraph {
+  GraphKey key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev = nullptr;        // orders replays on the set's stream with the caller's
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    key = GraphKey{};
+  }
+};
+
 struct Work {
   double *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr;
   double *e1 = nullptr, *e2 = nullptr, *rho = nullptr, *b = nullptr;
@@ -211,6 +238,7 @@ struct Work {
   MergePlan rplan;
   bool extra = false;             // an additional set (owns those buffers)
   IrVectors f32;                  // single-precision vectors, allocated on first use
+  ChunkGraph graph;               // captured PCG chunk (rr_solve_opts.graph)
   hipStream_t stream = nullptr;   // batched solves: this set's stream
 };
 
