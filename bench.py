@@ -123,7 +123,7 @@ def main():
     lams = [1e-2, 1.0, 100.0]
     print(f"[bench] data {N}x{F} nnz={nnz}", file=sys.stderr, flush=True)
 
-    R = rr.Ridge(P.X, n_clusters=args.k, seed=5826, lambda_slots=4)
+    R = rr.Ridge(P.X, n_clusters=args.k, seed=5826, lambda_slots=4, autotune=True)
     sinfo = R.info
     print(f"[bench] setup {sinfo['setup_ms']:.0f} ms (k-means {sinfo['kmeans_ms']:.0f} ms, "
           f"{sinfo['kmeans_iters']} Lloyd passes), F_C={sinfo['n_coarse']}", file=sys.stderr, flush=True)
@@ -324,6 +324,8 @@ def main():
                                 "err": calib[l]["err"], "coarse_factor_ms": calib[l]["coarse_ms"]}
                        for l in lams},
         "setup_ms": sinfo["setup_ms"],
+        "autotune": {"plan_ms": sinfo["plan_ms"], "rows_div": sinfo["tuned_rows_div"],
+                     "cols_div": sinfo["tuned_cols_div"], "cached": sinfo["tune_cached"]},
         "kmeans_ms": sinfo["kmeans_ms"],
         "kmeans_passes": sinfo["kmeans_iters"],
         "operator": {"apply_bytes": b_apply, "apply_ms": csr_ms + csc_ms, "apply_gbs": gbs_op,

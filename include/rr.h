@@ -99,6 +99,10 @@ typedef struct {
                               in increasing order                              */
   int32_t n_labels_in;
   int32_t lambda_slots;    /* coarse factors cached per handle; 0 -> 4          */
+  int32_t autotune;        /* 0/1 X: 1 chooses each sliced pass's lane-stream
+                              length among three candidates by timing them on
+                              this device, cached per device and shape bucket
+                              (log2 of N, F, nnz) for the life of the process  */
 } rr_setup_opts;
 
 /*
@@ -127,6 +131,11 @@ typedef struct {
   int32_t binary;          /* 1 when X was given without values               */
   double setup_ms;         /* wall time of rr_setup                            */
   double kmeans_ms;        /* of which clustering                              */
+  double plan_ms;          /* of which building (and tuning) the sliced plans  */
+  int32_t tuned_rows_div;  /* lane-stream divisors used by the two passes      */
+  int32_t tuned_cols_div;
+  int32_t tune_cached;     /* 1: autotune reused an earlier measurement        */
+  int32_t pad_;
 } rr_setup_info;
 
 /* Host-side facts about a handle. */

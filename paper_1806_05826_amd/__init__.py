@@ -42,13 +42,15 @@ class rr_csr(C.Structure):
 class rr_setup_opts(C.Structure):
     _fields_ = [("n_clusters", C.c_int32), ("kmeans_max_iter", C.c_int32),
                 ("seed", C.c_uint64), ("labels_in", C.c_void_p), ("n_labels_in", C.c_int32),
-                ("lambda_slots", C.c_int32)]
+                ("lambda_slots", C.c_int32), ("autotune", C.c_int32)]
 
 
 class rr_setup_info(C.Structure):
     _fields_ = [("n_rows", C.c_int64), ("n_cols", C.c_int64), ("nnz", C.c_int64),
                 ("n_coarse", C.c_int32), ("n_centres", C.c_int32), ("kmeans_iters", C.c_int32),
-                ("binary", C.c_int32), ("setup_ms", C.c_double), ("kmeans_ms", C.c_double)]
+                ("binary", C.c_int32), ("setup_ms", C.c_double), ("kmeans_ms", C.c_double),
+                ("plan_ms", C.c_double), ("tuned_rows_div", C.c_int32),
+                ("tuned_cols_div", C.c_int32), ("tune_cached", C.c_int32), ("pad_", C.c_int32)]
 
 
 class rr_solve_opts(C.Structure):
@@ -142,7 +144,7 @@ def _dev_f64(t, n=None, name="vector"):
 # --- the C ABI, one Python function per entry point -------------------------
 
 def rr_setup(row_ptr, col_idx, values, n_cols, n_clusters=0, seed=0, kmeans_max_iter=0,
-             labels_in=None, n_labels_in=0, lambda_slots=0, stream=None):
+             labels_in=None, n_labels_in=0, lambda_slots=0, autotune=False, stream=None):
     """X is a device CSR: row_ptr/col_idx int32 CUDA tensors, values float64
     CUDA tensor or None (binary).  Returns an opaque handle (int)."""
     import torch
@@ -156,7 +158,7 @@ def rr_setup(row_ptr, col_idx, values, n_cols, n_clusters=0, seed=0, kmeans_max_
     X = rr_csr(row_ptr.numel() - 1, int(n_cols), col_idx.numel(), _ptr(row_ptr), _ptr(col_idx),
                _ptr(values))
     o = rr_setup_opts(int(n_clusters), int(kmeans_max_iter), int(seed) & (2**64 - 1),
-                      _ptr(labels_in), int(n_labels_in), int(lambda_slots))
+                      _ptr(labels_in), int(n_labels_in), int(lambda_slots), 1 if autotune else 0)
     h = C.c_void_p()
     _check(_lib.rr_setup(C.byref(X), C.byref(o), _stream(stream), C.byref(h)))
     return h.value
@@ -340,7 +342,7 @@ class Ridge:
     copy)."""
 
     def __init__(self, X, n_clusters=0, seed=0, kmeans_max_iter=0, labels=None, binary=None,
-                 lambda_slots=0, device="cuda"):
+                 lambda_slots=0, autotune=False, device="cuda"):
         import numpy as np
         import torch
         X = X.tocsr()
@@ -358,7 +360,7 @@ class Ridge:
             lab = torch.as_tensor(np.asarray(labels, dtype=np.int32), device=self.device)
             nlab = int(np.max(labels)) + 1 if len(labels) else 1
         self.h = rr_setup(rp, ci, vals, self.F, n_clusters, seed, kmeans_max_iter, lab, nlab,
-                          lambda_slots)
+                          lambda_slots, autotune)
         torch.cuda.current_stream().synchronize()
         self.info = rr_get_setup_info(self.h)
 

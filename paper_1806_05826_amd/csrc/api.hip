@@ -219,7 +219,11 @@ rr_status setup_impl(const rr_csr* Xin, const rr_setup_opts* o, hipStream_t s, r
         ncu > 0)
       X.num_cu = ncu;
   }
-  RR_TRY(build_sell_plans(X, s));
+  {
+    const double tt = now_ms();
+    RR_TRY(build_sell_plans(X, s, (o && o->autotune) ? 1 : 0, &h->tuning));
+    h->tune_ms = now_ms() - tt;
+  }
   // column norms and Gershgorin row sums g = X^T (X 1)
   RR_TRY(dalloc(&h->colnorm, X.F));
   RR_TRY(dalloc(&h->gersh, X.F));
@@ -1175,6 +1179,10 @@ rr_status rr_get_setup_info(const rr_handle* h, rr_setup_info* info) {
   i.binary = h->X.binary ? 1 : 0;
   i.setup_ms = h->setup_ms;
   i.kmeans_ms = h->kmeans_ms;
+  i.plan_ms = h->tune_ms;
+  i.tuned_rows_div = h->tuning.div_rows;
+  i.tuned_cols_div = h->tuning.div_cols;
+  i.tune_cached = h->tuning.cached;
   *info = i;
   return RR_OK;
 }

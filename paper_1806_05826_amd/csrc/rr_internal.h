@@ -163,6 +163,13 @@ struct SellPlan {
   double* part = nullptr;     // [nout] partial sums
 };
 
+// Autotuning record of the sliced plans (see build_sell_plans).
+struct SellTuning {
+  int div_rows = 2, div_cols = 2, cached = 0, n = 0;
+  int cand_div[6] = {}, cand_pass[6] = {};
+  float cand_ms[6] = {};
+};
+
 // Sparse matrix stored both ways.
 struct Sparse {
   int N = 0, F = 0, nnz = 0;
@@ -272,7 +279,8 @@ struct rr_handle {
   std::vector<rr::Work*> extra_sets;   // work sets 1, 2, ... for concurrent solves
   int npartials = 0;
   double* omega_tmp = nullptr;    // device scalar for the smoother weight
-  double setup_ms = 0, kmeans_ms = 0;
+  double setup_ms = 0, kmeans_ms = 0, tune_ms = 0;
+  rr::SellTuning tuning;
   std::vector<hipEvent_t> ev_pool;
   hipStream_t bstream = nullptr;    // the handle's own stream for batched solves
 };
@@ -320,7 +328,10 @@ int launch_csc(const Sparse& X, const double* u, int mode, const Epi& e, const i
                hipStream_t s, hipEvent_t mid = nullptr);
 rr_status build_csc(Sparse& X, hipStream_t s);
 rr_status renumber_features(Sparse& X, int* fperm, int* finv, hipStream_t s);
-rr_status build_sell_plans(Sparse& X, hipStream_t s);
+// Lane-stream target of the sliced plans: nnz / (CUs x 16 waves x 64 lanes x
+// div), clamped to [8, 64].  With autotune the divisor of each pass is chosen
+// among {1, 2, 4} by timing, once per device and shape bucket.
+rr_status build_sell_plans(Sparse& X, hipStream_t s, int autotune, SellTuning* tuned);
 void free_sell(SellPlan& sp);
 int launch_sell(const SellPlan& sp, const double* v, int mode, const Epi& e, const int* done,
                 hipStream_t s, const StageArgs* stage = nullptr, hipEvent_t mid = nullptr);

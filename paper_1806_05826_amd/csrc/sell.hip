@@ -25,7 +25,10 @@
 // (reading them through a position index) and applies the epilogue.  Every
 // sum's order is fixed by the plan, so results are bitwise reproducible.
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <numeric>
+#include <string>
 #include <queue>
 
 #include "rr_device.h"
@@ -436,7 +439,7 @@ void emit_lane_task(SellBuild& B, const std::vector<std::vector<int>>& lanes,
 // Host-side construction from a segment-major pattern (ptr[S+1], gidx sorted
 // inside every segment).  Setup only.
 rr_status build_sell(SellPlan& sp, const std::vector<int>& ptr, const std::vector<int>& gidx,
-                     int S, int gdim, int num_cu, hipStream_t s) {
+                     int S, int gdim, int num_cu, hipStream_t s, int target_div) {
   free_sell(sp);
   const int W = kSliceRows;
   const int R = std::max(1, cdiv(gdim, W));
@@ -468,7 +471,8 @@ rr_status build_sell(SellPlan& sp, const std::vector<int>& ptr, const std::vecto
   // are cut in two halves, each with its own partial sum; longer pairs get a
   // whole wave
   const int target = (int)std::min<long long>(
-      64, std::max<long long>(8, nnz / std::max(1LL, (long long)num_cu * kSliceWaves * 64 * 2)));
+      64, std::max<long long>(8, nnz / std::max(1LL, (long long)num_cu * kSliceWaves * 64 *
+                                                        std::max(1, target_div))));
   const int cmax = 2 * target;
   std::vector<Pair> items;
   std::vector<int> islice;
@@ -660,7 +664,33 @@ rr_status build_sell(SellPlan& sp, const std::vector<int>& ptr, const std::vecto
   return RR_OK;
 }
 
-rr_status build_sell_plans(Sparse& X, hipStream_t s) {
+// Mean time of `reps` back-to-back launches of a pass (gather + reduction).
+static rr_status time_pass(const SellPlan& sp, const double* v, double* out, int reps,
+                           hipStream_t s, float* ms) {
+  hipEvent_t a, b;
+  RR_HIP(hipEventCreate(&a));
+  RR_HIP(hipEventCreate(&b));
+  Epi e{};
+  e.out = out;
+  launch_sell(sp, v, EPI_STORE, e, nullptr, s);
+  RR_HIP(hipEventRecord(a, s));
+  for (int i = 0; i < reps; ++i) launch_sell(sp, v, EPI_STORE, e, nullptr, s);
+  RR_HIP(hipEventRecord(b, s));
+  RR_HIP(hipEventSynchronize(b));
+  RR_HIP(hipEventElapsedTime(ms, a, b));
+  *ms /= reps;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return RR_OK;
+}
+
+namespace {
+// tuned lane-stream divisors per shape bucket (log2 of N, F, nnz) and device
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tune_cache;
+}
+
+rr_status build_sell_plans(Sparse& X, hipStream_t s, int autotune, SellTuning* tuned) {
   if (!X.binary) return RR_OK;   // valued matrices use the row-group / merge-path kernels
   std::vector<int> rp(X.N + 1), ci(std::max(X.nnz, 1)), cp(X.F + 1), ri(std::max(X.nnz, 1));
   RR_HIP(hipMemcpyAsync(rp.data(), X.row_ptr, sizeof(int) * (X.N + 1), hipMemcpyDeviceToHost, s));
@@ -670,8 +700,70 @@ rr_status build_sell_plans(Sparse& X, hipStream_t s) {
     RR_HIP(hipMemcpyAsync(ri.data(), X.row_idx, sizeof(int) * X.nnz, hipMemcpyDeviceToHost, s));
   }
   RR_HIP(hipStreamSynchronize(s));
-  RR_TRY(build_sell(X.sell_csr, rp, ci, X.N, X.F, X.num_cu, s));
-  RR_TRY(build_sell(X.sell_csc, cp, ri, X.F, X.N, X.num_cu, s));
+  int div_rows = 2, div_cols = 2;
+  if (autotune) {
+    int dev = 0;
+    RR_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    RR_HIP(hipGetDeviceProperties(&prop, dev));
+    auto lg = [](long long v) { int b = 0; while ((1LL << b) < v) ++b; return b; };
+    const std::string key = std::string(prop.gcnArchName) + ":" + std::to_string(lg(X.N)) + ":" +
+                            std::to_string(lg(X.F)) + ":" + std::to_string(lg(X.nnz));
+    bool hit = false;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune_cache.find(key);
+      if (it != g_tune_cache.end()) {
+        div_rows = it->second.first;
+        div_cols = it->second.second;
+        hit = true;
+      }
+    }
+    if (tuned) tuned->cached = hit ? 1 : 0;
+    if (!hit) {
+      // time each candidate plan on a vector of ones and keep the fastest
+      double *v = nullptr, *out = nullptr;
+      const int nmax = std::max(X.N, X.F);
+      RR_HIP(hipMalloc(&v, sizeof(double) * nmax));
+      RR_HIP(hipMalloc(&out, sizeof(double) * nmax));
+      launch_fill(v, 1.0, nmax, s);
+      const int cand[3] = {1, 2, 4};
+      float best_r = 1e30f, best_c = 1e30f;
+      rr_status st = RR_OK;
+      for (int c : cand) {
+        if (st != RR_OK) break;
+        for (int pass = 0; pass < 2 && st == RR_OK; ++pass) {
+          SellPlan sp;
+          st = pass == 0 ? build_sell(sp, rp, ci, X.N, X.F, X.num_cu, s, c)
+                         : build_sell(sp, cp, ri, X.F, X.N, X.num_cu, s, c);
+          sp.pass = pass;
+          float ms = 0.f;
+          if (st == RR_OK) st = time_pass(sp, v, out, 10, s, &ms);
+          free_sell(sp);
+          if (st != RR_OK) break;
+          if (pass == 0 && ms < best_r) { best_r = ms; div_rows = c; }
+          if (pass == 1 && ms < best_c) { best_c = ms; div_cols = c; }
+          if (tuned && tuned->n < 6) {
+            tuned->cand_div[tuned->n] = c;
+            tuned->cand_pass[tuned->n] = pass;
+            tuned->cand_ms[tuned->n] = ms;
+            tuned->n++;
+          }
+        }
+      }
+      (void)hipFree(v);
+      (void)hipFree(out);
+      RR_TRY(st);
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune_cache[key] = {div_rows, div_cols};
+    }
+  }
+  if (tuned) {
+    tuned->div_rows = div_rows;
+    tuned->div_cols = div_cols;
+  }
+  RR_TRY(build_sell(X.sell_csr, rp, ci, X.N, X.F, X.num_cu, s, div_rows));
+  RR_TRY(build_sell(X.sell_csc, cp, ri, X.F, X.N, X.num_cu, s, div_cols));
   X.sell_csr.pass = 0;
   X.sell_csc.pass = 1;
   return RR_OK;
