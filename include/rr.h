@@ -111,7 +111,9 @@ typedef struct {
  * X^T X, then the aggregation (k-means++ over the columns, exact integer
  * arithmetic for binary X) and the lambda-independent coarse Gram matrix
  * K = P^T X^T X P.  X's arrays are only read during the call.  For non-binary
- * X only labels_in aggregation is implemented (RR_ERR_UNSUPPORTED otherwise).
+ * X the k-means aggregation is not implemented (RR_ERR_UNSUPPORTED): pass
+ * labels_in; K is then formed one coarse column at a time, K e_c =
+ * P^T X^T X (P e_c), in FP64 (F_C operator applications at setup).
  * Errors: RR_ERR_INVALID_ARG for an invalid matrix (bad row_ptr, column index
  * out of range or not increasing) or options; RR_ERR_DEVICE on HIP failure.
  * On success *out receives a handle to release with rr_destroy.
@@ -281,7 +283,13 @@ rr_status rr_coarse_gram(rr_handle* h, double* K, rr_stream stream);
 rr_status rr_coarse_factor(rr_handle* h, double lambda, double* L, double* Ac_inv,
                            rr_stream stream);
 
-/* The automatic smoother weight for this lambda (host double). */
+/* The automatic smoother weight for this lambda (host double).  X >= 0: the
+ * Gershgorin weight 1 / max_j (X^T X 1 + lambda)_j / D_j.  X with negative
+ * entries: 1 / (1.1 rho), rho the norm ratio after 30 power iterations with
+ * D^-1/2 A D^-1/2 from a fixed start vector whose entries, in the caller's
+ * feature order, are u + 0.5 for u the successive SplitMix64 outputs of seed
+ * 0x5eed mapped to [0, 1) by their top 53 bits, normalised to unit length.
+ * Runs on the null stream with work set 0's buffers. */
 rr_status rr_smoother_weight(rr_handle* h, double lambda, double* omega);
 
 /* Message for the last non-OK status on this thread ("" if none). */

@@ -168,6 +168,11 @@ void destroy_handle(rr_handle* h) {
   dfree(h->perm); dfree(h->coff); dfree(h->K);
   for (auto& s : h->slots) { dfree(s.L); dfree(s.Ainv); }
   dfree(h->chol_work); dfree(h->chol_flag); dfree(h->omega_tmp); dfree(h->mlp_scale);
+  if (h->pw) {
+    dfree(h->pw->v); dfree(h->pw->t); dfree(h->pw->u); dfree(h->pw->D); dfree(h->pw->vin);
+    dfree(h->pw->parts); dfree(h->pw->nrm);
+    delete h->pw;
+  }
   free_mlp(h->mlp);
   free_work(h->w);
   for (Work* w : h->extra_sets) {
@@ -303,9 +308,88 @@ rr_status check_lambda(double lam, bool allow_zero) {
   return RR_OK;
 }
 
-rr_status auto_omega(rr_handle* h, double lam, double* omega, hipStream_t s) {
-  if (!h->nonneg)
-    return fail(RR_ERR_UNSUPPORTED, "automatic smoother weight for X with negative entries: pass omega");
+// ---- smoother weight by power iteration (X with negative entries) ---------
+
+// v = s * v / rho (rho = *nrm, or 1 before the first product); s = D^-1/2
+__global__ void k_pw_scale(int F, const double* __restrict__ v, const double* __restrict__ D,
+                           const double* nrm, double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < F) out[j] = v[j] / (sqrt(D[j]) * (nrm ? *nrm : 1.0));
+}
+
+// w = s * t and the block partials of ||w||^2
+__global__ __launch_bounds__(kBlock) void k_pw_post(int F, const double* __restrict__ t,
+                                                    const double* __restrict__ D,
+                                                    double* __restrict__ w, double* parts) {
+  double acc = 0.0;
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < F; j += gridDim.x * kBlock) {
+    const double x = t[j] / sqrt(D[j]);
+    w[j] = x;
+    acc += x * x;
+  }
+  __shared__ double red[kBlock / 64];
+  const double tot = block_sum(acc, red);
+  if (threadIdx.x == 0) parts[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pw_norm(const double* parts, int n, double* nrm) {
+  __shared__ double red[kBlock / 64];
+  const double t = sum_parts<kBlock>(parts, n, red);
+  if (threadIdx.x == 0) *nrm = sqrt(t);
+}
+
+// The oracle's power estimate: 30 products with D^-1/2 A D^-1/2 from a
+// start vector with SplitMix64(kPowerSeed) entries in [0.5, 1.5) (caller's
+// feature order), rho = the last norm ratio, omega = 1 / (1.1 rho).
+constexpr uint64_t kPowerSeed = 0x5eedULL;
+rr_status omega_power(rr_handle* h, const Sparse& X, double lam, double* omega, hipStream_t s) {
+  const int F = X.F, N = X.N;
+  if (!h->pw) {
+    h->pw = new (std::nothrow) rr_handle::PowerWork();
+    if (!h->pw) return fail(RR_ERR_DEVICE, "out of host memory");
+    RR_TRY(dalloc(&h->pw->v, F)); RR_TRY(dalloc(&h->pw->t, F)); RR_TRY(dalloc(&h->pw->u, N));
+    RR_TRY(dalloc(&h->pw->D, F)); RR_TRY(dalloc(&h->pw->vin, F));
+    RR_TRY(dalloc(&h->pw->parts, kMaxParts)); RR_TRY(dalloc(&h->pw->nrm, 1));
+  }
+  rr_handle::PowerWork& p = *h->pw;
+  std::vector<double> v0(F);
+  uint64_t st = kPowerSeed;
+  double ss = 0.0;
+  for (int j = 0; j < F; ++j) {
+    v0[j] = (double)(splitmix64_next(st) >> 11) * (1.0 / 9007199254740992.0) + 0.5;
+    ss += v0[j] * v0[j];
+  }
+  const double inv = 1.0 / std::sqrt(ss);
+  for (auto& x : v0) x *= inv;
+  RR_HIP(hipMemcpyAsync(p.vin, v0.data(), sizeof(double) * F, hipMemcpyHostToDevice, s));
+  launch_gather(p.v, p.vin, h->fperm, F, s);   // caller order -> internal order
+  launch_colnorm_diag(F, h->colnorm, lam, p.D, s);
+  const int g = vec_grid(F);
+  for (int it = 0; it < 30; ++it) {
+    // t = A (s v / rho); v = s t
+    k_pw_scale<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, p.v, p.D, it ? p.nrm : nullptr, p.vin);
+    launch_csr(X, p.vin, p.u, nullptr, s);
+    Epi e{};
+    e.lam = lam;
+    e.p = p.vin;
+    e.out = p.t;
+    launch_csc(X, p.u, EPI_APPLY, e, nullptr, s);
+    k_pw_post<<<g, kBlock, 0, s>>>(F, p.t, p.D, p.v, p.parts);
+    k_pw_norm<<<1, kBlock, 0, s>>>(p.parts, g, p.nrm);
+  }
+  double rho = 0.0;
+  RR_HIP(hipMemcpyAsync(&rho, p.nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+  RR_HIP(hipStreamSynchronize(s));
+  RR_HIP(hipGetLastError());
+  if (!(rho > 0.0) || !std::isfinite(rho)) return fail(RR_ERR_BREAKDOWN, "power iteration failed");
+  *omega = 1.0 / (1.1 * rho);
+  return RR_OK;
+}
+
+// X is the operator view of the work set whose stream s runs the estimate:
+// its partial-sum buffers are ordered with that set's own solve.
+rr_status auto_omega(rr_handle* h, const Sparse& X, double lam, double* omega, hipStream_t s) {
+  if (!h->nonneg) return omega_power(h, X, lam, omega, s);
   launch_omega_gersh(h->X.F, h->gersh, h->colnorm, lam, h->omega_tmp, nullptr, nullptr, s);
   RR_HIP(hipMemcpyAsync(omega, h->omega_tmp, sizeof(double), hipMemcpyDeviceToHost, s));
   RR_HIP(hipStreamSynchronize(s));
@@ -313,7 +397,7 @@ rr_status auto_omega(rr_handle* h, double lam, double* omega, hipStream_t s) {
 }
 
 // The coarse factor for lambda, from the cache or freshly computed.
-rr_status get_slot(rr_handle* h, double lam, LambdaSlot** out, double* ms, hipStream_t s) {
+rr_status get_slot(rr_handle* h, const Sparse& X, double lam, LambdaSlot** out, double* ms, hipStream_t s) {
   *ms = 0.0;
   for (auto& sl : h->slots)
     if (sl.valid && sl.lam == lam) {
@@ -336,7 +420,7 @@ rr_status get_slot(rr_handle* h, double lam, LambdaSlot** out, double* ms, hipSt
   const double t0 = now_ms();
   victim->valid = false;
   RR_TRY(coarse_factor(h, lam, *victim, s));
-  RR_TRY(auto_omega(h, lam, &victim->omega, s));
+  RR_TRY(auto_omega(h, X, lam, &victim->omega, s));
   RR_HIP(hipStreamSynchronize(s));
   victim->lam = lam;
   victim->valid = true;
@@ -536,7 +620,7 @@ rr_status Solve::begin() {
   }
   omega = op.omega;
   if (kind == PK_VCYCLE || kind == PK_ADDITIVE || kind == PK_LEARNED) {
-    RR_TRY(get_slot(h, lam, &sl, &coarse_ms, s));
+    RR_TRY(get_slot(h, w.X, lam, &sl, &coarse_ms, s));
     sl->in_use++;
     if (omega == 0.0) omega = sl->omega;
   }
@@ -808,6 +892,51 @@ rr_status Solve::finish(rr_solve_info* info) {
   return RR_OK;
 }
 
+}  // namespace
+
+namespace rr {
+
+// ---- coarse Gram matrix of a valued X ---------------------------------------
+
+// v = P e_s: the scaled indicator of cluster s
+__global__ void k_cluster_vec(int F, const int* __restrict__ labels, const double* __restrict__ cscale,
+                              int cl, double* __restrict__ v) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < F) v[j] = (labels[j] == cl) ? cscale[cl] : 0.0;
+}
+
+// K = P^T X^T X P column by column: K e_s = P^T X^T (X (P e_s)) with the
+// operator's passes and the restriction (FP64; K is symmetric, so column s is
+// stored as row s).
+rr_status build_coarse_gram_valued(rr_handle* h, hipStream_t s) {
+  const int F = h->X.F, N = h->X.N, fc = h->FC;
+  double *v = nullptr, *u = nullptr, *t = nullptr;
+  RR_TRY(dalloc(&v, F));
+  RR_TRY(dalloc(&u, N));
+  RR_TRY(dalloc(&t, F));
+  for (int c = 0; c < fc; ++c) {
+    k_cluster_vec<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, h->labels, h->cscale, c, v);
+    launch_csr(h->X, v, u, nullptr, s);
+    Epi e{};
+    e.out = t;
+    launch_csc(h->X, u, EPI_STORE, e, nullptr, s);
+    Epi er{};
+    er.scale = h->cscale;
+    er.out = h->K + (size_t)c * fc;
+    launch_segsum(h->restrict_plan, h->coff + 1, h->perm, nullptr, t, EPI_SCALE, er, nullptr, s);
+  }
+  RR_HIP(hipStreamSynchronize(s));
+  RR_HIP(hipGetLastError());
+  dfree(v);
+  dfree(u);
+  dfree(t);
+  return RR_OK;
+}
+
+}  // namespace rr
+
+namespace {
+
 // ---- mixed precision: FP32 inner PCG inside FP64 iterative refinement ------
 
 rr_status ensure_f32(rr_handle* h, Work& w) {
@@ -885,7 +1014,7 @@ rr_status solve_ir(rr_handle* h, Work& w, double lam, const double* rhs, double*
   LambdaSlot* sl = nullptr;
   double coarse_ms = 0.0, omega = op.omega;
   if (kind == PK_VCYCLE) {
-    RR_TRY(get_slot(h, lam, &sl, &coarse_ms, s));
+    RR_TRY(get_slot(h, w.X, lam, &sl, &coarse_ms, s));
     if (omega == 0.0) omega = sl->omega;
   }
   if (!std::isfinite(omega) || omega < 0.0) return fail(RR_ERR_INVALID_ARG, "omega must be finite and >= 0");
@@ -1273,7 +1402,7 @@ rr_status rr_apply_precond(rr_handle* h, double lambda, int32_t precond, double 
   if (h->FC == 0) return fail(RR_ERR_INVALID_ARG, "two-level preconditioner needs a coarse level");
   LambdaSlot* sl = nullptr;
   double ms = 0.0;
-  RR_TRY(get_slot(h, lambda, &sl, &ms, s));
+  RR_TRY(get_slot(h, w.X, lambda, &sl, &ms, s));
   if (omega == 0.0) omega = sl->omega;
   if (!std::isfinite(omega) || omega < 0.0) return fail(RR_ERR_INVALID_ARG, "omega must be finite and >= 0");
   Scalars& hs = *w.sc_host;
@@ -1306,7 +1435,7 @@ rr_status rr_coarse_factor(rr_handle* h, double lambda, double* L, double* Ainv,
   hipStream_t s = (hipStream_t)stream;
   LambdaSlot* sl = nullptr;
   double ms = 0.0;
-  RR_TRY(get_slot(h, lambda, &sl, &ms, s));
+  RR_TRY(get_slot(h, h->w.X, lambda, &sl, &ms, s));
   const size_t bytes = sizeof(double) * h->FC * h->FC;
   if (L) RR_HIP(hipMemcpyAsync(L, sl->L, bytes, hipMemcpyDeviceToDevice, s));
   if (Ainv) RR_HIP(hipMemcpyAsync(Ainv, sl->Ainv, bytes, hipMemcpyDeviceToDevice, s));
@@ -1518,7 +1647,7 @@ rr_status rr_smoother_weight(rr_handle* h, double lambda, double* omega) {
   RR_TRY(check_handle(h));
   RR_TRY(check_lambda(lambda, false));
   if (!omega) return fail(RR_ERR_INVALID_ARG, "null omega");
-  return auto_omega(h, lambda, omega, nullptr);
+  return auto_omega(h, h->w.X, lambda, omega, nullptr);
 }
 
 }  // extern "C"

@@ -659,7 +659,7 @@ rr_status set_labels(rr_handle* h, const int* labels_in, int nlab, hipStream_t s
 rr_status build_coarse_gram(rr_handle* h, hipStream_t s) {
   const Sparse& X = h->X;
   const int fc = h->FC;
-  if (!X.binary) return fail(RR_ERR_UNSUPPORTED, "coarse Gram for a non-binary X is not implemented");
+  if (!X.binary) return build_coarse_gram_valued(h, s);
   KmWork kw;
   RR_TRY(make_items(h, kw, fc, false, s));
   unsigned long long* StS = nullptr;

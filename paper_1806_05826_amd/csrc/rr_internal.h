@@ -275,6 +275,11 @@ struct rr_handle {
   int* chol_flag = nullptr;     // device int
   rr::Mlp mlp;                    // learned coarse correction (rr_mlp_init)
   double* mlp_scale = nullptr;    // device scalar ||P^T r|| of the learned correction
+  struct PowerWork {              // buffers of the power-iteration smoother weight
+    double *v = nullptr, *t = nullptr, *u = nullptr, *D = nullptr, *vin = nullptr;
+    double *parts = nullptr, *nrm = nullptr;
+  };
+  PowerWork* pw = nullptr;
   rr::Work w;                     // work set 0
   std::vector<rr::Work*> extra_sets;   // work sets 1, 2, ... for concurrent solves
   int npartials = 0;
@@ -425,5 +430,6 @@ uint64_t splitmix64_next(uint64_t& state);   // SplitMix64 (Steele, Lea & Flood)
 rr_status run_kmeans(rr_handle* h, int k, uint64_t seed, int max_iter, hipStream_t s);
 rr_status set_labels(rr_handle* h, const int* labels_in, int nlab, hipStream_t s);
 rr_status build_coarse_gram(rr_handle* h, hipStream_t s);
+rr_status build_coarse_gram_valued(rr_handle* h, hipStream_t s);   // (api.hip)
 
 }  // namespace rr

@@ -338,8 +338,8 @@ def test_real_valued_matrix(rr):
     rng = np.random.default_rng(6)
     X = sp.random(800, 300, density=0.03, random_state=7, format="csr")
     X.data = rng.standard_normal(X.nnz)
-    with pytest.raises(rr.RRError) as e:     # coarse level needs binary X for now
-        rr.Ridge(X, labels=datagen.random_labels(300, 30, 2), binary=False)
+    with pytest.raises(rr.RRError) as e:     # GPU k-means clusters 0/1 columns only
+        rr.Ridge(X, n_clusters=30, seed=1, binary=False)
     assert e.value.status == rr.RR_ERR_UNSUPPORTED
     R = rr.Ridge(X, binary=False)
     y = rng.standard_normal(800)
@@ -348,6 +348,38 @@ def test_real_valued_matrix(rr):
     x_t, inf = krylov.solve(X, y, 0.7, "jacobi", tol=1e-13)
     w, info = R.solve(0.7, y, precond="jacobi", fixed_iters=inf.iters)
     assert np.linalg.norm(host(w) - x_t) <= 1e-10 * np.linalg.norm(x_t)
+
+
+@pytest.mark.parametrize("lam", [0.05, 0.7])
+def test_real_valued_two_level(rr, lam):
+    """X with negative entries: smoother weight by power iteration, coarse
+    Gram built column by column from labels_in, V(1,1) and additive solves."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(16)
+    X = sp.random(1500, 700, density=0.02, random_state=17, format="csr")
+    X.data = rng.standard_normal(X.nnz)
+    F = X.shape[1]
+    lab = datagen.random_labels(F, 60, 5)
+    labc, fc = kmeans.compact(lab)
+    R = rr.Ridge(X, labels=lab, binary=False)
+    assert R.info["n_coarse"] == fc
+    assert np.array_equal(host(R.labels()), labc)
+    K_or = coarse.coarse_gram(X, labc, fc)
+    K = host(R.coarse_gram())
+    assert np.abs(K - K_or).max() <= 1e-12 * np.abs(K_or).max()
+    om_or = op.omega_power(X, lam, seed=0x5eed)
+    om = R.smoother_weight(lam)
+    assert abs(om - om_or) <= 1e-10 * om_or
+    y = rng.standard_normal(1500)
+    for kind in ("vcycle", "additive"):
+        x_t, inf = krylov.solve(X, y, lam, kind, labc, fc, omega=om_or, tol=1e-13)
+        w, info = R.solve(lam, y, precond=kind, fixed_iters=inf.iters)
+        print(f"[valued {kind} lam={lam}] oracle iters={inf.iters}", flush=True)
+        assert np.linalg.norm(host(w) - x_t) <= 1e-10 * np.linalg.norm(x_t)
+        w, info = R.solve(lam, y, precond=kind, tol=1e-10)
+        assert info["status"] == 0
+        x_n, inf_n = krylov.solve(X, y, lam, kind, labc, fc, omega=om_or, tol=1e-10)
+        assert abs(info["iters"] - inf_n.iters) <= 1
 
 
 def test_errors(rr):
