@@ -88,6 +88,15 @@ typedef struct {
                               matrix: every stored entry is 1                  */
 } rr_csr;
 
+/* Dense feature matrix X (N x F), row-major FP32 (the dense case of the
+ * data-matrices subsection: real-valued samples, every feature stored). */
+typedef struct {
+  int64_t n_rows;          /* N >= 1                                           */
+  int64_t n_cols;          /* F >= 1                                           */
+  int64_t ld;              /* >= F: elements between consecutive rows          */
+  const float* values;     /* device float[N * ld], finite                     */
+} rr_dense;
+
 typedef struct {
   int32_t n_clusters;      /* k >= 1: k-means++ clusters of the feature columns;
                               0: no coarse level (only NONE/JACOBI solves)      */
@@ -137,7 +146,8 @@ typedef struct {
   int32_t tuned_rows_div;  /* lane-stream divisors used by the two passes      */
   int32_t tuned_cols_div;
   int32_t tune_cached;     /* 1: autotune reused an earlier measurement        */
-  int32_t pad_;
+  int32_t dense;           /* 1 for a handle made by rr_setup_dense (nnz =
+                              n_rows * n_cols)                                 */
 } rr_setup_info;
 
 /* Host-side facts about a handle. */
@@ -152,10 +162,16 @@ rr_status rr_get_centres(const rr_handle* h, int32_t* centres, rr_stream stream)
 /* Arithmetic of rr_solve. */
 typedef enum {
   RR_PREC_F64 = 0,         /* FP64 vectors, sums and scalars throughout          */
-  RR_PREC_F32_IR = 1       /* iterative refinement: r = b - A x and x in FP64;
+  RR_PREC_F32_IR = 1,      /* iterative refinement: r = b - A x and x in FP64;
                               each correction A d = r by PCG with FP32 vectors
                               and FP32 operator sums, FP64 scalars and FP64
                               coarse solve (0/1 X; none / Jacobi / V(1,1))      */
+  RR_PREC_BF16_IR = 2      /* dense X (rr_solve_block): iterative refinement
+                              whose corrections run PCG with a BF16-operand
+                              operator (X and the input block rounded to BF16,
+                              FP32 matrix-core sums, U = X V rounded to BF16),
+                              FP64 vectors, scalars and coarse solve; the
+                              residual b - A x uses the FP64 operator           */
 } rr_precision;
 
 /* Krylov method of rr_solve. */
@@ -291,6 +307,55 @@ rr_status rr_coarse_factor(rr_handle* h, double lambda, double* L, double* Ac_in
  * 0x5eed mapped to [0, 1) by their top 53 bits, normalised to unit length.
  * Runs on the null stream with work set 0's buffers. */
 rr_status rr_smoother_weight(rr_handle* h, double lambda, double* omega);
+
+/*
+ * Dense X with many right-hand sides.
+ *
+ * rr_setup_dense: copy X (device FP32, row-major) into four library-owned
+ * copies (FP32 and BF16, X and X^T, zero-padded to multiples of 128 rows and
+ * columns: 12 bytes per entry), the column norms ||x_j||^2 and, for X >= 0,
+ * the Gershgorin sums X^T X 1 (FP64); then the aggregation (labels_in, or
+ * k-means++ over the columns in FP64 on the matrix cores when n_clusters > 0)
+ * and K = P^T X^T X P (FP64 matrix cores).  The options of rr_setup apply
+ * (autotune is ignored).  Errors: RR_ERR_INVALID_ARG for bad sizes, a
+ * non-finite entry or bad options; RR_ERR_DEVICE on HIP failure.  The handle
+ * takes rr_solve_block, rr_apply_operator_block, rr_get_setup_info,
+ * rr_get_labels, rr_get_centres, rr_coarse_gram, rr_coarse_factor,
+ * rr_smoother_weight and rr_destroy; the other calls return
+ * RR_ERR_UNSUPPORTED for it.
+ */
+rr_status rr_setup_dense(const rr_dense* X, const rr_setup_opts* opts, rr_stream stream,
+                         rr_handle** out);
+
+/*
+ * rr_solve_block: nrhs systems (X^T X + lambda I) w_c = b_c with one lambda,
+ * solved together: one operator application multiplies the whole block
+ * (matrix-core GEMMs), every column keeps its own CG scalars, stopping test
+ * and iteration count, and a converged column stays fixed.
+ *   rhs: device double, column c at rhs + c * ld_rhs; y_c (N entries,
+ *        ld_rhs >= N) or, with opts->rhs_is_b, b_c (F entries, ld_rhs >= F).
+ *   w:   device double, column c at w + c * ld_w (ld_w >= F), written.
+ *   opts: tol, max_iter, fixed_iters, precond (none / Jacobi / V(1,1) /
+ *        additive), rhs_is_b, omega, precision (RR_PREC_F64: FP64 operator;
+ *        RR_PREC_BF16_IR: refinement with BF16-operand corrections, inner_tol
+ *        relative to each step's residual, default 1e-3); other fields must be
+ *        zero.
+ *   info: NULL or host rr_solve_info[nrhs], one per column (iters = PCG
+ *        iterations, summed over refinement steps).
+ * 1 <= nrhs <= 4096.  Returns RR_ERR_NOT_CONVERGED / RR_ERR_BREAKDOWN if any
+ * column did; synchronizes the stream.
+ */
+rr_status rr_solve_block(rr_handle* h, double lambda, int32_t nrhs, const double* rhs,
+                         int64_t ld_rhs, double* w, int64_t ld_w, const rr_solve_opts* opts,
+                         rr_solve_info* info, rr_stream stream);
+
+/* q_c = (X^T X + lambda I) v_c for nrhs columns (device double, leading
+ * dimensions ldv, ldq >= F) of a dense handle, with the FP64 operator
+ * (precision RR_PREC_F64) or the BF16-operand one (RR_PREC_BF16_IR).
+ * lambda >= 0.  Stream-ordered. */
+rr_status rr_apply_operator_block(rr_handle* h, double lambda, int32_t nrhs, const double* v,
+                                  int64_t ldv, double* q, int64_t ldq, int32_t precision,
+                                  rr_stream stream);
 
 /* Message for the last non-OK status on this thread ("" if none). */
 const char* rr_last_error(void);

@@ -77,3 +77,51 @@ def omega_power(X, lam: float, seed: int, iters: int = 30, safety: float = 1.1) 
         rho = float(np.linalg.norm(w))
         v = w / rho
     return 1.0 / (safety * rho)
+
+
+# --- BF16 operands (the correction operator of iterative refinement) -----------
+
+def bf16_round(a) -> np.ndarray:
+    """Values rounded to BF16 (8 significant bits), returned as FP64: first
+    FP64 -> FP32, then FP32 -> BF16, each to nearest with ties to even.
+    BF16 keeps the FP32 exponent, so the second step clears the low 16 bits
+    of the FP32 pattern after adding half of their unit (plus the kept
+    lowest bit for ties)."""
+    f = np.asarray(a, dtype=np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    finite = np.isfinite(f)
+    keep = (u >> np.uint64(16)) & np.uint64(1)
+    r = ((u + np.uint64(0x7FFF) + keep) >> np.uint64(16)) << np.uint64(16)
+    r = np.where(finite, r, u & np.uint64(0xFFFF0000))
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def apply_A_bf16(X, lam: float, V: np.ndarray) -> np.ndarray:
+    """The BF16-operand operator on columns V (F x m): X and V rounded to
+    BF16, U = X V rounded to BF16, then X^T U + lam V with exact (FP64)
+    sums.  This is the definition; a GPU summing in FP32 differs from it by
+    at most the rounding of those sums (see apply_A_bf16_bound)."""
+    Xb = bf16_round(X.toarray() if sp.issparse(X) else X)
+    V = np.asarray(V, dtype=np.float64)
+    U = bf16_round(Xb @ bf16_round(V))
+    return Xb.T @ U + lam * V
+
+
+def apply_A_bf16_bound(X, V: np.ndarray) -> np.ndarray:
+    """Elementwise bound on |Q - apply_A_bf16(X, lam, V)| for a Q whose two
+    products sum exact BF16 x BF16 products in FP32, in any order.  With
+    S = |X~| |V~| and gamma_n = n 2^-24 / (1 - n 2^-24): the FP32 sum for U
+    errs by at most gamma_F S, so its BF16 rounding differs from that of the
+    exact U by at most du = 2^-7 S + 2 gamma_F S; the second sum adds at most
+    gamma_N |X~|^T (S + du)."""
+    Xb = np.abs(bf16_round(X.toarray() if sp.issparse(X) else X))
+    Vb = np.abs(bf16_round(V))
+    N, F = Xb.shape
+
+    def gamma(n):
+        e = n * 2.0 ** -24
+        return e / (1.0 - e)
+
+    S = Xb @ Vb
+    du = 2.0 ** -7 * S + 2.0 * gamma(F) * S
+    return Xb.T @ du + gamma(N) * (Xb.T @ (S + du))

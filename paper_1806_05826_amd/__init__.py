@@ -31,12 +31,17 @@ RR_OK, RR_ERR_INVALID_ARG, RR_ERR_DEVICE = 0, 1, 2
 RR_ERR_NOT_CONVERGED, RR_ERR_BREAKDOWN, RR_ERR_UNSUPPORTED = 4, 5, 6
 PRECOND = {"none": 0, "jacobi": 1, "vcycle": 2, "additive": 3, "learned": 4}
 KRYLOV = {"pcg": 0, "fcg": 1}
-PRECISION = {"f64": 0, "f32_ir": 1}
+PRECISION = {"f64": 0, "f32_ir": 1, "bf16_ir": 2}
 
 
 class rr_csr(C.Structure):
     _fields_ = [("n_rows", C.c_int64), ("n_cols", C.c_int64), ("nnz", C.c_int64),
                 ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("values", C.c_void_p)]
+
+
+class rr_dense(C.Structure):
+    _fields_ = [("n_rows", C.c_int64), ("n_cols", C.c_int64), ("ld", C.c_int64),
+                ("values", C.c_void_p)]
 
 
 class rr_setup_opts(C.Structure):
@@ -50,7 +55,7 @@ class rr_setup_info(C.Structure):
                 ("n_coarse", C.c_int32), ("n_centres", C.c_int32), ("kmeans_iters", C.c_int32),
                 ("binary", C.c_int32), ("setup_ms", C.c_double), ("kmeans_ms", C.c_double),
                 ("plan_ms", C.c_double), ("tuned_rows_div", C.c_int32),
-                ("tuned_cols_div", C.c_int32), ("tune_cached", C.c_int32), ("pad_", C.c_int32)]
+                ("tuned_cols_div", C.c_int32), ("tune_cached", C.c_int32), ("dense", C.c_int32)]
 
 
 class rr_solve_opts(C.Structure):
@@ -96,6 +101,11 @@ _SIGS = {
     "rr_coarse_gram": [_P, _P, _P],
     "rr_coarse_factor": [_P, C.c_double, _P, _P, _P],
     "rr_smoother_weight": [_P, C.c_double, C.POINTER(C.c_double)],
+    "rr_setup_dense": [C.POINTER(rr_dense), C.POINTER(rr_setup_opts), _P, C.POINTER(_P)],
+    "rr_solve_block": [_P, C.c_double, C.c_int32, _P, C.c_int64, _P, C.c_int64,
+                       C.POINTER(rr_solve_opts), _P, _P],
+    "rr_apply_operator_block": [_P, C.c_double, C.c_int32, _P, C.c_int64, _P, C.c_int64,
+                                C.c_int32, _P],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -162,6 +172,67 @@ def rr_setup(row_ptr, col_idx, values, n_cols, n_clusters=0, seed=0, kmeans_max_
     h = C.c_void_p()
     _check(_lib.rr_setup(C.byref(X), C.byref(o), _stream(stream), C.byref(h)))
     return h.value
+
+
+def _rows_f64(t, name):
+    """A (count, n) float64 CUDA tensor whose rows are the block's columns."""
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.dim() == 2 and t.stride(1) == 1):
+        raise ValueError(f"{name}: need a 2-D float64 CUDA tensor with unit column stride")
+    return t
+
+
+def rr_setup_dense(X, n_clusters=0, seed=0, kmeans_max_iter=0, labels_in=None, n_labels_in=0,
+                   lambda_slots=0, stream=None):
+    """X: (N, F) float32 CUDA tensor with unit column stride (row-major).
+    Returns an opaque handle (int)."""
+    import torch
+    if not (X.is_cuda and X.dtype == torch.float32 and X.dim() == 2 and X.stride(1) == 1):
+        raise ValueError("X: need a 2-D float32 CUDA tensor with unit column stride")
+    if labels_in is not None and not (labels_in.is_cuda and labels_in.dtype == torch.int32):
+        raise ValueError("labels_in: need an int32 CUDA tensor")
+    D = rr_dense(X.shape[0], X.shape[1], X.stride(0), _ptr(X))
+    o = rr_setup_opts(int(n_clusters), int(kmeans_max_iter), int(seed) & (2**64 - 1),
+                      _ptr(labels_in), int(n_labels_in), int(lambda_slots), 0)
+    h = C.c_void_p()
+    _check(_lib.rr_setup_dense(C.byref(D), C.byref(o), _stream(stream), C.byref(h)))
+    return h.value
+
+
+def rr_solve_block(h, lam, rhs, w, tol=0.0, max_iter=0, fixed_iters=0, precond="vcycle",
+                   rhs_is_b=False, omega=0.0, precision="f64", inner_tol=0.0, stream=None,
+                   raise_on=(RR_ERR_INVALID_ARG, RR_ERR_DEVICE, RR_ERR_UNSUPPORTED)):
+    """rhs: (m, N) (or (m, F) with rhs_is_b), w: (m, F); row c is column c
+    of the block.  Returns (status, [info dict per column])."""
+    _rows_f64(rhs, "rhs")
+    _rows_f64(w, "w")
+    m = rhs.shape[0]
+    if w.shape[0] != m:
+        raise ValueError("rhs and w need the same number of rows")
+    o = rr_solve_opts(float(tol), int(max_iter), int(fixed_iters),
+                      PRECOND[precond] if isinstance(precond, str) else int(precond),
+                      1 if rhs_is_b else 0, float(omega), None, 0.0, None, 0, 0, 0, 0,
+                      PRECISION[precision] if isinstance(precision, str) else int(precision),
+                      0, float(inner_tol))
+    infos = (rr_solve_info * max(m, 1))()
+    st = _lib.rr_solve_block(C.c_void_p(h), float(lam), int(m), _ptr(rhs), C.c_int64(rhs.stride(0)),
+                             _ptr(w), C.c_int64(w.stride(0)), C.byref(o), C.cast(infos, C.c_void_p),
+                             _stream(stream))
+    if st in raise_on:
+        raise RRError(st, rr_last_error())
+    return st, [{f: getattr(infos[i], f) for f, _ in rr_solve_info._fields_} for i in range(m)]
+
+
+def rr_apply_operator_block(h, lam, v, q, precision="f64", stream=None):
+    """q[c] = (X^T X + lam I) v[c] for the rows of v (m, F); q (m, F)."""
+    _rows_f64(v, "v")
+    _rows_f64(q, "q")
+    if v.shape != q.shape:
+        raise ValueError("v and q need the same shape")
+    _check(_lib.rr_apply_operator_block(
+        C.c_void_p(h), float(lam), int(v.shape[0]), _ptr(v), C.c_int64(v.stride(0)), _ptr(q),
+        C.c_int64(q.stride(0)), PRECISION[precision] if isinstance(precision, str) else int(precision),
+        _stream(stream)))
 
 
 def rr_destroy(h):
@@ -439,3 +510,58 @@ class Ridge:
 
     def smoother_weight(self, lam):
         return rr_smoother_weight(self.h, lam)
+
+
+class DenseRidge(Ridge):
+    """A handle over dense X (N x F, FP32) for blocks of right-hand sides.
+    ``X`` is a host array or a CUDA tensor; it is copied to the device as
+    float32 and handed to rr_setup_dense."""
+
+    def __init__(self, X, n_clusters=0, seed=0, kmeans_max_iter=0, labels=None, lambda_slots=0,
+                 device="cuda"):
+        import numpy as np
+        import torch
+        self.device = torch.device(device)
+        Xt = torch.as_tensor(X, dtype=torch.float32, device=self.device).contiguous()
+        self.N, self.F = Xt.shape
+        lab = None
+        nlab = 0
+        if labels is not None:
+            lab = torch.as_tensor(np.asarray(labels, dtype=np.int32), device=self.device)
+            nlab = int(np.max(labels)) + 1 if len(labels) else 1
+        self.h = rr_setup_dense(Xt, n_clusters, seed, kmeans_max_iter, lab, nlab, lambda_slots)
+        torch.cuda.current_stream().synchronize()
+        del Xt
+        self.info = rr_get_setup_info(self.h)
+
+    def _block(self, v, n):
+        import torch
+        t = torch.as_tensor(v, dtype=torch.float64, device=self.device)
+        if t.dim() == 1:
+            t = t[None, :]
+        t = t.contiguous()
+        if t.shape[1] != n:
+            raise ValueError(f"expected rows of {n} entries")
+        return t
+
+    def solve_block(self, lam, Y, rhs_is_b=False, **kw):
+        """Y: (m, N) targets (or (m, F) right-hand sides); returns (W (m, F), infos)."""
+        import torch
+        rhs = self._block(Y, self.F if rhs_is_b else self.N)
+        w = torch.empty(rhs.shape[0], self.F, dtype=torch.float64, device=self.device)
+        st, infos = rr_solve_block(self.h, lam, rhs, w, rhs_is_b=rhs_is_b, **kw)
+        return w, infos
+
+    def solve(self, lam, y, rhs_is_b=False, **kw):
+        w, infos = self.solve_block(lam, y, rhs_is_b=rhs_is_b, **kw)
+        return w[0], infos[0]
+
+    def apply_operator_block(self, lam, V, precision="f64"):
+        import torch
+        v = self._block(V, self.F)
+        q = torch.empty_like(v)
+        rr_apply_operator_block(self.h, lam, v, q, precision)
+        return q
+
+    def apply_operator(self, lam, v):
+        return self.apply_operator_block(lam, v)[0]

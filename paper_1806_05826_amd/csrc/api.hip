@@ -174,6 +174,7 @@ void destroy_handle(rr_handle* h) {
     delete h->pw;
   }
   free_mlp(h->mlp);
+  dense_free(h);
   free_work(h->w);
   for (Work* w : h->extra_sets) {
     free_work(*w);
@@ -302,6 +303,15 @@ rr_status check_handle(const rr_handle* h) {
   return RR_OK;
 }
 
+// Calls built on the sparse operator.
+rr_status check_sparse(const rr_handle* h) {
+  RR_TRY(check_handle(h));
+  if (h->dense)
+    return fail(RR_ERR_UNSUPPORTED, "not available for a dense handle (use rr_solve_block, "
+                                    "rr_apply_operator_block)");
+  return RR_OK;
+}
+
 rr_status check_lambda(double lam, bool allow_zero) {
   if (!std::isfinite(lam) || lam < 0.0 || (!allow_zero && lam == 0.0))
     return fail(RR_ERR_INVALID_ARG, "lambda must be finite and > 0");
@@ -368,12 +378,16 @@ rr_status omega_power(rr_handle* h, const Sparse& X, double lam, double* omega, 
   for (int it = 0; it < 30; ++it) {
     // t = A (s v / rho); v = s t
     k_pw_scale<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, p.v, p.D, it ? p.nrm : nullptr, p.vin);
-    launch_csr(X, p.vin, p.u, nullptr, s);
-    Epi e{};
-    e.lam = lam;
-    e.p = p.vin;
-    e.out = p.t;
-    launch_csc(X, p.u, EPI_APPLY, e, nullptr, s);
+    if (h->dense) {
+      RR_TRY(dense_apply_one(h, p.vin, lam, p.t, s));
+    } else {
+      launch_csr(X, p.vin, p.u, nullptr, s);
+      Epi e{};
+      e.lam = lam;
+      e.p = p.vin;
+      e.out = p.t;
+      launch_csc(X, p.u, EPI_APPLY, e, nullptr, s);
+    }
     k_pw_post<<<g, kBlock, 0, s>>>(F, p.t, p.D, p.v, p.parts);
     k_pw_norm<<<1, kBlock, 0, s>>>(p.parts, g, p.nrm);
   }
@@ -1182,8 +1196,10 @@ rr_status solve_batched_impl(int nprob, rr_handle* const* hs, const double* lams
   if (op.precision != RR_PREC_F64)
     return fail(RR_ERR_UNSUPPORTED, "batched solves run in FP64");
   op.profile = 0;
-  for (int i = 0; i < nprob; ++i)
+  for (int i = 0; i < nprob; ++i) {
     if (!hs[i]) return fail(RR_ERR_INVALID_ARG, "null handle in batch");
+    RR_TRY(check_sparse(hs[i]));
+  }
   std::vector<int> wave(nprob, 0), set(nprob, 0);
   int nwaves = 0;
   for (int i = 0; i < nprob; ++i) {
@@ -1257,6 +1273,13 @@ rr_status solve_batched_impl(int nprob, rr_handle* const* hs, const double* lams
 
 }  // namespace
 
+namespace rr {
+rr_status get_slot_dense(rr_handle* h, double lam, LambdaSlot** out, hipStream_t s) {
+  double ms = 0.0;
+  return get_slot(h, h->w.X, lam, out, &ms, s);
+}
+}  // namespace rr
+
 extern "C" {
 
 const char* rr_last_error(void) { return g_last_error.c_str(); }
@@ -1288,6 +1311,52 @@ rr_status rr_setup(const rr_csr* X, const rr_setup_opts* opts, rr_stream stream,
   return RR_OK;
 }
 
+rr_status rr_setup_dense(const rr_dense* X, const rr_setup_opts* opts, rr_stream stream,
+                         rr_handle** out) {
+  g_last_error.clear();
+  if (!X || !out) return fail(RR_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (opts && (opts->n_clusters < 0 || opts->kmeans_max_iter < 0 || opts->lambda_slots < 0))
+    return fail(RR_ERR_INVALID_ARG, "negative option");
+  rr_handle* h = new (std::nothrow) rr_handle();
+  if (!h) return fail(RR_ERR_DEVICE, "out of host memory");
+  const double t0 = now_ms();
+  hipStream_t s = (hipStream_t)stream;
+  rr_status st = RR_OK;
+  if (hipGetDevice(&h->device) != hipSuccess) st = fail(RR_ERR_DEVICE, "hipGetDevice failed");
+  if (st == RR_OK) st = dense_setup(h, X, opts, s);
+  if (st != RR_OK) {
+    const std::string msg = g_last_error;
+    (void)hipStreamSynchronize(s);
+    destroy_handle(h);
+    g_last_error = msg;
+    return st;
+  }
+  h->setup_ms = now_ms() - t0;
+  *out = h;
+  return RR_OK;
+}
+
+rr_status rr_solve_block(rr_handle* h, double lambda, int32_t nrhs, const double* rhs,
+                         int64_t ld_rhs, double* w, int64_t ld_w, const rr_solve_opts* opts,
+                         rr_solve_info* info, rr_stream stream) {
+  g_last_error.clear();
+  RR_TRY(check_handle(h));
+  RR_TRY(check_lambda(lambda, false));
+  if (!h->dense) return fail(RR_ERR_UNSUPPORTED, "rr_solve_block takes a handle from rr_setup_dense");
+  return dense_solve_block(h, lambda, nrhs, rhs, ld_rhs, w, ld_w, opts, info, (hipStream_t)stream);
+}
+
+rr_status rr_apply_operator_block(rr_handle* h, double lambda, int32_t nrhs, const double* v,
+                                  int64_t ldv, double* q, int64_t ldq, int32_t precision,
+                                  rr_stream stream) {
+  g_last_error.clear();
+  RR_TRY(check_handle(h));
+  RR_TRY(check_lambda(lambda, true));
+  if (!h->dense) return fail(RR_ERR_UNSUPPORTED, "rr_apply_operator_block takes a handle from rr_setup_dense");
+  return dense_apply_block(h, lambda, nrhs, v, ldv, q, ldq, precision, (hipStream_t)stream);
+}
+
 rr_status rr_destroy(rr_handle* h) {
   if (!h) return RR_OK;
   (void)hipDeviceSynchronize();
@@ -1312,6 +1381,8 @@ rr_status rr_get_setup_info(const rr_handle* h, rr_setup_info* info) {
   i.tuned_rows_div = h->tuning.div_rows;
   i.tuned_cols_div = h->tuning.div_cols;
   i.tune_cached = h->tuning.cached;
+  i.dense = h->dense ? 1 : 0;
+  if (h->dense) i.nnz = (int64_t)h->X.N * h->X.F;
   *info = i;
   return RR_OK;
 }
@@ -1338,7 +1409,7 @@ rr_status rr_get_centres(const rr_handle* h, int32_t* centres, rr_stream stream)
 rr_status rr_solve(rr_handle* h, double lambda, const double* rhs, double* w,
                    const rr_solve_opts* opts, rr_solve_info* info, rr_stream stream) {
   g_last_error.clear();
-  RR_TRY(check_handle(h));
+  RR_TRY(check_sparse(h));
   return solve_impl(h, lambda, rhs, w, opts, info, (hipStream_t)stream);
 }
 
@@ -1351,7 +1422,7 @@ rr_status rr_solve_batched(int32_t nprob, rr_handle* const* handles, const doubl
 
 rr_status rr_apply_operator(rr_handle* h, double lambda, const double* v, double* Av,
                             rr_stream stream) {
-  RR_TRY(check_handle(h));
+  RR_TRY(check_sparse(h));
   RR_TRY(check_lambda(lambda, true));
   if (!v || !Av) return fail(RR_ERR_INVALID_ARG, "null vector");
   hipStream_t s = (hipStream_t)stream;
@@ -1369,7 +1440,7 @@ rr_status rr_apply_operator(rr_handle* h, double lambda, const double* v, double
 }
 
 rr_status rr_apply_rhs(rr_handle* h, const double* y, double* b, rr_stream stream) {
-  RR_TRY(check_handle(h));
+  RR_TRY(check_sparse(h));
   if (!y || !b) return fail(RR_ERR_INVALID_ARG, "null vector");
   Epi e{};
   e.out = h->w.vout;
@@ -1381,7 +1452,7 @@ rr_status rr_apply_rhs(rr_handle* h, const double* y, double* b, rr_stream strea
 
 rr_status rr_apply_precond(rr_handle* h, double lambda, int32_t precond, double omega,
                            const double* r, double* z, rr_stream stream) {
-  RR_TRY(check_handle(h));
+  RR_TRY(check_sparse(h));
   RR_TRY(check_lambda(lambda, false));
   if (!r || !z) return fail(RR_ERR_INVALID_ARG, "null vector");
   if (precond < 0 || precond > 3) return fail(RR_ERR_INVALID_ARG, "unknown preconditioner");
@@ -1443,7 +1514,7 @@ rr_status rr_coarse_factor(rr_handle* h, double lambda, double* L, double* Ainv,
 }
 
 rr_status rr_mlp_init(rr_handle* h, int32_t hidden, uint64_t seed) {
-  RR_TRY(check_handle(h));
+  RR_TRY(check_sparse(h));
   if (h->FC == 0) return fail(RR_ERR_INVALID_ARG, "no coarse level");
   if (hidden < 16 || hidden > 1024) return fail(RR_ERR_INVALID_ARG, "hidden must be in [16, 1024]");
   RR_HIP(hipDeviceSynchronize());
@@ -1583,7 +1654,7 @@ rr_status rr_mlp_train(rr_handle* h, const float* in, const float* target, int64
 rr_status rr_collect_pairs(rr_handle* h, const double* lambdas, int32_t n_solves,
                            int32_t pairs_per_solve, int32_t every, const double* y, float* inputs,
                            float* targets, int64_t* n_pairs, rr_stream stream) {
-  RR_TRY(check_handle(h));
+  RR_TRY(check_sparse(h));
   if (h->FC == 0) return fail(RR_ERR_INVALID_ARG, "no coarse level");
   if (n_solves < 0 || pairs_per_solve < 1 || every < 1 || !lambdas || !y || !inputs || !targets)
     return fail(RR_ERR_INVALID_ARG, "bad pair-collection arguments");

@@ -249,6 +249,44 @@ struct Work {
   hipStream_t stream = nullptr;   // batched solves: this set's stream
 };
 
+// Dense X (rr_setup_dense).  Four resident copies, FP32 and BF16, row-major
+// and transposed, so that both products of the operator stream their first
+// operand along the contraction index; rows and columns are zero-padded to
+// multiples of kDensePad.
+constexpr int kDensePad = 128;
+struct DenseX {
+  int N = 0, F = 0, Np = 0, Fp = 0;
+  float* X32 = nullptr;       // [Np x Fp] row-major
+  float* XT32 = nullptr;      // [Fp x Np] row-major
+  uint16_t* Xb = nullptr;     // BF16 of X32
+  uint16_t* XTb = nullptr;    // BF16 of XT32
+  double* Xc = nullptr;       // [FC x Np] coarse columns X P (row s = column s of X P)
+};
+
+// Buffers of a block solve with up to m_cap right-hand sides.  F-blocks are
+// column-major with leading dimension Fp, N-blocks with Np; rows past F (N)
+// and columns past the solve's m are never written after the zero fill.
+struct DenseWork {
+  int m_cap = 0, nb = 0;      // nb = column partials per F-vector (blocks of 1024)
+  double *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr;
+  double *e1 = nullptr, *e2 = nullptr, *rho = nullptr, *b = nullptr;
+  double *wx = nullptr, *wr = nullptr;  // refinement: FP64 iterate and residual
+  double* D = nullptr;        // [Fp] Jacobi diagonal
+  uint16_t* vb = nullptr;     // BF16 copy of the operator's input block
+  uint16_t* ub = nullptr;     // BF16 U = X V  [Np x m_cap]
+  double* u = nullptr;        // FP64 U        [Np x m_cap]
+  void* part = nullptr;       // split-K partial sums
+  size_t part_bytes = 0;
+  double *c = nullptr, *yc = nullptr;   // coarse blocks [FC x m_cap]
+  double* parts = nullptr;    // column partials: 6 regions of [m_cap x nb]
+  double *rz = nullptr, *pq = nullptr, *alpha = nullptr, *beta = nullptr;
+  double *rr = nullptr, *bb = nullptr;  // per column
+  int *done = nullptr, *iters = nullptr, *status = nullptr;  // per column
+  int* done_in = nullptr;     // per column: finished before a solve starts
+  int* nactive = nullptr;     // device int: columns still iterating
+  int* nactive_host = nullptr;  // pinned mirror
+};
+
 }  // namespace rr
 
 struct rr_handle {
@@ -280,6 +318,8 @@ struct rr_handle {
     double *parts = nullptr, *nrm = nullptr;
   };
   PowerWork* pw = nullptr;
+  rr::DenseX* dense = nullptr;    // rr_setup_dense: X is dense (no sparse X)
+  rr::DenseWork* dwork = nullptr;
   rr::Work w;                     // work set 0
   std::vector<rr::Work*> extra_sets;   // work sets 1, 2, ... for concurrent solves
   int npartials = 0;
@@ -431,5 +471,20 @@ rr_status run_kmeans(rr_handle* h, int k, uint64_t seed, int max_iter, hipStream
 rr_status set_labels(rr_handle* h, const int* labels_in, int nlab, hipStream_t s);
 rr_status build_coarse_gram(rr_handle* h, hipStream_t s);
 rr_status build_coarse_gram_valued(rr_handle* h, hipStream_t s);   // (api.hip)
+
+// ---- dense X (dense.hip) -------------------------------------------------------
+rr_status dense_setup(rr_handle* h, const rr_dense* X, const rr_setup_opts* o, hipStream_t s);
+void dense_free(rr_handle* h);
+rr_status dense_coarse_gram(rr_handle* h, hipStream_t s);
+// t = A v + 0 (EPI_APPLY with lam) for one F-vector in FP64 (power iteration)
+rr_status dense_apply_one(rr_handle* h, const double* v, double lam, double* t, hipStream_t s);
+rr_status dense_solve_block(rr_handle* h, double lam, int m, const double* rhs, int64_t ld_rhs,
+                            double* w, int64_t ld_w, const rr_solve_opts* o, rr_solve_info* info,
+                            hipStream_t s);
+rr_status dense_apply_block(rr_handle* h, double lam, int m, const double* v, int64_t ldv,
+                            double* q, int64_t ldq, int precision, hipStream_t s);
+rr_status dense_kmeans(rr_handle* h, int k, uint64_t seed, int max_iter, hipStream_t s);
+// the cached coarse factor and smoother weight for lambda (api.hip)
+rr_status get_slot_dense(rr_handle* h, double lam, LambdaSlot** out, hipStream_t s);
 
 }  // namespace rr

@@ -1,0 +1,222 @@
+"""GPU parity of the dense-X path (rr_setup_dense / rr_solve_block /
+rr_apply_operator_block) against the CPU oracle on seeded block-correlated
+Gaussian features (datagen.block_correlated_dense), sizes with ragged tails
+against the 128-row and 128-column padding of the matrix-core tiles.
+
+Bars: FP64 operator within a rigorous summation bound of the oracle's; the
+BF16-operand operator within oracle.operator.apply_A_bf16_bound of its
+definition; K = P^T X^T X P to 1e-12 of max|K|; FP64 block solves: natural
+stops within the oracle's own spread under rounding-level changes +-1,
+converged iterates within 1e-10 per column; the
+BF16 refinement reaches the dense Cholesky solution to 1e-10."""
+import numpy as np
+import pytest
+
+import datagen
+from oracle import coarse, kmeans, krylov, operator as op, precond
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rr():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1806_05826_amd as rr
+    return rr
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def small(rr):
+    """1037 x 261, 37 blocks of 7 columns with correlation 0.9 inside a block
+    (plus 2 free columns): every GEMM dimension has a ragged tile."""
+    X = datagen.block_correlated_dense(1037, 37, 7, 0.9, seed=31)
+    X = np.concatenate([X, datagen.block_correlated_dense(1037, 2, 1, 0.0, seed=32)], axis=1)
+    print(f"[dense small] X {X.shape}", flush=True)
+    return X.astype(np.float32)
+
+
+def test_operator_f64_and_bf16(rr, small):
+    X = small.astype(np.float64)
+    R = rr.DenseRidge(small)
+    assert R.info["dense"] == 1 and R.info["nnz"] == X.size
+    rng = np.random.default_rng(5)
+    for m in (1, 37, 130):
+        V = rng.standard_normal((m, X.shape[1]))
+        Q = host(R.apply_operator_block(0.7, V))
+        for c in range(m):
+            want = op.apply_A(X, 0.7, V[c])
+            bound = 4 * (X.shape[0] + X.shape[1]) * 2.0**-53 * (np.abs(X).T @ (np.abs(X) @ np.abs(V[c])) + 0.7 * np.abs(V[c]))
+            assert np.all(np.abs(Q[c] - want) <= bound), (m, c)
+        Qb = host(R.apply_operator_block(0.7, V, precision="bf16_ir"))
+        want_b = op.apply_A_bf16(X, 0.7, V.T).T
+        bound_b = op.apply_A_bf16_bound(X, V.T).T + 1e-12 * np.abs(want_b)
+        assert np.all(np.abs(Qb - want_b) <= bound_b), m
+        # almost every U entry rounds the same way as the exact one
+        rel = np.abs(Qb - want_b) / np.abs(want_b).max()
+        assert np.median(rel) < 1e-5
+    R.close()
+
+
+def test_operator_lambda_zero_and_zero_block(rr, small):
+    R = rr.DenseRidge(small)
+    V = np.zeros((3, small.shape[1]))
+    assert np.all(host(R.apply_operator_block(0.0, V)) == 0.0)
+    V[1, 5] = 1.0
+    q = host(R.apply_operator_block(0.0, V))[1]
+    X = small.astype(np.float64)
+    assert np.allclose(q, X.T @ X[:, 5], rtol=1e-12, atol=1e-9)
+    R.close()
+
+
+@pytest.fixture(scope="module")
+def clustered(rr, small):
+    lab, fc, _, _ = kmeans.kmeans_features(small.astype(np.float64), 40, 3, binary=False)
+    print(f"[dense clustered] F_C={fc}", flush=True)
+    R = rr.DenseRidge(small, labels=lab)
+    yield small.astype(np.float64), lab, fc, R
+    R.close()
+
+
+def test_coarse_gram_and_weight(rr, clustered):
+    X, lab, fc, R = clustered
+    assert R.info["n_coarse"] == fc
+    assert np.array_equal(host(R.labels()), lab)
+    K_or = coarse.coarse_gram(X, lab, fc)
+    K = host(R.coarse_gram())
+    assert np.abs(K - K_or).max() <= 1e-12 * np.abs(K_or).max()
+    for lam in (0.1, 10.0):
+        om = R.smoother_weight(lam)
+        om_or = op.omega_power(X, lam, seed=0x5eed)
+        assert abs(om - om_or) <= 1e-10 * om_or
+
+
+def oracle_spread(X, b, lam, kind, lab, fc, omega, tol, n=8, seed=0):
+    """Iteration counts of the oracle under rounding-level changes: the
+    operator through the Gram matrix (another summation order) on odd runs,
+    the diagonal (or an identity scaling for CG) perturbed by at most 2 ulp,
+    and for the two-level forms also the coarse solve through an explicit
+    inverse.  Near a residual plateau the natural stop spans this range."""
+    F = X.shape[1]
+    rng = np.random.default_rng(seed)
+    G = X.T @ X
+    its = []
+    for t in range(n):
+        pert = np.ones(F) if t == 0 else 1.0 + (rng.random(F) - 0.5) * 4 * 2**-53
+        A = (lambda v: G @ v + lam * v) if t % 2 else (lambda v: op.apply_A(X, lam, v))
+        if kind == "none":
+            B = lambda r, pert=pert: r * pert
+        elif kind == "jacobi":
+            D = op.jacobi_diagonal(X, lam) * pert
+            B = lambda r, D=D: r / D
+        else:
+            tl = precond.TwoLevel(X, lam, lab, fc, omega)
+            tl.D = tl.D * pert
+            if t == 2:
+                Ai = np.linalg.inv(tl.Ac)
+                tl.coarse_correction = lambda r, tl=tl, Ai=Ai: tl.P @ (Ai @ (tl.P.T @ r))
+            B = tl.vcycle if kind == "vcycle" else tl.additive
+        _, inf = krylov.pcg(A, b, B, tol=tol, max_iter=20000)
+        its.append(inf.iters)
+    return min(its), max(its)
+
+
+@pytest.mark.parametrize("kind", ["vcycle", "additive", "jacobi", "none"])
+def test_block_solve_f64_parity(rr, clustered, kind):
+    """(P2) natural stop at relative residual 1e-10: each column's count
+    within the oracle's own spread under rounding-level changes, +-1; (P1)
+    at the oracle's count for a residual of 1e-12 the block iterate equals
+    the oracle's to 1e-10 per column."""
+    X, lab, fc, R = clustered
+    lam = 0.1
+    _, Y = datagen.targets(X, 77, n_rhs=9)
+    Y = Y.T.copy()                      # (m, N)
+    om = op.omega_power(X, lam, seed=0x5eed)
+    tol = 1e-10
+    W, infos = R.solve_block(lam, Y, precond=kind, tol=tol, max_iter=20000)
+    kfix = 0
+    for c in range(Y.shape[0]):
+        lo, hi = oracle_spread(X, op.rhs(X, Y[c]), lam, kind, lab, fc, om, tol, seed=c)
+        k = infos[c]["iters"]
+        print(f"[dense {kind}] col {c}: gpu {k} its, oracle {lo}..{hi}", flush=True)
+        assert infos[c]["status"] == 0
+        assert lo - 1 <= k <= hi + 1
+        assert infos[c]["true_relres"] <= 10 * tol
+        _, inf12 = krylov.solve(X, Y[c], lam, kind, lab, fc, omega=om, tol=1e-12, max_iter=20000)
+        kfix = max(kfix, inf12.iters)
+    W, infos = R.solve_block(lam, Y, precond=kind, fixed_iters=kfix)
+    W = host(W)
+    for c in range(Y.shape[0]):
+        x_or, _ = krylov.solve(X, Y[c], lam, kind, lab, fc, omega=om, fixed_iters=kfix)
+        assert infos[c]["iters"] == kfix
+        assert np.linalg.norm(W[c] - x_or) <= 1e-10 * np.linalg.norm(x_or), c
+
+
+def test_block_solve_fixed_iterations(rr, clustered):
+    """Three V(1,1) iterations: the GPU iterate is the oracle's up to rounding."""
+    X, lab, fc, R = clustered
+    lam = 0.1
+    _, Y = datagen.targets(X, 78, n_rhs=4)
+    Y = Y.T.copy()
+    om = op.omega_power(X, lam, seed=0x5eed)
+    W, infos = R.solve_block(lam, Y, precond="vcycle", fixed_iters=3)
+    W = host(W)
+    for c in range(4):
+        x_or, inf = krylov.solve(X, Y[c], lam, "vcycle", lab, fc, omega=om, fixed_iters=3)
+        assert infos[c]["iters"] == 3
+        assert np.linalg.norm(W[c] - x_or) <= 1e-11 * np.linalg.norm(x_or)
+
+
+def test_block_solve_bf16_refinement(rr, clustered):
+    X, lab, fc, R = clustered
+    lam = 0.1
+    _, Y = datagen.targets(X, 79, n_rhs=6)
+    Y = Y.T.copy()
+    W, infos = R.solve_block(lam, Y, precond="vcycle", precision="bf16_ir", tol=1e-13)
+    W = host(W)
+    for c in range(6):
+        w_star = krylov.reference_solution(X, Y[c], lam)
+        err = np.linalg.norm(W[c] - w_star) / np.linalg.norm(w_star)
+        print(f"[dense bf16 IR] col {c}: {infos[c]['ir_steps']} steps, {infos[c]['iters']} its, "
+              f"err {err:.2e}", flush=True)
+        assert infos[c]["status"] == 0 and infos[c]["ir_steps"] >= 2
+        assert err <= 1e-10
+
+
+def test_block_solve_edges(rr, clustered):
+    X, lab, fc, R = clustered
+    F = X.shape[1]
+    rng = np.random.default_rng(9)
+    B = rng.standard_normal((3, F))
+    B[1] = 0.0                                   # a zero right-hand side
+    W, infos = R.solve_block(1.0, B, rhs_is_b=True, precond="vcycle", tol=1e-13)
+    W = host(W)
+    assert infos[1]["iters"] == 0 and np.all(W[1] == 0.0)
+    A = X.T @ X + np.eye(F)
+    for c in (0, 2):
+        ref = np.linalg.solve(A, B[c])
+        assert np.linalg.norm(W[c] - ref) <= 1e-10 * np.linalg.norm(ref)
+    w1, info1 = R.solve(1.0, B[0], rhs_is_b=True, precond="vcycle", tol=1e-13)
+    assert np.linalg.norm(host(w1) - W[0]) <= 1e-12 * np.linalg.norm(W[0])
+
+
+def test_dense_errors(rr, small):
+    R = rr.DenseRidge(small)
+    with pytest.raises(rr.RRError) as e:          # no coarse level
+        R.solve_block(1.0, np.ones((1, small.shape[0])), precond="vcycle")
+    assert e.value.status == rr.RR_ERR_INVALID_ARG
+    with pytest.raises(rr.RRError) as e:          # sparse-only call
+        rr.rr_apply_rhs(R.h, torch.zeros(small.shape[0], dtype=torch.float64, device="cuda"),
+                        torch.zeros(small.shape[1], dtype=torch.float64, device="cuda"))
+    assert e.value.status == rr.RR_ERR_UNSUPPORTED
+    bad = small.copy()
+    bad[3, 4] = np.nan
+    with pytest.raises(rr.RRError) as e:
+        rr.DenseRidge(bad)
+    assert e.value.status == rr.RR_ERR_INVALID_ARG
+    R.close()

@@ -205,3 +205,35 @@ def test_exact_argmin_against_fractions():
     num = np.array([[3 * 10**12, 3 * 10**12 - 1]], dtype=np.int64)
     den = np.array([10**10, 10**10], dtype=np.int64)
     assert exact_argmin(num, den, np.array([True, True]))[0] == 1
+
+
+def test_bf16_round_ties_and_specials():
+    """Round to nearest, ties to even, at 8 significant bits; FP32 range."""
+    v = np.array([1.0, 1 + 2**-8, 1 + 3 * 2**-8, 1 + 2**-8 + 2**-20, -(1 + 3 * 2**-8),
+                  65504.0, 0.0, np.inf, -np.inf, 2.0**100 * (1 + 2**-9)])
+    want = np.array([1.0, 1.0, 1 + 2**-6, 1 + 2**-7, -(1 + 2**-6), 65536.0, 0.0, np.inf,
+                     -np.inf, 2.0**100])
+    assert np.array_equal(op.bf16_round(v), want)
+    # every BF16 value is a fixed point; neighbours 2^-7 apart at 1
+    r = np.random.default_rng(3).standard_normal(1000)
+    b = op.bf16_round(r)
+    assert np.array_equal(op.bf16_round(b), b)
+    assert np.all(np.abs(b - r) <= 2.0**-8 * np.abs(r) * (1 + 2**-20))
+
+
+def test_bf16_operator_bound_covers_a_perturbed_sum():
+    """The bound admits the FP32-summed operator on random data and is tight
+    enough to reject a transposed operand."""
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((60, 20)).astype(np.float32).astype(np.float64)
+    V = rng.standard_normal((20, 3))
+    Q = op.apply_A_bf16(X, 0.5, V)
+    B = op.apply_A_bf16_bound(X, V)
+    Xb = op.bf16_round(X)
+    U32 = (Xb.astype(np.float32) @ op.bf16_round(V).astype(np.float32)).astype(np.float64)
+    Q32 = (Xb.T.astype(np.float32) @ op.bf16_round(U32).astype(np.float32)).astype(np.float64) + 0.5 * V
+    assert np.all(np.abs(Q32 - Q) <= B)
+    Xs = X.copy()
+    Xs[:, [0, 1]] = Xs[:, [1, 0]]                # a swapped pair of columns
+    assert np.any(np.abs(op.apply_A_bf16(Xs, 0.5, V) - Q) > B)
+    assert B.max() < 0.1 * np.abs(Q).max()
