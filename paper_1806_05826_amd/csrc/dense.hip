@@ -1211,9 +1211,254 @@ rr_status dense_solve_block(rr_handle* h, double lam, int m, const double* rhs, 
   return RR_OK;
 }
 
+// ---- k-means++ over the columns of a dense X (FP64) -----------------------------
+//
+// The clustering section's K-means++ with Euclidean distances, on the
+// columns x_j in R^N.  Seeding: ||x_j - x_c||^2 = c_j + c_c - 2 x_j^T x_c
+// (clamped at 0, exactly 0 for j = c), the next centre is the first j whose
+// inclusive prefix of D^2 exceeds u T (u the next SplitMix64 draw in [0, 1),
+// T the total).  Lloyd: mu_s = mean of the member columns, score_js =
+// ||mu_s||^2 - 2 x_j^T mu_s (||x_j||^2 dropped), the lowest s on ties, stop
+// when no label changes.  Sums run in FP64 in another order than a CPU
+// implementation, so labels agree with one up to near-ties.
+
+namespace {
+
+struct SeedState {
+  int stop;        // T = 0 reached: no further centre
+  int n_centres;
+  int last;        // the newest centre
+  int pad;
+};
+
+// d2_j = min(d2_j, c_j + c_c - 2 x_j^T x_c) for the newest centre c
+// (first = 1: d2_j = that distance).  One wave per feature.
+__global__ __launch_bounds__(256) void k_km_dist(int F, int N, const float* __restrict__ XT, long long ld,
+                                                 const double* __restrict__ cn, const SeedState* st,
+                                                 double* __restrict__ d2, int first) {
+  if (st->stop) return;
+  const int c = st->last;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (j >= F) return;
+  const float* xj = XT + (long long)j * ld;
+  const float* xc = XT + (long long)c * ld;
+  double g = 0.0;
+  for (int i = lane; i < N; i += 64) g += (double)xj[i] * (double)xc[i];
+  for (int off = 32; off > 0; off >>= 1) g += __shfl_xor(g, off, 64);
+  if (lane == 0) {
+    double d = (j == c) ? 0.0 : cn[j] + cn[c] - 2.0 * g;
+    if (d < 0.0) d = 0.0;
+    d2[j] = first ? d : fmin(d2[j], d);
+  }
+}
+
+// One block: T = sum d2 (chunks in a fixed order), r = u T, and the first j
+// whose inclusive prefix exceeds r becomes centre `slot`; T = 0 stops the
+// seeding.
+constexpr int kDrawThreads = 1024;
+__global__ __launch_bounds__(kDrawThreads) void k_km_draw(int F, const double* __restrict__ d2,
+                                                          const double* __restrict__ u, int slot,
+                                                          int* centres, SeedState* st) {
+  __shared__ double pre[kDrawThreads];
+  __shared__ double total;
+  __shared__ int pick, stopped;
+  const int t = threadIdx.x;
+  if (t == 0) {
+    stopped = st->stop;
+    pick = F;
+  }
+  __syncthreads();
+  if (stopped) return;
+  const int L = (F + kDrawThreads - 1) / kDrawThreads;
+  const int j0 = min(F, t * L), j1 = min(F, j0 + L);
+  double sum = 0.0;
+  for (int j = j0; j < j1; ++j) sum += d2[j];
+  pre[t] = sum;
+  __syncthreads();
+  if (t == 0) {   // exclusive prefix of the chunk sums, in chunk order
+    double run = 0.0;
+    for (int i = 0; i < kDrawThreads; ++i) {
+      const double v = pre[i];
+      pre[i] = run;
+      run += v;
+    }
+    total = run;
+  }
+  __syncthreads();
+  if (!(total > 0.0)) {
+    if (t == 0) st->stop = 1;
+    return;
+  }
+  const double r = u[slot - 1] * total;
+  double run = pre[t];
+  for (int j = j0; j < j1; ++j) {
+    const double nx = run + d2[j];
+    if (nx > r && run <= r) atomicMin(&pick, j);
+    run = nx;
+  }
+  __syncthreads();
+  if (t == 0) {
+    const int j = min(pick, F - 1);
+    centres[slot] = j;
+    st->last = j;
+    st->n_centres = slot + 1;
+  }
+}
+
+__global__ void k_km_first(int c, int* centres, SeedState* st) {
+  centres[0] = c;
+  st->stop = 0;
+  st->n_centres = 1;
+  st->last = c;
+}
+
+// labels: centre s -> s, every other feature -1
+__global__ void k_km_init_labels(int F, int* labels) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < F) labels[j] = -1;
+}
+__global__ void k_km_set_centres(int nc, const int* centres, int* labels) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < nc) labels[centres[s]] = s;
+}
+
+// mu[s][i] = (1 / n_s) sum_{j in s} X[i][j]  (rows of X^T); ||mu_s||^2 later
+__global__ void k_km_means(int N, const float* XT, long long ld, const int* perm, const int* off,
+                           double* mu) {
+  const int s = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int a = off[s], b = off[s + 1];
+  double t = 0.0;
+  for (int e = a; e < b; ++e) t += (double)XT[(long long)perm[e] * ld + i];
+  mu[(long long)s * ld + i] = (b > a) ? t / (double)(b - a) : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_km_norms(int N, const double* mu, long long ld, double* q) {
+  const double* m = mu + (long long)blockIdx.x * ld;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < N; i += 256) v += m[i] * m[i];
+  __shared__ double red[4];
+  const double t = block_sum_n<256>(v, red);
+  if (threadIdx.x == 0) q[blockIdx.x] = t;
+}
+
+// new label = argmin over active s of q_s - 2 G_js (lowest s on ties);
+// counts changes
+__global__ void k_km_assign(int F, int k, const double* __restrict__ G, long long ldg,
+                            const double* __restrict__ q, const int* __restrict__ off, int* labels,
+                            int* changed) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= F) return;
+  double best = __builtin_inf();
+  int bs = -1;
+  for (int s2 = 0; s2 < k; ++s2) {
+    if (off[s2 + 1] == off[s2]) continue;
+    const double v = q[s2] - 2.0 * G[(long long)s2 * ldg + j];
+    if (v < best) {
+      best = v;
+      bs = s2;
+    }
+  }
+  if (bs != labels[j]) {
+    labels[j] = bs;
+    atomicAdd(changed, 1);
+  }
+}
+
+}  // namespace
+
 rr_status dense_kmeans(rr_handle* h, int k, uint64_t seed, int max_iter, hipStream_t s) {
-  (void)h; (void)k; (void)seed; (void)max_iter; (void)s;
-  return fail(RR_ERR_UNSUPPORTED, "k-means for dense X: pass labels_in");
+  DenseX& d = *h->dense;
+  const int F = d.F, N = d.N;
+  k = std::min(k, F);
+  // seeding draws (host SplitMix64, as many as the seeding can use)
+  uint64_t st_rng = seed;
+  const int first = (int)(splitmix64_next(st_rng) % (uint64_t)F);
+  std::vector<double> u(std::max(k - 1, 1));
+  for (int i = 0; i + 1 < k; ++i) u[i] = (double)(splitmix64_next(st_rng) >> 11) * (1.0 / 9007199254740992.0);
+  double *d2 = nullptr, *du = nullptr;
+  SeedState* st = nullptr;
+  RR_TRY(zalloc(&d2, F));
+  RR_TRY(zalloc(&du, u.size()));
+  RR_TRY(zalloc(&st, 1));
+  RR_HIP(hipMemcpyAsync(du, u.data(), sizeof(double) * u.size(), hipMemcpyHostToDevice, s));
+  k_km_first<<<1, 1, 0, s>>>(first, h->centres, st);
+  const int gd = cdiv(F, 4);
+  k_km_dist<<<gd, 256, 0, s>>>(F, N, d.XT32, d.Np, h->colnorm, st, d2, 1);
+  for (int slot = 1; slot < k; ++slot) {
+    k_km_draw<<<1, kDrawThreads, 0, s>>>(F, d2, du, slot, h->centres, st);
+    if (slot + 1 < k) k_km_dist<<<gd, 256, 0, s>>>(F, N, d.XT32, d.Np, h->colnorm, st, d2, 0);
+  }
+  SeedState hs{};
+  RR_HIP(hipMemcpyAsync(&hs, st, sizeof(SeedState), hipMemcpyDeviceToHost, s));
+  RR_HIP(hipStreamSynchronize(s));
+  zfree(d2);
+  zfree(du);
+  zfree(st);
+  const int nc = hs.n_centres;
+  h->n_centres = nc;
+  // Lloyd
+  const int kp = (int)rup(nc, GD_N);
+  double *mu = nullptr, *q = nullptr, *G = nullptr, *part = nullptr;
+  int *labels = h->labels, *perm = nullptr, *off = nullptr, *changed = nullptr;
+  RR_TRY(zalloc(&mu, (size_t)kp * d.Np));
+  RR_TRY(zalloc(&q, kp));
+  RR_TRY(zalloc(&G, (size_t)kp * d.Fp));
+  RR_TRY(zalloc(&perm, F));
+  RR_TRY(zalloc(&off, nc + 1));
+  RR_TRY(zalloc(&changed, 1));
+  int S = 0, kc = 0;
+  pick_split((d.Fp / GD_M) * (kp / GD_N), d.Np, GD_K, &S, &kc);
+  const long long sstride = (long long)d.Fp * kp;
+  RR_TRY(zalloc(&part, (size_t)S * sstride));
+  k_km_init_labels<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, labels);
+  k_km_set_centres<<<cdiv(nc, kBlock), kBlock, 0, s>>>(nc, h->centres, labels);
+  std::vector<int> hl(F), hperm(F), hoff(nc + 1);
+  int it = 0;
+  rr_status res = RR_OK;
+  while (it < max_iter) {
+    // members per cluster (host counting sort of F labels)
+    RR_HIP(hipMemcpyAsync(hl.data(), labels, sizeof(int) * F, hipMemcpyDeviceToHost, s));
+    RR_HIP(hipStreamSynchronize(s));
+    std::fill(hoff.begin(), hoff.end(), 0);
+    for (int j = 0; j < F; ++j)
+      if (hl[j] >= 0) ++hoff[hl[j] + 1];
+    for (int c = 0; c < nc; ++c) hoff[c + 1] += hoff[c];
+    {
+      std::vector<int> pos(hoff.begin(), hoff.end() - 1);
+      for (int j = 0; j < F; ++j)
+        if (hl[j] >= 0) hperm[pos[hl[j]]++] = j;
+    }
+    RR_HIP(hipMemcpyAsync(perm, hperm.data(), sizeof(int) * F, hipMemcpyHostToDevice, s));
+    RR_HIP(hipMemcpyAsync(off, hoff.data(), sizeof(int) * (nc + 1), hipMemcpyHostToDevice, s));
+    k_km_means<<<dim3(cdiv(N, kBlock), nc), kBlock, 0, s>>>(N, d.XT32, d.Np, perm, off, mu);
+    k_km_norms<<<nc, 256, 0, s>>>(N, mu, d.Np, q);
+    // G = X^T mu  (F x nc, FP64 matrix cores)
+    if (d.Fp % GD_M || d.Np % GD_K || kc % GD_K) {
+      res = fail(RR_ERR_DEVICE, "internal: GEMM shape");
+      break;
+    }
+    k_gemm_f64<float><<<dim3(d.Fp / GD_M, kp / GD_N, S), 256, 0, s>>>(d.XT32, d.Np, mu, d.Np, part, d.Fp,
+                                                                        sstride, kc, d.Np);
+    DEpi e{};
+    e.out = G;
+    e.ld = d.Fp;
+    k_dreduce<EPI_STORE, double><<<dim3(cdiv(F, 1024), nc), 256, 0, s>>>(F, part, d.Fp, sstride, S, e, nullptr);
+    RR_HIP(hipMemsetAsync(changed, 0, sizeof(int), s));
+    k_km_assign<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, nc, G, d.Fp, q, off, labels, changed);
+    int hc = 0;
+    RR_HIP(hipMemcpyAsync(&hc, changed, sizeof(int), hipMemcpyDeviceToHost, s));
+    RR_HIP(hipStreamSynchronize(s));
+    ++it;
+    if (hc == 0) break;
+  }
+  h->kmeans_iters = it;
+  zfree(mu); zfree(q); zfree(G); zfree(part); zfree(perm); zfree(off); zfree(changed);
+  RR_TRY(res);
+  // compaction (drop empty clusters), P and the cluster-sorted permutation
+  return set_labels(h, h->labels, nc, s);
 }
 
 }  // namespace rr

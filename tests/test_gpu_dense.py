@@ -205,6 +205,36 @@ def test_block_solve_edges(rr, clustered):
     assert np.linalg.norm(host(w1) - W[0]) <= 1e-12 * np.linalg.norm(W[0])
 
 
+def test_dense_kmeans(rr, small):
+    """GPU k-means++ on dense columns against the oracle (FP64 in both, sums
+    in different orders): the seeding draws the same centres (a draw would
+    differ only if u T fell within rounding of a prefix boundary), the labels
+    agree on >= 99 % of the features, and the GPU labels are a Lloyd fixed
+    point up to near-ties of the FP64 scores."""
+    X = small.astype(np.float64)
+    k = 40
+    R = rr.DenseRidge(small, n_clusters=k, seed=3)
+    assert np.array_equal(host(R.centres()), kmeans.seed_real(X, k, 3))
+    lab_or, fc_or, it_or, _ = kmeans.kmeans_features(X, k, 3, binary=False)
+    lab = host(R.labels())
+    fc = R.info["n_coarse"]
+    print(f"[dense kmeans] F_C gpu {fc} oracle {fc_or}, passes gpu {R.info['kmeans_iters']} "
+          f"oracle {it_or}, agree {np.mean(lab == lab_or):.4f}", flush=True)
+    assert np.mean(lab == lab_or) >= 0.99
+    mu = np.stack([X[:, lab == c].mean(axis=1) for c in range(fc)], axis=1)
+    score = np.einsum("is,is->s", mu, mu)[None, :] - 2.0 * (X.T @ mu)
+    best = np.argmin(score, axis=1)
+    rows = np.arange(X.shape[1])
+    gap = score[rows, lab] - score[rows, best]
+    scale = np.abs(score).max()
+    assert np.all(gap <= 1e-9 * scale)
+    # the two-level solve on the GPU's own aggregation converges
+    _, Y = datagen.targets(X, 80, n_rhs=2)
+    W, infos = R.solve_block(0.1, Y.T.copy(), precond="vcycle", tol=1e-10)
+    assert all(i["status"] == 0 for i in infos)
+    R.close()
+
+
 def test_dense_errors(rr, small):
     R = rr.DenseRidge(small)
     with pytest.raises(rr.RRError) as e:          # no coarse level
