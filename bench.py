@@ -94,6 +94,79 @@ def cpu_baseline(X, y, lam, labels, fc, step_iters, budget_s=15.0):
                       f"iteration, scaled to the step's {step_iters} iterations"}
 
 
+def dense_section(rr, torch, dev, log):
+    """Dense correlated features with many right-hand sides: X 50,000 x 4096
+    FP32, 64 groups of 64 columns with correlation 0.9, 256 targets,
+    lambda = 0.1, k-means k = 128.  Times the block V(1,1) solve to relative
+    error <= 1e-10 per column against a reference converged to 1e-13, in
+    FP64 and as BF16-operand refinement, and the operator's matrix-core
+    GEMMs (4 N F m flops per block application)."""
+    import numpy as np
+    import datagen
+    N, F, m, lam, k = 50_000, 4096, 256, 0.1, 128
+    t0 = time.perf_counter()
+    X = datagen.block_correlated_dense(N, 64, 64, 0.9, seed=5826 + 3000)
+    _, Y = datagen.targets(X, 5826 + 3000, n_rhs=m)
+    gen_s = time.perf_counter() - t0
+    R = rr.DenseRidge(X, n_clusters=k, seed=5826)
+    del X
+    sinfo = R.info
+    log(f"[bench dense] data {N}x{F}, {m} rhs (generated in {gen_s:.1f} s); setup "
+        f"{sinfo['setup_ms']:.0f} ms (k-means {sinfo['kmeans_ms']:.0f} ms, "
+        f"{sinfo['kmeans_iters']} passes), F_C={sinfo['n_coarse']}")
+    Yd = torch.as_tensor(np.ascontiguousarray(Y.T), dtype=torch.float64, device=dev)
+    del Y
+    Wref, inf_ref = R.solve_block(lam, Yd, precond="vcycle", tol=1e-13, max_iter=3000)
+    ref_n = torch.linalg.norm(Wref, dim=1)
+
+    def run(**kw):
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        W, infos = R.solve_block(lam, Yd, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - ta) * 1e3
+        err = float((torch.linalg.norm(W - Wref, dim=1) / ref_n).max())
+        its = [i["iters"] for i in infos]
+        return {"ms": ms, "max_err": err, "max_iters": max(its), "mean_iters": sum(its) / len(its),
+                "ir_steps": max(i["ir_steps"] for i in infos),
+                "status_ok": all(i["status"] == 0 for i in infos)}
+
+    forms = {}
+    # relative residual 1e-12 leaves relative errors below 1e-10 on this matrix
+    forms["vcycle_f64"] = run(precond="vcycle", tol=1e-12, max_iter=3000)
+    forms["vcycle_bf16_ir"] = run(precond="vcycle", precision="bf16_ir", tol=1e-12, max_iter=3000)
+    forms["jacobi_f64"] = run(precond="jacobi", tol=1e-12, max_iter=3000)
+    forms["jacobi_bf16_ir"] = run(precond="jacobi", precision="bf16_ir", tol=1e-12, max_iter=3000)
+    for name, f in forms.items():
+        log(f"[bench dense] {name}: {f['ms']:.1f} ms, {f['max_iters']} its (max), "
+            f"{f['ir_steps']} IR steps, max rel. error {f['max_err']:.2e}")
+    # operator timing: one block application (both GEMMs and the sum)
+    V = torch.randn(m, F, dtype=torch.float64, device=dev)
+    Q = torch.empty_like(V)
+    gemm = {}
+    for prec, peak in (("bf16_ir", 2500.0), ("f64", 78.6)):
+        for _ in range(2):
+            rr.rr_apply_operator_block(R.h, lam, V, Q, prec)
+        reps = 20 if prec == "bf16_ir" else 5
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            rr.rr_apply_operator_block(R.h, lam, V, Q, prec)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        tf = 4.0 * N * F * m / (ms * 1e-3) / 1e12
+        gemm[prec] = {"ms_per_apply": ms, "tflops": tf, "peak_tflops": peak, "frac": tf / peak}
+        log(f"[bench dense] operator {prec}: {ms:.3f} ms per block apply, {tf:.1f} TFLOP/s "
+            f"({100 * tf / peak:.1f} % of {peak} TFLOP/s)")
+    R.close()
+    return {"workload": f"dense {N}x{F} FP32, 64 groups x 64 columns (correlation 0.9), {m} rhs, "
+                        f"lambda={lam}, k-means k={k}",
+            "setup_ms": sinfo["setup_ms"], "kmeans_ms": sinfo["kmeans_ms"],
+            "n_coarse": sinfo["n_coarse"], "ref_iters": max(i["iters"] for i in inf_ref),
+            "forms": forms, "operator": gemm}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +176,9 @@ def main():
     ap.add_argument("--k", type=int, default=1000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a plain 256 MiB device copy (scale for memory counters)")
+    ap.add_argument("--no-dense", action="store_true", help="skip the dense many-rhs section")
+    ap.add_argument("--dense-only", action="store_true",
+                    help="run only the dense many-rhs section and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -117,6 +193,13 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    if args.dense_only:
+        print(json.dumps({"dense_many_rhs": dense_section(rr, torch, dev, log)}), flush=True)
+        return
     P = datagen.chembl_like()
     N, F = P.X.shape
     nnz = P.X.nnz
@@ -298,6 +381,8 @@ def main():
         labels = datagen.random_labels(F, args.k, 11)
         cpu = cpu_baseline(P.X, P.y, 1.0, labels, args.k, total_iters)
 
+    dense = None if args.no_dense else dense_section(rr, torch, dev, log)
+
     line = {
         "metric": METRIC,
         "value": ms_per_step / 1e3,
@@ -335,6 +420,7 @@ def main():
         "batched_lambdas": batched,
         "mixed_precision": mixed,
         "learned": learned,
+        "dense_many_rhs": dense,
         "roofline": {"bound": "hbm", "achieved": gbs_gather, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs_gather / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "rr::k_sell<1> (column-pass gather of t = X^T u through LDS slices)",

@@ -66,77 +66,107 @@ __device__ inline uint16_t bf16_of(double x) { return bf16_of((float)x); }
 // ---- GEMM, BF16 operands, FP32 accumulation ---------------------------------
 //
 // C[M x Nc] = A[M x K] B[K x Nc]; A row-major (lda), B column-major (ldb),
-// C column-major (ldc).  Workgroup tile 128 x 128, 4 waves of 64 x 64 (4 x 4
-// MFMA 16x16x32 tiles), k-step 32 staged through double-buffered LDS.
+// C column-major (ldc); grid (column tiles, row tiles, splits).  Workgroup
+// tile 128 x 256, 8 waves of 64 x 64 (4 x 4 MFMA 16x16x32 tiles), k-step 64.
+// The next k-step is prefetched into registers while the current one is
+// multiplied from a double-buffered LDS tile; thread t moves chunk t % 8
+// of rows (columns) t / 8 + 64 i.  An LDS row holds 64 k values of one row
+// of A (column of B) as eight 16-byte chunks, chunk c stored at position
+// c ^ (row & 7), so the 16 rows of a fragment read spread over the banks.
 // blockIdx.z takes the k range [z kchunk, (z+1) kchunk) and writes its own
 // C (offset z * sstride): the partial sums of a split contraction.
-constexpr int GB_M = 128, GB_N = 128, GB_K = 32, GB_PITCH = 40;   // LDS row: 32 + 8 pad
+constexpr int GB_M = 128, GB_N = 256, GB_K = 64, GB_THREADS = 512;
 enum { GOUT_BF16 = 0, GOUT_F32 = 1 };
 
-template <int OUT>
-__global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t* __restrict__ A, long long lda,
-                                                   const uint16_t* __restrict__ B, long long ldb,
-                                                   void* __restrict__ C, long long ldc,
-                                                   long long sstride, int kchunk, int K) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[2][GB_M * GB_PITCH];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][GB_N * GB_PITCH];
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wm = w >> 1, wn = w & 1;
-  const long long m0 = (long long)blockIdx.x * GB_M, n0 = (long long)blockIdx.y * GB_N;
-  const int k0 = blockIdx.z * kchunk;
-  const int k1 = min(K, k0 + kchunk);
-  const int sr = t >> 2, sk = (t & 3) * 8;      // staging: row (or column), k offset
-  const uint16_t* Ag = A + (m0 + sr) * lda + sk;
-  const uint16_t* Bg = B + (n0 + sr) * ldb + sk;
-  uint4 ra0 = {}, ra1 = {}, rb0 = {}, rb1 = {};
-  f32x4 acc[4][4];
+// wait for this thread's LDS writes (lgkmcnt 0), not for loads in flight
+__device__ inline void wait_lds_writes() {
+  __builtin_amdgcn_s_waitcnt((3 << 14) | (7 << 4) | 15);   // vmcnt 63, expcnt 7, lgkmcnt 0
+}
+
+// multiply the staged k-step from As, Bs into the wave's 64 x 64 tile
+__device__ __forceinline__ void bf16_mul(const uint16_t* As, const uint16_t* Bs, int wm, int wn,
+                                         int lane, f32x4 (&acc)[4][4]) {
+  const int fr = lane & 15, kq = lane >> 4;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  if (k0 < k1) {
-    ra0 = *(const uint4*)(Ag + k0);
-    ra1 = *(const uint4*)(Ag + 64 * lda + k0);
-    rb0 = *(const uint4*)(Bg + k0);
-    rb1 = *(const uint4*)(Bg + 64 * ldb + k0);
-    *(uint4*)&As[0][sr * GB_PITCH + sk] = ra0;
-    *(uint4*)&As[0][(sr + 64) * GB_PITCH + sk] = ra1;
-    *(uint4*)&Bs[0][sr * GB_PITCH + sk] = rb0;
-    *(uint4*)&Bs[0][(sr + 64) * GB_PITCH + sk] = rb1;
-  }
-  __syncthreads();
-  const int fr = lane & 15, kq = (lane >> 4) * 8;
-  int buf = 0;
-  for (int k = k0; k < k1; k += GB_K) {
-    const bool more = k + GB_K < k1;
-    if (more) {
-      ra0 = *(const uint4*)(Ag + k + GB_K);
-      ra1 = *(const uint4*)(Ag + 64 * lda + k + GB_K);
-      rb0 = *(const uint4*)(Bg + k + GB_K);
-      rb1 = *(const uint4*)(Bg + 64 * ldb + k + GB_K);
-    }
+  for (int ks = 0; ks < 2; ++ks) {
+    const int kc = 4 * ks + kq;
     bf16x8 a[4], b[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      a[i] = __builtin_bit_cast(bf16x8, *(const uint4*)&As[buf][(wm * 64 + i * 16 + fr) * GB_PITCH + kq]);
-      b[i] = __builtin_bit_cast(bf16x8, *(const uint4*)&Bs[buf][(wn * 64 + i * 16 + fr) * GB_PITCH + kq]);
+      const int r = wm * 64 + i * 16 + fr;
+      a[i] = __builtin_bit_cast(bf16x8, *(const uint4*)&As[r * GB_K + 8 * (kc ^ (r & 7))]);
+      const int n = wn * 64 + i * 16 + fr;
+      b[i] = __builtin_bit_cast(bf16x8, *(const uint4*)&Bs[n * GB_K + 8 * (kc ^ (n & 7))]);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    if (more) {
-      // the other buffer was last read before the barrier that ended the
-      // previous step
-      *(uint4*)&As[buf ^ 1][sr * GB_PITCH + sk] = ra0;
-      *(uint4*)&As[buf ^ 1][(sr + 64) * GB_PITCH + sk] = ra1;
-      *(uint4*)&Bs[buf ^ 1][sr * GB_PITCH + sk] = rb0;
-      *(uint4*)&Bs[buf ^ 1][(sr + 64) * GB_PITCH + sk] = rb1;
-    }
-    __syncthreads();
-    buf ^= 1;
   }
+}
+
+template <int OUT>
+__global__ __launch_bounds__(GB_THREADS) void k_gemm_bf16(const uint16_t* __restrict__ A, long long lda,
+                                                          const uint16_t* __restrict__ B, long long ldb,
+                                                          void* __restrict__ C, long long ldc,
+                                                          long long sstride, int kchunk, int K) {
+  __shared__ __attribute__((aligned(16))) uint16_t As0[GB_M * GB_K], As1[GB_M * GB_K];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs0[GB_N * GB_K], Bs1[GB_N * GB_K];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wm = w >> 2, wn = w & 3;   // 2 x 4 waves
+  const long long m0 = (long long)blockIdx.y * GB_M, n0 = (long long)blockIdx.x * GB_N;
+  const int k0 = blockIdx.z * kchunk;
+  const int k1 = min(K, k0 + kchunk);
+  const int T = (k1 - k0) / GB_K;
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // step st multiplies from buffer st % 2 while the loads of step st + 1
+  // are in flight; they then go into the other buffer (last read in step
+  // st - 1, before the barrier that ended it)
+  uint4 ra0, ra1, rb0, rb1, rb2, rb3;
+  auto load = [&](int k) {
+    const int r = t >> 3, c = t & 7;
+    ra0 = *(const uint4*)(A + (m0 + r) * lda + k + 8 * c);
+    ra1 = *(const uint4*)(A + (m0 + r + 64) * lda + k + 8 * c);
+    rb0 = *(const uint4*)(B + (n0 + r) * ldb + k + 8 * c);
+    rb1 = *(const uint4*)(B + (n0 + r + 64) * ldb + k + 8 * c);
+    rb2 = *(const uint4*)(B + (n0 + r + 128) * ldb + k + 8 * c);
+    rb3 = *(const uint4*)(B + (n0 + r + 192) * ldb + k + 8 * c);
+  };
+  auto store = [&](uint16_t* As, uint16_t* Bs) {
+    const int r = t >> 3, c = t & 7;
+    *(uint4*)&As[r * GB_K + 8 * (c ^ (r & 7))] = ra0;
+    *(uint4*)&As[(r + 64) * GB_K + 8 * (c ^ (r & 7))] = ra1;
+    *(uint4*)&Bs[r * GB_K + 8 * (c ^ (r & 7))] = rb0;
+    *(uint4*)&Bs[(r + 64) * GB_K + 8 * (c ^ (r & 7))] = rb1;
+    *(uint4*)&Bs[(r + 128) * GB_K + 8 * (c ^ (r & 7))] = rb2;
+    *(uint4*)&Bs[(r + 192) * GB_K + 8 * (c ^ (r & 7))] = rb3;
+  };
+  if (T > 0) {
+    load(k0);
+    store(As0, Bs0);
+  }
+  if (T > 1) load(k0 + GB_K);
+  wait_lds_writes();
+  __builtin_amdgcn_s_barrier();
+  for (int st = 0; st < T; st += 2) {
+    bf16_mul(As0, Bs0, wm, wn, lane, acc);
+    if (st + 1 < T) store(As1, Bs1);
+    if (st + 2 < T) load(k0 + (st + 2) * GB_K);
+    wait_lds_writes();
+    __builtin_amdgcn_s_barrier();
+    if (st + 1 >= T) break;
+    bf16_mul(As1, Bs1, wm, wn, lane, acc);
+    if (st + 2 < T) store(As0, Bs0);
+    if (st + 3 < T) load(k0 + (st + 3) * GB_K);
+    wait_lds_writes();
+    __builtin_amdgcn_s_barrier();
+  }
+  const int fr = lane & 15;
   // MFMA result: value v of lane l is row 4 (l / 16) + v, column l % 16
   const int rq = (lane >> 4) * 4;
 #pragma unroll
@@ -175,7 +205,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const TA* __restrict__ A, long
   __shared__ double Bs[2][GD_N * GD_PITCH];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wm = w >> 1, wn = w & 1;
-  const long long m0 = (long long)blockIdx.x * GD_M, n0 = (long long)blockIdx.y * GD_N;
+  const long long m0 = (long long)blockIdx.y * GD_M, n0 = (long long)blockIdx.x * GD_N;
   const int k0 = blockIdx.z * kchunk;
   const int k1 = min(K, k0 + kchunk);
   const int ar = t >> 1, ak = (t & 1) * 8;     // A staging: row, 8 k values
@@ -623,11 +653,12 @@ __global__ void k_iota(int* p, int n) {
 // ---- host side ------------------------------------------------------------------------
 
 constexpr int kMaxBlockRhs = 4096;
+constexpr int kBf16Target = 512;   // BF16 split contraction: about two workgroups per CU
 
-// number of contraction splits: about 1024 workgroups, at least 8 k-steps each
-void pick_split(int tiles, int K, int bk, int* S, int* kchunk) {
+// number of contraction splits: about `target` workgroups, at least 8 k-steps each
+void pick_split(int tiles, int K, int bk, int* S, int* kchunk, int target = 1024) {
   const int ktiles = K / bk;
-  int s = std::max(1, std::min(cdiv(1024, std::max(tiles, 1)), std::max(1, ktiles / 8)));
+  int s = std::max(1, std::min(cdiv(target, std::max(tiles, 1)), std::max(1, ktiles / 8)));
   const int per = cdiv(ktiles, s);
   *kchunk = per * bk;
   *S = cdiv(ktiles, per);
@@ -661,7 +692,7 @@ rr_status ensure_dwork(rr_handle* h, int m) {
   pick_split(d.Fp / GD_M, d.Np, GD_K, &S, &kc);
   size_t pb = (size_t)S * fp * sizeof(double);
   int Sb = 0;
-  pick_split(d.Fp / GB_M, d.Np, GB_K, &Sb, &kc);
+  pick_split(d.Fp / GB_M, d.Np, GB_K, &Sb, &kc, kBf16Target);
   pb = std::max(pb, (size_t)Sb * fp * sizeof(float));
   W.part_bytes = pb;
   RR_HIP(hipMalloc(&W.part, pb));
@@ -719,12 +750,12 @@ rr_status pass_rows(rr_handle* h, int m, bool bf16, const double* V, const uint1
   if (bf16) {
     const int nt = cdiv(m, GB_N);
     if (d.Np % GB_M || d.Fp % GB_K || nt * GB_N > W.m_cap) return fail(RR_ERR_DEVICE, "internal: GEMM shape");
-    dim3 g(d.Np / GB_M, nt, 1);
-    k_gemm_bf16<GOUT_BF16><<<g, 256, 0, s>>>(d.Xb, d.Fp, Vb, d.Fp, W.ub, d.Np, 0, d.Fp, d.Fp);
+    dim3 g(nt, d.Np / GB_M, 1);
+    k_gemm_bf16<GOUT_BF16><<<g, GB_THREADS, 0, s>>>(d.Xb, d.Fp, Vb, d.Fp, W.ub, d.Np, 0, d.Fp, d.Fp);
   } else {
     const int nt = cdiv(m, GD_N);
     if (d.Np % GD_M || d.Fp % GD_K || nt * GD_N > W.m_cap) return fail(RR_ERR_DEVICE, "internal: GEMM shape");
-    dim3 g(d.Np / GD_M, nt, 1);
+    dim3 g(nt, d.Np / GD_M, 1);
     k_gemm_f64<float><<<g, 256, 0, s>>>(d.X32, d.Fp, V, d.Fp, W.u, d.Np, 0, d.Fp, d.Fp);
   }
   return RR_OK;
@@ -740,11 +771,11 @@ rr_status pass_cols(rr_handle* h, int m, bool bf16, int mode, const DEpi& e, dou
   dim3 gr(cdiv(d.F, 1024), m);
   if (bf16) {
     const int nt = cdiv(m, GB_N);
-    pick_split((d.Fp / GB_M) * nt, d.Np, GB_K, &S, &kc);
+    pick_split((d.Fp / GB_M) * nt, d.Np, GB_K, &S, &kc, kBf16Target);
     if (d.Fp % GB_M || d.Np % GB_K || kc % GB_K || (size_t)S * sstride * sizeof(float) > W.part_bytes)
       return fail(RR_ERR_DEVICE, "internal: GEMM shape");
-    dim3 g(d.Fp / GB_M, nt, S);
-    k_gemm_bf16<GOUT_F32><<<g, 256, 0, s>>>(d.XTb, d.Np, W.ub, d.Np, W.part, d.Fp, sstride, kc, d.Np);
+    dim3 g(nt, d.Fp / GB_M, S);
+    k_gemm_bf16<GOUT_F32><<<g, GB_THREADS, 0, s>>>(d.XTb, d.Np, W.ub, d.Np, W.part, d.Fp, sstride, kc, d.Np);
     const float* P = (const float*)W.part;
     switch (mode) {
       case EPI_STORE: k_dreduce<EPI_STORE, float><<<gr, 256, 0, s>>>(d.F, P, d.Fp, sstride, S, e, dots); break;
@@ -759,7 +790,7 @@ rr_status pass_cols(rr_handle* h, int m, bool bf16, int mode, const DEpi& e, dou
     pick_split((d.Fp / GD_M) * nt, d.Np, GD_K, &S, &kc);
     if (d.Fp % GD_M || d.Np % GD_K || kc % GD_K || (size_t)S * sstride * sizeof(double) > W.part_bytes)
       return fail(RR_ERR_DEVICE, "internal: GEMM shape");
-    dim3 g(d.Fp / GD_M, nt, S);
+    dim3 g(nt, d.Fp / GD_M, S);
     k_gemm_f64<float><<<g, 256, 0, s>>>(d.XT32, d.Np, W.u, d.Np, (double*)W.part, d.Fp, sstride, kc, d.Np);
     const double* P = (const double*)W.part;
     switch (mode) {
@@ -992,7 +1023,7 @@ rr_status dense_coarse_gram(rr_handle* h, hipStream_t s) {
   double* part = nullptr;
   RR_TRY(zalloc(&part, (size_t)S * sstride));
   if (FCp % GD_N || d.Np % GD_K) return fail(RR_ERR_DEVICE, "internal: GEMM shape");
-  dim3 g(FCp / GD_M, cdiv(fc, GD_N), S);
+  dim3 g(cdiv(fc, GD_N), FCp / GD_M, S);
   k_gemm_f64<double><<<g, 256, 0, s>>>(d.Xc, d.Np, d.Xc, d.Np, part, FCp, sstride, kc, d.Np);
   DEpi e{};
   e.out = h->K;
@@ -1440,7 +1471,7 @@ rr_status dense_kmeans(rr_handle* h, int k, uint64_t seed, int max_iter, hipStre
       res = fail(RR_ERR_DEVICE, "internal: GEMM shape");
       break;
     }
-    k_gemm_f64<float><<<dim3(d.Fp / GD_M, kp / GD_N, S), 256, 0, s>>>(d.XT32, d.Np, mu, d.Np, part, d.Fp,
+    k_gemm_f64<float><<<dim3(kp / GD_N, d.Fp / GD_M, S), 256, 0, s>>>(d.XT32, d.Np, mu, d.Np, part, d.Fp,
                                                                         sstride, kc, d.Np);
     DEpi e{};
     e.out = G;
