@@ -653,7 +653,7 @@ __global__ void k_iota(int* p, int n) {
 // ---- host side ------------------------------------------------------------------------
 
 constexpr int kMaxBlockRhs = 4096;
-constexpr int kBf16Target = 512;   // BF16 split contraction: about two workgroups per CU
+constexpr int kBf16Target = 256;   // BF16 split contraction: about one workgroup per CU
 
 // number of contraction splits: about `target` workgroups, at least 8 k-steps each
 void pick_split(int tiles, int K, int bk, int* S, int* kchunk, int target = 1024) {
