@@ -9,12 +9,13 @@
 // pieces to keep lane streams short.  Workgroups own one slice each; they
 // copy its part of v into LDS and then work through wave tasks:
 //   * lane tasks: 64 lane streams of uint16 local indexes, entry k of lane l
-//     stored at base + 64 k + l (every load instruction reads 128
-//     consecutive bytes).  A lane stream holds one pair or, for short
+//     stored at base + 256 (k / 4) + 4 l + k % 4, so a lane loads four
+//     consecutive entries (8 bytes) at a time and every load instruction
+//     reads 512 consecutive bytes.  A lane stream holds one pair or, for short
 //     pairs, several pairs back to back; bit 15 marks the last entry of a
 //     pair, where the lane writes its running sum to the next of its output
 //     positions (base + 64 c + l) and restarts.  Streams are padded with the
-//     zero entry to the task's longest one;
+//     zero entry to the task's longest one, rounded up to a multiple of 4;
 //   * wave tasks: one long pair, stored contiguously and padded to a
 //     multiple of 64 entries; lane l reads 8 entries (16 bytes) of every full
 //     512 and one entry (2 bytes) of every 64 of the rest, then the wave adds
@@ -35,7 +36,8 @@
 
 namespace rr {
 
-constexpr int kLaneUnroll = 16;     // index loads in flight per lane (lane tasks)
+constexpr int kLaneGroup = 4;       // lane-task entries per load (8 bytes)
+constexpr int kLaneUnroll = 8;      // loads (of kLaneGroup entries) in flight per lane
 constexpr int kWaveUnroll = 16;     // 16-byte loads in flight per lane (wave tasks)
 constexpr unsigned kEndFlag = 0x8000u;
 constexpr unsigned kLocalMask = 0x7fffu;
@@ -104,38 +106,44 @@ __device__ inline void sell_body(const int* __restrict__ wrange, const int* __re
     const int len = __builtin_amdgcn_readlane(my.z, i);
     const int obase = __builtin_amdgcn_readlane(my.w, i);
     if (kind == 0) {
-      const uint16_t* p = idx + base + lane;
+      // group g of lane l: entries 4 g .. 4 g + 3 in one 8-byte load
+      const uint2* p = reinterpret_cast<const uint2*>(idx + base) + lane;
       T* o = out + obase + lane;
       T acc = T(0);
-      int k = 0;
-      for (; k + kLaneUnroll <= len; k += kLaneUnroll) {
-        unsigned q[kLaneUnroll];
+      const int ng = len / kLaneGroup;
+      auto add = [&](unsigned e) {
+        acc += vs[e & kLocalMask];
+        if (e & kEndFlag) {
+          *o = acc;
+          o += 64;
+          acc = T(0);
+        }
+      };
+      int g = 0;
+      for (; g + kLaneUnroll <= ng; g += kLaneUnroll) {
+        uint2 q[kLaneUnroll];
 #pragma unroll
-        for (int j = 0; j < kLaneUnroll; ++j) q[j] = p[(size_t)(k + j) * 64];
+        for (int j = 0; j < kLaneUnroll; ++j) q[j] = p[(size_t)(g + j) * 64];
 #pragma unroll
         for (int j = 0; j < kLaneUnroll; ++j) {
-          acc += vs[q[j] & kLocalMask];
-          if (q[j] & kEndFlag) {
-            *o = acc;
-            o += 64;
-            acc = T(0);
-          }
+          add(q[j].x & 0xffffu);
+          add(q[j].x >> 16);
+          add(q[j].y & 0xffffu);
+          add(q[j].y >> 16);
         }
       }
-      if (k < len) {   // the rest (len is the same in every lane): loads issued together
-        unsigned q[kLaneUnroll];
+      if (g < ng) {   // the rest (ng is the same in every lane): loads issued together
+        uint2 q[kLaneUnroll];
 #pragma unroll
         for (int j = 0; j < kLaneUnroll; ++j)
-          q[j] = (k + j < len) ? (unsigned)p[(size_t)(k + j) * 64] : (unsigned)W;
+          q[j] = (g + j < ng) ? p[(size_t)(g + j) * 64] : make_uint2(0u, 0u);
 #pragma unroll
         for (int j = 0; j < kLaneUnroll; ++j) {
-          if (k + j < len) {
-            acc += vs[q[j] & kLocalMask];
-            if (q[j] & kEndFlag) {
-              *o = acc;
-              o += 64;
-              acc = T(0);
-            }
+          if (g + j < ng) {
+            add(q[j].x & 0xffffu);
+            add(q[j].x >> 16);
+            add(q[j].y & 0xffffu);
+            add(q[j].y >> 16);
           }
         }
       }
@@ -412,7 +420,8 @@ void emit_lane_task(SellBuild& B, const std::vector<std::vector<int>>& lanes,
     m = std::max(m, len);
     J = std::max(J, (int)ln.size());
   }
-  const int base = (int)B.idx.size();
+  m = (m + kLaneGroup - 1) / kLaneGroup * kLaneGroup;
+  const int base = (int)B.idx.size();   // a multiple of 64: every task fills whole 64-entry rows
   B.idx.resize(B.idx.size() + (size_t)m * 64, (uint16_t)W);
   const int obase = B.nout;
   for (int l = 0; l < (int)lanes.size(); ++l) {
@@ -422,7 +431,8 @@ void emit_lane_task(SellBuild& B, const std::vector<std::vector<int>>& lanes,
       for (int e = 0; e < pa.len; ++e, ++k) {
         unsigned q = (unsigned)(gidx[pa.start + e] - g0);
         if (e == pa.len - 1) q |= kEndFlag;
-        B.idx[base + (size_t)k * 64 + l] = (uint16_t)q;
+        B.idx[base + (size_t)(k / kLaneGroup) * 64 * kLaneGroup + (size_t)l * kLaneGroup + k % kLaneGroup] =
+            (uint16_t)q;
       }
       B.pos[pi] = obase + c * 64 + l;
       ++c;
@@ -616,8 +626,8 @@ rr_status build_sell(SellPlan& sp, const std::vector<int>& ptr, const std::vecto
     const size_t n16 = B.idx.size();
     bool ok;
     if (t.x == 0)
-      ok = t.z >= 1 && (size_t)t.y + (size_t)(t.z - 1) * 64 + 63 < n16 && t.w >= 0 &&
-           t.w + 63 < B.nout;
+      ok = t.z >= 1 && t.z % kLaneGroup == 0 && t.y % kLaneGroup == 0 &&
+           (size_t)t.y + (size_t)t.z * 64 <= n16 && t.w >= 0 && t.w + 63 < B.nout;
     else
       ok = t.z >= 1 && (t.z & 15) <= 8 &&
            (size_t)t.y * 8 + (size_t)(t.z >> 4) * 512 + (size_t)(t.z & 15) * 64 <= n16 &&
@@ -631,7 +641,9 @@ rr_status build_sell(SellPlan& sp, const std::vector<int>& ptr, const std::vecto
     for (int l = 0; l < 64; ++l) {
       int c = 0;
       for (int k = 0; k < t.z; ++k)
-        if (B.idx[t.y + (size_t)k * 64 + l] & kEndFlag) ++c;
+        if (B.idx[t.y + (size_t)(k / kLaneGroup) * 64 * kLaneGroup + (size_t)l * kLaneGroup +
+                  k % kLaneGroup] & kEndFlag)
+          ++c;
       if (c > 0 && t.w + 64 * (c - 1) + l >= B.nout)
         return fail(RR_ERR_DEVICE, "internal: SELL output out of range");
     }
