@@ -13,6 +13,12 @@
   plain PCG applies.
 * ``additive``: z = S r + P A_c^-1 P^T r (no extra operator application).
 
+Block smoother (the cluster-aligned block option): S = omega D_B^-1 with D_B
+the block diagonal of A over blocks that never cross a cluster: each
+cluster's members in increasing feature index, cut into consecutive groups
+of at most 32.  Its weight comes from the power estimate of rho(D_B^-1 A)
+(block_omega).
+
 Reading: the paper recommends CG as the pre-smoother inside flexible CG; a
 fixed symmetric smoother keeps B stationary and SPD so the same cycle also
 drives plain PCG.
@@ -25,8 +31,60 @@ from . import coarse as _coarse
 from .operator import apply_A, jacobi_diagonal
 
 
+def smoother_blocks(labels: np.ndarray, F_C: int, size: int = 32) -> list:
+    """Feature index arrays of the block smoother: for every cluster in
+    order, its members in increasing index cut into groups of <= size."""
+    out = []
+    for s in range(F_C):
+        members = np.flatnonzero(labels == s)
+        for a in range(0, members.size, size):
+            out.append(members[a:a + size])
+    return out
+
+
+def block_inverses(X, lam: float, blocks: list) -> list:
+    """(A_BB)^-1 for every block B, A_BB = X_B^T X_B + lam I (dense FP64)."""
+    import scipy.sparse as sp
+    Xc = X.tocsc() if sp.issparse(X) else np.asarray(X, dtype=np.float64)
+    inv = []
+    for B in blocks:
+        XB = Xc[:, B]
+        XB = XB.toarray() if sp.issparse(XB) else XB
+        G = XB.T @ XB + lam * np.eye(B.size)
+        inv.append(np.linalg.inv(G))
+    return inv
+
+
+def block_apply(blocks: list, inv: list, r: np.ndarray) -> np.ndarray:
+    """D_B^-1 r."""
+    z = np.zeros_like(np.asarray(r, dtype=np.float64))
+    for B, Gi in zip(blocks, inv):
+        z[B] = Gi @ r[B]
+    return z
+
+
+def block_omega(X, lam: float, blocks: list, inv: list, seed: int, iters: int = 30,
+                safety: float = 1.1) -> float:
+    """omega = 1 / (safety * rho_est), rho_est the norm ratio after `iters`
+    power steps v <- D_B^-1 A v / ||.|| (D_B^-1 A is similar to the SPD
+    D_B^-1/2 A D_B^-1/2, so its eigenvalues are real and positive) from the
+    unit-normalised SplitMix64(seed) start vector with entries in [0.5, 1.5)
+    (the same start as operator.omega_power)."""
+    from .splitmix64 import SplitMix64
+    rng = SplitMix64(seed)
+    v = np.array([rng.next_unit() + 0.5 for _ in range(X.shape[1])])
+    v /= np.linalg.norm(v)
+    rho = 0.0
+    for _ in range(iters):
+        w = block_apply(blocks, inv, apply_A(X, lam, v))
+        rho = float(np.linalg.norm(w))
+        v = w / rho
+    return 1.0 / (safety * rho)
+
+
 class TwoLevel:
-    def __init__(self, X, lam: float, labels: np.ndarray, F_C: int, omega: float):
+    def __init__(self, X, lam: float, labels: np.ndarray, F_C: int, omega: float,
+                 smoother: str = "point", block_size: int = 32):
         self.X = X
         self.lam = float(lam)
         self.D = jacobi_diagonal(X, lam)
@@ -34,8 +92,14 @@ class TwoLevel:
         self.P = _coarse.prolongation(labels, F_C)
         self.Ac = _coarse.coarse_matrix(X, labels, F_C, lam)
         self.L = _coarse.cholesky(self.Ac)
+        self.smoother = smoother
+        if smoother == "block":
+            self.blocks = smoother_blocks(labels, F_C, block_size)
+            self.inv = block_inverses(X, lam, self.blocks)
 
     def smooth(self, r):
+        if self.smoother == "block":
+            return self.omega * block_apply(self.blocks, self.inv, r)
         return self.omega * r / self.D
 
     def coarse_correction(self, r):
@@ -53,14 +117,14 @@ class TwoLevel:
         return self.smooth(r) + self.coarse_correction(r)
 
 
-def make(kind: str, X, lam: float, labels=None, F_C=None, omega=None):
+def make(kind: str, X, lam: float, labels=None, F_C=None, omega=None, smoother="point"):
     """Return (apply_B, operator applications per call)."""
     if kind == "none":
         return (lambda r: np.array(r, dtype=np.float64, copy=True)), 0
     D = jacobi_diagonal(X, lam)
     if kind == "jacobi":
         return (lambda r: r / D), 0
-    tl = TwoLevel(X, lam, labels, F_C, omega)
+    tl = TwoLevel(X, lam, labels, F_C, omega, smoother)
     if kind == "vcycle":
         return tl.vcycle, 2
     if kind == "additive":

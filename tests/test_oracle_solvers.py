@@ -199,3 +199,65 @@ def test_not_converged_and_breakdown():
     # omega far above 2 / rho(D^-1 A): the V-cycle is indefinite
     w, info = krylov.solve(P.X, P.y, 1.0, "vcycle", lab, 50, omega=50.0, tol=1e-10)
     assert info.status == krylov.BREAKDOWN
+
+
+# --- the cluster-aligned block smoother ----------------------------------------
+
+def test_block_smoother_structure_and_point_limit():
+    """Blocks never cross a cluster, cover every feature once in increasing
+    order, hold <= 32 features; with blocks of one feature the block
+    smoother is the point Jacobi smoother."""
+    import datagen
+    from oracle import precond, operator as op
+    P = datagen.tiny_sparse()
+    F = P.X.shape[1]
+    lab = datagen.random_labels(F, 7, 3)
+    blocks = precond.smoother_blocks(lab, 7)
+    allf = np.concatenate(blocks)
+    assert np.array_equal(np.sort(allf), np.arange(F))
+    assert all(b.size <= 32 and np.all(np.diff(b) > 0) and np.unique(lab[b]).size == 1 for b in blocks)
+    ones = precond.smoother_blocks(lab, 7, size=1)
+    inv = precond.block_inverses(P.X, 0.5, ones)
+    r = np.random.default_rng(2).standard_normal(F)
+    assert np.allclose(precond.block_apply(ones, inv, r), r / op.jacobi_diagonal(P.X, 0.5),
+                       rtol=1e-14, atol=0)
+
+
+def test_block_smoother_exact_on_one_block():
+    """F <= 32 in one cluster: D_B = A, so with omega = 1 the pre-smoothing
+    already solves A e = r and V(1,1) PCG ends after one iteration."""
+    import datagen
+    from oracle import krylov
+    X = datagen.zipf_binary_csr(80, 24, 5, 1.1, 6)
+    y = np.random.default_rng(7).standard_normal(80)
+    lab = np.zeros(24, dtype=np.int64)
+    x, inf = krylov.solve(X, y, 0.3, "vcycle", lab, 1, omega=1.0, tol=1e-12, smoother="block")
+    assert inf.iters == 1
+    ref = krylov.reference_solution(X, y, 0.3)
+    assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_block_smoother_spd_and_weight():
+    """The block V(1,1) preconditioner is SPD on a tiny problem with the
+    power weight, and the weight's estimate is within 2 % of rho(D_B^-1 A)
+    from the eigenvalues."""
+    import datagen
+    from oracle import precond, operator as op
+    P = datagen.tiny_sparse()
+    F = P.X.shape[1]
+    lab = datagen.random_labels(F, 9, 4)
+    lam = 0.7
+    blocks = precond.smoother_blocks(lab, 9)
+    inv = precond.block_inverses(P.X, lam, blocks)
+    om = precond.block_omega(P.X, lam, blocks, inv, 0x5eed)
+    A = P.X.T @ P.X
+    A = np.asarray(A.todense()) + lam * np.eye(F)
+    DBinv = np.zeros((F, F))
+    for B, Gi in zip(blocks, inv):
+        DBinv[np.ix_(B, B)] = Gi
+    rho = np.max(np.abs(np.linalg.eigvals(DBinv @ A)))
+    assert abs(1.0 / (1.1 * om) - rho) <= 0.02 * rho
+    tl = precond.TwoLevel(P.X, lam, lab, 9, om, "block")
+    Bm = np.stack([tl.vcycle(e) for e in np.eye(F)], axis=1)
+    assert np.abs(Bm - Bm.T).max() <= 1e-12 * np.abs(Bm).max()
+    assert np.linalg.eigvalsh(0.5 * (Bm + Bm.T)).min() > 0
