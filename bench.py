@@ -206,7 +206,7 @@ def main():
     lams = [1e-2, 1.0, 100.0]
     print(f"[bench] data {N}x{F} nnz={nnz}", file=sys.stderr, flush=True)
 
-    R = rr.Ridge(P.X, n_clusters=args.k, seed=5826, lambda_slots=4, autotune=True)
+    R = rr.Ridge(P.X, n_clusters=args.k, seed=5826, lambda_slots=4, autotune=True, block_smoother=True)
     sinfo = R.info
     print(f"[bench] setup {sinfo['setup_ms']:.0f} ms (k-means {sinfo['kmeans_ms']:.0f} ms, "
           f"{sinfo['kmeans_iters']} Lloyd passes), F_C={sinfo['n_coarse']}", file=sys.stderr, flush=True)
@@ -261,18 +261,21 @@ def main():
 
     # other forms for comparison (untimed calibration, one timed solve each)
     compare = {}
-    for kind in ("jacobi", "additive"):
+    for name, kind, sm in (("jacobi", "jacobi", "point"), ("additive", "additive", "point"),
+                           ("vcycle_block", "vcycle", "block"), ("additive_block", "additive", "block")):
         lam = 1.0
-        st, inf = rr.rr_solve(R.h, lam, y, w, tol=1e-14, max_iter=5000, precond=kind, raise_on=(1, 2, 6))
+        st, inf = rr.rr_solve(R.h, lam, y, w, tol=1e-14, max_iter=5000, precond=kind, smoother=sm,
+                              raise_on=(1, 2, 6))
         wref = w.clone()
         st, inf = rr.rr_solve(R.h, lam, y, w, tol=1e-300, x_ref=wref, err_tol=1e-10,
-                              max_iter=5000, precond=kind, raise_on=(1, 2, 6))
+                              max_iter=5000, precond=kind, smoother=sm, raise_on=(1, 2, 6))
         k = inf["iters"]
         torch.cuda.synchronize()
         ta = time.perf_counter()
-        rr.rr_solve(R.h, lam, y, w, fixed_iters=k, precond=kind, chunk=16, raise_on=(1, 2, 6))
+        rr.rr_solve(R.h, lam, y, w, fixed_iters=k, precond=kind, smoother=sm, chunk=16,
+                    raise_on=(1, 2, 6))
         torch.cuda.synchronize()
-        compare[kind] = {"lambda": lam, "iters": k, "ms": (time.perf_counter() - ta) * 1e3}
+        compare[name] = {"lambda": lam, "iters": k, "ms": (time.perf_counter() - ta) * 1e3}
     compare["vcycle"] = {"lambda": 1.0, "iters": calib[1.0]["iters"], "ms": last[1.0]["ms"]}
     # flexible CG (truncation 1) with the same V(1,1) preconditioner
     lam = 1.0

@@ -112,6 +112,11 @@ typedef struct {
                               length among three candidates by timing them on
                               this device, cached per device and shape bucket
                               (log2 of N, F, nnz) for the life of the process  */
+  int32_t block_smoother;  /* sparse X with a coarse level: 1 also builds the
+                              cluster-aligned smoother blocks (each cluster's
+                              features in increasing index, cut into groups of
+                              at most 32) and their Gram matrices X_B^T X_B,
+                              for solves with smoother = RR_SMOOTHER_BLOCK     */
 } rr_setup_opts;
 
 /*
@@ -174,6 +179,16 @@ typedef enum {
                               residual b - A x uses the FP64 operator           */
 } rr_precision;
 
+/* Smoother of the two-level cycle: S = omega D^-1 with D the diagonal of A
+ * (point) or its cluster-aligned block diagonal D_B (blocks of <= 32
+ * features inside one cluster, solved exactly).  The block form's automatic
+ * weight is 1 / (1.1 rho), rho the norm ratio after 30 power steps
+ * v <- D_B^-1 A v / ||.|| from the start vector of rr_smoother_weight. */
+typedef enum {
+  RR_SMOOTHER_POINT = 0,
+  RR_SMOOTHER_BLOCK = 1
+} rr_smoother;
+
 /* Krylov method of rr_solve. */
 typedef enum {
   RR_KRYLOV_PCG = 0,       /* preconditioned CG (needs a fixed SPD preconditioner) */
@@ -214,6 +229,10 @@ typedef struct {
                               0 -> 1e-4.  tol then bounds the FP64 residual
                               ||b - A x|| / ||b||, max_iter the inner iterations
                               of each step (at most 40 steps)                    */
+  int32_t smoother;        /* rr_smoother of the two-level forms (V(1,1),
+                              additive, learned): point Jacobi (default) or the
+                              block smoother of a handle set up with
+                              block_smoother = 1 (FP64 solves)                   */
 } rr_solve_opts;
 
 typedef struct {

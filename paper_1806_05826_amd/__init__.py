@@ -31,6 +31,7 @@ RR_OK, RR_ERR_INVALID_ARG, RR_ERR_DEVICE = 0, 1, 2
 RR_ERR_NOT_CONVERGED, RR_ERR_BREAKDOWN, RR_ERR_UNSUPPORTED = 4, 5, 6
 PRECOND = {"none": 0, "jacobi": 1, "vcycle": 2, "additive": 3, "learned": 4}
 KRYLOV = {"pcg": 0, "fcg": 1}
+SMOOTHER = {"point": 0, "block": 1}
 PRECISION = {"f64": 0, "f32_ir": 1, "bf16_ir": 2}
 
 
@@ -47,7 +48,8 @@ class rr_dense(C.Structure):
 class rr_setup_opts(C.Structure):
     _fields_ = [("n_clusters", C.c_int32), ("kmeans_max_iter", C.c_int32),
                 ("seed", C.c_uint64), ("labels_in", C.c_void_p), ("n_labels_in", C.c_int32),
-                ("lambda_slots", C.c_int32), ("autotune", C.c_int32)]
+                ("lambda_slots", C.c_int32), ("autotune", C.c_int32),
+                ("block_smoother", C.c_int32)]
 
 
 class rr_setup_info(C.Structure):
@@ -64,7 +66,7 @@ class rr_solve_opts(C.Structure):
                 ("x_ref", C.c_void_p), ("err_tol", C.c_double),
                 ("residual_history", C.c_void_p), ("chunk", C.c_int32), ("profile", C.c_int32),
                 ("krylov", C.c_int32), ("fcg_m", C.c_int32), ("precision", C.c_int32),
-                ("graph", C.c_int32), ("inner_tol", C.c_double)]
+                ("graph", C.c_int32), ("inner_tol", C.c_double), ("smoother", C.c_int32)]
 
 
 class rr_solve_info(C.Structure):
@@ -154,7 +156,8 @@ def _dev_f64(t, n=None, name="vector"):
 # --- the C ABI, one Python function per entry point -------------------------
 
 def rr_setup(row_ptr, col_idx, values, n_cols, n_clusters=0, seed=0, kmeans_max_iter=0,
-             labels_in=None, n_labels_in=0, lambda_slots=0, autotune=False, stream=None):
+             labels_in=None, n_labels_in=0, lambda_slots=0, autotune=False, block_smoother=False,
+             stream=None):
     """X is a device CSR: row_ptr/col_idx int32 CUDA tensors, values float64
     CUDA tensor or None (binary).  Returns an opaque handle (int)."""
     import torch
@@ -168,7 +171,8 @@ def rr_setup(row_ptr, col_idx, values, n_cols, n_clusters=0, seed=0, kmeans_max_
     X = rr_csr(row_ptr.numel() - 1, int(n_cols), col_idx.numel(), _ptr(row_ptr), _ptr(col_idx),
                _ptr(values))
     o = rr_setup_opts(int(n_clusters), int(kmeans_max_iter), int(seed) & (2**64 - 1),
-                      _ptr(labels_in), int(n_labels_in), int(lambda_slots), 1 if autotune else 0)
+                      _ptr(labels_in), int(n_labels_in), int(lambda_slots), 1 if autotune else 0,
+                      1 if block_smoother else 0)
     h = C.c_void_p()
     _check(_lib.rr_setup(C.byref(X), C.byref(o), _stream(stream), C.byref(h)))
     return h.value
@@ -256,7 +260,7 @@ def rr_get_centres(h, centres, stream=None):
 def rr_solve(h, lam, rhs, w, tol=0.0, max_iter=0, fixed_iters=0, precond="vcycle",
              rhs_is_b=False, omega=0.0, x_ref=None, err_tol=0.0, residual_history=None,
              chunk=0, profile=False, krylov="pcg", fcg_m=0, precision="f64", inner_tol=0.0,
-             graph=False, stream=None,
+             graph=False, smoother="point", stream=None,
              raise_on=(RR_ERR_INVALID_ARG, RR_ERR_DEVICE, RR_ERR_UNSUPPORTED)):
     """Returns (status, info dict).  Statuses in `raise_on` raise RRError."""
     _dev_f64(rhs, None, "rhs")
@@ -267,7 +271,8 @@ def rr_solve(h, lam, rhs, w, tol=0.0, max_iter=0, fixed_iters=0, precond="vcycle
                       _ptr(residual_history), int(chunk), int(profile),
                       KRYLOV[krylov] if isinstance(krylov, str) else int(krylov), int(fcg_m),
                       PRECISION[precision] if isinstance(precision, str) else int(precision),
-                      1 if graph else 0, float(inner_tol))
+                      1 if graph else 0, float(inner_tol),
+                      SMOOTHER[smoother] if isinstance(smoother, str) else int(smoother))
     info = rr_solve_info()
     st = _lib.rr_solve(C.c_void_p(h), float(lam), _ptr(rhs), _ptr(w), C.byref(o), C.byref(info),
                        _stream(stream))
@@ -277,8 +282,8 @@ def rr_solve(h, lam, rhs, w, tol=0.0, max_iter=0, fixed_iters=0, precond="vcycle
 
 
 def rr_solve_batched(handles, lams, rhs, ws, tol=0.0, max_iter=0, fixed_iters=0, precond="vcycle",
-                     rhs_is_b=False, omega=0.0, chunk=0, krylov="pcg", fcg_m=0, stream=None,
-                     raise_on=(RR_ERR_INVALID_ARG, RR_ERR_DEVICE, RR_ERR_UNSUPPORTED)):
+                     rhs_is_b=False, omega=0.0, chunk=0, krylov="pcg", fcg_m=0, smoother="point",
+                     stream=None, raise_on=(RR_ERR_INVALID_ARG, RR_ERR_DEVICE, RR_ERR_UNSUPPORTED)):
     """Batched solves; returns (status, [info dict per problem])."""
     n = len(handles)
     if not (len(lams) == len(rhs) == len(ws) == n):
@@ -293,7 +298,7 @@ def rr_solve_batched(handles, lams, rhs, ws, tol=0.0, max_iter=0, fixed_iters=0,
                       PRECOND[precond] if isinstance(precond, str) else int(precond),
                       1 if rhs_is_b else 0, float(omega), None, 0.0, None, int(chunk), 0,
                       KRYLOV[krylov] if isinstance(krylov, str) else int(krylov), int(fcg_m),
-                      0, 0, 0.0)
+                      0, 0, 0.0, SMOOTHER[smoother] if isinstance(smoother, str) else int(smoother))
     infos = (rr_solve_info * max(n, 1))()
     st = _lib.rr_solve_batched(C.c_int32(n), C.cast(H, C.c_void_p), C.cast(L, C.c_void_p),
                                C.cast(Rp, C.c_void_p), C.cast(Wp, C.c_void_p), C.byref(o),
@@ -413,7 +418,7 @@ class Ridge:
     copy)."""
 
     def __init__(self, X, n_clusters=0, seed=0, kmeans_max_iter=0, labels=None, binary=None,
-                 lambda_slots=0, autotune=False, device="cuda"):
+                 lambda_slots=0, autotune=False, block_smoother=False, device="cuda"):
         import numpy as np
         import torch
         X = X.tocsr()
@@ -431,7 +436,7 @@ class Ridge:
             lab = torch.as_tensor(np.asarray(labels, dtype=np.int32), device=self.device)
             nlab = int(np.max(labels)) + 1 if len(labels) else 1
         self.h = rr_setup(rp, ci, vals, self.F, n_clusters, seed, kmeans_max_iter, lab, nlab,
-                          lambda_slots, autotune)
+                          lambda_slots, autotune, block_smoother)
         torch.cuda.current_stream().synchronize()
         self.info = rr_get_setup_info(self.h)
 

@@ -166,7 +166,8 @@ void destroy_handle(rr_handle* h) {
   dfree(h->colnorm); dfree(h->gersh); dfree(h->fperm); dfree(h->finv);
   dfree(h->labels); dfree(h->centres); dfree(h->csize); dfree(h->cscale);
   dfree(h->perm); dfree(h->coff); dfree(h->K);
-  for (auto& s : h->slots) { dfree(s.L); dfree(s.Ainv); }
+  for (auto& s : h->slots) { dfree(s.L); dfree(s.Ainv); dfree(s.Dinv); }
+  dfree(h->boff); dfree(h->bperm); dfree(h->bgram);
   dfree(h->chol_work); dfree(h->chol_flag); dfree(h->omega_tmp); dfree(h->mlp_scale);
   if (h->pw) {
     dfree(h->pw->v); dfree(h->pw->t); dfree(h->pw->u); dfree(h->pw->D); dfree(h->pw->vin);
@@ -280,6 +281,7 @@ rr_status setup_impl(const rr_csr* Xin, const rr_setup_opts* o, hipStream_t s, r
     }
     RR_TRY(dalloc(&h->chol_work, 2 * (size_t)fc * fc));
     RR_TRY(dalloc(&h->chol_flag, 1));
+    if (o && o->block_smoother) RR_TRY(build_smoother_blocks(h, s));
     np = std::max(np, h->restrict_plan.nblocks + cdiv(h->restrict_plan.nspan, kBlock / 64) + 1);
   }
   np = std::max(np, std::max(3 * kMaxParts, kMaxReduceBlocks + 1));
@@ -402,6 +404,64 @@ rr_status omega_power(rr_handle* h, const Sparse& X, double lam, double* omega, 
 
 // X is the operator view of the work set whose stream s runs the estimate:
 // its partial-sum buffers are ordered with that set's own solve.
+__global__ void k_div_by(int F, const double* __restrict__ v, const double* nrm, double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < F) out[j] = v[j] / *nrm;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sq_parts(int F, const double* __restrict__ v, double* parts) {
+  double acc = 0.0;
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < F; j += gridDim.x * kBlock) acc += v[j] * v[j];
+  __shared__ double red[kBlock / 64];
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) parts[blockIdx.x] = t;
+}
+
+// The block smoother's weight: 30 power steps v <- D_B^-1 A v / ||.|| from
+// the same start vector as omega_power; omega = 1 / (1.1 rho).
+rr_status omega_block_power(rr_handle* h, const Sparse& X, double lam, LambdaSlot& sl, hipStream_t s) {
+  const int F = X.F, N = X.N;
+  if (!h->pw) {
+    h->pw = new (std::nothrow) rr_handle::PowerWork();
+    if (!h->pw) return fail(RR_ERR_DEVICE, "out of host memory");
+    RR_TRY(dalloc(&h->pw->v, F)); RR_TRY(dalloc(&h->pw->t, F)); RR_TRY(dalloc(&h->pw->u, N));
+    RR_TRY(dalloc(&h->pw->D, F)); RR_TRY(dalloc(&h->pw->vin, F));
+    RR_TRY(dalloc(&h->pw->parts, kMaxParts)); RR_TRY(dalloc(&h->pw->nrm, 1));
+  }
+  rr_handle::PowerWork& p = *h->pw;
+  std::vector<double> v0(F);
+  uint64_t st = kPowerSeed;
+  double ss = 0.0;
+  for (int j = 0; j < F; ++j) {
+    v0[j] = (double)(splitmix64_next(st) >> 11) * (1.0 / 9007199254740992.0) + 0.5;
+    ss += v0[j] * v0[j];
+  }
+  const double inv = 1.0 / std::sqrt(ss);
+  for (auto& x : v0) x *= inv;
+  RR_HIP(hipMemcpyAsync(p.v, v0.data(), sizeof(double) * F, hipMemcpyHostToDevice, s));
+  launch_gather(p.vin, p.v, h->fperm, F, s);   // caller order -> internal order
+  const int g = vec_grid(F);
+  for (int it = 0; it < 30; ++it) {
+    if (it) k_div_by<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, p.v, p.nrm, p.vin);
+    launch_csr(X, p.vin, p.u, nullptr, s);
+    Epi e{};
+    e.lam = lam;
+    e.p = p.vin;
+    e.out = p.t;
+    launch_csc(X, p.u, EPI_APPLY, e, nullptr, s);
+    launch_block_smooth(h, sl.Dinv, 1.0, p.t, nullptr, nullptr, nullptr, p.v, nullptr, nullptr, s);
+    k_sq_parts<<<g, kBlock, 0, s>>>(F, p.v, p.parts);
+    k_pw_norm<<<1, kBlock, 0, s>>>(p.parts, g, p.nrm);
+  }
+  double rho = 0.0;
+  RR_HIP(hipMemcpyAsync(&rho, p.nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+  RR_HIP(hipStreamSynchronize(s));
+  RR_HIP(hipGetLastError());
+  if (!(rho > 0.0) || !std::isfinite(rho)) return fail(RR_ERR_BREAKDOWN, "block power iteration failed");
+  sl.omega_block = 1.0 / (1.1 * rho);
+  return RR_OK;
+}
+
 rr_status auto_omega(rr_handle* h, const Sparse& X, double lam, double* omega, hipStream_t s) {
   if (!h->nonneg) return omega_power(h, X, lam, omega, s);
   launch_omega_gersh(h->X.F, h->gersh, h->colnorm, lam, h->omega_tmp, nullptr, nullptr, s);
@@ -434,6 +494,7 @@ rr_status get_slot(rr_handle* h, const Sparse& X, double lam, LambdaSlot** out, 
   const double t0 = now_ms();
   victim->valid = false;
   RR_TRY(coarse_factor(h, lam, *victim, s));
+  RR_TRY(block_factor(h, lam, *victim, s));
   RR_TRY(auto_omega(h, X, lam, &victim->omega, s));
   RR_HIP(hipStreamSynchronize(s));
   victim->lam = lam;
@@ -522,11 +583,19 @@ rr_status precond_two_level(rr_handle* h, Work& w, Prof& pf, int tag, int kind, 
     if (stage) launch_stage_update(*stage, s);
     launch_segsum(w.rplan, h->coff + 1, h->perm, nullptr, r, EPI_SCALE, er, done, s);
     launch_gemv(h->FC, sl.Ainv, w.c, w.yc, done, s);
+    if (w.block) {   // z = w D_B^-1 r + P yc
+      *n_rz = launch_block_smooth(h, sl.Dinv, omega, r, nullptr, w.yc, r, z, w.parts.rz, done, s);
+      return RR_OK;
+    }
     launch_prolong(F, h->labels, h->cscale, w.yc, nullptr, z, r, w.D, omega, 1, w.sc,
                    w.parts.rz, s);
     *n_rz = w.parts.n_vec;
     return RR_OK;
   }
+  // block smoother: e1 = w D_B^-1 r replaces the point step the update formed
+  // (on the iteration that converges this is wasted work, nothing more)
+  if (w.block)
+    launch_block_smooth(h, sl.Dinv, omega, r, nullptr, nullptr, nullptr, w.e1, nullptr, done, s);
   // V(1,1): rho1 = r - A e1
   RR_TRY(op_csr(h, w, pf, tag, w.e1, s, stage));
   Epi e = base_epi(w, lam);
@@ -547,6 +616,15 @@ rr_status precond_two_level(rr_handle* h, Work& w, Prof& pf, int tag, int kind, 
   launch_prolong(F, h->labels, h->cscale, w.yc, w.e1, w.e2, nullptr, nullptr, 0.0, 0, w.sc, nullptr, s);
   // z = e2 + w D^-1 (r - A e2), <r,z> -> beta
   RR_TRY(op_csr(h, w, pf, tag, w.e2, s));
+  if (w.block) {   // rho2 = r - A e2, then z = e2 + w D_B^-1 rho2
+    Epi eb = base_epi(w, lam);
+    eb.p = w.e2;
+    eb.r = r;
+    eb.out = w.rho;
+    RR_TRY(op_csc(h, w, pf, tag, EPI_RESID, eb, s));
+    *n_rz = launch_block_smooth(h, sl.Dinv, omega, w.rho, w.e2, nullptr, r, z, w.parts.rz, done, s);
+    return RR_OK;
+  }
   Epi e2 = base_epi(w, lam);
   e2.p = w.e2;
   e2.r = r;
@@ -632,11 +710,20 @@ rr_status Solve::begin() {
     RR_TRY(dalloc(&w.fcg_paps, kMaxFcg));
     w.fcg_m = fcg_m;
   }
+  if (op.smoother != RR_SMOOTHER_POINT && op.smoother != RR_SMOOTHER_BLOCK)
+    return fail(RR_ERR_INVALID_ARG, "unknown smoother");
+  const bool block = op.smoother == RR_SMOOTHER_BLOCK;
+  if (block && !(kind == PK_VCYCLE || kind == PK_ADDITIVE || kind == PK_LEARNED))
+    return fail(RR_ERR_INVALID_ARG, "the block smoother belongs to the two-level forms");
+  if (block && h->nblk == 0)
+    return fail(RR_ERR_INVALID_ARG, "no smoother blocks: set up with block_smoother = 1");
+  w.block = block;
   omega = op.omega;
   if (kind == PK_VCYCLE || kind == PK_ADDITIVE || kind == PK_LEARNED) {
     RR_TRY(get_slot(h, w.X, lam, &sl, &coarse_ms, s));
     sl->in_use++;
-    if (omega == 0.0) omega = sl->omega;
+    if (block && sl->omega_block == 0.0) RR_TRY(omega_block_power(h, w.X, lam, *sl, s));
+    if (omega == 0.0) omega = block ? sl->omega_block : sl->omega;
   }
   if (!std::isfinite(omega) || omega < 0.0) return fail(RR_ERR_INVALID_ARG, "omega must be finite and >= 0");
   launch_colnorm_diag(F, h->colnorm, lam, w.D, s);
@@ -728,7 +815,8 @@ rr_status Solve::queue_chunk() {
     // the chunk's launches are the same for every chunk of this solve (all
     // changing state lives in device memory): capture them once per
     // signature, then replay
-    GraphKey key{kind, lam, omega, sl ? sl->Ainv : nullptr, xref, op.residual_history, chunk};
+    GraphKey key{kind, lam, omega, sl ? sl->Ainv : nullptr, xref, op.residual_history, chunk,
+                 (sl && w.block) ? sl->Dinv : nullptr};
     // the legacy default stream cannot be captured: use the set's own
     // stream, ordered after and before the caller's with events
     hipStream_t gs = s;
@@ -1015,6 +1103,8 @@ rr_status solve_ir(rr_handle* h, Work& w, double lam, const double* rhs, double*
   if (kind == PK_VCYCLE && h->FC == 0)
     return fail(RR_ERR_INVALID_ARG, "two-level preconditioner needs a coarse level (n_clusters > 0)");
   if (op.krylov != RR_KRYLOV_PCG) return fail(RR_ERR_UNSUPPORTED, "iterative refinement runs PCG inner solves");
+  if (op.smoother != RR_SMOOTHER_POINT)
+    return fail(RR_ERR_UNSUPPORTED, "iterative refinement smooths with the point smoother");
   if (op.x_ref || op.residual_history || op.fixed_iters)
     return fail(RR_ERR_INVALID_ARG, "x_ref, residual_history and fixed_iters are not used with refinement");
   if (op.max_iter < 0 || op.chunk < 0 || op.tol < 0 || op.inner_tol < 0 || op.inner_tol >= 1)

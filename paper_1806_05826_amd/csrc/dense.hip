@@ -1081,7 +1081,8 @@ rr_status dense_solve_block(rr_handle* h, double lam, int m, const double* rhs, 
   if (o) op = *o;
   if (!rhs || !wout) return fail(RR_ERR_INVALID_ARG, "null rhs or w");
   if (ld_rhs < (op.rhs_is_b ? F : N) || ld_w < F) return fail(RR_ERR_INVALID_ARG, "leading dimension too small");
-  if (op.x_ref || op.residual_history || op.krylov != RR_KRYLOV_PCG || op.graph || op.profile)
+  if (op.x_ref || op.residual_history || op.krylov != RR_KRYLOV_PCG || op.graph || op.profile ||
+      op.smoother != RR_SMOOTHER_POINT)
     return fail(RR_ERR_UNSUPPORTED, "block solves take tol, max_iter, fixed_iters, precond, rhs_is_b, "
                                     "omega, precision and inner_tol");
   const int kind = op.precond;

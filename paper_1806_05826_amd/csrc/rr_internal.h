@@ -192,6 +192,8 @@ struct LambdaSlot {
   double* L = nullptr;      // [FC*FC] lower Cholesky factor
   double* Ainv = nullptr;   // [FC*FC]
   double omega = 0.0;       // automatic smoother weight at this lambda
+  double* Dinv = nullptr;   // block smoother: (X_B^T X_B + lam I)^-1, 32 x 32 per block
+  double omega_block = 0.0; // its automatic weight (0: not yet estimated)
   bool valid = false;
   unsigned long long stamp = 0;
   int in_use = 0;           // solves running with this factor (not evicted meanwhile)
@@ -205,9 +207,10 @@ struct GraphKey {
   const double* xref = nullptr;
   const double* history = nullptr;
   int chunk = 0;
+  const double* dinv = nullptr;   // block smoother's inverses (null: point smoother)
   bool operator==(const GraphKey& o) const {
     return kind == o.kind && lam == o.lam && omega == o.omega && ainv == o.ainv &&
-           xref == o.xref && history == o.history && chunk == o.chunk;
+           xref == o.xref && history == o.history && chunk == o.chunk && dinv == o.dinv;
   }
 };
 struct ChunkGraph {
@@ -244,6 +247,7 @@ struct Work {
   Sparse X;
   MergePlan rplan;
   bool extra = false;             // an additional set (owns those buffers)
+  bool block = false;             // the running solve smooths with the block smoother
   IrVectors f32;                  // single-precision vectors, allocated on first use
   ChunkGraph graph;               // captured PCG chunk (rr_solve_opts.graph)
   hipStream_t stream = nullptr;   // batched solves: this set's stream
@@ -318,6 +322,10 @@ struct rr_handle {
     double *parts = nullptr, *nrm = nullptr;
   };
   PowerWork* pw = nullptr;
+  int nblk = 0;                   // block smoother: blocks of <= 32 features
+  int* boff = nullptr;            // [nblk+1] offsets into bperm
+  int* bperm = nullptr;           // [F] internal features in block order
+  double* bgram = nullptr;        // [nblk * 32 * 32] X_B^T X_B, row-major, zero-padded
   rr::DenseX* dense = nullptr;    // rr_setup_dense: X is dense (no sparse X)
   rr::DenseWork* dwork = nullptr;
   rr::Work w;                     // work set 0
@@ -471,6 +479,16 @@ rr_status run_kmeans(rr_handle* h, int k, uint64_t seed, int max_iter, hipStream
 rr_status set_labels(rr_handle* h, const int* labels_in, int nlab, hipStream_t s);
 rr_status build_coarse_gram(rr_handle* h, hipStream_t s);
 rr_status build_coarse_gram_valued(rr_handle* h, hipStream_t s);   // (api.hip)
+
+// ---- block smoother (block.hip) ------------------------------------------------
+constexpr int kSmoothBlock = 32;
+rr_status build_smoother_blocks(rr_handle* h, hipStream_t s);
+rr_status block_factor(rr_handle* h, double lam, LambdaSlot& slot, hipStream_t s);
+// out = base + omega D_B^-1 rho + P yc (base, yc optional), over internal
+// features; with parts: one <r, out> partial per workgroup, count returned.
+int launch_block_smooth(const rr_handle* h, const double* Dinv, double omega, const double* rho,
+                        const double* base, const double* yc, const double* r, double* out,
+                        double* parts, const int* done, hipStream_t s);
 
 // ---- dense X (dense.hip) -------------------------------------------------------
 rr_status dense_setup(rr_handle* h, const rr_dense* X, const rr_setup_opts* o, hipStream_t s);

@@ -405,3 +405,83 @@ def test_errors(rr):
     assert e.value.status == rr.RR_ERR_INVALID_ARG
     with pytest.raises(rr.RRError):
         rr.Ridge(P.X, labels=np.full(500, -1))
+
+
+# --- the cluster-aligned block smoother ------------------------------------------
+
+@pytest.fixture(scope="module")
+def blocked(rr):
+    P = datagen.mid_sparse()
+    F = P.X.shape[1]
+    lab = datagen.random_labels(F, 150, 21)
+    labc, fc = kmeans.compact(lab)
+    R = rr.Ridge(P.X, labels=lab, block_smoother=True)
+    assert np.array_equal(host(R.labels()), labc)
+    print(f"[blocked] F_C={fc}", flush=True)
+    return P, labc, fc, R
+
+
+@pytest.mark.parametrize("kind", ["vcycle", "additive"])
+def test_block_smoother_parity(rr, blocked, kind):
+    """Block weight equal to the oracle's power estimate; natural stop within
+    the oracle's own spread under rounding-level changes, +-1; converged and
+    3-iteration iterates equal to the oracle's."""
+    P, lab, fc, R = blocked
+    lam = 0.5
+    blocks = precond.smoother_blocks(lab, fc)
+    om = precond.block_omega(P.X, lam, blocks, precond.block_inverses(P.X, lam, blocks), 0x5eed)
+    w, info = R.solve(lam, P.y, precond=kind, smoother="block", tol=1e-10)
+    assert abs(info["omega"] - om) <= 1e-10 * om
+    # the oracle's own counts with the block inverses perturbed by <= 2 ulp
+    b = op.rhs(P.X, P.y)
+    rng = np.random.default_rng(1)
+    its = []
+    for t in range(6):
+        tl = precond.TwoLevel(P.X, lam, lab, fc, om, "block")
+        if t:
+            tl.inv = [G * (1 + (rng.random(G.shape) - 0.5) * 4 * 2**-53) for G in tl.inv]
+            tl.inv = [0.5 * (G + G.T) for G in tl.inv]
+        B = tl.vcycle if kind == "vcycle" else tl.additive
+        _, inf = krylov.pcg(lambda v: op.apply_A(P.X, lam, v), b, B, tol=1e-10)
+        its.append(inf.iters)
+    print(f"[block {kind}] gpu {info['iters']} its, oracle {min(its)}..{max(its)}", flush=True)
+    assert min(its) - 1 <= info["iters"] <= max(its) + 1
+    x13, inf13 = krylov.solve(P.X, P.y, lam, kind, lab, fc, omega=om, tol=1e-13, smoother="block")
+    w, info = R.solve(lam, P.y, precond=kind, smoother="block", fixed_iters=inf13.iters)
+    assert np.linalg.norm(host(w) - x13) <= 1e-10 * np.linalg.norm(x13)
+    x3, _ = krylov.solve(P.X, P.y, lam, kind, lab, fc, omega=om, fixed_iters=3, smoother="block")
+    w, info = R.solve(lam, P.y, precond=kind, smoother="block", fixed_iters=3)
+    assert np.linalg.norm(host(w) - x3) <= 1e-11 * np.linalg.norm(x3)
+
+
+def test_block_smoother_fcg_and_options(rr, blocked):
+    P, lab, fc, R = blocked
+    w, info = R.solve(0.5, P.y, precond="vcycle", smoother="block", krylov="fcg", fcg_m=2, tol=1e-10)
+    assert info["status"] == 0
+    with pytest.raises(rr.RRError) as e:           # the block smoother belongs to two-level forms
+        R.solve(0.5, P.y, precond="jacobi", smoother="block")
+    assert e.value.status == rr.RR_ERR_INVALID_ARG
+    R2 = rr.Ridge(P.X, labels=lab)                  # no blocks built
+    with pytest.raises(rr.RRError) as e:
+        R2.solve(0.5, P.y, precond="vcycle", smoother="block")
+    assert e.value.status == rr.RR_ERR_INVALID_ARG
+    R2.close()
+
+
+def test_block_smoother_valued_x(rr):
+    import scipy.sparse as sp
+    rng = np.random.default_rng(26)
+    X = sp.random(1500, 700, density=0.02, random_state=27, format="csr")
+    X.data = rng.standard_normal(X.nnz)
+    lab = datagen.random_labels(700, 40, 8)
+    labc, fc = kmeans.compact(lab)
+    R = rr.Ridge(X, labels=lab, binary=False, block_smoother=True)
+    y = rng.standard_normal(1500)
+    lam = 0.3
+    blocks = precond.smoother_blocks(labc, fc)
+    om = precond.block_omega(X, lam, blocks, precond.block_inverses(X, lam, blocks), 0x5eed)
+    x13, inf13 = krylov.solve(X, y, lam, "vcycle", labc, fc, omega=om, tol=1e-13, smoother="block")
+    w, info = R.solve(lam, y, precond="vcycle", smoother="block", fixed_iters=inf13.iters)
+    assert abs(info["omega"] - om) <= 1e-10 * om
+    assert np.linalg.norm(host(w) - x13) <= 1e-10 * np.linalg.norm(x13)
+    R.close()
