@@ -167,6 +167,72 @@ def dense_section(rr, torch, dev, log):
             "forms": forms, "operator": gemm}
 
 
+def batched_uneven_section(rr, torch, dev, log, n_problems=100):
+    """Independent uneven problems in one rr_solve_batched call against one
+    rr_solve call after another: the batched-uneven workload's generator
+    (binary entries, density 1-5 %, Zipf columns, lambda log-uniform in
+    [1e-3, 10], k = ceil(d / 10) clamped to [8, 800], tolerance 1e-8) at
+    n in [500, 5000] and d in [200, 2000] so setup stays within seconds."""
+    import numpy as np
+    import datagen
+    t0 = time.perf_counter()
+    batch = datagen.batched_problems(n_problems, seed=5826 + 4000, n_range=(500, 5000),
+                                     d_range=(200, 2000))
+    gen_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Rs, rhs, ws, lams = [], [], [], []
+    for P, lam in batch:
+        k = int(min(800, max(8, -(-P.X.shape[1] // 10))))
+        Rs.append(rr.Ridge(P.X, n_clusters=k, seed=9))
+        rhs.append(torch.as_tensor(P.y, dtype=torch.float64, device=dev))
+        ws.append(torch.empty(P.X.shape[1], dtype=torch.float64, device=dev))
+        lams.append(lam)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    nnz = int(sum(P.X.nnz for P, _ in batch))
+    # warm both paths once (per-lambda coarse factors are then cached)
+    for R, lam, b, w in zip(Rs, lams, rhs, ws):
+        rr.rr_solve(R.h, lam, b, w, tol=1e-8, precond="vcycle", max_iter=5000, raise_on=(1, 2, 6))
+    rr.rr_solve_batched([R.h for R in Rs], lams, rhs, ws, tol=1e-8, precond="vcycle", max_iter=5000)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    iters_seq = []
+    for R, lam, b, w in zip(Rs, lams, rhs, ws):
+        st, inf = rr.rr_solve(R.h, lam, b, w, tol=1e-8, precond="vcycle", max_iter=5000,
+                              raise_on=(1, 2, 6))
+        iters_seq.append(inf["iters"])
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - ta) * 1e3
+    ta = time.perf_counter()
+    st, infos = rr.rr_solve_batched([R.h for R in Rs], lams, rhs, ws, tol=1e-8, precond="vcycle",
+                                    max_iter=5000)
+    torch.cuda.synchronize()
+    bat_ms = (time.perf_counter() - ta) * 1e3
+    ok = st == 0 and all(i["status"] == 0 for i in infos)
+    same = [i["iters"] for i in infos] == iters_seq
+    # the same with every problem's iteration chunks replayed from HIP graphs
+    rr.rr_solve_batched([R.h for R in Rs], lams, rhs, ws, tol=1e-8, precond="vcycle", max_iter=5000,
+                        chunk=16, graph=True)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    st, infos_g = rr.rr_solve_batched([R.h for R in Rs], lams, rhs, ws, tol=1e-8, precond="vcycle",
+                                      max_iter=5000, chunk=16, graph=True)
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - ta) * 1e3
+    ok = ok and st == 0 and all(i["status"] == 0 for i in infos_g)
+    for R in Rs:
+        R.close()
+    log(f"[bench batched] {n_problems} problems, {nnz / 1e6:.1f} M nnz (generated {gen_s:.1f} s, "
+        f"setup {setup_s:.1f} s): sequential {seq_ms:.1f} ms, batched {bat_ms:.1f} ms "
+        f"({seq_ms / bat_ms:.2f}x), with graphs {graph_ms:.1f} ms ({seq_ms / graph_ms:.2f}x), "
+        f"all converged {ok}, same iterations {same}")
+    return {"problems": n_problems, "nnz": nnz, "n_range": [500, 5000], "d_range": [200, 2000],
+            "tol": 1e-8, "setup_s": setup_s, "sequential_ms": seq_ms, "batched_ms": bat_ms,
+            "speedup": seq_ms / bat_ms, "batched_graph_ms": graph_ms,
+            "graph_speedup": seq_ms / graph_ms, "all_converged": ok, "same_iterations": same,
+            "total_iters": int(sum(iters_seq))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,7 +242,8 @@ def main():
     ap.add_argument("--k", type=int, default=1000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a plain 256 MiB device copy (scale for memory counters)")
-    ap.add_argument("--no-dense", action="store_true", help="skip the dense many-rhs section")
+    ap.add_argument("--no-dense", action="store_true",
+                    help="skip the dense many-rhs and batched uneven-problem sections")
     ap.add_argument("--dense-only", action="store_true",
                     help="run only the dense many-rhs section and print its JSON")
     args = ap.parse_args()
@@ -346,12 +413,13 @@ def main():
     mixed["ms_per_step"] = (time.perf_counter() - ta) * 1e3 / 3
     mixed["vs_plain"] = ms_per_step / mixed["ms_per_step"]
 
-    # learned coarse correction (lambda = 1): pairs from V(1,1) solves at
-    # lambda log-uniform in [0.3, 3], Adam on the BF16 network, then flexible
-    # CG with the network against V(1,1) PCG, both to relative residual 1e-10
+    # learned coarse correction: about 10,000 pairs from V(1,1) solves at
+    # lambda log-uniform in [1e-2, 100], Adam on the BF16 network, then
+    # flexible CG with the network against V(1,1) PCG at lambda = 1, both to
+    # relative residual 1e-10
     learned = {}
     fc = sinfo["n_coarse"]
-    llams = list(np.exp(np.random.default_rng(2).uniform(np.log(0.3), np.log(3.0), 64)))
+    llams = list(np.exp(np.random.default_rng(2).uniform(np.log(1e-2), np.log(100.0), 250)))
     per = 40
     inp = torch.empty((len(llams) * per, fc + 1), dtype=torch.float32, device=dev)
     tgt = torch.empty((len(llams) * per, fc), dtype=torch.float32, device=dev)
@@ -385,6 +453,7 @@ def main():
         cpu = cpu_baseline(P.X, P.y, 1.0, labels, args.k, total_iters)
 
     dense = None if args.no_dense else dense_section(rr, torch, dev, log)
+    uneven = None if args.no_dense else batched_uneven_section(rr, torch, dev, log)
 
     line = {
         "metric": METRIC,
@@ -424,6 +493,7 @@ def main():
         "mixed_precision": mixed,
         "learned": learned,
         "dense_many_rhs": dense,
+        "batched_uneven": uneven,
         "roofline": {"bound": "hbm", "achieved": gbs_gather, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs_gather / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "rr::k_sell<1> (column-pass gather of t = X^T u through LDS slices)",

@@ -283,7 +283,8 @@ def rr_solve(h, lam, rhs, w, tol=0.0, max_iter=0, fixed_iters=0, precond="vcycle
 
 def rr_solve_batched(handles, lams, rhs, ws, tol=0.0, max_iter=0, fixed_iters=0, precond="vcycle",
                      rhs_is_b=False, omega=0.0, chunk=0, krylov="pcg", fcg_m=0, smoother="point",
-                     stream=None, raise_on=(RR_ERR_INVALID_ARG, RR_ERR_DEVICE, RR_ERR_UNSUPPORTED)):
+                     graph=False, stream=None,
+                     raise_on=(RR_ERR_INVALID_ARG, RR_ERR_DEVICE, RR_ERR_UNSUPPORTED)):
     """Batched solves; returns (status, [info dict per problem])."""
     n = len(handles)
     if not (len(lams) == len(rhs) == len(ws) == n):
@@ -298,7 +299,8 @@ def rr_solve_batched(handles, lams, rhs, ws, tol=0.0, max_iter=0, fixed_iters=0,
                       PRECOND[precond] if isinstance(precond, str) else int(precond),
                       1 if rhs_is_b else 0, float(omega), None, 0.0, None, int(chunk), 0,
                       KRYLOV[krylov] if isinstance(krylov, str) else int(krylov), int(fcg_m),
-                      0, 0, 0.0, SMOOTHER[smoother] if isinstance(smoother, str) else int(smoother))
+                      0, 1 if graph else 0, 0.0,
+                      SMOOTHER[smoother] if isinstance(smoother, str) else int(smoother))
     infos = (rr_solve_info * max(n, 1))()
     st = _lib.rr_solve_batched(C.c_int32(n), C.cast(H, C.c_void_p), C.cast(L, C.c_void_p),
                                C.cast(Rp, C.c_void_p), C.cast(Wp, C.c_void_p), C.byref(o),
