@@ -100,7 +100,7 @@ def dense_section(rr, torch, dev, log):
     lambda = 0.1, k-means k = 128.  Times the block V(1,1) solve to relative
     error <= 1e-10 per column against a reference converged to 1e-13, in
     FP64 and as BF16-operand refinement, and the operator's matrix-core
-    GEMMs (4 N F m flops per block application)."""
+    GEMMs (4 N F m flops per block application) in BF16, FP32 and FP64."""
     import numpy as np
     import datagen
     N, F, m, lam, k = 50_000, 4096, 256, 0.1, 128
@@ -135,6 +135,7 @@ def dense_section(rr, torch, dev, log):
     # relative residual 1e-12 leaves relative errors below 1e-10 on this matrix
     forms["vcycle_f64"] = run(precond="vcycle", tol=1e-12, max_iter=3000)
     forms["vcycle_bf16_ir"] = run(precond="vcycle", precision="bf16_ir", tol=1e-12, max_iter=3000)
+    forms["vcycle_f32_ir"] = run(precond="vcycle", precision="f32_ir", tol=1e-12, max_iter=3000)
     forms["jacobi_f64"] = run(precond="jacobi", tol=1e-12, max_iter=3000)
     forms["jacobi_bf16_ir"] = run(precond="jacobi", precision="bf16_ir", tol=1e-12, max_iter=3000)
     for name, f in forms.items():
@@ -144,10 +145,10 @@ def dense_section(rr, torch, dev, log):
     V = torch.randn(m, F, dtype=torch.float64, device=dev)
     Q = torch.empty_like(V)
     gemm = {}
-    for prec, peak in (("bf16_ir", 2500.0), ("f64", 78.6)):
+    for prec, peak in (("bf16_ir", 2500.0), ("f32_ir", 157.3), ("f64", 78.6)):
         for _ in range(2):
             rr.rr_apply_operator_block(R.h, lam, V, Q, prec)
-        reps = 20 if prec == "bf16_ir" else 5
+        reps = {"bf16_ir": 20, "f32_ir": 10}.get(prec, 5)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):

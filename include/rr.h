@@ -170,7 +170,10 @@ typedef enum {
   RR_PREC_F32_IR = 1,      /* iterative refinement: r = b - A x and x in FP64;
                               each correction A d = r by PCG with FP32 vectors
                               and FP32 operator sums, FP64 scalars and FP64
-                              coarse solve (0/1 X; none / Jacobi / V(1,1))      */
+                              coarse solve (0/1 X; none / Jacobi / V(1,1)).
+                              Dense X (rr_solve_block): corrections with the
+                              FP32-operand operator (FP32 matrix-core sums, U
+                              in FP32) and FP64 vectors; inner_tol default 1e-5 */
   RR_PREC_BF16_IR = 2      /* dense X (rr_solve_block): iterative refinement
                               whose corrections run PCG with a BF16-operand
                               operator (X and the input block rounded to BF16,
@@ -356,9 +359,9 @@ rr_status rr_setup_dense(const rr_dense* X, const rr_setup_opts* opts, rr_stream
  *   w:   device double, column c at w + c * ld_w (ld_w >= F), written.
  *   opts: tol, max_iter, fixed_iters, precond (none / Jacobi / V(1,1) /
  *        additive), rhs_is_b, omega, precision (RR_PREC_F64: FP64 operator;
- *        RR_PREC_BF16_IR: refinement with BF16-operand corrections, inner_tol
- *        relative to each step's residual, default 1e-3); other fields must be
- *        zero.
+ *        RR_PREC_BF16_IR / RR_PREC_F32_IR: refinement with BF16- / FP32-operand
+ *        corrections, inner_tol relative to each step's residual, default
+ *        1e-3 / 1e-5); other fields must be zero.
  *   info: NULL or host rr_solve_info[nrhs], one per column (iters = PCG
  *        iterations, summed over refinement steps).
  * 1 <= nrhs <= 4096.  Returns RR_ERR_NOT_CONVERGED / RR_ERR_BREAKDOWN if any
@@ -370,7 +373,8 @@ rr_status rr_solve_block(rr_handle* h, double lambda, int32_t nrhs, const double
 
 /* q_c = (X^T X + lambda I) v_c for nrhs columns (device double, leading
  * dimensions ldv, ldq >= F) of a dense handle, with the FP64 operator
- * (precision RR_PREC_F64) or the BF16-operand one (RR_PREC_BF16_IR).
+ * (precision RR_PREC_F64), the FP32-operand one (RR_PREC_F32_IR) or the
+ * BF16-operand one (RR_PREC_BF16_IR).
  * lambda >= 0.  Stream-ordered. */
 rr_status rr_apply_operator_block(rr_handle* h, double lambda, int32_t nrhs, const double* v,
                                   int64_t ldv, double* q, int64_t ldq, int32_t precision,

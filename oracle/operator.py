@@ -125,3 +125,36 @@ def apply_A_bf16_bound(X, V: np.ndarray) -> np.ndarray:
     S = Xb @ Vb
     du = 2.0 ** -7 * S + 2.0 * gamma(F) * S
     return Xb.T @ du + gamma(N) * (Xb.T @ (S + du))
+
+
+def f32_round(a) -> np.ndarray:
+    """Values rounded to FP32 (nearest, ties to even), returned as FP64."""
+    return np.asarray(a, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def apply_A_f32(X, lam: float, V: np.ndarray) -> np.ndarray:
+    """The FP32-operand operator on columns V (F x m): V rounded to FP32, U =
+    X V rounded to FP32, then X^T U + lam V with exact sums (X is FP32
+    already).  A GPU summing in FP32 differs by at most apply_A_f32_bound."""
+    Xd = f32_round(X.toarray() if sp.issparse(X) else X)
+    V = np.asarray(V, dtype=np.float64)
+    U = f32_round(Xd @ f32_round(V))
+    return Xd.T @ U + lam * V
+
+
+def apply_A_f32_bound(X, V: np.ndarray) -> np.ndarray:
+    """Elementwise bound on |Q - apply_A_f32(X, lam, V)| for FP32 sums in any
+    order: with S = |X| |V~|, the computed U differs from the rounded exact
+    one by at most du = (gamma_F + 2^-24) S (the sum's error plus one
+    rounding), and the second sum adds at most gamma_N |X|^T (S + du)."""
+    Xa = np.abs(f32_round(X.toarray() if sp.issparse(X) else X))
+    Va = np.abs(f32_round(V))
+    N, F = Xa.shape
+
+    def gamma(n):
+        e = n * 2.0 ** -24
+        return e / (1.0 - e)
+
+    S = Xa @ Va
+    du = (gamma(F) + 2.0 ** -24) * S
+    return Xa.T @ du + gamma(N) * (Xa.T @ (S + du))

@@ -272,6 +272,84 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const TA* __restrict__ A, long
     }
 }
 
+// ---- GEMM, FP32 operands and accumulation -------------------------------------
+//
+// The FP64 kernel's tiling with MFMA 16x16x4 FP32: A (FP32 X) as stored, B
+// of type TB rounded to FP32 while staged (the FP64 block, or the FP32 U).
+template <typename TB>
+__global__ __launch_bounds__(256) void k_gemm_f32(const float* __restrict__ A, long long lda,
+                                                  const TB* __restrict__ B, long long ldb,
+                                                  float* __restrict__ C, long long ldc,
+                                                  long long sstride, int kchunk, int K) {
+  __shared__ float As[2][GD_M * GD_PITCH];
+  __shared__ float Bs[2][GD_N * GD_PITCH];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const long long m0 = (long long)blockIdx.y * GD_M, n0 = (long long)blockIdx.x * GD_N;
+  const int k0 = blockIdx.z * kchunk;
+  const int k1 = min(K, k0 + kchunk);
+  const int ar = t >> 1, ak = (t & 1) * 8;     // A staging: row, 8 k values
+  const int bc = t >> 2, bk = (t & 3) * 4;     // B staging: column, 4 k values
+  const float* Ag = A + (m0 + ar) * lda + ak;
+  const TB* Bg = B + (n0 + bc) * ldb + bk;
+  float ra[8], rb[4];
+  f32x4 acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  auto gload = [&](int k) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) ra[e] = Ag[k + e];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) rb[e] = (float)Bg[k + e];
+  };
+  auto lstore = [&](int bf) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) As[bf][ar * GD_PITCH + ak + e] = ra[e];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Bs[bf][bc * GD_PITCH + bk + e] = rb[e];
+  };
+  if (k0 < k1) {
+    gload(k0);
+    lstore(0);
+  }
+  __syncthreads();
+  const int fr = lane & 15, fk = lane >> 4;
+  int buf = 0;
+  for (int k = k0; k < k1; k += GD_K) {
+    const bool more = k + GD_K < k1;
+    if (more) gload(k + GD_K);
+#pragma unroll
+    for (int kk = 0; kk < GD_K; kk += 4) {
+      float a[4], b[2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[buf][(wm * 64 + i * 16 + fr) * GD_PITCH + kk + fk];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Bs[buf][(wn * 32 + j * 16 + fr) * GD_PITCH + kk + fk];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) lstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  // FP32 MFMA result: value v of lane l is row 4 (l / 16) + v, column l % 16
+  float* Cz = C + blockIdx.z * sstride;
+  const int rq = fk * 4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const long long col = n0 + wn * 32 + j * 16 + fr;
+      const long long row = m0 + wm * 64 + i * 16 + rq;
+      *(f32x4*)(Cz + col * ldc + row) = acc[i][j];
+    }
+}
+
 // ---- split-contraction sum with the operator's epilogues -----------------------
 //
 // t = sum_s part_s (fixed order), then per element (feature j, column c):
@@ -653,6 +731,8 @@ __global__ void k_iota(int* p, int n) {
 // ---- host side ------------------------------------------------------------------------
 
 constexpr int kMaxBlockRhs = 4096;
+// operator precision of a block application
+enum OpPrec { OP_F64 = 0, OP_BF16 = 1, OP_F32 = 2 };
 constexpr int kBf16Target = 256;   // BF16 split contraction: about one workgroup per CU
 
 // number of contraction splits: about `target` workgroups, at least 8 k-steps each
@@ -686,6 +766,7 @@ rr_status ensure_dwork(rr_handle* h, int m) {
   RR_TRY(zalloc(&W.vb, fp));
   RR_TRY(zalloc(&W.ub, np));
   RR_TRY(zalloc(&W.u, np));
+  RR_TRY(zalloc(&W.uf, np));
   // split partials of the column pass (Fp x m_cap per split); the split
   // count is largest when a solve has a single column tile
   int S = 0, kc = 0;
@@ -714,7 +795,7 @@ rr_status ensure_dwork(rr_handle* h, int m) {
 void dense_free_work(DenseWork& W) {
   zfree(W.x); zfree(W.r); zfree(W.p); zfree(W.q); zfree(W.z); zfree(W.e1); zfree(W.e2);
   zfree(W.rho); zfree(W.b); zfree(W.wx); zfree(W.wr); zfree(W.D); zfree(W.vb); zfree(W.ub);
-  zfree(W.u); zfree(W.c); zfree(W.yc); zfree(W.parts);
+  zfree(W.u); zfree(W.uf); zfree(W.c); zfree(W.yc); zfree(W.parts);
   zfree(W.rz); zfree(W.pq); zfree(W.alpha); zfree(W.beta); zfree(W.rr); zfree(W.bb);
   zfree(W.done); zfree(W.iters); zfree(W.status); zfree(W.done_in); zfree(W.nactive);
   if (W.part) (void)hipFree(W.part);
@@ -743,11 +824,11 @@ namespace {
 // ---- operator passes ---------------------------------------------------------------
 
 // U = X V (N x m): FP64 from the FP32 copy, or BF16 (output rounded to BF16)
-rr_status pass_rows(rr_handle* h, int m, bool bf16, const double* V, const uint16_t* Vb,
+rr_status pass_rows(rr_handle* h, int m, int op, const double* V, const uint16_t* Vb,
                     hipStream_t s) {
   DenseX& d = *h->dense;
   DenseWork& W = *h->dwork;
-  if (bf16) {
+  if (op == OP_BF16) {
     const int nt = cdiv(m, GB_N);
     if (d.Np % GB_M || d.Fp % GB_K || nt * GB_N > W.m_cap) return fail(RR_ERR_DEVICE, "internal: GEMM shape");
     dim3 g(nt, d.Np / GB_M, 1);
@@ -756,27 +837,40 @@ rr_status pass_rows(rr_handle* h, int m, bool bf16, const double* V, const uint1
     const int nt = cdiv(m, GD_N);
     if (d.Np % GD_M || d.Fp % GD_K || nt * GD_N > W.m_cap) return fail(RR_ERR_DEVICE, "internal: GEMM shape");
     dim3 g(nt, d.Np / GD_M, 1);
-    k_gemm_f64<float><<<g, 256, 0, s>>>(d.X32, d.Fp, V, d.Fp, W.u, d.Np, 0, d.Fp, d.Fp);
+    if (op == OP_F32)
+      k_gemm_f32<double><<<g, 256, 0, s>>>(d.X32, d.Fp, V, d.Fp, W.uf, d.Np, 0, d.Fp, d.Fp);
+    else
+      k_gemm_f64<float><<<g, 256, 0, s>>>(d.X32, d.Fp, V, d.Fp, W.u, d.Np, 0, d.Fp, d.Fp);
   }
   return RR_OK;
 }
 
 // t = X^T U (split contraction) and the epilogue over the first F rows
-rr_status pass_cols(rr_handle* h, int m, bool bf16, int mode, const DEpi& e, double* dots,
+rr_status pass_cols(rr_handle* h, int m, int op, int mode, const DEpi& e, double* dots,
                     hipStream_t s) {
   DenseX& d = *h->dense;
   DenseWork& W = *h->dwork;
   int S = 0, kc = 0;
   const long long sstride = (long long)d.Fp * W.m_cap;
   dim3 gr(cdiv(d.F, 1024), m);
-  if (bf16) {
-    const int nt = cdiv(m, GB_N);
-    pick_split((d.Fp / GB_M) * nt, d.Np, GB_K, &S, &kc, kBf16Target);
-    if (d.Fp % GB_M || d.Np % GB_K || kc % GB_K || (size_t)S * sstride * sizeof(float) > W.part_bytes)
-      return fail(RR_ERR_DEVICE, "internal: GEMM shape");
-    dim3 g(nt, d.Fp / GB_M, S);
-    k_gemm_bf16<GOUT_F32><<<g, GB_THREADS, 0, s>>>(d.XTb, d.Np, W.ub, d.Np, W.part, d.Fp, sstride, kc, d.Np);
-    const float* P = (const float*)W.part;
+  if (op == OP_BF16 || op == OP_F32) {
+    float* P32 = (float*)W.part;
+    if (op == OP_BF16) {
+      const int nt = cdiv(m, GB_N);
+      pick_split((d.Fp / GB_M) * nt, d.Np, GB_K, &S, &kc, kBf16Target);
+      if (d.Fp % GB_M || d.Np % GB_K || kc % GB_K || (size_t)S * sstride * sizeof(float) > W.part_bytes)
+        return fail(RR_ERR_DEVICE, "internal: GEMM shape");
+      dim3 g(nt, d.Fp / GB_M, S);
+      k_gemm_bf16<GOUT_F32><<<g, GB_THREADS, 0, s>>>(d.XTb, d.Np, W.ub, d.Np, W.part, d.Fp, sstride, kc, d.Np);
+    } else {
+      const int nt = cdiv(m, GD_N);
+      pick_split((d.Fp / GD_M) * nt, d.Np, GD_K, &S, &kc);
+      if (d.Fp % GD_M || d.Np % GD_K || kc % GD_K || (size_t)S * sstride * sizeof(float) > W.part_bytes)
+        return fail(RR_ERR_DEVICE, "internal: GEMM shape");
+      dim3 g(nt, d.Fp / GD_M, S);
+      k_gemm_f32<float><<<g, 256, 0, s>>>(d.XT32, d.Np, W.uf, d.Np, P32, d.Fp, sstride, kc, d.Np);
+    }
+    const float* P = P32;
     switch (mode) {
       case EPI_STORE: k_dreduce<EPI_STORE, float><<<gr, 256, 0, s>>>(d.F, P, d.Fp, sstride, S, e, dots); break;
       case EPI_APPLY: k_dreduce<EPI_APPLY, float><<<gr, 256, 0, s>>>(d.F, P, d.Fp, sstride, S, e, dots); break;
@@ -806,10 +900,10 @@ rr_status pass_cols(rr_handle* h, int m, bool bf16, int mode, const DEpi& e, dou
 }
 
 // the operator on block V (FP64, and its BF16 copy Vb for the BF16 form)
-rr_status apply(rr_handle* h, int m, bool bf16, const double* V, const uint16_t* Vb, int mode,
+rr_status apply(rr_handle* h, int m, int op, const double* V, const uint16_t* Vb, int mode,
                 const DEpi& e, double* dots, hipStream_t s) {
-  RR_TRY(pass_rows(h, m, bf16, V, Vb, s));
-  return pass_cols(h, m, bf16, mode, e, dots, s);
+  RR_TRY(pass_rows(h, m, op, V, Vb, s));
+  return pass_cols(h, m, op, mode, e, dots, s);
 }
 
 DEpi epi(const DenseX& d, double* out, const double* p, const double* r, double lam) {
@@ -826,7 +920,7 @@ DEpi epi(const DenseX& d, double* out, const double* p, const double* r, double 
 
 struct BlockRun {
   int m = 0;
-  bool bf16 = false;
+  int op = OP_F64;                // operator precision
   int kind = RR_PRECOND_VCYCLE;
   double lam = 0.0, omega = 0.0, tol = 1e-10;
   int max_iter = 10000, fixed = 0;
@@ -855,17 +949,17 @@ rr_status precond(rr_handle* h, BlockRun& br, const double* r, double* z, double
       k_blk_additive<<<gv, 256, 0, s>>>(F, ld, r, W.D, br.omega, h->labels, h->cscale, W.yc, FC, z, dots);
       return RR_OK;
     default: {   // V(1,1)
-      uint16_t* vb = br.bf16 ? W.vb : nullptr;
+      uint16_t* vb = br.op == OP_BF16 ? W.vb : nullptr;
       k_blk_diag<<<gv, 256, 0, s>>>(F, ld, r, W.D, br.omega, W.e1, vb, nullptr);
       DEpi e1 = epi(d, W.rho, W.e1, r, br.lam);
-      RR_TRY(apply(h, m, br.bf16, W.e1, W.vb, EPI_RESID, e1, nullptr, s));
+      RR_TRY(apply(h, m, br.op, W.e1, W.vb, EPI_RESID, e1, nullptr, s));
       k_blk_restrict<<<gc, kBlock, 0, s>>>(FC, ld, h->perm, h->coff, h->cscale, W.rho, W.c, FC);
       k_blk_coarse<<<gc, kBlock, 0, s>>>(FC, br.sl->Ainv, W.c, W.yc, FC);
       k_blk_prolong<<<gf, kBlock, 0, s>>>(F, ld, W.e1, h->labels, h->cscale, W.yc, FC, W.e2, vb);
       DEpi e2 = epi(d, z, W.e2, r, br.lam);
       e2.D = W.D;
       e2.omega = br.omega;
-      RR_TRY(apply(h, m, br.bf16, W.e2, W.vb, EPI_POST, e2, dots, s));
+      RR_TRY(apply(h, m, br.op, W.e2, W.vb, EPI_POST, e2, dots, s));
       br.applies += 2;
       return RR_OK;
     }
@@ -888,13 +982,13 @@ rr_status block_pcg(rr_handle* h, BlockRun& br, const double* b, double* x, hipS
   k_blk_init<<<gv, 256, 0, s>>>(F, ld, b, x, W.r, pr_bb);
   k_col_start<<<1, ct, 0, s>>>(m, pr_bb, nb, W.bb, W.rr, W.done, W.iters, W.status, br.done_in);
   const double tol2 = br.tol * br.tol;
-  uint16_t* pb = br.bf16 ? W.vb : nullptr;
+  uint16_t* pb = br.op == OP_BF16 ? W.vb : nullptr;
   for (int it = 1; it <= br.max_iter; ++it) {
     RR_TRY(precond(h, br, W.r, W.z, pr_rz, s));
     k_col_beta<<<1, ct, 0, s>>>(m, pr_rz, nb, W.rz, W.beta, it == 1, W.done, W.status);
     k_blk_pdir<<<gv, 256, 0, s>>>(F, ld, W.z, W.p, pb, W.beta);
     DEpi eq = epi(d, W.q, W.p, nullptr, br.lam);
-    RR_TRY(apply(h, m, br.bf16, W.p, W.vb, EPI_APPLY_DOT, eq, pr_pq, s));
+    RR_TRY(apply(h, m, br.op, W.p, W.vb, EPI_APPLY_DOT, eq, pr_pq, s));
     ++br.applies;
     k_col_alpha<<<1, ct, 0, s>>>(m, pr_pq, nb, W.rz, W.alpha, W.done, W.status, W.iters, it);
     k_blk_update<<<gv, 256, 0, s>>>(F, ld, x, W.r, W.p, W.q, W.alpha, pr_rr);
@@ -966,9 +1060,9 @@ rr_status dense_setup(rr_handle* h, const rr_dense* Xin, const rr_setup_opts* o,
   if (h->nonneg) {   // g = X^T (X 1)
     DenseWork& W = *h->dwork;
     k_fill_ones<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, W.p);
-    RR_TRY(pass_rows(h, 1, false, W.p, nullptr, s));
+    RR_TRY(pass_rows(h, 1, OP_F64, W.p, nullptr, s));
     DEpi e = epi(d, W.q, nullptr, nullptr, 0.0);
-    RR_TRY(pass_cols(h, 1, false, EPI_STORE, e, nullptr, s));
+    RR_TRY(pass_cols(h, 1, OP_F64, EPI_STORE, e, nullptr, s));
     RR_HIP(hipMemcpyAsync(h->gersh, W.q, sizeof(double) * F, hipMemcpyDeviceToDevice, s));
     RR_HIP(hipMemsetAsync(W.p, 0, sizeof(double) * F, s));
   }
@@ -1040,9 +1134,9 @@ rr_status dense_apply_one(rr_handle* h, const double* v, double lam, double* t, 
   DenseX& d = *h->dense;
   DenseWork& W = *h->dwork;
   RR_HIP(hipMemcpyAsync(W.p, v, sizeof(double) * d.F, hipMemcpyDeviceToDevice, s));
-  RR_TRY(pass_rows(h, 1, false, W.p, nullptr, s));
+  RR_TRY(pass_rows(h, 1, OP_F64, W.p, nullptr, s));
   DEpi e = epi(d, W.q, W.p, nullptr, lam);
-  RR_TRY(pass_cols(h, 1, false, EPI_APPLY, e, nullptr, s));
+  RR_TRY(pass_cols(h, 1, OP_F64, EPI_APPLY, e, nullptr, s));
   RR_HIP(hipMemcpyAsync(t, W.q, sizeof(double) * d.F, hipMemcpyDeviceToDevice, s));
   return RR_OK;
 }
@@ -1052,17 +1146,17 @@ rr_status dense_apply_block(rr_handle* h, double lam, int m, const double* v, in
   DenseX& d = *h->dense;
   if (m < 1 || m > kMaxBlockRhs) return fail(RR_ERR_INVALID_ARG, "nrhs must be in [1, 4096]");
   if (!v || !q || ldv < d.F || ldq < d.F) return fail(RR_ERR_INVALID_ARG, "bad block arguments");
-  if (precision != RR_PREC_F64 && precision != RR_PREC_BF16_IR)
-    return fail(RR_ERR_INVALID_ARG, "precision must be RR_PREC_F64 or RR_PREC_BF16_IR");
+  if (precision != RR_PREC_F64 && precision != RR_PREC_BF16_IR && precision != RR_PREC_F32_IR)
+    return fail(RR_ERR_INVALID_ARG, "precision must be RR_PREC_F64, RR_PREC_F32_IR or RR_PREC_BF16_IR");
   RR_TRY(ensure_dwork(h, m));
   DenseWork& W = *h->dwork;
   hipError_t err;
   copy_block(W.p, d.Fp, v, ldv, d.F, m, s, &err);
   if (err != hipSuccess) return fail(RR_ERR_DEVICE, hipGetErrorString(err));
-  const bool bf = precision == RR_PREC_BF16_IR;
-  if (bf) k_blk_to_bf16<<<dim3(cdiv(d.F, kBlock), m), kBlock, 0, s>>>(d.F, d.Fp, W.p, W.vb);
+  const int op = precision == RR_PREC_BF16_IR ? OP_BF16 : (precision == RR_PREC_F32_IR ? OP_F32 : OP_F64);
+  if (op == OP_BF16) k_blk_to_bf16<<<dim3(cdiv(d.F, kBlock), m), kBlock, 0, s>>>(d.F, d.Fp, W.p, W.vb);
   DEpi e = epi(d, W.q, W.p, nullptr, lam);
-  RR_TRY(apply(h, m, bf, W.p, W.vb, EPI_APPLY, e, nullptr, s));
+  RR_TRY(apply(h, m, op, W.p, W.vb, EPI_APPLY, e, nullptr, s));
   copy_block(q, ldq, W.q, d.Fp, d.F, m, s, &err);
   if (err != hipSuccess) return fail(RR_ERR_DEVICE, hipGetErrorString(err));
   return RR_OK;
@@ -1091,11 +1185,11 @@ rr_status dense_solve_block(rr_handle* h, double lam, int m, const double* rhs, 
     return fail(RR_ERR_INVALID_ARG, "block solves take the none, Jacobi, V(1,1) and additive forms");
   if ((kind == RR_PRECOND_VCYCLE || kind == RR_PRECOND_ADDITIVE) && h->FC == 0)
     return fail(RR_ERR_INVALID_ARG, "two-level preconditioner needs a coarse level (n_clusters > 0)");
-  if (op.precision != RR_PREC_F64 && op.precision != RR_PREC_BF16_IR)
-    return fail(RR_ERR_INVALID_ARG, "precision must be RR_PREC_F64 or RR_PREC_BF16_IR");
+  if (op.precision != RR_PREC_F64 && op.precision != RR_PREC_BF16_IR && op.precision != RR_PREC_F32_IR)
+    return fail(RR_ERR_INVALID_ARG, "precision must be RR_PREC_F64, RR_PREC_F32_IR or RR_PREC_BF16_IR");
   if (op.max_iter < 0 || op.fixed_iters < 0 || op.tol < 0 || op.inner_tol < 0 || op.inner_tol >= 1)
     return fail(RR_ERR_INVALID_ARG, "bad solve option");
-  const bool ir = op.precision == RR_PREC_BF16_IR;
+  const bool ir = op.precision != RR_PREC_F64;
   if (ir && op.fixed_iters) return fail(RR_ERR_INVALID_ARG, "fixed_iters is not used with refinement");
   RR_TRY(ensure_dwork(h, m));
   DenseWork& W = *h->dwork;
@@ -1109,7 +1203,7 @@ rr_status dense_solve_block(rr_handle* h, double lam, int m, const double* rhs, 
     copy_block(W.u, d.Np, rhs, ld_rhs, N, m, s, &err);
     if (err != hipSuccess) return fail(RR_ERR_DEVICE, hipGetErrorString(err));
     DEpi e = epi(d, W.b, nullptr, nullptr, 0.0);
-    RR_TRY(pass_cols(h, m, false, EPI_STORE, e, nullptr, s));
+    RR_TRY(pass_cols(h, m, OP_F64, EPI_STORE, e, nullptr, s));
   }
   BlockRun br;
   br.m = m;
@@ -1152,7 +1246,8 @@ rr_status dense_solve_block(rr_handle* h, double lam, int m, const double* rhs, 
   } else {
     // refinement: wx = 0, wr = b; corrections A e = wr by BF16-operand PCG
     const double tol = br.tol;
-    const double itol = op.inner_tol > 0 ? op.inner_tol : 1e-3;
+    const bool f32 = op.precision == RR_PREC_F32_IR;
+    const double itol = op.inner_tol > 0 ? op.inner_tol : (f32 ? 1e-5 : 1e-3);
     constexpr int kMaxSteps = 60;
     RR_HIP(hipMemsetAsync(W.wx, 0, sizeof(double) * d.Fp * m, s));
     RR_HIP(hipMemcpyAsync(W.wr, W.b, sizeof(double) * d.Fp * m, hipMemcpyDeviceToDevice, s));
@@ -1165,7 +1260,7 @@ rr_status dense_solve_block(rr_handle* h, double lam, int m, const double* rhs, 
       rr[c] = bb[c];
       if (bb[c] == 0.0) odone[c] = 1;
     }
-    br.bf16 = true;
+    br.op = f32 ? OP_F32 : OP_BF16;
     br.tol = itol;
     br.fixed = 0;
     for (int step = 0; step < kMaxSteps; ++step) {
@@ -1180,9 +1275,9 @@ rr_status dense_solve_block(rr_handle* h, double lam, int m, const double* rhs, 
       RR_HIP(hipMemcpyAsync(st_in.data(), W.status, sizeof(int) * m, hipMemcpyDeviceToHost, s));
       k_blk_add<<<gf, kBlock, 0, s>>>(F, d.Fp, W.wx, W.x);
       // wr = b - A wx (FP64 operator) with its squared norms
-      RR_TRY(pass_rows(h, m, false, W.wx, nullptr, s));
+      RR_TRY(pass_rows(h, m, OP_F64, W.wx, nullptr, s));
       DEpi e = epi(d, W.wr, W.wx, W.b, lam);
-      RR_TRY(pass_cols(h, m, false, EPI_TRUE, e, pr_tr, s));
+      RR_TRY(pass_cols(h, m, OP_F64, EPI_TRUE, e, pr_tr, s));
       br.applies += 1;
       k_col_norms<<<1, ct, 0, s>>>(m, pr_tr, nb, W.pq);
       RR_HIP(hipMemcpyAsync(rr.data(), W.pq, sizeof(double) * m, hipMemcpyDeviceToHost, s));
@@ -1208,9 +1303,9 @@ rr_status dense_solve_block(rr_handle* h, double lam, int m, const double* rhs, 
     RR_HIP(hipMemcpyAsync(W.x, W.wx, sizeof(double) * d.Fp * m, hipMemcpyDeviceToDevice, s));
   }
   // true residual per column
-  RR_TRY(pass_rows(h, m, false, W.x, nullptr, s));
+  RR_TRY(pass_rows(h, m, OP_F64, W.x, nullptr, s));
   DEpi et = epi(d, W.q, W.x, W.b, lam);
-  RR_TRY(pass_cols(h, m, false, EPI_TRUE, et, pr_tr, s));
+  RR_TRY(pass_cols(h, m, OP_F64, EPI_TRUE, et, pr_tr, s));
   k_col_norms<<<1, ct, 0, s>>>(m, pr_tr, nb, W.pq);
   std::vector<double> tr(m);
   RR_HIP(hipMemcpyAsync(tr.data(), W.pq, sizeof(double) * m, hipMemcpyDeviceToHost, s));

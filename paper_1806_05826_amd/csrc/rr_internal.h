@@ -279,6 +279,7 @@ struct DenseWork {
   uint16_t* vb = nullptr;     // BF16 copy of the operator's input block
   uint16_t* ub = nullptr;     // BF16 U = X V  [Np x m_cap]
   double* u = nullptr;        // FP64 U        [Np x m_cap]
+  float* uf = nullptr;        // FP32 U        [Np x m_cap]
   void* part = nullptr;       // split-K partial sums
   size_t part_bytes = 0;
   double *c = nullptr, *yc = nullptr;   // coarse blocks [FC x m_cap]

@@ -60,6 +60,10 @@ def test_operator_f64_and_bf16(rr, small):
         # almost every U entry rounds the same way as the exact one
         rel = np.abs(Qb - want_b) / np.abs(want_b).max()
         assert np.median(rel) < 1e-5
+        Qf = host(R.apply_operator_block(0.7, V, precision="f32_ir"))
+        want_f = op.apply_A_f32(X, 0.7, V.T).T
+        bound_f = op.apply_A_f32_bound(X, V.T).T + 1e-12 * np.abs(want_f)
+        assert np.all(np.abs(Qf - want_f) <= bound_f), m
     R.close()
 
 
@@ -183,6 +187,22 @@ def test_block_solve_bf16_refinement(rr, clustered):
         w_star = krylov.reference_solution(X, Y[c], lam)
         err = np.linalg.norm(W[c] - w_star) / np.linalg.norm(w_star)
         print(f"[dense bf16 IR] col {c}: {infos[c]['ir_steps']} steps, {infos[c]['iters']} its, "
+              f"err {err:.2e}", flush=True)
+        assert infos[c]["status"] == 0 and infos[c]["ir_steps"] >= 2
+        assert err <= 1e-10
+
+
+def test_block_solve_f32_refinement(rr, clustered):
+    X, lab, fc, R = clustered
+    lam = 0.1
+    _, Y = datagen.targets(X, 81, n_rhs=5)
+    Y = Y.T.copy()
+    W, infos = R.solve_block(lam, Y, precond="vcycle", precision="f32_ir", tol=1e-13)
+    W = host(W)
+    for c in range(5):
+        w_star = krylov.reference_solution(X, Y[c], lam)
+        err = np.linalg.norm(W[c] - w_star) / np.linalg.norm(w_star)
+        print(f"[dense f32 IR] col {c}: {infos[c]['ir_steps']} steps, {infos[c]['iters']} its, "
               f"err {err:.2e}", flush=True)
         assert infos[c]["status"] == 0 and infos[c]["ir_steps"] >= 2
         assert err <= 1e-10

@@ -237,3 +237,20 @@ def test_bf16_operator_bound_covers_a_perturbed_sum():
     Xs[:, [0, 1]] = Xs[:, [1, 0]]                # a swapped pair of columns
     assert np.any(np.abs(op.apply_A_bf16(Xs, 0.5, V) - Q) > B)
     assert B.max() < 0.1 * np.abs(Q).max()
+
+
+def test_f32_operator_bound_covers_a_perturbed_sum():
+    """The FP32 bound admits an FP32-summed operator and rejects a swapped
+    pair of columns."""
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((300, 40)).astype(np.float32).astype(np.float64)
+    V = rng.standard_normal((40, 3))
+    Q = op.apply_A_f32(X, 0.5, V)
+    B = op.apply_A_f32_bound(X, V)
+    U32 = (X.astype(np.float32) @ V.astype(np.float32))
+    Q32 = (X.T.astype(np.float32) @ U32).astype(np.float64) + 0.5 * V
+    assert np.all(np.abs(Q32 - Q) <= B)
+    Xs = X.copy()
+    Xs[:, [0, 1]] = Xs[:, [1, 0]]
+    assert np.any(np.abs(op.apply_A_f32(Xs, 0.5, V) - Q) > B)
+    assert B.max() < 1e-3 * np.abs(Q).max()
