@@ -13,6 +13,14 @@
   plain PCG applies.
 * ``additive``: z = S r + P A_c^-1 P^T r (no extra operator application).
 
+* ``rougher``: the configuration of the paper's experiments (TLFCG): a
+  few iterations of plain CG on A e = r from e = 0 as pre-smoother (the
+  paper calls CG a rougher), then the coarse correction of the rougher's
+  residual, no post-smoothing:
+      e1 = CG_s(A, r);  rho = r - A e1 (the CG recurrence residual);
+      z = e1 + P A_c^-1 P^T rho.
+  It is not a fixed linear map of r, so it drives flexible CG.
+
 Block smoother (the cluster-aligned block option): S = omega D_B^-1 with D_B
 the block diagonal of A over blocks that never cross a cluster: each
 cluster's members in increasing feature index, cut into consecutive groups
@@ -82,6 +90,28 @@ def block_omega(X, lam: float, blocks: list, inv: list, seed: int, iters: int = 
     return 1.0 / (safety * rho)
 
 
+def cg_rougher(apply_A, r: np.ndarray, steps: int = 2):
+    """`steps` iterations of plain CG on A e = r from e = 0: returns e and the
+    recurrence residual r - A e (exact arithmetic).  Stops early when the
+    residual vanishes."""
+    r = np.asarray(r, dtype=np.float64)
+    e = np.zeros_like(r)
+    res = r.copy()
+    p = res.copy()
+    rr = float(res @ res)
+    for i in range(steps):
+        if rr == 0.0:
+            break
+        q = apply_A(p)
+        alpha = rr / float(p @ q)
+        e += alpha * p
+        res -= alpha * q
+        rr_new = float(res @ res)
+        p = res + (rr_new / rr) * p
+        rr = rr_new
+    return e, res
+
+
 class TwoLevel:
     def __init__(self, X, lam: float, labels: np.ndarray, F_C: int, omega: float,
                  smoother: str = "point", block_size: int = 32):
@@ -116,6 +146,10 @@ class TwoLevel:
     def additive(self, r):
         return self.smooth(r) + self.coarse_correction(r)
 
+    def rougher(self, r, steps: int = 2):
+        e1, rho = cg_rougher(lambda v: apply_A(self.X, self.lam, v), r, steps)
+        return e1 + self.coarse_correction(rho)
+
 
 def make(kind: str, X, lam: float, labels=None, F_C=None, omega=None, smoother="point"):
     """Return (apply_B, operator applications per call)."""
@@ -129,4 +163,6 @@ def make(kind: str, X, lam: float, labels=None, F_C=None, omega=None, smoother="
         return tl.vcycle, 2
     if kind == "additive":
         return tl.additive, 0
+    if kind == "rougher":
+        return tl.rougher, 2
     raise ValueError(kind)

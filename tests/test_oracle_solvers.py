@@ -261,3 +261,48 @@ def test_block_smoother_spd_and_weight():
     Bm = np.stack([tl.vcycle(e) for e in np.eye(F)], axis=1)
     assert np.abs(Bm - Bm.T).max() <= 1e-12 * np.abs(Bm).max()
     assert np.linalg.eigvalsh(0.5 * (Bm + Bm.T)).min() > 0
+
+
+# --- the CG rougher of the paper's experiments (TLFCG) -----------------------------
+
+def test_cg_rougher_is_the_krylov_optimum():
+    """Two CG steps from 0 give the A-orthogonal (Galerkin) projection of the
+    solution onto span{r, A r}, and the returned residual is r - A e."""
+    from oracle import precond
+    rng = np.random.default_rng(11)
+    M = rng.standard_normal((30, 30))
+    A = M @ M.T + 0.5 * np.eye(30)
+    r = rng.standard_normal(30)
+    e, res = precond.cg_rougher(lambda v: A @ v, r, 2)
+    V = np.stack([r, A @ r], axis=1)
+    c = np.linalg.solve(V.T @ A @ V, V.T @ r)
+    assert np.allclose(e, V @ c, rtol=1e-10, atol=1e-12)
+    assert np.allclose(res, r - A @ e, rtol=1e-10, atol=1e-12)
+
+
+def test_cg_rougher_exact_on_two_eigenvalues():
+    """A with two distinct eigenvalues: two CG steps solve A e = r exactly,
+    so the coarse correction of the residual adds nothing."""
+    from oracle import precond
+    rng = np.random.default_rng(12)
+    Q, _ = np.linalg.qr(rng.standard_normal((20, 20)))
+    A = Q @ np.diag([2.0] * 9 + [7.0] * 11) @ Q.T
+    r = rng.standard_normal(20)
+    e, res = precond.cg_rougher(lambda v: A @ v, r, 2)
+    assert np.allclose(e, np.linalg.solve(A, r), rtol=1e-12, atol=1e-12)
+    assert np.linalg.norm(res) <= 1e-12 * np.linalg.norm(r)
+
+
+def test_tlfcg_converges_to_the_solution():
+    """TLFCG reaches the dense Cholesky solution and needs fewer iterations
+    than unpreconditioned CG on a clustered tiny problem."""
+    import datagen
+    from oracle import kmeans, krylov
+    P = datagen.tiny_sparse()
+    lab, fc, _, _ = kmeans.kmeans_features(P.X, 50, 1)
+    x, inf = krylov.solve_tlfcg(P.X, P.y, 1.0, lab, fc, tol=1e-12)
+    ref = krylov.reference_solution(P.X, P.y, 1.0)
+    assert inf.status == 0
+    assert np.linalg.norm(x - ref) <= 1e-9 * np.linalg.norm(ref)
+    _, inf_cg = krylov.solve(P.X, P.y, 1.0, "none", tol=1e-12)
+    assert inf.iters < inf_cg.iters
