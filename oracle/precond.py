@@ -15,8 +15,9 @@
 
 * ``rougher``: the configuration of the paper's experiments (TLFCG): a
   few iterations of plain CG on A e = r from e = 0 as pre-smoother (the
-  paper calls CG a rougher), then the coarse correction of the rougher's
-  residual, no post-smoothing:
+  paper calls CG a rougher; a Jacobi-preconditioned CG variant is offered
+  too), then the coarse correction of the rougher's residual, no
+  post-smoothing:
       e1 = CG_s(A, r);  rho = r - A e1 (the CG recurrence residual);
       z = e1 + P A_c^-1 P^T rho.
   It is not a fixed linear map of r, so it drives flexible CG.
@@ -90,25 +91,28 @@ def block_omega(X, lam: float, blocks: list, inv: list, seed: int, iters: int = 
     return 1.0 / (safety * rho)
 
 
-def cg_rougher(apply_A, r: np.ndarray, steps: int = 2):
-    """`steps` iterations of plain CG on A e = r from e = 0: returns e and the
-    recurrence residual r - A e (exact arithmetic).  Stops early when the
-    residual vanishes."""
+def cg_rougher(apply_A, r: np.ndarray, steps: int = 2, D=None):
+    """`steps` iterations of CG on A e = r from e = 0 (plain CG, or
+    Jacobi-preconditioned CG with diagonal D): returns e and the recurrence
+    residual r - A e (exact arithmetic).  Stops early when the residual
+    vanishes."""
     r = np.asarray(r, dtype=np.float64)
     e = np.zeros_like(r)
     res = r.copy()
-    p = res.copy()
-    rr = float(res @ res)
+    z = res / D if D is not None else res.copy()
+    p = z.copy()
+    rz = float(res @ z)
     for i in range(steps):
-        if rr == 0.0:
+        if rz == 0.0:
             break
         q = apply_A(p)
-        alpha = rr / float(p @ q)
+        alpha = rz / float(p @ q)
         e += alpha * p
         res -= alpha * q
-        rr_new = float(res @ res)
-        p = res + (rr_new / rr) * p
-        rr = rr_new
+        z = res / D if D is not None else res
+        rz_new = float(res @ z)
+        p = z + (rz_new / rz) * p
+        rz = rz_new
     return e, res
 
 
@@ -146,8 +150,9 @@ class TwoLevel:
     def additive(self, r):
         return self.smooth(r) + self.coarse_correction(r)
 
-    def rougher(self, r, steps: int = 2):
-        e1, rho = cg_rougher(lambda v: apply_A(self.X, self.lam, v), r, steps)
+    def rougher(self, r, steps: int = 2, jacobi: bool = False):
+        e1, rho = cg_rougher(lambda v: apply_A(self.X, self.lam, v), r, steps,
+                             self.D if jacobi else None)
         return e1 + self.coarse_correction(rho)
 
 

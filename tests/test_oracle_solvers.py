@@ -306,3 +306,20 @@ def test_tlfcg_converges_to_the_solution():
     assert np.linalg.norm(x - ref) <= 1e-9 * np.linalg.norm(ref)
     _, inf_cg = krylov.solve(P.X, P.y, 1.0, "none", tol=1e-12)
     assert inf.iters < inf_cg.iters
+
+
+def test_jacobi_cg_rougher_is_the_preconditioned_optimum():
+    """Jacobi-PCG steps give the A-orthogonal projection onto the
+    preconditioned Krylov space span{D^-1 r, D^-1 A D^-1 r}."""
+    from oracle import precond
+    rng = np.random.default_rng(13)
+    M = rng.standard_normal((25, 25))
+    A = M @ M.T + 0.5 * np.eye(25)
+    D = np.diag(A).copy()
+    r = rng.standard_normal(25)
+    e, res = precond.cg_rougher(lambda v: A @ v, r, 2, D)
+    z0 = r / D
+    V = np.stack([z0, (A @ z0) / D], axis=1)
+    c = np.linalg.solve(V.T @ A @ V, V.T @ r)
+    assert np.allclose(e, V @ c, rtol=1e-10, atol=1e-12)
+    assert np.allclose(res, r - A @ e, rtol=1e-10, atol=1e-12)
