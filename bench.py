@@ -359,6 +359,22 @@ def main():
                 raise_on=(1, 2, 6))
     torch.cuda.synchronize()
     compare["fcg1_vcycle"] = {"lambda": lam, "iters": k, "ms": (time.perf_counter() - ta) * 1e3}
+    # the paper's configuration (TLFCG): flexible CG, two CG steps as rougher;
+    # and the variant whose rougher steps are Jacobi-preconditioned
+    for name, jac in (("tlfcg", False), ("tlfcg_jacobi_rougher", True)):
+        st, inf = rr.rr_solve(R.h, lam, y, w, tol=1e-14, max_iter=5000, precond="rougher",
+                              krylov="fcg", fcg_m=1, rougher_jacobi=jac, raise_on=(1, 2, 6))
+        wref = w.clone()
+        st, inf = rr.rr_solve(R.h, lam, y, w, tol=1e-300, x_ref=wref, err_tol=1e-10, max_iter=5000,
+                              precond="rougher", krylov="fcg", fcg_m=1, rougher_jacobi=jac,
+                              raise_on=(1, 2, 6))
+        k = inf["iters"]
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        rr.rr_solve(R.h, lam, y, w, fixed_iters=k, precond="rougher", krylov="fcg", fcg_m=1,
+                    rougher_jacobi=jac, chunk=16, raise_on=(1, 2, 6))
+        torch.cuda.synchronize()
+        compare[name] = {"lambda": lam, "iters": k, "ms": (time.perf_counter() - ta) * 1e3}
 
     # batched form: the three lambdas as one rr_solve_batched call on the same
     # handle (three work sets, concurrent) against three rr_solve calls, both

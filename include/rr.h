@@ -64,7 +64,7 @@ typedef enum {
                               z = e2 + w D^-1 rho2  (three operator applications
                               per PCG iteration, SPD for w rho(D^-1 A) < 2)      */
   RR_PRECOND_ADDITIVE = 3, /* z = w D^-1 r + P A_c^-1 P^T r                      */
-  RR_PRECOND_LEARNED = 4   /* the VCYCLE cycle with its coarse solve replaced by
+  RR_PRECOND_LEARNED = 4,  /* the VCYCLE cycle with its coarse solve replaced by
                               the network: e2 = e1 + P (||r_c|| y), y its output
                               for [r_c / ||r_c||, log lambda], r_c = P^T rho1
                               (rr_mlp_init / rr_mlp_train); no coarse Cholesky
@@ -72,6 +72,12 @@ typedef enum {
                               an iteration chunk that reduces ||r|| by less than
                               10 % the solve continues with RR_PRECOND_VCYCLE
                               (info.fallback_iter)                               */
+  RR_PRECOND_ROUGHER = 5   /* the configuration of the paper's experiments
+                              (TLFCG): rougher_steps iterations of plain CG on
+                              A e = r from e = 0 as pre-smoother, then
+                              z = e1 + P A_c^-1 P^T (r - A e1) with the CG
+                              recurrence residual; no post-smoothing;
+                              nonlinear, so flexible CG only                    */
 } rr_precond;
 
 typedef struct rr_handle rr_handle;
@@ -236,6 +242,11 @@ typedef struct {
                               additive, learned): point Jacobi (default) or the
                               block smoother of a handle set up with
                               block_smoother = 1 (FP64 solves)                   */
+  int32_t rougher_steps;   /* RR_PRECOND_ROUGHER: CG steps, 0 -> 2 (the paper's
+                              choice), at most 16                                */
+  int32_t rougher_jacobi;  /* RR_PRECOND_ROUGHER: 1 preconditions the rougher's
+                              CG steps with the Jacobi diagonal (a variant; the
+                              paper's rougher is plain CG)                       */
 } rr_solve_opts;
 
 typedef struct {

@@ -29,7 +29,7 @@ _lib = C.CDLL(LIB_PATH)
 
 RR_OK, RR_ERR_INVALID_ARG, RR_ERR_DEVICE = 0, 1, 2
 RR_ERR_NOT_CONVERGED, RR_ERR_BREAKDOWN, RR_ERR_UNSUPPORTED = 4, 5, 6
-PRECOND = {"none": 0, "jacobi": 1, "vcycle": 2, "additive": 3, "learned": 4}
+PRECOND = {"none": 0, "jacobi": 1, "vcycle": 2, "additive": 3, "learned": 4, "rougher": 5}
 KRYLOV = {"pcg": 0, "fcg": 1}
 SMOOTHER = {"point": 0, "block": 1}
 PRECISION = {"f64": 0, "f32_ir": 1, "bf16_ir": 2}
@@ -66,7 +66,8 @@ class rr_solve_opts(C.Structure):
                 ("x_ref", C.c_void_p), ("err_tol", C.c_double),
                 ("residual_history", C.c_void_p), ("chunk", C.c_int32), ("profile", C.c_int32),
                 ("krylov", C.c_int32), ("fcg_m", C.c_int32), ("precision", C.c_int32),
-                ("graph", C.c_int32), ("inner_tol", C.c_double), ("smoother", C.c_int32)]
+                ("graph", C.c_int32), ("inner_tol", C.c_double), ("smoother", C.c_int32),
+                ("rougher_steps", C.c_int32), ("rougher_jacobi", C.c_int32)]
 
 
 class rr_solve_info(C.Structure):
@@ -260,7 +261,7 @@ def rr_get_centres(h, centres, stream=None):
 def rr_solve(h, lam, rhs, w, tol=0.0, max_iter=0, fixed_iters=0, precond="vcycle",
              rhs_is_b=False, omega=0.0, x_ref=None, err_tol=0.0, residual_history=None,
              chunk=0, profile=False, krylov="pcg", fcg_m=0, precision="f64", inner_tol=0.0,
-             graph=False, smoother="point", stream=None,
+             graph=False, smoother="point", rougher_steps=0, rougher_jacobi=False, stream=None,
              raise_on=(RR_ERR_INVALID_ARG, RR_ERR_DEVICE, RR_ERR_UNSUPPORTED)):
     """Returns (status, info dict).  Statuses in `raise_on` raise RRError."""
     _dev_f64(rhs, None, "rhs")
@@ -272,7 +273,8 @@ def rr_solve(h, lam, rhs, w, tol=0.0, max_iter=0, fixed_iters=0, precond="vcycle
                       KRYLOV[krylov] if isinstance(krylov, str) else int(krylov), int(fcg_m),
                       PRECISION[precision] if isinstance(precision, str) else int(precision),
                       1 if graph else 0, float(inner_tol),
-                      SMOOTHER[smoother] if isinstance(smoother, str) else int(smoother))
+                      SMOOTHER[smoother] if isinstance(smoother, str) else int(smoother),
+                      int(rougher_steps), 1 if rougher_jacobi else 0)
     info = rr_solve_info()
     st = _lib.rr_solve(C.c_void_p(h), float(lam), _ptr(rhs), _ptr(w), C.byref(o), C.byref(info),
                        _stream(stream))

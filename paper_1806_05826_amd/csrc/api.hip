@@ -579,6 +579,33 @@ rr_status precond_two_level(rr_handle* h, Work& w, Prof& pf, int tag, int kind, 
   Epi er{};
   er.scale = h->cscale;
   er.out = w.c;
+  if (kind == PK_ROUGHER) {
+    // e1 = rsteps CG steps on A e = r from 0, rho its residual; then
+    // z = e1 + P A_c^-1 P^T rho (pre-smoothing only, as in the paper's runs)
+    double* rr_a = w.parts.init;
+    double* rr_b = w.parts.tr;
+    const int nv = w.parts.n_vec;
+    const double* Dj = w.rjacobi ? w.D : nullptr;
+    launch_rg_start(F, r, Dj, w.e2, rr_a, w.sc, stage, s);
+    for (int i = 0; i < w.rsteps; ++i) {
+      RR_TRY(op_csr(h, w, pf, tag, w.e2, s));
+      Epi eq = base_epi(w, lam);
+      eq.p = w.e2;
+      eq.out = w.q;
+      eq.partials = w.parts.pq;
+      int npq = 0;
+      RR_TRY(op_csc(h, w, pf, tag, EPI_APPLY_DOT, eq, s, &npq));
+      launch_rg_step(F, i == 0, r, Dj, w.e1, w.rho, w.e2, w.q, rr_a, nv, w.parts.pq, npq, rr_b, w.sc,
+                     s);
+      if (i + 1 < w.rsteps) launch_rg_dir(F, w.rho, Dj, w.e2, rr_b, nv, rr_a, nv, w.sc, s);
+      std::swap(rr_a, rr_b);
+    }
+    launch_segsum(w.rplan, h->coff + 1, h->perm, nullptr, w.rho, EPI_SCALE, er, done, s);
+    launch_gemv(h->FC, sl.Ainv, w.c, w.yc, done, s);
+    launch_prolong(F, h->labels, h->cscale, w.yc, w.e1, z, nullptr, nullptr, 0.0, 0, w.sc, nullptr, s);
+    *n_rz = 0;
+    return RR_OK;
+  }
   if (kind == PK_ADDITIVE) {
     if (stage) launch_stage_update(*stage, s);
     launch_segsum(w.rplan, h->coff + 1, h->perm, nullptr, r, EPI_SCALE, er, done, s);
@@ -677,9 +704,18 @@ rr_status Solve::begin() {
   RR_TRY(check_lambda(lam, false));
   if (!rhs || !wout) return fail(RR_ERR_INVALID_ARG, "null rhs or w");
   kind = op.precond;
-  if (kind < 0 || kind > 4) return fail(RR_ERR_INVALID_ARG, "unknown preconditioner");
-  if ((kind == PK_VCYCLE || kind == PK_ADDITIVE || kind == PK_LEARNED) && h->FC == 0)
+  if (kind < 0 || kind > 5) return fail(RR_ERR_INVALID_ARG, "unknown preconditioner");
+  if ((kind == PK_VCYCLE || kind == PK_ADDITIVE || kind == PK_LEARNED || kind == PK_ROUGHER) &&
+      h->FC == 0)
     return fail(RR_ERR_INVALID_ARG, "two-level preconditioner needs a coarse level (n_clusters > 0)");
+  if (kind == PK_ROUGHER) {
+    if (op.krylov != RR_KRYLOV_FCG)
+      return fail(RR_ERR_INVALID_ARG, "the CG rougher is nonlinear: use flexible CG");
+    if (op.rougher_steps < 0 || op.rougher_steps > 16)
+      return fail(RR_ERR_INVALID_ARG, "rougher_steps must be in [0, 16]");
+  }
+  ws->rsteps = op.rougher_steps > 0 ? op.rougher_steps : 2;
+  ws->rjacobi = op.rougher_jacobi != 0;
   if (kind == PK_LEARNED) {
     if (op.krylov != RR_KRYLOV_FCG)
       return fail(RR_ERR_INVALID_ARG, "the learned coarse correction is nonlinear: use flexible CG");
@@ -719,7 +755,7 @@ rr_status Solve::begin() {
     return fail(RR_ERR_INVALID_ARG, "no smoother blocks: set up with block_smoother = 1");
   w.block = block;
   omega = op.omega;
-  if (kind == PK_VCYCLE || kind == PK_ADDITIVE || kind == PK_LEARNED) {
+  if (kind == PK_VCYCLE || kind == PK_ADDITIVE || kind == PK_LEARNED || kind == PK_ROUGHER) {
     RR_TRY(get_slot(h, w.X, lam, &sl, &coarse_ms, s));
     sl->in_use++;
     if (block && sl->omega_block == 0.0) RR_TRY(omega_block_power(h, w.X, lam, *sl, s));
@@ -748,7 +784,7 @@ rr_status Solve::begin() {
     launch_gather(w.xref, op.x_ref, h->fperm, F, s);
     xref = w.xref;
   }
-  two_level = (kind == PK_VCYCLE || kind == PK_ADDITIVE || kind == PK_LEARNED);
+  two_level = (kind == PK_VCYCLE || kind == PK_ADDITIVE || kind == PK_LEARNED || kind == PK_ROUGHER);
   const int nv = w.parts.n_vec;
   launch_pcg_init(F, w.b, w.x, w.r, w.p, w.z, w.e1, w.D, xref, omega, kind, w.parts.init, s);
   launch_finish_init(w.sc, w.parts.init, nv, op.residual_history, kind, s);
@@ -935,7 +971,8 @@ rr_status Solve::finish(rr_solve_info* info) {
   inf.iters = hs.iter;
   // the V-cycle's two applications after the last update are skipped; the
   // ones before the first iteration are not
-  inf.op_applies = (kind == PK_VCYCLE || kind == PK_LEARNED) ? 3 * hs.iter : hs.iter;
+  inf.op_applies = (kind == PK_VCYCLE || kind == PK_LEARNED) ? 3 * hs.iter
+                   : kind == PK_ROUGHER ? (1 + w.rsteps) * hs.iter : hs.iter;
   inf.relres = hs.bb > 0 ? std::sqrt(hs.rr / hs.bb) : 0.0;
   inf.true_relres = hs.bb > 0 ? std::sqrt(hs.true_rr / hs.bb) : 0.0;
   inf.err = hs.ref2 > 0 ? std::sqrt(hs.ee / hs.ref2) : 0.0;

@@ -470,4 +470,84 @@ void launch_gemv(int n, const double* A, const double* x, double* y, const int* 
   if (n > 0) k_gemv<<<cdiv(n, kBlock / 64), kBlock, 0, s>>>(n, A, x, y, done);
 }
 
+// ---- CG rougher: CG on A e = r from e = 0 (plain, or Jacobi-preconditioned when D
+// is given; then the partials are <r, D^-1 r> and the directions D^-1 r + beta p) --
+
+__global__ __launch_bounds__(kBlock) void k_rg_start(int F, const double* __restrict__ r,
+                                                     const double* __restrict__ D,
+                                                     double* __restrict__ p, double* rr_parts,
+                                                     Scalars* sc, StageArgs stage) {
+  if (sc->done) return;
+  __shared__ double red[kBlock / 64];
+  if (stage.sc) {
+    double rz_unused;
+    if (stage_update<kBlock>(stage, red, rz_unused)) return;
+  }
+  double acc = 0.0;
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < F; j += gridDim.x * kBlock) {
+    const double v = r[j];
+    const double z = D ? v / D[j] : v;
+    p[j] = z;
+    acc += v * z;
+  }
+  store_block_partial<kBlock>(acc, rr_parts, blockIdx.x);
+}
+
+void launch_rg_start(int F, const double* r, const double* D, double* p, double* rr_parts,
+                     Scalars* sc, const StageArgs* stage, hipStream_t s) {
+  StageArgs st{};
+  if (stage) st = *stage;
+  k_rg_start<<<vec_grid(F), kBlock, 0, s>>>(F, r, D, p, rr_parts, sc, st);
+}
+
+__global__ __launch_bounds__(kBlock) void k_rg_step(int F, int first, const double* __restrict__ r,
+                                                    const double* __restrict__ D,
+                                                    double* __restrict__ e, double* __restrict__ res,
+                                                    const double* __restrict__ p,
+                                                    const double* __restrict__ q, const double* rr,
+                                                    int n_rr, const double* pq, int n_pq,
+                                                    double* rr_out, const Scalars* sc) {
+  if (sc->done) return;
+  __shared__ double red[kBlock / 64];
+  const double rrv = sum_parts<kBlock>(rr, n_rr, red);
+  const double pqv = sum_parts<kBlock>(pq, n_pq, red);
+  // a vanishing residual (or a breakdown) leaves the rougher where it is
+  const double alpha = (finite_pos(rrv) && finite_pos(pqv)) ? rrv / pqv : 0.0;
+  double acc = 0.0;
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < F; j += gridDim.x * kBlock) {
+    const double pj = p[j];
+    e[j] = (first ? 0.0 : e[j]) + alpha * pj;
+    const double v = (first ? r[j] : res[j]) - alpha * q[j];
+    res[j] = v;
+    acc += v * (D ? v / D[j] : v);
+  }
+  store_block_partial<kBlock>(acc, rr_out, blockIdx.x);
+}
+
+void launch_rg_step(int F, int first, const double* r, const double* D, double* e, double* res,
+                    const double* p, const double* q, const double* rr, int n_rr, const double* pq,
+                    int n_pq, double* rr_out, const Scalars* sc, hipStream_t s) {
+  k_rg_step<<<vec_grid(F), kBlock, 0, s>>>(F, first, r, D, e, res, p, q, rr, n_rr, pq, n_pq, rr_out,
+                                           sc);
+}
+
+__global__ __launch_bounds__(kBlock) void k_rg_dir(int F, const double* __restrict__ res,
+                                                   const double* __restrict__ D,
+                                                   double* __restrict__ p, const double* rr_new,
+                                                   int n_new, const double* rr_old, int n_old,
+                                                   const Scalars* sc) {
+  if (sc->done) return;
+  __shared__ double red[kBlock / 64];
+  const double a = sum_parts<kBlock>(rr_new, n_new, red);
+  const double b = sum_parts<kBlock>(rr_old, n_old, red);
+  const double beta = finite_pos(b) ? a / b : 0.0;
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < F; j += gridDim.x * kBlock)
+    p[j] = (D ? res[j] / D[j] : res[j]) + beta * p[j];
+}
+
+void launch_rg_dir(int F, const double* res, const double* D, double* p, const double* rr_new,
+                   int n_new, const double* rr_old, int n_old, const Scalars* sc, hipStream_t s) {
+  k_rg_dir<<<vec_grid(F), kBlock, 0, s>>>(F, res, D, p, rr_new, n_new, rr_old, n_old, sc);
+}
+
 }  // namespace rr

@@ -248,6 +248,8 @@ struct Work {
   MergePlan rplan;
   bool extra = false;             // an additional set (owns those buffers)
   bool block = false;             // the running solve smooths with the block smoother
+  int rsteps = 2;                 // CG steps of the rougher (RR_PRECOND_ROUGHER)
+  bool rjacobi = false;           // Jacobi-preconditioned rougher steps
   IrVectors f32;                  // single-precision vectors, allocated on first use
   ChunkGraph graph;               // captured PCG chunk (rr_solve_opts.graph)
   hipStream_t stream = nullptr;   // batched solves: this set's stream
@@ -402,7 +404,8 @@ int collapse_parts(double* partials, int n, const int* done, hipStream_t s);
 rr_status validate_csr(const Sparse& X, hipStream_t s);
 
 // ---- vector kernels (blas1.hip) ---------------------------------------------
-enum PcgKind { PK_NONE = 0, PK_JACOBI = 1, PK_VCYCLE = 2, PK_ADDITIVE = 3, PK_LEARNED = 4 };
+enum PcgKind { PK_NONE = 0, PK_JACOBI = 1, PK_VCYCLE = 2, PK_ADDITIVE = 3, PK_LEARNED = 4,
+               PK_ROUGHER = 5 };
 int vec_grid(int F);   // blocks of the PCG vector kernels (<= kMaxParts)
 void launch_pcg_init(int F, const double* b, double* x, double* r, double* p, double* z,
                      double* e1, const double* D, const double* xref, double omega, int kind,
@@ -480,6 +483,20 @@ rr_status run_kmeans(rr_handle* h, int k, uint64_t seed, int max_iter, hipStream
 rr_status set_labels(rr_handle* h, const int* labels_in, int nlab, hipStream_t s);
 rr_status build_coarse_gram(rr_handle* h, hipStream_t s);
 rr_status build_coarse_gram_valued(rr_handle* h, hipStream_t s);   // (api.hip)
+
+// ---- CG rougher (blas1.hip) --------------------------------------------------------
+// With D non-null the steps are Jacobi-preconditioned (z = D^-1 res).
+// Stage check of the preceding update, then p = z and <r, z> partials.
+void launch_rg_start(int F, const double* r, const double* D, double* p, double* rr_parts,
+                     Scalars* sc, const StageArgs* stage, hipStream_t s);
+// alpha = rz / pq; e = (first ? 0 : e) + alpha p; res = (first ? r : res) - alpha q;
+// <res, z> partials
+void launch_rg_step(int F, int first, const double* r, const double* D, double* e, double* res,
+                    const double* p, const double* q, const double* rr, int n_rr, const double* pq,
+                    int n_pq, double* rr_out, const Scalars* sc, hipStream_t s);
+// p = z + (rz_new / rz_old) p
+void launch_rg_dir(int F, const double* res, const double* D, double* p, const double* rr_new,
+                   int n_new, const double* rr_old, int n_old, const Scalars* sc, hipStream_t s);
 
 // ---- block smoother (block.hip) ------------------------------------------------
 constexpr int kSmoothBlock = 32;

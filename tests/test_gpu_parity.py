@@ -485,3 +485,54 @@ def test_block_smoother_valued_x(rr):
     assert abs(info["omega"] - om) <= 1e-10 * om
     assert np.linalg.norm(host(w) - x13) <= 1e-10 * np.linalg.norm(x13)
     R.close()
+
+
+# --- TLFCG: flexible CG with the CG rougher (the paper's configuration) -----------
+
+@pytest.mark.parametrize("steps", [2, 1, 3])
+def test_tlfcg_parity(rr, clustered, steps):
+    """Early iterates equal to the oracle's to rounding; converged iterates
+    within 1e-10; the natural stop within 2 iterations or 5 % of the oracle's
+    count (a nonlinear preconditioner inside flexible CG amplifies rounding
+    differences more than a fixed one)."""
+    name, P, R, (lab, fc, it, centres) = clustered
+    lam = 1.0
+    x3, _ = krylov.solve_tlfcg(P.X, P.y, lam, lab, fc, steps=steps, fixed_iters=3)
+    w, info = R.solve(lam, P.y, precond="rougher", krylov="fcg", fcg_m=1, rougher_steps=steps,
+                      fixed_iters=3)
+    assert info["iters"] == 3
+    assert np.linalg.norm(host(w) - x3) <= 1e-10 * np.linalg.norm(x3)
+    if steps != 2:
+        return
+    x13, inf13 = krylov.solve_tlfcg(P.X, P.y, lam, lab, fc, tol=1e-13)
+    w, info = R.solve(lam, P.y, precond="rougher", krylov="fcg", fcg_m=1, fixed_iters=inf13.iters)
+    assert np.linalg.norm(host(w) - x13) <= 1e-10 * np.linalg.norm(x13)
+    _, inf = krylov.solve_tlfcg(P.X, P.y, lam, lab, fc, tol=1e-10)
+    w, info = R.solve(lam, P.y, precond="rougher", krylov="fcg", fcg_m=1, tol=1e-10)
+    print(f"[tlfcg {name}] gpu {info['iters']} its, oracle {inf.iters}; "
+          f"operator applications {info['op_applies']}", flush=True)
+    assert info["status"] == 0 and info["true_relres"] <= 1e-9
+    assert abs(info["iters"] - inf.iters) <= max(2, inf.iters // 20)
+
+
+def test_tlfcg_jacobi_rougher(rr, clustered):
+    """The Jacobi-preconditioned rougher: early and converged iterates equal
+    to the oracle's."""
+    name, P, R, (lab, fc, it, centres) = clustered
+    lam = 1.0
+    x3, _ = krylov.solve_tlfcg(P.X, P.y, lam, lab, fc, fixed_iters=3, jacobi=True)
+    w, info = R.solve(lam, P.y, precond="rougher", krylov="fcg", fcg_m=1, rougher_jacobi=True,
+                      fixed_iters=3)
+    assert np.linalg.norm(host(w) - x3) <= 1e-10 * np.linalg.norm(x3)
+    x13, inf13 = krylov.solve_tlfcg(P.X, P.y, lam, lab, fc, tol=1e-13, jacobi=True)
+    w, info = R.solve(lam, P.y, precond="rougher", krylov="fcg", fcg_m=1, rougher_jacobi=True,
+                      fixed_iters=inf13.iters)
+    print(f"[tlfcg jacobi {name}] oracle {inf13.iters} its to 1e-13", flush=True)
+    assert np.linalg.norm(host(w) - x13) <= 1e-10 * np.linalg.norm(x13)
+
+
+def test_tlfcg_needs_flexible_cg(rr, clustered):
+    name, P, R, _ = clustered
+    with pytest.raises(rr.RRError) as e:
+        R.solve(1.0, P.y, precond="rougher")
+    assert e.value.status == rr.RR_ERR_INVALID_ARG
