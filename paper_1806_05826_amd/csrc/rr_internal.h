@@ -160,6 +160,8 @@ struct SellPlan {
   int* bslice = nullptr;      // [nblk] slice of every workgroup
   int* pos = nullptr;         // [nitems] output position of every piece of a (segment, slice) pair
   int* sbase = nullptr;       // [S+1] first piece of every segment
+  int* lseg = nullptr;        // [nlong] segments of more than 16 pieces (added by a wave each)
+  int nlong = 0;
   double* part = nullptr;     // [nout] partial sums
 };
 

@@ -6,16 +6,18 @@
 // into slices of W entries whose part of v fits in LDS (W = 16384 FP64 =
 // 128 KB, plus one zero entry used for padding).  Every nonempty (segment,
 // slice) pair produces one partial sum, or one per piece when it is cut into
-// pieces to keep lane streams short.  Workgroups own one slice each; they
+// pieces to keep lane streams short or a long pair's wave task near the
+// others' load.  Workgroups own one slice each; they
 // copy its part of v into LDS and then work through wave tasks:
 //   * lane tasks: 64 lane streams of uint16 local indexes, entry k of lane l
 //     stored at base + 256 (k / 4) + 4 l + k % 4, so a lane loads four
 //     consecutive entries (8 bytes) at a time and every load instruction
-//     reads 512 consecutive bytes.  A lane stream holds one pair or, for short
-//     pairs, several pairs back to back; bit 15 marks the last entry of a
-//     pair, where the lane writes its running sum to the next of its output
-//     positions (base + 64 c + l) and restarts.  Streams are padded with the
-//     zero entry to the task's longest one, rounded up to a multiple of 4;
+//     reads 512 consecutive bytes.  A lane task is a stack of layers of 64
+//     pairs of nearly equal length: lane l takes the l-th pair of every
+//     layer, padded with the zero entry to the layer's longest; bit 15 marks
+//     the layer's last entry in every lane, where all 64 lanes write their
+//     running sums together (layer c to base + 64 c + l) and restart.  The
+//     task is padded to a multiple of 4 entries;
 //   * wave tasks: one long pair, stored contiguously and padded to a
 //     multiple of 64 entries; lane l reads 8 entries (16 bytes) of every full
 //     512 and one entry (2 bytes) of every 64 of the rest, then the wave adds
@@ -93,6 +95,30 @@ __device__ inline void sell_body(const int* __restrict__ wrange, const int* __re
   if (t0 + lane < t1) my = task[t0 + lane];
   const int g0 = bslice[blockIdx.x] * W;
   fill_slice(vs, v + g0, min(W, gdim - g0));
+  // Lane-task batches of kLaneUnroll 8-byte loads run one ahead: `pre` holds
+  // the loads of the next batch (the rest of this task, else the first batch
+  // of the next task if that is a lane task described by the same
+  // descriptor load), issued before the current batch is summed.
+  uint2 pre[kLaneUnroll];
+  bool have = false;
+  auto issue = [&](int base, int g, int ng) {
+    const uint2* p = reinterpret_cast<const uint2*>(idx + base) + lane;
+#pragma unroll
+    for (int j = 0; j < kLaneUnroll; ++j) pre[j] = (g + j < ng) ? p[(size_t)(g + j) * 64] : make_uint2(0u, 0u);
+  };
+  // the first batch of task tn, if it is a lane task and its descriptor is in
+  // the block loaded last
+  auto issue_task = [&](int tn) {
+    const int k = (tn - t0) & 63;
+    if (tn < t1 && __builtin_amdgcn_readlane(my.x, k) == 0) {
+      issue(__builtin_amdgcn_readlane(my.y, k), 0, __builtin_amdgcn_readlane(my.z, k) / kLaneGroup);
+      have = true;
+    }
+  };
+  auto issue_next = [&](int t) {
+    if (((t + 1 - t0) & 63) != 0) issue_task(t + 1);
+  };
+  issue_task(t0);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   for (int t = t0; t < t1; ++t) {
@@ -107,7 +133,6 @@ __device__ inline void sell_body(const int* __restrict__ wrange, const int* __re
     const int obase = __builtin_amdgcn_readlane(my.w, i);
     if (kind == 0) {
       // group g of lane l: entries 4 g .. 4 g + 3 in one 8-byte load
-      const uint2* p = reinterpret_cast<const uint2*>(idx + base) + lane;
       T* o = out + obase + lane;
       T acc = T(0);
       const int ng = len / kLaneGroup;
@@ -119,27 +144,22 @@ __device__ inline void sell_body(const int* __restrict__ wrange, const int* __re
           acc = T(0);
         }
       };
-      int g = 0;
-      for (; g + kLaneUnroll <= ng; g += kLaneUnroll) {
+      for (int g = 0; g < ng; g += kLaneUnroll) {
+        if (!have) issue(base, g, ng);
         uint2 q[kLaneUnroll];
 #pragma unroll
-        for (int j = 0; j < kLaneUnroll; ++j) q[j] = p[(size_t)(g + j) * 64];
-#pragma unroll
-        for (int j = 0; j < kLaneUnroll; ++j) {
-          add(q[j].x & 0xffffu);
-          add(q[j].x >> 16);
-          add(q[j].y & 0xffffu);
-          add(q[j].y >> 16);
+        for (int j = 0; j < kLaneUnroll; ++j) q[j] = pre[j];
+        have = false;
+        if (g + kLaneUnroll < ng) {
+          issue(base, g + kLaneUnroll, ng);
+          have = true;
+        } else {
+          issue_next(t);
         }
-      }
-      if (g < ng) {   // the rest (ng is the same in every lane): loads issued together
-        uint2 q[kLaneUnroll];
-#pragma unroll
-        for (int j = 0; j < kLaneUnroll; ++j)
-          q[j] = (g + j < ng) ? p[(size_t)(g + j) * 64] : make_uint2(0u, 0u);
+        const int cnt = min(kLaneUnroll, ng - g);
 #pragma unroll
         for (int j = 0; j < kLaneUnroll; ++j) {
-          if (g + j < ng) {
+          if (j < cnt) {
             add(q[j].x & 0xffffu);
             add(q[j].x >> 16);
             add(q[j].y & 0xffffu);
@@ -148,6 +168,7 @@ __device__ inline void sell_body(const int* __restrict__ wrange, const int* __re
         }
       }
     } else {
+      issue_next(t);
       const uint4* p = reinterpret_cast<const uint4*>(idx) + base + lane;
       const int ng = len >> 4, nt = len & 15;
       T acc[4] = {T(0), T(0), T(0), T(0)};
@@ -225,32 +246,56 @@ __global__ __launch_bounds__(kSliceBlock) void k_sell32(const int* __restrict__ 
   sell_body<float>(wrange, bslice, task, idx, v, gdim, W, out, done, stage);
 }
 
-// segment s: t = sum of its partial sums in slice order, then the epilogue.
-// One thread per segment; the positions and values of up to 16 pieces are
-// loaded together.
+// segment s: t = sum of its partial sums, then the epilogue.  Segments of
+// up to kReduceBatch pieces take one thread, which loads the positions and
+// values of all pieces together and adds them in slice order; the longer
+// ones (listed in lseg) take a whole wave each, lane i adding pieces i,
+// i + 64, ... before a fixed butterfly.
 constexpr int kReduceBatch = 16;
+
+template <typename T>
+__device__ inline T short_seg_sum(const T* __restrict__ part, const int* __restrict__ pos, int a, int z) {
+  int pi[kReduceBatch];
+#pragma unroll
+  for (int j = 0; j < kReduceBatch; ++j) pi[j] = (a + j < z) ? pos[a + j] : -1;
+  T pv[kReduceBatch];
+#pragma unroll
+  for (int j = 0; j < kReduceBatch; ++j) pv[j] = (pi[j] >= 0) ? part[pi[j]] : T(0);
+  T t = T(0);
+#pragma unroll
+  for (int j = 0; j < kReduceBatch; ++j)
+    if (a + j < z) t += pv[j];
+  return t;
+}
+
+template <typename T>
+__device__ inline T long_seg_sum(const T* __restrict__ part, const int* __restrict__ pos, int a, int z,
+                                 int lane) {
+  T t = T(0);
+  for (int k = a + lane; k < z; k += 64) t += part[pos[k]];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+  return t;
+}
+
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_sell_reduce(const double* __restrict__ part,
                                                        const int* __restrict__ pos,
                                                        const int* __restrict__ sbase, int S,
+                                                       const int* __restrict__ lseg, int nlong,
                                                        Epi e, const int* done) {
   if (is_done(done)) return;
   double dot = 0.0;
-  for (int s = blockIdx.x * kBlock + threadIdx.x; s < S; s += gridDim.x * kBlock) {
+  const int gt = blockIdx.x * kBlock + threadIdx.x, nt = gridDim.x * kBlock;
+  for (int L = gt >> 6; L < nlong; L += nt >> 6) {
+    const int s = lseg[L];
+    const double t = long_seg_sum(part, pos, sbase[s], sbase[s + 1], threadIdx.x & 63);
+    if ((threadIdx.x & 63) == 0) seg_finish<MODE>(s, t, e, dot);
+  }
+  for (int s = gt; s < S; s += nt) {
     const int a = sbase[s], z = sbase[s + 1];
-    double t = 0.0;
-    for (int k0 = a; k0 < z; k0 += kReduceBatch) {
-      int pi[kReduceBatch];
-#pragma unroll
-      for (int j = 0; j < kReduceBatch; ++j) pi[j] = (k0 + j < z) ? pos[k0 + j] : -1;
-      double pv[kReduceBatch];
-#pragma unroll
-      for (int j = 0; j < kReduceBatch; ++j) pv[j] = (pi[j] >= 0) ? part[pi[j]] : 0.0;
-#pragma unroll
-      for (int j = 0; j < kReduceBatch; ++j)
-        if (k0 + j < z) t += pv[j];
-    }
-    seg_finish<MODE>(s, t, e, dot);
+    if (z - a > kReduceBatch) continue;
+    seg_finish<MODE>(s, short_seg_sum(part, pos, a, z), e, dot);
   }
   if constexpr (has_dot<MODE>()) store_block_partial<kBlock>(dot, e.partials, blockIdx.x);
 }
@@ -264,24 +309,12 @@ template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_sell_reduce32(const float* __restrict__ part,
                                                          const int* __restrict__ pos,
                                                          const int* __restrict__ sbase, int S,
+                                                         const int* __restrict__ lseg, int nlong,
                                                          Epi32 e, const int* done) {
   if (is_done(done)) return;
   double dot = 0.0;
   const float lam = (float)e.lam, omega = (float)e.omega;
-  for (int s = blockIdx.x * kBlock + threadIdx.x; s < S; s += gridDim.x * kBlock) {
-    const int a = sbase[s], z = sbase[s + 1];
-    float t = 0.0f;
-    for (int k0 = a; k0 < z; k0 += kReduceBatch) {
-      int pi[kReduceBatch];
-#pragma unroll
-      for (int j = 0; j < kReduceBatch; ++j) pi[j] = (k0 + j < z) ? pos[k0 + j] : -1;
-      float pv[kReduceBatch];
-#pragma unroll
-      for (int j = 0; j < kReduceBatch; ++j) pv[j] = (pi[j] >= 0) ? part[pi[j]] : 0.0f;
-#pragma unroll
-      for (int j = 0; j < kReduceBatch; ++j)
-        if (k0 + j < z) t += pv[j];
-    }
+  auto finish = [&](int s, float t) {
     if constexpr (MODE == EPI_STORE) {
       e.out[s] = t;
     } else if constexpr (MODE == EPI_APPLY_DOT) {
@@ -298,6 +331,17 @@ __global__ __launch_bounds__(kBlock) void k_sell_reduce32(const float* __restric
       e.out[s] = zz;
       dot += (double)rs * (double)zz;
     }
+  };
+  const int gt = blockIdx.x * kBlock + threadIdx.x, nt = gridDim.x * kBlock;
+  for (int L = gt >> 6; L < nlong; L += nt >> 6) {
+    const int s = lseg[L];
+    const float t = long_seg_sum(part, pos, sbase[s], sbase[s + 1], threadIdx.x & 63);
+    if ((threadIdx.x & 63) == 0) finish(s, t);
+  }
+  for (int s = gt; s < S; s += nt) {
+    const int a = sbase[s], z = sbase[s + 1];
+    if (z - a > kReduceBatch) continue;
+    finish(s, short_seg_sum(part, pos, a, z));
   }
   if constexpr (MODE == EPI_APPLY_DOT || MODE == EPI_POST)
     store_block_partial<kBlock>(dot, e.partials, blockIdx.x);
@@ -320,16 +364,20 @@ int launch_sell32(const SellPlan& sp, float* part, const float* v, int mode, con
   const int g = sell_reduce_grid(sp.S);
   switch (mode) {
     case EPI_STORE:
-      k_sell_reduce32<EPI_STORE><<<g, kBlock, 0, s>>>(part, sp.pos, sp.sbase, sp.S, e, done);
+      k_sell_reduce32<EPI_STORE><<<g, kBlock, 0, s>>>(part, sp.pos, sp.sbase, sp.S, sp.lseg, sp.nlong, e,
+                                                   done);
       return 0;
     case EPI_APPLY_DOT:
-      k_sell_reduce32<EPI_APPLY_DOT><<<g, kBlock, 0, s>>>(part, sp.pos, sp.sbase, sp.S, e, done);
+      k_sell_reduce32<EPI_APPLY_DOT><<<g, kBlock, 0, s>>>(part, sp.pos, sp.sbase, sp.S, sp.lseg, sp.nlong, e,
+                                                       done);
       break;
     case EPI_RESID:
-      k_sell_reduce32<EPI_RESID><<<g, kBlock, 0, s>>>(part, sp.pos, sp.sbase, sp.S, e, done);
+      k_sell_reduce32<EPI_RESID><<<g, kBlock, 0, s>>>(part, sp.pos, sp.sbase, sp.S, sp.lseg, sp.nlong, e,
+                                                   done);
       return 0;
     case EPI_POST:
-      k_sell_reduce32<EPI_POST><<<g, kBlock, 0, s>>>(part, sp.pos, sp.sbase, sp.S, e, done);
+      k_sell_reduce32<EPI_POST><<<g, kBlock, 0, s>>>(part, sp.pos, sp.sbase, sp.S, sp.lseg, sp.nlong, e,
+                                                  done);
       break;
     default:
       return 0;
@@ -340,7 +388,7 @@ int launch_sell32(const SellPlan& sp, float* part, const float* v, int mode, con
 template <int MODE>
 static void sell_reduce_mode(const SellPlan& sp, const Epi& e, const int* done, hipStream_t s) {
   k_sell_reduce<MODE><<<sell_reduce_grid(sp.S), kBlock, 0, s>>>(sp.part, sp.pos, sp.sbase, sp.S,
-                                                                e, done);
+                                                                sp.lseg, sp.nlong, e, done);
 }
 
 int launch_sell(const SellPlan& sp, const double* v, int mode, const Epi& e, const int* done,
@@ -389,6 +437,7 @@ void free_sell(SellPlan& sp) {
   if (sp.bslice) (void)hipFree(sp.bslice);
   if (sp.pos) (void)hipFree(sp.pos);
   if (sp.sbase) (void)hipFree(sp.sbase);
+  if (sp.lseg) (void)hipFree(sp.lseg);
   if (sp.part) (void)hipFree(sp.part);
   sp = SellPlan{};
 }
@@ -409,37 +458,37 @@ struct SellBuild {
   int nout = 0;
 };
 
-// One lane task from up to 64 lane streams, each a list of pairs.
-void emit_lane_task(SellBuild& B, const std::vector<std::vector<int>>& lanes,
-                    const std::vector<Pair>& pairs, const std::vector<int>& gidx, int g0, int W,
-                    int r) {
-  int m = 0, J = 0;
-  for (const auto& ln : lanes) {
-    int len = 0;
-    for (int pi : ln) len += pairs[pi].len;
-    m = std::max(m, len);
-    J = std::max(J, (int)ln.size());
-  }
+// One lane task from a stack of layers of up to 64 pairs each: lane l takes
+// the layer's l-th pair, padded with the zero entry to the layer's length
+// llen[c] (its longest pair), and every lane's stream carries the end flag on
+// the layer's last entry, so that the layer's 64 sums are stored together,
+// at obase + 64 c + l.
+void emit_layer_task(SellBuild& B, const std::vector<std::vector<int>>& layers,
+                     const std::vector<int>& llen, const std::vector<Pair>& pairs,
+                     const std::vector<int>& gidx, int g0, int W, int r) {
+  int m = 0;
+  for (int L : llen) m += L;
   m = (m + kLaneGroup - 1) / kLaneGroup * kLaneGroup;
-  const int base = (int)B.idx.size();   // a multiple of 64: every task fills whole 64-entry rows
-  B.idx.resize(B.idx.size() + (size_t)m * 64, (uint16_t)W);
+  const size_t base = B.idx.size();   // a multiple of 64: every task fills whole 64-entry rows
+  B.idx.resize(base + (size_t)m * 64, (uint16_t)W);
+  auto at = [&](int k, int l) {
+    return base + (size_t)(k / kLaneGroup) * 64 * kLaneGroup + (size_t)l * kLaneGroup + k % kLaneGroup;
+  };
   const int obase = B.nout;
-  for (int l = 0; l < (int)lanes.size(); ++l) {
-    int k = 0, c = 0;
-    for (int pi : lanes[l]) {
-      const Pair& pa = pairs[pi];
-      for (int e = 0; e < pa.len; ++e, ++k) {
-        unsigned q = (unsigned)(gidx[pa.start + e] - g0);
-        if (e == pa.len - 1) q |= kEndFlag;
-        B.idx[base + (size_t)(k / kLaneGroup) * 64 * kLaneGroup + (size_t)l * kLaneGroup + k % kLaneGroup] =
-            (uint16_t)q;
+  int k0 = 0;
+  for (size_t c = 0; c < layers.size(); ++c) {
+    for (int l = 0; l < 64; ++l) {
+      if (l < (int)layers[c].size()) {
+        const Pair& pa = pairs[layers[c][l]];
+        for (int e = 0; e < pa.len; ++e) B.idx[at(k0 + e, l)] = (uint16_t)(gidx[pa.start + e] - g0);
+        B.pos[layers[c][l]] = obase + (int)c * 64 + l;
       }
-      B.pos[pi] = obase + c * 64 + l;
-      ++c;
+      B.idx[at(k0 + llen[c] - 1, l)] |= (uint16_t)kEndFlag;
     }
+    k0 += llen[c];
   }
-  B.nout += J * 64;
-  B.tasks.push_back(make_int4(0, base, m, obase));
+  B.nout += (int)layers.size() * 64;
+  B.tasks.push_back(make_int4(0, (int)base, m, obase));
   B.tcost.push_back((long long)m + 4);
   B.tslice.push_back(r);
 }
@@ -478,12 +527,17 @@ rr_status build_sell(SellPlan& sp, const std::vector<int>& ptr, const std::vecto
   sp.nslots = (int)pairs.size();
   const long long nnz = ptr[S];
   // lane streams of about `target` entries; pairs of (2, 4] target entries
-  // are cut in two halves, each with its own partial sum; longer pairs get a
-  // whole wave
+  // are cut in two halves, each with its own partial sum; longer pairs get
+  // wave tasks
   const int target = (int)std::min<long long>(
       64, std::max<long long>(8, nnz / std::max(1LL, (long long)num_cu * kSliceWaves * 64 *
                                                         std::max(1, target_div))));
   const int cmax = 2 * target;
+  // pairs longer than hcap entries (a wave's mean share of the pass, in
+  // whole 512-entry groups) become several wave tasks, so that no wave holds
+  // one pair much longer than the others' work
+  const int hcap = (int)std::max<long long>(
+      1024, nnz / ((long long)std::max(1, num_cu) * kSliceWaves) / 512 * 512);
   std::vector<Pair> items;
   std::vector<int> islice;
   std::vector<int> sbase(S + 1, 0);
@@ -493,6 +547,15 @@ rr_status build_sell(SellPlan& sp, const std::vector<int>& ptr, const std::vecto
     if (q == (size_t)S) break;
     for (; i < pairs.size() && pseg[i] == (int)q; ++i) {
       const Pair pa = pairs[i];
+      if (pa.len > hcap) {
+        const int nc = cdiv(pa.len, hcap);
+        const int step = cdiv(cdiv(pa.len, nc), 512) * 512;
+        for (int a = 0; a < pa.len; a += step) {
+          items.push_back({pa.start + a, std::min(step, pa.len - a)});
+          islice.push_back(pslice[i]);
+        }
+        continue;
+      }
       const int nc = (pa.len > cmax && pa.len <= 2 * cmax) ? 2 : 1;
       for (int c = 0; c < nc; ++c) {
         const int a = (int)((long long)pa.len * c / nc), b = (int)((long long)pa.len * (c + 1) / nc);
@@ -504,11 +567,8 @@ rr_status build_sell(SellPlan& sp, const std::vector<int>& ptr, const std::vecto
   pairs.swap(items);
   pslice.swap(islice);
   sp.nitems = (int)pairs.size();
-  std::vector<std::vector<int>> light(R), medium(R), heavy(R);
-  for (int i = 0; i < (int)pairs.size(); ++i) {
-    const int len = pairs[i].len;
-    (len > cmax ? heavy : (len > target ? medium : light))[pslice[i]].push_back(i);
-  }
+  std::vector<std::vector<int>> small(R), heavy(R);
+  for (int i = 0; i < (int)pairs.size(); ++i) (pairs[i].len > cmax ? heavy : small)[pslice[i]].push_back(i);
   SellBuild B;
   B.pos.assign(pairs.size(), -1);
   const uint16_t pad = (uint16_t)W;   // index of the zero entry
@@ -530,52 +590,60 @@ rr_status build_sell(SellPlan& sp, const std::vector<int>& ptr, const std::vecto
       B.tcost.push_back((long long)ng * 8 + nt + 8);
       B.tslice.push_back(r);
     }
-    // medium pairs: one per lane, 64 of similar length per task
-    std::vector<int>& md = medium[r];
-    std::sort(md.begin(), md.end(), by_len_desc);
-    for (size_t c = 0; c < md.size(); c += 64) {
-      std::vector<std::vector<int>> lanes;
-      for (size_t l = c; l < std::min(md.size(), c + 64); ++l) lanes.push_back({md[l]});
-      emit_lane_task(B, lanes, pairs, gidx, g0, W, r);
+  }
+  // short pairs, longest first, in layers of 64; the layers, longest first,
+  // go to the least loaded of ntask stacks, one lane task each.  Returns the
+  // number of tasks, adds their cost to *cost and emits them if asked.
+  auto pack_small = [&](int r, int ntask, bool emit, long long* cost) -> int {
+    const std::vector<int>& sm = small[r];
+    const int nlay = cdiv((int)sm.size(), 64);
+    std::vector<std::vector<int>> stack(ntask);
+    std::vector<long long> load(ntask, 0);
+    using Item = std::pair<long long, int>;   // (load, stack)
+    std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
+    for (int k = 0; k < ntask; ++k) heap.push({0, k});
+    for (int c = 0; c < nlay; ++c) {
+      const Item it = heap.top();
+      heap.pop();
+      stack[it.second].push_back(c);
+      load[it.second] += pairs[sm[64 * c]].len;
+      heap.push({load[it.second], it.second});
     }
-    // short pairs: longest first onto the least loaded of nl lane streams
-    std::vector<int>& lt = light[r];
-    if (!lt.empty()) {
-      std::sort(lt.begin(), lt.end(), by_len_desc);
-      long long tot = 0;
-      for (int i : lt) tot += pairs[i].len;
-      const int nl = 64 * std::max(1, cdiv(tot, 64LL * target));
-      std::vector<std::vector<int>> lanes(nl);
-      std::vector<int> load(nl, 0);
-      using Item = std::pair<int, int>;   // (load, lane)
-      std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
-      for (int l = 0; l < nl; ++l) heap.push({0, l});
-      for (int i : lt) {
-        const Item it = heap.top();
-        heap.pop();
-        lanes[it.second].push_back(i);
-        load[it.second] += pairs[i].len;
-        heap.push({load[it.second], it.second});
+    int cnt = 0;
+    for (int k = 0; k < ntask; ++k) {
+      if (stack[k].empty()) continue;
+      ++cnt;
+      *cost += (load[k] + kLaneGroup - 1) / kLaneGroup * kLaneGroup + 4;
+      if (!emit) continue;
+      std::vector<std::vector<int>> layers;
+      std::vector<int> llen;
+      for (int c : stack[k]) {
+        layers.emplace_back(sm.begin() + 64 * c, sm.begin() + std::min<size_t>(sm.size(), 64 * c + 64));
+        llen.push_back(pairs[sm[64 * c]].len);
       }
-      std::vector<int> order(nl);
-      std::iota(order.begin(), order.end(), 0);
-      std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return load[a] > load[b]; });
-      for (int c = 0; c < nl; c += 64) {
-        std::vector<std::vector<int>> tl;
-        for (int l = c; l < c + 64; ++l)
-          if (!lanes[order[l]].empty()) tl.push_back(lanes[order[l]]);
-        if (!tl.empty()) emit_lane_task(B, tl, pairs, gidx, g0, W, r);
-      }
+      emit_layer_task(B, layers, llen, pairs, gidx, r * W, W, r);
     }
+    return cnt;
+  };
+  std::vector<long long> ltot(R, 0), scost(R, 0);
+  std::vector<int> lntask(R, 0), tcount(R, 0), nlay(R, 0);
+  for (int r = 0; r < R; ++r) {
+    std::vector<int>& sm = small[r];
+    if (sm.empty()) continue;
+    std::sort(sm.begin(), sm.end(), by_len_desc);
+    nlay[r] = cdiv((int)sm.size(), 64);
+    for (int c = 0; c < nlay[r]; ++c) ltot[r] += pairs[sm[64 * c]].len;
+    lntask[r] = (int)std::min<long long>(nlay[r], std::max<long long>(1, (ltot[r] + target - 1) / target));
+    tcount[r] += pack_small(r, lntask[r], false, &scost[r]);
   }
   // workgroups: each slice gets a share of about num_cu workgroups by cost;
   // its tasks go, heaviest first, to the least loaded wave of its workgroups
-  std::vector<long long> scost(R, 0);
   long long total = 0;
   for (size_t t = 0; t < B.tasks.size(); ++t) {
     scost[B.tslice[t]] += B.tcost[t];
-    total += B.tcost[t];
+    tcount[B.tslice[t]]++;
   }
+  for (int r = 0; r < R; ++r) total += scost[r];
   std::vector<int> nb(R, 0);
   {
     std::vector<std::pair<double, int>> frac;
@@ -589,6 +657,27 @@ rr_status build_sell(SellPlan& sp, const std::vector<int>& ptr, const std::vecto
     }
     std::sort(frac.begin(), frac.end(), [](auto& a, auto& b) { return a.first > b.first; });
     for (size_t k = 0; k < frac.size() && used < num_cu; ++k, ++used) nb[frac[k].second]++;
+  }
+  // the short pairs of every slice are re-stacked so that its task count is
+  // a whole multiple of its waves, if that changes their stacks' height by
+  // at most a fourth (fewer, taller stacks when the count is a little above
+  // a multiple; more, lower ones of at least 8 entries when the slice has
+  // idle waves): a wave with one task more than the others would set the
+  // pass's time
+  for (int r = 0; r < R; ++r) {
+    if (small[r].empty()) continue;
+    const int nbin = nb[r] * kSliceWaves;
+    int nt = lntask[r];
+    const int T = tcount[r];
+    if (T > nbin) {
+      const int excess = T - T / nbin * nbin;
+      if (4 * (nt - excess) >= 3 * nt && nt - excess >= 1) nt -= excess;
+    } else if (T < nbin) {
+      nt = (int)std::max<long long>(nt, std::min<long long>({(long long)nt + (nbin - T), ltot[r] / 8,
+                                                             (long long)nlay[r]}));
+    }
+    long long unused = 0;
+    pack_small(r, nt, true, &unused);
   }
   std::vector<std::vector<int>> stasks(R);
   for (size_t t = 0; t < B.tasks.size(); ++t) stasks[B.tslice[t]].push_back((int)t);
@@ -659,6 +748,13 @@ rr_status build_sell(SellPlan& sp, const std::vector<int>& ptr, const std::vecto
   RR_HIP(hipMalloc(&sp.bslice, sizeof(int) * std::max<size_t>(1, bslice.size())));
   RR_HIP(hipMalloc(&sp.pos, sizeof(int) * std::max<size_t>(1, B.pos.size())));
   RR_HIP(hipMalloc(&sp.sbase, sizeof(int) * sbase.size()));
+  std::vector<int> lseg;
+  for (int q = 0; q < S; ++q)
+    if (sbase[q + 1] - sbase[q] > kReduceBatch) lseg.push_back(q);
+  sp.nlong = (int)lseg.size();
+  RR_HIP(hipMalloc(&sp.lseg, sizeof(int) * std::max<size_t>(1, lseg.size())));
+  if (!lseg.empty())
+    RR_HIP(hipMemcpyAsync(sp.lseg, lseg.data(), sizeof(int) * lseg.size(), hipMemcpyHostToDevice, s));
   RR_HIP(hipMalloc(&sp.part, sizeof(double) * std::max(1, sp.nout)));
   RR_HIP(hipMemcpyAsync(sp.idx, B.idx.data(), sizeof(uint16_t) * B.idx.size(), hipMemcpyHostToDevice, s));
   if (!tasks_sorted.empty())
@@ -733,34 +829,50 @@ rr_status build_sell_plans(Sparse& X, hipStream_t s, int autotune, SellTuning* t
     }
     if (tuned) tuned->cached = hit ? 1 : 0;
     if (!hit) {
-      // time each candidate plan on a vector of ones and keep the fastest
+      // build every candidate plan, time them in interleaved rounds on a
+      // vector of ones (best round of each) and keep the fastest; a larger
+      // divisor must win by 3 % to replace a smaller one
       double *v = nullptr, *out = nullptr;
       const int nmax = std::max(X.N, X.F);
       RR_HIP(hipMalloc(&v, sizeof(double) * nmax));
       RR_HIP(hipMalloc(&out, sizeof(double) * nmax));
       launch_fill(v, 1.0, nmax, s);
-      const int cand[3] = {1, 2, 4};
-      float best_r = 1e30f, best_c = 1e30f;
+      constexpr int kCand = 3, kRounds = 5;
+      const int cand[kCand] = {1, 2, 4};
+      SellPlan plans[2][kCand];
+      float best[2][kCand];
       rr_status st = RR_OK;
-      for (int c : cand) {
-        if (st != RR_OK) break;
-        for (int pass = 0; pass < 2 && st == RR_OK; ++pass) {
-          SellPlan sp;
-          st = pass == 0 ? build_sell(sp, rp, ci, X.N, X.F, X.num_cu, s, c)
-                         : build_sell(sp, cp, ri, X.F, X.N, X.num_cu, s, c);
-          sp.pass = pass;
-          float ms = 0.f;
-          if (st == RR_OK) st = time_pass(sp, v, out, 10, s, &ms);
-          free_sell(sp);
-          if (st != RR_OK) break;
-          if (pass == 0 && ms < best_r) { best_r = ms; div_rows = c; }
-          if (pass == 1 && ms < best_c) { best_c = ms; div_cols = c; }
-          if (tuned && tuned->n < 6) {
-            tuned->cand_div[tuned->n] = c;
-            tuned->cand_pass[tuned->n] = pass;
-            tuned->cand_ms[tuned->n] = ms;
-            tuned->n++;
+      for (int pass = 0; pass < 2 && st == RR_OK; ++pass)
+        for (int c = 0; c < kCand && st == RR_OK; ++c) {
+          st = pass == 0 ? build_sell(plans[pass][c], rp, ci, X.N, X.F, X.num_cu, s, cand[c])
+                         : build_sell(plans[pass][c], cp, ri, X.F, X.N, X.num_cu, s, cand[c]);
+          plans[pass][c].pass = pass;
+          best[pass][c] = 1e30f;
+        }
+      for (int round = 0; round < kRounds && st == RR_OK; ++round)
+        for (int pass = 0; pass < 2 && st == RR_OK; ++pass)
+          for (int c = 0; c < kCand && st == RR_OK; ++c) {
+            float ms = 0.f;
+            st = time_pass(plans[pass][c], v, out, 4, s, &ms);
+            best[pass][c] = std::min(best[pass][c], ms);
           }
+      for (int pass = 0; pass < 2; ++pass)
+        for (int c = 0; c < kCand; ++c) free_sell(plans[pass][c]);
+      if (st == RR_OK) {
+        int pick[2] = {0, 0};
+        for (int pass = 0; pass < 2; ++pass)
+          for (int c = 1; c < kCand; ++c)
+            if (best[pass][c] < 0.97f * best[pass][pick[pass]]) pick[pass] = c;
+        div_rows = cand[pick[0]];
+        div_cols = cand[pick[1]];
+        if (tuned) {
+          for (int c = 0; c < kCand; ++c)
+            for (int pass = 0; pass < 2 && tuned->n < 6; ++pass) {
+              tuned->cand_div[tuned->n] = cand[c];
+              tuned->cand_pass[tuned->n] = pass;
+              tuned->cand_ms[tuned->n] = best[pass][c];
+              tuned->n++;
+            }
         }
       }
       (void)hipFree(v);
