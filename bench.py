@@ -168,33 +168,45 @@ def dense_section(rr, torch, dev, log):
             "forms": forms, "operator": gemm}
 
 
-def batched_uneven_section(rr, torch, dev, log, n_problems=100):
+def batched_uneven_section(rr, torch, dev, log, full=False):
     """Independent uneven problems in one rr_solve_batched call against one
     rr_solve call after another: the batched-uneven workload's generator
     (binary entries, density 1-5 %, Zipf columns, lambda log-uniform in
-    [1e-3, 10], k = ceil(d / 10) clamped to [8, 800], tolerance 1e-8) at
-    n in [500, 5000] and d in [200, 2000] so setup stays within seconds."""
+    [1e-3, 10], k = ceil(d / 10) clamped to [8, 800], tolerance 1e-8).  By
+    default 100 problems at n in [500, 5000] and d in [200, 2000], so setup
+    stays within seconds; with ``full`` the whole workload, 500 problems at
+    n in [500, 20000] and d in [200, 8000]."""
     import numpy as np
     import datagen
+    n_problems, n_range, d_range = (500, (500, 20_000), (200, 8_000)) if full else \
+        (100, (500, 5000), (200, 2000))
     t0 = time.perf_counter()
-    batch = datagen.batched_problems(n_problems, seed=5826 + 4000, n_range=(500, 5000),
-                                     d_range=(200, 2000))
+    batch = datagen.batched_problems(n_problems, seed=5826 + 4000, n_range=n_range, d_range=d_range,
+                                     workers=min(16, os.cpu_count() or 1) if full else 1)
     gen_s = time.perf_counter() - t0
+    nnz = int(sum(P.X.nnz for P, _ in batch))
+    if full:
+        log(f"[bench batched] generated {n_problems} problems, {nnz / 1e6:.1f} M nnz in {gen_s:.1f} s")
     t0 = time.perf_counter()
     Rs, rhs, ws, lams = [], [], [], []
-    for P, lam in batch:
+    for i, (P, lam) in enumerate(batch):
         k = int(min(800, max(8, -(-P.X.shape[1] // 10))))
         Rs.append(rr.Ridge(P.X, n_clusters=k, seed=9))
         rhs.append(torch.as_tensor(P.y, dtype=torch.float64, device=dev))
         ws.append(torch.empty(P.X.shape[1], dtype=torch.float64, device=dev))
         lams.append(lam)
+        if full and (i + 1) % 50 == 0:
+            log(f"[bench batched] set up {i + 1} problems ({time.perf_counter() - t0:.1f} s)")
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    nnz = int(sum(P.X.nnz for P, _ in batch))
-    # warm both paths once (per-lambda coarse factors are then cached)
-    for R, lam, b, w in zip(Rs, lams, rhs, ws):
-        rr.rr_solve(R.h, lam, b, w, tol=1e-8, precond="vcycle", max_iter=5000, raise_on=(1, 2, 6))
+    # warm the paths once (per-lambda coarse factors are then cached)
+    if not full:
+        for R, lam, b, w in zip(Rs, lams, rhs, ws):
+            rr.rr_solve(R.h, lam, b, w, tol=1e-8, precond="vcycle", max_iter=5000, raise_on=(1, 2, 6))
     rr.rr_solve_batched([R.h for R in Rs], lams, rhs, ws, tol=1e-8, precond="vcycle", max_iter=5000)
+    if full:
+        torch.cuda.synchronize()
+        log(f"[bench batched] warm-up done ({time.perf_counter() - t0:.1f} s)")
     torch.cuda.synchronize()
     ta = time.perf_counter()
     iters_seq = []
@@ -227,7 +239,7 @@ def batched_uneven_section(rr, torch, dev, log, n_problems=100):
         f"setup {setup_s:.1f} s): sequential {seq_ms:.1f} ms, batched {bat_ms:.1f} ms "
         f"({seq_ms / bat_ms:.2f}x), with graphs {graph_ms:.1f} ms ({seq_ms / graph_ms:.2f}x), "
         f"all converged {ok}, same iterations {same}")
-    return {"problems": n_problems, "nnz": nnz, "n_range": [500, 5000], "d_range": [200, 2000],
+    return {"problems": n_problems, "nnz": nnz, "n_range": list(n_range), "d_range": list(d_range),
             "tol": 1e-8, "setup_s": setup_s, "sequential_ms": seq_ms, "batched_ms": bat_ms,
             "speedup": seq_ms / bat_ms, "batched_graph_ms": graph_ms,
             "graph_speedup": seq_ms / graph_ms, "all_converged": ok, "same_iterations": same,
@@ -243,6 +255,9 @@ def main():
     ap.add_argument("--k", type=int, default=1000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a plain 256 MiB device copy (scale for memory counters)")
+    ap.add_argument("--batched-full", action="store_true",
+                    help="run only the batched uneven-problem section, at its full size (500 "
+                         "problems up to 20000 x 8000; minutes of setup)")
     ap.add_argument("--no-dense", action="store_true",
                     help="skip the dense many-rhs and batched uneven-problem sections")
     ap.add_argument("--dense-only", action="store_true",
@@ -267,6 +282,10 @@ def main():
 
     if args.dense_only:
         print(json.dumps({"dense_many_rhs": dense_section(rr, torch, dev, log)}), flush=True)
+        return
+    if args.batched_full:
+        print(json.dumps({"batched_uneven": batched_uneven_section(rr, torch, dev, log, full=True)}),
+              flush=True)
         return
     P = datagen.chembl_like()
     N, F = P.X.shape

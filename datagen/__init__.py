@@ -185,20 +185,38 @@ def lambdas_loguniform(n: int, lo: float, hi: float, seed: int) -> np.ndarray:
     return np.exp(rng.uniform(np.log(lo), np.log(hi), size=n))
 
 
+def _one_batched(args):
+    n, d, m, sub, exponent = args
+    P = sparse_problem(n, d, m, sub, exponent)
+    return P.X.indptr, P.X.indices, P.w_true, P.y
+
+
 def batched_problems(n_problems: int, seed: int, n_range=(500, 20_000),
                      d_range=(200, 8_000), density_range=(0.01, 0.05),
-                     lam_range=(1e-3, 10.0), exponent: float = 1.1):
+                     lam_range=(1e-3, 10.0), exponent: float = 1.1, workers: int = 1):
     """Independent sparse binary ridge problems of uneven size: n and d
     uniform in their ranges, density uniform, Zipf column popularity,
-    lambda log-uniform.  Returns a list of (SparseProblem, lambda)."""
+    lambda log-uniform.  Returns a list of (SparseProblem, lambda).  With
+    ``workers`` > 1 the problems are drawn by a process pool; every problem
+    has a seed of its own, so the result does not depend on ``workers``."""
     rng = _rng(seed)
-    out = []
+    params, lams = [], []
     for p in range(n_problems):
         n = int(rng.integers(n_range[0], n_range[1] + 1))
         d = int(rng.integers(d_range[0], d_range[1] + 1))
         rho = float(rng.uniform(*density_range))
         m = max(1, int(round(rho * d)))
-        lam = float(np.exp(rng.uniform(np.log(lam_range[0]), np.log(lam_range[1]))))
-        sub = seed * 1000 + p
-        out.append((sparse_problem(n, d, m, sub, exponent), lam))
+        lams.append(float(np.exp(rng.uniform(np.log(lam_range[0]), np.log(lam_range[1])))))
+        params.append((n, d, m, seed * 1000 + p, exponent))
+    if workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            parts = pool.map(_one_batched, params, chunksize=1)
+    else:
+        parts = [_one_batched(a) for a in params]
+    out = []
+    for (n, d, _, _, _), (indptr, indices, w, y), lam in zip(params, parts, lams):
+        X = sp.csr_matrix((np.ones(indices.size), indices, indptr), shape=(n, d))
+        X.has_sorted_indices = True
+        out.append((SparseProblem(X=X, w_true=w, y=y, binary=True), lam))
     return out
