@@ -82,7 +82,7 @@ void free_work(Work& w) {
   if (w.extra) {
     dfree(w.X.sell_csr.part); dfree(w.X.sell_csc.part);
     dfree(w.X.csc_plan.head); dfree(w.X.csc_plan.tail);
-    dfree(w.rplan.head); dfree(w.rplan.tail);
+    dfree(w.rplan.head); dfree(w.rplan.tail); dfree(w.rplan.cpart);
   }
   w.graph.reset();
   if (w.graph.ev) (void)hipEventDestroy(w.graph.ev);
@@ -137,6 +137,7 @@ rr_status get_work_set(rr_handle* h, int k, Work** out) {
     w->X.sell_csr.part = w->X.sell_csc.part = nullptr;
     w->X.csc_plan.head = w->X.csc_plan.tail = nullptr;
     w->rplan.head = w->rplan.tail = nullptr;
+    w->rplan.cpart = nullptr;
     RR_TRY(alloc_work(*w, h->X.F, h->X.N, h->FC, h->npartials));
     if (h->X.binary) {
       RR_TRY(dalloc(&w->X.sell_csr.part, h->X.sell_csr.nout));
@@ -149,6 +150,7 @@ rr_status get_work_set(rr_handle* h, int k, Work** out) {
       RR_TRY(dalloc(&w->rplan.head, h->restrict_plan.nblocks));
       RR_TRY(dalloc(&w->rplan.tail, h->restrict_plan.nblocks));
     }
+    if (h->restrict_plan.ncpart > 0) RR_TRY(dalloc(&w->rplan.cpart, h->restrict_plan.ncpart));
   }
   *out = h->extra_sets[k - 1];
   return RR_OK;

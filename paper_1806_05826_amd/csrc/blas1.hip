@@ -445,7 +445,9 @@ void launch_omega_gersh(int F, const double* g, const double* colnorm, double la
   k_omega_gersh<<<1, 1024, 0, s>>>(F, g, colnorm, lam, out);
 }
 
-// y = A x, A row-major n x n: one wave per row.
+// y = A x, A row-major n x n: one wave per row; lane l takes columns
+// l + 64 k, 16 loads of A and of x in flight at a time (a whole row when
+// n <= 1024, the coarse sizes of interest).
 __global__ __launch_bounds__(kBlock) void k_gemv(int n, const double* __restrict__ A,
                                                  const double* __restrict__ x,
                                                  double* __restrict__ y, const int* done) {
@@ -455,12 +457,17 @@ __global__ __launch_bounds__(kBlock) void k_gemv(int n, const double* __restrict
   if (row >= n) return;
   const double* a = A + (size_t)row * n;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  int c = lane;
-  for (; c + 192 < n; c += 256) {
+  for (int c0 = lane; c0 < n; c0 += 1024) {
+    double av[16], xv[16];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) acc[k] += a[c + 64 * k] * x[c + 64 * k];
+    for (int k = 0; k < 16; ++k) {
+      const int c = c0 + 64 * k;
+      av[k] = c < n ? a[c] : 0.0;
+      xv[k] = c < n ? x[c] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k & 3] += av[k] * xv[k];
   }
-  for (; c < n; c += 64) acc[0] += a[c] * x[c];
   double t = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
   if (lane == 0) y[row] = t;

@@ -651,7 +651,8 @@ rr_status set_labels(rr_handle* h, const int* labels_in, int nlab, hipStream_t s
   RR_HIP(hipFree(tmp));
   RR_HIP(hipFree(keys_out));
   RR_HIP(hipFree(iota));
-  return build_merge_plan(h->restrict_plan, h->coff + 1, h->coff, hfc, F, s);
+  RR_TRY(build_merge_plan(h->restrict_plan, h->coff + 1, h->coff, hfc, F, s));
+  return build_chunk_plan(h->restrict_plan, h->coff, hfc, s);
 }
 
 // K = diag(n)^-1/2 S^T S diag(n)^-1/2 with S = X P_u (binary X: exact

@@ -142,6 +142,14 @@ struct MergePlan {
   int4* span = nullptr;    // device [nspan]: (segment, first block, last block, 0)
   double* head = nullptr;  // device [nblocks]
   double* tail = nullptr;  // device [nblocks]
+  // optional chunked form for sums without a dot product (the restriction):
+  // chunks of at most kChunk entries, (segment, first, end, partial slot or
+  // -1 when the chunk is its segment's only one); segments of several chunks
+  // (segment, first slot, slots, 0); the chunk partials (per work set)
+  int nchunk = 0, nfin = 0, ncpart = 0;
+  int4* chunk = nullptr;
+  int4* fin = nullptr;
+  double* cpart = nullptr;
 };
 
 // Sliced-ELL plan of a segmented gather-sum out_s = sum_{e in s} v[g_e]
@@ -368,6 +376,7 @@ rr_status fail(rr_status st, const std::string& msg);
 inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
 
 // ---- sparse kernels (spmv.hip) ----------------------------------------------
+rr_status build_chunk_plan(MergePlan& mp, const int* d_seg_ptr, int nseg, hipStream_t s);
 rr_status build_merge_plan(MergePlan& mp, const int* d_seg_end, const int* d_seg_ptr,
                            int nseg, int nnz, hipStream_t s);
 void free_merge_plan(MergePlan& mp);

@@ -266,6 +266,70 @@ __global__ __launch_bounds__(kBlock) void k_segfix(const int4* __restrict__ span
   if constexpr (has_dot<MODE>()) store_block_partial<kBlock>(dot, e.partials, nmain + blockIdx.x);
 }
 
+// Chunked segmented sum for epilogues without a dot product: one wave per
+// chunk of at most kChunk entries (lane l adds entries l, l + 64, ... in
+// order, then a fixed butterfly); a segment's only chunk finishes it, the
+// chunks of longer segments leave partials that one wave per such segment
+// adds in chunk order (k_chunk_fin).
+constexpr int kChunk = 256;
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_chunk_sum(const int4* __restrict__ chunk, int nchunk,
+                                                      const int* __restrict__ idx,
+                                                      const double* __restrict__ v,
+                                                      double* __restrict__ cpart, Epi e,
+                                                      const int* done) {
+  if (is_done(done)) return;
+  const int wv = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (wv >= nchunk) return;
+  const int4 c = chunk[wv];
+  int j[kChunk / 64];
+#pragma unroll
+  for (int k = 0; k < kChunk / 64; ++k) j[k] = (c.y + lane + 64 * k < c.z) ? idx[c.y + lane + 64 * k] : -1;
+  double t = 0.0;
+#pragma unroll
+  for (int k = 0; k < kChunk / 64; ++k) t += (j[k] >= 0) ? v[j[k]] : 0.0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+  if (lane == 0) {
+    if (c.w < 0) {
+      double dot = 0.0;
+      seg_finish<MODE>(c.x, t, e, dot);
+    } else {
+      cpart[c.w] = t;
+    }
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_chunk_fin(const int4* __restrict__ fin, int nfin,
+                                                      const double* __restrict__ cpart, Epi e,
+                                                      const int* done) {
+  if (is_done(done)) return;
+  const int wv = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (wv >= nfin) return;
+  const int4 f = fin[wv];
+  double t = 0.0;
+  for (int k = lane; k < f.z; k += 64) t += cpart[f.y + k];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+  if (lane == 0) {
+    double dot = 0.0;
+    seg_finish<MODE>(f.x, t, e, dot);
+  }
+}
+
+template <int MODE>
+static void chunk_mode(const MergePlan& mp, const int* idx, const double* v, const Epi& e,
+                       const int* done, hipStream_t s) {
+  k_chunk_sum<MODE><<<cdiv(mp.nchunk, kBlock / 64), kBlock, 0, s>>>(mp.chunk, mp.nchunk, idx, v,
+                                                                    mp.cpart, e, done);
+  if (mp.nfin > 0)
+    k_chunk_fin<MODE><<<cdiv(mp.nfin, kBlock / 64), kBlock, 0, s>>>(mp.fin, mp.nfin, mp.cpart, e,
+                                                                    done);
+}
+
 // Collapse n block partials into partials[0] (one block, fixed order).
 __global__ __launch_bounds__(kBlock) void k_collapse(double* partials, int n, const int* done) {
   if (is_done(done)) return;
@@ -311,6 +375,15 @@ int launch_csc(const Sparse& X, const double* u, int mode, const Epi& e, const i
 int launch_segsum(const MergePlan& mp, const int* seg_end, const int* idx, const double* val,
                   const double* v, int mode, const Epi& e, const int* done, hipStream_t s) {
   if (mp.nblocks == 0) return 0;
+  if (mp.nchunk > 0 && !val) {
+    switch (mode) {
+      case EPI_STORE: chunk_mode<EPI_STORE>(mp, idx, v, e, done, s); return 0;
+      case EPI_APPLY: chunk_mode<EPI_APPLY>(mp, idx, v, e, done, s); return 0;
+      case EPI_RESID: chunk_mode<EPI_RESID>(mp, idx, v, e, done, s); return 0;
+      case EPI_SCALE: chunk_mode<EPI_SCALE>(mp, idx, v, e, done, s); return 0;
+      default: break;   // epilogues with a dot product take the merge path
+    }
+  }
   switch (mode) {
     case EPI_STORE: return segsum_mode<EPI_STORE>(mp, seg_end, idx, val, v, e, done, s);
     case EPI_APPLY: return segsum_mode<EPI_APPLY>(mp, seg_end, idx, val, v, e, done, s);
@@ -338,7 +411,44 @@ void free_merge_plan(MergePlan& mp) {
   if (mp.span) (void)hipFree(mp.span);
   if (mp.head) (void)hipFree(mp.head);
   if (mp.tail) (void)hipFree(mp.tail);
+  if (mp.chunk) (void)hipFree(mp.chunk);
+  if (mp.fin) (void)hipFree(mp.fin);
+  if (mp.cpart) (void)hipFree(mp.cpart);
   mp = MergePlan{};
+}
+
+// The chunked form of a plan whose segments are seg_ptr[0..nseg] (setup only).
+rr_status build_chunk_plan(MergePlan& mp, const int* d_seg_ptr, int nseg, hipStream_t s) {
+  std::vector<int> ptr(nseg + 1);
+  RR_HIP(hipMemcpyAsync(ptr.data(), d_seg_ptr, sizeof(int) * (nseg + 1), hipMemcpyDeviceToHost, s));
+  RR_HIP(hipStreamSynchronize(s));
+  std::vector<int4> chunk, fin;
+  int slots = 0;
+  for (int q = 0; q < nseg; ++q) {
+    const int a = ptr[q], z = ptr[q + 1];
+    if (z < a) return fail(RR_ERR_DEVICE, "internal: decreasing segment offsets");
+    const int nc = std::max(1, cdiv(z - a, kChunk));
+    if (nc == 1) {
+      chunk.push_back(make_int4(q, a, z, -1));
+      continue;
+    }
+    fin.push_back(make_int4(q, slots, nc, 0));
+    for (int c = 0; c < nc; ++c) chunk.push_back(make_int4(q, a + c * kChunk, std::min(z, a + (c + 1) * kChunk), slots++));
+  }
+  mp.nchunk = (int)chunk.size();
+  mp.nfin = (int)fin.size();
+  mp.ncpart = slots;
+  if (mp.nchunk) {
+    RR_HIP(hipMalloc(&mp.chunk, sizeof(int4) * mp.nchunk));
+    RR_HIP(hipMemcpyAsync(mp.chunk, chunk.data(), sizeof(int4) * mp.nchunk, hipMemcpyHostToDevice, s));
+  }
+  if (mp.nfin) {
+    RR_HIP(hipMalloc(&mp.fin, sizeof(int4) * mp.nfin));
+    RR_HIP(hipMemcpyAsync(mp.fin, fin.data(), sizeof(int4) * mp.nfin, hipMemcpyHostToDevice, s));
+    RR_HIP(hipMalloc(&mp.cpart, sizeof(double) * mp.ncpart));
+  }
+  RR_HIP(hipStreamSynchronize(s));
+  return RR_OK;
 }
 
 // seg_end = ptr + 1 (nseg entries), seg_ptr = ptr (nseg + 1 entries).
