@@ -97,6 +97,19 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(
     const double* __restrict__ q, double* __restrict__ z, double* __restrict__ e1,
     const double* __restrict__ D, const double* __restrict__ xref, double omega, int kind,
     Scalars* sc, const double* __restrict__ parts_pq, int n_pq, double* parts_upd) {
+  // this thread's first entry is loaded before the done flag and the
+  // partials, so that the three loads are in flight together
+  const int j0 = blockIdx.x * kBlock + threadIdx.x;
+  const bool need_d = kind == PK_JACOBI || kind == PK_VCYCLE || kind == PK_LEARNED;
+  double x0 = 0.0, p0 = 0.0, r0 = 0.0, q0 = 0.0, d0 = 1.0, xr0 = 0.0;
+  if (j0 < F) {
+    x0 = x[j0];
+    p0 = p[j0];
+    r0 = r[j0];
+    q0 = q[j0];
+    if (need_d) d0 = D[j0];
+    if (xref) xr0 = xref[j0];
+  }
   if (sc->done) return;
   __shared__ double red[kBlock / 64];
   const double pq = sum_parts<kBlock>(parts_pq, n_pq, red);
@@ -117,27 +130,30 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(
     sc->iter = sc->iter + 1;
   }
   double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-  for (int j = blockIdx.x * kBlock + threadIdx.x; j < F; j += gridDim.x * kBlock) {
-    const double xj = x[j] + alpha * p[j];
-    const double rj = r[j] - alpha * q[j];
+  auto entry = [&](int j, double xo, double pj, double ro, double qj, double dj, double xrj) {
+    const double xj = xo + alpha * pj;
+    const double rj = ro - alpha * qj;
     x[j] = xj;
     r[j] = rj;
     v0 += rj * rj;
     if (xref) {
-      const double d = xj - xref[j];
+      const double d = xj - xrj;
       v1 += d * d;
     }
     if (kind == PK_JACOBI) {
-      const double zj = rj / D[j];
+      const double zj = rj / dj;
       z[j] = zj;
       v2 += rj * zj;
     } else if (kind == PK_NONE) {
       z[j] = rj;
       v2 += rj * rj;
     } else if (kind == PK_VCYCLE || kind == PK_LEARNED) {
-      e1[j] = (omega * rj) / D[j];
+      e1[j] = (omega * rj) / dj;
     }
-  }
+  };
+  if (j0 < F) entry(j0, x0, p0, r0, q0, d0, xr0);
+  for (int j = j0 + gridDim.x * kBlock; j < F; j += gridDim.x * kBlock)
+    entry(j, x[j], p[j], r[j], q[j], need_d ? D[j] : 1.0, xref ? xref[j] : 0.0);
   store_parts3(v0, v1, v2, parts_upd, gridDim.x);
 }
 
@@ -156,6 +172,12 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(int F, double* __restrict__ 
                                                     const double* __restrict__ z, Scalars* sc,
                                                     const double* __restrict__ parts_rz,
                                                     int n_rz, int first, StageArgs stage) {
+  const int j0 = blockIdx.x * kBlock + threadIdx.x;
+  double z0 = 0.0, p0 = 0.0;   // loaded together with the done flag and the partials
+  if (j0 < F) {
+    z0 = z[j0];
+    p0 = p[j0];
+  }
   if (sc->done) return;
   __shared__ double red[kBlock / 64];
   double rz_new;
@@ -176,8 +198,8 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(int F, double* __restrict__ 
     sc->rz_next = rz_new;
     sc->beta = beta;
   }
-  for (int j = blockIdx.x * kBlock + threadIdx.x; j < F; j += gridDim.x * kBlock)
-    p[j] = z[j] + beta * p[j];
+  if (j0 < F) p[j0] = z0 + beta * p0;
+  for (int j = j0 + gridDim.x * kBlock; j < F; j += gridDim.x * kBlock) p[j] = z[j] + beta * p[j];
 }
 
 void launch_pupdate(int F, double* p, const double* z, Scalars* sc, const double* parts_rz,
@@ -222,20 +244,30 @@ __global__ __launch_bounds__(kBlock) void k_prolong(int F, const int* __restrict
                                                     const double* __restrict__ D, double omega,
                                                     int additive, const Scalars* sc,
                                                     double* parts_rz) {
+  // this thread's first label and operands are loaded before the done flag
+  const int j0 = blockIdx.x * kBlock + threadIdx.x;
+  int l0 = 0;
+  double a0 = 0.0, d0 = 1.0;
+  if (j0 < F) {
+    l0 = labels[j0];
+    a0 = additive ? r[j0] : e1[j0];
+    if (additive) d0 = D[j0];
+  }
   if (sc && sc->done) return;
   double v = 0.0;
-  for (int j = blockIdx.x * kBlock + threadIdx.x; j < F; j += gridDim.x * kBlock) {
-    const int s = labels[j];
+  auto entry = [&](int j, int s, double a, double dj) {
     const double corr = cscale[s] * yc[s];
     if (additive) {
-      const double rj = r[j];
-      const double zj = (omega * rj) / D[j] + corr;
+      const double zj = (omega * a) / dj + corr;
       out[j] = zj;
-      v += rj * zj;
+      v += a * zj;
     } else {
-      out[j] = e1[j] + corr;
+      out[j] = a + corr;
     }
-  }
+  };
+  if (j0 < F) entry(j0, l0, a0, d0);
+  for (int j = j0 + gridDim.x * kBlock; j < F; j += gridDim.x * kBlock)
+    entry(j, labels[j], additive ? r[j] : e1[j], additive ? D[j] : 1.0);
   if (parts_rz) store_block_partial<kBlock>(v, parts_rz, blockIdx.x);
 }
 

@@ -81,11 +81,6 @@ __device__ inline void sell_body(const int* __restrict__ wrange, const int* __re
                                  const T* __restrict__ v, int gdim, int W, T* __restrict__ out,
                                  const int* done, const StageArgs& stage) {
   if (is_done(done)) return;
-  if (stage.sc) {   // convergence check of the preceding x/r update
-    __shared__ double red_s[kSliceWaves];
-    double rz_unused;
-    if (stage_update<kSliceBlock>(stage, red_s, rz_unused)) return;
-  }
   __shared__ __align__(16) T vs[kSliceRows + 1];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -119,6 +114,14 @@ __device__ inline void sell_body(const int* __restrict__ wrange, const int* __re
     if (((t + 1 - t0) & 63) != 0) issue_task(t + 1);
   };
   issue_task(t0);
+  if (stage.sc) {   // convergence check of the preceding x/r update, under the slice copy
+    __shared__ double red_s[kSliceWaves];
+    double rz_unused;
+    if (stage_update<kSliceBlock>(stage, red_s, rz_unused)) {
+      __builtin_amdgcn_s_waitcnt(0);   // the slice copy lands before the workgroup ends
+      return;
+    }
+  }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   for (int t = t0; t < t1; ++t) {
