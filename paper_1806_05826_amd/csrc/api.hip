@@ -165,6 +165,7 @@ void destroy_handle(rr_handle* h) {
   free_sell(X.sell_csr);
   free_sell(X.sell_csc);
   free_merge_plan(h->restrict_plan);
+  free_cluster_rows(h->crow);
   dfree(h->colnorm); dfree(h->gersh); dfree(h->fperm); dfree(h->finv);
   dfree(h->labels); dfree(h->centres); dfree(h->csize); dfree(h->cscale);
   dfree(h->perm); dfree(h->coff); dfree(h->K);
@@ -284,6 +285,7 @@ rr_status setup_impl(const rr_csr* Xin, const rr_setup_opts* o, hipStream_t s, r
     RR_TRY(dalloc(&h->chol_work, 2 * (size_t)fc * fc));
     RR_TRY(dalloc(&h->chol_flag, 1));
     if (o && o->block_smoother) RR_TRY(build_smoother_blocks(h, s));
+    RR_TRY(build_cluster_rows(h, s));
     np = std::max(np, h->restrict_plan.nblocks + cdiv(h->restrict_plan.nspan, kBlock / 64) + 1);
   }
   np = std::max(np, std::max(3 * kMaxParts, kMaxReduceBlocks + 1));
@@ -643,8 +645,12 @@ rr_status precond_two_level(rr_handle* h, Work& w, Prof& pf, int tag, int kind, 
     launch_gemv(h->FC, sl.Ainv, w.c, w.yc, done, s);
   }
   launch_prolong(F, h->labels, h->cscale, w.yc, w.e1, w.e2, nullptr, nullptr, 0.0, 0, w.sc, nullptr, s);
-  // z = e2 + w D^-1 (r - A e2), <r,z> -> beta
-  RR_TRY(op_csr(h, w, pf, tag, w.e2, s));
+  // z = e2 + w D^-1 (r - A e2), <r,z> -> beta; X e2 = X e1 + X P yc, where
+  // u still holds X e1
+  if (h->crow.nlayer > 0)
+    launch_cluster_rows(h, w.yc, w.u, done, s);
+  else
+    RR_TRY(op_csr(h, w, pf, tag, w.e2, s));
   if (w.block) {   // rho2 = r - A e2, then z = e2 + w D_B^-1 rho2
     Epi eb = base_epi(w, lam);
     eb.p = w.e2;

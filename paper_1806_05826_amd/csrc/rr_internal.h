@@ -306,6 +306,16 @@ struct DenseWork {
 
 }  // namespace rr
 
+// X's rows with every column index replaced by its cluster label, for the
+// V(1,1) cycle's second row pass (see crows.hip); 0/1 X only.
+constexpr int kMaxCrClusters = 8191;   // F_C + 1 FP64 entries in 64 KB of LDS
+struct ClusterRows {
+  int nlayer = 0;
+  int2* layer = nullptr;      // [nlayer] (first entry, entries per lane)
+  uint16_t* ent = nullptr;    // labels, lane-interleaved in groups of 4
+  int* rowid = nullptr;       // [nlayer * 64] row of every lane, -1 for none
+};
+
 struct rr_handle {
   int device = 0;
   rr::Sparse X;
@@ -323,6 +333,7 @@ struct rr_handle {
   int* perm = nullptr;          // [F] features sorted by cluster (stable)
   int* coff = nullptr;          // [FC+1] cluster offsets into perm
   rr::MergePlan restrict_plan;  // segments = clusters over perm
+  ClusterRows crow;             // label table for the V(1,1) second row pass
   double* K = nullptr;          // [FC*FC] coarse Gram
   std::deque<rr::LambdaSlot> slots;
   unsigned long long stamp = 0;
@@ -377,6 +388,9 @@ inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
 
 // ---- sparse kernels (spmv.hip) ----------------------------------------------
 rr_status build_chunk_plan(MergePlan& mp, const int* d_seg_ptr, int nseg, hipStream_t s);
+rr_status build_cluster_rows(rr_handle* h, hipStream_t s);
+void free_cluster_rows(ClusterRows& cr);
+void launch_cluster_rows(const rr_handle* h, const double* yc, double* u, const int* done, hipStream_t s);
 rr_status build_merge_plan(MergePlan& mp, const int* d_seg_end, const int* d_seg_ptr,
                            int nseg, int nnz, hipStream_t s);
 void free_merge_plan(MergePlan& mp);
@@ -402,7 +416,7 @@ rr_status build_sell_plans(Sparse& X, hipStream_t s, int autotune, SellTuning* t
 void free_sell(SellPlan& sp);
 int launch_sell(const SellPlan& sp, const double* v, int mode, const Epi& e, const int* done,
                 hipStream_t s, const StageArgs* stage = nullptr, hipEvent_t mid = nullptr);
-int sell_reduce_grid(int S);
+int sell_reduce_grid(const SellPlan& sp);
 // Single-precision pass over v (float) with FP32 sums into `part` (float
 // [sp.nout], the caller's); returns the count of dot partials left.
 int launch_sell32(const SellPlan& sp, float* part, const float* v, int mode, const Epi32& e,

@@ -252,8 +252,8 @@ __global__ __launch_bounds__(kSliceBlock) void k_sell32(const int* __restrict__ 
 // segment s: t = sum of its partial sums, then the epilogue.  Segments of
 // up to kReduceBatch pieces take one thread, which loads the positions and
 // values of all pieces together and adds them in slice order; the longer
-// ones (listed in lseg) take a whole wave each, lane i adding pieces i,
-// i + 64, ... before a fixed butterfly.
+// ones (listed in lseg) take a whole wave each, on blocks of their own,
+// lane i adding pieces i, i + 64, ... before a fixed butterfly.
 constexpr int kReduceBatch = 16;
 
 template <typename T>
@@ -285,25 +285,34 @@ template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_sell_reduce(const double* __restrict__ part,
                                                        const int* __restrict__ pos,
                                                        const int* __restrict__ sbase, int S,
-                                                       const int* __restrict__ lseg, int nlong,
+                                                       const int* __restrict__ lseg, int nlong, int nlb,
                                                        Epi e, const int* done) {
   if (is_done(done)) return;
   double dot = 0.0;
-  const int gt = blockIdx.x * kBlock + threadIdx.x, nt = gridDim.x * kBlock;
-  for (int L = gt >> 6; L < nlong; L += nt >> 6) {
-    const int s = lseg[L];
-    const double t = long_seg_sum(part, pos, sbase[s], sbase[s + 1], threadIdx.x & 63);
-    if ((threadIdx.x & 63) == 0) seg_finish<MODE>(s, t, e, dot);
-  }
-  for (int s = gt; s < S; s += nt) {
-    const int a = sbase[s], z = sbase[s + 1];
-    if (z - a > kReduceBatch) continue;
-    seg_finish<MODE>(s, short_seg_sum(part, pos, a, z), e, dot);
+  const int nsb = gridDim.x - nlb;   // the last nlb blocks take the long segments
+  if ((int)blockIdx.x >= nsb) {
+    for (int L = ((blockIdx.x - nsb) * kBlock + threadIdx.x) >> 6; L < nlong; L += nlb * (kBlock / 64)) {
+      const int s = lseg[L];
+      const double t = long_seg_sum(part, pos, sbase[s], sbase[s + 1], threadIdx.x & 63);
+      if ((threadIdx.x & 63) == 0) seg_finish<MODE>(s, t, e, dot);
+    }
+  } else {
+    for (int s = blockIdx.x * kBlock + threadIdx.x; s < S; s += nsb * kBlock) {
+      const int a = sbase[s], z = sbase[s + 1];
+      if (z - a > kReduceBatch) continue;
+      seg_finish<MODE>(s, short_seg_sum(part, pos, a, z), e, dot);
+    }
   }
   if constexpr (has_dot<MODE>()) store_block_partial<kBlock>(dot, e.partials, blockIdx.x);
 }
 
-int sell_reduce_grid(int S) { return std::max(1, std::min(kMaxReduceBlocks, cdiv(S, kBlock))); }
+// Blocks of the segment reduction: up to 256 for the long segments, the
+// rest (at least one) for the others; at most kMaxReduceBlocks in all.
+static int sell_long_blocks(const SellPlan& sp) { return std::min(256, cdiv(sp.nlong, kBlock / 64)); }
+int sell_reduce_grid(const SellPlan& sp) {
+  const int nlb = sell_long_blocks(sp);
+  return std::max(1, std::min(kMaxReduceBlocks - nlb, cdiv(sp.S, kBlock))) + nlb;
+}
 
 // Single-precision segment reduction: FP32 sums and epilogue, FP64 dot
 // products (modes EPI_STORE, EPI_APPLY_DOT, EPI_RESID, EPI_POST; EPI_RESID
@@ -312,7 +321,7 @@ template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_sell_reduce32(const float* __restrict__ part,
                                                          const int* __restrict__ pos,
                                                          const int* __restrict__ sbase, int S,
-                                                         const int* __restrict__ lseg, int nlong,
+                                                         const int* __restrict__ lseg, int nlong, int nlb,
                                                          Epi32 e, const int* done) {
   if (is_done(done)) return;
   double dot = 0.0;
@@ -335,16 +344,19 @@ __global__ __launch_bounds__(kBlock) void k_sell_reduce32(const float* __restric
       dot += (double)rs * (double)zz;
     }
   };
-  const int gt = blockIdx.x * kBlock + threadIdx.x, nt = gridDim.x * kBlock;
-  for (int L = gt >> 6; L < nlong; L += nt >> 6) {
-    const int s = lseg[L];
-    const float t = long_seg_sum(part, pos, sbase[s], sbase[s + 1], threadIdx.x & 63);
-    if ((threadIdx.x & 63) == 0) finish(s, t);
-  }
-  for (int s = gt; s < S; s += nt) {
-    const int a = sbase[s], z = sbase[s + 1];
-    if (z - a > kReduceBatch) continue;
-    finish(s, short_seg_sum(part, pos, a, z));
+  const int nsb = gridDim.x - nlb;
+  if ((int)blockIdx.x >= nsb) {
+    for (int L = ((blockIdx.x - nsb) * kBlock + threadIdx.x) >> 6; L < nlong; L += nlb * (kBlock / 64)) {
+      const int s = lseg[L];
+      const float t = long_seg_sum(part, pos, sbase[s], sbase[s + 1], threadIdx.x & 63);
+      if ((threadIdx.x & 63) == 0) finish(s, t);
+    }
+  } else {
+    for (int s = blockIdx.x * kBlock + threadIdx.x; s < S; s += nsb * kBlock) {
+      const int a = sbase[s], z = sbase[s + 1];
+      if (z - a > kReduceBatch) continue;
+      finish(s, short_seg_sum(part, pos, a, z));
+    }
   }
   if constexpr (MODE == EPI_APPLY_DOT || MODE == EPI_POST)
     store_block_partial<kBlock>(dot, e.partials, blockIdx.x);
@@ -364,23 +376,23 @@ int launch_sell32(const SellPlan& sp, float* part, const float* v, int mode, con
   } else if (stage) {
     launch_stage_update(*stage, s);
   }
-  const int g = sell_reduce_grid(sp.S);
+  const int g = sell_reduce_grid(sp), nlb = sell_long_blocks(sp);
   switch (mode) {
     case EPI_STORE:
-      k_sell_reduce32<EPI_STORE><<<g, kBlock, 0, s>>>(part, sp.pos, sp.sbase, sp.S, sp.lseg, sp.nlong, e,
-                                                   done);
+      k_sell_reduce32<EPI_STORE><<<g, kBlock, 0, s>>>(part, sp.pos, sp.sbase, sp.S, sp.lseg, sp.nlong,
+                                                         nlb, e, done);
       return 0;
     case EPI_APPLY_DOT:
-      k_sell_reduce32<EPI_APPLY_DOT><<<g, kBlock, 0, s>>>(part, sp.pos, sp.sbase, sp.S, sp.lseg, sp.nlong, e,
-                                                       done);
+      k_sell_reduce32<EPI_APPLY_DOT><<<g, kBlock, 0, s>>>(part, sp.pos, sp.sbase, sp.S, sp.lseg, sp.nlong,
+                                                             nlb, e, done);
       break;
     case EPI_RESID:
-      k_sell_reduce32<EPI_RESID><<<g, kBlock, 0, s>>>(part, sp.pos, sp.sbase, sp.S, sp.lseg, sp.nlong, e,
-                                                   done);
+      k_sell_reduce32<EPI_RESID><<<g, kBlock, 0, s>>>(part, sp.pos, sp.sbase, sp.S, sp.lseg, sp.nlong,
+                                                         nlb, e, done);
       return 0;
     case EPI_POST:
-      k_sell_reduce32<EPI_POST><<<g, kBlock, 0, s>>>(part, sp.pos, sp.sbase, sp.S, sp.lseg, sp.nlong, e,
-                                                  done);
+      k_sell_reduce32<EPI_POST><<<g, kBlock, 0, s>>>(part, sp.pos, sp.sbase, sp.S, sp.lseg, sp.nlong,
+                                                        nlb, e, done);
       break;
     default:
       return 0;
@@ -390,8 +402,8 @@ int launch_sell32(const SellPlan& sp, float* part, const float* v, int mode, con
 
 template <int MODE>
 static void sell_reduce_mode(const SellPlan& sp, const Epi& e, const int* done, hipStream_t s) {
-  k_sell_reduce<MODE><<<sell_reduce_grid(sp.S), kBlock, 0, s>>>(sp.part, sp.pos, sp.sbase, sp.S,
-                                                                sp.lseg, sp.nlong, e, done);
+  k_sell_reduce<MODE><<<sell_reduce_grid(sp), kBlock, 0, s>>>(sp.part, sp.pos, sp.sbase, sp.S, sp.lseg,
+                                                              sp.nlong, sell_long_blocks(sp), e, done);
 }
 
 int launch_sell(const SellPlan& sp, const double* v, int mode, const Epi& e, const int* done,
@@ -419,7 +431,7 @@ int launch_sell(const SellPlan& sp, const double* v, int mode, const Epi& e, con
     case EPI_SCALE: sell_reduce_mode<EPI_SCALE>(sp, e, done, s); break;
   }
   if (mode != EPI_APPLY_DOT && mode != EPI_POST && mode != EPI_TRUE) return 0;
-  return collapse_parts(e.partials, sell_reduce_grid(sp.S), done, s);
+  return collapse_parts(e.partials, sell_reduce_grid(sp), done, s);
 }
 
 void launch_sell_gather(const SellPlan& sp, const double* v, hipStream_t s) {
