@@ -283,6 +283,36 @@ def test_labels_in_matches_oracle(rr):
     assert np.linalg.norm(host(w) - x_t) <= 1e-10 * np.linalg.norm(x_t)
 
 
+@pytest.mark.parametrize("kind", ["vcycle", "additive"])
+def test_large_clusters_precond_and_solve(rr, kind):
+    """Clusters of 700 and 300 features (several 256-member chunks of the
+    restriction sum) beside small ones: the preconditioner and a fixed-count
+    solve against the oracle.  The V(1,1) cycle's second row pass goes
+    through the label table (X e2 = X e1 + X P yc)."""
+    P = datagen.mid_sparse()
+    F = P.X.shape[1]
+    rng = np.random.default_rng(31)
+    perm = rng.permutation(F)
+    lab = np.empty(F, dtype=np.int64)
+    lab[perm[:700]] = 0
+    lab[perm[700:1000]] = 1
+    lab[perm[1000:]] = 2 + rng.integers(0, 198, F - 1000)
+    labc, fc = kmeans.compact(lab)
+    assert np.bincount(labc).max() == 700
+    R = rr.Ridge(P.X, labels=lab)
+    lam = 1.0
+    omega = op.omega_gershgorin(P.X, lam)
+    B, _ = precond.make(kind, P.X, lam, labc, fc, omega)
+    r = rng.standard_normal(F)
+    z = host(R.apply_precond(lam, r, kind))
+    zr = B(r)
+    kappa_c = np.linalg.cond(coarse.coarse_matrix(P.X, labc, fc, lam))
+    assert np.linalg.norm(z - zr) <= 32 * kappa_c * 2**-52 * np.linalg.norm(zr)
+    x_t, inf = krylov.solve(P.X, P.y, lam, kind, labc, fc, tol=1e-12)
+    w, info = R.solve(lam, P.y, precond=kind, fixed_iters=inf.iters)
+    assert np.linalg.norm(host(w) - x_t) <= 1e-10 * np.linalg.norm(x_t)
+
+
 def test_singleton_clusters_one_iteration(rr):
     P = datagen.tiny_sparse()
     F = P.X.shape[1]
