@@ -108,12 +108,13 @@ def dense_section(rr, torch, dev, log):
     X = datagen.block_correlated_dense(N, 64, 64, 0.9, seed=5826 + 3000)
     _, Y = datagen.targets(X, 5826 + 3000, n_rhs=m)
     gen_s = time.perf_counter() - t0
-    R = rr.DenseRidge(X, n_clusters=k, seed=5826)
+    R = rr.DenseRidge(X, n_clusters=k, seed=5826, autotune=True)
     del X
     sinfo = R.info
     log(f"[bench dense] data {N}x{F}, {m} rhs (generated in {gen_s:.1f} s); setup "
         f"{sinfo['setup_ms']:.0f} ms (k-means {sinfo['kmeans_ms']:.0f} ms, "
-        f"{sinfo['kmeans_iters']} passes), F_C={sinfo['n_coarse']}")
+        f"{sinfo['kmeans_iters']} passes), F_C={sinfo['n_coarse']}, tuned split targets "
+        f"(f64, bf16, f32) {sinfo['dense_split']}")
     Yd = torch.as_tensor(np.ascontiguousarray(Y.T), dtype=torch.float64, device=dev)
     del Y
     Wref, inf_ref = R.solve_block(lam, Yd, precond="vcycle", tol=1e-13, max_iter=3000)
@@ -165,6 +166,7 @@ def dense_section(rr, torch, dev, log):
                         f"lambda={lam}, k-means k={k}",
             "setup_ms": sinfo["setup_ms"], "kmeans_ms": sinfo["kmeans_ms"],
             "n_coarse": sinfo["n_coarse"], "ref_iters": max(i["iters"] for i in inf_ref),
+            "split_targets_f64_bf16_f32": sinfo["dense_split"],
             "forms": forms, "operator": gemm}
 
 

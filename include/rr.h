@@ -117,7 +117,12 @@ typedef struct {
   int32_t autotune;        /* 0/1 X: 1 chooses each sliced pass's lane-stream
                               length among three candidates by timing them on
                               this device, cached per device and shape bucket
-                              (log2 of N, F, nnz) for the life of the process  */
+                              (log2 of N, F, nnz) for the life of the process;
+                              dense X: 1 chooses the split of the column pass's
+                              contraction (the workgroups it aims at, one of
+                              128..2048) per operator precision, timed on a
+                              256-column block, cached per device and shape
+                              bucket (log2 of the padded N, F)                 */
   int32_t block_smoother;  /* sparse X with a coarse level: 1 also builds the
                               cluster-aligned smoother blocks (each cluster's
                               features in increasing index, cut into groups of
@@ -159,6 +164,10 @@ typedef struct {
   int32_t tune_cached;     /* 1: autotune reused an earlier measurement        */
   int32_t dense;           /* 1 for a handle made by rr_setup_dense (nnz =
                               n_rows * n_cols)                                 */
+  int32_t dense_split[3];  /* dense X: workgroups the column pass's split
+                              contraction aims at, for the FP64, BF16 and FP32
+                              operators (tuned when autotune = 1)              */
+  int32_t dense_split_cached; /* 1: those came from an earlier measurement     */
 } rr_setup_info;
 
 /* Host-side facts about a handle. */
@@ -350,7 +359,7 @@ rr_status rr_smoother_weight(rr_handle* h, double lambda, double* omega);
  * the Gershgorin sums X^T X 1 (FP64); then the aggregation (labels_in, or
  * k-means++ over the columns in FP64 on the matrix cores when n_clusters > 0)
  * and K = P^T X^T X P (FP64 matrix cores).  The options of rr_setup apply
- * (autotune is ignored).  Errors: RR_ERR_INVALID_ARG for bad sizes, a
+ * (autotune tunes the column pass's split contraction).  Errors: RR_ERR_INVALID_ARG for bad sizes, a
  * non-finite entry or bad options; RR_ERR_DEVICE on HIP failure.  The handle
  * takes rr_solve_block, rr_apply_operator_block, rr_get_setup_info,
  * rr_get_labels, rr_get_centres, rr_coarse_gram, rr_coarse_factor,

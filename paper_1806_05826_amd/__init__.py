@@ -57,7 +57,8 @@ class rr_setup_info(C.Structure):
                 ("n_coarse", C.c_int32), ("n_centres", C.c_int32), ("kmeans_iters", C.c_int32),
                 ("binary", C.c_int32), ("setup_ms", C.c_double), ("kmeans_ms", C.c_double),
                 ("plan_ms", C.c_double), ("tuned_rows_div", C.c_int32),
-                ("tuned_cols_div", C.c_int32), ("tune_cached", C.c_int32), ("dense", C.c_int32)]
+                ("tuned_cols_div", C.c_int32), ("tune_cached", C.c_int32), ("dense", C.c_int32),
+                ("dense_split", C.c_int32 * 3), ("dense_split_cached", C.c_int32)]
 
 
 class rr_solve_opts(C.Structure):
@@ -188,7 +189,7 @@ def _rows_f64(t, name):
 
 
 def rr_setup_dense(X, n_clusters=0, seed=0, kmeans_max_iter=0, labels_in=None, n_labels_in=0,
-                   lambda_slots=0, stream=None):
+                   lambda_slots=0, autotune=False, stream=None):
     """X: (N, F) float32 CUDA tensor with unit column stride (row-major).
     Returns an opaque handle (int)."""
     import torch
@@ -198,7 +199,7 @@ def rr_setup_dense(X, n_clusters=0, seed=0, kmeans_max_iter=0, labels_in=None, n
         raise ValueError("labels_in: need an int32 CUDA tensor")
     D = rr_dense(X.shape[0], X.shape[1], X.stride(0), _ptr(X))
     o = rr_setup_opts(int(n_clusters), int(kmeans_max_iter), int(seed) & (2**64 - 1),
-                      _ptr(labels_in), int(n_labels_in), int(lambda_slots), 0)
+                      _ptr(labels_in), int(n_labels_in), int(lambda_slots), 1 if autotune else 0)
     h = C.c_void_p()
     _check(_lib.rr_setup_dense(C.byref(D), C.byref(o), _stream(stream), C.byref(h)))
     return h.value
@@ -247,7 +248,11 @@ def rr_destroy(h):
 def rr_get_setup_info(h) -> dict:
     i = rr_setup_info()
     _check(_lib.rr_get_setup_info(C.c_void_p(h), C.byref(i)))
-    return {f: getattr(i, f) for f, _ in rr_setup_info._fields_}
+    out = {}
+    for f, _ in rr_setup_info._fields_:
+        v = getattr(i, f)
+        out[f] = list(v) if isinstance(v, C.Array) else v
+    return out
 
 
 def rr_get_labels(h, labels, stream=None):
@@ -527,7 +532,7 @@ class DenseRidge(Ridge):
     float32 and handed to rr_setup_dense."""
 
     def __init__(self, X, n_clusters=0, seed=0, kmeans_max_iter=0, labels=None, lambda_slots=0,
-                 device="cuda"):
+                 autotune=False, device="cuda"):
         import numpy as np
         import torch
         self.device = torch.device(device)
@@ -538,7 +543,7 @@ class DenseRidge(Ridge):
         if labels is not None:
             lab = torch.as_tensor(np.asarray(labels, dtype=np.int32), device=self.device)
             nlab = int(np.max(labels)) + 1 if len(labels) else 1
-        self.h = rr_setup_dense(Xt, n_clusters, seed, kmeans_max_iter, lab, nlab, lambda_slots)
+        self.h = rr_setup_dense(Xt, n_clusters, seed, kmeans_max_iter, lab, nlab, lambda_slots, autotune)
         torch.cuda.current_stream().synchronize()
         del Xt
         self.info = rr_get_setup_info(self.h)

@@ -1517,7 +1517,11 @@ rr_status rr_get_setup_info(const rr_handle* h, rr_setup_info* info) {
   i.tuned_cols_div = h->tuning.div_cols;
   i.tune_cached = h->tuning.cached;
   i.dense = h->dense ? 1 : 0;
-  if (h->dense) i.nnz = (int64_t)h->X.N * h->X.F;
+  if (h->dense) {
+    i.nnz = (int64_t)h->X.N * h->X.F;
+    for (int k = 0; k < 3; ++k) i.dense_split[k] = h->dense->split_target[k];
+    i.dense_split_cached = h->dense->split_cached;
+  }
   *info = i;
   return RR_OK;
 }

@@ -13,10 +13,14 @@
 // dimension a GEMM touches is a multiple of its tile, so the GEMMs have no
 // bounds checks; the host checks that before each launch.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "rr_device.h"
@@ -733,7 +737,6 @@ __global__ void k_iota(int* p, int n) {
 constexpr int kMaxBlockRhs = 4096;
 // operator precision of a block application
 enum OpPrec { OP_F64 = 0, OP_BF16 = 1, OP_F32 = 2 };
-constexpr int kBf16Target = 256;   // BF16 split contraction: about one workgroup per CU
 
 // number of contraction splits: about `target` workgroups, at least 8 k-steps each
 void pick_split(int tiles, int K, int bk, int* S, int* kchunk, int target = 1024) {
@@ -770,11 +773,12 @@ rr_status ensure_dwork(rr_handle* h, int m) {
   // split partials of the column pass (Fp x m_cap per split); the split
   // count is largest when a solve has a single column tile
   int S = 0, kc = 0;
-  pick_split(d.Fp / GD_M, d.Np, GD_K, &S, &kc);
+  pick_split(d.Fp / GD_M, d.Np, GD_K, &S, &kc, d.split_target[OP_F64]);
   size_t pb = (size_t)S * fp * sizeof(double);
-  int Sb = 0;
-  pick_split(d.Fp / GB_M, d.Np, GB_K, &Sb, &kc, kBf16Target);
-  pb = std::max(pb, (size_t)Sb * fp * sizeof(float));
+  pick_split(d.Fp / GD_M, d.Np, GD_K, &S, &kc, d.split_target[OP_F32]);
+  pb = std::max(pb, (size_t)S * fp * sizeof(float));
+  pick_split(d.Fp / GB_M, d.Np, GB_K, &S, &kc, d.split_target[OP_BF16]);
+  pb = std::max(pb, (size_t)S * fp * sizeof(float));
   W.part_bytes = pb;
   RR_HIP(hipMalloc(&W.part, pb));
   const int fc = std::max(h->FC, 1);
@@ -857,14 +861,14 @@ rr_status pass_cols(rr_handle* h, int m, int op, int mode, const DEpi& e, double
     float* P32 = (float*)W.part;
     if (op == OP_BF16) {
       const int nt = cdiv(m, GB_N);
-      pick_split((d.Fp / GB_M) * nt, d.Np, GB_K, &S, &kc, kBf16Target);
+      pick_split((d.Fp / GB_M) * nt, d.Np, GB_K, &S, &kc, d.split_target[OP_BF16]);
       if (d.Fp % GB_M || d.Np % GB_K || kc % GB_K || (size_t)S * sstride * sizeof(float) > W.part_bytes)
         return fail(RR_ERR_DEVICE, "internal: GEMM shape");
       dim3 g(nt, d.Fp / GB_M, S);
       k_gemm_bf16<GOUT_F32><<<g, GB_THREADS, 0, s>>>(d.XTb, d.Np, W.ub, d.Np, W.part, d.Fp, sstride, kc, d.Np);
     } else {
       const int nt = cdiv(m, GD_N);
-      pick_split((d.Fp / GD_M) * nt, d.Np, GD_K, &S, &kc);
+      pick_split((d.Fp / GD_M) * nt, d.Np, GD_K, &S, &kc, d.split_target[OP_F32]);
       if (d.Fp % GD_M || d.Np % GD_K || kc % GD_K || (size_t)S * sstride * sizeof(float) > W.part_bytes)
         return fail(RR_ERR_DEVICE, "internal: GEMM shape");
       dim3 g(nt, d.Fp / GD_M, S);
@@ -881,7 +885,7 @@ rr_status pass_cols(rr_handle* h, int m, int op, int mode, const DEpi& e, double
     }
   } else {
     const int nt = cdiv(m, GD_N);
-    pick_split((d.Fp / GD_M) * nt, d.Np, GD_K, &S, &kc);
+    pick_split((d.Fp / GD_M) * nt, d.Np, GD_K, &S, &kc, d.split_target[OP_F64]);
     if (d.Fp % GD_M || d.Np % GD_K || kc % GD_K || (size_t)S * sstride * sizeof(double) > W.part_bytes)
       return fail(RR_ERR_DEVICE, "internal: GEMM shape");
     dim3 g(nt, d.Fp / GD_M, S);
@@ -1011,6 +1015,89 @@ void copy_block(double* dst, long long ldd, const double* src, long long lds, in
 
 // ---- setup --------------------------------------------------------------------------------
 
+namespace {
+std::mutex g_dtune_mu;
+std::map<std::string, std::array<int, 3>> g_dtune_cache;
+}
+
+// The column pass's split target per operator precision: every candidate
+// timed on a block of 256 zero columns (the work does not depend on the
+// values), in interleaved rounds, best round each; a candidate must win by
+// 3 % to replace the default.  Cached per device and shape bucket.
+static rr_status dense_autotune(rr_handle* h, hipStream_t s) {
+  DenseX& d = *h->dense;
+  int dev = 0;
+  RR_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  RR_HIP(hipGetDeviceProperties(&prop, dev));
+  auto lg = [](long long v) { int b = 0; while ((1LL << b) < v) ++b; return b; };
+  const std::string key = std::string(prop.gcnArchName) + ":" + std::to_string(lg(d.Np)) + ":" +
+                          std::to_string(lg(d.Fp));
+  {
+    std::lock_guard<std::mutex> lk(g_dtune_mu);
+    auto it = g_dtune_cache.find(key);
+    if (it != g_dtune_cache.end()) {
+      for (int k = 0; k < 3; ++k) d.split_target[k] = it->second[k];
+      d.split_cached = 1;
+      return RR_OK;
+    }
+  }
+  constexpr int kCand = 5, kRounds = 3, kReps = 3, kM = 256;
+  const int cand[kCand] = {128, 256, 512, 1024, 2048};
+  const int defaults[3] = {d.split_target[0], d.split_target[1], d.split_target[2]};
+  for (int k = 0; k < 3; ++k) d.split_target[k] = cand[kCand - 1];
+  dense_free_work(*h->dwork);
+  RR_TRY(ensure_dwork(h, kM));   // partial buffers for the largest split
+  DenseWork& W = *h->dwork;
+  hipEvent_t a, b;
+  RR_HIP(hipEventCreate(&a));
+  RR_HIP(hipEventCreate(&b));
+  float best[3][kCand];
+  for (int k = 0; k < 3; ++k)
+    for (int c = 0; c < kCand; ++c) best[k][c] = 1e30f;
+  rr_status st = RR_OK;
+  for (int round = 0; round < kRounds && st == RR_OK; ++round)
+    for (int op = 0; op < 3 && st == RR_OK; ++op)
+      for (int c = 0; c < kCand && st == RR_OK; ++c) {
+        d.split_target[op] = cand[c];
+        DEpi e = epi(d, W.q, nullptr, nullptr, 0.0);
+        st = pass_rows(h, kM, op, W.p, W.vb, s);
+        if (st == RR_OK) st = pass_cols(h, kM, op, EPI_STORE, e, nullptr, s);
+        if (st != RR_OK) break;
+        if (hipEventRecord(a, s) != hipSuccess) { st = fail(RR_ERR_DEVICE, "autotune event"); break; }
+        for (int r = 0; r < kReps && st == RR_OK; ++r) {
+          st = pass_rows(h, kM, op, W.p, W.vb, s);
+          if (st == RR_OK) st = pass_cols(h, kM, op, EPI_STORE, e, nullptr, s);
+        }
+        if (st != RR_OK) break;
+        float ms = 0.f;
+        if (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+            hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+          st = fail(RR_ERR_DEVICE, "autotune timing");
+          break;
+        }
+        best[op][c] = std::min(best[op][c], ms / kReps);
+      }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  RR_TRY(st);
+  std::array<int, 3> pick{};
+  for (int op = 0; op < 3; ++op) {
+    int bc = 0;
+    for (int c = 0; c < kCand; ++c)
+      if (cand[c] == defaults[op]) bc = c;
+    for (int c = 0; c < kCand; ++c)
+      if (best[op][c] < 0.97f * best[op][bc]) bc = c;
+    pick[op] = cand[bc];
+    d.split_target[op] = cand[bc];
+  }
+  dense_free_work(*h->dwork);
+  RR_TRY(ensure_dwork(h, 1));
+  std::lock_guard<std::mutex> lk(g_dtune_mu);
+  g_dtune_cache[key] = pick;
+  return RR_OK;
+}
+
 rr_status dense_setup(rr_handle* h, const rr_dense* Xin, const rr_setup_opts* o, hipStream_t s) {
   if (!Xin || !Xin->values) return fail(RR_ERR_INVALID_ARG, "null dense matrix");
   if (Xin->n_rows < 1 || Xin->n_cols < 1 || Xin->ld < Xin->n_cols)
@@ -1096,6 +1183,7 @@ rr_status dense_setup(rr_handle* h, const rr_dense* Xin, const rr_setup_opts* o,
     dense_free_work(*h->dwork);
     RR_TRY(ensure_dwork(h, 1));
   }
+  if (o && o->autotune) RR_TRY(dense_autotune(h, s));
   RR_HIP(hipStreamSynchronize(s));
   RR_HIP(hipGetLastError());
   return RR_OK;

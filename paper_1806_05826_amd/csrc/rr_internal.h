@@ -277,6 +277,10 @@ struct DenseX {
   uint16_t* Xb = nullptr;     // BF16 of X32
   uint16_t* XTb = nullptr;    // BF16 of XT32
   double* Xc = nullptr;       // [FC x Np] coarse columns X P (row s = column s of X P)
+  // workgroups the column pass's split contraction aims at, per operator
+  // precision (FP64, BF16, FP32); chosen by timing when the setup asks
+  int split_target[3] = {1024, 256, 1024};
+  int split_cached = 0;       // 1: the targets came from an earlier measurement
 };
 
 // Buffers of a block solve with up to m_cap right-hand sides.  F-blocks are

@@ -67,6 +67,33 @@ def test_operator_f64_and_bf16(rr, small):
     R.close()
 
 
+def test_dense_autotune(rr, small):
+    """The tuned split of the column pass's contraction: one of the
+    candidates per operator precision, reused from the cache by a second
+    handle of the same shape bucket, and the operator still within the same
+    bounds as with the default split."""
+    X = small.astype(np.float64)
+    R0 = rr.DenseRidge(small)
+    assert R0.info["dense_split"] == [1024, 256, 1024]
+    R = rr.DenseRidge(small, autotune=True)
+    split = R.info["dense_split"]
+    assert all(t in (128, 256, 512, 1024, 2048) for t in split), split
+    R2 = rr.DenseRidge(small, autotune=True)
+    assert R2.info["dense_split_cached"] == 1 and R2.info["dense_split"] == split
+    print(f"[dense autotune] split targets {split}", flush=True)
+    V = np.random.default_rng(9).standard_normal((37, X.shape[1]))
+    Q = host(R.apply_operator_block(0.7, V))
+    for c in range(V.shape[0]):
+        want = op.apply_A(X, 0.7, V[c])
+        bound = 4 * (X.shape[0] + X.shape[1]) * 2.0**-53 * (np.abs(X).T @ (np.abs(X) @ np.abs(V[c])) + 0.7 * np.abs(V[c]))
+        assert np.all(np.abs(Q[c] - want) <= bound), c
+    Qb = host(R.apply_operator_block(0.7, V, precision="bf16_ir"))
+    want_b = op.apply_A_bf16(X, 0.7, V.T).T
+    assert np.all(np.abs(Qb - want_b) <= op.apply_A_bf16_bound(X, V.T).T + 1e-12 * np.abs(want_b))
+    for h in (R0, R, R2):
+        h.close()
+
+
 def test_operator_lambda_zero_and_zero_block(rr, small):
     R = rr.DenseRidge(small)
     V = np.zeros((3, small.shape[1]))
