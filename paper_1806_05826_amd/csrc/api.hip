@@ -1122,7 +1122,10 @@ rr_status precond32(rr_handle* h, Work& w, double lam, double omega, const Lambd
   launch_segsum(w.rplan, h->coff + 1, h->perm, nullptr, w.rho, EPI_SCALE, ec, done, s);
   launch_gemv(h->FC, sl.Ainv, w.c, w.yc, done, s);
   launch_prolong32(F, h->labels, h->cscale, w.yc, f.e1, f.e2, done, s);
-  launch_sell32(w.X.sell_csr, f.part_rows, f.e2, EPI_STORE, e, done, s);
+  if (h->crow.nlayer > 0)   // X e2 = X e1 + X P yc, u still holding X e1
+    launch_cluster_rows32(h, w.yc, f.u, done, s);
+  else
+    launch_sell32(w.X.sell_csr, f.part_rows, f.e2, EPI_STORE, e, done, s);
   Epi32 ep{};
   ep.lam = lam;
   ep.omega = omega;

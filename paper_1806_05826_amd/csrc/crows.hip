@@ -23,29 +23,33 @@ constexpr int kCrThreads = 256;
 constexpr int kCrUnroll = 16;   // 8-byte label loads in flight per lane (64 entries)
 
 // One wave per layer: its descriptor, row ids, u1 and first 16 label loads
-// are issued before the workgroup fills the LDS vector.
+// are issued before the workgroup fills the LDS vector.  T is the type of u
+// and of the sums (FP64, or FP32 for the single-precision inner solves,
+// whose prolongation rounds s_l yc_l to FP32 the same way).
+template <typename T>
 __global__ __launch_bounds__(kCrThreads) void k_cluster_rows(int nlayer, const int2* __restrict__ layer,
                                                              const uint16_t* __restrict__ ent,
                                                              const int* __restrict__ rowid, int FC,
                                                              const double* __restrict__ cscale,
                                                              const double* __restrict__ yc,
-                                                             double* __restrict__ u, const int* done) {
-  extern __shared__ double yt[];   // [FC + 1]
+                                                             T* __restrict__ u, const int* done) {
+  extern __shared__ __align__(8) unsigned char yt_raw[];
+  T* yt = reinterpret_cast<T*>(yt_raw);   // [FC + 1]
   if (is_done(done)) return;
   const int lane = threadIdx.x & 63;
   const int L = blockIdx.x * (kCrThreads / 64) + (threadIdx.x >> 6);
   const bool active = L < nlayer;
   const int2 d = active ? layer[L] : make_int2(0, 0);   // (first entry, entries per lane)
   const int row = active ? rowid[(size_t)L * 64 + lane] : -1;
-  const double u0 = row >= 0 ? u[row] : 0.0;
+  const T u0 = row >= 0 ? u[row] : T(0);
   const uint2* p = reinterpret_cast<const uint2*>(ent + d.x) + lane;
   const int ng = d.y / 4;
   uint2 q[kCrUnroll];
 #pragma unroll
   for (int j = 0; j < kCrUnroll; ++j) q[j] = (j < ng) ? p[(size_t)j * 64] : make_uint2(0u, 0u);
-  for (int c = threadIdx.x; c <= FC; c += kCrThreads) yt[c] = c < FC ? cscale[c] * yc[c] : 0.0;
+  for (int c = threadIdx.x; c <= FC; c += kCrThreads) yt[c] = c < FC ? (T)(cscale[c] * yc[c]) : T(0);
   __syncthreads();
-  double acc = 0.0;
+  T acc = T(0);
   for (int g = 0; g < ng; g += kCrUnroll) {
     if (g > 0) {
 #pragma unroll
@@ -129,8 +133,15 @@ rr_status build_cluster_rows(rr_handle* h, hipStream_t s) {
 void launch_cluster_rows(const rr_handle* h, const double* yc, double* u, const int* done, hipStream_t s) {
   const ClusterRows& cr = h->crow;
   const int g = cdiv(cr.nlayer, kCrThreads / 64);
-  k_cluster_rows<<<g, kCrThreads, sizeof(double) * (h->FC + 1), s>>>(cr.nlayer, cr.layer, cr.ent, cr.rowid,
-                                                                     h->FC, h->cscale, yc, u, done);
+  k_cluster_rows<double><<<g, kCrThreads, sizeof(double) * (h->FC + 1), s>>>(
+      cr.nlayer, cr.layer, cr.ent, cr.rowid, h->FC, h->cscale, yc, u, done);
+}
+
+void launch_cluster_rows32(const rr_handle* h, const double* yc, float* u, const int* done, hipStream_t s) {
+  const ClusterRows& cr = h->crow;
+  const int g = cdiv(cr.nlayer, kCrThreads / 64);
+  k_cluster_rows<float><<<g, kCrThreads, sizeof(float) * (h->FC + 1), s>>>(
+      cr.nlayer, cr.layer, cr.ent, cr.rowid, h->FC, h->cscale, yc, u, done);
 }
 
 }  // namespace rr

@@ -395,6 +395,7 @@ rr_status build_chunk_plan(MergePlan& mp, const int* d_seg_ptr, int nseg, hipStr
 rr_status build_cluster_rows(rr_handle* h, hipStream_t s);
 void free_cluster_rows(ClusterRows& cr);
 void launch_cluster_rows(const rr_handle* h, const double* yc, double* u, const int* done, hipStream_t s);
+void launch_cluster_rows32(const rr_handle* h, const double* yc, float* u, const int* done, hipStream_t s);
 rr_status build_merge_plan(MergePlan& mp, const int* d_seg_end, const int* d_seg_ptr,
                            int nseg, int nnz, hipStream_t s);
 void free_merge_plan(MergePlan& mp);
