@@ -1,7 +1,8 @@
 // u2 = u1 + S (s o yc) for the second operator application of the V(1,1)
-// cycle (0/1 X).  The cycle applies A to e1 and then to e2 = e1 + P yc, with
-// (P yc)_j = s_l(j) yc_l(j) (the adjusted square-root-average prolongation,
-// s_c = 1/sqrt(n_c)).  Since X e2 = X e1 + X P yc and X P yc gathers, for
+// cycle of the two-level-iteration subsection (0/1 X).  The cycle applies A
+// to e1 and then to e2 = e1 + P yc, with (P yc)_j = s_l(j) yc_l(j) (the
+// adjusted square-root-average prolongation of the data-matrices
+// subsection, s_c = 1/sqrt(n_c)).  Since X e2 = X e1 + X P yc and X P yc gathers, for
 // every row, s_l yc_l over the labels l of its entries, the row pass of e2
 // reduces to u1 = X e1 (already formed) plus a gather from an F_C-entry
 // vector that fits in LDS whole: no slices, no partial sums, no reduction.
