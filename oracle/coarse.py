@@ -77,3 +77,19 @@ def coarse_solve(L: np.ndarray, c: np.ndarray) -> np.ndarray:
     """y = A_c^{-1} c via the two triangular solves with L."""
     t = sla.solve_triangular(L, c, lower=True)
     return sla.solve_triangular(L.T, t, lower=False)
+
+
+def coarse_eigen(K: np.ndarray):
+    """(ev, Q) with K = Q diag(ev) Q^T.  The Bayesian-regression experiments
+    solve the coarse level with the SVD of X_c (experiments section): its
+    right singular vectors and squared singular values are the eigenvectors
+    and eigenvalues of K = X_c^T X_c, so the symmetric eigendecomposition
+    (LAPACK through NumPy, a library step) stands for it."""
+    ev, Q = np.linalg.eigh(np.asarray(K, dtype=np.float64))
+    return ev, Q
+
+
+def eigen_coarse_inverse(ev: np.ndarray, Q: np.ndarray, lam: float) -> np.ndarray:
+    """A_c(lam)^-1 = Q diag(1 / (ev + lam)) Q^T: the same decomposition
+    serves every lam, with no new factorization."""
+    return (Q / (ev + lam)) @ Q.T

@@ -24,6 +24,17 @@ def rhs(X, y: np.ndarray) -> np.ndarray:
     return np.asarray(X.T @ np.asarray(y, dtype=np.float64), dtype=np.float64)
 
 
+def noise_rhs(X, y: np.ndarray, tau: float, lam: float, xi1: np.ndarray, xi2: np.ndarray) -> np.ndarray:
+    """The right-hand side of one noise-injection sample (Bayesian regression
+    subsection, eq. ni_xtx): X^T (y + e1) + e2 / tau with e1 ~ N(0, I_N / tau)
+    and e2 ~ N(0, lam I_F), formed from standard-normal draws as
+    e1 = xi1 / sqrt(tau), e2 = sqrt(lam) xi2.  The sample solves
+    (X^T X + (lam / tau) I) w = this."""
+    e1 = np.asarray(xi1, dtype=np.float64) / np.sqrt(tau)
+    e2 = np.sqrt(lam) * np.asarray(xi2, dtype=np.float64)
+    return rhs(X, np.asarray(y, dtype=np.float64) + e1) + e2 / tau
+
+
 def column_sq_norms(X) -> np.ndarray:
     """c_j = ||x_j||^2, the diagonal of X^T X."""
     if sp.issparse(X):

@@ -254,3 +254,68 @@ def test_f32_operator_bound_covers_a_perturbed_sum():
     Xs[:, [0, 1]] = Xs[:, [1, 0]]
     assert np.any(np.abs(op.apply_A_f32(Xs, 0.5, V) - Q) > B)
     assert B.max() < 1e-3 * np.abs(Q).max()
+
+
+# --- the eigen coarse solver and the noise-injection sampler ------------------
+
+def test_eigen_coarse_inverse_closed_form_and_svd():
+    """A_c(lam)^-1 from K = Q diag(ev) Q^T equals inv(K + lam I) at several
+    lam, and equals the SVD form V diag(1/(s^2 + lam)) V^T built from the
+    right singular vectors of X_c = X P (the paper's coarse solver for
+    Bayesian regression)."""
+    P = datagen.sparse_problem(400, 90, 8, seed=21)
+    lab = datagen.random_labels(90, 12, 4)
+    labc = np.unique(lab, return_inverse=True)[1]
+    fc = int(labc.max()) + 1
+    K = coarse.coarse_gram(P.X, labc, fc)
+    ev, Q = coarse.coarse_eigen(K)
+    assert np.allclose(Q.T @ Q, np.eye(fc), atol=1e-13)
+    assert np.linalg.norm(Q @ np.diag(ev) @ Q.T - K) <= 1e-13 * np.linalg.norm(K)
+    Xc = (P.X @ coarse.prolongation(labc, fc)).toarray()
+    _, s, Vt = np.linalg.svd(Xc, full_matrices=False)
+    for lam in (1e-2, 1.0, 37.0):
+        Ai = coarse.eigen_coarse_inverse(ev, Q, lam)
+        ref = np.linalg.inv(K + lam * np.eye(fc))
+        assert np.linalg.norm(Ai - ref) <= 1e-11 * np.linalg.norm(ref)
+        svd = (Vt.T / (s**2 + lam)) @ Vt
+        assert np.linalg.norm(Ai - svd) <= 1e-11 * np.linalg.norm(ref)
+
+
+def test_noise_rhs_reduces_to_rhs_and_is_linear():
+    P = datagen.sparse_problem(300, 40, 6, seed=23)
+    rng = np.random.default_rng(1)
+    xi1, xi2 = rng.standard_normal(300), rng.standard_normal(40)
+    z1, z2 = np.zeros(300), np.zeros(40)
+    assert np.array_equal(op.noise_rhs(P.X, P.y, 2.0, 3.0, z1, z2), op.rhs(P.X, P.y))
+    # b - X^T y = X^T xi1 / sqrt(tau) + sqrt(lam) / tau xi2, term by term
+    b = op.noise_rhs(P.X, P.y, 4.0, 9.0, xi1, xi2)
+    want = op.rhs(P.X, P.y) + (P.X.T @ xi1) / 2.0 + (3.0 / 4.0) * xi2
+    assert np.allclose(b, want, rtol=1e-14, atol=1e-13)
+
+
+def test_noise_injection_samples_the_posterior():
+    """Solving (X^T X + (lam/tau) I) w = X^T (y + e1) + e2 / tau draws w from
+    N((X^T X + beta I)^-1 X^T y, ((X^T X + beta I) tau)^-1) with beta =
+    lam / tau (the Bayesian regression subsection): the sample mean and
+    covariance of 40,000 draws match to within their sampling error."""
+    rng = np.random.default_rng(7)
+    N, F, tau, lam = 60, 5, 2.5, 4.0
+    X = rng.standard_normal((N, F))
+    y = rng.standard_normal(N)
+    M = X.T @ X + (lam / tau) * np.eye(F)
+    S = 40_000
+    xi1 = rng.standard_normal((S, N))
+    xi2 = rng.standard_normal((S, F))
+    B = np.stack([op.noise_rhs(X, y, tau, lam, xi1[i], xi2[i]) for i in range(S)])
+    W = np.linalg.solve(M, B.T).T
+    mean_ref = np.linalg.solve(M, X.T @ y)
+    cov_ref = np.linalg.inv(M * tau)
+    sd = np.sqrt(np.diag(cov_ref))
+    assert np.all(np.abs(W.mean(0) - mean_ref) <= 5 * sd / np.sqrt(S))
+    C = np.cov(W.T)
+    # sampling error of a covariance entry: about sqrt((s_ii s_jj + s_ij^2) / S)
+    err = np.sqrt((np.outer(np.diag(cov_ref), np.diag(cov_ref)) + cov_ref**2) / S)
+    assert np.all(np.abs(C - cov_ref) <= 5 * err)
+    # a mistaken scale (e1 with variance 1/tau^2, or e2 / sqrt(tau)) is ruled out
+    bad = np.linalg.inv(M * tau * tau)
+    assert np.any(np.abs(C - bad) > 5 * err)
