@@ -173,6 +173,55 @@ def dense_section(rr, torch, dev, log):
             "forms": forms, "operator": gemm}
 
 
+def bayes_section(rr, torch, dev, log, P, R, k, n_samples=100):
+    """Noise-injection samples of Bayesian regression (eq. ni_xtx) on the
+    200,000 x 100,000 workload: every sample draws standard normals xi1 (N),
+    xi2 (F) and a precision ratio beta = lambda / tau (log-uniform in [0.5, 2],
+    a new value each sample as in a Gibbs sweep), forms b = X^T (y + e1) +
+    e2 / tau on the GPU and solves (X^T X + beta I) w = b by V(1,1) PCG to
+    relative residual 1e-8.  The handle with the eigen coarse solver (K =
+    Q diag(ev) Q^T once, one GEMM per beta) against the bench's Cholesky
+    handle (a factorization per beta)."""
+    import numpy as np
+    t0 = time.perf_counter()
+    RE = rr.Ridge(P.X, n_clusters=k, seed=5826, lambda_slots=4, coarse_eigen=True)
+    torch.cuda.synchronize()
+    eig_setup_ms = (time.perf_counter() - t0) * 1e3
+    N, F = P.X.shape
+    rng = np.random.default_rng(5826 + 5000)
+    betas = np.exp(rng.uniform(np.log(0.5), np.log(2.0), n_samples))
+    taus = np.exp(rng.uniform(np.log(0.5), np.log(2.0), n_samples))
+    g = torch.Generator(device=dev).manual_seed(5826 + 5001)
+    y = torch.as_tensor(P.y, dtype=torch.float64, device=dev)
+    xi1 = torch.randn((n_samples, N), dtype=torch.float64, device=dev, generator=g)
+    xi2 = torch.randn((n_samples, F), dtype=torch.float64, device=dev, generator=g)
+    b = torch.empty(F, dtype=torch.float64, device=dev)
+    w = torch.empty(F, dtype=torch.float64, device=dev)
+    out = {"samples": n_samples, "tol": 1e-8, "eigen_setup_ms": eig_setup_ms,
+           "eigen_sweeps": RE.info["eigen_sweeps"]}
+    for name, H in (("eigen", RE), ("cholesky", R)):
+        iters = []
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for i in range(n_samples):
+            tau = float(taus[i])
+            lam = float(betas[i]) * tau
+            rr.rr_noise_rhs(H.h, tau, lam, y, xi1[i], xi2[i], b)
+            st, inf = rr.rr_solve(H.h, lam / tau, b, w, rhs_is_b=True, tol=1e-8, precond="vcycle",
+                                  max_iter=5000, raise_on=(1, 2, 6))
+            iters.append(inf["iters"])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - ta) * 1e3
+        out[name] = {"ms_per_sample": ms / n_samples, "mean_iters": float(np.mean(iters))}
+    RE.close()
+    log(f"[bench bayes] {n_samples} noise-injection samples, beta in [0.5, 2]: eigen coarse "
+        f"{out['eigen']['ms_per_sample']:.2f} ms/sample ({out['eigen']['mean_iters']:.1f} its; "
+        f"decomposition in setup {eig_setup_ms:.0f} ms, {out['eigen_sweeps']} Jacobi sweeps), "
+        f"Cholesky per beta {out['cholesky']['ms_per_sample']:.2f} ms/sample "
+        f"({out['cholesky']['mean_iters']:.1f} its)")
+    return out
+
+
 def batched_uneven_section(rr, torch, dev, log, full=False):
     """Independent uneven problems in one rr_solve_batched call against one
     rr_solve call after another: the batched-uneven workload's generator
@@ -493,6 +542,7 @@ def main():
         labels = datagen.random_labels(F, args.k, 11)
         cpu = cpu_baseline(P.X, P.y, 1.0, labels, args.k, total_iters)
 
+    bayes = None if args.no_dense else bayes_section(rr, torch, dev, log, P, R, args.k)
     dense = None if args.no_dense else dense_section(rr, torch, dev, log)
     uneven = None if args.no_dense else batched_uneven_section(rr, torch, dev, log)
 
@@ -535,6 +585,7 @@ def main():
         "learned": learned,
         "dense_many_rhs": dense,
         "batched_uneven": uneven,
+        "bayes_noise_injection": bayes,
         "roofline": {"bound": "hbm", "achieved": gbs_gather, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs_gather / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "rr::k_sell<1> (column-pass gather of t = X^T u through LDS slices)",

@@ -128,6 +128,12 @@ typedef struct {
                               features in increasing index, cut into groups of
                               at most 32) and their Gram matrices X_B^T X_B,
                               for solves with smoother = RR_SMOOTHER_BLOCK     */
+  int32_t coarse_eigen;    /* with a coarse level: 1 also forms K = Q diag(ev) Q^T
+                              (parallel cyclic Jacobi, FP64) at setup; the
+                              solves then take A_c(lambda)^-1 = Q diag(1/(ev +
+                              lambda)) Q^T, one GEMM per new lambda instead of
+                              a Cholesky factorization (the SVD coarse solver
+                              of the Bayesian-regression experiments)          */
 } rr_setup_opts;
 
 /*
@@ -168,6 +174,7 @@ typedef struct {
                               contraction aims at, for the FP64, BF16 and FP32
                               operators (tuned when autotune = 1)              */
   int32_t dense_split_cached; /* 1: those came from an earlier measurement     */
+  int32_t eigen_sweeps;    /* coarse_eigen: Jacobi sweeps run (0: not formed)  */
 } rr_setup_info;
 
 /* Host-side facts about a handle. */
@@ -337,9 +344,27 @@ rr_status rr_coarse_gram(rr_handle* h, double* K, rr_stream stream);
 
 /* The Cholesky factor L (lower, row-major, zeros above the diagonal) of
  * A_c = K + lambda I and A_c^-1, device double[F_C * F_C] each; either may be
- * NULL.  Errors: RR_ERR_BREAKDOWN if A_c is not numerically positive definite. */
+ * NULL.  Errors: RR_ERR_BREAKDOWN if A_c is not numerically positive definite.
+ * A handle set up with coarse_eigen forms A_c^-1 from the eigendecomposition
+ * and no L: it returns RR_ERR_UNSUPPORTED when L is requested. */
 rr_status rr_coarse_factor(rr_handle* h, double lambda, double* L, double* Ac_inv,
                            rr_stream stream);
+
+/* The eigendecomposition K = Q diag(ev) Q^T formed with coarse_eigen: Q
+ * device double[F_C * F_C] row-major (column k is the k-th eigenvector), ev
+ * device double[F_C] (unsorted); either may be NULL.  RR_ERR_INVALID_ARG if
+ * the handle was set up without coarse_eigen. */
+rr_status rr_coarse_eigen(rr_handle* h, double* Q, double* ev, rr_stream stream);
+
+/* The right-hand side of one noise-injection sample (the Bayesian
+ * regression subsection, eq. ni_xtx): b = X^T (y + e1) + e2 / tau with
+ * e1 = xi1 / sqrt(tau) ~ N(0, I_N / tau) and e2 = sqrt(lambda) xi2 ~ N(0,
+ * lambda I_F), from the caller's standard-normal draws xi1 (device
+ * double[N]) and xi2 (device double[F]).  The sample w solves
+ * (X^T X + (lambda / tau) I) w = b: rr_solve with rhs_is_b at lambda / tau.
+ * tau > 0 and lambda > 0, finite. */
+rr_status rr_noise_rhs(rr_handle* h, double tau, double lambda, const double* y, const double* xi1,
+                       const double* xi2, double* b, rr_stream stream);
 
 /* The automatic smoother weight for this lambda (host double).  X >= 0: the
  * Gershgorin weight 1 / max_j (X^T X 1 + lambda)_j / D_j.  X with negative

@@ -49,7 +49,7 @@ class rr_setup_opts(C.Structure):
     _fields_ = [("n_clusters", C.c_int32), ("kmeans_max_iter", C.c_int32),
                 ("seed", C.c_uint64), ("labels_in", C.c_void_p), ("n_labels_in", C.c_int32),
                 ("lambda_slots", C.c_int32), ("autotune", C.c_int32),
-                ("block_smoother", C.c_int32)]
+                ("block_smoother", C.c_int32), ("coarse_eigen", C.c_int32)]
 
 
 class rr_setup_info(C.Structure):
@@ -58,7 +58,8 @@ class rr_setup_info(C.Structure):
                 ("binary", C.c_int32), ("setup_ms", C.c_double), ("kmeans_ms", C.c_double),
                 ("plan_ms", C.c_double), ("tuned_rows_div", C.c_int32),
                 ("tuned_cols_div", C.c_int32), ("tune_cached", C.c_int32), ("dense", C.c_int32),
-                ("dense_split", C.c_int32 * 3), ("dense_split_cached", C.c_int32)]
+                ("dense_split", C.c_int32 * 3), ("dense_split_cached", C.c_int32),
+                ("eigen_sweeps", C.c_int32)]
 
 
 class rr_solve_opts(C.Structure):
@@ -104,6 +105,8 @@ _SIGS = {
     "rr_apply_precond": [_P, C.c_double, C.c_int32, C.c_double, _P, _P, _P],
     "rr_coarse_gram": [_P, _P, _P],
     "rr_coarse_factor": [_P, C.c_double, _P, _P, _P],
+    "rr_coarse_eigen": [_P, _P, _P, _P],
+    "rr_noise_rhs": [_P, C.c_double, C.c_double, _P, _P, _P, _P, _P],
     "rr_smoother_weight": [_P, C.c_double, C.POINTER(C.c_double)],
     "rr_setup_dense": [C.POINTER(rr_dense), C.POINTER(rr_setup_opts), _P, C.POINTER(_P)],
     "rr_solve_block": [_P, C.c_double, C.c_int32, _P, C.c_int64, _P, C.c_int64,
@@ -159,7 +162,7 @@ def _dev_f64(t, n=None, name="vector"):
 
 def rr_setup(row_ptr, col_idx, values, n_cols, n_clusters=0, seed=0, kmeans_max_iter=0,
              labels_in=None, n_labels_in=0, lambda_slots=0, autotune=False, block_smoother=False,
-             stream=None):
+             coarse_eigen=False, stream=None):
     """X is a device CSR: row_ptr/col_idx int32 CUDA tensors, values float64
     CUDA tensor or None (binary).  Returns an opaque handle (int)."""
     import torch
@@ -174,7 +177,7 @@ def rr_setup(row_ptr, col_idx, values, n_cols, n_clusters=0, seed=0, kmeans_max_
                _ptr(values))
     o = rr_setup_opts(int(n_clusters), int(kmeans_max_iter), int(seed) & (2**64 - 1),
                       _ptr(labels_in), int(n_labels_in), int(lambda_slots), 1 if autotune else 0,
-                      1 if block_smoother else 0)
+                      1 if block_smoother else 0, 1 if coarse_eigen else 0)
     h = C.c_void_p()
     _check(_lib.rr_setup(C.byref(X), C.byref(o), _stream(stream), C.byref(h)))
     return h.value
@@ -189,7 +192,7 @@ def _rows_f64(t, name):
 
 
 def rr_setup_dense(X, n_clusters=0, seed=0, kmeans_max_iter=0, labels_in=None, n_labels_in=0,
-                   lambda_slots=0, autotune=False, stream=None):
+                   lambda_slots=0, autotune=False, coarse_eigen=False, stream=None):
     """X: (N, F) float32 CUDA tensor with unit column stride (row-major).
     Returns an opaque handle (int)."""
     import torch
@@ -199,7 +202,8 @@ def rr_setup_dense(X, n_clusters=0, seed=0, kmeans_max_iter=0, labels_in=None, n
         raise ValueError("labels_in: need an int32 CUDA tensor")
     D = rr_dense(X.shape[0], X.shape[1], X.stride(0), _ptr(X))
     o = rr_setup_opts(int(n_clusters), int(kmeans_max_iter), int(seed) & (2**64 - 1),
-                      _ptr(labels_in), int(n_labels_in), int(lambda_slots), 1 if autotune else 0)
+                      _ptr(labels_in), int(n_labels_in), int(lambda_slots), 1 if autotune else 0,
+                      0, 1 if coarse_eigen else 0)
     h = C.c_void_p()
     _check(_lib.rr_setup_dense(C.byref(D), C.byref(o), _stream(stream), C.byref(h)))
     return h.value
@@ -399,6 +403,16 @@ def rr_apply_rhs(h, y, b, stream=None):
     _check(_lib.rr_apply_rhs(C.c_void_p(h), _ptr(y), _ptr(b), _stream(stream)))
 
 
+def rr_noise_rhs(h, tau, lam, y, xi1, xi2, b, stream=None):
+    """b = X^T (y + xi1 / sqrt(tau)) + sqrt(lam) / tau * xi2 (device float64)."""
+    _check(_lib.rr_noise_rhs(C.c_void_p(h), float(tau), float(lam), _ptr(y), _ptr(xi1), _ptr(xi2),
+                             _ptr(b), _stream(stream)))
+
+
+def rr_coarse_eigen(h, Q, ev, stream=None):
+    _check(_lib.rr_coarse_eigen(C.c_void_p(h), _ptr(Q), _ptr(ev), _stream(stream)))
+
+
 def rr_apply_precond(h, lam, precond, omega, r, z, stream=None):
     k = PRECOND[precond] if isinstance(precond, str) else int(precond)
     _check(_lib.rr_apply_precond(C.c_void_p(h), float(lam), k, float(omega), _ptr(r), _ptr(z),
@@ -427,7 +441,8 @@ class Ridge:
     copy)."""
 
     def __init__(self, X, n_clusters=0, seed=0, kmeans_max_iter=0, labels=None, binary=None,
-                 lambda_slots=0, autotune=False, block_smoother=False, device="cuda"):
+                 lambda_slots=0, autotune=False, block_smoother=False, coarse_eigen=False,
+                 device="cuda"):
         import numpy as np
         import torch
         X = X.tocsr()
@@ -445,7 +460,7 @@ class Ridge:
             lab = torch.as_tensor(np.asarray(labels, dtype=np.int32), device=self.device)
             nlab = int(np.max(labels)) + 1 if len(labels) else 1
         self.h = rr_setup(rp, ci, vals, self.F, n_clusters, seed, kmeans_max_iter, lab, nlab,
-                          lambda_slots, autotune, block_smoother)
+                          lambda_slots, autotune, block_smoother, coarse_eigen)
         torch.cuda.current_stream().synchronize()
         self.info = rr_get_setup_info(self.h)
 
@@ -524,6 +539,24 @@ class Ridge:
 
     def smoother_weight(self, lam):
         return rr_smoother_weight(self.h, lam)
+
+    def coarse_eigen(self):
+        """(Q, ev) with K = Q diag(ev) Q^T (a handle set up with coarse_eigen)."""
+        import torch
+        fc = self.info["n_coarse"]
+        Q = torch.empty(fc * fc, dtype=torch.float64, device=self.device)
+        ev = torch.empty(fc, dtype=torch.float64, device=self.device)
+        rr_coarse_eigen(self.h, Q, ev)
+        return Q.view(fc, fc), ev
+
+    def noise_rhs(self, tau, lam, y, xi1, xi2):
+        import torch
+        y = self._vec(y, self.N)
+        xi1 = self._vec(xi1, self.N)
+        xi2 = self._vec(xi2, self.F)
+        out = torch.empty(self.F, dtype=torch.float64, device=self.device)
+        rr_noise_rhs(self.h, tau, lam, y, xi1, xi2, out)
+        return out
 
 
 class DenseRidge(Ridge):

@@ -171,6 +171,7 @@ void destroy_handle(rr_handle* h) {
   dfree(h->perm); dfree(h->coff); dfree(h->K);
   for (auto& s : h->slots) { dfree(s.L); dfree(s.Ainv); dfree(s.Dinv); }
   dfree(h->boff); dfree(h->bperm); dfree(h->bgram);
+  dfree(h->eig_q); dfree(h->eig_v);
   dfree(h->chol_work); dfree(h->chol_flag); dfree(h->omega_tmp); dfree(h->mlp_scale);
   if (h->pw) {
     dfree(h->pw->v); dfree(h->pw->t); dfree(h->pw->u); dfree(h->pw->D); dfree(h->pw->vin);
@@ -286,6 +287,7 @@ rr_status setup_impl(const rr_csr* Xin, const rr_setup_opts* o, hipStream_t s, r
     RR_TRY(dalloc(&h->chol_flag, 1));
     if (o && o->block_smoother) RR_TRY(build_smoother_blocks(h, s));
     RR_TRY(build_cluster_rows(h, s));
+    if (o && o->coarse_eigen) RR_TRY(coarse_eigen(h, &h->eig_sweeps, s));
     np = std::max(np, h->restrict_plan.nblocks + cdiv(h->restrict_plan.nspan, kBlock / 64) + 1);
   }
   np = std::max(np, std::max(3 * kMaxParts, kMaxReduceBlocks + 1));
@@ -497,7 +499,7 @@ rr_status get_slot(rr_handle* h, const Sparse& X, double lam, LambdaSlot** out, 
   }
   const double t0 = now_ms();
   victim->valid = false;
-  RR_TRY(coarse_factor(h, lam, *victim, s));
+  RR_TRY(h->eig_q ? coarse_from_eigen(h, lam, *victim, s) : coarse_factor(h, lam, *victim, s));
   RR_TRY(block_factor(h, lam, *victim, s));
   RR_TRY(auto_omega(h, X, lam, &victim->omega, s));
   RR_HIP(hipStreamSynchronize(s));
@@ -1520,6 +1522,7 @@ rr_status rr_get_setup_info(const rr_handle* h, rr_setup_info* info) {
   i.tuned_cols_div = h->tuning.div_cols;
   i.tune_cached = h->tuning.cached;
   i.dense = h->dense ? 1 : 0;
+  i.eigen_sweeps = h->eig_q ? std::max(1, h->eig_sweeps) : 0;
   if (h->dense) {
     i.nnz = (int64_t)h->X.N * h->X.F;
     for (int k = 0; k < 3; ++k) i.dense_split[k] = h->dense->split_target[k];
@@ -1592,6 +1595,36 @@ rr_status rr_apply_rhs(rr_handle* h, const double* y, double* b, rr_stream strea
   return RR_OK;
 }
 
+rr_status rr_noise_rhs(rr_handle* h, double tau, double lambda, const double* y, const double* xi1,
+                       const double* xi2, double* b, rr_stream stream) {
+  RR_TRY(check_sparse(h));
+  if (!y || !xi1 || !xi2 || !b) return fail(RR_ERR_INVALID_ARG, "null vector");
+  if (!(tau > 0.0) || !(lambda > 0.0) || !std::isfinite(tau) || !std::isfinite(lambda))
+    return fail(RR_ERR_INVALID_ARG, "tau and lambda must be finite and > 0");
+  hipStream_t s = (hipStream_t)stream;
+  double* v = nullptr;
+  RR_TRY(dalloc(&v, std::max(1, h->X.N)));
+  launch_noise_rhs_in(h->X.N, y, xi1, 1.0 / std::sqrt(tau), v, s);   // y + e1
+  Epi e{};
+  e.out = h->w.vout;
+  launch_csc(h->X, v, EPI_STORE, e, nullptr, s);
+  launch_gather(b, h->w.vout, h->finv, h->X.F, s);
+  launch_axpy_out(h->X.F, b, xi2, std::sqrt(lambda) / tau, s);        // + e2 / tau
+  RR_HIP(hipStreamSynchronize(s));
+  dfree(v);
+  RR_HIP(hipGetLastError());
+  return RR_OK;
+}
+
+rr_status rr_coarse_eigen(rr_handle* h, double* Q, double* ev, rr_stream stream) {
+  RR_TRY(check_handle(h));
+  if (!h->eig_q) return fail(RR_ERR_INVALID_ARG, "the handle was set up without coarse_eigen");
+  hipStream_t s = (hipStream_t)stream;
+  if (Q) RR_HIP(hipMemcpyAsync(Q, h->eig_q, sizeof(double) * h->FC * h->FC, hipMemcpyDeviceToDevice, s));
+  if (ev) RR_HIP(hipMemcpyAsync(ev, h->eig_v, sizeof(double) * h->FC, hipMemcpyDeviceToDevice, s));
+  return RR_OK;
+}
+
 rr_status rr_apply_precond(rr_handle* h, double lambda, int32_t precond, double omega,
                            const double* r, double* z, rr_stream stream) {
   RR_TRY(check_sparse(h));
@@ -1646,6 +1679,7 @@ rr_status rr_coarse_factor(rr_handle* h, double lambda, double* L, double* Ainv,
   RR_TRY(check_lambda(lambda, false));
   if (h->FC == 0) return fail(RR_ERR_INVALID_ARG, "no coarse level");
   hipStream_t s = (hipStream_t)stream;
+  if (L && h->eig_q) return fail(RR_ERR_UNSUPPORTED, "a coarse_eigen handle forms no Cholesky factor");
   LambdaSlot* sl = nullptr;
   double ms = 0.0;
   RR_TRY(get_slot(h, h->w.X, lambda, &sl, &ms, s));

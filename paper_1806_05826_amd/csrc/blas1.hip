@@ -589,4 +589,22 @@ void launch_rg_dir(int F, const double* res, const double* D, double* p, const d
   k_rg_dir<<<vec_grid(F), kBlock, 0, s>>>(F, res, D, p, rr_new, n_new, rr_old, n_old, sc);
 }
 
+// Noise-injection right-hand side: v = y + a xi1 (N) and b += c xi2 (F).
+__global__ void k_noise_in(int N, const double* __restrict__ y, const double* __restrict__ xi1, double a,
+                           double* __restrict__ v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) v[i] = y[i] + a * xi1[i];
+}
+void launch_noise_rhs_in(int N, const double* y, const double* xi1, double a, double* v, hipStream_t s) {
+  if (N > 0) k_noise_in<<<cdiv(N, kBlock), kBlock, 0, s>>>(N, y, xi1, a, v);
+}
+
+__global__ void k_axpy_out(int F, double* __restrict__ b, const double* __restrict__ xi2, double c) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < F) b[j] += c * xi2[j];
+}
+void launch_axpy_out(int F, double* b, const double* xi2, double c, hipStream_t s) {
+  if (F > 0) k_axpy_out<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, b, xi2, c);
+}
+
 }  // namespace rr

@@ -1182,6 +1182,7 @@ rr_status dense_setup(rr_handle* h, const rr_dense* Xin, const rr_setup_opts* o,
     // the coarse blocks of the work buffers depend on FC
     dense_free_work(*h->dwork);
     RR_TRY(ensure_dwork(h, 1));
+    if (o && o->coarse_eigen) RR_TRY(coarse_eigen(h, &h->eig_sweeps, s));
   }
   if (o && o->autotune) RR_TRY(dense_autotune(h, s));
   RR_HIP(hipStreamSynchronize(s));

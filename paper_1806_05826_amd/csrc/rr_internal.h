@@ -339,6 +339,9 @@ struct rr_handle {
   rr::MergePlan restrict_plan;  // segments = clusters over perm
   ClusterRows crow;             // label table for the V(1,1) second row pass
   double* K = nullptr;          // [FC*FC] coarse Gram
+  double* eig_q = nullptr;      // [FC*FC] eigenvectors of K (columns), with coarse_eigen
+  double* eig_v = nullptr;      // [FC] their eigenvalues
+  int eig_sweeps = 0;           // Jacobi sweeps the decomposition took
   std::deque<rr::LambdaSlot> slots;
   unsigned long long stamp = 0;
   double* chol_work = nullptr;  // [FC*FC] scratch for the factorization
@@ -506,6 +509,11 @@ void launch_make_pairs(int FC, int npairs, const double* S, const double* Ainv_r
 
 // ---- coarse level (coarse.hip) ---------------------------------------------
 rr_status coarse_factor(rr_handle* h, double lam, LambdaSlot& slot, hipStream_t s);
+constexpr int kMaxJacobiSweeps = 40;
+rr_status coarse_eigen(rr_handle* h, int* sweeps, hipStream_t s);
+rr_status coarse_from_eigen(rr_handle* h, double lam, LambdaSlot& slot, hipStream_t s);
+void launch_noise_rhs_in(int N, const double* y, const double* xi1, double a, double* v, hipStream_t s);
+void launch_axpy_out(int F, double* b, const double* xi2, double c, hipStream_t s);
 
 // ---- clustering (kmeans.hip) -----------------------------------------------
 uint64_t splitmix64_next(uint64_t& state);   // SplitMix64 (Steele, Lea & Flood)
