@@ -24,6 +24,18 @@ def rhs(X, y: np.ndarray) -> np.ndarray:
     return np.asarray(X.T @ np.asarray(y, dtype=np.float64), dtype=np.float64)
 
 
+def weighted_rows(X, d: np.ndarray):
+    """diag(sqrt(d)) X, so that its Gram matrix is X^T D X: the weighted
+    operator X^T D X + lam I of Newton steps (the subsection on optimization
+    by the Newton method) is apply_A of this matrix, and every coarse-level
+    and smoother function of the oracle taken on it is the weighted one.
+    Weights d >= 0."""
+    d = np.asarray(d, dtype=np.float64)
+    if np.any(d < 0) or not np.all(np.isfinite(d)):
+        raise ValueError("row weights must be finite and >= 0")
+    return sp.diags(np.sqrt(d)) @ (X if sp.issparse(X) else sp.csr_matrix(X))
+
+
 def noise_rhs(X, y: np.ndarray, tau: float, lam: float, xi1: np.ndarray, xi2: np.ndarray) -> np.ndarray:
     """The right-hand side of one noise-injection sample (Bayesian regression
     subsection, eq. ni_xtx): X^T (y + e1) + e2 / tau with e1 ~ N(0, I_N / tau)

@@ -319,3 +319,27 @@ def test_noise_injection_samples_the_posterior():
     # a mistaken scale (e1 with variance 1/tau^2, or e2 / sqrt(tau)) is ruled out
     bad = np.linalg.inv(M * tau * tau)
     assert np.any(np.abs(C - bad) > 5 * err)
+
+
+def test_weighted_operator_is_the_logistic_hessian():
+    """For L2-regularized logistic regression f(w) = sum_i log(1 + e^{z_i})
+    - t_i z_i + beta ||w||^2 / 2 with z = X w, the Hessian is X^T D X + beta I
+    with D = diag(p (1 - p)), p = sigma(z): apply_A of weighted_rows(X, d)
+    equals central differences of the analytic gradient X^T (p - t) + beta w."""
+    P = datagen.sparse_problem(500, 60, 7, seed=29)
+    X = P.X
+    rng = np.random.default_rng(3)
+    t = (rng.random(500) < 0.4).astype(np.float64)
+    w = 0.3 * rng.standard_normal(60)
+    beta = 0.7
+    grad = lambda w: X.T @ (1.0 / (1.0 + np.exp(-(X @ w))) - t) + beta * w
+    p = 1.0 / (1.0 + np.exp(-(X @ w)))
+    Xd = op.weighted_rows(X, p * (1.0 - p))
+    for _ in range(3):
+        v = rng.standard_normal(60)
+        eps = 1e-5
+        fd = (grad(w + eps * v) - grad(w - eps * v)) / (2 * eps)
+        hv = op.apply_A(Xd, beta, v)
+        assert np.linalg.norm(hv - fd) <= 1e-7 * np.linalg.norm(hv)
+    with pytest.raises(ValueError):
+        op.weighted_rows(X, -np.ones(500))
