@@ -222,6 +222,50 @@ def bayes_section(rr, torch, dev, log, P, R, k, n_samples=100):
     return out
 
 
+def newton_section(rr, torch, dev, log, P, k, steps=5, beta=1.0):
+    """L2-regularized logistic regression on the 200,000 x 100,000 matrix
+    (targets t = 1[y > median y]) by Newton steps: each step forms z = X w,
+    p = sigma(z), the gradient g = X^T (p - t) + beta w, sets the row weights
+    d = p (1 - p) (which rebuilds the Jacobi diagonal, the Gershgorin sums
+    and the coarse matrix P^T X^T D X P) and solves (X^T D X + beta I) s = -g
+    by V(1,1) PCG to relative residual 1e-8 (the Hessian form of the
+    subsection on optimization by the Newton method)."""
+    import numpy as np
+    R = rr.Ridge(P.X, n_clusters=k, seed=5826, lambda_slots=4)   # no block-smoother blocks
+    N, F = P.X.shape
+    y = np.asarray(P.y)
+    t = torch.as_tensor((y > np.median(y)).astype(np.float64), device=dev)
+    w = torch.zeros(F, dtype=torch.float64, device=dev)
+    s = torch.empty(F, dtype=torch.float64, device=dev)
+    rows = []
+    for k in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        z = R.apply_rows(w)
+        p = torch.sigmoid(z)
+        g = R.apply_rhs(p - t) + beta * w
+        loss = float((torch.nn.functional.softplus(z) - t * z).sum() + 0.5 * beta * (w * w).sum())
+        gnorm = float(g.norm())
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        R.set_row_weights(p * (1.0 - p))
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        st, inf = rr.rr_solve(R.h, beta, -g, s, rhs_is_b=True, tol=1e-8, precond="vcycle",
+                              max_iter=5000, raise_on=(1, 2, 6))
+        w += s
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        rows.append({"loss": loss, "grad_norm": gnorm, "iters": inf["iters"],
+                     "gradient_ms": (t1 - t0) * 1e3, "weights_ms": (t2 - t1) * 1e3,
+                     "solve_ms": (t3 - t2) * 1e3})
+    R.close()
+    log("[bench newton] " + "; ".join(
+        f"step {i}: loss {r['loss']:.6e}, |g| {r['grad_norm']:.2e}, {r['iters']} its, weights "
+        f"{r['weights_ms']:.1f} ms, solve {r['solve_ms']:.1f} ms" for i, r in enumerate(rows)))
+    return {"steps": rows, "beta": beta, "tol": 1e-8}
+
+
 def batched_uneven_section(rr, torch, dev, log, full=False):
     """Independent uneven problems in one rr_solve_batched call against one
     rr_solve call after another: the batched-uneven workload's generator
@@ -543,6 +587,7 @@ def main():
         cpu = cpu_baseline(P.X, P.y, 1.0, labels, args.k, total_iters)
 
     bayes = None if args.no_dense else bayes_section(rr, torch, dev, log, P, R, args.k)
+    newton = None if args.no_dense else newton_section(rr, torch, dev, log, P, args.k)
     dense = None if args.no_dense else dense_section(rr, torch, dev, log)
     uneven = None if args.no_dense else batched_uneven_section(rr, torch, dev, log)
 
@@ -586,6 +631,7 @@ def main():
         "dense_many_rhs": dense,
         "batched_uneven": uneven,
         "bayes_noise_injection": bayes,
+        "newton_logistic": newton,
         "roofline": {"bound": "hbm", "achieved": gbs_gather, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs_gather / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "rr::k_sell<1> (column-pass gather of t = X^T u through LDS slices)",

@@ -331,7 +331,8 @@ rr_status rr_solve_batched(int32_t nprob, rr_handle* const* handles, const doubl
 rr_status rr_apply_operator(rr_handle* h, double lambda, const double* v, double* Av,
                             rr_stream stream);
 
-/* b = X^T y, y device double[N], b device double[F]. */
+/* b = X^T y, y device double[N], b device double[F] (row weights do not
+ * apply). */
 rr_status rr_apply_rhs(rr_handle* h, const double* y, double* b, rr_stream stream);
 
 /* z = B r for the preconditioner `precond` (rr_precond) at this lambda;
@@ -365,6 +366,26 @@ rr_status rr_coarse_eigen(rr_handle* h, double* Q, double* ev, rr_stream stream)
  * tau > 0 and lambda > 0, finite. */
 rr_status rr_noise_rhs(rr_handle* h, double tau, double lambda, const double* y, const double* xi1,
                        const double* xi2, double* b, rr_stream stream);
+
+/* Row weights d (device double[N], finite, >= 0; NULL clears them): from
+ * here on the handle's operator is X^T D X + lambda I, D = diag(d), the
+ * Hessian form of Newton steps for logistic regression and L2-loss SVMs
+ * (the subsection on optimization by the Newton method).  The row pass
+ * scales its output by d in the reduction's epilogue; solves from y form
+ * b = X^T D y (rr_apply_rhs stays the plain X^T y, as a Newton gradient
+ * needs).  The call rebuilds what depends on the
+ * operator: the Jacobi diagonal sum_i d_i x_ij + lambda, the Gershgorin sums
+ * X^T D X 1, the coarse matrix P^T X^T D X P (F_C operator applications) and,
+ * with coarse_eigen, its eigendecomposition; cached per-lambda factors and
+ * captured graphs are dropped.  The aggregation P is kept.  0/1 X only,
+ * without block-smoother blocks; no solve may run on the handle meanwhile.
+ * Not with single-precision inner solves or rr_noise_rhs (RR_ERR_UNSUPPORTED).
+ * RR_ERR_INVALID_ARG for a negative or non-finite weight. */
+rr_status rr_set_row_weights(rr_handle* h, const double* d, rr_stream stream);
+
+/* u = X v, the plain product whatever the row weights: v device double[F]
+ * (caller's feature order), u device double[N]. */
+rr_status rr_apply_rows(rr_handle* h, const double* v, double* u, rr_stream stream);
 
 /* The automatic smoother weight for this lambda (host double).  X >= 0: the
  * Gershgorin weight 1 / max_j (X^T X 1 + lambda)_j / D_j.  X with negative

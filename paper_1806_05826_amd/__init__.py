@@ -107,6 +107,8 @@ _SIGS = {
     "rr_coarse_factor": [_P, C.c_double, _P, _P, _P],
     "rr_coarse_eigen": [_P, _P, _P, _P],
     "rr_noise_rhs": [_P, C.c_double, C.c_double, _P, _P, _P, _P, _P],
+    "rr_set_row_weights": [_P, _P, _P],
+    "rr_apply_rows": [_P, _P, _P, _P],
     "rr_smoother_weight": [_P, C.c_double, C.POINTER(C.c_double)],
     "rr_setup_dense": [C.POINTER(rr_dense), C.POINTER(rr_setup_opts), _P, C.POINTER(_P)],
     "rr_solve_block": [_P, C.c_double, C.c_int32, _P, C.c_int64, _P, C.c_int64,
@@ -409,6 +411,15 @@ def rr_noise_rhs(h, tau, lam, y, xi1, xi2, b, stream=None):
                              _ptr(b), _stream(stream)))
 
 
+def rr_set_row_weights(h, d, stream=None):
+    """d: float64 CUDA tensor of N weights >= 0, or None to clear them."""
+    _check(_lib.rr_set_row_weights(C.c_void_p(h), _ptr(d), _stream(stream)))
+
+
+def rr_apply_rows(h, v, u, stream=None):
+    _check(_lib.rr_apply_rows(C.c_void_p(h), _ptr(v), _ptr(u), _stream(stream)))
+
+
 def rr_coarse_eigen(h, Q, ev, stream=None):
     _check(_lib.rr_coarse_eigen(C.c_void_p(h), _ptr(Q), _ptr(ev), _stream(stream)))
 
@@ -548,6 +559,17 @@ class Ridge:
         ev = torch.empty(fc, dtype=torch.float64, device=self.device)
         rr_coarse_eigen(self.h, Q, ev)
         return Q.view(fc, fc), ev
+
+    def set_row_weights(self, d):
+        """The operator becomes X^T D X + lam I (d: N weights >= 0; None clears)."""
+        rr_set_row_weights(self.h, None if d is None else self._vec(d, self.N))
+
+    def apply_rows(self, v):
+        import torch
+        v = self._vec(v, self.F)
+        out = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        rr_apply_rows(self.h, v, out)
+        return out
 
     def noise_rhs(self, tau, lam, y, xi1, xi2):
         import torch

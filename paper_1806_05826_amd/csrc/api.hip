@@ -171,7 +171,7 @@ void destroy_handle(rr_handle* h) {
   dfree(h->perm); dfree(h->coff); dfree(h->K);
   for (auto& s : h->slots) { dfree(s.L); dfree(s.Ainv); dfree(s.Dinv); }
   dfree(h->boff); dfree(h->bperm); dfree(h->bgram);
-  dfree(h->eig_q); dfree(h->eig_v);
+  dfree(h->eig_q); dfree(h->eig_v); dfree(h->rw);
   dfree(h->chol_work); dfree(h->chol_flag); dfree(h->omega_tmp); dfree(h->mlp_scale);
   if (h->pw) {
     dfree(h->pw->v); dfree(h->pw->t); dfree(h->pw->u); dfree(h->pw->D); dfree(h->pw->vin);
@@ -650,7 +650,7 @@ rr_status precond_two_level(rr_handle* h, Work& w, Prof& pf, int tag, int kind, 
   // z = e2 + w D^-1 (r - A e2), <r,z> -> beta; X e2 = X e1 + X P yc, where
   // u still holds X e1
   if (h->crow.nlayer > 0)
-    launch_cluster_rows(h, w.yc, w.u, done, s);
+    launch_cluster_rows(h, w.yc, w.X.rw, w.u, done, s);
   else
     RR_TRY(op_csr(h, w, pf, tag, w.e2, s));
   if (w.block) {   // rho2 = r - A e2, then z = e2 + w D_B^-1 rho2
@@ -763,6 +763,7 @@ rr_status Solve::begin() {
     return fail(RR_ERR_INVALID_ARG, "the block smoother belongs to the two-level forms");
   if (block && h->nblk == 0)
     return fail(RR_ERR_INVALID_ARG, "no smoother blocks: set up with block_smoother = 1");
+  if (block && w.X.rw) return fail(RR_ERR_UNSUPPORTED, "the block smoother is built for unweighted X");
   w.block = block;
   omega = op.omega;
   if (kind == PK_VCYCLE || kind == PK_ADDITIVE || kind == PK_LEARNED || kind == PK_ROUGHER) {
@@ -778,7 +779,12 @@ rr_status Solve::begin() {
   } else {
     Epi e{};
     e.out = w.b;
-    launch_csc(w.X, rhs, EPI_STORE, e, nullptr, s);
+    if (w.X.rw) {   // weighted least squares: b = X^T D y
+      launch_row_scale(w.X.N, w.X.rw, rhs, w.u, s);
+      launch_csc(w.X, w.u, EPI_STORE, e, nullptr, s);
+    } else {
+      launch_csc(w.X, rhs, EPI_STORE, e, nullptr, s);
+    }
   }
   Scalars& hs = *w.sc_host;
   std::memset(&hs, 0, sizeof(Scalars));
@@ -1147,6 +1153,7 @@ rr_status solve_ir(rr_handle* h, Work& w, double lam, const double* rhs, double*
   if (!rhs || !wout) return fail(RR_ERR_INVALID_ARG, "null rhs or w");
   if (!h->X.binary)
     return fail(RR_ERR_UNSUPPORTED, "single-precision inner solves are built for 0/1 X only");
+  if (h->X.rw) return fail(RR_ERR_UNSUPPORTED, "single-precision inner solves are built for unweighted X");
   const int kind = op.precond;
   if (kind != PK_NONE && kind != PK_JACOBI && kind != PK_VCYCLE)
     return fail(RR_ERR_UNSUPPORTED, "iterative refinement supports the none, Jacobi and V(1,1) preconditioners");
@@ -1589,7 +1596,7 @@ rr_status rr_apply_rhs(rr_handle* h, const double* y, double* b, rr_stream strea
   if (!y || !b) return fail(RR_ERR_INVALID_ARG, "null vector");
   Epi e{};
   e.out = h->w.vout;
-  launch_csc(h->X, y, EPI_STORE, e, nullptr, (hipStream_t)stream);
+  launch_csc(h->X, y, EPI_STORE, e, nullptr, (hipStream_t)stream);   // the plain X^T y, whatever the weights
   launch_gather(b, h->w.vout, h->finv, h->X.F, (hipStream_t)stream);
   RR_HIP(hipGetLastError());
   return RR_OK;
@@ -1599,6 +1606,7 @@ rr_status rr_noise_rhs(rr_handle* h, double tau, double lambda, const double* y,
                        const double* xi2, double* b, rr_stream stream) {
   RR_TRY(check_sparse(h));
   if (!y || !xi1 || !xi2 || !b) return fail(RR_ERR_INVALID_ARG, "null vector");
+  if (h->X.rw) return fail(RR_ERR_UNSUPPORTED, "noise injection is built for unweighted X");
   if (!(tau > 0.0) || !(lambda > 0.0) || !std::isfinite(tau) || !std::isfinite(lambda))
     return fail(RR_ERR_INVALID_ARG, "tau and lambda must be finite and > 0");
   hipStream_t s = (hipStream_t)stream;
@@ -1612,6 +1620,79 @@ rr_status rr_noise_rhs(rr_handle* h, double tau, double lambda, const double* y,
   launch_axpy_out(h->X.F, b, xi2, std::sqrt(lambda) / tau, s);        // + e2 / tau
   RR_HIP(hipStreamSynchronize(s));
   dfree(v);
+  RR_HIP(hipGetLastError());
+  return RR_OK;
+}
+
+__global__ void k_check_weights(int N, const double* d, int* bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N && !(d[i] >= 0.0 && d[i] < __builtin_inf())) *bad = 1;
+}
+
+rr_status rr_set_row_weights(rr_handle* h, const double* d, rr_stream stream) {
+  RR_TRY(check_sparse(h));
+  if (!h->X.binary) return fail(RR_ERR_UNSUPPORTED, "row weights are built for 0/1 X");
+  if (h->nblk > 0) return fail(RR_ERR_UNSUPPORTED, "the block smoother's blocks are built for unweighted X");
+  hipStream_t s = (hipStream_t)stream;
+  const int N = h->X.N, F = h->X.F;
+  if (d) {
+    int* flag = nullptr;
+    RR_HIP(hipMalloc(&flag, sizeof(int)));
+    RR_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+    k_check_weights<<<cdiv(N, kBlock), kBlock, 0, s>>>(N, d, flag);
+    int bad = 0;
+    RR_HIP(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    RR_HIP(hipStreamSynchronize(s));
+    (void)hipFree(flag);
+    if (bad) return fail(RR_ERR_INVALID_ARG, "row weights must be finite and >= 0");
+    if (!h->rw) RR_TRY(dalloc(&h->rw, std::max(1, N)));
+    RR_HIP(hipMemcpyAsync(h->rw, d, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+  }
+  const double* rw = d ? h->rw : nullptr;
+  h->X.rw = rw;
+  h->w.X.rw = rw;
+  for (Work* e : h->extra_sets) e->X.rw = rw;
+  // Jacobi diagonal: c_j = sum_i d_i x_ij (0/1 X), the column pass of d
+  if (rw) {
+    Epi e{};
+    e.out = h->colnorm;
+    launch_csc(h->X, rw, EPI_STORE, e, nullptr, s);
+  } else {
+    k_colnorm_binary<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, h->X.col_ptr, h->colnorm);
+  }
+  // Gershgorin sums g = X^T D X 1
+  launch_fill(h->w.x, 1.0, F, s);
+  launch_csr(h->X, h->w.x, h->w.u, nullptr, s);
+  {
+    Epi e{};
+    e.out = h->gersh;
+    launch_csc(h->X, h->w.u, EPI_STORE, e, nullptr, s);
+  }
+  // the Galerkin coarse matrix of the weighted operator
+  if (h->FC > 0) {
+    RR_TRY(rw ? build_coarse_gram_valued(h, s) : build_coarse_gram(h, s));
+    if (h->eig_q) RR_TRY(coarse_eigen(h, &h->eig_sweeps, s));
+  }
+  // cached per-lambda factors, weights and captured iterations no longer hold
+  for (auto& sl : h->slots) {
+    sl.valid = false;
+    sl.lam = -1.0;
+  }
+  h->w.graph.reset();
+  for (Work* e : h->extra_sets) e->graph.reset();
+  RR_HIP(hipStreamSynchronize(s));
+  RR_HIP(hipGetLastError());
+  return RR_OK;
+}
+
+rr_status rr_apply_rows(rr_handle* h, const double* v, double* u, rr_stream stream) {
+  RR_TRY(check_sparse(h));
+  if (!v || !u) return fail(RR_ERR_INVALID_ARG, "null vector");
+  hipStream_t s = (hipStream_t)stream;
+  Sparse X = h->X;
+  X.rw = nullptr;   // the plain product, whatever the weights
+  launch_gather(h->w.x, v, h->fperm, X.F, s);
+  launch_csr(X, h->w.x, u, nullptr, s);
   RR_HIP(hipGetLastError());
   return RR_OK;
 }

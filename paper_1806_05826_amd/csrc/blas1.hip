@@ -607,4 +607,13 @@ void launch_axpy_out(int F, double* b, const double* xi2, double c, hipStream_t 
   if (F > 0) k_axpy_out<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, b, xi2, c);
 }
 
+// out = D in (row weights), in place allowed.
+__global__ void k_row_scale(int N, const double* __restrict__ rw, const double* in, double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) out[i] = rw[i] * in[i];
+}
+void launch_row_scale(int N, const double* rw, const double* in, double* out, hipStream_t s) {
+  if (N > 0) k_row_scale<<<cdiv(N, kBlock), kBlock, 0, s>>>(N, rw, in, out);
+}
+
 }  // namespace rr

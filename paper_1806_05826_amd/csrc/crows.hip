@@ -33,6 +33,7 @@ __global__ __launch_bounds__(kCrThreads) void k_cluster_rows(int nlayer, const i
                                                              const int* __restrict__ rowid, int FC,
                                                              const double* __restrict__ cscale,
                                                              const double* __restrict__ yc,
+                                                             const double* __restrict__ rw,
                                                              T* __restrict__ u, const int* done) {
   extern __shared__ __align__(8) unsigned char yt_raw[];
   T* yt = reinterpret_cast<T*>(yt_raw);   // [FC + 1]
@@ -66,7 +67,7 @@ __global__ __launch_bounds__(kCrThreads) void k_cluster_rows(int nlayer, const i
       }
     }
   }
-  if (row >= 0) u[row] = u0 + acc;
+  if (row >= 0) u[row] = rw ? u0 + (T)rw[row] * acc : u0 + acc;   // D X P yc with row weights
 }
 
 }  // namespace
@@ -131,18 +132,19 @@ rr_status build_cluster_rows(rr_handle* h, hipStream_t s) {
   return RR_OK;
 }
 
-void launch_cluster_rows(const rr_handle* h, const double* yc, double* u, const int* done, hipStream_t s) {
+void launch_cluster_rows(const rr_handle* h, const double* yc, const double* rw, double* u, const int* done,
+                         hipStream_t s) {
   const ClusterRows& cr = h->crow;
   const int g = cdiv(cr.nlayer, kCrThreads / 64);
   k_cluster_rows<double><<<g, kCrThreads, sizeof(double) * (h->FC + 1), s>>>(
-      cr.nlayer, cr.layer, cr.ent, cr.rowid, h->FC, h->cscale, yc, u, done);
+      cr.nlayer, cr.layer, cr.ent, cr.rowid, h->FC, h->cscale, yc, rw, u, done);
 }
 
 void launch_cluster_rows32(const rr_handle* h, const double* yc, float* u, const int* done, hipStream_t s) {
   const ClusterRows& cr = h->crow;
   const int g = cdiv(cr.nlayer, kCrThreads / 64);
   k_cluster_rows<float><<<g, kCrThreads, sizeof(float) * (h->FC + 1), s>>>(
-      cr.nlayer, cr.layer, cr.ent, cr.rowid, h->FC, h->cscale, yc, u, done);
+      cr.nlayer, cr.layer, cr.ent, cr.rowid, h->FC, h->cscale, yc, nullptr, u, done);
 }
 
 }  // namespace rr

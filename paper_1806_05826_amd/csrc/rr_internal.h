@@ -190,6 +190,8 @@ struct Sparse {
   int* col_ptr = nullptr;   // [F+1]
   int* row_idx = nullptr;   // [nnz]
   double* cval = nullptr;   // [nnz] or null (CSC order)
+  const double* rw = nullptr;   // [N] row weights d (rr_set_row_weights): the row pass
+                                // forms u = D X v, so the operator is X^T D X + lam I
   int csr_group = 16;       // lanes per row in the CSR kernel
   MergePlan csc_plan;       // segments = columns (merge-path form, valued X)
   SellPlan sell_csr;        // u = X v   (0/1 X)
@@ -339,6 +341,7 @@ struct rr_handle {
   rr::MergePlan restrict_plan;  // segments = clusters over perm
   ClusterRows crow;             // label table for the V(1,1) second row pass
   double* K = nullptr;          // [FC*FC] coarse Gram
+  double* rw = nullptr;         // [N] row weights (owned), null when unweighted
   double* eig_q = nullptr;      // [FC*FC] eigenvectors of K (columns), with coarse_eigen
   double* eig_v = nullptr;      // [FC] their eigenvalues
   int eig_sweeps = 0;           // Jacobi sweeps the decomposition took
@@ -397,7 +400,9 @@ inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
 rr_status build_chunk_plan(MergePlan& mp, const int* d_seg_ptr, int nseg, hipStream_t s);
 rr_status build_cluster_rows(rr_handle* h, hipStream_t s);
 void free_cluster_rows(ClusterRows& cr);
-void launch_cluster_rows(const rr_handle* h, const double* yc, double* u, const int* done, hipStream_t s);
+void launch_cluster_rows(const rr_handle* h, const double* yc, const double* rw, double* u, const int* done,
+                         hipStream_t s);
+void launch_row_scale(int N, const double* rw, const double* in, double* out, hipStream_t s);
 void launch_cluster_rows32(const rr_handle* h, const double* yc, float* u, const int* done, hipStream_t s);
 rr_status build_merge_plan(MergePlan& mp, const int* d_seg_end, const int* d_seg_ptr,
                            int nseg, int nnz, hipStream_t s);

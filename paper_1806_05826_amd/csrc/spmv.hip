@@ -68,7 +68,8 @@ void launch_csr(const Sparse& X, const double* v, double* u, const int* done, hi
   if (X.binary && X.N > 0) {
     Epi e{};
     e.out = u;
-    launch_sell(X.sell_csr, v, EPI_STORE, e, done, s, stage, mid);
+    e.scale = X.rw;   // u = D X v with row weights, fused in the reduction's epilogue
+    launch_sell(X.sell_csr, v, X.rw ? EPI_SCALE : EPI_STORE, e, done, s, stage, mid);
     return;
   }
   if (stage) launch_stage_update(*stage, s);
@@ -83,6 +84,7 @@ void launch_csr(const Sparse& X, const double* v, double* u, const int* done, hi
     case 32: csr_dispatch<32>(X, v, u, done, s); break;
     default: csr_dispatch<64>(X, v, u, done, s); break;
   }
+  if (X.rw) launch_row_scale(X.N, X.rw, u, u, s);
   if (mid) (void)hipEventRecord(mid, s);
 }
 
