@@ -375,7 +375,8 @@ rr_status rr_noise_rhs(rr_handle* h, double tau, double lambda, const double* y,
  * b = X^T D y (rr_apply_rhs stays the plain X^T y, as a Newton gradient
  * needs).  The call rebuilds what depends on the
  * operator: the Jacobi diagonal sum_i d_i x_ij + lambda, the Gershgorin sums
- * X^T D X 1, the coarse matrix P^T X^T D X P (F_C operator applications) and,
+ * X^T D X 1, the coarse matrix P^T X^T D X P (from the label table and one
+ * FP64 GEMM through an F_C x N scratch matrix kept by the handle) and,
  * with coarse_eigen, its eigendecomposition; cached per-lambda factors and
  * captured graphs are dropped.  The aggregation P is kept.  0/1 X only,
  * without block-smoother blocks; no solve may run on the handle meanwhile.

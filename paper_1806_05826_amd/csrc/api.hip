@@ -171,7 +171,7 @@ void destroy_handle(rr_handle* h) {
   dfree(h->perm); dfree(h->coff); dfree(h->K);
   for (auto& s : h->slots) { dfree(s.L); dfree(s.Ainv); dfree(s.Dinv); }
   dfree(h->boff); dfree(h->bperm); dfree(h->bgram);
-  dfree(h->eig_q); dfree(h->eig_v); dfree(h->rw);
+  dfree(h->eig_q); dfree(h->eig_v); dfree(h->rw); dfree(h->wxc);
   dfree(h->chol_work); dfree(h->chol_flag); dfree(h->omega_tmp); dfree(h->mlp_scale);
   if (h->pw) {
     dfree(h->pw->v); dfree(h->pw->t); dfree(h->pw->u); dfree(h->pw->D); dfree(h->pw->vin);
@@ -1670,7 +1670,12 @@ rr_status rr_set_row_weights(rr_handle* h, const double* d, rr_stream stream) {
   }
   // the Galerkin coarse matrix of the weighted operator
   if (h->FC > 0) {
-    RR_TRY(rw ? build_coarse_gram_valued(h, s) : build_coarse_gram(h, s));
+    if (!rw)
+      RR_TRY(build_coarse_gram(h, s));
+    else if (h->crow.nlayer > 0)
+      RR_TRY(weighted_gram_from_labels(h, s));
+    else
+      RR_TRY(build_coarse_gram_valued(h, s));
     if (h->eig_q) RR_TRY(coarse_eigen(h, &h->eig_sweeps, s));
   }
   // cached per-lambda factors, weights and captured iterations no longer hold

@@ -72,6 +72,45 @@ __global__ __launch_bounds__(kCrThreads) void k_cluster_rows(int nlayer, const i
 
 }  // namespace
 
+namespace {
+
+// Xc[c][i] = s_c sqrt(d_i) (count of label c in row i): the columns of
+// D^1/2 X P as rows, from the label table; each lane owns its row, so the
+// additions are plain and in a fixed order.
+__global__ __launch_bounds__(kCrThreads) void k_weighted_xc(int nlayer, const int2* __restrict__ layer,
+                                                            const uint16_t* __restrict__ ent,
+                                                            const int* __restrict__ rowid, int FC, int Np,
+                                                            const double* __restrict__ cscale,
+                                                            const double* __restrict__ rw, double* Xc) {
+  const int lane = threadIdx.x & 63;
+  const int L = blockIdx.x * (kCrThreads / 64) + (threadIdx.x >> 6);
+  if (L >= nlayer) return;
+  const int2 d = layer[L];
+  const int row = rowid[(size_t)L * 64 + lane];
+  if (row < 0) return;
+  const double sd = sqrt(rw[row]);
+  for (int k = 0; k < d.y; ++k) {
+    const int c = ent[(size_t)d.x + (size_t)(k / 4) * 256 + (size_t)lane * 4 + k % 4];
+    if (c < FC) Xc[(size_t)c * Np + row] += cscale[c] * sd;
+  }
+}
+
+}  // namespace
+
+// K = P^T X^T D X P = (D^1/2 X P)^T (D^1/2 X P) in one pass over the label
+// table and one FP64 GEMM (setup of row weights).
+rr_status weighted_gram_from_labels(rr_handle* h, hipStream_t s) {
+  const ClusterRows& cr = h->crow;
+  const int FC = h->FC, N = h->X.N;
+  const int FCp = (FC + 127) / 128 * 128, Np = (N + 127) / 128 * 128;
+  const size_t bytes = sizeof(double) * (size_t)FCp * Np;
+  if (!h->wxc) RR_HIP(hipMalloc(&h->wxc, bytes));
+  RR_HIP(hipMemsetAsync(h->wxc, 0, bytes, s));
+  k_weighted_xc<<<cdiv(cr.nlayer, kCrThreads / 64), kCrThreads, 0, s>>>(cr.nlayer, cr.layer, cr.ent, cr.rowid,
+                                                                        FC, Np, h->cscale, h->X.rw, h->wxc);
+  return gram_rows(h->wxc, FC, FCp, Np, h->K, s);
+}
+
 void free_cluster_rows(ClusterRows& cr) {
   if (cr.layer) (void)hipFree(cr.layer);
   if (cr.ent) (void)hipFree(cr.ent);

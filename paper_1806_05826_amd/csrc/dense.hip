@@ -1191,6 +1191,30 @@ rr_status dense_setup(rr_handle* h, const rr_dense* Xin, const rr_setup_opts* o,
 }
 
 // K = (X P)^T (X P): the coarse columns X P (FP64), then one FP64 GEMM.
+// K = Xc Xc^T (fc x fc, ld fc) from Xc (FCp x Np row-major FP64, rows past
+// fc and columns past the data zero; FCp a multiple of 128, Np of 16): one
+// FP64 matrix-core GEMM split over the contraction, partials added in a
+// fixed order.
+rr_status gram_rows(const double* Xc, int fc, int FCp, int Np, double* K, hipStream_t s) {
+  int S = 0, kc = 0;
+  const int tiles = (FCp / GD_M) * cdiv(fc, GD_N);
+  pick_split(tiles, Np, GD_K, &S, &kc);
+  const long long sstride = (long long)FCp * FCp;
+  double* part = nullptr;
+  RR_TRY(zalloc(&part, (size_t)S * sstride));
+  if (FCp % GD_M || Np % GD_K) return fail(RR_ERR_DEVICE, "internal: GEMM shape");
+  dim3 g(cdiv(fc, GD_N), FCp / GD_M, S);
+  k_gemm_f64<double><<<g, 256, 0, s>>>(Xc, Np, Xc, Np, part, FCp, sstride, kc, Np);
+  DEpi e{};
+  e.out = K;
+  e.ld = fc;
+  k_dreduce<EPI_STORE, double><<<dim3(cdiv(fc, 1024), fc), 256, 0, s>>>(fc, part, FCp, sstride, S, e, nullptr);
+  RR_HIP(hipStreamSynchronize(s));
+  RR_HIP(hipGetLastError());
+  zfree(part);
+  return RR_OK;
+}
+
 rr_status dense_coarse_gram(rr_handle* h, hipStream_t s) {
   DenseX& d = *h->dense;
   const int fc = h->FC;
@@ -1199,23 +1223,7 @@ rr_status dense_coarse_gram(rr_handle* h, hipStream_t s) {
   RR_TRY(zalloc(&d.Xc, (size_t)FCp * d.Np));
   k_dense_xc<<<dim3(cdiv(d.N, kBlock), fc), kBlock, 0, s>>>(d.N, d.XT32, d.Np, h->perm, h->coff,
                                                             h->cscale, d.Xc);
-  int S = 0, kc = 0;
-  const int tiles = (FCp / GD_M) * cdiv(fc, GD_N);
-  pick_split(tiles, d.Np, GD_K, &S, &kc);
-  const long long sstride = (long long)FCp * FCp;
-  double* part = nullptr;
-  RR_TRY(zalloc(&part, (size_t)S * sstride));
-  if (FCp % GD_N || d.Np % GD_K) return fail(RR_ERR_DEVICE, "internal: GEMM shape");
-  dim3 g(cdiv(fc, GD_N), FCp / GD_M, S);
-  k_gemm_f64<double><<<g, 256, 0, s>>>(d.Xc, d.Np, d.Xc, d.Np, part, FCp, sstride, kc, d.Np);
-  DEpi e{};
-  e.out = h->K;
-  e.ld = fc;
-  k_dreduce<EPI_STORE, double><<<dim3(cdiv(fc, 1024), fc), 256, 0, s>>>(fc, part, FCp, sstride, S, e, nullptr);
-  RR_HIP(hipStreamSynchronize(s));
-  RR_HIP(hipGetLastError());
-  zfree(part);
-  return RR_OK;
+  return gram_rows(d.Xc, fc, FCp, d.Np, h->K, s);
 }
 
 rr_status dense_apply_one(rr_handle* h, const double* v, double lam, double* t, hipStream_t s) {

@@ -342,6 +342,7 @@ struct rr_handle {
   ClusterRows crow;             // label table for the V(1,1) second row pass
   double* K = nullptr;          // [FC*FC] coarse Gram
   double* rw = nullptr;         // [N] row weights (owned), null when unweighted
+  double* wxc = nullptr;        // [FCp x Np] D^1/2 X P as rows, for the weighted coarse matrix
   double* eig_q = nullptr;      // [FC*FC] eigenvectors of K (columns), with coarse_eigen
   double* eig_v = nullptr;      // [FC] their eigenvalues
   int eig_sweeps = 0;           // Jacobi sweeps the decomposition took
@@ -403,6 +404,8 @@ void free_cluster_rows(ClusterRows& cr);
 void launch_cluster_rows(const rr_handle* h, const double* yc, const double* rw, double* u, const int* done,
                          hipStream_t s);
 void launch_row_scale(int N, const double* rw, const double* in, double* out, hipStream_t s);
+rr_status gram_rows(const double* Xc, int fc, int FCp, int Np, double* K, hipStream_t s);
+rr_status weighted_gram_from_labels(rr_handle* h, hipStream_t s);
 void launch_cluster_rows32(const rr_handle* h, const double* yc, float* u, const int* done, hipStream_t s);
 rr_status build_merge_plan(MergePlan& mp, const int* d_seg_end, const int* d_seg_ptr,
                            int nseg, int nnz, hipStream_t s);
