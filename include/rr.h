@@ -134,6 +134,16 @@ typedef struct {
                               lambda)) Q^T, one GEMM per new lambda instead of
                               a Cholesky factorization (the SVD coarse solver
                               of the Bayesian-regression experiments)          */
+  double lf_tolerance;     /* 0/1 X: > 0 selects leader-follower clustering of
+                              the feature columns instead of k-means (the
+                              aggregation of the paper's experiments): in the
+                              caller's feature order, a feature follows the
+                              nearest earlier leader (ties: the earliest) if
+                              its Euclidean distance is < lf_tolerance, else
+                              it becomes the next leader; leaders are not
+                              updated.  n_clusters is then ignored and
+                              rr_get_centres returns the leaders in creation
+                              order.  At most 38,400 clusters               */
 } rr_setup_opts;
 
 /*

@@ -49,7 +49,8 @@ class rr_setup_opts(C.Structure):
     _fields_ = [("n_clusters", C.c_int32), ("kmeans_max_iter", C.c_int32),
                 ("seed", C.c_uint64), ("labels_in", C.c_void_p), ("n_labels_in", C.c_int32),
                 ("lambda_slots", C.c_int32), ("autotune", C.c_int32),
-                ("block_smoother", C.c_int32), ("coarse_eigen", C.c_int32)]
+                ("block_smoother", C.c_int32), ("coarse_eigen", C.c_int32),
+                ("lf_tolerance", C.c_double)]
 
 
 class rr_setup_info(C.Structure):
@@ -164,7 +165,7 @@ def _dev_f64(t, n=None, name="vector"):
 
 def rr_setup(row_ptr, col_idx, values, n_cols, n_clusters=0, seed=0, kmeans_max_iter=0,
              labels_in=None, n_labels_in=0, lambda_slots=0, autotune=False, block_smoother=False,
-             coarse_eigen=False, stream=None):
+             coarse_eigen=False, lf_tolerance=0.0, stream=None):
     """X is a device CSR: row_ptr/col_idx int32 CUDA tensors, values float64
     CUDA tensor or None (binary).  Returns an opaque handle (int)."""
     import torch
@@ -179,7 +180,7 @@ def rr_setup(row_ptr, col_idx, values, n_cols, n_clusters=0, seed=0, kmeans_max_
                _ptr(values))
     o = rr_setup_opts(int(n_clusters), int(kmeans_max_iter), int(seed) & (2**64 - 1),
                       _ptr(labels_in), int(n_labels_in), int(lambda_slots), 1 if autotune else 0,
-                      1 if block_smoother else 0, 1 if coarse_eigen else 0)
+                      1 if block_smoother else 0, 1 if coarse_eigen else 0, float(lf_tolerance))
     h = C.c_void_p()
     _check(_lib.rr_setup(C.byref(X), C.byref(o), _stream(stream), C.byref(h)))
     return h.value
@@ -453,7 +454,7 @@ class Ridge:
 
     def __init__(self, X, n_clusters=0, seed=0, kmeans_max_iter=0, labels=None, binary=None,
                  lambda_slots=0, autotune=False, block_smoother=False, coarse_eigen=False,
-                 device="cuda"):
+                 lf_tolerance=0.0, device="cuda"):
         import numpy as np
         import torch
         X = X.tocsr()
@@ -471,7 +472,7 @@ class Ridge:
             lab = torch.as_tensor(np.asarray(labels, dtype=np.int32), device=self.device)
             nlab = int(np.max(labels)) + 1 if len(labels) else 1
         self.h = rr_setup(rp, ci, vals, self.F, n_clusters, seed, kmeans_max_iter, lab, nlab,
-                          lambda_slots, autotune, block_smoother, coarse_eigen)
+                          lambda_slots, autotune, block_smoother, coarse_eigen, lf_tolerance)
         torch.cuda.current_stream().synchronize()
         self.info = rr_get_setup_info(self.h)
 

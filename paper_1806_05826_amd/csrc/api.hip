@@ -265,6 +265,12 @@ rr_status setup_impl(const rr_csr* Xin, const rr_setup_opts* o, hipStream_t s, r
   if (o && o->labels_in) {
     if (o->n_labels_in < 1) return fail(RR_ERR_INVALID_ARG, "n_labels_in must be >= 1");
     RR_TRY(set_labels(h, o->labels_in, o->n_labels_in, s));
+  } else if (o && o->lf_tolerance > 0.0) {
+    if (!std::isfinite(o->lf_tolerance)) return fail(RR_ERR_INVALID_ARG, "lf_tolerance must be finite");
+    int fc = 0;
+    RR_TRY(leader_follower(h, o->lf_tolerance, &fc, s));
+    h->n_centres = fc;
+    RR_TRY(set_labels(h, nullptr, fc, s));
   } else if (k > 0) {
     RR_TRY(dalloc(&h->centres, std::min(k, F)));
     const int mi = (o->kmeans_max_iter > 0) ? o->kmeans_max_iter : 100;

@@ -406,6 +406,7 @@ void launch_cluster_rows(const rr_handle* h, const double* yc, const double* rw,
 void launch_row_scale(int N, const double* rw, const double* in, double* out, hipStream_t s);
 rr_status gram_rows(const double* Xc, int fc, int FCp, int Np, double* K, hipStream_t s);
 rr_status weighted_gram_from_labels(rr_handle* h, hipStream_t s);
+rr_status leader_follower(rr_handle* h, double tol, int* fc, hipStream_t s);
 void launch_cluster_rows32(const rr_handle* h, const double* yc, float* u, const int* done, hipStream_t s);
 rr_status build_merge_plan(MergePlan& mp, const int* d_seg_end, const int* d_seg_ptr,
                            int nseg, int nnz, hipStream_t s);
