@@ -266,6 +266,38 @@ def newton_section(rr, torch, dev, log, P, k, steps=5, beta=1.0):
     return {"steps": rows, "beta": beta, "tol": 1e-8}
 
 
+def leader_section(rr, torch, dev, log, P, R, tol=24.0):
+    """Leader-follower aggregation (the paper's experiments' clustering) on
+    the 200,000 x 100,000 workload at distance tolerance `tol`, against the
+    bench's k-means (k = 1000) handle: V(1,1) PCG to relative residual 1e-10
+    at each lambda, iterations and time per solve."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    RL = rr.Ridge(P.X, lf_tolerance=tol, lambda_slots=4)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    y = torch.as_tensor(P.y, dtype=torch.float64, device=dev)
+    w = torch.empty(P.X.shape[1], dtype=torch.float64, device=dev)
+    out = {"tolerance": tol, "n_coarse": RL.info["n_coarse"], "setup_ms": setup_ms,
+           "clustering_ms": RL.info["kmeans_ms"], "per_lambda": {}}
+    for lam in (1e-2, 1.0, 100.0):
+        row = {}
+        for name, H in (("leader_follower", RL), ("kmeans", R)):
+            rr.rr_solve(H.h, lam, y, w, tol=1e-10, precond="vcycle", max_iter=5000, raise_on=(1, 2, 6))
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            st, inf = rr.rr_solve(H.h, lam, y, w, tol=1e-10, precond="vcycle", max_iter=5000, raise_on=(1, 2, 6))
+            torch.cuda.synchronize()
+            row[name] = {"iters": inf["iters"], "ms": (time.perf_counter() - ta) * 1e3}
+        out["per_lambda"][str(lam)] = row
+    RL.close()
+    log(f"[bench leader] tolerance {tol}: F_C={out['n_coarse']}, clustering {out['clustering_ms']:.0f} ms; " +
+        "; ".join(f"lambda={l}: LF {r['leader_follower']['iters']} its {r['leader_follower']['ms']:.1f} ms, "
+                  f"k-means {r['kmeans']['iters']} its {r['kmeans']['ms']:.1f} ms"
+                  for l, r in out["per_lambda"].items()))
+    return out
+
+
 def batched_uneven_section(rr, torch, dev, log, full=False):
     """Independent uneven problems in one rr_solve_batched call against one
     rr_solve call after another: the batched-uneven workload's generator
@@ -588,6 +620,7 @@ def main():
 
     bayes = None if args.no_dense else bayes_section(rr, torch, dev, log, P, R, args.k)
     newton = None if args.no_dense else newton_section(rr, torch, dev, log, P, args.k)
+    lf = None if args.no_dense else leader_section(rr, torch, dev, log, P, R)
     dense = None if args.no_dense else dense_section(rr, torch, dev, log)
     uneven = None if args.no_dense else batched_uneven_section(rr, torch, dev, log)
 
@@ -632,6 +665,7 @@ def main():
         "batched_uneven": uneven,
         "bayes_noise_injection": bayes,
         "newton_logistic": newton,
+        "leader_follower": lf,
         "roofline": {"bound": "hbm", "achieved": gbs_gather, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs_gather / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "rr::k_sell<1> (column-pass gather of t = X^T u through LDS slices)",
