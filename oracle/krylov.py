@@ -128,9 +128,10 @@ def fcg(apply_A, b, apply_B, m=1, tol=1e-10, max_iter=10_000, fixed_iters=None):
 
 def solve(X, y, lam, method="vcycle", labels=None, F_C=None, omega=None,
           tol=1e-10, max_iter=10_000, fixed_iters=None, x_ref=None, rhs_is_b=False,
-          smoother="point"):
+          smoother="point", P=None):
     """Convenience wrapper: b = X^T y (or y itself with ``rhs_is_b``), then
-    PCG with the named preconditioner (point or block smoother)."""
+    PCG with the named preconditioner (point or block smoother; P replaces
+    the adjusted square-root average prolongation when given)."""
     from . import operator as op
     from . import precond
     b = np.asarray(y, dtype=np.float64) if rhs_is_b else op.rhs(X, y)
@@ -140,7 +141,7 @@ def solve(X, y, lam, method="vcycle", labels=None, F_C=None, omega=None,
             omega = precond.block_omega(X, lam, blocks, precond.block_inverses(X, lam, blocks), 0x5eed)
         else:
             omega = op.omega_gershgorin(X, lam)
-    B, _ = precond.make(method, X, lam, labels, F_C, omega, smoother)
+    B, _ = precond.make(method, X, lam, labels, F_C, omega, smoother, P=P)
     return pcg(lambda v: op.apply_A(X, lam, v), b, B, tol, max_iter, fixed_iters, x_ref)
 
 

@@ -35,8 +35,10 @@ drives plain PCG.
 from __future__ import annotations
 
 import numpy as np
+import scipy.sparse as sp
 
 from . import coarse as _coarse
+from . import interp as _interp
 from .operator import apply_A, jacobi_diagonal
 
 
@@ -118,13 +120,17 @@ def cg_rougher(apply_A, r: np.ndarray, steps: int = 2, D=None):
 
 class TwoLevel:
     def __init__(self, X, lam: float, labels: np.ndarray, F_C: int, omega: float,
-                 smoother: str = "point", block_size: int = 32):
+                 smoother: str = "point", block_size: int = 32, P=None):
         self.X = X
         self.lam = float(lam)
         self.D = jacobi_diagonal(X, lam)
         self.omega = float(omega)
-        self.P = _coarse.prolongation(labels, F_C)
-        self.Ac = _coarse.coarse_matrix(X, labels, F_C, lam)
+        if P is None:       # the adjusted square-root average
+            self.P = _coarse.prolongation(labels, F_C)
+            self.Ac = _coarse.coarse_matrix(X, labels, F_C, lam)
+        else:               # any given prolongation (least-squares interpolation)
+            self.P = sp.csr_matrix(P)
+            self.Ac = _interp.galerkin_coarse(X, self.P, lam)
         self.L = _coarse.cholesky(self.Ac)
         self.smoother = smoother
         if smoother == "block":
@@ -156,14 +162,14 @@ class TwoLevel:
         return e1 + self.coarse_correction(rho)
 
 
-def make(kind: str, X, lam: float, labels=None, F_C=None, omega=None, smoother="point"):
+def make(kind: str, X, lam: float, labels=None, F_C=None, omega=None, smoother="point", P=None):
     """Return (apply_B, operator applications per call)."""
     if kind == "none":
         return (lambda r: np.array(r, dtype=np.float64, copy=True)), 0
     D = jacobi_diagonal(X, lam)
     if kind == "jacobi":
         return (lambda r: r / D), 0
-    tl = TwoLevel(X, lam, labels, F_C, omega, smoother)
+    tl = TwoLevel(X, lam, labels, F_C, omega, smoother, P=P)
     if kind == "vcycle":
         return tl.vcycle, 2
     if kind == "additive":
