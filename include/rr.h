@@ -354,7 +354,8 @@ rr_status rr_apply_precond(rr_handle* h, double lambda, int32_t precond, double 
 rr_status rr_coarse_gram(rr_handle* h, double* K, rr_stream stream);
 
 /* The Cholesky factor L (lower, row-major, zeros above the diagonal) of
- * A_c = K + lambda I and A_c^-1, device double[F_C * F_C] each; either may be
+ * A_c = K + lambda P^T P (P^T P = I for the adjusted square-root average,
+ * diagonal under rr_set_interpolation) and A_c^-1, device double[F_C * F_C] each; either may be
  * NULL.  Errors: RR_ERR_BREAKDOWN if A_c is not numerically positive definite.
  * A handle set up with coarse_eigen forms A_c^-1 from the eigendecomposition
  * and no L: it returns RR_ERR_UNSUPPORTED when L is requested. */
@@ -397,6 +398,35 @@ rr_status rr_set_row_weights(rr_handle* h, const double* d, rr_stream stream);
 /* u = X v, the plain product whatever the row weights: v device double[F]
  * (caller's feature order), u device double[N]. */
 rr_status rr_apply_rows(rr_handle* h, const double* v, double* u, rr_stream stream);
+
+/* Least-squares interpolation (the least-squares interpolation subsection):
+ * replaces the adjusted square-root average P by the P whose row j holds one
+ * weight p_j in column labels[j], the minimiser of
+ * sum_k eta_k (v_k(j) - p_j v_k(r))^2, i.e.
+ *   p_j = sum_k eta_k v_k(j) v_k(r) / sum_k eta_k v_k(r)^2,
+ * where r is the coarse feature of j's cluster and
+ * eta_k = <(X^T X + beta I) v_k, v_k> (computed here with the operator).
+ *   V      device double[n_proto * F]: prototype k is V[k*F .. k*F+F-1], in
+ *          the caller's feature order (for instance the leading principal
+ *          components of X^T X); read during the call only.  NULL restores
+ *          the adjusted square-root average.
+ *   n_proto 1..64.  beta >= 0, finite.
+ *   rep    device int32[F_C]: the coarse feature (caller's index) of each
+ *          cluster, which must be a member of it; NULL takes each cluster's
+ *          member of lowest index (the leader under leader-follower).
+ *   p      device double[F] (caller's order) receiving the weights, or NULL.
+ * A cluster whose coarse feature has sum_k eta_k v_k(r)^2 = 0 keeps p_j = 1.
+ * The coarse Gram K = P^T X^T X P is rebuilt with one operator application
+ * per cluster, and A_c = K + lambda diag(P^T P); cached per-lambda factors and
+ * captured graphs are dropped; no solve may run on the handle meanwhile.
+ * The V(1,1) cycle's second row pass then runs as a full pass.  Solves with
+ * the block smoother, the learned coarse correction or single-precision inner
+ * solves return RR_ERR_UNSUPPORTED while it is set, and so do handles with
+ * row weights or coarse_eigen.  RR_ERR_INVALID_ARG for a coarse feature
+ * outside its cluster or prototypes giving non-finite weights (the previous
+ * interpolation then stays). */
+rr_status rr_set_interpolation(rr_handle* h, const double* V, int32_t n_proto, double beta,
+                               const int32_t* rep, double* p, rr_stream stream);
 
 /* The automatic smoother weight for this lambda (host double).  X >= 0: the
  * Gershgorin weight 1 / max_j (X^T X 1 + lambda)_j / D_j.  X with negative

@@ -110,6 +110,7 @@ _SIGS = {
     "rr_noise_rhs": [_P, C.c_double, C.c_double, _P, _P, _P, _P, _P],
     "rr_set_row_weights": [_P, _P, _P],
     "rr_apply_rows": [_P, _P, _P, _P],
+    "rr_set_interpolation": [_P, _P, C.c_int32, C.c_double, _P, _P, _P],
     "rr_smoother_weight": [_P, C.c_double, C.POINTER(C.c_double)],
     "rr_setup_dense": [C.POINTER(rr_dense), C.POINTER(rr_setup_opts), _P, C.POINTER(_P)],
     "rr_solve_block": [_P, C.c_double, C.c_int32, _P, C.c_int64, _P, C.c_int64,
@@ -421,6 +422,15 @@ def rr_apply_rows(h, v, u, stream=None):
     _check(_lib.rr_apply_rows(C.c_void_p(h), _ptr(v), _ptr(u), _stream(stream)))
 
 
+def rr_set_interpolation(h, V, n_proto, beta, rep=None, p=None, stream=None):
+    """V: float64 CUDA tensor of n_proto * F prototype values (prototype k
+    contiguous), or None to restore the adjusted square-root average; rep:
+    int32 CUDA tensor of F_C coarse features or None; p: float64 CUDA tensor
+    of F receiving the weights, or None."""
+    _check(_lib.rr_set_interpolation(C.c_void_p(h), _ptr(V), int(n_proto), float(beta), _ptr(rep),
+                                     _ptr(p), _stream(stream)))
+
+
 def rr_coarse_eigen(h, Q, ev, stream=None):
     _check(_lib.rr_coarse_eigen(C.c_void_p(h), _ptr(Q), _ptr(ev), _stream(stream)))
 
@@ -564,6 +574,23 @@ class Ridge:
     def set_row_weights(self, d):
         """The operator becomes X^T D X + lam I (d: N weights >= 0; None clears)."""
         rr_set_row_weights(self.h, None if d is None else self._vec(d, self.N))
+
+    def set_interpolation(self, V, beta=0.0, rep=None):
+        """Least-squares interpolation from prototypes V (F x K, or None to
+        restore the adjusted square-root average); returns the weights p
+        (F) or None."""
+        import torch
+        if V is None:
+            rr_set_interpolation(self.h, None, 0, 0.0)
+            return None
+        Vt = torch.as_tensor(V, dtype=torch.float64, device=self.device)
+        if Vt.dim() != 2 or Vt.shape[0] != self.F:
+            raise ValueError("V must be F x K")
+        Vk = Vt.t().contiguous()      # prototype k contiguous
+        r = None if rep is None else torch.as_tensor(rep, dtype=torch.int32, device=self.device).contiguous()
+        p = torch.empty(self.F, dtype=torch.float64, device=self.device)
+        rr_set_interpolation(self.h, Vk, Vt.shape[1], beta, r, p)
+        return p
 
     def apply_rows(self, v):
         import torch

@@ -172,6 +172,7 @@ void destroy_handle(rr_handle* h) {
   for (auto& s : h->slots) { dfree(s.L); dfree(s.Ainv); dfree(s.Dinv); }
   dfree(h->boff); dfree(h->bperm); dfree(h->bgram);
   dfree(h->eig_q); dfree(h->eig_v); dfree(h->rw); dfree(h->wxc);
+  free_interpolation(h);
   dfree(h->chol_work); dfree(h->chol_flag); dfree(h->omega_tmp); dfree(h->mlp_scale);
   if (h->pw) {
     dfree(h->pw->v); dfree(h->pw->t); dfree(h->pw->u); dfree(h->pw->D); dfree(h->pw->vin);
@@ -588,9 +589,6 @@ rr_status precond_two_level(rr_handle* h, Work& w, Prof& pf, int tag, int kind, 
                             double* snap = nullptr) {
   const int F = h->X.F;
   const int* done = &w.sc->done;
-  Epi er{};
-  er.scale = h->cscale;
-  er.out = w.c;
   if (kind == PK_ROUGHER) {
     // e1 = rsteps CG steps on A e = r from 0, rho its residual; then
     // z = e1 + P A_c^-1 P^T rho (pre-smoothing only, as in the paper's runs)
@@ -612,22 +610,23 @@ rr_status precond_two_level(rr_handle* h, Work& w, Prof& pf, int tag, int kind, 
       if (i + 1 < w.rsteps) launch_rg_dir(F, w.rho, Dj, w.e2, rr_b, nv, rr_a, nv, w.sc, s);
       std::swap(rr_a, rr_b);
     }
-    launch_segsum(w.rplan, h->coff + 1, h->perm, nullptr, w.rho, EPI_SCALE, er, done, s);
+    launch_restrict(h, w.rplan, w.rho, w.c, done, s);
     launch_gemv(h->FC, sl.Ainv, w.c, w.yc, done, s);
-    launch_prolong(F, h->labels, h->cscale, w.yc, w.e1, z, nullptr, nullptr, 0.0, 0, w.sc, nullptr, s);
+    launch_prolong(F, h->labels, h->cscale, w.yc, w.e1, z, nullptr, nullptr, 0.0, 0, w.sc, nullptr, s,
+                   h->lsw);
     *n_rz = 0;
     return RR_OK;
   }
   if (kind == PK_ADDITIVE) {
     if (stage) launch_stage_update(*stage, s);
-    launch_segsum(w.rplan, h->coff + 1, h->perm, nullptr, r, EPI_SCALE, er, done, s);
+    launch_restrict(h, w.rplan, r, w.c, done, s);
     launch_gemv(h->FC, sl.Ainv, w.c, w.yc, done, s);
     if (w.block) {   // z = w D_B^-1 r + P yc
       *n_rz = launch_block_smooth(h, sl.Dinv, omega, r, nullptr, w.yc, r, z, w.parts.rz, done, s);
       return RR_OK;
     }
     launch_prolong(F, h->labels, h->cscale, w.yc, nullptr, z, r, w.D, omega, 1, w.sc,
-                   w.parts.rz, s);
+                   w.parts.rz, s, h->lsw);
     *n_rz = w.parts.n_vec;
     return RR_OK;
   }
@@ -643,7 +642,7 @@ rr_status precond_two_level(rr_handle* h, Work& w, Prof& pf, int tag, int kind, 
   e.out = w.rho;
   RR_TRY(op_csc(h, w, pf, tag, EPI_RESID, e, s));
   // e2 = e1 + P A_c^-1 P^T rho1 (learned: the network's coarse correction)
-  launch_segsum(w.rplan, h->coff + 1, h->perm, nullptr, w.rho, EPI_SCALE, er, done, s);
+  launch_restrict(h, w.rplan, w.rho, w.c, done, s);
   if (snap) launch_copy_done(snap, w.c, h->FC, done, s);
   if (kind == PK_LEARNED) {
     launch_learned_in(h->FC, w.c, lam, h->mlp.xb, h->mlp_scale, done, s);
@@ -652,10 +651,11 @@ rr_status precond_two_level(rr_handle* h, Work& w, Prof& pf, int tag, int kind, 
   } else {
     launch_gemv(h->FC, sl.Ainv, w.c, w.yc, done, s);
   }
-  launch_prolong(F, h->labels, h->cscale, w.yc, w.e1, w.e2, nullptr, nullptr, 0.0, 0, w.sc, nullptr, s);
+  launch_prolong(F, h->labels, h->cscale, w.yc, w.e1, w.e2, nullptr, nullptr, 0.0, 0, w.sc, nullptr, s,
+                 h->lsw);
   // z = e2 + w D^-1 (r - A e2), <r,z> -> beta; X e2 = X e1 + X P yc, where
-  // u still holds X e1
-  if (h->crow.nlayer > 0)
+  // u still holds X e1 (the label table carries the square-root-average P)
+  if (h->crow.nlayer > 0 && !h->lsw)
     launch_cluster_rows(h, w.yc, w.X.rw, w.u, done, s);
   else
     RR_TRY(op_csr(h, w, pf, tag, w.e2, s));
@@ -770,6 +770,9 @@ rr_status Solve::begin() {
   if (block && h->nblk == 0)
     return fail(RR_ERR_INVALID_ARG, "no smoother blocks: set up with block_smoother = 1");
   if (block && w.X.rw) return fail(RR_ERR_UNSUPPORTED, "the block smoother is built for unweighted X");
+  if (h->lsw && (block || kind == PK_LEARNED))
+    return fail(RR_ERR_UNSUPPORTED,
+                "least-squares interpolation is built for the point smoother and the algebraic coarse solve");
   w.block = block;
   omega = op.omega;
   if (kind == PK_VCYCLE || kind == PK_ADDITIVE || kind == PK_LEARNED || kind == PK_ROUGHER) {
@@ -1059,11 +1062,26 @@ namespace rr {
 
 // ---- coarse Gram matrix of a valued X ---------------------------------------
 
-// v = P e_s: the scaled indicator of cluster s
+// v = P e_s: the scaled indicator of cluster s (per-feature weights pw for
+// least-squares interpolation)
 __global__ void k_cluster_vec(int F, const int* __restrict__ labels, const double* __restrict__ cscale,
-                              int cl, double* __restrict__ v) {
+                              const double* __restrict__ pw, int cl, double* __restrict__ v) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < F) v[j] = (labels[j] == cl) ? cscale[cl] : 0.0;
+  if (j < F) v[j] = (labels[j] == cl) ? (pw ? pw[j] : cscale[cl]) : 0.0;
+}
+
+// c = P^T v: each cluster's sum scaled by 1/sqrt(n_s), or each member
+// weighted by its own p_j (the merge path's per-entry values)
+void launch_restrict(const rr_handle* h, const MergePlan& mp, const double* v, double* out,
+                     const int* done, hipStream_t s) {
+  Epi er{};
+  er.out = out;
+  if (h->lsw) {
+    launch_segsum(mp, h->coff + 1, h->perm, h->lsw_perm, v, EPI_STORE, er, done, s);
+  } else {
+    er.scale = h->cscale;
+    launch_segsum(mp, h->coff + 1, h->perm, nullptr, v, EPI_SCALE, er, done, s);
+  }
 }
 
 // K = P^T X^T X P column by column: K e_s = P^T X^T (X (P e_s)) with the
@@ -1076,15 +1094,12 @@ rr_status build_coarse_gram_valued(rr_handle* h, hipStream_t s) {
   RR_TRY(dalloc(&u, N));
   RR_TRY(dalloc(&t, F));
   for (int c = 0; c < fc; ++c) {
-    k_cluster_vec<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, h->labels, h->cscale, c, v);
+    k_cluster_vec<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, h->labels, h->cscale, h->lsw, c, v);
     launch_csr(h->X, v, u, nullptr, s);
     Epi e{};
     e.out = t;
     launch_csc(h->X, u, EPI_STORE, e, nullptr, s);
-    Epi er{};
-    er.scale = h->cscale;
-    er.out = h->K + (size_t)c * fc;
-    launch_segsum(h->restrict_plan, h->coff + 1, h->perm, nullptr, t, EPI_SCALE, er, nullptr, s);
+    launch_restrict(h, h->restrict_plan, t, h->K + (size_t)c * fc, nullptr, s);
   }
   RR_HIP(hipStreamSynchronize(s));
   RR_HIP(hipGetLastError());
@@ -1160,6 +1175,9 @@ rr_status solve_ir(rr_handle* h, Work& w, double lam, const double* rhs, double*
   if (!h->X.binary)
     return fail(RR_ERR_UNSUPPORTED, "single-precision inner solves are built for 0/1 X only");
   if (h->X.rw) return fail(RR_ERR_UNSUPPORTED, "single-precision inner solves are built for unweighted X");
+  if (h->lsw)
+    return fail(RR_ERR_UNSUPPORTED,
+                "single-precision inner solves use the adjusted square-root average interpolation");
   const int kind = op.precond;
   if (kind != PK_NONE && kind != PK_JACOBI && kind != PK_VCYCLE)
     return fail(RR_ERR_UNSUPPORTED, "iterative refinement supports the none, Jacobi and V(1,1) preconditioners");
@@ -1639,6 +1657,7 @@ rr_status rr_set_row_weights(rr_handle* h, const double* d, rr_stream stream) {
   RR_TRY(check_sparse(h));
   if (!h->X.binary) return fail(RR_ERR_UNSUPPORTED, "row weights are built for 0/1 X");
   if (h->nblk > 0) return fail(RR_ERR_UNSUPPORTED, "the block smoother's blocks are built for unweighted X");
+  if (h->lsw) return fail(RR_ERR_UNSUPPORTED, "row weights with least-squares interpolation are not built");
   hipStream_t s = (hipStream_t)stream;
   const int N = h->X.N, F = h->X.F;
   if (d) {
@@ -1685,6 +1704,32 @@ rr_status rr_set_row_weights(rr_handle* h, const double* d, rr_stream stream) {
     if (h->eig_q) RR_TRY(coarse_eigen(h, &h->eig_sweeps, s));
   }
   // cached per-lambda factors, weights and captured iterations no longer hold
+  for (auto& sl : h->slots) {
+    sl.valid = false;
+    sl.lam = -1.0;
+  }
+  h->w.graph.reset();
+  for (Work* e : h->extra_sets) e->graph.reset();
+  RR_HIP(hipStreamSynchronize(s));
+  RR_HIP(hipGetLastError());
+  return RR_OK;
+}
+
+rr_status rr_set_interpolation(rr_handle* h, const double* V, int32_t n_proto, double beta,
+                               const int32_t* rep, double* p, rr_stream stream) {
+  g_last_error.clear();
+  RR_TRY(check_sparse(h));
+  if (h->FC == 0) return fail(RR_ERR_INVALID_ARG, "no aggregation (n_clusters = 0)");
+  if (V && (n_proto < 1 || n_proto > 64))
+    return fail(RR_ERR_INVALID_ARG, "n_proto must lie in [1, 64]");
+  if (V && !(beta >= 0.0 && beta < __builtin_inf()))
+    return fail(RR_ERR_INVALID_ARG, "beta must be finite and non-negative");
+  if (h->X.rw) return fail(RR_ERR_UNSUPPORTED, "least-squares interpolation with row weights is not built");
+  if (h->eig_q)
+    return fail(RR_ERR_UNSUPPORTED, "the coarse eigendecomposition assumes P^T P = I");
+  hipStream_t s = (hipStream_t)stream;
+  RR_TRY(set_interpolation(h, V, n_proto, beta, rep, p, s));
+  // cached per-lambda factors and captured iterations no longer hold
   for (auto& sl : h->slots) {
     sl.valid = false;
     sl.lam = -1.0;
@@ -1750,6 +1795,7 @@ rr_status rr_apply_precond(rr_handle* h, double lambda, int32_t precond, double 
   if (precond == PK_VCYCLE) k_smooth<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, w.vin, w.D, omega, w.e1);
   Prof pf;
   int nrz = 0;
+  w.block = false;   // this call applies the point smoother, whatever the last solve used
   RR_TRY(precond_two_level(h, w, pf, 0, precond, lambda, omega, *sl, w.vin, w.vout, nullptr, &nrz, s));
   launch_gather(z, w.vout, h->finv, F, s);
   RR_HIP(hipStreamSynchronize(s));

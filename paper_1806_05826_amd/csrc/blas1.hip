@@ -234,9 +234,12 @@ void launch_finish_true(Scalars* sc, const double* parts, int n, hipStream_t s) 
 }
 
 // Prolongation: out = e1 + P yc (V-cycle), or the additive form
-// z = w D^-1 r + P yc with partials of <r,z>.
+// z = w D^-1 r + P yc with partials of <r,z>.  P(j, s) is cscale[s] (adjusted
+// square-root average) or, with pw, the feature's own weight pw[j]
+// (least-squares interpolation).
 __global__ __launch_bounds__(kBlock) void k_prolong(int F, const int* __restrict__ labels,
                                                     const double* __restrict__ cscale,
+                                                    const double* __restrict__ pw,
                                                     const double* __restrict__ yc,
                                                     const double* __restrict__ e1,
                                                     double* __restrict__ out,
@@ -256,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(int F, const int* __restrict
   if (sc && sc->done) return;
   double v = 0.0;
   auto entry = [&](int j, int s, double a, double dj) {
-    const double corr = cscale[s] * yc[s];
+    const double corr = (pw ? pw[j] : cscale[s]) * yc[s];
     if (additive) {
       const double zj = (omega * a) / dj + corr;
       out[j] = zj;
@@ -274,8 +277,8 @@ __global__ __launch_bounds__(kBlock) void k_prolong(int F, const int* __restrict
 void launch_prolong(int F, const int* labels, const double* cscale, const double* yc,
                     const double* e1, double* out, const double* r, const double* D,
                     double omega, int additive, const Scalars* sc, double* parts_rz,
-                    hipStream_t s) {
-  k_prolong<<<vec_grid(F), kBlock, 0, s>>>(F, labels, cscale, yc, e1, out, r, D, omega,
+                    hipStream_t s, const double* pw) {
+  k_prolong<<<vec_grid(F), kBlock, 0, s>>>(F, labels, cscale, pw, yc, e1, out, r, D, omega,
                                            additive, sc, parts_rz);
 }
 

@@ -1,5 +1,6 @@
 // Coarse level per lambda: A_c = K + lambda I (the Galerkin coarse matrix
-// P^T A P = X_c^T X_c + lambda I, since P^T P = I), its Cholesky factor L
+// P^T A P = X_c^T X_c + lambda I, since P^T P = I; with least-squares
+// interpolation P^T P is the diagonal G and A_c = K + lambda G), its Cholesky factor L
 // (the coarse solver of the paper's experiments) and A_c^-1 = L^-T L^-1,
 // kept explicitly so that each coarse solve is one matrix-vector product on
 // the whole GPU instead of two sequential triangular solves.  All FP64.
@@ -11,11 +12,12 @@ namespace rr {
 
 constexpr int NB = 32;   // Cholesky panel width
 
-__global__ void k_form_ac(int n, const double* __restrict__ K, double lam, double* __restrict__ A) {
+__global__ void k_form_ac(int n, const double* __restrict__ K, double lam, const double* __restrict__ g,
+                          double* __restrict__ A) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (long long)n * n) return;
   const int r = (int)(i / n), c = (int)(i % n);
-  A[i] = K[i] + (r == c ? lam : 0.0);
+  A[i] = K[i] + (r == c ? (g ? lam * g[r] : lam) : 0.0);
 }
 
 // Unblocked Cholesky of the nb x nb diagonal block at (k0, k0), in LDS.
@@ -384,7 +386,7 @@ rr_status coarse_factor(rr_handle* h, double lam, LambdaSlot& slot, hipStream_t 
   const long long nn = (long long)n * n;
   double* A = h->chol_work;
   RR_HIP(hipMemsetAsync(h->chol_flag, 0, sizeof(int), s));
-  k_form_ac<<<cdiv(nn, kBlock), kBlock, 0, s>>>(n, h->K, lam, A);
+  k_form_ac<<<cdiv(nn, kBlock), kBlock, 0, s>>>(n, h->K, lam, h->pgram, A);
   for (int k0 = 0; k0 < n; k0 += NB) {
     const int nb = std::min(NB, n - k0);
     k_potrf_diag<<<1, kBlock, 0, s>>>(A, n, k0, nb, h->chol_flag);

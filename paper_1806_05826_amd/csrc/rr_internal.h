@@ -346,6 +346,10 @@ struct rr_handle {
   double* eig_q = nullptr;      // [FC*FC] eigenvectors of K (columns), with coarse_eigen
   double* eig_v = nullptr;      // [FC] their eigenvalues
   int eig_sweeps = 0;           // Jacobi sweeps the decomposition took
+  // least-squares interpolation: P(j, labels[j]) = lsw[j] instead of cscale
+  double* lsw = nullptr;        // [F] null: the adjusted square-root average
+  double* lsw_perm = nullptr;   // [F] lsw in perm order (restriction values)
+  double* pgram = nullptr;      // [FC] diagonal of P^T P
   std::deque<rr::LambdaSlot> slots;
   unsigned long long stamp = 0;
   double* chol_work = nullptr;  // [FC*FC] scratch for the factorization
@@ -476,7 +480,7 @@ void launch_fcg_update(int F, double* x, double* r, const double* p, const doubl
 void launch_prolong(int F, const int* labels, const double* cscale, const double* yc,
                     const double* e1, double* out, const double* r, const double* D,
                     double omega, int additive, const Scalars* sc, double* parts_rz,
-                    hipStream_t s);
+                    hipStream_t s, const double* pw = nullptr);
 void launch_fill(double* x, double v, long long n, hipStream_t s);
 // ---- single-precision inner solves (mixed.hip) -------------------------------
 void launch_ir_init(int F, const double* r64, const double* colnorm, double lam, double omega,
@@ -530,6 +534,13 @@ rr_status run_kmeans(rr_handle* h, int k, uint64_t seed, int max_iter, hipStream
 rr_status set_labels(rr_handle* h, const int* labels_in, int nlab, hipStream_t s);
 rr_status build_coarse_gram(rr_handle* h, hipStream_t s);
 rr_status build_coarse_gram_valued(rr_handle* h, hipStream_t s);   // (api.hip)
+// c = P^T v over the restriction plan mp (either interpolation)  (api.hip)
+void launch_restrict(const rr_handle* h, const MergePlan& mp, const double* v, double* out,
+                     const int* done, hipStream_t s);
+// least-squares interpolation weights from prototypes  (interp.hip)
+rr_status set_interpolation(rr_handle* h, const double* V, int nproto, double beta, const int* rep,
+                            double* p_out, hipStream_t s);
+void free_interpolation(rr_handle* h);
 
 // ---- CG rougher (blas1.hip) --------------------------------------------------------
 // With D non-null the steps are Jacobi-preconditioned (z = D^-1 res).
