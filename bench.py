@@ -290,11 +290,49 @@ def leader_section(rr, torch, dev, log, P, R, tol=24.0):
             torch.cuda.synchronize()
             row[name] = {"iters": inf["iters"], "ms": (time.perf_counter() - ta) * 1e3}
         out["per_lambda"][str(lam)] = row
+    out["least_squares"] = ls_interp_part(rr, torch, dev, RL, y, w)
     RL.close()
     log(f"[bench leader] tolerance {tol}: F_C={out['n_coarse']}, clustering {out['clustering_ms']:.0f} ms; " +
         "; ".join(f"lambda={l}: LF {r['leader_follower']['iters']} its {r['leader_follower']['ms']:.1f} ms, "
                   f"k-means {r['kmeans']['iters']} its {r['kmeans']['ms']:.1f} ms"
                   for l, r in out["per_lambda"].items()))
+    ls = out["least_squares"]
+    log(f"[bench leader] least-squares interpolation ({ls['prototypes']} principal components): " +
+        "; ".join(f"lambda={l}: {r['iters']} its {r['ms']:.1f} ms (weights + coarse Gram {r['set_ms']:.0f} ms)"
+                  for l, r in ls["per_lambda"].items()))
+    return out
+
+
+def ls_interp_part(rr, torch, dev, RL, y, w, n_proto=8, sweeps=30):
+    """Least-squares interpolation on the leader-follower aggregation of
+    RL.  The prototypes are the n_proto leading principal components of
+    X^T X, from `sweeps` steps of subspace iteration (products through
+    rr_apply_operator, orthonormalisation on the host) before any timing;
+    rr_set_interpolation then runs at beta = lambda for every lambda, and a
+    V(1,1) PCG solve to relative residual 1e-10 follows."""
+    import numpy as np
+    F = RL.F
+    Q = np.linalg.qr(np.random.default_rng(5826).standard_normal((F, n_proto)))[0]
+    for _ in range(sweeps):
+        Qd = torch.as_tensor(Q, device=dev)
+        Z = np.stack([RL.apply_operator(0.0, Qd[:, k].contiguous()).cpu().numpy()
+                      for k in range(n_proto)], axis=1)
+        Q = np.linalg.qr(Z)[0]
+    out = {"prototypes": n_proto, "subspace_sweeps": sweeps, "per_lambda": {}}
+    for lam in (1e-2, 1.0, 100.0):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        RL.set_interpolation(Q, lam)
+        torch.cuda.synchronize()
+        set_ms = (time.perf_counter() - t0) * 1e3
+        rr.rr_solve(RL.h, lam, y, w, tol=1e-10, precond="vcycle", max_iter=5000, raise_on=(1, 2, 6))
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        st, inf = rr.rr_solve(RL.h, lam, y, w, tol=1e-10, precond="vcycle", max_iter=5000, raise_on=(1, 2, 6))
+        torch.cuda.synchronize()
+        out["per_lambda"][str(lam)] = {"iters": inf["iters"], "ms": (time.perf_counter() - ta) * 1e3,
+                                       "set_ms": set_ms, "converged": bool(inf["status"] == 0)}
+    RL.set_interpolation(None)
     return out
 
 

@@ -27,6 +27,8 @@ precond     z = B r for CG (none), Jacobi, the two-level V(1,1) cycle and the
 krylov      PCG and flexible CG with truncation
 refine      iterative refinement around a lower-precision inner solve
 mlp         the learned coarse-correction network (forward, backward, loss)
+leader      leader-follower clustering of the feature columns
+interp      least-squares interpolation weights from prototype vectors
 
 Every function is pinned by tests under ``tests/`` that check it against
 closed forms, brute force, invariants or library routines.
