@@ -156,13 +156,14 @@ def reference_solution(X, y, lam, rhs_is_b=False):
 
 
 def solve_tlfcg(X, y, lam, labels, F_C, m=1, steps=2, tol=1e-10, max_iter=10_000,
-                fixed_iters=None, rhs_is_b=False, jacobi=False):
+                fixed_iters=None, rhs_is_b=False, jacobi=False, P=None):
     """Flexible CG (truncation m) with the two-level preconditioner whose
     pre-smoother is `steps` iterations of CG (Jacobi-preconditioned with
-    `jacobi`): the configuration of the paper's experiments."""
+    `jacobi`): the configuration of the paper's experiments.  P replaces the
+    adjusted square-root average prolongation when given."""
     from . import operator as op
     from . import precond
     b = np.asarray(y, dtype=np.float64) if rhs_is_b else op.rhs(X, y)
-    tl = precond.TwoLevel(X, lam, labels, F_C, omega=0.0)
+    tl = precond.TwoLevel(X, lam, labels, F_C, omega=0.0, P=P)
     return fcg(lambda v: op.apply_A(X, lam, v), b, lambda r, i: tl.rougher(r, steps, jacobi), m=m, tol=tol,
                max_iter=max_iter, fixed_iters=fixed_iters)

@@ -94,6 +94,51 @@ def test_precond_and_solves(rr):
     R.close()
 
 
+def test_tlfcg_with_least_squares_interpolation(rr):
+    """The paper's configuration (flexible CG, two CG pre-smoothing steps)
+    on the least-squares prolongation: early iterates to rounding, and the
+    natural stop within 2 iterations or 5 % of the oracle's count."""
+    Pb = datagen.sparse_problem(3001, 1237, 7, seed=77)
+    X, y = Pb.X, Pb.y
+    lab, fc, _ = leader.leader_follower(X, 3.0)
+    V = principal(X, 4)
+    lam = 1.0
+    eta = interp.prototype_energies(X, V, lam)
+    Pm = interp.ls_prolongation(lab, fc, interp.ls_weights(V, eta, lab, fc,
+                                                            interp.representatives(lab, fc)))
+    R = rr.Ridge(X, lf_tolerance=3.0)
+    R.set_interpolation(V, lam)
+    x3, _ = krylov.solve_tlfcg(X, y, lam, lab, fc, fixed_iters=3, P=Pm)
+    w, info = R.solve(lam, y, precond="rougher", krylov="fcg", fcg_m=1, fixed_iters=3)
+    assert np.linalg.norm(host(w) - x3) <= 1e-10 * np.linalg.norm(x3)
+    _, inf = krylov.solve_tlfcg(X, y, lam, lab, fc, tol=1e-10, P=Pm)
+    w, info = R.solve(lam, y, precond="rougher", krylov="fcg", fcg_m=1, tol=1e-10)
+    assert info["status"] == 0 and info["true_relres"] <= 1e-9
+    assert abs(info["iters"] - inf.iters) <= max(2, inf.iters // 20)
+    R.close()
+
+
+def test_graph_replays_equal_eager(rr):
+    """Captured iterations with the least-squares restriction and
+    prolongation replay bitwise equal to eager runs; changing the
+    interpolation drops the captured graphs."""
+    P = datagen.sparse_problem(3001, 1237, 7, seed=77)
+    R = rr.Ridge(P.X, lf_tolerance=3.0)
+    R.set_interpolation(principal(P.X, 4), 1.0)
+    for rep in range(3):
+        for lam in (0.1, 1.0):
+            we, ie = R.solve(lam, P.y, precond="vcycle", tol=1e-10, chunk=4)
+            wg, ig = R.solve(lam, P.y, precond="vcycle", tol=1e-10, chunk=4, graph=True)
+            assert ie["iters"] == ig["iters"] and ie["status"] == ig["status"] == 0
+            assert np.array_equal(host(we), host(wg)), (rep, lam)
+            R.apply_operator(lam, np.ones(P.X.shape[1]))
+    R.set_interpolation(None)
+    we, ie = R.solve(1.0, P.y, precond="vcycle", tol=1e-10, chunk=4)
+    wg, ig = R.solve(1.0, P.y, precond="vcycle", tol=1e-10, chunk=4, graph=True)
+    assert np.array_equal(host(we), host(wg))
+    R.close()
+
+
 def test_caller_representatives_and_restore(rr):
     P = datagen.tiny_sparse()
     X = P.X
