@@ -139,6 +139,25 @@ def test_graph_replays_equal_eager(rr):
     R.close()
 
 
+def test_batched_lambdas_on_one_handle(rr):
+    """Several lambdas in one rr_solve_batched call (one work set each, with
+    its own restriction buffers) equal one rr_solve after another."""
+    P = datagen.sparse_problem(3001, 1237, 7, seed=77)
+    R = rr.Ridge(P.X, lf_tolerance=3.0)
+    R.set_interpolation(principal(P.X, 4), 1.0)
+    lams = [0.1, 1.0, 10.0]
+    y = torch.as_tensor(P.y, dtype=torch.float64, device="cuda")
+    ws = [torch.empty(P.X.shape[1], dtype=torch.float64, device="cuda") for _ in lams]
+    st, infos = rr.rr_solve_batched([R.h] * len(lams), lams, [y] * len(lams), ws, tol=1e-10,
+                                    precond="vcycle")
+    assert st == 0
+    for lam, w, inf in zip(lams, ws, infos):
+        w1, inf1 = R.solve(lam, P.y, precond="vcycle", tol=1e-10)
+        assert inf["status"] == 0 and inf["iters"] == inf1["iters"]
+        assert np.array_equal(host(w), host(w1)), lam
+    R.close()
+
+
 def test_caller_representatives_and_restore(rr):
     P = datagen.tiny_sparse()
     X = P.X
