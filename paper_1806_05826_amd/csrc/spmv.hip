@@ -272,11 +272,12 @@ __global__ __launch_bounds__(kBlock) void k_segfix(const int4* __restrict__ span
 // chunk of at most kChunk entries (lane l adds entries l, l + 64, ... in
 // order, then a fixed butterfly); a segment's only chunk finishes it, the
 // chunks of longer segments leave partials that one wave per such segment
-// adds in chunk order (k_chunk_fin).
+// adds in chunk order (k_chunk_fin).  With VAL, entry e adds v[idx[e]] * val[e].
 constexpr int kChunk = 256;
-template <int MODE>
+template <int MODE, bool VAL>
 __global__ __launch_bounds__(kBlock) void k_chunk_sum(const int4* __restrict__ chunk, int nchunk,
                                                       const int* __restrict__ idx,
+                                                      const double* __restrict__ val,
                                                       const double* __restrict__ v,
                                                       double* __restrict__ cpart, Epi e,
                                                       const int* done) {
@@ -289,8 +290,16 @@ __global__ __launch_bounds__(kBlock) void k_chunk_sum(const int4* __restrict__ c
 #pragma unroll
   for (int k = 0; k < kChunk / 64; ++k) j[k] = (c.y + lane + 64 * k < c.z) ? idx[c.y + lane + 64 * k] : -1;
   double t = 0.0;
+  if constexpr (VAL) {
+    double a[kChunk / 64];
 #pragma unroll
-  for (int k = 0; k < kChunk / 64; ++k) t += (j[k] >= 0) ? v[j[k]] : 0.0;
+    for (int k = 0; k < kChunk / 64; ++k) a[k] = (j[k] >= 0) ? val[c.y + lane + 64 * k] : 0.0;
+#pragma unroll
+    for (int k = 0; k < kChunk / 64; ++k) t += (j[k] >= 0) ? v[j[k]] * a[k] : 0.0;
+  } else {
+#pragma unroll
+    for (int k = 0; k < kChunk / 64; ++k) t += (j[k] >= 0) ? v[j[k]] : 0.0;
+  }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
   if (lane == 0) {
@@ -323,10 +332,14 @@ __global__ __launch_bounds__(kBlock) void k_chunk_fin(const int4* __restrict__ f
 }
 
 template <int MODE>
-static void chunk_mode(const MergePlan& mp, const int* idx, const double* v, const Epi& e,
-                       const int* done, hipStream_t s) {
-  k_chunk_sum<MODE><<<cdiv(mp.nchunk, kBlock / 64), kBlock, 0, s>>>(mp.chunk, mp.nchunk, idx, v,
-                                                                    mp.cpart, e, done);
+static void chunk_mode(const MergePlan& mp, const int* idx, const double* val, const double* v,
+                       const Epi& e, const int* done, hipStream_t s) {
+  if (val)
+    k_chunk_sum<MODE, true><<<cdiv(mp.nchunk, kBlock / 64), kBlock, 0, s>>>(mp.chunk, mp.nchunk, idx,
+                                                                          val, v, mp.cpart, e, done);
+  else
+    k_chunk_sum<MODE, false><<<cdiv(mp.nchunk, kBlock / 64), kBlock, 0, s>>>(
+        mp.chunk, mp.nchunk, idx, nullptr, v, mp.cpart, e, done);
   if (mp.nfin > 0)
     k_chunk_fin<MODE><<<cdiv(mp.nfin, kBlock / 64), kBlock, 0, s>>>(mp.fin, mp.nfin, mp.cpart, e,
                                                                     done);
@@ -377,12 +390,12 @@ int launch_csc(const Sparse& X, const double* u, int mode, const Epi& e, const i
 int launch_segsum(const MergePlan& mp, const int* seg_end, const int* idx, const double* val,
                   const double* v, int mode, const Epi& e, const int* done, hipStream_t s) {
   if (mp.nblocks == 0) return 0;
-  if (mp.nchunk > 0 && !val) {
+  if (mp.nchunk > 0) {
     switch (mode) {
-      case EPI_STORE: chunk_mode<EPI_STORE>(mp, idx, v, e, done, s); return 0;
-      case EPI_APPLY: chunk_mode<EPI_APPLY>(mp, idx, v, e, done, s); return 0;
-      case EPI_RESID: chunk_mode<EPI_RESID>(mp, idx, v, e, done, s); return 0;
-      case EPI_SCALE: chunk_mode<EPI_SCALE>(mp, idx, v, e, done, s); return 0;
+      case EPI_STORE: chunk_mode<EPI_STORE>(mp, idx, val, v, e, done, s); return 0;
+      case EPI_APPLY: chunk_mode<EPI_APPLY>(mp, idx, val, v, e, done, s); return 0;
+      case EPI_RESID: chunk_mode<EPI_RESID>(mp, idx, val, v, e, done, s); return 0;
+      case EPI_SCALE: chunk_mode<EPI_SCALE>(mp, idx, val, v, e, done, s); return 0;
       default: break;   // epilogues with a dot product take the merge path
     }
   }
