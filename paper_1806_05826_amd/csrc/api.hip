@@ -1728,14 +1728,15 @@ rr_status rr_set_interpolation(rr_handle* h, const double* V, int32_t n_proto, d
   if (h->eig_q)
     return fail(RR_ERR_UNSUPPORTED, "the coarse eigendecomposition assumes P^T P = I");
   hipStream_t s = (hipStream_t)stream;
-  RR_TRY(set_interpolation(h, V, n_proto, beta, rep, p, s));
-  // cached per-lambda factors and captured iterations no longer hold
+  // cached per-lambda factors and captured iterations no longer hold (dropped
+  // first, so that a failure part-way leaves none behind)
   for (auto& sl : h->slots) {
     sl.valid = false;
     sl.lam = -1.0;
   }
   h->w.graph.reset();
   for (Work* e : h->extra_sets) e->graph.reset();
+  RR_TRY(set_interpolation(h, V, n_proto, beta, rep, p, s));
   RR_HIP(hipStreamSynchronize(s));
   RR_HIP(hipGetLastError());
   return RR_OK;
