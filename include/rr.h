@@ -17,6 +17,13 @@
  *   - the Krylov iteration: PCG from x0 = 0, r0 = b, stopped on the
  *     relative residual (initialisation of the flexible CG algorithm; the
  *     residual plotted in the experiments).
+ * Beside these: flexible CG with the CG pre-smoother of the experiments
+ * (TLFCG), leader-follower clustering (clustering section), least-squares
+ * interpolation of prototype vectors (rr_set_interpolation), the
+ * eigendecomposition of the coarse Gram matrix for many lambda and the
+ * noise-injection right-hand side of Bayesian regression (rr_coarse_eigen,
+ * rr_noise_rhs), the weighted operator X^T D X + beta I of Newton steps
+ * (rr_set_row_weights), and a learned coarse correction (rr_mlp_*).
  *
  * Conventions for every entry point:
  *   - Every call returns rr_status; RR_OK (0) on success.  On any other
@@ -32,8 +39,17 @@
  *     the caller's column order; N-vectors by sample.
  *   - A handle is not thread-safe: one call at a time per handle.  Several
  *     handles may be used concurrently on different streams.
- *   - Device memory for a handle is allocated by rr_setup and released by
- *     rr_destroy; rr_solve and the step-level calls allocate nothing.
+ *   - Device memory for a handle is allocated by rr_setup (rr_setup_dense)
+ *     and released by rr_destroy.  Some buffers are allocated on first use
+ *     and kept until rr_destroy: further work sets of rr_solve_batched, the
+ *     FCG direction ring, the FP32 vectors of single-precision inner
+ *     solves, the power-iteration buffers of the smoother weight, an extra
+ *     per-lambda factor slot while every cached one is in use by a running
+ *     solve, and the weights of rr_set_row_weights and
+ *     rr_set_interpolation.  Repeating a solve of a kind the handle has
+ *     already run allocates nothing; the set-up calls (rr_set_row_weights,
+ *     rr_set_interpolation, rr_collect_pairs, rr_mlp_init, rr_mlp_train)
+ *     may also allocate and free temporaries.
  */
 #ifndef RR_H
 #define RR_H
