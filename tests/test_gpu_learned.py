@@ -105,6 +105,39 @@ def test_backward_matches_oracle(rr, tiny):
         assert err <= tol, (k, err, tol)
 
 
+def test_adam_steps_match_oracle(rr, tiny):
+    """rr_mlp_train on one pair takes one Adam step per epoch.  The gradient
+    of a single pair has no batch sum, so rr_mlp_backward gives the very
+    gradient the step uses; the oracle's FP64 Adam applied to it must give
+    the GPU's FP32 weights after every step, within FP32 rounding of the
+    update (relative 1e-5 of lr per step) and of the weight itself."""
+    P, R = tiny
+    rr.rr_mlp_init(R.h, hidden=32, seed=13)          # fresh Adam state
+    npar, n_in, n_out = rr.rr_mlp_size(R.h)
+    rng = np.random.default_rng(3)
+    X = cuda32(rng.standard_normal((1, n_in)))
+    T = cuda32(rng.standard_normal((1, n_out)))
+    lr = 1e-3
+    p = {"theta": rr.rr_mlp_get_weights(R.h).astype(np.float64)}
+    opt = mlp.Adam(p, lr=lr)
+    out = torch.empty((1, n_out), dtype=torch.float32, device="cuda")
+    grads = torch.empty(npar, dtype=torch.float32, device="cuda")
+    moved = 0
+    for t in range(1, 6):
+        rr.rr_mlp_forward(R.h, X, out)
+        rr.rr_mlp_backward(R.h, X, (out - T).contiguous(), grads)
+        g = host(grads).astype(np.float64)
+        before = p["theta"].copy()
+        rr.rr_mlp_train(R.h, X, T, epochs=1, batch=1, lr=lr, seed=t)
+        opt.step(p, {"theta": g})
+        got = rr.rr_mlp_get_weights(R.h).astype(np.float64)
+        tol = t * 1e-5 * lr + 4 * np.spacing(np.abs(p["theta"]).astype(np.float32)).astype(np.float64)
+        assert np.all(np.abs(got - p["theta"]) <= tol), (t, np.max(np.abs(got - p["theta"]) - tol))
+        p["theta"] = got          # carry the GPU's FP32 weights (the next gradient is theirs)
+        moved += int(np.count_nonzero(got != before))
+    assert moved > npar        # the steps did move most parameters
+
+
 @pytest.fixture(scope="module")
 def wide(rr):
     P = datagen.sparse_problem(8000, 3000, 25, seed=79)

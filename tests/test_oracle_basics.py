@@ -20,13 +20,27 @@ def test_splitmix64_published_vectors():
     r = SplitMix64(1234567)
     for tok in rows[1:6]:
         assert r.next() == int(tok[0])
-    assert rows[6][0] == "buckets"
-    seed, n = int(rows[6][1]), int(rows[6][2])
-    r = SplitMix64(seed)
+
+
+def test_splitmix64_unit_draws_follow_the_published_outputs():
+    """next_unit() is the top 53 bits of next() over 2^53: on the published
+    seed it must give exactly those fractions (Fraction arithmetic, no
+    rounding), and over many draws it must look uniform on [0, 1)."""
+    rows = read_golden("splitmix64.txt")
+    r = SplitMix64(int(rows[0][1]))
+    for tok in rows[1:6]:
+        u = r.next_unit()
+        assert Fraction(u) == Fraction(int(tok[0]) >> 11, 1 << 53)
+        assert 0.0 <= u < 1.0
+    # chi-square of 5 equal buckets over 100,000 draws: 4 degrees of
+    # freedom, P(chi2 > 18.47) = 0.001
+    r = SplitMix64(987654321)
+    n = 100000
     counts = [0] * 5
     for _ in range(n):
         counts[int(r.next_unit() * 5)] += 1
-    assert counts == [int(t) for t in rows[7]]
+    chi2 = sum((c - n / 5) ** 2 / (n / 5) for c in counts)
+    assert chi2 < 18.47, counts
 
 
 def _tiny_binary(seed, n=40, f=17, m=4):

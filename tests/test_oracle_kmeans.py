@@ -147,3 +147,71 @@ def test_real_valued_path_groups():
     lab, fc, it, _ = kmeans.kmeans_features(Xd, 4, 5, binary=False)
     group = np.repeat(np.arange(4), 5)
     assert len(set(zip(group.tolist(), lab.tolist()))) == fc
+
+
+# --- real-valued columns -------------------------------------------------------------
+
+def _brute_seed_real(Xd, k, seed):
+    """k-means++ seeding on real columns with exact fractions: D^2 to the
+    nearest chosen centre, draw r = u T with u = (next() >> 11) / 2^53, the
+    next centre the first j whose inclusive prefix of D^2 exceeds r."""
+    F = Xd.shape[1]
+    cols = [list(Xd[:, j]) for j in range(F)]
+    rng = SplitMix64(seed)
+    centres = [rng.next() % F]
+    while len(centres) < k:
+        d2 = [min(_sqdist_frac(cols[j], cols[c]) for c in centres) for j in range(F)]
+        T = sum(d2)
+        if T == 0:
+            break
+        r = Fraction(rng.next() >> 11, 1 << 53) * T
+        acc = 0
+        for j in range(F):
+            acc += d2[j]
+            if acc > r:
+                centres.append(j)
+                break
+    return centres
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_real_seeding_matches_brute_force(seed):
+    Xd = np.random.default_rng(300 + seed).standard_normal((10, 9))
+    assert list(kmeans.seed_real(Xd, 4, seed)) == _brute_seed_real(Xd, 4, seed)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_real_lloyd_matches_brute_force(seed):
+    """Lloyd from the seeds' member sets, nearest exact mean (ties to the
+    lowest index), until no label changes."""
+    Xd = np.random.default_rng(400 + seed).standard_normal((8, 14))
+    centres = kmeans.seed_real(Xd, 4, seed)
+    labels, _ = kmeans.lloyd_real(Xd, centres)
+    members = {s: [int(c)] for s, c in enumerate(centres)}
+    prev = None
+    for _ in range(100):
+        new = _brute_assign(Xd, members)
+        if new == prev:
+            break
+        prev = new
+        members = {s: [j for j in range(Xd.shape[1]) if new[j] == s] for s in range(len(centres))}
+    assert list(labels) == prev
+
+
+def test_real_seeding_distribution():
+    """Real columns: the second centre is drawn with probability D^2_j / T."""
+    Xd = np.random.default_rng(78).standard_normal((5, 6)) * np.array([0.5, 1, 1.5, 2, 1, 3])
+    trials = 3000
+    firsts, counts = {}, {}
+    for s in range(trials):
+        cs = kmeans.seed_real(Xd, 2, 5000 + s)
+        firsts[cs[0]] = firsts.get(cs[0], 0) + 1
+        counts[(cs[0], cs[1])] = counts.get((cs[0], cs[1]), 0) + 1
+    for f0, nf in firsts.items():
+        if nf < 300:
+            continue
+        d2 = ((Xd - Xd[:, [f0]]) ** 2).sum(axis=0)
+        p = d2 / d2.sum()
+        for j in range(6):
+            emp = counts.get((f0, j), 0) / nf
+            assert abs(emp - p[j]) <= 4 * np.sqrt(p[j] * (1 - p[j]) / nf) + 1e-12

@@ -94,3 +94,19 @@ def test_features_and_scale_invariance():
     assert np.allclose(c2, 3.0 * c1, rtol=1e-13)
     x, nrm = mlp.features(r, 0.5)
     assert x[-1] == np.log(0.5) and abs(np.linalg.norm(x[:-1]) - 1) < 1e-15
+
+
+def test_adam_constant_gradient_closed_form():
+    """With the same gradient g at every step the bias-corrected moments are
+    exactly g and g^2, so after t steps theta = theta0 - t lr g / (|g| + eps);
+    a missing or shifted bias correction breaks this from the second step."""
+    rng = np.random.default_rng(21)
+    p = {"W": rng.standard_normal((3, 4)), "b": rng.standard_normal(3)}
+    g = {"W": rng.standard_normal((3, 4)), "b": np.array([2e-8, -3.0, 0.5])}
+    theta0 = {k: v.copy() for k, v in p.items()}
+    opt = mlp.Adam(p, lr=1e-2, eps=1e-8)
+    for t in range(1, 8):
+        opt.step(p, g)
+        for k in p:
+            ref = theta0[k] - t * 1e-2 * g[k] / (np.abs(g[k]) + 1e-8)
+            assert np.allclose(p[k], ref, rtol=0, atol=1e-12 * t), (k, t)

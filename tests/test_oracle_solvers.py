@@ -323,3 +323,105 @@ def test_jacobi_cg_rougher_is_the_preconditioned_optimum():
     c = np.linalg.solve(V.T @ A @ V, V.T @ r)
     assert np.allclose(e, V @ c, rtol=1e-10, atol=1e-12)
     assert np.allclose(res, r - A @ e, rtol=1e-10, atol=1e-12)
+
+
+# --- the two-level forms against dense matrices built entry by entry ----------------
+
+def _dense_prolongation(labels, F_C):
+    """P[j, labels[j]] = 1 / sqrt(n_s), written one entry at a time."""
+    n = [0] * F_C
+    for s in labels:
+        n[int(s)] += 1
+    P = np.zeros((len(labels), F_C))
+    for j, s in enumerate(labels):
+        P[j, int(s)] = 1.0 / np.sqrt(n[int(s)])
+    return P
+
+
+def _dense_A(X, lam):
+    Xd = X.toarray()
+    return Xd.T @ Xd + lam * np.eye(Xd.shape[1])
+
+
+def test_additive_is_weighted_jacobi_plus_galerkin_correction():
+    """B = omega D^-1 + P (P^T A P)^-1 P^T, every matrix formed densely."""
+    X = datagen.zipf_binary_csr(120, 40, 6, 1.1, 31)
+    lam = 0.3
+    lab = datagen.random_labels(40, 6, 2)
+    omega = op.omega_gershgorin(X, lam)
+    A = _dense_A(X, lam)
+    P = _dense_prolongation(lab, 6)
+    ref = omega * np.diag(1.0 / np.diag(A)) + P @ np.linalg.inv(P.T @ A @ P) @ P.T
+    B, _ = precond.make("additive", X, lam, lab, 6, omega)
+    M = _dense_B(B, 40)
+    assert np.abs(M - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_additive_with_singleton_clusters_closed_form():
+    """P = I: B = omega D^-1 + A^-1."""
+    X = datagen.zipf_binary_csr(90, 25, 5, 1.1, 32)
+    lam = 0.6
+    lab = np.arange(25, dtype=np.int32)
+    omega = 0.37
+    A = _dense_A(X, lam)
+    ref = omega * np.diag(1.0 / np.diag(A)) + np.linalg.inv(A)
+    B, _ = precond.make("additive", X, lam, lab, 25, omega)
+    M = _dense_B(B, 25)
+    assert np.abs(M - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_rougher_with_singleton_clusters_is_the_exact_inverse():
+    """P = I makes the coarse correction exact on the rougher's residual:
+    z = e1 + A^-1 (r - A e1) = A^-1 r, and TLFCG stops after one iteration.
+    Correcting r instead of the residual would give e1 + A^-1 r."""
+    X = datagen.zipf_binary_csr(200, 60, 8, 1.1, 5)
+    lam = 0.5
+    lab = np.arange(60, dtype=np.int32)
+    A = _dense_A(X, lam)
+    tl = precond.TwoLevel(X, lam, lab, 60, op.omega_gershgorin(X, lam))
+    r = np.random.default_rng(4).standard_normal(60)
+    ref = np.linalg.solve(A, r)
+    for steps in (1, 2, 3):
+        z = tl.rougher(r, steps)
+        assert np.linalg.norm(z - ref) <= 1e-11 * np.linalg.norm(ref)
+    y = np.random.default_rng(5).standard_normal(200)
+    _, inf = krylov.solve_tlfcg(X, y, lam, lab, 60, tol=1e-12)
+    assert inf.status == krylov.OK and inf.iters == 1
+
+
+def test_rougher_exact_smoothing_leaves_nothing_to_correct():
+    """A with two distinct eigenvalues (orthogonal 0/1 columns of 4 and 9
+    entries): two CG steps solve A e = r, the residual is zero, so z = A^-1 r
+    for any aggregation; a coarse correction of r itself would add
+    P A_c^-1 P^T r."""
+    N, F = 80, 12
+    Xd = np.zeros((N, F))
+    row = 0
+    for j in range(F):
+        m = 4 if j % 3 else 9
+        Xd[row:row + m, j] = 1.0
+        row += m
+    X = sp.csr_matrix(Xd)
+    lam = 0.25
+    lab = np.array([0, 1, 2, 0, 1, 2, 0, 1, 2, 0, 1, 2], dtype=np.int32)
+    tl = precond.TwoLevel(X, lam, lab, 3, 0.5)
+    r = np.random.default_rng(6).standard_normal(F)
+    z = tl.rougher(r, 2)
+    assert np.allclose(z, r / (Xd.sum(axis=0) + lam), rtol=1e-12, atol=0)
+
+
+def test_rougher_general_case_against_dense_projection():
+    """e1 = the A-orthogonal projection of A^-1 r onto span{r, A r} (two CG
+    steps), then z = e1 + P (P^T A P)^-1 P^T (r - A e1), all dense."""
+    X = datagen.zipf_binary_csr(150, 45, 6, 1.1, 7)
+    lam = 0.4
+    lab = datagen.random_labels(45, 7, 8)
+    A = _dense_A(X, lam)
+    P = _dense_prolongation(lab, 7)
+    r = np.random.default_rng(9).standard_normal(45)
+    V = np.stack([r, A @ r], axis=1)
+    e1 = V @ np.linalg.solve(V.T @ A @ V, V.T @ r)
+    ref = e1 + P @ np.linalg.solve(P.T @ A @ P, P.T @ (r - A @ e1))
+    tl = precond.TwoLevel(X, lam, lab, 7, op.omega_gershgorin(X, lam))
+    z = tl.rougher(r, 2)
+    assert np.linalg.norm(z - ref) <= 1e-10 * np.linalg.norm(ref)
