@@ -78,9 +78,9 @@ void free_work(Work& w) {
   if (w.sc_host) (void)hipHostFree(w.sc_host);
   IrVectors& f = w.f32;
   dfree(f.x); dfree(f.r); dfree(f.p); dfree(f.q); dfree(f.z); dfree(f.e1); dfree(f.e2);
-  dfree(f.D); dfree(f.u); dfree(f.part_rows); dfree(f.part_cols);
+  dfree(f.D); dfree(f.u); dfree(f.part_cols);
   if (w.extra) {
-    dfree(w.X.sell_csr.part); dfree(w.X.sell_csc.part);
+    dfree(w.X.sell_csc.part);
     dfree(w.X.csc_plan.head); dfree(w.X.csc_plan.tail);
     dfree(w.rplan.head); dfree(w.rplan.tail); dfree(w.rplan.cpart);
   }
@@ -134,13 +134,12 @@ rr_status get_work_set(rr_handle* h, int k, Work** out) {
     w->extra = true;
     w->X = h->X;
     w->rplan = h->restrict_plan;
-    w->X.sell_csr.part = w->X.sell_csc.part = nullptr;
+    w->X.sell_csc.part = nullptr;
     w->X.csc_plan.head = w->X.csc_plan.tail = nullptr;
     w->rplan.head = w->rplan.tail = nullptr;
     w->rplan.cpart = nullptr;
     RR_TRY(alloc_work(*w, h->X.F, h->X.N, h->FC, h->npartials));
     if (h->X.binary) {
-      RR_TRY(dalloc(&w->X.sell_csr.part, h->X.sell_csr.nout));
       RR_TRY(dalloc(&w->X.sell_csc.part, h->X.sell_csc.nout));
     } else {
       RR_TRY(dalloc(&w->X.csc_plan.head, h->X.csc_plan.nblocks));
@@ -162,7 +161,7 @@ void destroy_handle(rr_handle* h) {
   dfree(X.row_ptr); dfree(X.col_idx); dfree(X.val);
   dfree(X.col_ptr); dfree(X.row_idx); dfree(X.cval);
   free_merge_plan(X.csc_plan);
-  free_sell(X.sell_csr);
+  free_rows(X.rows);
   free_sell(X.sell_csc);
   free_merge_plan(h->restrict_plan);
   free_cluster_rows(h->crow);
@@ -651,11 +650,28 @@ rr_status precond_two_level(rr_handle* h, Work& w, Prof& pf, int tag, int kind, 
   } else {
     launch_gemv(h->FC, sl.Ainv, w.c, w.yc, done, s);
   }
+  // z = e2 + w D^-1 (r - A e2), <r,z> -> beta; X e2 = X e1 + X P yc, where
+  // u still holds X e1 (the label table carries the square-root-average P).
+  // With the point smoother, e2 = e1 + P yc is formed inside the column
+  // pass's epilogue, the only place that reads it.
+  const bool label_rows = h->crow.nlayer > 0 && !h->lsw;
+  if (label_rows && !w.block && h->X.binary) {
+    launch_cluster_rows(h, w.yc, w.X.rw, w.u, done, s);
+    Epi ep = base_epi(w, lam);
+    ep.p = w.e1;
+    ep.r = r;
+    ep.omega = omega;
+    ep.out = z;
+    ep.partials = w.parts.rz;
+    ep.labels = h->labels;
+    ep.cscale = h->cscale;
+    ep.yc = w.yc;
+    RR_TRY(op_csc(h, w, pf, tag, EPI_POST_P, ep, s, n_rz));
+    return RR_OK;
+  }
   launch_prolong(F, h->labels, h->cscale, w.yc, w.e1, w.e2, nullptr, nullptr, 0.0, 0, w.sc, nullptr, s,
                  h->lsw);
-  // z = e2 + w D^-1 (r - A e2), <r,z> -> beta; X e2 = X e1 + X P yc, where
-  // u still holds X e1 (the label table carries the square-root-average P)
-  if (h->crow.nlayer > 0 && !h->lsw)
+  if (label_rows)
     launch_cluster_rows(h, w.yc, w.X.rw, w.u, done, s);
   else
     RR_TRY(op_csr(h, w, pf, tag, w.e2, s));
@@ -1036,7 +1052,7 @@ rr_status Solve::finish(rr_solve_info* info) {
       const hipEvent_t* ev = &h->ev_pool[3 * ti];
       float ms = 0.f;
       RR_HIP(hipEventRecord(ev[0], s));
-      for (int i = 0; i < kReps; ++i) launch_sell_gather(w.X.sell_csr, w.x, s);
+      for (int i = 0; i < kReps; ++i) launch_rows(w.X.rows, w.x, w.u, nullptr, nullptr, s);
       RR_HIP(hipEventRecord(ev[1], s));
       for (int i = 0; i < kReps; ++i) launch_sell_gather(w.X.sell_csc, w.u, s);
       RR_HIP(hipEventRecord(ev[2], s));
@@ -1123,7 +1139,6 @@ rr_status ensure_f32(rr_handle* h, Work& w) {
   RR_TRY(dalloc(&f.q, F)); RR_TRY(dalloc(&f.z, F)); RR_TRY(dalloc(&f.e1, F));
   RR_TRY(dalloc(&f.e2, F)); RR_TRY(dalloc(&f.D, F));
   RR_TRY(dalloc(&f.u, N));
-  RR_TRY(dalloc(&f.part_rows, h->X.sell_csr.nout));
   RR_TRY(dalloc(&f.part_cols, h->X.sell_csc.nout));
   return RR_OK;
 }
@@ -1138,7 +1153,7 @@ rr_status precond32(rr_handle* h, Work& w, double lam, double omega, const Lambd
   Epi32 e{};
   e.lam = lam;
   e.out = f.u;
-  launch_sell32(w.X.sell_csr, f.part_rows, f.e1, EPI_STORE, e, done, s, stage);
+  launch_rows32(w.X.rows, f.e1, f.u, done, s, stage);
   Epi32 er{};
   er.lam = lam;
   er.p = f.e1;
@@ -1154,7 +1169,7 @@ rr_status precond32(rr_handle* h, Work& w, double lam, double omega, const Lambd
   if (h->crow.nlayer > 0)   // X e2 = X e1 + X P yc, u still holding X e1
     launch_cluster_rows32(h, w.yc, f.u, done, s);
   else
-    launch_sell32(w.X.sell_csr, f.part_rows, f.e2, EPI_STORE, e, done, s);
+    launch_rows32(w.X.rows, f.e2, f.u, done, s);
   Epi32 ep{};
   ep.lam = lam;
   ep.omega = omega;
@@ -1257,7 +1272,7 @@ rr_status solve_ir(rr_handle* h, Work& w, double lam, const double* rhs, double*
         const int* done = &w.sc->done;
         Epi32 e{};
         e.out = f.u;
-        launch_sell32(w.X.sell_csr, f.part_rows, f.p, EPI_STORE, e, done, s);
+        launch_rows32(w.X.rows, f.p, f.u, done, s);
         Epi32 eq{};
         eq.lam = lam;
         eq.p = f.p;

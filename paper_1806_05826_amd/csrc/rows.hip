@@ -1,0 +1,271 @@
+// Row pass of the operator for 0/1 matrices, u = X v (u_i = sum of v_j over
+// the columns j of row i), in one kernel with no partial sums.
+//
+// The features are numbered by descending column count (the library's
+// popularity order), so the first W = 16384 features carry most entries of
+// every row (88 % on the 200,000 x 100,000 Zipf(1.1) workload).  Every
+// workgroup copies v[0, W) into LDS once (128 KB of FP64, plus one zero
+// entry for padding) and sums a row's "hot" entries from there; the row's
+// remaining "cold" entries are gathered from v in global memory, where the
+// few hundred KB of cold features stay resident in L2.  A row is finished
+// by its own lanes, so u is written once per row with no partial sums and no
+// second kernel (the sliced pass over all features wrote one partial per
+// (row, slice) pair and needed a reduction kernel).
+//
+// Layout: rows are taken in order, 64 / L rows per layer (L lanes per row).
+// Lane l of a layer serves row 64 c / L + l / L and takes every L-th hot and
+// every L-th cold entry of it (entry k of the row goes to lane k mod L).  A
+// layer holds two lane-interleaved streams padded to the layer's longest
+// lane: hot uint16 local indexes (entry k of lane l at hoff + 256 (k / 4) +
+// 4 l + k % 4, so each 8-byte load of 4 entries reads 512 consecutive bytes
+// per wave; padding = W, the zero entry) and cold int32 feature indexes
+// (the same interleave, 16-byte loads; padding = -1).  The lanes of a row add
+// their sums in a fixed butterfly, so results are bitwise reproducible.
+#include <algorithm>
+#include <climits>
+
+#include "rr_device.h"
+
+namespace rr {
+
+constexpr int kHotBatch = 8;    // 8-byte hot index loads (4 entries each) per batch
+constexpr int kColdBatch = 2;   // 16-byte cold index loads (4 entries each) per batch
+
+template <typename T, int L>
+__global__ __launch_bounds__(kSliceBlock) void k_rows(int nlayer, int N, const int4* __restrict__ lay,
+                                                      const uint16_t* __restrict__ hidx,
+                                                      const int* __restrict__ cidx,
+                                                      const T* __restrict__ v, int F, T* __restrict__ u,
+                                                      const double* __restrict__ scale, const int* done,
+                                                      StageArgs stage) {
+  if (is_done(done)) return;
+  __shared__ __align__(16) T vs[kSliceRows + 1];
+  constexpr unsigned kPad = (unsigned)kSliceRows | ((unsigned)kSliceRows << 16);
+  const int lane = threadIdx.x & 63;
+  const int nw = gridDim.x * kSliceWaves;
+  int c = blockIdx.x * kSliceWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int4 d = make_int4(0, 0, 0, 0);
+  uint2 hq[kHotBatch];
+  int4 cq[kColdBatch];
+  // the first batch of hot and cold indexes of layer c
+  auto load_first = [&]() {
+    d = lay[c];
+    const uint2* hp = reinterpret_cast<const uint2*>(hidx + d.x) + lane;
+    const int4* cp = reinterpret_cast<const int4*>(cidx + d.z) + lane;
+#pragma unroll
+    for (int j = 0; j < kHotBatch; ++j) hq[j] = (4 * j < d.y) ? hp[j * 64] : make_uint2(kPad, kPad);
+#pragma unroll
+    for (int j = 0; j < kColdBatch; ++j) cq[j] = (4 * j < d.w) ? cp[j * 64] : make_int4(-1, -1, -1, -1);
+  };
+  bool have = c < nlayer;
+  if (have) load_first();   // in flight during the slice copy
+  fill_slice(vs, v, min(kSliceRows, F));
+  if (stage.sc) {   // convergence check of the preceding x/r update, under the slice copy
+    __shared__ double red_s[kSliceWaves];
+    double rz_unused;
+    if (stage_update<kSliceBlock>(stage, red_s, rz_unused)) {
+      __builtin_amdgcn_s_waitcnt(0);   // the slice copy lands before the workgroup ends
+      return;
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (; c < nlayer; c += nw) {
+    if (!have) load_first();
+    have = false;
+    // cold entries of the first batch: gathers from global memory, issued
+    // before the LDS sums
+    T cv[4 * kColdBatch];
+#pragma unroll
+    for (int j = 0; j < kColdBatch; ++j) {
+      cv[4 * j + 0] = cq[j].x >= 0 ? v[cq[j].x] : T(0);
+      cv[4 * j + 1] = cq[j].y >= 0 ? v[cq[j].y] : T(0);
+      cv[4 * j + 2] = cq[j].z >= 0 ? v[cq[j].z] : T(0);
+      cv[4 * j + 3] = cq[j].w >= 0 ? v[cq[j].w] : T(0);
+    }
+    T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+    auto add_hot = [&]() {
+#pragma unroll
+      for (int j = 0; j < kHotBatch; ++j) {
+        a0 += vs[hq[j].x & 0xffffu];
+        a1 += vs[hq[j].x >> 16];
+        a2 += vs[hq[j].y & 0xffffu];
+        a3 += vs[hq[j].y >> 16];
+      }
+    };
+    add_hot();
+    for (int g = 4 * kHotBatch; g < d.y; g += 4 * kHotBatch) {   // longer rows: further batches
+      const uint2* hp = reinterpret_cast<const uint2*>(hidx + d.x) + (g / 4) * 64 + lane;
+#pragma unroll
+      for (int j = 0; j < kHotBatch; ++j) hq[j] = (g + 4 * j < d.y) ? hp[j * 64] : make_uint2(kPad, kPad);
+      add_hot();
+    }
+    T cs = T(0);
+#pragma unroll
+    for (int k = 0; k < 4 * kColdBatch; ++k) cs += cv[k];
+    for (int g = 4 * kColdBatch; g < d.w; g += 4 * kColdBatch) {
+      const int4* cp = reinterpret_cast<const int4*>(cidx + d.z) + (g / 4) * 64 + lane;
+#pragma unroll
+      for (int j = 0; j < kColdBatch; ++j) cq[j] = (g + 4 * j < d.w) ? cp[j * 64] : make_int4(-1, -1, -1, -1);
+#pragma unroll
+      for (int j = 0; j < kColdBatch; ++j) {
+        cv[4 * j + 0] = cq[j].x >= 0 ? v[cq[j].x] : T(0);
+        cv[4 * j + 1] = cq[j].y >= 0 ? v[cq[j].y] : T(0);
+        cv[4 * j + 2] = cq[j].z >= 0 ? v[cq[j].z] : T(0);
+        cv[4 * j + 3] = cq[j].w >= 0 ? v[cq[j].w] : T(0);
+      }
+#pragma unroll
+      for (int k = 0; k < 4 * kColdBatch; ++k) cs += cv[k];
+    }
+    T sum = ((a0 + a1) + (a2 + a3)) + cs;
+    if constexpr (L >= 2) sum += __shfl_xor(sum, 1, 64);
+    if constexpr (L >= 4) sum += __shfl_xor(sum, 2, 64);
+    const int row = c * (64 / L) + lane / L;
+    if ((lane & (L - 1)) == 0 && row < N) u[row] = scale ? (T)((double)sum * scale[row]) : sum;
+  }
+}
+
+template <typename T>
+static void rows_dispatch(const RowPlan& rp, const T* v, T* u, const double* scale, const int* done,
+                          hipStream_t s, const StageArgs& st) {
+  switch (rp.L) {
+    case 1:
+      k_rows<T, 1><<<rp.nblk, kSliceBlock, 0, s>>>(rp.nlayer, rp.N, rp.layer, rp.hidx, rp.cidx, v, rp.F, u,
+                                                   scale, done, st);
+      break;
+    case 2:
+      k_rows<T, 2><<<rp.nblk, kSliceBlock, 0, s>>>(rp.nlayer, rp.N, rp.layer, rp.hidx, rp.cidx, v, rp.F, u,
+                                                   scale, done, st);
+      break;
+    default:
+      k_rows<T, 4><<<rp.nblk, kSliceBlock, 0, s>>>(rp.nlayer, rp.N, rp.layer, rp.hidx, rp.cidx, v, rp.F, u,
+                                                   scale, done, st);
+      break;
+  }
+}
+
+void launch_rows(const RowPlan& rp, const double* v, double* u, const double* scale, const int* done,
+                 hipStream_t s, const StageArgs* stage) {
+  StageArgs st{};
+  if (stage) st = *stage;
+  if (rp.nblk > 0)
+    rows_dispatch<double>(rp, v, u, scale, done, s, st);
+  else if (stage)
+    launch_stage_update(*stage, s);
+}
+
+void launch_rows32(const RowPlan& rp, const float* v, float* u, const int* done, hipStream_t s,
+                   const StageArgs* stage) {
+  StageArgs st{};
+  if (stage) st = *stage;
+  if (rp.nblk > 0)
+    rows_dispatch<float>(rp, v, u, nullptr, done, s, st);
+  else if (stage)
+    launch_stage_update(*stage, s);
+}
+
+void free_rows(RowPlan& rp) {
+  if (rp.layer) (void)hipFree(rp.layer);
+  if (rp.hidx) (void)hipFree(rp.hidx);
+  if (rp.cidx) (void)hipFree(rp.cidx);
+  rp = RowPlan{};
+}
+
+// Host-side construction from the CSR (columns sorted inside every row, in
+// the popularity order).  Setup only.
+rr_status build_rows(RowPlan& out, const std::vector<int>& ptr, const std::vector<int>& col, int N, int F,
+                     int num_cu, int L, hipStream_t s) {
+  free_rows(out);
+  if (L != 1 && L != 2 && L != 4) return fail(RR_ERR_DEVICE, "internal: lanes per row must be 1, 2 or 4");
+  const int W = kSliceRows;
+  const int rpl = 64 / L;
+  const int nlayer = cdiv(N, rpl);
+  std::vector<int4> lay(std::max(1, nlayer));
+  std::vector<uint16_t> hidx;
+  std::vector<int> cidx;
+  long long hot = 0, cold = 0;
+  std::vector<int> hc(64), cc(64);
+  for (int c = 0; c < nlayer; ++c) {
+    int hm = 0, cm = 0;
+    for (int l = 0; l < 64; ++l) {
+      const int i = c * rpl + l / L, sub = l % L;
+      hc[l] = cc[l] = 0;
+      if (i >= N) continue;
+      int h = 0, k2 = 0;
+      for (int k = ptr[i]; k < ptr[i + 1]; ++k) {
+        if (col[k] < W) {
+          if (h % L == sub) ++hc[l];
+          ++h;
+        } else {
+          if (k2 % L == sub) ++cc[l];
+          ++k2;
+        }
+      }
+      hm = std::max(hm, hc[l]);
+      cm = std::max(cm, cc[l]);
+    }
+    hm = (hm + 3) / 4 * 4;
+    cm = (cm + 3) / 4 * 4;
+    const size_t hoff = hidx.size(), coff = cidx.size();
+    if (hoff + (size_t)hm * 64 > (size_t)INT_MAX || coff + (size_t)cm * 64 > (size_t)INT_MAX)
+      return fail(RR_ERR_UNSUPPORTED, "row pass: more than 2^31 padded entries");
+    lay[c] = make_int4((int)hoff, hm, (int)coff, cm);
+    hidx.resize(hoff + (size_t)hm * 64, (uint16_t)W);
+    cidx.resize(coff + (size_t)cm * 64, -1);
+    for (int l = 0; l < 64; ++l) {
+      const int i = c * rpl + l / L, sub = l % L;
+      if (i >= N) continue;
+      int h = 0, k2 = 0, hs = 0, cs = 0;
+      for (int k = ptr[i]; k < ptr[i + 1]; ++k) {
+        const int j = col[k];
+        if (j < W) {
+          if (h % L == sub) {
+            hidx[hoff + (size_t)(hs / 4) * 256 + 4 * l + hs % 4] = (uint16_t)j;
+            ++hs;
+          }
+          ++h;
+        } else {
+          if (k2 % L == sub) {
+            cidx[coff + (size_t)(cs / 4) * 256 + 4 * l + cs % 4] = j;
+            ++cs;
+          }
+          ++k2;
+        }
+      }
+      hot += hs;
+      cold += cs;
+    }
+  }
+  // the kernel trusts the plan: check every access it will make
+  for (int c = 0; c < nlayer; ++c) {
+    const int4 d = lay[c];
+    if (d.x % 256 || d.z % 256 || d.y % 4 || d.w % 4 || (size_t)d.x + (size_t)d.y * 64 > hidx.size() ||
+        (size_t)d.z + (size_t)d.w * 64 > cidx.size())
+      return fail(RR_ERR_DEVICE, "internal: row plan out of range");
+  }
+  for (uint16_t q : hidx)
+    if (q > W) return fail(RR_ERR_DEVICE, "internal: row plan hot index out of range");
+  for (int q : cidx)
+    if (q != -1 && (q < W || q >= F)) return fail(RR_ERR_DEVICE, "internal: row plan cold index out of range");
+  if (hidx.empty()) hidx.resize(256, (uint16_t)W);
+  if (cidx.empty()) cidx.resize(256, -1);
+  out.N = N;
+  out.F = F;
+  out.W = W;
+  out.L = L;
+  out.nlayer = nlayer;
+  out.nblk = nlayer > 0 ? std::min(std::max(1, num_cu), cdiv(nlayer, kSliceWaves)) : 0;
+  out.hot_entries = hot;
+  out.cold_entries = cold;
+  out.idx_bytes = (long long)hidx.size() * 2 + (long long)cidx.size() * 4;
+  RR_HIP(hipMalloc(&out.layer, sizeof(int4) * lay.size()));
+  RR_HIP(hipMalloc(&out.hidx, sizeof(uint16_t) * hidx.size()));
+  RR_HIP(hipMalloc(&out.cidx, sizeof(int) * cidx.size()));
+  RR_HIP(hipMemcpyAsync(out.layer, lay.data(), sizeof(int4) * lay.size(), hipMemcpyHostToDevice, s));
+  RR_HIP(hipMemcpyAsync(out.hidx, hidx.data(), sizeof(uint16_t) * hidx.size(), hipMemcpyHostToDevice, s));
+  RR_HIP(hipMemcpyAsync(out.cidx, cidx.data(), sizeof(int) * cidx.size(), hipMemcpyHostToDevice, s));
+  RR_HIP(hipStreamSynchronize(s));
+  return RR_OK;
+}
+
+}  // namespace rr

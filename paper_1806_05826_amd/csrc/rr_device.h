@@ -100,6 +100,30 @@ __device__ inline bool stage_update(const StageArgs& st, double* lds, double& rz
   return fin;
 }
 
+// dst[0, W] = src[0, n) followed by zeros (n <= W = kSliceRows), with direct
+// global-to-LDS loads: at step k wave w moves the 64 E entries starting at
+// (16 k + w) 64 E, 16 bytes (E entries) per lane; the entries past the last
+// whole E-group below n and the zero tail are written one by one.  The
+// caller waits for the loads (s_waitcnt) and synchronises the workgroup.
+template <typename T>
+__device__ inline void fill_slice(T* dst, const T* __restrict__ src, int n) {
+  constexpr int E = 16 / (int)sizeof(T);
+  constexpr int ROW = 64 * E;
+  static_assert(kSliceRows % (kSliceWaves * ROW) == 0, "slice copy covers whole 1 KB rows");
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nfull = n - n % E;
+#pragma unroll
+  for (int k = 0; k < kSliceRows / (kSliceWaves * ROW); ++k) {
+    const int e0 = (k * kSliceWaves + w) * ROW;
+    if (e0 + E * lane < nfull)
+      __builtin_amdgcn_global_load_lds(
+          (const __attribute__((address_space(1))) void*)(src + e0 + E * lane),
+          (__attribute__((address_space(3))) void*)(dst + e0), 16, 0, 0);
+  }
+  for (int i = nfull + (int)threadIdx.x; i <= kSliceRows; i += kSliceBlock)
+    dst[i] = (i < n) ? src[i] : T(0);
+}
+
 // Segment epilogues: what happens to a finished column sum t of column s.
 template <int MODE>
 __device__ inline void seg_finish(int s, double t, const Epi& e, double& dot) {
@@ -121,6 +145,14 @@ __device__ inline void seg_finish(int s, double t, const Epi& e, double& dot) {
     const double z = e2 + (e.omega * rho) / e.D[s];
     e.out[s] = z;
     dot += rs * z;
+  } else if constexpr (MODE == EPI_POST_P) {
+    const int l = e.labels[s];
+    const double e2 = e.p[s] + e.cscale[l] * e.yc[l];
+    const double rs = e.r[s];
+    const double rho = rs - (t + e.lam * e2);
+    const double z = e2 + (e.omega * rho) / e.D[s];
+    e.out[s] = z;
+    dot += rs * z;
   } else if constexpr (MODE == EPI_TRUE) {
     const double res = e.r[s] - (t + e.lam * e.p[s]);
     if (e.out) e.out[s] = res;
@@ -132,7 +164,7 @@ __device__ inline void seg_finish(int s, double t, const Epi& e, double& dot) {
 
 template <int MODE>
 constexpr bool has_dot() {
-  return MODE == EPI_APPLY_DOT || MODE == EPI_POST || MODE == EPI_TRUE;
+  return MODE == EPI_APPLY_DOT || MODE == EPI_POST || MODE == EPI_POST_P || MODE == EPI_TRUE;
 }
 
 // The epilogue's dot product leaves one partial per block (consumed by the

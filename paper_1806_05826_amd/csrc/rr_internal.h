@@ -82,7 +82,8 @@ enum EpiMode {
   EPI_RESID = 3,      // out[s] = r[s] - (t + lam p[s])
   EPI_POST = 4,       // rho = r - (t + lam e2); z = e2 + w rho / D; <r,z> -> beta
   EPI_TRUE = 5,       // res = r - (t + lam x); <res,res> -> true_rr
-  EPI_SCALE = 6       // out[s] = t * scale[s]
+  EPI_SCALE = 6,      // out[s] = t * scale[s]
+  EPI_POST_P = 7      // EPI_POST with e2 = e1 + P yc formed in place (p = e1)
 };
 
 struct Epi {
@@ -96,6 +97,9 @@ struct Epi {
   Scalars* sc;
   double* partials;      // block partials of the epilogue's dot product
   double* history;
+  const int* labels;     // EPI_POST_P: cluster of every feature,
+  const double* cscale;  // the prolongation's 1/sqrt(n_s)
+  const double* yc;      // and the coarse correction
 };
 
 // Single-precision vectors of an inner solve of iterative refinement.
@@ -103,7 +107,7 @@ struct IrVectors {
   float *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr;
   float *e1 = nullptr, *e2 = nullptr, *D = nullptr;   // [F]
   float* u = nullptr;                                                  // [N]
-  float *part_rows = nullptr, *part_cols = nullptr;   // operator partial sums (sliced passes)
+  float* part_cols = nullptr;   // column pass partial sums (sliced pass)
 };
 
 // The learned coarse correction's network (mlp.hip).
@@ -150,6 +154,12 @@ struct MergePlan {
   int4* chunk = nullptr;
   int4* fin = nullptr;
   double* cpart = nullptr;
+  // one-kernel form, used instead when no segment exceeds kOneSegMax
+  // entries: segments of up to kWaveSeg entries take one wave each, longer
+  // ones a whole block, (segment, first, end, 0) each
+  int nwitem = 0, nbitem = 0;
+  int4* witem = nullptr;
+  int4* bitem = nullptr;
 };
 
 // Sliced-ELL plan of a segmented gather-sum out_s = sum_{e in s} v[g_e]
@@ -173,7 +183,19 @@ struct SellPlan {
   double* part = nullptr;     // [nout] partial sums
 };
 
-// Autotuning record of the sliced plans (see build_sell_plans).
+// Row pass of 0/1 X without partial sums (rows.hip): layer c of 64 / L rows
+// holds lane-interleaved hot uint16 indexes into the LDS copy of v[0, W) and
+// cold int32 feature indexes gathered from global memory.
+struct RowPlan {
+  int N = 0, F = 0, W = 0, L = 1, nlayer = 0, nblk = 0;
+  long long hot_entries = 0, cold_entries = 0, idx_bytes = 0;
+  int4* layer = nullptr;      // [nlayer] (hot offset, hot length, cold offset, cold length) per lane
+  uint16_t* hidx = nullptr;   // hot lane streams (W = the zero entry)
+  int* cidx = nullptr;        // cold lane streams (-1 = padding)
+};
+
+// Autotuning record of the operator plans (see build_sell_plans): lanes per
+// row of the row pass (div_rows) and the column pass's lane-stream divisor.
 struct SellTuning {
   int div_rows = 2, div_cols = 2, cached = 0, n = 0;
   int cand_div[6] = {}, cand_pass[6] = {};
@@ -194,7 +216,7 @@ struct Sparse {
                                 // forms u = D X v, so the operator is X^T D X + lam I
   int csr_group = 16;       // lanes per row in the CSR kernel
   MergePlan csc_plan;       // segments = columns (merge-path form, valued X)
-  SellPlan sell_csr;        // u = X v   (0/1 X)
+  RowPlan rows;             // u = X v   (0/1 X)
   SellPlan sell_csc;        // t = X^T u (0/1 X)
   int num_cu = 256;
 };
@@ -430,9 +452,10 @@ int launch_csc(const Sparse& X, const double* u, int mode, const Epi& e, const i
                hipStream_t s, hipEvent_t mid = nullptr);
 rr_status build_csc(Sparse& X, hipStream_t s);
 rr_status renumber_features(Sparse& X, int* fperm, int* finv, hipStream_t s);
-// Lane-stream target of the sliced plans: nnz / (CUs x 16 waves x 64 lanes x
-// div), clamped to [8, 64].  With autotune the divisor of each pass is chosen
-// among {1, 2, 4} by timing, once per device and shape bucket.
+// The operator's plans for 0/1 X: the row pass (lanes per row) and the sliced
+// column pass (lane-stream target nnz / (CUs x 16 waves x 64 lanes x div),
+// clamped to [8, 64]).  With autotune, lanes per row and the divisor are
+// chosen among {1, 2, 4} by timing, once per device and shape bucket.
 rr_status build_sell_plans(Sparse& X, hipStream_t s, int autotune, SellTuning* tuned);
 void free_sell(SellPlan& sp);
 int launch_sell(const SellPlan& sp, const double* v, int mode, const Epi& e, const int* done,
@@ -444,6 +467,13 @@ int launch_sell32(const SellPlan& sp, float* part, const float* v, int mode, con
                   const int* done, hipStream_t s, const StageArgs* stage = nullptr);
 // The gather kernel alone (partial sums only; no reduction, no epilogue).
 void launch_sell_gather(const SellPlan& sp, const double* v, hipStream_t s);
+void launch_rows(const RowPlan& rp, const double* v, double* u, const double* scale, const int* done,
+                 hipStream_t s, const StageArgs* stage = nullptr);
+void launch_rows32(const RowPlan& rp, const float* v, float* u, const int* done, hipStream_t s,
+                   const StageArgs* stage = nullptr);
+void free_rows(RowPlan& rp);
+rr_status build_rows(RowPlan& out, const std::vector<int>& ptr, const std::vector<int>& col, int N, int F,
+                     int num_cu, int L, hipStream_t s);
 // More than kMaxParts block partials are first added into partials[0] by one
 // block; returns the count the consumer should add.
 int collapse_parts(double* partials, int n, const int* done, hipStream_t s);

@@ -44,30 +44,6 @@ constexpr int kWaveUnroll = 16;     // 16-byte loads in flight per lane (wave ta
 constexpr unsigned kEndFlag = 0x8000u;
 constexpr unsigned kLocalMask = 0x7fffu;
 
-// dst[0, W] = src[0, n) followed by zeros (n <= W = kSliceRows), with direct
-// global-to-LDS loads: at step k wave w moves the 64 E entries starting at
-// (16 k + w) 64 E, 16 bytes (E entries) per lane; the entries past the last
-// whole E-group below n and the zero tail are written one by one.  The
-// caller waits for the loads (s_waitcnt) and synchronises the workgroup.
-template <typename T>
-__device__ inline void fill_slice(T* dst, const T* __restrict__ src, int n) {
-  constexpr int E = 16 / (int)sizeof(T);
-  constexpr int ROW = 64 * E;
-  static_assert(kSliceRows % (kSliceWaves * ROW) == 0, "slice copy covers whole 1 KB rows");
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nfull = n - n % E;
-#pragma unroll
-  for (int k = 0; k < kSliceRows / (kSliceWaves * ROW); ++k) {
-    const int e0 = (k * kSliceWaves + w) * ROW;
-    if (e0 + E * lane < nfull)
-      __builtin_amdgcn_global_load_lds(
-          (const __attribute__((address_space(1))) void*)(src + e0 + E * lane),
-          (__attribute__((address_space(3))) void*)(dst + e0), 16, 0, 0);
-  }
-  for (int i = nfull + (int)threadIdx.x; i <= kSliceRows; i += kSliceBlock)
-    dst[i] = (i < n) ? src[i] : T(0);
-}
-
 // task.x: kind (0 lane task, 1 wave task); task.y: offset of its indexes
 // (uint16 units for lane tasks, 16-byte units for wave tasks); task.z:
 // length (longest lane stream; for wave tasks 16 x the 512-entry groups +
@@ -427,10 +403,11 @@ int launch_sell(const SellPlan& sp, const double* v, int mode, const Epi& e, con
     case EPI_APPLY_DOT: sell_reduce_mode<EPI_APPLY_DOT>(sp, e, done, s); break;
     case EPI_RESID: sell_reduce_mode<EPI_RESID>(sp, e, done, s); break;
     case EPI_POST: sell_reduce_mode<EPI_POST>(sp, e, done, s); break;
+    case EPI_POST_P: sell_reduce_mode<EPI_POST_P>(sp, e, done, s); break;
     case EPI_TRUE: sell_reduce_mode<EPI_TRUE>(sp, e, done, s); break;
     case EPI_SCALE: sell_reduce_mode<EPI_SCALE>(sp, e, done, s); break;
   }
-  if (mode != EPI_APPLY_DOT && mode != EPI_POST && mode != EPI_TRUE) return 0;
+  if (mode != EPI_APPLY_DOT && mode != EPI_POST && mode != EPI_POST_P && mode != EPI_TRUE) return 0;
   return collapse_parts(e.partials, sell_reduce_grid(sp), done, s);
 }
 
@@ -807,8 +784,26 @@ static rr_status time_pass(const SellPlan& sp, const double* v, double* out, int
   return RR_OK;
 }
 
+// Mean time of `reps` back-to-back launches of the row pass.
+static rr_status time_rows(const RowPlan& rp, const double* v, double* out, int reps, hipStream_t s,
+                           float* ms) {
+  hipEvent_t a, b;
+  RR_HIP(hipEventCreate(&a));
+  RR_HIP(hipEventCreate(&b));
+  launch_rows(rp, v, out, nullptr, nullptr, s);
+  RR_HIP(hipEventRecord(a, s));
+  for (int i = 0; i < reps; ++i) launch_rows(rp, v, out, nullptr, nullptr, s);
+  RR_HIP(hipEventRecord(b, s));
+  RR_HIP(hipEventSynchronize(b));
+  RR_HIP(hipEventElapsedTime(ms, a, b));
+  *ms /= reps;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return RR_OK;
+}
+
 namespace {
-// tuned lane-stream divisors per shape bucket (log2 of N, F, nnz) and device
+// tuned (lanes per row, column lane-stream divisor) per shape bucket (log2 of N, F, nnz) and device
 std::mutex g_tune_mu;
 std::map<std::string, std::pair<int, int>> g_tune_cache;
 }
@@ -823,7 +818,8 @@ rr_status build_sell_plans(Sparse& X, hipStream_t s, int autotune, SellTuning* t
     RR_HIP(hipMemcpyAsync(ri.data(), X.row_idx, sizeof(int) * X.nnz, hipMemcpyDeviceToHost, s));
   }
   RR_HIP(hipStreamSynchronize(s));
-  int div_rows = 2, div_cols = 2;
+  // defaults: two lanes per row once rows average 16 entries or more
+  int lanes = (X.N > 0 && (long long)X.nnz >= 16LL * X.N) ? 2 : 1, div_cols = 2;
   if (autotune) {
     int dev = 0;
     RR_HIP(hipGetDevice(&dev));
@@ -837,7 +833,7 @@ rr_status build_sell_plans(Sparse& X, hipStream_t s, int autotune, SellTuning* t
       std::lock_guard<std::mutex> lk(g_tune_mu);
       auto it = g_tune_cache.find(key);
       if (it != g_tune_cache.end()) {
-        div_rows = it->second.first;
+        lanes = it->second.first;
         div_cols = it->second.second;
         hit = true;
       }
@@ -846,7 +842,7 @@ rr_status build_sell_plans(Sparse& X, hipStream_t s, int autotune, SellTuning* t
     if (!hit) {
       // build every candidate plan, time them in interleaved rounds on a
       // vector of ones (best round of each) and keep the fastest; a larger
-      // divisor must win by 3 % to replace a smaller one
+      // candidate must win by 3 % to replace a smaller one
       double *v = nullptr, *out = nullptr;
       const int nmax = std::max(X.N, X.F);
       RR_HIP(hipMalloc(&v, sizeof(double) * nmax));
@@ -854,31 +850,34 @@ rr_status build_sell_plans(Sparse& X, hipStream_t s, int autotune, SellTuning* t
       launch_fill(v, 1.0, nmax, s);
       constexpr int kCand = 3, kRounds = 5;
       const int cand[kCand] = {1, 2, 4};
-      SellPlan plans[2][kCand];
+      RowPlan rplans[kCand];
+      SellPlan cplans[kCand];
       float best[2][kCand];
       rr_status st = RR_OK;
-      for (int pass = 0; pass < 2 && st == RR_OK; ++pass)
-        for (int c = 0; c < kCand && st == RR_OK; ++c) {
-          st = pass == 0 ? build_sell(plans[pass][c], rp, ci, X.N, X.F, X.num_cu, s, cand[c])
-                         : build_sell(plans[pass][c], cp, ri, X.F, X.N, X.num_cu, s, cand[c]);
-          plans[pass][c].pass = pass;
-          best[pass][c] = 1e30f;
-        }
+      for (int c = 0; c < kCand && st == RR_OK; ++c) {
+        st = build_rows(rplans[c], rp, ci, X.N, X.F, X.num_cu, cand[c], s);
+        if (st == RR_OK) st = build_sell(cplans[c], cp, ri, X.F, X.N, X.num_cu, s, cand[c]);
+        cplans[c].pass = 1;
+        best[0][c] = best[1][c] = 1e30f;
+      }
       for (int round = 0; round < kRounds && st == RR_OK; ++round)
-        for (int pass = 0; pass < 2 && st == RR_OK; ++pass)
-          for (int c = 0; c < kCand && st == RR_OK; ++c) {
-            float ms = 0.f;
-            st = time_pass(plans[pass][c], v, out, 4, s, &ms);
-            best[pass][c] = std::min(best[pass][c], ms);
-          }
-      for (int pass = 0; pass < 2; ++pass)
-        for (int c = 0; c < kCand; ++c) free_sell(plans[pass][c]);
+        for (int c = 0; c < kCand && st == RR_OK; ++c) {
+          float ms = 0.f;
+          st = time_rows(rplans[c], v, out, 4, s, &ms);
+          best[0][c] = std::min(best[0][c], ms);
+          if (st == RR_OK) st = time_pass(cplans[c], v, out, 4, s, &ms);
+          best[1][c] = std::min(best[1][c], ms);
+        }
+      for (int c = 0; c < kCand; ++c) {
+        free_rows(rplans[c]);
+        free_sell(cplans[c]);
+      }
       if (st == RR_OK) {
         int pick[2] = {0, 0};
         for (int pass = 0; pass < 2; ++pass)
           for (int c = 1; c < kCand; ++c)
             if (best[pass][c] < 0.97f * best[pass][pick[pass]]) pick[pass] = c;
-        div_rows = cand[pick[0]];
+        lanes = cand[pick[0]];
         div_cols = cand[pick[1]];
         if (tuned) {
           for (int c = 0; c < kCand; ++c)
@@ -894,16 +893,15 @@ rr_status build_sell_plans(Sparse& X, hipStream_t s, int autotune, SellTuning* t
       (void)hipFree(out);
       RR_TRY(st);
       std::lock_guard<std::mutex> lk(g_tune_mu);
-      g_tune_cache[key] = {div_rows, div_cols};
+      g_tune_cache[key] = {lanes, div_cols};
     }
   }
   if (tuned) {
-    tuned->div_rows = div_rows;
+    tuned->div_rows = lanes;
     tuned->div_cols = div_cols;
   }
-  RR_TRY(build_sell(X.sell_csr, rp, ci, X.N, X.F, X.num_cu, s, div_rows));
+  RR_TRY(build_rows(X.rows, rp, ci, X.N, X.F, X.num_cu, lanes, s));
   RR_TRY(build_sell(X.sell_csc, cp, ri, X.F, X.N, X.num_cu, s, div_cols));
-  X.sell_csr.pass = 0;
   X.sell_csc.pass = 1;
   return RR_OK;
 }

@@ -66,10 +66,9 @@ static void csr_dispatch(const Sparse& X, const double* v, double* u, const int*
 void launch_csr(const Sparse& X, const double* v, double* u, const int* done, hipStream_t s,
                 const StageArgs* stage, hipEvent_t mid) {
   if (X.binary && X.N > 0) {
-    Epi e{};
-    e.out = u;
-    e.scale = X.rw;   // u = D X v with row weights, fused in the reduction's epilogue
-    launch_sell(X.sell_csr, v, X.rw ? EPI_SCALE : EPI_STORE, e, done, s, stage, mid);
+    // u = D X v with row weights, applied as each row is finished
+    launch_rows(X.rows, v, u, X.rw, done, s, stage);
+    if (mid) (void)hipEventRecord(mid, s);
     return;
   }
   if (stage) launch_stage_update(*stage, s);
@@ -345,6 +344,85 @@ static void chunk_mode(const MergePlan& mp, const int* idx, const double* val, c
                                                                     done);
 }
 
+// One-kernel segmented sum for epilogues without a dot product: a segment
+// of at most kWaveSeg entries is summed by one wave (lane l adds entries l,
+// l + 64, ... in order, then a fixed butterfly), a longer one (at most
+// kOneSegMax entries) by a whole block (thread k adds entries k, k + 256,
+// ... in order, then the fixed block tree).  Blocks [0, nb) take the long
+// segments, the others four short ones each.
+constexpr int kWaveSeg = 1024;
+constexpr int kOneSegMax = 4096;
+template <int MODE, bool VAL>
+__global__ __launch_bounds__(kBlock) void k_seg1(const int4* __restrict__ witem, int nw,
+                                                 const int4* __restrict__ bitem, int nb,
+                                                 const int* __restrict__ idx, const double* __restrict__ val,
+                                                 const double* __restrict__ v, Epi e, const int* done) {
+  if (is_done(done)) return;
+  double dot = 0.0;
+  if ((int)blockIdx.x < nb) {
+    const int4 it = bitem[blockIdx.x];
+    constexpr int U = kOneSegMax / kBlock;
+    int j[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int q = it.y + (int)threadIdx.x + k * kBlock;
+      j[k] = q < it.z ? idx[q] : -1;
+    }
+    double t = 0.0;
+    if constexpr (VAL) {
+      double a[U];
+#pragma unroll
+      for (int k = 0; k < U; ++k) a[k] = j[k] >= 0 ? val[it.y + (int)threadIdx.x + k * kBlock] : 0.0;
+#pragma unroll
+      for (int k = 0; k < U; ++k) t += j[k] >= 0 ? v[j[k]] * a[k] : 0.0;
+    } else {
+#pragma unroll
+      for (int k = 0; k < U; ++k) t += j[k] >= 0 ? v[j[k]] : 0.0;
+    }
+    __shared__ double red[kBlock / 64];
+    t = block_sum(t, red);
+    if (threadIdx.x == 0) seg_finish<MODE>(it.x, t, e, dot);
+    return;
+  }
+  const int wv = ((int)blockIdx.x - nb) * (kBlock / 64) + (int)(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (wv >= nw) return;
+  const int4 it = witem[wv];
+  constexpr int U = kWaveSeg / 64;
+  int j[U];
+#pragma unroll
+  for (int k = 0; k < U; ++k) {
+    const int q = it.y + lane + 64 * k;
+    j[k] = q < it.z ? idx[q] : -1;
+  }
+  double t = 0.0;
+  if constexpr (VAL) {
+    double a[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) a[k] = j[k] >= 0 ? val[it.y + lane + 64 * k] : 0.0;
+#pragma unroll
+    for (int k = 0; k < U; ++k) t += j[k] >= 0 ? v[j[k]] * a[k] : 0.0;
+  } else {
+#pragma unroll
+    for (int k = 0; k < U; ++k) t += j[k] >= 0 ? v[j[k]] : 0.0;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+  if (lane == 0) seg_finish<MODE>(it.x, t, e, dot);
+}
+
+template <int MODE>
+static void seg1_mode(const MergePlan& mp, const int* idx, const double* val, const double* v,
+                      const Epi& e, const int* done, hipStream_t s) {
+  const int grid = mp.nbitem + cdiv(mp.nwitem, kBlock / 64);
+  if (val)
+    k_seg1<MODE, true><<<grid, kBlock, 0, s>>>(mp.witem, mp.nwitem, mp.bitem, mp.nbitem, idx, val, v, e,
+                                               done);
+  else
+    k_seg1<MODE, false><<<grid, kBlock, 0, s>>>(mp.witem, mp.nwitem, mp.bitem, mp.nbitem, idx, nullptr, v,
+                                                e, done);
+}
+
 // Collapse n block partials into partials[0] (one block, fixed order).
 __global__ __launch_bounds__(kBlock) void k_collapse(double* partials, int n, const int* done) {
   if (is_done(done)) return;
@@ -389,6 +467,13 @@ int launch_csc(const Sparse& X, const double* u, int mode, const Epi& e, const i
 
 int launch_segsum(const MergePlan& mp, const int* seg_end, const int* idx, const double* val,
                   const double* v, int mode, const Epi& e, const int* done, hipStream_t s) {
+  if (mp.nwitem + mp.nbitem > 0) {
+    switch (mode) {
+      case EPI_STORE: seg1_mode<EPI_STORE>(mp, idx, val, v, e, done, s); return 0;
+      case EPI_SCALE: seg1_mode<EPI_SCALE>(mp, idx, val, v, e, done, s); return 0;
+      default: break;
+    }
+  }
   if (mp.nblocks == 0) return 0;
   if (mp.nchunk > 0) {
     switch (mode) {
@@ -429,6 +514,8 @@ void free_merge_plan(MergePlan& mp) {
   if (mp.chunk) (void)hipFree(mp.chunk);
   if (mp.fin) (void)hipFree(mp.fin);
   if (mp.cpart) (void)hipFree(mp.cpart);
+  if (mp.witem) (void)hipFree(mp.witem);
+  if (mp.bitem) (void)hipFree(mp.bitem);
   mp = MergePlan{};
 }
 
@@ -437,6 +524,27 @@ rr_status build_chunk_plan(MergePlan& mp, const int* d_seg_ptr, int nseg, hipStr
   std::vector<int> ptr(nseg + 1);
   RR_HIP(hipMemcpyAsync(ptr.data(), d_seg_ptr, sizeof(int) * (nseg + 1), hipMemcpyDeviceToHost, s));
   RR_HIP(hipStreamSynchronize(s));
+  int longest = 0;
+  for (int q = 0; q < nseg; ++q) longest = std::max(longest, ptr[q + 1] - ptr[q]);
+  if (longest <= kOneSegMax) {   // one kernel: a wave or a block per segment
+    std::vector<int4> wi, bi;
+    for (int q = 0; q < nseg; ++q) {
+      if (ptr[q + 1] < ptr[q]) return fail(RR_ERR_DEVICE, "internal: decreasing segment offsets");
+      (ptr[q + 1] - ptr[q] > kWaveSeg ? bi : wi).push_back(make_int4(q, ptr[q], ptr[q + 1], 0));
+    }
+    mp.nwitem = (int)wi.size();
+    mp.nbitem = (int)bi.size();
+    if (mp.nwitem) {
+      RR_HIP(hipMalloc(&mp.witem, sizeof(int4) * mp.nwitem));
+      RR_HIP(hipMemcpyAsync(mp.witem, wi.data(), sizeof(int4) * mp.nwitem, hipMemcpyHostToDevice, s));
+    }
+    if (mp.nbitem) {
+      RR_HIP(hipMalloc(&mp.bitem, sizeof(int4) * mp.nbitem));
+      RR_HIP(hipMemcpyAsync(mp.bitem, bi.data(), sizeof(int4) * mp.nbitem, hipMemcpyHostToDevice, s));
+    }
+    RR_HIP(hipStreamSynchronize(s));
+    return RR_OK;
+  }
   std::vector<int4> chunk, fin;
   int slots = 0;
   for (int q = 0; q < nseg; ++q) {
