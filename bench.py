@@ -4,10 +4,13 @@ column popularity, 12.0 M nonzeros), lambda in {1e-2, 1, 100}, k-means
 aggregation with k = 1000, FP64 throughout.
 
 One step = the three solves, each run for the number of iterations at which
-its iterate first reaches relative error <= 1e-10 against a tightly converged
-reference (calibrated before the timed region).  Setup (transpose, k-means,
-coarse Gram) and the per-lambda coarse factorizations are timed separately
-and reported beside the step.
+its iterate first reaches relative error <= 1e-10 against the CPU oracle's
+solution on the same aggregation (the oracle's FP64 V(1,1) PCG with the
+GPU's k-means labels, converged to relative residual 1e-13; calibrated before
+the timed region).  Setup (transpose, k-means, coarse Gram) and the
+per-lambda coarse factorizations are timed separately and reported beside the
+step.  The oracle's reference solves are timed on one host thread and give
+the CPU baseline.
 
 Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -24,8 +27,11 @@ METRIC = "time-to-1e-10 rel. error (s) + SpMV HBM GB/s; batched/BF16/learned vs 
 HBM_PEAK_GBS = 8000.0
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sell_columns_binary_200kx100k_traffic.md")
-SELL_SOURCE = os.path.join(ROOT, "paper_1806_05826_amd", "csrc", "sell.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "operator_binary_200kx100k_traffic.md")
+CSRC = os.path.join(ROOT, "paper_1806_05826_amd", "csrc")
+# the kernels of one operator application (0/1 X) and their sources
+APPLY_KERNELS = ("k_rows", "k_sell<1>", "k_sell_reduce<2>")
+APPLY_SOURCES = ("rows.hip", "sell.hip", "rr_device.h")
 
 
 def column_gather_bytes(N, F, nnz):
@@ -41,11 +47,24 @@ def apply_bytes(N, F, nnz):
     return 8 * nnz + 4 * (N + 1) + 4 * (F + 1) + 8 * F * 2 + 16 * N + 8 * F
 
 
-def measured_traffic():
-    """HBM bytes per launch of the column gather kernel from the committed
-    counter summary, or None when it is missing or was taken on a different
-    version of the kernel source."""
+def apply_bytes_valued(N, F, nnz):
+    """One application with FP64 values stored both ways: 12 bytes per entry
+    per pass (4-byte index, 8-byte value) on top of the pattern's vectors."""
+    return apply_bytes(N, F, nnz) + 16 * nnz
+
+
+def sources_hash():
     import hashlib
+    h = hashlib.sha256()
+    for f in APPLY_SOURCES:
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes of one operator application (row pass, column gather,
+    column reduction) from the committed counter summary, or None when it is
+    missing or was taken on a different version of the kernels' sources."""
     try:
         text = open(TRAFFIC_FILE).read()
     except OSError:
@@ -56,45 +75,68 @@ def measured_traffic():
             k, v = line[2:].split(":", 1)
             fields[k.strip()] = v.strip().strip("`")
     try:
-        src_hash = hashlib.sha256(open(SELL_SOURCE, "rb").read()).hexdigest()
-        if fields.get("sell.hip sha256") != src_hash:
+        if fields.get("sources sha256") != sources_hash():
             return None
-        fetch = float(fields["FETCH_SIZE KiB per dispatch"]) * float(fields["FETCH_SIZE scale"])
-        write = float(fields["WRITE_SIZE KiB per dispatch"]) * float(fields["WRITE_SIZE scale"])
+        return float(fields["apply HBM bytes"])
     except (KeyError, ValueError, OSError):
         return None
-    return (fetch + write) * 1024.0
 
 
-def cpu_baseline(X, y, lam, labels, fc, step_iters, budget_s=12.0):
-    """The oracle's two-level PCG (FP64 SciPy/NumPy, BLAS held to one thread)
-    timed for whole iterations: solves of 64 iterations (fewer than the 77
-    the lambda = 1 system needs, so none runs past convergence) repeated
-    until `budget_s` has passed; seconds per iteration times the step's
-    iteration count gives the CPU figure for one step."""
+def oracle_reference(X, y, lams, labels, fc, log):
+    """The oracle's V(1,1) two-level PCG (FP64 SciPy/NumPy, BLAS held to one
+    thread) on the GPU's aggregation, run to relative residual 1e-13 per
+    lambda: its solution is the reference w*, and its time per iteration
+    gives the CPU baseline."""
     from threadpoolctl import threadpool_limits
     from oracle import krylov, operator as op, precond
-    cores = len(os.sched_getaffinity(0))
-    k = 64
+    out = {}
     with threadpool_limits(limits=1):
-        omega = op.omega_gershgorin(X, lam)
-        B, _ = precond.make("vcycle", X, lam, labels, fc, omega)
         b = op.rhs(X, y)
-        A = lambda v: op.apply_A(X, lam, v)
-        reps, spent = 0, 0.0
-        while spent < budget_s:
+        for lam in lams:
+            omega = op.omega_gershgorin(X, lam)
+            B, _ = precond.make("vcycle", X, lam, labels, fc, omega)
+            A = lambda v, lam=lam: op.apply_A(X, lam, v)
             t0 = time.perf_counter()
-            krylov.pcg(A, b, B, fixed_iters=k)
-            spent += time.perf_counter() - t0
-            reps += 1
-    t_iter = spent / (reps * k)
-    return {"value": t_iter * step_iters, "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} solves of {k} iterations ({reps * k} in all, {spent:.1f} s) of the "
-                      f"oracle's V(1,1) two-level PCG at lambda=1 on the same matrix (seeded random "
-                      f"aggregation, F_C={fc}; one thread: SciPy sparse products are single-threaded "
-                      f"and BLAS is held to one thread; {cores} cores visible), "
-                      f"{t_iter * 1e3:.1f} ms per iteration, scaled to the step's {step_iters} "
-                      f"iterations"}
+            x, inf = krylov.pcg(A, b, B, tol=1e-13, max_iter=400)
+            dt = time.perf_counter() - t0
+            k10 = next((k for k, h in enumerate(inf.history) if h <= 1e-10), None)
+            out[lam] = {"w": x, "iters": inf.iters, "iters_relres_1e-10": k10, "s": dt,
+                        "s_per_iter": dt / max(1, inf.iters), "true_relres": inf.true_relres}
+            log(f"[bench oracle] lambda={lam}: {inf.iters} iterations to relres 1e-13 in {dt:.1f} s "
+                f"(relres 1e-10 at iteration {k10}), true relres {inf.true_relres:.1e}")
+    return out
+
+
+def valued_operator_section(rr, torch, dev, log, P):
+    """The operator of the same 0/1 matrix stored with FP64 values (CSR and
+    CSC with 8-byte values: 294.8 MB per application, larger than the 256 MB
+    Infinity Cache): 50 back-to-back applications timed with HIP events on
+    the current stream."""
+    N, F = P.X.shape
+    nnz = P.X.nnz
+    R = rr.Ridge(P.X, n_clusters=0, binary=False)
+    v = torch.randn(F, dtype=torch.float64, device=dev, generator=torch.Generator(device=dev).manual_seed(3))
+    out = torch.empty_like(v)
+    for _ in range(5):
+        rr.rr_apply_operator(R.h, 1.0, v, out)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 50
+    e0.record()
+    for _ in range(reps):
+        rr.rr_apply_operator(R.h, 1.0, v, out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    R.close()
+    b = apply_bytes_valued(N, F, nnz)
+    gbs = b / (ms * 1e-3) / 1e9
+    log(f"[bench valued] FP64-valued operator: {ms * 1e3:.1f} us per application, {gbs:.0f} GB/s "
+        f"({gbs / HBM_PEAK_GBS:.3f} of HBM peak)")
+    return {"apply_bytes": b, "apply_ms": ms, "apply_gbs": gbs, "frac": gbs / HBM_PEAK_GBS,
+            "kernels": "rr::k_csr (row groups) and the merge-path column pass (rr::k_segsum, "
+                       "rr::k_segfix)"}
 
 
 def dense_section(rr, torch, dev, log):
@@ -303,22 +345,24 @@ def leader_section(rr, torch, dev, log, P, R, tol=24.0):
     return out
 
 
-def ls_interp_part(rr, torch, dev, RL, y, w, n_proto=8, sweeps=30):
+def ls_interp_part(rr, torch, dev, RL, y, w, n_proto=8, steps=40):
     """Least-squares interpolation on the leader-follower aggregation of
     RL.  The prototypes are the n_proto leading principal components of
-    X^T X, from `sweeps` steps of subspace iteration (products through
-    rr_apply_operator, orthonormalisation on the host) before any timing;
-    rr_set_interpolation then runs at beta = lambda for every lambda, and a
-    V(1,1) PCG solve to relative residual 1e-10 follows."""
+    X^T X from rr_prototypes (`steps` Lanczos steps with full
+    reorthogonalisation on the GPU), before any timing; rr_set_interpolation
+    then runs at beta = lambda for every lambda, and a V(1,1) PCG solve to
+    relative residual 1e-10 follows."""
     import numpy as np
     F = RL.F
-    Q = np.linalg.qr(np.random.default_rng(5826).standard_normal((F, n_proto)))[0]
-    for _ in range(sweeps):
-        Qd = torch.as_tensor(Q, device=dev)
-        Z = np.stack([RL.apply_operator(0.0, Qd[:, k].contiguous()).cpu().numpy()
-                      for k in range(n_proto)], axis=1)
-        Q = np.linalg.qr(Z)[0]
-    out = {"prototypes": n_proto, "subspace_sweeps": sweeps, "per_lambda": {}}
+    V = torch.empty((n_proto, F), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev = rr.rr_prototypes(RL.h, n_proto, V, steps=steps)
+    torch.cuda.synchronize()
+    proto_ms = (time.perf_counter() - t0) * 1e3
+    Q = V.t().contiguous().cpu().numpy()
+    out = {"prototypes": n_proto, "lanczos_steps": steps, "prototype_ms": proto_ms,
+           "ritz_values": [float(x) for x in ev], "per_lambda": {}}
     for lam in (1e-2, 1.0, 100.0):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -336,14 +380,16 @@ def ls_interp_part(rr, torch, dev, RL, y, w, n_proto=8, sweeps=30):
     return out
 
 
-def batched_uneven_section(rr, torch, dev, log, full=False):
-    """Independent uneven problems in one rr_solve_batched call against one
-    rr_solve call after another: the batched-uneven workload's generator
+def batched_uneven_section(rr, torch, dev, log, full=True):
+    """Independent uneven problems: the batched-uneven workload's generator
     (binary entries, density 1-5 %, Zipf columns, lambda log-uniform in
-    [1e-3, 10], k = ceil(d / 10) clamped to [8, 800], tolerance 1e-8).  By
-    default 100 problems at n in [500, 5000] and d in [200, 2000], so setup
-    stays within seconds; with ``full`` the whole workload, 500 problems at
-    n in [500, 20000] and d in [200, 8000]."""
+    [1e-3, 10], k = ceil(d / 10) clamped to [8, 800], relative residual 1e-8),
+    by default the whole workload: 500 problems, n in [500, 20000], d in
+    [200, 8000]; with ``full`` False 100 problems at n in [500, 5000] and d
+    in [200, 2000].  Times every problem in one persistent kernel launch
+    (replayed from a HIP graph) against the stream form of rr_solve_batched
+    (a work set and a stream per problem, iteration chunks replayed from HIP
+    graphs) and, for the small batch, one rr_solve after another."""
     import numpy as np
     import datagen
     n_problems, n_range, d_range = (500, (500, 20_000), (200, 8_000)) if full else \
@@ -353,8 +399,7 @@ def batched_uneven_section(rr, torch, dev, log, full=False):
                                      workers=min(16, os.cpu_count() or 1) if full else 1)
     gen_s = time.perf_counter() - t0
     nnz = int(sum(P.X.nnz for P, _ in batch))
-    if full:
-        log(f"[bench batched] generated {n_problems} problems, {nnz / 1e6:.1f} M nnz in {gen_s:.1f} s")
+    log(f"[bench batched] generated {n_problems} problems, {nnz / 1e6:.1f} M nnz in {gen_s:.1f} s")
     t0 = time.perf_counter()
     Rs, rhs, ws, lams = [], [], [], []
     for i, (P, lam) in enumerate(batch):
@@ -363,55 +408,69 @@ def batched_uneven_section(rr, torch, dev, log, full=False):
         rhs.append(torch.as_tensor(P.y, dtype=torch.float64, device=dev))
         ws.append(torch.empty(P.X.shape[1], dtype=torch.float64, device=dev))
         lams.append(lam)
-        if full and (i + 1) % 50 == 0:
+        if (i + 1) % 100 == 0:
             log(f"[bench batched] set up {i + 1} problems ({time.perf_counter() - t0:.1f} s)")
+    shapes = [(P.X.shape[0], P.X.shape[1], P.X.nnz) for P, _ in batch]
+    del batch
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    # warm the paths once (per-lambda coarse factors are then cached)
-    if not full:
-        for R, lam, b, w in zip(Rs, lams, rhs, ws):
-            rr.rr_solve(R.h, lam, b, w, tol=1e-8, precond="vcycle", max_iter=5000, raise_on=(1, 2, 6))
-    rr.rr_solve_batched([R.h for R in Rs], lams, rhs, ws, tol=1e-8, precond="vcycle", max_iter=5000)
-    if full:
+    hs = [R.h for R in Rs]
+    kw = dict(tol=1e-8, precond="vcycle", max_iter=5000)
+
+    def timed(f):
         torch.cuda.synchronize()
-        log(f"[bench batched] warm-up done ({time.perf_counter() - t0:.1f} s)")
-    torch.cuda.synchronize()
-    ta = time.perf_counter()
-    iters_seq = []
-    for R, lam, b, w in zip(Rs, lams, rhs, ws):
-        st, inf = rr.rr_solve(R.h, lam, b, w, tol=1e-8, precond="vcycle", max_iter=5000,
-                              raise_on=(1, 2, 6))
-        iters_seq.append(inf["iters"])
-    torch.cuda.synchronize()
-    seq_ms = (time.perf_counter() - ta) * 1e3
-    ta = time.perf_counter()
-    st, infos = rr.rr_solve_batched([R.h for R in Rs], lams, rhs, ws, tol=1e-8, precond="vcycle",
-                                    max_iter=5000)
-    torch.cuda.synchronize()
-    bat_ms = (time.perf_counter() - ta) * 1e3
-    ok = st == 0 and all(i["status"] == 0 for i in infos)
-    same = [i["iters"] for i in infos] == iters_seq
-    # the same with every problem's iteration chunks replayed from HIP graphs
-    rr.rr_solve_batched([R.h for R in Rs], lams, rhs, ws, tol=1e-8, precond="vcycle", max_iter=5000,
-                        chunk=16, graph=True)
-    torch.cuda.synchronize()
-    ta = time.perf_counter()
-    st, infos_g = rr.rr_solve_batched([R.h for R in Rs], lams, rhs, ws, tol=1e-8, precond="vcycle",
-                                      max_iter=5000, chunk=16, graph=True)
-    torch.cuda.synchronize()
-    graph_ms = (time.perf_counter() - ta) * 1e3
-    ok = ok and st == 0 and all(i["status"] == 0 for i in infos_g)
+        ta = time.perf_counter()
+        r = f()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - ta) * 1e3
+
+    # warm-up (per-lambda coarse factors are then cached, the launch graph captured)
+    rr.rr_solve_batched(hs, lams, rhs, ws, persistent=True, graph=True, **kw)
+    (st_p, inf_p), pers_ms = timed(lambda: rr.rr_solve_batched(hs, lams, rhs, ws, persistent=True,
+                                                               graph=True, **kw))
+    log(f"[bench batched] persistent launch: {pers_ms:.1f} ms")
+    rr.rr_solve_batched(hs, lams, rhs, ws, chunk=16, graph=True, **kw)
+    (st_g, inf_g), graph_ms = timed(lambda: rr.rr_solve_batched(hs, lams, rhs, ws, chunk=16, graph=True,
+                                                                **kw))
+    log(f"[bench batched] stream work sets with graph replay: {graph_ms:.1f} ms")
+    seq_ms = None
+    if not full:
+        def seq():
+            return [rr.rr_solve(h, lam, b, w, raise_on=(1, 2, 6), **kw)[1]["iters"]
+                    for h, lam, b, w in zip(hs, lams, rhs, ws)]
+        seq()
+        _, seq_ms = timed(seq)
+    ok = st_p == 0 and st_g == 0 and all(i["status"] == 0 for i in inf_p + inf_g)
+    it_p = [i["iters"] for i in inf_p]
+    it_g = [i["iters"] for i in inf_g]
+    # the two paths add in different orders: iteration counts at the natural
+    # stop agree within 1 + 2 %
+    within_band = all(abs(a - b) <= 1 + 0.02 * b for a, b in zip(it_p, it_g))
     for R in Rs:
         R.close()
+    # the persistent launch's schedule: each problem's time on its workgroup
+    # (rr_solve_info.ms), the busy fraction of the workgroups over the launch
+    # and the longest problems
+    busy = [i["ms"] for i in inf_p]
+    grid = min(n_problems, torch.cuda.get_device_properties(0).multi_processor_count)
+    util = sum(busy) / (grid * pers_ms)
+    top = sorted(range(n_problems), key=lambda i: -busy[i])[:5]
+    log(f"[bench batched] persistent: workgroups busy {100 * util:.0f} % of the launch; longest problems "
+        + ", ".join(f"{busy[i]:.0f} ms ({it_p[i]} it, {shapes[i][0]}x{shapes[i][1]}, "
+                    f"{shapes[i][2] / 1e6:.2f} M nnz)" for i in top))
     log(f"[bench batched] {n_problems} problems, {nnz / 1e6:.1f} M nnz (generated {gen_s:.1f} s, "
-        f"setup {setup_s:.1f} s): sequential {seq_ms:.1f} ms, batched {bat_ms:.1f} ms "
-        f"({seq_ms / bat_ms:.2f}x), with graphs {graph_ms:.1f} ms ({seq_ms / graph_ms:.2f}x), "
-        f"all converged {ok}, same iterations {same}")
-    return {"problems": n_problems, "nnz": nnz, "n_range": list(n_range), "d_range": list(d_range),
-            "tol": 1e-8, "setup_s": setup_s, "sequential_ms": seq_ms, "batched_ms": bat_ms,
-            "speedup": seq_ms / bat_ms, "batched_graph_ms": graph_ms,
-            "graph_speedup": seq_ms / graph_ms, "all_converged": ok, "same_iterations": same,
-            "total_iters": int(sum(iters_seq))}
+        f"setup {setup_s:.1f} s): persistent {pers_ms:.1f} ms, stream+graphs {graph_ms:.1f} ms "
+        f"({graph_ms / pers_ms:.2f}x), all converged {ok}, iterations within 1 + 2 % {within_band}")
+    out = {"problems": n_problems, "nnz": nnz, "n_range": list(n_range), "d_range": list(d_range),
+           "tol": 1e-8, "setup_s": setup_s, "persistent_ms": pers_ms, "batched_graph_ms": graph_ms,
+           "persistent_vs_graph": graph_ms / pers_ms, "all_converged": ok,
+           "iterations_within_band": within_band, "total_iters": int(sum(it_p)),
+           "max_iters": int(max(it_p)), "persistent_busy_fraction": util,
+           "persistent_longest_ms": [busy[i] for i in top]}
+    if seq_ms is not None:
+        out["sequential_ms"] = seq_ms
+        out["persistent_vs_sequential"] = seq_ms / pers_ms
+    return out
 
 
 def main():
@@ -423,9 +482,11 @@ def main():
     ap.add_argument("--k", type=int, default=1000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a plain 256 MiB device copy (scale for memory counters)")
-    ap.add_argument("--batched-full", action="store_true",
-                    help="run only the batched uneven-problem section, at its full size (500 "
-                         "problems up to 20000 x 8000; minutes of setup)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched uneven-problem section (500 problems up to "
+                         "20000 x 8000)")
+    ap.add_argument("--batched-small", action="store_true",
+                    help="run the batched uneven-problem section on 100 problems up to 5000 x 2000")
     ap.add_argument("--no-dense", action="store_true",
                     help="skip the dense many-rhs and batched uneven-problem sections")
     ap.add_argument("--dense-only", action="store_true",
@@ -451,8 +512,9 @@ def main():
     if args.dense_only:
         print(json.dumps({"dense_many_rhs": dense_section(rr, torch, dev, log)}), flush=True)
         return
-    if args.batched_full:
-        print(json.dumps({"batched_uneven": batched_uneven_section(rr, torch, dev, log, full=True)}),
+    if args.batched_only:
+        print(json.dumps({"batched_uneven": batched_uneven_section(rr, torch, dev, log,
+                                                                   full=not args.batched_small)}),
               flush=True)
         return
     P = datagen.chembl_like()
@@ -468,20 +530,36 @@ def main():
     y = torch.as_tensor(P.y, dtype=torch.float64, device=dev)
     w = torch.empty(F, dtype=torch.float64, device=dev)
 
-    # calibration: reference solutions and the iteration reaching 1e-10 error
+    # calibration: the oracle's solution on the GPU's aggregation is the
+    # reference; each lambda's fixed count is the GPU's first iteration within
+    # 1e-10 relative error of it (with --no-cpu the GPU's own solve to 1e-14
+    # serves as the reference instead)
     calib = {}
     wrefs = {}
+    orc = None
+    if not args.no_cpu:
+        labels = R.labels().cpu().numpy()
+        orc = oracle_reference(P.X, P.y, lams, labels, sinfo["n_coarse"], log)
     for lam in lams:
-        st, inf_ref = rr.rr_solve(R.h, lam, y, w, tol=1e-14, max_iter=3000, precond="vcycle",
-                                  raise_on=(1, 2, 6))
-        wref = w.clone()
+        if orc is not None:
+            wref = torch.as_tensor(orc[lam]["w"], dtype=torch.float64, device=dev)
+            st, inf_ref = rr.rr_solve(R.h, lam, y, w, tol=1e-13, max_iter=3000, precond="vcycle",
+                                      raise_on=(1, 2, 6))
+        else:
+            st, inf_ref = rr.rr_solve(R.h, lam, y, w, tol=1e-14, max_iter=3000, precond="vcycle",
+                                      raise_on=(1, 2, 6))
+            wref = w.clone()
         wrefs[lam] = wref
         st, inf = rr.rr_solve(R.h, lam, y, w, tol=1e-300, x_ref=wref, err_tol=1e-10,
                               max_iter=3000, precond="vcycle", raise_on=(1, 2, 6))
         calib[lam] = {"iters": inf["iters"], "err": inf["err"], "ref_iters": inf_ref["iters"],
                       "ref_true_relres": inf_ref["true_relres"], "coarse_ms": inf_ref["coarse_ms"]}
+        if orc is not None:
+            calib[lam]["oracle_iters_to_relres_1e-10"] = orc[lam]["iters_relres_1e-10"]
+            calib[lam]["gpu_iters_to_relres_1e-10"] = rr.rr_solve(
+                R.h, lam, y, w, tol=1e-10, max_iter=3000, precond="vcycle", raise_on=(1, 2, 6))[1]["iters"]
         print(f"[bench] lambda={lam}: {inf['iters']} iterations to rel. error {inf['err']:.2e} "
-              f"(reference: {inf_ref['iters']} its, true relres {inf_ref['true_relres']:.1e})",
+              f"against the {'oracle' if orc is not None else 'GPU'} reference",
               file=sys.stderr, flush=True)
 
     def step(profile=False):
@@ -502,6 +580,12 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
+    # the timed solves' iterates against the reference
+    err_final = {}
+    for lam in lams:
+        rr.rr_solve(R.h, lam, y, w, fixed_iters=calib[lam]["iters"], precond="vcycle", chunk=16,
+                    raise_on=(1, 2, 6))
+        err_final[lam] = float(torch.linalg.norm(w - wrefs[lam]) / torch.linalg.norm(wrefs[lam]))
     # kernel timing with HIP events recorded by the library on its stream
     prof = step(profile=True)
     torch.cuda.synchronize()
@@ -513,6 +597,9 @@ def main():
     gbs_gather = b_gather / (gcsc_ms * 1e-3) / 1e9
     b_apply = apply_bytes(N, F, nnz)
     gbs_op = b_apply / ((csc_ms + csr_ms) * 1e-3) / 1e9
+    # the HBM-resident case: the same matrix with FP64 values stored both ways
+    # (295 MB per application, more than the 256 MB Infinity Cache)
+    valued = valued_operator_section(rr, torch, dev, log, P)
 
     # other forms for comparison (untimed calibration, one timed solve each)
     compare = {}
@@ -590,24 +677,22 @@ def main():
         batched[name + "_iters"] = its
     batched["speedup"] = batched["plain_ms"] / batched["batched_ms"]
 
-    # mixed precision: FP32 inner V(1,1) PCG inside FP64 refinement; per
-    # lambda the loosest outer residual whose solution is within 1e-10
-    # relative error of the FP64 reference
-    mixed = {"per_lambda": {}}
+    # mixed precision: FP64 flexible CG (one direction kept) whose V(1,1)
+    # cycle runs in FP32, each lambda run for the iterations that reach
+    # relative error 1e-10 against the reference (calibrated as for the plain
+    # step), against the plain step; the refinement form (FP32 inner PCG
+    # restarted at every refinement step) is timed once beside it
+    mixed = {"form": "f32_cycle: FP64 FCG(1), Krylov space and operator FP64, V(1,1) cycle in FP32",
+             "per_lambda": {}}
+    mk = dict(precond="vcycle", krylov="fcg", fcg_m=1, precision="f32_cycle")
     for lam in lams:
-        for otol in (1e-10, 3e-11, 1e-11, 3e-12, 1e-12, 3e-13, 1e-13):
-            st, inf = rr.rr_solve(R.h, lam, y, w, tol=otol, max_iter=3000, precond="vcycle",
-                                  precision="f32_ir", chunk=16, raise_on=(1, 2, 6))
-            err = float(torch.linalg.norm(w - wrefs[lam]) / torch.linalg.norm(wrefs[lam]))
-            if err <= 1e-10:
-                break
-        mixed["per_lambda"][str(lam)] = {"outer_tol": otol, "err": err, "ir_steps": inf["ir_steps"],
-                                         "inner_iters": inf["iters"]}
+        st, inf = rr.rr_solve(R.h, lam, y, w, tol=1e-300, x_ref=wrefs[lam], err_tol=1e-10,
+                              max_iter=3000, raise_on=(1, 2, 6), **mk)
+        mixed["per_lambda"][str(lam)] = {"iters": inf["iters"], "err": inf["err"]}
     def mixed_step():
         for lam in lams:
-            rr.rr_solve(R.h, lam, y, w, tol=mixed["per_lambda"][str(lam)]["outer_tol"],
-                        max_iter=3000, precond="vcycle", precision="f32_ir", chunk=16,
-                        raise_on=(1, 2, 6))
+            rr.rr_solve(R.h, lam, y, w, fixed_iters=mixed["per_lambda"][str(lam)]["iters"], chunk=16,
+                        raise_on=(1, 2, 6), **mk)
     mixed_step()
     torch.cuda.synchronize()
     ta = time.perf_counter()
@@ -616,6 +701,19 @@ def main():
     torch.cuda.synchronize()
     mixed["ms_per_step"] = (time.perf_counter() - ta) * 1e3 / 3
     mixed["vs_plain"] = ms_per_step / mixed["ms_per_step"]
+    ir = {}
+    for lam in lams:
+        for otol in (1e-10, 3e-11, 1e-11, 3e-12, 1e-12, 3e-13, 1e-13):
+            st, inf = rr.rr_solve(R.h, lam, y, w, tol=otol, max_iter=3000, precond="vcycle",
+                                  precision="f32_ir", chunk=16, raise_on=(1, 2, 6))
+            err = float(torch.linalg.norm(w - wrefs[lam]) / torch.linalg.norm(wrefs[lam]))
+            if err <= 1e-10:
+                break
+        ir[str(lam)] = {"outer_tol": otol, "err": err, "ir_steps": inf["ir_steps"],
+                        "inner_iters": inf["iters"], "ms": inf["ms"]}
+    mixed["refinement"] = {"per_lambda": ir, "ms_per_step": sum(v["ms"] for v in ir.values())}
+    log(f"[bench mixed] FP32 cycle: {mixed['ms_per_step']:.1f} ms per step ({mixed['vs_plain']:.2f}x "
+        f"the FP64 step); refinement {mixed['refinement']['ms_per_step']:.1f} ms")
 
     # learned coarse correction: about 10,000 pairs from V(1,1) solves at
     # lambda log-uniform in [1e-2, 100], Adam on the BF16 network, then
@@ -639,8 +737,30 @@ def main():
     torch.cuda.synchronize()
     learned.update({"pairs": npairs, "train_s": time.perf_counter() - ta, "epochs": 60,
                     "loss_first": hist[0], "loss_last": hist[-1]})
-    for name, kw in (("learned_fcg", dict(precond="learned", krylov="fcg", fcg_m=4)),
-                     ("vcycle_pcg", dict(precond="vcycle")),
+    def learned_solve():
+        kw = dict(precond="learned", krylov="fcg", fcg_m=4)
+        st, inf = rr.rr_solve(R.h, 1.0, y, w, tol=1e-10, max_iter=5000, chunk=8, raise_on=(1, 2, 6), **kw)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        st, inf = rr.rr_solve(R.h, 1.0, y, w, tol=1e-10, max_iter=5000, chunk=8, raise_on=(1, 2, 6), **kw)
+        torch.cuda.synchronize()
+        return {"iters": inf["iters"], "ms": (time.perf_counter() - ta) * 1e3,
+                "true_relres": inf["true_relres"], "fallback_iter": inf["fallback_iter"]}
+    learned["learned_fcg"] = learned_solve()
+    # a second round on-policy: pairs from the network's own solves (the
+    # residual directions a solve it steers produces), 20 more epochs on the
+    # union of both sets
+    llams2 = llams[:100]
+    inp2 = torch.empty((len(llams2) * per, fc + 1), dtype=torch.float32, device=dev)
+    tgt2 = torch.empty((len(llams2) * per, fc), dtype=torch.float32, device=dev)
+    n2 = rr.rr_collect_pairs_learned(R.h, llams2, per, 1, y, inp2, tgt2)
+    hist2 = rr.rr_mlp_train(R.h, torch.cat([inp[:npairs], inp2[:n2]]).contiguous(),
+                            torch.cat([tgt[:npairs], tgt2[:n2]]).contiguous(), epochs=20, batch=256,
+                            lr=5e-4, seed=6)
+    learned["on_policy_pairs"] = n2
+    learned["on_policy_loss_last"] = hist2[-1]
+    learned["learned_fcg_on_policy"] = learned_solve()
+    for name, kw in (("vcycle_pcg", dict(precond="vcycle")),
                      ("jacobi_fcg", dict(precond="jacobi", krylov="fcg", fcg_m=4))):
         st, inf = rr.rr_solve(R.h, 1.0, y, w, tol=1e-10, max_iter=5000, chunk=8, raise_on=(1, 2, 6), **kw)
         torch.cuda.synchronize()
@@ -652,15 +772,23 @@ def main():
 
     total_iters = sum(calib[l]["iters"] for l in lams)
     cpu = None
-    if not args.no_cpu:
-        labels = datagen.random_labels(F, args.k, 11)
-        cpu = cpu_baseline(P.X, P.y, 1.0, labels, args.k, total_iters)
+    if orc is not None:
+        cpu_s = sum(orc[l]["s_per_iter"] * calib[l]["iters"] for l in lams)
+        cores = len(os.sched_getaffinity(0))
+        cpu = {"value": cpu_s, "unit": "s", "cores": 1, "kind": "oracle",
+               "sample": "the oracle's three reference solves (V(1,1) two-level PCG on the GPU's "
+                         "k-means aggregation, lambda in {1e-2, 1, 100}, to relative residual 1e-13: "
+                         + ", ".join(f"{orc[l]['iters']} iterations in {orc[l]['s']:.1f} s" for l in lams)
+                         + f") on one thread (SciPy sparse products are single-threaded and BLAS is "
+                           f"held to one thread; {cores} cores visible); seconds per iteration of "
+                           f"each lambda times the step's iteration count for it"}
 
     bayes = None if args.no_dense else bayes_section(rr, torch, dev, log, P, R, args.k)
     newton = None if args.no_dense else newton_section(rr, torch, dev, log, P, args.k)
     lf = None if args.no_dense else leader_section(rr, torch, dev, log, P, R)
     dense = None if args.no_dense else dense_section(rr, torch, dev, log)
-    uneven = None if args.no_dense else batched_uneven_section(rr, torch, dev, log)
+    uneven = None if args.no_dense else batched_uneven_section(rr, torch, dev, log,
+                                                               full=not args.batched_small)
 
     line = {
         "metric": METRIC,
@@ -684,8 +812,13 @@ def main():
             "n_clusters": args.k,
             "n_coarse": sinfo["n_coarse"],
         },
-        "per_lambda": {str(l): {"iters": calib[l]["iters"], "ms": last[l]["ms"],
-                                "err": calib[l]["err"], "coarse_factor_ms": calib[l]["coarse_ms"]}
+        "reference": "oracle" if orc is not None else "gpu",
+        "per_lambda": {str(l): {"iters": last[l]["iters"], "ms": last[l]["ms"],
+                                "err": calib[l]["err"],
+                                "err_final": err_final[l],
+                                "coarse_factor_ms": calib[l]["coarse_ms"],
+                                "oracle_iters_to_relres_1e-10": calib[l].get("oracle_iters_to_relres_1e-10"),
+                                "gpu_iters_to_relres_1e-10": calib[l].get("gpu_iters_to_relres_1e-10")}
                        for l in lams},
         "setup_ms": sinfo["setup_ms"],
         "autotune": {"plan_ms": sinfo["plan_ms"], "rows_div": sinfo["tuned_rows_div"],
@@ -704,10 +837,19 @@ def main():
         "bayes_noise_injection": bayes,
         "newton_logistic": newton,
         "leader_follower": lf,
-        "roofline": {"bound": "hbm", "achieved": gbs_gather, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs_gather / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "rr::k_sell<1> (column-pass gather of t = X^T u through LDS slices)",
-                     "bytes_per_launch": b_gather, "ms_per_launch": gcsc_ms},
+        "operator_valued_f64": valued,
+        "roofline": {"bound": "hbm", "achieved": gbs_op, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs_op / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "kernel": "one operator application q = X^T (X p) + lambda p (rr::k_rows row "
+                               "pass, rr::k_sell<1> column gather, rr::k_sell_reduce<2> column sums "
+                               "and epilogue), HIP events on the solve's stream around each pass "
+                               "inside the timed solves",
+                     "bytes_per_launch": b_apply, "ms_per_launch": csr_ms + csc_ms,
+                     "cache_resident": "the pattern's index arrays and vectors (about 60 MB) stay in "
+                                       "the 256 MB Infinity Cache between passes; operator_valued_f64 "
+                                       "is the HBM-resident case",
+                     "column_gather": {"kernel": "rr::k_sell<1>", "bytes": b_gather, "ms": gcsc_ms,
+                                       "gbs": gbs_gather, "frac": gbs_gather / HBM_PEAK_GBS}},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -65,6 +65,7 @@ typedef enum {
   RR_OK = 0,
   RR_ERR_INVALID_ARG = 1,   /* bad size, pointer, option or input matrix   */
   RR_ERR_DEVICE = 2,        /* a HIP call failed                            */
+  RR_ERR_WORKSPACE = 3,     /* the caller's workspace is too small          */
   RR_ERR_NOT_CONVERGED = 4, /* max_iter reached; w holds the last iterate   */
   RR_ERR_BREAKDOWN = 5,     /* <p,Ap> or <r,z> not positive / not finite    */
   RR_ERR_UNSUPPORTED = 6    /* valid request this build does not implement  */
@@ -86,8 +87,11 @@ typedef enum {
                               (rr_mlp_init / rr_mlp_train); no coarse Cholesky
                               is applied; nonlinear, so flexible CG only; after
                               an iteration chunk that reduces ||r|| by less than
-                              10 % the solve continues with RR_PRECOND_VCYCLE
-                              (info.fallback_iter)                               */
+                              10 %, or a step whose <p,Ap> is not positive and
+                              finite or whose <p,r> is not finite (a network
+                              giving NaN or Inf), the solve continues from the
+                              last good iterate with RR_PRECOND_VCYCLE and a
+                              fresh flexible-CG history (info.fallback_iter)   */
   RR_PRECOND_ROUGHER = 5   /* the configuration of the paper's experiments
                               (TLFCG): rougher_steps iterations of plain CG on
                               A e = r from e = 0 as pre-smoother, then
@@ -119,7 +123,14 @@ typedef struct {
   const float* values;     /* device float[N * ld], finite                     */
 } rr_dense;
 
+/* Option structs are versioned: struct_size must hold sizeof(the struct) as
+ * the caller's copy of this header defines it.  The library reads that many
+ * bytes; fields past them (a caller built against an older header) take
+ * their defaults.  struct_size = 0 is rejected (RR_ERR_INVALID_ARG), so a
+ * zero-initialised struct must still set it.  A NULL options pointer means
+ * every default. */
 typedef struct {
+  uint32_t struct_size;    /* sizeof(rr_setup_opts)                             */
   int32_t n_clusters;      /* k >= 1: k-means++ clusters of the feature columns;
                               0: no coarse level (only NONE/JACOBI solves)      */
   int32_t kmeans_max_iter; /* Lloyd assignment passes; 0 -> 100                 */
@@ -159,7 +170,18 @@ typedef struct {
                               it becomes the next leader; leaders are not
                               updated.  n_clusters is then ignored and
                               rr_get_centres returns the leaders in creation
-                              order.  At most 38,400 clusters               */
+                              order.  At most 18,944 clusters (the exact
+                              integer coarse Gram matrix keeps a histogram of
+                              F_C counts per workgroup in LDS)              */
+  /* Buffers of later solves, reserved here so that those solves allocate
+   * nothing (see "Device memory" below).  Solves that need more than was
+   * reserved allocate it then, or fail with RR_ERR_WORKSPACE on a handle
+   * set up on a caller workspace. */
+  int32_t reserve_fcg_m;   /* flexible-CG directions (fcg_m of later solves)   */
+  int32_t reserve_sets;    /* work sets beyond the handle's own, for
+                              rr_solve_batched with the handle several times */
+  int32_t reserve_f32;     /* 1: the vectors of RR_PREC_F32_IR solves (0/1 X) */
+  int32_t reserved0;
 } rr_setup_opts;
 
 /*
@@ -180,6 +202,47 @@ rr_status rr_setup(const rr_csr* X, const rr_setup_opts* opts, rr_stream stream,
 
 /* Release a handle and its device memory (NULL is a no-op). */
 rr_status rr_destroy(rr_handle* h);
+
+/*
+ * Device memory.  A handle takes its device memory, at setup and whenever a
+ * later call needs more (for instance a larger flexible-CG ring than was
+ * reserved), from one of three sources, fixed when it is set up:
+ *   - a caller workspace (rr_setup_ws): the handle lives inside that buffer,
+ *     which the caller allocates (for instance as a PyTorch tensor), keeps
+ *     alive and unmodified until rr_destroy, and frees afterwards.  The
+ *     library never frees it; a request that does not fit fails with
+ *     RR_ERR_WORKSPACE;
+ *   - the caller's allocator installed with rr_set_allocator when the handle
+ *     was set up (the Python binding installs PyTorch's caching allocator):
+ *     alloc(bytes, device, ctx) returns device memory or NULL, free(ptr,
+ *     device, ctx) takes it back; the library frees only after synchronising
+ *     the device, so no queued work still uses the block;
+ *   - otherwise hipMalloc / hipFree.
+ * Once a handle's solve buffers are reserved (rr_setup_opts.reserve_*),
+ * rr_solve, rr_solve_batched (with distinct handles or reserved work sets,
+ * lambdas whose factors fit the lambda_slots) and the operator and
+ * preconditioner calls allocate no device memory.  The persistent batched
+ * solve keeps per-device descriptor buffers, taken from the allocator current
+ * at their first use and grown when a larger batch arrives.
+ */
+typedef void* (*rr_alloc_fn)(size_t bytes, int32_t device, void* ctx);
+typedef void (*rr_free_fn)(void* ptr, int32_t device, void* ctx);
+/* Install (both functions) or remove (both NULL) the caller's allocator for
+ * handles set up from now on; existing handles keep their source. */
+rr_status rr_set_allocator(rr_alloc_fn alloc, rr_free_fn free_fn, void* ctx);
+
+/* *bytes = the workspace rr_setup_ws needs for this X and these options.
+ * Computed exactly by running the setup once (with hipMalloc memory that is
+ * released before returning): setup is deterministic, so an identical
+ * rr_setup_ws call makes the same requests.  Costs one setup. */
+rr_status rr_setup_workspace_size(const rr_csr* X, const rr_setup_opts* opts, rr_stream stream,
+                                  size_t* bytes);
+
+/* rr_setup with every device allocation of the handle carved out of the
+ * caller's workspace (device memory, 256-byte aligned, ws_bytes bytes; too
+ * small: RR_ERR_WORKSPACE).  The workspace must outlive the handle. */
+rr_status rr_setup_ws(const rr_csr* X, const rr_setup_opts* opts, void* workspace, size_t ws_bytes,
+                      rr_stream stream, rr_handle** out);
 
 typedef struct {
   int64_t n_rows, n_cols, nnz;
@@ -222,12 +285,21 @@ typedef enum {
                               Dense X (rr_solve_block): corrections with the
                               FP32-operand operator (FP32 matrix-core sums, U
                               in FP32) and FP64 vectors; inner_tol default 1e-5 */
-  RR_PREC_BF16_IR = 2      /* dense X (rr_solve_block): iterative refinement
+  RR_PREC_BF16_IR = 2,     /* dense X (rr_solve_block): iterative refinement
                               whose corrections run PCG with a BF16-operand
                               operator (X and the input block rounded to BF16,
                               FP32 matrix-core sums, U = X V rounded to BF16),
                               FP64 vectors, scalars and coarse solve; the
                               residual b - A x uses the FP64 operator           */
+  RR_PREC_F32_CYCLE = 3    /* 0/1 X, V(1,1), flexible CG: the Krylov space, its
+                              operator q = A p, x, r and every scalar stay FP64
+                              (so the solve reaches the FP64 tolerance without
+                              restarts); the preconditioner's cycle runs in FP32
+                              (r rounded, its two operator applications and
+                              smoothing in FP32, the coarse solve in FP64) and
+                              z is widened back.  Flexible CG absorbs the
+                              cycle's rounding; reserve_f32 at setup reserves
+                              its vectors                                       */
 } rr_precision;
 
 /* Smoother of the two-level cycle: S = omega D^-1 with D the diagonal of A
@@ -248,6 +320,8 @@ typedef enum {
 } rr_krylov;
 
 typedef struct {
+  uint32_t struct_size;    /* sizeof(rr_solve_opts)                              */
+  int32_t reserved0;
   double tol;              /* stop when ||r_k|| <= tol ||b||; 0 -> 1e-10        */
   int32_t max_iter;        /* 0 -> 10000                                        */
   int32_t fixed_iters;     /* > 0: run exactly this many iterations              */
@@ -289,6 +363,13 @@ typedef struct {
   int32_t rougher_jacobi;  /* RR_PRECOND_ROUGHER: 1 preconditions the rougher's
                               CG steps with the Jacobi diagonal (a variant; the
                               paper's rougher is plain CG)                       */
+  int32_t persistent;      /* rr_solve_batched: 1 solves every problem in one
+                              persistent kernel launch (replayed from a HIP
+                              graph when graph = 1): a workgroup runs a whole
+                              PCG solve, problems taken longest first.  0/1 X
+                              with at most 8192 features, FP64 PCG, V(1,1)
+                              (n_coarse <= 5120) or Jacobi, point smoother,
+                              no row weights or least-squares interpolation  */
 } rr_solve_opts;
 
 typedef struct {
@@ -302,7 +383,8 @@ typedef struct {
   double true_relres;      /* ||b - A x_k|| / ||b||, recomputed at exit          */
   double err;              /* ||x_k - x_ref|| / ||x_ref|| when x_ref is given    */
   double omega;            /* smoother weight used                               */
-  double ms;               /* wall time of the call                              */
+  double ms;               /* wall time of the call (persistent batched solves:
+                              the problem's own time on its workgroup)          */
   double coarse_ms;        /* of which the per-lambda coarse factorization       */
   double csr_avg_ms;       /* profile: mean time of a row pass u = X v           */
   double csc_avg_ms;       /* profile: mean time of a column pass t = X^T u with
@@ -444,6 +526,25 @@ rr_status rr_apply_rows(rr_handle* h, const double* v, double* u, rr_stream stre
 rr_status rr_set_interpolation(rr_handle* h, const double* V, int32_t n_proto, double beta,
                                const int32_t* rep, double* p, rr_stream stream);
 
+/*
+ * rr_prototypes: prototype vectors for rr_set_interpolation, the n_proto
+ * leading eigenvectors of X^T X (the least-squares interpolation subsection
+ * names the principal components of the data and computes them with Arnoldi
+ * iterations; X^T X is symmetric, so Arnoldi is Lanczos here).  `steps`
+ * Lanczos steps (0 -> max(30, 3 n_proto); n_proto <= steps <= 512) from a
+ * fixed start vector (SplitMix64(seed) entries in [0.5, 1.5) in the caller's
+ * feature order, normalised), every new basis vector orthogonalised twice
+ * against the whole basis; the Ritz pairs of the projected tridiagonal
+ * matrix give V (device double[n_proto * F], prototype k at V[k*F ..], the
+ * caller's feature order, unit norm, each sign fixed by its largest Lanczos
+ * coefficient) and ev (host double[n_proto], descending Ritz values).  The
+ * Lanczos basis, (steps + 1) * F doubles, is allocated for the call.  A
+ * Krylov space that closes before n_proto directions (X of lower rank)
+ * returns RR_ERR_INVALID_ARG.  0/1 or valued sparse X.
+ */
+rr_status rr_prototypes(rr_handle* h, int32_t n_proto, int32_t steps, uint64_t seed, double* V,
+                        double* ev, rr_stream stream);
+
 /* The automatic smoother weight for this lambda (host double).  X >= 0: the
  * Gershgorin weight 1 / max_j (X^T X 1 + lambda)_j / D_j.  X with negative
  * entries: 1 / (1.1 rho), rho the norm ratio after 30 power iterations with
@@ -517,6 +618,7 @@ const char* rr_last_error(void);
  * is what admits such a nonlinear preconditioner.
  */
 typedef struct {
+  uint32_t struct_size;    /* sizeof(rr_mlp_train_opts)                            */
   int32_t epochs;          /* passes over the pairs; 0 -> 20                       */
   int32_t batch;           /* mini-batch size, 1..1024; 0 -> 256                   */
   double lr;               /* Adam step size; 0 -> 1e-3                            */
@@ -565,6 +667,17 @@ rr_status rr_mlp_train(rr_handle* h, const float* in, const float* target, int64
 rr_status rr_collect_pairs(rr_handle* h, const double* lambdas, int32_t n_solves,
                            int32_t pairs_per_solve, int32_t every, const double* y, float* inputs,
                            float* targets, int64_t* n_pairs, rr_stream stream);
+
+/* The same pairs from the network's own solves: for each lambdas[i] the
+ * flexible CG solve with RR_PRECOND_LEARNED (truncation 4) records the
+ * coarse residuals its cycle hands to the network, so a second training
+ * round sees the residual directions a solve the network steers produces
+ * (the V(1,1) solves of rr_collect_pairs never do).  Needs a network
+ * (rr_mlp_init); the solves fall back as RR_PRECOND_LEARNED does, and the
+ * residuals after a fallback come from the algebraic cycle. */
+rr_status rr_collect_pairs_learned(rr_handle* h, const double* lambdas, int32_t n_solves,
+                                   int32_t pairs_per_solve, int32_t every, const double* y,
+                                   float* inputs, float* targets, int64_t* n_pairs, rr_stream stream);
 
 #ifdef __cplusplus
 }

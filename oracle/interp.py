@@ -75,3 +75,15 @@ def galerkin_coarse(X, P, lam: float) -> np.ndarray:
     Xc = Xc.toarray() if sp.issparse(Xc) else np.asarray(Xc)
     Pd = P.toarray()
     return Xc.T @ Xc + lam * (Pd.T @ Pd)
+
+
+def leading_prototypes(X, K: int):
+    """The K leading eigenvectors of X^T X (columns of an F x K matrix, unit
+    norm) and their eigenvalues, descending: the principal directions of the
+    feature space that the paper takes as prototypes (its least-squares
+    interpolation subsection).  Plain definition: the dense symmetric
+    eigendecomposition of X^T X."""
+    G = (sp.csr_matrix(X, dtype=np.float64).T @ sp.csr_matrix(X, dtype=np.float64)).toarray()
+    ev, Q = np.linalg.eigh(G)
+    order = np.argsort(-ev, kind="stable")[:K]
+    return Q[:, order], ev[order]

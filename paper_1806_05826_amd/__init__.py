@@ -27,12 +27,12 @@ if not os.path.exists(LIB_PATH):
 
 _lib = C.CDLL(LIB_PATH)
 
-RR_OK, RR_ERR_INVALID_ARG, RR_ERR_DEVICE = 0, 1, 2
+RR_OK, RR_ERR_INVALID_ARG, RR_ERR_DEVICE, RR_ERR_WORKSPACE = 0, 1, 2, 3
 RR_ERR_NOT_CONVERGED, RR_ERR_BREAKDOWN, RR_ERR_UNSUPPORTED = 4, 5, 6
 PRECOND = {"none": 0, "jacobi": 1, "vcycle": 2, "additive": 3, "learned": 4, "rougher": 5}
 KRYLOV = {"pcg": 0, "fcg": 1}
 SMOOTHER = {"point": 0, "block": 1}
-PRECISION = {"f64": 0, "f32_ir": 1, "bf16_ir": 2}
+PRECISION = {"f64": 0, "f32_ir": 1, "bf16_ir": 2, "f32_cycle": 3}
 
 
 class rr_csr(C.Structure):
@@ -45,12 +45,22 @@ class rr_dense(C.Structure):
                 ("values", C.c_void_p)]
 
 
-class rr_setup_opts(C.Structure):
-    _fields_ = [("n_clusters", C.c_int32), ("kmeans_max_iter", C.c_int32),
+class _Versioned(C.Structure):
+    """An options struct whose first field, struct_size, is set to the
+    struct's size on construction (the library reads that many bytes)."""
+
+    def __init__(self, **kw):
+        super().__init__(**kw)
+        self.struct_size = C.sizeof(self)
+
+
+class rr_setup_opts(_Versioned):
+    _fields_ = [("struct_size", C.c_uint32), ("n_clusters", C.c_int32), ("kmeans_max_iter", C.c_int32),
                 ("seed", C.c_uint64), ("labels_in", C.c_void_p), ("n_labels_in", C.c_int32),
                 ("lambda_slots", C.c_int32), ("autotune", C.c_int32),
                 ("block_smoother", C.c_int32), ("coarse_eigen", C.c_int32),
-                ("lf_tolerance", C.c_double)]
+                ("lf_tolerance", C.c_double), ("reserve_fcg_m", C.c_int32),
+                ("reserve_sets", C.c_int32), ("reserve_f32", C.c_int32), ("reserved0", C.c_int32)]
 
 
 class rr_setup_info(C.Structure):
@@ -63,14 +73,15 @@ class rr_setup_info(C.Structure):
                 ("eigen_sweeps", C.c_int32)]
 
 
-class rr_solve_opts(C.Structure):
-    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("fixed_iters", C.c_int32),
+class rr_solve_opts(_Versioned):
+    _fields_ = [("struct_size", C.c_uint32), ("reserved0", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32), ("fixed_iters", C.c_int32),
                 ("precond", C.c_int32), ("rhs_is_b", C.c_int32), ("omega", C.c_double),
                 ("x_ref", C.c_void_p), ("err_tol", C.c_double),
                 ("residual_history", C.c_void_p), ("chunk", C.c_int32), ("profile", C.c_int32),
                 ("krylov", C.c_int32), ("fcg_m", C.c_int32), ("precision", C.c_int32),
                 ("graph", C.c_int32), ("inner_tol", C.c_double), ("smoother", C.c_int32),
-                ("rougher_steps", C.c_int32), ("rougher_jacobi", C.c_int32)]
+                ("rougher_steps", C.c_int32), ("rougher_jacobi", C.c_int32),
+                ("persistent", C.c_int32)]
 
 
 class rr_solve_info(C.Structure):
@@ -101,6 +112,7 @@ _SIGS = {
     "rr_mlp_backward": [_P, _P, _P, C.c_int32, _P, _P],
     "rr_mlp_train": [_P, _P, _P, C.c_int64, _P, _P, _P],
     "rr_collect_pairs": [_P, _P, C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, _P, _P],
+    "rr_collect_pairs_learned": [_P, _P, C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, _P, _P],
     "rr_apply_operator": [_P, C.c_double, _P, _P, _P],
     "rr_apply_rhs": [_P, _P, _P, _P],
     "rr_apply_precond": [_P, C.c_double, C.c_int32, C.c_double, _P, _P, _P],
@@ -117,6 +129,11 @@ _SIGS = {
                        C.POINTER(rr_solve_opts), _P, _P],
     "rr_apply_operator_block": [_P, C.c_double, C.c_int32, _P, C.c_int64, _P, C.c_int64,
                                 C.c_int32, _P],
+    "rr_setup_ws": [C.POINTER(rr_csr), C.POINTER(rr_setup_opts), _P, C.c_size_t, _P, C.POINTER(_P)],
+    "rr_setup_workspace_size": [C.POINTER(rr_csr), C.POINTER(rr_setup_opts), _P,
+                                C.POINTER(C.c_size_t)],
+    "rr_set_allocator": [_P, _P, _P],
+    "rr_prototypes": [_P, C.c_int32, C.c_int32, C.c_uint64, _P, _P, _P],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -124,6 +141,43 @@ for _name, _args in _SIGS.items():
     _f.restype = C.c_int
 _lib.rr_last_error.argtypes = []
 _lib.rr_last_error.restype = C.c_char_p
+
+
+# --- device memory: PyTorch's caching allocator supplies the library's memory
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_void_p)
+
+
+def _torch_alloc(nbytes, device, ctx):
+    try:
+        import torch
+        return torch.cuda.caching_allocator_alloc(int(nbytes), device=int(device))
+    except Exception:   # the library reports the failed allocation
+        return None
+
+
+def _torch_free(ptr, device, ctx):
+    try:
+        import torch
+        torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:   # interpreter shutdown: torch may already be gone
+        pass
+
+
+_torch_alloc_c = _ALLOC_FN(_torch_alloc)
+_torch_free_c = _FREE_FN(_torch_free)
+
+
+def rr_set_allocator(use_torch=True):
+    """Route the device memory of handles set up from now on through
+    PyTorch's caching allocator (the default at import), or back to
+    hipMalloc with use_torch=False."""
+    if use_torch:
+        _check(_lib.rr_set_allocator(C.cast(_torch_alloc_c, C.c_void_p),
+                                     C.cast(_torch_free_c, C.c_void_p), None))
+    else:
+        _check(_lib.rr_set_allocator(None, None, None))
 
 
 class RRError(RuntimeError):
@@ -141,6 +195,10 @@ def _check(st: int, allow=()):
     if st != RR_OK and st not in allow:
         raise RRError(st, rr_last_error())
     return st
+
+
+if os.environ.get("RR_TORCH_ALLOCATOR", "1") != "0":
+    rr_set_allocator(True)
 
 
 def _stream(stream=None):
@@ -164,11 +222,10 @@ def _dev_f64(t, n=None, name="vector"):
 
 # --- the C ABI, one Python function per entry point -------------------------
 
-def rr_setup(row_ptr, col_idx, values, n_cols, n_clusters=0, seed=0, kmeans_max_iter=0,
-             labels_in=None, n_labels_in=0, lambda_slots=0, autotune=False, block_smoother=False,
-             coarse_eigen=False, lf_tolerance=0.0, stream=None):
-    """X is a device CSR: row_ptr/col_idx int32 CUDA tensors, values float64
-    CUDA tensor or None (binary).  Returns an opaque handle (int)."""
+def _setup_args(row_ptr, col_idx, values, n_cols, n_clusters=0, seed=0, kmeans_max_iter=0,
+                labels_in=None, n_labels_in=0, lambda_slots=0, autotune=False, block_smoother=False,
+                coarse_eigen=False, lf_tolerance=0.0, reserve_fcg_m=0, reserve_sets=0,
+                reserve_f32=False):
     import torch
     for t, nm in ((row_ptr, "row_ptr"), (col_idx, "col_idx")):
         if not (t.is_cuda and t.dtype == torch.int32 and t.is_contiguous()):
@@ -179,12 +236,66 @@ def rr_setup(row_ptr, col_idx, values, n_cols, n_clusters=0, seed=0, kmeans_max_
         raise ValueError("labels_in: need an int32 CUDA tensor")
     X = rr_csr(row_ptr.numel() - 1, int(n_cols), col_idx.numel(), _ptr(row_ptr), _ptr(col_idx),
                _ptr(values))
-    o = rr_setup_opts(int(n_clusters), int(kmeans_max_iter), int(seed) & (2**64 - 1),
-                      _ptr(labels_in), int(n_labels_in), int(lambda_slots), 1 if autotune else 0,
-                      1 if block_smoother else 0, 1 if coarse_eigen else 0, float(lf_tolerance))
+    o = rr_setup_opts(n_clusters=int(n_clusters), kmeans_max_iter=int(kmeans_max_iter),
+                      seed=int(seed) & (2**64 - 1), labels_in=_ptr(labels_in),
+                      n_labels_in=int(n_labels_in), lambda_slots=int(lambda_slots),
+                      autotune=1 if autotune else 0, block_smoother=1 if block_smoother else 0,
+                      coarse_eigen=1 if coarse_eigen else 0, lf_tolerance=float(lf_tolerance),
+                      reserve_fcg_m=int(reserve_fcg_m), reserve_sets=int(reserve_sets),
+                      reserve_f32=1 if reserve_f32 else 0)
+    return X, o
+
+
+def rr_setup(row_ptr, col_idx, values, n_cols, n_clusters=0, seed=0, kmeans_max_iter=0,
+             labels_in=None, n_labels_in=0, lambda_slots=0, autotune=False, block_smoother=False,
+             coarse_eigen=False, lf_tolerance=0.0, reserve_fcg_m=0, reserve_sets=0,
+             reserve_f32=False, workspace=None, stream=None):
+    """X is a device CSR: row_ptr/col_idx int32 CUDA tensors, values float64
+    CUDA tensor or None (binary).  With ``workspace`` (a contiguous CUDA
+    tensor of at least rr_setup_workspace_size bytes, 256-byte aligned) the
+    handle lives in that memory (rr_setup_ws).  Returns an opaque handle."""
+    import torch
+    for t, nm in ((row_ptr, "row_ptr"), (col_idx, "col_idx")):
+        if not (t.is_cuda and t.dtype == torch.int32 and t.is_contiguous()):
+            raise ValueError(f"{nm}: need a contiguous int32 CUDA tensor")
+    if values is not None:
+        _dev_f64(values, col_idx.numel(), "values")
+    if labels_in is not None and not (labels_in.is_cuda and labels_in.dtype == torch.int32):
+        raise ValueError("labels_in: need an int32 CUDA tensor")
+    X = rr_csr(row_ptr.numel() - 1, int(n_cols), col_idx.numel(), _ptr(row_ptr), _ptr(col_idx),
+               _ptr(values))
+    o = rr_setup_opts(n_clusters=int(n_clusters), kmeans_max_iter=int(kmeans_max_iter),
+                      seed=int(seed) & (2**64 - 1), labels_in=_ptr(labels_in),
+                      n_labels_in=int(n_labels_in), lambda_slots=int(lambda_slots),
+                      autotune=1 if autotune else 0, block_smoother=1 if block_smoother else 0,
+                      coarse_eigen=1 if coarse_eigen else 0, lf_tolerance=float(lf_tolerance),
+                      reserve_fcg_m=int(reserve_fcg_m), reserve_sets=int(reserve_sets),
+                      reserve_f32=1 if reserve_f32 else 0)
     h = C.c_void_p()
-    _check(_lib.rr_setup(C.byref(X), C.byref(o), _stream(stream), C.byref(h)))
+    if workspace is None:
+        _check(_lib.rr_setup(C.byref(X), C.byref(o), _stream(stream), C.byref(h)))
+    else:
+        if not (workspace.is_cuda and workspace.is_contiguous()):
+            raise ValueError("workspace: need a contiguous CUDA tensor")
+        nbytes = workspace.numel() * workspace.element_size()
+        _check(_lib.rr_setup_ws(C.byref(X), C.byref(o), _ptr(workspace), C.c_size_t(nbytes),
+                                _stream(stream), C.byref(h)))
     return h.value
+
+
+def rr_setup_ws(row_ptr, col_idx, values, n_cols, workspace, stream=None, **opts):
+    """rr_setup with the handle's device memory carved out of ``workspace``
+    (a contiguous CUDA tensor of at least rr_setup_workspace_size bytes)."""
+    return rr_setup(row_ptr, col_idx, values, n_cols, workspace=workspace, stream=stream, **opts)
+
+
+def rr_setup_workspace_size(row_ptr, col_idx, values, n_cols, stream=None, **opts):
+    """Bytes of device workspace rr_setup_ws needs for this X and options
+    (the same keyword options as rr_setup; runs one setup to measure)."""
+    X, o = _setup_args(row_ptr, col_idx, values, n_cols, **opts)
+    n = C.c_size_t()
+    _check(_lib.rr_setup_workspace_size(C.byref(X), C.byref(o), _stream(stream), C.byref(n)))
+    return n.value
 
 
 def _rows_f64(t, name):
@@ -205,9 +316,10 @@ def rr_setup_dense(X, n_clusters=0, seed=0, kmeans_max_iter=0, labels_in=None, n
     if labels_in is not None and not (labels_in.is_cuda and labels_in.dtype == torch.int32):
         raise ValueError("labels_in: need an int32 CUDA tensor")
     D = rr_dense(X.shape[0], X.shape[1], X.stride(0), _ptr(X))
-    o = rr_setup_opts(int(n_clusters), int(kmeans_max_iter), int(seed) & (2**64 - 1),
-                      _ptr(labels_in), int(n_labels_in), int(lambda_slots), 1 if autotune else 0,
-                      0, 1 if coarse_eigen else 0)
+    o = rr_setup_opts(n_clusters=int(n_clusters), kmeans_max_iter=int(kmeans_max_iter),
+                      seed=int(seed) & (2**64 - 1), labels_in=_ptr(labels_in),
+                      n_labels_in=int(n_labels_in), lambda_slots=int(lambda_slots),
+                      autotune=1 if autotune else 0, coarse_eigen=1 if coarse_eigen else 0)
     h = C.c_void_p()
     _check(_lib.rr_setup_dense(C.byref(D), C.byref(o), _stream(stream), C.byref(h)))
     return h.value
@@ -223,11 +335,11 @@ def rr_solve_block(h, lam, rhs, w, tol=0.0, max_iter=0, fixed_iters=0, precond="
     m = rhs.shape[0]
     if w.shape[0] != m:
         raise ValueError("rhs and w need the same number of rows")
-    o = rr_solve_opts(float(tol), int(max_iter), int(fixed_iters),
-                      PRECOND[precond] if isinstance(precond, str) else int(precond),
-                      1 if rhs_is_b else 0, float(omega), None, 0.0, None, 0, 0, 0, 0,
-                      PRECISION[precision] if isinstance(precision, str) else int(precision),
-                      0, float(inner_tol))
+    o = rr_solve_opts(tol=float(tol), max_iter=int(max_iter), fixed_iters=int(fixed_iters),
+                      precond=PRECOND[precond] if isinstance(precond, str) else int(precond),
+                      rhs_is_b=1 if rhs_is_b else 0, omega=float(omega),
+                      precision=PRECISION[precision] if isinstance(precision, str) else int(precision),
+                      inner_tol=float(inner_tol))
     infos = (rr_solve_info * max(m, 1))()
     st = _lib.rr_solve_block(C.c_void_p(h), float(lam), int(m), _ptr(rhs), C.c_int64(rhs.stride(0)),
                              _ptr(w), C.c_int64(w.stride(0)), C.byref(o), C.cast(infos, C.c_void_p),
@@ -279,15 +391,17 @@ def rr_solve(h, lam, rhs, w, tol=0.0, max_iter=0, fixed_iters=0, precond="vcycle
     """Returns (status, info dict).  Statuses in `raise_on` raise RRError."""
     _dev_f64(rhs, None, "rhs")
     _dev_f64(w, None, "w")
-    o = rr_solve_opts(float(tol), int(max_iter), int(fixed_iters),
-                      PRECOND[precond] if isinstance(precond, str) else int(precond),
-                      1 if rhs_is_b else 0, float(omega), _ptr(x_ref), float(err_tol),
-                      _ptr(residual_history), int(chunk), int(profile),
-                      KRYLOV[krylov] if isinstance(krylov, str) else int(krylov), int(fcg_m),
-                      PRECISION[precision] if isinstance(precision, str) else int(precision),
-                      1 if graph else 0, float(inner_tol),
-                      SMOOTHER[smoother] if isinstance(smoother, str) else int(smoother),
-                      int(rougher_steps), 1 if rougher_jacobi else 0)
+    o = rr_solve_opts(tol=float(tol), max_iter=int(max_iter), fixed_iters=int(fixed_iters),
+                      precond=PRECOND[precond] if isinstance(precond, str) else int(precond),
+                      rhs_is_b=1 if rhs_is_b else 0, omega=float(omega), x_ref=_ptr(x_ref),
+                      err_tol=float(err_tol), residual_history=_ptr(residual_history),
+                      chunk=int(chunk), profile=int(profile),
+                      krylov=KRYLOV[krylov] if isinstance(krylov, str) else int(krylov),
+                      fcg_m=int(fcg_m),
+                      precision=PRECISION[precision] if isinstance(precision, str) else int(precision),
+                      graph=1 if graph else 0, inner_tol=float(inner_tol),
+                      smoother=SMOOTHER[smoother] if isinstance(smoother, str) else int(smoother),
+                      rougher_steps=int(rougher_steps), rougher_jacobi=1 if rougher_jacobi else 0)
     info = rr_solve_info()
     st = _lib.rr_solve(C.c_void_p(h), float(lam), _ptr(rhs), _ptr(w), C.byref(o), C.byref(info),
                        _stream(stream))
@@ -298,7 +412,7 @@ def rr_solve(h, lam, rhs, w, tol=0.0, max_iter=0, fixed_iters=0, precond="vcycle
 
 def rr_solve_batched(handles, lams, rhs, ws, tol=0.0, max_iter=0, fixed_iters=0, precond="vcycle",
                      rhs_is_b=False, omega=0.0, chunk=0, krylov="pcg", fcg_m=0, smoother="point",
-                     graph=False, stream=None,
+                     graph=False, persistent=False, stream=None,
                      raise_on=(RR_ERR_INVALID_ARG, RR_ERR_DEVICE, RR_ERR_UNSUPPORTED)):
     """Batched solves; returns (status, [info dict per problem])."""
     n = len(handles)
@@ -310,12 +424,13 @@ def rr_solve_batched(handles, lams, rhs, ws, tol=0.0, max_iter=0, fixed_iters=0,
     L = (C.c_double * max(n, 1))(*[float(x) for x in lams])
     Rp = (C.c_void_p * max(n, 1))(*[_ptr(t) for t in rhs])
     Wp = (C.c_void_p * max(n, 1))(*[_ptr(t) for t in ws])
-    o = rr_solve_opts(float(tol), int(max_iter), int(fixed_iters),
-                      PRECOND[precond] if isinstance(precond, str) else int(precond),
-                      1 if rhs_is_b else 0, float(omega), None, 0.0, None, int(chunk), 0,
-                      KRYLOV[krylov] if isinstance(krylov, str) else int(krylov), int(fcg_m),
-                      0, 1 if graph else 0, 0.0,
-                      SMOOTHER[smoother] if isinstance(smoother, str) else int(smoother))
+    o = rr_solve_opts(tol=float(tol), max_iter=int(max_iter), fixed_iters=int(fixed_iters),
+                      precond=PRECOND[precond] if isinstance(precond, str) else int(precond),
+                      rhs_is_b=1 if rhs_is_b else 0, omega=float(omega), chunk=int(chunk),
+                      krylov=KRYLOV[krylov] if isinstance(krylov, str) else int(krylov),
+                      fcg_m=int(fcg_m), graph=1 if graph else 0,
+                      smoother=SMOOTHER[smoother] if isinstance(smoother, str) else int(smoother),
+                      persistent=1 if persistent else 0)
     infos = (rr_solve_info * max(n, 1))()
     st = _lib.rr_solve_batched(C.c_int32(n), C.cast(H, C.c_void_p), C.cast(L, C.c_void_p),
                                C.cast(Rp, C.c_void_p), C.cast(Wp, C.c_void_p), C.byref(o),
@@ -325,8 +440,8 @@ def rr_solve_batched(handles, lams, rhs, ws, tol=0.0, max_iter=0, fixed_iters=0,
     return st, [{f: getattr(infos[i], f) for f, _ in rr_solve_info._fields_} for i in range(n)]
 
 
-class rr_mlp_train_opts(C.Structure):
-    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double),
+class rr_mlp_train_opts(_Versioned):
+    _fields_ = [("struct_size", C.c_uint32), ("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double),
                 ("seed", C.c_uint64)]
 
 
@@ -379,7 +494,7 @@ def rr_mlp_train(h, inp, target, epochs=0, batch=0, lr=0.0, seed=0, stream=None)
     import numpy as np
     _dev_f32(inp, "in")
     _dev_f32(target, "target")
-    o = rr_mlp_train_opts(int(epochs), int(batch), float(lr), int(seed))
+    o = rr_mlp_train_opts(epochs=int(epochs), batch=int(batch), lr=float(lr), seed=int(seed))
     hist = np.zeros(max(1, epochs if epochs > 0 else 20), dtype=np.float32)
     _check(_lib.rr_mlp_train(C.c_void_p(h), _ptr(inp), _ptr(target), C.c_int64(int(inp.shape[0])),
                              C.byref(o), hist.ctypes.data_as(C.c_void_p), _stream(stream)))
@@ -396,6 +511,19 @@ def rr_collect_pairs(h, lams, pairs_per_solve, every, y, inputs, targets, stream
     _check(_lib.rr_collect_pairs(C.c_void_p(h), C.cast(L, C.c_void_p), len(lams), int(pairs_per_solve),
                                  int(every), _ptr(y), _ptr(inputs), _ptr(targets), C.byref(n),
                                  _stream(stream)))
+    return n.value
+
+
+def rr_collect_pairs_learned(h, lams, pairs_per_solve, every, y, inputs, targets, stream=None):
+    """Pairs from the network's own flexible-CG solves; returns the count."""
+    _dev_f32(inputs, "inputs")
+    _dev_f32(targets, "targets")
+    _dev_f64(y, None, "y")
+    L = (C.c_double * max(1, len(lams)))(*[float(x) for x in lams])
+    n = C.c_int64()
+    _check(_lib.rr_collect_pairs_learned(C.c_void_p(h), C.cast(L, C.c_void_p), len(lams),
+                                         int(pairs_per_solve), int(every), _ptr(y), _ptr(inputs),
+                                         _ptr(targets), C.byref(n), _stream(stream)))
     return n.value
 
 
@@ -431,6 +559,18 @@ def rr_set_interpolation(h, V, n_proto, beta, rep=None, p=None, stream=None):
                                      _ptr(p), _stream(stream)))
 
 
+def rr_prototypes(h, n_proto, V, steps=0, seed=0x5eed, stream=None):
+    """V: (n_proto, F) float64 CUDA tensor receiving the leading
+    eigenvectors of X^T X (caller's feature order); returns the Ritz values
+    (numpy, descending)."""
+    import numpy as np
+    _dev_f64(V, None, "V")
+    ev = np.empty(int(n_proto), dtype=np.float64)
+    _check(_lib.rr_prototypes(C.c_void_p(h), int(n_proto), int(steps), int(seed) & (2**64 - 1),
+                              _ptr(V), ev.ctypes.data_as(C.c_void_p), _stream(stream)))
+    return ev
+
+
 def rr_coarse_eigen(h, Q, ev, stream=None):
     _check(_lib.rr_coarse_eigen(C.c_void_p(h), _ptr(Q), _ptr(ev), _stream(stream)))
 
@@ -464,7 +604,8 @@ class Ridge:
 
     def __init__(self, X, n_clusters=0, seed=0, kmeans_max_iter=0, labels=None, binary=None,
                  lambda_slots=0, autotune=False, block_smoother=False, coarse_eigen=False,
-                 lf_tolerance=0.0, device="cuda"):
+                 lf_tolerance=0.0, reserve_fcg_m=0, reserve_sets=0, reserve_f32=False,
+                 workspace=None, device="cuda"):
         import numpy as np
         import torch
         X = X.tocsr()
@@ -481,8 +622,10 @@ class Ridge:
         if labels is not None:
             lab = torch.as_tensor(np.asarray(labels, dtype=np.int32), device=self.device)
             nlab = int(np.max(labels)) + 1 if len(labels) else 1
+        self.workspace = workspace   # kept alive with the handle
         self.h = rr_setup(rp, ci, vals, self.F, n_clusters, seed, kmeans_max_iter, lab, nlab,
-                          lambda_slots, autotune, block_smoother, coarse_eigen, lf_tolerance)
+                          lambda_slots, autotune, block_smoother, coarse_eigen, lf_tolerance,
+                          reserve_fcg_m, reserve_sets, reserve_f32, workspace)
         torch.cuda.current_stream().synchronize()
         self.info = rr_get_setup_info(self.h)
 
@@ -587,7 +730,13 @@ class Ridge:
         if Vt.dim() != 2 or Vt.shape[0] != self.F:
             raise ValueError("V must be F x K")
         Vk = Vt.t().contiguous()      # prototype k contiguous
-        r = None if rep is None else torch.as_tensor(rep, dtype=torch.int32, device=self.device).contiguous()
+        r = None
+        if rep is not None:
+            fc = self.info["n_coarse"]
+            r = torch.as_tensor(rep, device=self.device)
+            if r.dtype not in (torch.int32, torch.int64) or r.dim() != 1 or r.numel() != fc:
+                raise ValueError(f"rep must be a 1-D integer tensor of n_coarse = {fc} elements")
+            r = r.to(torch.int32).contiguous()
         p = torch.empty(self.F, dtype=torch.float64, device=self.device)
         rr_set_interpolation(self.h, Vk, Vt.shape[1], beta, r, p)
         return p

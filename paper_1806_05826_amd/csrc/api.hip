@@ -7,7 +7,9 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
+#include <numeric>
 
 #include "rr_device.h"
 
@@ -60,13 +62,41 @@ template <class T>
 rr_status dalloc(T** p, size_t n) {
   *p = nullptr;
   if (n == 0) n = 1;
-  hipError_t e = hipMalloc((void**)p, sizeof(T) * n);
+  hipError_t e = dmalloc((void**)p, sizeof(T) * n);
   if (e != hipSuccess) return fail(RR_ERR_DEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
   return RR_OK;
 }
 
 void dfree(void* p) {
-  if (p) (void)hipFree(p);
+  if (p) (void)dev_free(p);
+}
+
+// A versioned options struct: struct_size bytes of the caller's copy, the
+// rest (fields a caller built against an older header lacks) zero, which is
+// every field's default.
+template <typename T>
+rr_status read_opts(const T* in, T* out) {
+  *out = T{};
+  if (!in) {
+    out->struct_size = sizeof(T);
+    return RR_OK;
+  }
+  const uint32_t sz = in->struct_size;
+  if (sz < sizeof(uint32_t) || sz > (1u << 16))
+    return fail(RR_ERR_INVALID_ARG, "options: struct_size must hold sizeof(the options struct)");
+  std::memcpy(out, in, std::min<size_t>(sz, sizeof(T)));
+  out->struct_size = sizeof(T);
+  return RR_OK;
+}
+
+MemCtx* mem_of(const rr_handle* h) { return h ? &const_cast<rr_handle*>(h)->mem : nullptr; }
+
+// A call on a handle living in a caller workspace that ran out of it.
+rr_status ws_status(const rr_handle* h, rr_status st) {
+  if (st != RR_OK && h && h->mem.mode == MemCtx::kBump && h->mem.overflow)
+    return fail(RR_ERR_WORKSPACE, "the handle's workspace is too small (" + std::to_string(h->mem.cap) +
+                                      " bytes, " + std::to_string(h->mem.used) + " in use)");
+  return st;
 }
 
 void free_work(Work& w) {
@@ -82,7 +112,7 @@ void free_work(Work& w) {
   if (w.extra) {
     dfree(w.X.sell_csc.part);
     dfree(w.X.csc_plan.head); dfree(w.X.csc_plan.tail);
-    dfree(w.rplan.head); dfree(w.rplan.tail); dfree(w.rplan.cpart);
+    dfree(w.rplan.head); dfree(w.rplan.tail);
   }
   w.graph.reset();
   if (w.graph.ev) (void)hipEventDestroy(w.graph.ev);
@@ -119,6 +149,21 @@ rr_status alloc_work(Work& w, int F, int N, int FC, int np) {
   return RR_OK;
 }
 
+// The flexible-CG ring of a work set: m directions and their images.
+rr_status reserve_fcg(Work& w, int m, int F) {
+  if (w.fcg_m >= m) return RR_OK;
+  dfree(w.fcg_p);
+  dfree(w.fcg_ap);
+  dfree(w.fcg_paps);
+  w.fcg_p = w.fcg_ap = w.fcg_paps = nullptr;
+  w.fcg_m = 0;
+  RR_TRY(dalloc(&w.fcg_p, (size_t)m * F));
+  RR_TRY(dalloc(&w.fcg_ap, (size_t)m * F));
+  RR_TRY(dalloc(&w.fcg_paps, kMaxFcg));
+  w.fcg_m = m;
+  return RR_OK;
+}
+
 // Work set k (0: the handle's own); sets beyond the first are created on
 // first use with their own partial-sum buffers for the operator passes and
 // the restriction.
@@ -137,7 +182,6 @@ rr_status get_work_set(rr_handle* h, int k, Work** out) {
     w->X.sell_csc.part = nullptr;
     w->X.csc_plan.head = w->X.csc_plan.tail = nullptr;
     w->rplan.head = w->rplan.tail = nullptr;
-    w->rplan.cpart = nullptr;
     RR_TRY(alloc_work(*w, h->X.F, h->X.N, h->FC, h->npartials));
     if (h->X.binary) {
       RR_TRY(dalloc(&w->X.sell_csc.part, h->X.sell_csc.nout));
@@ -149,7 +193,6 @@ rr_status get_work_set(rr_handle* h, int k, Work** out) {
       RR_TRY(dalloc(&w->rplan.head, h->restrict_plan.nblocks));
       RR_TRY(dalloc(&w->rplan.tail, h->restrict_plan.nblocks));
     }
-    if (h->restrict_plan.ncpart > 0) RR_TRY(dalloc(&w->rplan.cpart, h->restrict_plan.ncpart));
   }
   *out = h->extra_sets[k - 1];
   return RR_OK;
@@ -163,6 +206,7 @@ void destroy_handle(rr_handle* h) {
   free_merge_plan(X.csc_plan);
   free_rows(X.rows);
   free_sell(X.sell_csc);
+  free_batch_plan(X.bplan);
   free_merge_plan(h->restrict_plan);
   free_cluster_rows(h->crow);
   dfree(h->colnorm); dfree(h->gersh); dfree(h->fperm); dfree(h->finv);
@@ -195,6 +239,9 @@ int pick_group(double avg) {
   while (g < 64 && g < avg / 2.0) g *= 2;
   return g;
 }
+
+rr_status ensure_f32(rr_handle* h, Work& w);   // below: FP32 vectors of refinement
+rr_status ensure_power_work(rr_handle* h, int F, int N);   // below
 
 rr_status setup_impl(const rr_csr* Xin, const rr_setup_opts* o, hipStream_t s, rr_handle* h) {
   const double t0 = now_ms();
@@ -233,6 +280,7 @@ rr_status setup_impl(const rr_csr* Xin, const rr_setup_opts* o, hipStream_t s, r
   {
     const double tt = now_ms();
     RR_TRY(build_sell_plans(X, s, (o && o->autotune) ? 1 : 0, &h->tuning));
+    RR_TRY(build_batch_plan(X.bplan, X, s));
     h->tune_ms = now_ms() - tt;
   }
   // column norms and Gershgorin row sums g = X^T (X 1)
@@ -279,6 +327,7 @@ rr_status setup_impl(const rr_csr* Xin, const rr_setup_opts* o, hipStream_t s, r
   h->kmeans_ms = now_ms() - tk;
   int np = cdiv(F, kBlock) + 1;   // >= every reduction grid (the segment reduction uses <= 256)
   if (!X.binary) np = std::max(np, X.csc_plan.nblocks + cdiv(X.csc_plan.nspan, kBlock / 64) + 1);
+  if (h->FC > 0 && X.binary) RR_TRY(check_coarse_size(h->FC));   // before the F_C^2 buffers
   if (h->FC > 0) {
     const int fc = h->FC;
     RR_TRY(dalloc(&h->K, (size_t)fc * fc));
@@ -308,6 +357,22 @@ rr_status setup_impl(const rr_csr* Xin, const rr_setup_opts* o, hipStream_t s, r
   w.rplan = h->restrict_plan;
   RR_HIP(hipStreamSynchronize(s));
   RR_HIP(hipGetLastError());
+  // buffers of later solves, reserved now so that those solves allocate
+  // nothing: the power-iteration vectors (X with negative entries, the block
+  // smoother's weight), the block smoother's inverses of every lambda slot
+  if (!h->nonneg || h->nblk > 0) RR_TRY(ensure_power_work(h, F, N));
+  for (auto& sl : h->slots)
+    if (h->nblk > 0 && !sl.Dinv) RR_TRY(dalloc(&sl.Dinv, (size_t)h->nblk * 32 * 32));
+  if (o && o->reserve_fcg_m > 0) RR_TRY(reserve_fcg(h->w, std::min(o->reserve_fcg_m, kMaxFcg), X.F));
+  if (o && o->reserve_sets > 0) {
+    if (o->reserve_sets > 64) return fail(RR_ERR_INVALID_ARG, "reserve_sets must be <= 64");
+    for (int k = 1; k <= o->reserve_sets; ++k) {
+      Work* w = nullptr;
+      RR_TRY(get_work_set(h, k, &w));
+      if (o->reserve_fcg_m > 0) RR_TRY(reserve_fcg(*w, std::min(o->reserve_fcg_m, kMaxFcg), X.F));
+    }
+  }
+  if (o && o->reserve_f32 && X.binary) RR_TRY(ensure_f32(h, h->w));
   h->setup_ms = now_ms() - t0;
   return RR_OK;
 }
@@ -362,19 +427,25 @@ __global__ __launch_bounds__(kBlock) void k_pw_norm(const double* parts, int n, 
   if (threadIdx.x == 0) *nrm = sqrt(t);
 }
 
+// Buffers of the power-iteration smoother weight (X with negative entries,
+// and the block smoother's weight).
+rr_status ensure_power_work(rr_handle* h, int F, int N) {
+  if (h->pw) return RR_OK;
+  h->pw = new (std::nothrow) rr_handle::PowerWork();
+  if (!h->pw) return fail(RR_ERR_DEVICE, "out of host memory");
+  RR_TRY(dalloc(&h->pw->v, F)); RR_TRY(dalloc(&h->pw->t, F)); RR_TRY(dalloc(&h->pw->u, N));
+  RR_TRY(dalloc(&h->pw->D, F)); RR_TRY(dalloc(&h->pw->vin, F));
+  RR_TRY(dalloc(&h->pw->parts, kMaxParts)); RR_TRY(dalloc(&h->pw->nrm, 1));
+  return RR_OK;
+}
+
 // The oracle's power estimate: 30 products with D^-1/2 A D^-1/2 from a
 // start vector with SplitMix64(kPowerSeed) entries in [0.5, 1.5) (caller's
 // feature order), rho = the last norm ratio, omega = 1 / (1.1 rho).
 constexpr uint64_t kPowerSeed = 0x5eedULL;
 rr_status omega_power(rr_handle* h, const Sparse& X, double lam, double* omega, hipStream_t s) {
   const int F = X.F, N = X.N;
-  if (!h->pw) {
-    h->pw = new (std::nothrow) rr_handle::PowerWork();
-    if (!h->pw) return fail(RR_ERR_DEVICE, "out of host memory");
-    RR_TRY(dalloc(&h->pw->v, F)); RR_TRY(dalloc(&h->pw->t, F)); RR_TRY(dalloc(&h->pw->u, N));
-    RR_TRY(dalloc(&h->pw->D, F)); RR_TRY(dalloc(&h->pw->vin, F));
-    RR_TRY(dalloc(&h->pw->parts, kMaxParts)); RR_TRY(dalloc(&h->pw->nrm, 1));
-  }
+  RR_TRY(ensure_power_work(h, F, N));
   rr_handle::PowerWork& p = *h->pw;
   std::vector<double> v0(F);
   uint64_t st = kPowerSeed;
@@ -433,13 +504,7 @@ __global__ __launch_bounds__(kBlock) void k_sq_parts(int F, const double* __rest
 // the same start vector as omega_power; omega = 1 / (1.1 rho).
 rr_status omega_block_power(rr_handle* h, const Sparse& X, double lam, LambdaSlot& sl, hipStream_t s) {
   const int F = X.F, N = X.N;
-  if (!h->pw) {
-    h->pw = new (std::nothrow) rr_handle::PowerWork();
-    if (!h->pw) return fail(RR_ERR_DEVICE, "out of host memory");
-    RR_TRY(dalloc(&h->pw->v, F)); RR_TRY(dalloc(&h->pw->t, F)); RR_TRY(dalloc(&h->pw->u, N));
-    RR_TRY(dalloc(&h->pw->D, F)); RR_TRY(dalloc(&h->pw->vin, F));
-    RR_TRY(dalloc(&h->pw->parts, kMaxParts)); RR_TRY(dalloc(&h->pw->nrm, 1));
-  }
+  RR_TRY(ensure_power_work(h, F, N));
   rr_handle::PowerWork& p = *h->pw;
   std::vector<double> v0(F);
   uint64_t st = kPowerSeed;
@@ -716,9 +781,15 @@ struct Solve {
   // coarse residual snapshots P^T r_k after every `snap_every`-th update
   double* snap = nullptr;
   int snap_every = 0, snap_max = 0, snap_queued = 0;
-  // learned coarse correction: switch to the algebraic cycle on a stall
+  // learned coarse correction: switch to the algebraic cycle on a stall or
+  // on a failed step (the flexible-CG history then restarts at fcg_base)
   double last_rr = -1.0;
   int fallback_iter = -1;
+  int fcg_base = 0;
+  bool skip_check = false;   // no update since the last convergence check
+  // precision RR_PREC_F32_CYCLE: the preconditioner's cycle runs in FP32
+  bool cycle32 = false;
+  rr_status precond(int tag, const StageArgs* st, int* nrz, double* snap_to = nullptr);
 
   rr_status begin();
   rr_status queue_chunk();
@@ -730,6 +801,24 @@ struct Solve {
     sl = nullptr;
   }
 };
+
+rr_status precond32(rr_handle* h, Work& w, double lam, double omega, const LambdaSlot& sl,
+                    const StageArgs* stage, int* n_rz, hipStream_t s);   // below
+
+// z = B r with the solve's preconditioner (two-level forms), in FP64 or as
+// the FP32 cycle whose z is widened back.
+rr_status Solve::precond(int tag, const StageArgs* st, int* nrz, double* snap_to) {
+  Work& w = *ws;
+  if (cycle32) {
+    const int F = h->X.F;
+    const int* done = &w.sc->done;
+    launch_cycle_in(F, w.r, h->colnorm, lam, omega, w.f32, done, s);
+    RR_TRY(precond32(h, w, lam, omega, *sl, st, nrz, s));
+    launch_widen(F, w.f32.z, w.z, done, s);
+    return RR_OK;
+  }
+  return precond_two_level(h, w, pf, tag, kind, lam, omega, *sl, w.r, w.z, st, nrz, s, snap_to);
+}
 
 rr_status Solve::begin() {
   t0 = now_ms();
@@ -768,15 +857,7 @@ rr_status Solve::begin() {
   fcg_m = op.fcg_m > 0 ? op.fcg_m : 1;
   if (op.krylov == RR_KRYLOV_FCG && w.fcg_m < fcg_m) {
     RR_HIP(hipStreamSynchronize(s));
-    dfree(w.fcg_p);
-    dfree(w.fcg_ap);
-    dfree(w.fcg_paps);
-    w.fcg_p = w.fcg_ap = w.fcg_paps = nullptr;
-    w.fcg_m = 0;
-    RR_TRY(dalloc(&w.fcg_p, (size_t)fcg_m * F));
-    RR_TRY(dalloc(&w.fcg_ap, (size_t)fcg_m * F));
-    RR_TRY(dalloc(&w.fcg_paps, kMaxFcg));
-    w.fcg_m = fcg_m;
+    RR_TRY(reserve_fcg(w, fcg_m, F));
   }
   if (op.smoother != RR_SMOOTHER_POINT && op.smoother != RR_SMOOTHER_BLOCK)
     return fail(RR_ERR_INVALID_ARG, "unknown smoother");
@@ -790,6 +871,15 @@ rr_status Solve::begin() {
     return fail(RR_ERR_UNSUPPORTED,
                 "least-squares interpolation is built for the point smoother and the algebraic coarse solve");
   w.block = block;
+  cycle32 = op.precision == RR_PREC_F32_CYCLE;
+  if (cycle32) {
+    if (kind != PK_VCYCLE || op.krylov != RR_KRYLOV_FCG)
+      return fail(RR_ERR_INVALID_ARG, "the FP32 cycle runs the V(1,1) preconditioner under flexible CG");
+    if (!h->X.binary || w.X.rw || h->lsw || block)
+      return fail(RR_ERR_UNSUPPORTED, "the FP32 cycle is built for unweighted 0/1 X with the point "
+                                      "smoother and the square-root-average P");
+    RR_TRY(ensure_f32(h, w));
+  }
   omega = op.omega;
   if (kind == PK_VCYCLE || kind == PK_ADDITIVE || kind == PK_LEARNED || kind == PK_ROUGHER) {
     RR_TRY(get_slot(h, w.X, lam, &sl, &coarse_ms, s));
@@ -835,7 +925,7 @@ rr_status Solve::begin() {
   if (op.krylov == RR_KRYLOV_FCG) {
     if (two_level) {
       int nrz = 0;
-      RR_TRY(precond_two_level(h, w, pf, -1, kind, lam, omega, *sl, w.r, w.z, nullptr, &nrz, s));
+      RR_TRY(precond(-1, nullptr, &nrz));
     }
   } else if (two_level) {
     int nrz = 0;
@@ -855,17 +945,22 @@ rr_status Solve::queue_chunk() {
     // orthogonalized against the m_i previous ones, m_i = max(1, i mod (m+1))
     const int m = fcg_m;
     for (int c = 0; c < chunk; ++c, ++queued) {
-      const int i = queued;
+      const int i = queued - fcg_base;
       const int slot = i % m;
       double* pi = w.fcg_p + (size_t)slot * F;
       double* qi = w.fcg_ap + (size_t)slot * F;
       FcgWindow win{};
+      if (queued > 0 && two_level) {
+        int nrz = 0;
+        double* sp = nullptr;   // coarse residual snapshots (pair collection)
+        if (snap && queued % snap_every == 0 && snap_queued < snap_max)
+          sp = snap + (size_t)(snap_queued++) * h->FC;
+        // after a fallback no update has run since the last check: its
+        // partials may be another solve's
+        RR_TRY(precond(100000000 + queued - 1, skip_check ? nullptr : &stage, &nrz, sp));
+        skip_check = false;
+      }
       if (i > 0) {
-        if (two_level) {
-          int nrz = 0;
-          RR_TRY(precond_two_level(h, w, pf, 100000000 + i - 1, kind, lam, omega, *sl, w.r, w.z,
-                                   &stage, &nrz, s));
-        }
         const int mi = std::max(1, i % (m + 1));
         for (int kk = i - mi; kk < i; ++kk) {
           win.p[win.n] = w.fcg_p + (size_t)(kk % m) * F;
@@ -876,13 +971,13 @@ rr_status Solve::queue_chunk() {
         launch_fcg_dots(F, w.z, win, w.parts.dots, w.sc, two_level ? nullptr : &stage, s);
       }
       launch_fcg_dir(F, w.z, w.r, pi, win, w.parts.dots, w.fcg_paps, w.parts.rz, w.sc, s);
-      RR_TRY(op_csr(h, w, pf, i, pi, s));
+      RR_TRY(op_csr(h, w, pf, queued, pi, s));
       Epi e = base_epi(w, lam);
       e.p = pi;
       e.out = qi;
       e.partials = w.parts.pq;
       int npq = 0;
-      RR_TRY(op_csc(h, w, pf, i, EPI_APPLY_DOT, e, s, &npq));
+      RR_TRY(op_csc(h, w, pf, queued, EPI_APPLY_DOT, e, s, &npq));
       launch_fcg_update(F, w.x, w.r, pi, qi, w.z, w.e1, w.D, xref, omega, kind, w.sc,
                         w.parts.pq, npq, w.parts.rz, w.fcg_paps, slot, w.parts.upd, s);
     }
@@ -967,6 +1062,22 @@ rr_status Solve::poll() {
   RR_HIP(hipMemcpyAsync(&hs, ws->sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
   RR_HIP(hipStreamSynchronize(s));
   RR_HIP(hipGetLastError());
+  if (hs.done && hs.status == kStatusFallback && kind == PK_LEARNED) {
+    // the network's correction made a step fail: the rest of the solve uses
+    // the algebraic cycle from the last good iterate, with a fresh
+    // flexible-CG history
+    fallback_iter = hs.iter;
+    kind = PK_VCYCLE;
+    stage.kind = kind;
+    fcg_base = queued;
+    skip_check = true;
+    hs.done = 0;
+    hs.status = RR_ERR_NOT_CONVERGED;
+    RR_HIP(hipMemcpyAsync(ws->sc, &hs, sizeof(Scalars), hipMemcpyHostToDevice, s));
+    k_smooth<<<cdiv(h->X.F, kBlock), kBlock, 0, s>>>(h->X.F, ws->r, ws->D, omega, ws->e1);
+    last_rr = -1.0;
+    return RR_OK;
+  }
   if (hs.done) {
     done = true;
     return RR_OK;
@@ -1344,7 +1455,8 @@ rr_status solve_ir(rr_handle* h, Work& w, double lam, const double* rhs, double*
 rr_status solve_impl(rr_handle* h, double lam, const double* rhs, double* wout,
                      const rr_solve_opts* o, rr_solve_info* info, hipStream_t s) {
   if (o && o->precision == RR_PREC_F32_IR) return solve_ir(h, h->w, lam, rhs, wout, *o, info, s);
-  if (o && o->precision != RR_PREC_F64) return fail(RR_ERR_INVALID_ARG, "unknown precision");
+  if (o && o->precision != RR_PREC_F64 && o->precision != RR_PREC_F32_CYCLE)
+    return fail(RR_ERR_INVALID_ARG, "unknown precision");
   Solve sv;
   sv.h = h;
   sv.ws = &h->w;
@@ -1369,6 +1481,10 @@ rr_status solve_impl(rr_handle* h, double lam, const double* rhs, double* wout,
 // in later waves.
 constexpr int kMaxSets = 8;
 
+rr_status solve_batched_persistent(int nprob, rr_handle* const* hs, const double* lams,
+                                   const double* const* rhs, double* const* ws, const rr_solve_opts& op,
+                                   rr_solve_info* infos, hipStream_t caller);
+
 rr_status solve_batched_impl(int nprob, rr_handle* const* hs, const double* lams,
                              const double* const* rhs, double* const* ws, const rr_solve_opts* o,
                              rr_solve_info* infos, hipStream_t caller) {
@@ -1386,6 +1502,7 @@ rr_status solve_batched_impl(int nprob, rr_handle* const* hs, const double* lams
     if (!hs[i]) return fail(RR_ERR_INVALID_ARG, "null handle in batch");
     RR_TRY(check_sparse(hs[i]));
   }
+  if (op.persistent) return solve_batched_persistent(nprob, hs, lams, rhs, ws, op, infos, caller);
   std::vector<int> wave(nprob, 0), set(nprob, 0);
   int nwaves = 0;
   for (int i = 0; i < nprob; ++i) {
@@ -1406,7 +1523,10 @@ rr_status solve_batched_impl(int nprob, rr_handle* const* hs, const double* lams
       if (wave[i] != wv) continue;
       rr_handle* h = hs[i];
       Work* w = nullptr;
-      RR_TRY(get_work_set(h, set[i], &w));
+      {
+        MemScope ms(&h->mem);
+        RR_TRY(get_work_set(h, set[i], &w));
+      }
       hipStream_t* st = (set[i] == 0) ? &h->bstream : &w->stream;
       if (!*st) RR_HIP(hipStreamCreateWithFlags(st, hipStreamNonBlocking));
       RR_HIP(hipStreamWaitEvent(*st, ev, 0));
@@ -1422,7 +1542,10 @@ rr_status solve_batched_impl(int nprob, rr_handle* const* hs, const double* lams
       idx.push_back(i);
     }
     std::vector<rr_status> st(sv.size(), RR_OK);
-    for (size_t j = 0; j < sv.size(); ++j) st[j] = sv[j]->begin();
+    for (size_t j = 0; j < sv.size(); ++j) {
+      MemScope ms(&sv[j]->h->mem);
+      st[j] = sv[j]->begin();
+    }
     for (;;) {
       bool active = false;
       for (size_t j = 0; j < sv.size(); ++j)
@@ -1457,6 +1580,237 @@ rr_status solve_batched_impl(int nprob, rr_handle* const* hs, const double* lams
   return first_bad;
 }
 
+// ---- persistent batched solve ------------------------------------------------
+
+// Device buffers of the persistent batched solve, kept by the library per
+// device and grown when a larger batch arrives (the solve itself allocates
+// nothing once they are large enough).
+struct BatchBuffers {
+  BatchProb* probs = nullptr;
+  int* order = nullptr;
+  BatchOut* out = nullptr;
+  int* queue = nullptr;
+  int cap = 0;
+  hipStream_t stream = nullptr;   // capture stream of the launch graph
+  hipEvent_t ev = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_n = -1, graph_grid = -1;
+  MemCtx mem;   // where the buffers came from
+};
+std::mutex g_batch_mu;
+BatchBuffers g_batch[64];
+
+rr_status batch_buffers(int dev, int n, BatchBuffers** out) {
+  if (dev < 0 || dev >= 64) return fail(RR_ERR_UNSUPPORTED, "device index above 63");
+  BatchBuffers& b = g_batch[dev];
+  if (b.cap < n) {
+    MemScope old_mem(&b.mem);
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    if (b.graph) (void)hipGraphDestroy(b.graph);
+    b.exec = nullptr;
+    b.graph = nullptr;
+    b.graph_n = b.graph_grid = -1;
+    dfree(b.probs);
+    dfree(b.order);
+    dfree(b.out);
+    b.probs = nullptr;
+    b.order = nullptr;
+    b.out = nullptr;
+    b.cap = 0;
+    if (b.queue) (void)dev_free(b.queue);
+    b.queue = nullptr;
+    b.mem = default_mem();
+    MemScope new_mem(&b.mem);
+    const int cap = std::max(n, 64);
+    RR_HIP(dmalloc(&b.probs, sizeof(BatchProb) * cap));
+    RR_HIP(dmalloc(&b.order, sizeof(int) * cap));
+    RR_HIP(dmalloc(&b.out, sizeof(BatchOut) * cap));
+    RR_HIP(dmalloc(&b.queue, sizeof(int)));
+    b.cap = cap;
+  }
+  if (!b.stream) RR_HIP(hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking));
+  if (!b.ev) RR_HIP(hipEventCreateWithFlags(&b.ev, hipEventDisableTiming));
+  *out = &b;
+  return RR_OK;
+}
+
+// All problems in one persistent kernel launch (captured once per batch size
+// into a HIP graph and replayed): one workgroup per problem at a time, the
+// problems taken longest first.
+rr_status solve_batched_persistent(int nprob, rr_handle* const* hs, const double* lams,
+                                   const double* const* rhs, double* const* ws, const rr_solve_opts& op,
+                                   rr_solve_info* infos, hipStream_t caller) {
+  const double t0 = now_ms();
+  if (op.krylov != RR_KRYLOV_PCG || op.precision != RR_PREC_F64 || op.smoother != RR_SMOOTHER_POINT)
+    return fail(RR_ERR_UNSUPPORTED, "the persistent batched solve runs FP64 PCG with the point smoother");
+  if (op.precond != RR_PRECOND_VCYCLE && op.precond != RR_PRECOND_JACOBI)
+    return fail(RR_ERR_UNSUPPORTED, "the persistent batched solve runs the V(1,1) or Jacobi preconditioner");
+  if (op.fixed_iters < 0 || op.max_iter < 0 || op.tol < 0)
+    return fail(RR_ERR_INVALID_ARG, "negative option");
+  const double tol = op.tol > 0 ? op.tol : 1e-10;
+  const int max_iter = op.fixed_iters > 0 ? op.fixed_iters : (op.max_iter > 0 ? op.max_iter : 10000);
+  int dev = 0;
+  RR_HIP(hipGetDevice(&dev));
+  std::vector<BatchProb> pv(nprob);
+  std::vector<long long> cost(nprob);
+  std::vector<LambdaSlot*> used;
+  rr_status res = RR_OK;
+  for (int i = 0; i < nprob && res == RR_OK; ++i) {
+    rr_handle* h = hs[i];
+    const Sparse& X = h->X;
+    if (!X.binary || !X.bplan.csplit) {
+      res = fail(RR_ERR_UNSUPPORTED, "the persistent batched solve needs 0/1 X with at most 8192 features");
+      break;
+    }
+    if (h->device != dev) {
+      res = fail(RR_ERR_INVALID_ARG, "every handle of a persistent batch must live on the current device");
+      break;
+    }
+    if (X.rw || h->lsw) {
+      res = fail(RR_ERR_UNSUPPORTED, "the persistent batched solve runs unweighted X with P of the square-root average");
+      break;
+    }
+    const bool vc = op.precond == RR_PRECOND_VCYCLE;
+    if (vc && (h->FC == 0 || 2 * h->FC > kBatchRows)) {
+      res = fail(RR_ERR_INVALID_ARG, "V(1,1) in the persistent batched solve needs 1 <= n_coarse <= 5120");
+      break;
+    }
+    res = check_lambda(lams[i], false);
+    if (res != RR_OK) break;
+    if (!rhs[i] || !ws[i]) {
+      res = fail(RR_ERR_INVALID_ARG, "null rhs or w");
+      break;
+    }
+    int k = 0;
+    for (int j = 0; j < i; ++j) k += (hs[j] == h);
+    MemScope ms(&h->mem);
+    Work* w = nullptr;
+    res = get_work_set(h, k, &w);
+    if (res != RR_OK) break;
+    BatchProb& P = pv[i];
+    std::memset(&P, 0, sizeof(P));
+    P.N = X.N;
+    P.F = X.F;
+    P.FC = vc ? h->FC : 0;
+    P.nchunk = X.bplan.nchunk;
+    P.grow = X.bplan.grow;
+    for (int c = 0; c < 3; ++c) P.cls[c] = X.bplan.cls[c];
+    P.kind = vc ? 1 : 0;
+    P.rhs_is_b = op.rhs_is_b ? 1 : 0;
+    P.max_iter = max_iter;
+    P.fixed = op.fixed_iters > 0 ? 1 : 0;
+    P.rp = X.row_ptr;
+    P.ci = X.col_idx;
+    P.ri = X.row_idx;
+    P.csplit = X.bplan.csplit;
+    P.perm = h->perm;
+    P.coff = h->coff;
+    P.labels = h->labels;
+    P.fperm = h->fperm;
+    P.finv = h->finv;
+    P.cscale = h->cscale;
+    P.colnorm = h->colnorm;
+    P.rhs = rhs[i];
+    P.lam = lams[i];
+    P.tol2 = op.fixed_iters > 0 ? 0.0 : tol * tol;
+    P.omega = op.omega;
+    if (vc) {
+      LambdaSlot* sl = nullptr;
+      double ms = 0.0;
+      res = get_slot(h, h->X, lams[i], &sl, &ms, caller);
+      if (res != RR_OK) break;
+      sl->in_use++;
+      used.push_back(sl);
+      P.Ainv = sl->Ainv;
+      if (P.omega == 0.0) P.omega = sl->omega;
+    }
+    if (!std::isfinite(P.omega) || P.omega < 0.0) {
+      res = fail(RR_ERR_INVALID_ARG, "omega must be finite and >= 0");
+      break;
+    }
+    P.w = ws[i];
+    P.x = w->x;
+    P.r = w->r;
+    P.p = w->p;
+    P.z = w->z;
+    P.e1 = w->e1;
+    P.b = w->b;
+    P.t = w->q;
+    cost[i] = (long long)X.nnz + X.N + X.F;
+  }
+  BatchBuffers* bb = nullptr;
+  std::unique_lock<std::mutex> lk(g_batch_mu);
+  if (res == RR_OK) res = batch_buffers(dev, nprob, &bb);
+  if (res == RR_OK) {
+    std::vector<int> order(nprob);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    int ncu = 256;
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    const int grid = std::max(1, std::min(nprob, ncu));
+    auto run = [&]() -> rr_status {
+      RR_HIP(hipMemcpyAsync(bb->probs, pv.data(), sizeof(BatchProb) * nprob, hipMemcpyHostToDevice, caller));
+      RR_HIP(hipMemcpyAsync(bb->order, order.data(), sizeof(int) * nprob, hipMemcpyHostToDevice, caller));
+      if (op.graph) {
+        if (!bb->exec || bb->graph_n != nprob || bb->graph_grid != grid) {
+          if (bb->exec) (void)hipGraphExecDestroy(bb->exec);
+          if (bb->graph) (void)hipGraphDestroy(bb->graph);
+          bb->exec = nullptr;
+          bb->graph = nullptr;
+          RR_HIP(hipStreamBeginCapture(bb->stream, hipStreamCaptureModeThreadLocal));
+          launch_batch_solve(bb->probs, bb->order, nprob, bb->queue, bb->out, grid, bb->stream);
+          hipGraph_t g = nullptr;
+          RR_HIP(hipStreamEndCapture(bb->stream, &g));
+          bb->graph = g;
+          RR_HIP(hipGraphInstantiate(&bb->exec, g, nullptr, nullptr, 0));
+          bb->graph_n = nprob;
+          bb->graph_grid = grid;
+        }
+        RR_HIP(hipEventRecord(bb->ev, caller));
+        RR_HIP(hipStreamWaitEvent(bb->stream, bb->ev, 0));
+        RR_HIP(hipGraphLaunch(bb->exec, bb->stream));
+        RR_HIP(hipEventRecord(bb->ev, bb->stream));
+        RR_HIP(hipStreamWaitEvent(caller, bb->ev, 0));
+      } else {
+        launch_batch_solve(bb->probs, bb->order, nprob, bb->queue, bb->out, grid, caller);
+      }
+      RR_HIP(hipGetLastError());
+      return RR_OK;
+    };
+    res = run();
+    if (res == RR_OK) {
+      std::vector<BatchOut> out(nprob);
+      RR_HIP(hipMemcpyAsync(out.data(), bb->out, sizeof(BatchOut) * nprob, hipMemcpyDeviceToHost, caller));
+      RR_HIP(hipStreamSynchronize(caller));
+      int clock_khz = 0;
+      (void)hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev);
+      for (int i = 0; i < nprob; ++i) {
+        int st = out[i].status;
+        if (op.fixed_iters > 0 && st == RR_ERR_NOT_CONVERGED && out[i].iters == op.fixed_iters) st = RR_OK;
+        if (infos) {
+          rr_solve_info inf{};
+          inf.status = st;
+          inf.iters = out[i].iters;
+          inf.op_applies = (pv[i].kind == 1 ? 3 : 1) * out[i].iters;
+          inf.relres = out[i].relres;
+          inf.true_relres = out[i].true_relres;
+          inf.omega = pv[i].omega;
+          // the problem's own time on its workgroup
+          inf.ms = clock_khz > 0 ? (double)(out[i].t_end - out[i].t_begin) / clock_khz : now_ms() - t0;
+          inf.fallback_iter = -1;
+          infos[i] = inf;
+        }
+        if (st != RR_OK && res == RR_OK)
+          res = fail((rr_status)st, st == RR_ERR_NOT_CONVERGED ? "max_iter reached before the tolerance"
+                                                               : "breakdown: <p,Ap> or <r,z> not positive");
+      }
+    }
+  }
+  for (LambdaSlot* sl : used) sl->in_use--;
+  return res;
+}
+
 }  // namespace
 
 namespace rr {
@@ -1470,10 +1824,12 @@ extern "C" {
 
 const char* rr_last_error(void) { return g_last_error.c_str(); }
 
-rr_status rr_setup(const rr_csr* X, const rr_setup_opts* opts, rr_stream stream, rr_handle** out) {
-  g_last_error.clear();
+rr_status setup_common(const rr_csr* X, const rr_setup_opts* opts, rr_stream stream, const MemCtx& mem,
+                       rr_handle** out) {
   if (!X || !out) return fail(RR_ERR_INVALID_ARG, "null argument");
   *out = nullptr;
+  rr_setup_opts o;
+  RR_TRY(read_opts(opts, &o));
   if (X->n_rows < 1 || X->n_cols < 1 || X->nnz < 0)
     return fail(RR_ERR_INVALID_ARG, "X: need n_rows >= 1, n_cols >= 1, nnz >= 0");
   if (X->n_rows >= (1ll << 31) - 1 || X->n_cols >= (1ll << 31) - 1 || X->nnz >= (1ll << 31) - 1 ||
@@ -1481,11 +1837,14 @@ rr_status rr_setup(const rr_csr* X, const rr_setup_opts* opts, rr_stream stream,
     return fail(RR_ERR_INVALID_ARG, "X: sizes must fit 32-bit indices");
   if (!X->row_ptr || (X->nnz > 0 && !X->col_idx))
     return fail(RR_ERR_INVALID_ARG, "X: null row_ptr or col_idx");
-  if (opts && (opts->n_clusters < 0 || opts->kmeans_max_iter < 0 || opts->lambda_slots < 0))
+  if (o.n_clusters < 0 || o.kmeans_max_iter < 0 || o.lambda_slots < 0 || o.reserve_fcg_m < 0 ||
+      o.reserve_sets < 0)
     return fail(RR_ERR_INVALID_ARG, "negative option");
   rr_handle* h = new (std::nothrow) rr_handle();
   if (!h) return fail(RR_ERR_DEVICE, "out of host memory");
-  rr_status st = setup_impl(X, opts, (hipStream_t)stream, h);
+  h->mem = mem;
+  MemScope scope(&h->mem);
+  rr_status st = ws_status(h, setup_impl(X, &o, (hipStream_t)stream, h));
   if (st != RR_OK) {
     const std::string msg = g_last_error;
     (void)hipStreamSynchronize((hipStream_t)stream);
@@ -1497,20 +1856,58 @@ rr_status rr_setup(const rr_csr* X, const rr_setup_opts* opts, rr_stream stream,
   return RR_OK;
 }
 
+rr_status rr_setup(const rr_csr* X, const rr_setup_opts* opts, rr_stream stream, rr_handle** out) {
+  g_last_error.clear();
+  return setup_common(X, opts, stream, default_mem(), out);
+}
+
+rr_status rr_setup_ws(const rr_csr* X, const rr_setup_opts* opts, void* workspace, size_t ws_bytes,
+                      rr_stream stream, rr_handle** out) {
+  g_last_error.clear();
+  if (!workspace || ws_bytes == 0) return fail(RR_ERR_INVALID_ARG, "null or empty workspace");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256)
+    return fail(RR_ERR_INVALID_ARG, "the workspace must be 256-byte aligned");
+  MemCtx m;
+  m.mode = MemCtx::kBump;
+  m.base = static_cast<char*>(workspace);
+  m.cap = ws_bytes;
+  return setup_common(X, opts, stream, m, out);
+}
+
+rr_status rr_setup_workspace_size(const rr_csr* X, const rr_setup_opts* opts, rr_stream stream,
+                                  size_t* bytes) {
+  g_last_error.clear();
+  if (!bytes) return fail(RR_ERR_INVALID_ARG, "null bytes");
+  *bytes = 0;
+  MemCtx m;
+  m.mode = MemCtx::kCount;
+  rr_handle* h = nullptr;
+  RR_TRY(setup_common(X, opts, stream, m, &h));
+  *bytes = h->mem.used;
+  (void)hipDeviceSynchronize();
+  MemScope scope(&h->mem);
+  destroy_handle(h);
+  return RR_OK;
+}
+
 rr_status rr_setup_dense(const rr_dense* X, const rr_setup_opts* opts, rr_stream stream,
                          rr_handle** out) {
   g_last_error.clear();
   if (!X || !out) return fail(RR_ERR_INVALID_ARG, "null argument");
   *out = nullptr;
-  if (opts && (opts->n_clusters < 0 || opts->kmeans_max_iter < 0 || opts->lambda_slots < 0))
+  rr_setup_opts o;
+  RR_TRY(read_opts(opts, &o));
+  if (o.n_clusters < 0 || o.kmeans_max_iter < 0 || o.lambda_slots < 0)
     return fail(RR_ERR_INVALID_ARG, "negative option");
   rr_handle* h = new (std::nothrow) rr_handle();
   if (!h) return fail(RR_ERR_DEVICE, "out of host memory");
+  h->mem = default_mem();
+  MemScope scope(&h->mem);
   const double t0 = now_ms();
   hipStream_t s = (hipStream_t)stream;
   rr_status st = RR_OK;
   if (hipGetDevice(&h->device) != hipSuccess) st = fail(RR_ERR_DEVICE, "hipGetDevice failed");
-  if (st == RR_OK) st = dense_setup(h, X, opts, s);
+  if (st == RR_OK) st = dense_setup(h, X, &o, s);
   if (st != RR_OK) {
     const std::string msg = g_last_error;
     (void)hipStreamSynchronize(s);
@@ -1526,16 +1923,20 @@ rr_status rr_setup_dense(const rr_dense* X, const rr_setup_opts* opts, rr_stream
 rr_status rr_solve_block(rr_handle* h, double lambda, int32_t nrhs, const double* rhs,
                          int64_t ld_rhs, double* w, int64_t ld_w, const rr_solve_opts* opts,
                          rr_solve_info* info, rr_stream stream) {
+  MemScope mem_scope_(mem_of(h));
   g_last_error.clear();
   RR_TRY(check_handle(h));
   RR_TRY(check_lambda(lambda, false));
   if (!h->dense) return fail(RR_ERR_UNSUPPORTED, "rr_solve_block takes a handle from rr_setup_dense");
-  return dense_solve_block(h, lambda, nrhs, rhs, ld_rhs, w, ld_w, opts, info, (hipStream_t)stream);
+  rr_solve_opts o;
+  RR_TRY(read_opts(opts, &o));
+  return dense_solve_block(h, lambda, nrhs, rhs, ld_rhs, w, ld_w, &o, info, (hipStream_t)stream);
 }
 
 rr_status rr_apply_operator_block(rr_handle* h, double lambda, int32_t nrhs, const double* v,
                                   int64_t ldv, double* q, int64_t ldq, int32_t precision,
                                   rr_stream stream) {
+  MemScope mem_scope_(mem_of(h));
   g_last_error.clear();
   RR_TRY(check_handle(h));
   RR_TRY(check_lambda(lambda, true));
@@ -1546,11 +1947,13 @@ rr_status rr_apply_operator_block(rr_handle* h, double lambda, int32_t nrhs, con
 rr_status rr_destroy(rr_handle* h) {
   if (!h) return RR_OK;
   (void)hipDeviceSynchronize();
+  MemScope scope(&h->mem);
   destroy_handle(h);
   return RR_OK;
 }
 
 rr_status rr_get_setup_info(const rr_handle* h, rr_setup_info* info) {
+  MemScope mem_scope_(mem_of(h));
   RR_TRY(check_handle(h));
   if (!info) return fail(RR_ERR_INVALID_ARG, "null info");
   rr_setup_info i{};
@@ -1579,6 +1982,7 @@ rr_status rr_get_setup_info(const rr_handle* h, rr_setup_info* info) {
 }
 
 rr_status rr_get_labels(const rr_handle* h, int32_t* labels, rr_stream stream) {
+  MemScope mem_scope_(mem_of(h));
   RR_TRY(check_handle(h));
   if (!labels) return fail(RR_ERR_INVALID_ARG, "null labels");
   if (h->FC == 0) return fail(RR_ERR_INVALID_ARG, "no aggregation (n_clusters = 0)");
@@ -1589,6 +1993,7 @@ rr_status rr_get_labels(const rr_handle* h, int32_t* labels, rr_stream stream) {
 }
 
 rr_status rr_get_centres(const rr_handle* h, int32_t* centres, rr_stream stream) {
+  MemScope mem_scope_(mem_of(h));
   RR_TRY(check_handle(h));
   if (!centres) return fail(RR_ERR_INVALID_ARG, "null centres");
   if (!h->centres || h->n_centres == 0) return fail(RR_ERR_INVALID_ARG, "no k-means seeding was run");
@@ -1599,20 +2004,31 @@ rr_status rr_get_centres(const rr_handle* h, int32_t* centres, rr_stream stream)
 
 rr_status rr_solve(rr_handle* h, double lambda, const double* rhs, double* w,
                    const rr_solve_opts* opts, rr_solve_info* info, rr_stream stream) {
+  MemScope mem_scope_(mem_of(h));
   g_last_error.clear();
   RR_TRY(check_sparse(h));
-  return solve_impl(h, lambda, rhs, w, opts, info, (hipStream_t)stream);
+  rr_solve_opts o;
+  RR_TRY(read_opts(opts, &o));
+  h->mem.overflow = false;
+  return ws_status(h, solve_impl(h, lambda, rhs, w, &o, info, (hipStream_t)stream));
 }
 
 rr_status rr_solve_batched(int32_t nprob, rr_handle* const* handles, const double* lambdas,
                            const double* const* rhs, double* const* w, const rr_solve_opts* opts,
                            rr_solve_info* info, rr_stream stream) {
   g_last_error.clear();
-  return solve_batched_impl(nprob, handles, lambdas, rhs, w, opts, info, (hipStream_t)stream);
+  rr_solve_opts o;
+  RR_TRY(read_opts(opts, &o));
+  for (int i = 0; i < nprob && handles; ++i)
+    if (handles[i]) handles[i]->mem.overflow = false;
+  rr_status st = solve_batched_impl(nprob, handles, lambdas, rhs, w, &o, info, (hipStream_t)stream);
+  for (int i = 0; st != RR_OK && i < nprob && handles; ++i) st = ws_status(handles[i], st);
+  return st;
 }
 
 rr_status rr_apply_operator(rr_handle* h, double lambda, const double* v, double* Av,
                             rr_stream stream) {
+  MemScope mem_scope_(mem_of(h));
   RR_TRY(check_sparse(h));
   RR_TRY(check_lambda(lambda, true));
   if (!v || !Av) return fail(RR_ERR_INVALID_ARG, "null vector");
@@ -1631,6 +2047,7 @@ rr_status rr_apply_operator(rr_handle* h, double lambda, const double* v, double
 }
 
 rr_status rr_apply_rhs(rr_handle* h, const double* y, double* b, rr_stream stream) {
+  MemScope mem_scope_(mem_of(h));
   RR_TRY(check_sparse(h));
   if (!y || !b) return fail(RR_ERR_INVALID_ARG, "null vector");
   Epi e{};
@@ -1643,6 +2060,7 @@ rr_status rr_apply_rhs(rr_handle* h, const double* y, double* b, rr_stream strea
 
 rr_status rr_noise_rhs(rr_handle* h, double tau, double lambda, const double* y, const double* xi1,
                        const double* xi2, double* b, rr_stream stream) {
+  MemScope mem_scope_(mem_of(h));
   RR_TRY(check_sparse(h));
   if (!y || !xi1 || !xi2 || !b) return fail(RR_ERR_INVALID_ARG, "null vector");
   if (h->X.rw) return fail(RR_ERR_UNSUPPORTED, "noise injection is built for unweighted X");
@@ -1669,6 +2087,7 @@ __global__ void k_check_weights(int N, const double* d, int* bad) {
 }
 
 rr_status rr_set_row_weights(rr_handle* h, const double* d, rr_stream stream) {
+  MemScope mem_scope_(mem_of(h));
   RR_TRY(check_sparse(h));
   if (!h->X.binary) return fail(RR_ERR_UNSUPPORTED, "row weights are built for 0/1 X");
   if (h->nblk > 0) return fail(RR_ERR_UNSUPPORTED, "the block smoother's blocks are built for unweighted X");
@@ -1677,13 +2096,13 @@ rr_status rr_set_row_weights(rr_handle* h, const double* d, rr_stream stream) {
   const int N = h->X.N, F = h->X.F;
   if (d) {
     int* flag = nullptr;
-    RR_HIP(hipMalloc(&flag, sizeof(int)));
+    RR_HIP(dmalloc(&flag, sizeof(int)));
     RR_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
     k_check_weights<<<cdiv(N, kBlock), kBlock, 0, s>>>(N, d, flag);
     int bad = 0;
     RR_HIP(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     RR_HIP(hipStreamSynchronize(s));
-    (void)hipFree(flag);
+    (void)dev_free(flag);
     if (bad) return fail(RR_ERR_INVALID_ARG, "row weights must be finite and >= 0");
     if (!h->rw) RR_TRY(dalloc(&h->rw, std::max(1, N)));
     RR_HIP(hipMemcpyAsync(h->rw, d, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
@@ -1732,6 +2151,7 @@ rr_status rr_set_row_weights(rr_handle* h, const double* d, rr_stream stream) {
 
 rr_status rr_set_interpolation(rr_handle* h, const double* V, int32_t n_proto, double beta,
                                const int32_t* rep, double* p, rr_stream stream) {
+  MemScope mem_scope_(mem_of(h));
   g_last_error.clear();
   RR_TRY(check_sparse(h));
   if (h->FC == 0) return fail(RR_ERR_INVALID_ARG, "no aggregation (n_clusters = 0)");
@@ -1757,7 +2177,20 @@ rr_status rr_set_interpolation(rr_handle* h, const double* V, int32_t n_proto, d
   return RR_OK;
 }
 
+rr_status rr_prototypes(rr_handle* h, int32_t n_proto, int32_t steps, uint64_t seed, double* V,
+                        double* ev, rr_stream stream) {
+  g_last_error.clear();
+  MemScope mem_scope_(mem_of(h));
+  RR_TRY(check_sparse(h));
+  if (n_proto < 1 || n_proto > 64) return fail(RR_ERR_INVALID_ARG, "n_proto must be in [1, 64]");
+  if (steps == 0) steps = std::max(30, 3 * n_proto);
+  if (steps < n_proto || steps > 512) return fail(RR_ERR_INVALID_ARG, "steps must be in [n_proto, 512]");
+  if (!V || !ev) return fail(RR_ERR_INVALID_ARG, "null V or ev");
+  return ws_status(h, lanczos_prototypes(h, n_proto, steps, seed, V, ev, (hipStream_t)stream));
+}
+
 rr_status rr_apply_rows(rr_handle* h, const double* v, double* u, rr_stream stream) {
+  MemScope mem_scope_(mem_of(h));
   RR_TRY(check_sparse(h));
   if (!v || !u) return fail(RR_ERR_INVALID_ARG, "null vector");
   hipStream_t s = (hipStream_t)stream;
@@ -1770,6 +2203,7 @@ rr_status rr_apply_rows(rr_handle* h, const double* v, double* u, rr_stream stre
 }
 
 rr_status rr_coarse_eigen(rr_handle* h, double* Q, double* ev, rr_stream stream) {
+  MemScope mem_scope_(mem_of(h));
   RR_TRY(check_handle(h));
   if (!h->eig_q) return fail(RR_ERR_INVALID_ARG, "the handle was set up without coarse_eigen");
   hipStream_t s = (hipStream_t)stream;
@@ -1780,6 +2214,7 @@ rr_status rr_coarse_eigen(rr_handle* h, double* Q, double* ev, rr_stream stream)
 
 rr_status rr_apply_precond(rr_handle* h, double lambda, int32_t precond, double omega,
                            const double* r, double* z, rr_stream stream) {
+  MemScope mem_scope_(mem_of(h));
   RR_TRY(check_sparse(h));
   RR_TRY(check_lambda(lambda, false));
   if (!r || !z) return fail(RR_ERR_INVALID_ARG, "null vector");
@@ -1820,6 +2255,7 @@ rr_status rr_apply_precond(rr_handle* h, double lambda, int32_t precond, double 
 }
 
 rr_status rr_coarse_gram(rr_handle* h, double* K, rr_stream stream) {
+  MemScope mem_scope_(mem_of(h));
   RR_TRY(check_handle(h));
   if (!K) return fail(RR_ERR_INVALID_ARG, "null K");
   if (h->FC == 0) return fail(RR_ERR_INVALID_ARG, "no coarse level");
@@ -1829,6 +2265,7 @@ rr_status rr_coarse_gram(rr_handle* h, double* K, rr_stream stream) {
 }
 
 rr_status rr_coarse_factor(rr_handle* h, double lambda, double* L, double* Ainv, rr_stream stream) {
+  MemScope mem_scope_(mem_of(h));
   RR_TRY(check_handle(h));
   RR_TRY(check_lambda(lambda, false));
   if (h->FC == 0) return fail(RR_ERR_INVALID_ARG, "no coarse level");
@@ -1844,6 +2281,7 @@ rr_status rr_coarse_factor(rr_handle* h, double lambda, double* L, double* Ainv,
 }
 
 rr_status rr_mlp_init(rr_handle* h, int32_t hidden, uint64_t seed) {
+  MemScope mem_scope_(mem_of(h));
   RR_TRY(check_sparse(h));
   if (h->FC == 0) return fail(RR_ERR_INVALID_ARG, "no coarse level");
   if (hidden < 16 || hidden > 1024) return fail(RR_ERR_INVALID_ARG, "hidden must be in [16, 1024]");
@@ -1866,6 +2304,7 @@ rr_status rr_mlp_init(rr_handle* h, int32_t hidden, uint64_t seed) {
 }
 
 rr_status rr_mlp_size(const rr_handle* h, int64_t* n_params, int32_t* n_in, int32_t* n_out) {
+  MemScope mem_scope_(mem_of(h));
   RR_TRY(check_handle(h));
   if (!h->mlp.w) return fail(RR_ERR_INVALID_ARG, "no network (rr_mlp_init)");
   if (n_params) *n_params = (int64_t)h->mlp.nparam;
@@ -1875,6 +2314,7 @@ rr_status rr_mlp_size(const rr_handle* h, int64_t* n_params, int32_t* n_in, int3
 }
 
 rr_status rr_mlp_set_weights(rr_handle* h, const float* host_params) {
+  MemScope mem_scope_(mem_of(h));
   RR_TRY(check_handle(h));
   if (!h->mlp.w) return fail(RR_ERR_INVALID_ARG, "no network (rr_mlp_init)");
   if (!host_params) return fail(RR_ERR_INVALID_ARG, "null parameters");
@@ -1882,6 +2322,7 @@ rr_status rr_mlp_set_weights(rr_handle* h, const float* host_params) {
 }
 
 rr_status rr_mlp_get_weights(const rr_handle* h, float* host_params) {
+  MemScope mem_scope_(mem_of(h));
   RR_TRY(check_handle(h));
   if (!h->mlp.w) return fail(RR_ERR_INVALID_ARG, "no network (rr_mlp_init)");
   if (!host_params) return fail(RR_ERR_INVALID_ARG, "null parameters");
@@ -1891,6 +2332,7 @@ rr_status rr_mlp_get_weights(const rr_handle* h, float* host_params) {
 }
 
 rr_status rr_mlp_forward(rr_handle* h, const float* in, int32_t batch, float* out, rr_stream stream) {
+  MemScope mem_scope_(mem_of(h));
   RR_TRY(check_handle(h));
   Mlp& n = h->mlp;
   if (!n.w) return fail(RR_ERR_INVALID_ARG, "no network (rr_mlp_init)");
@@ -1909,6 +2351,7 @@ rr_status rr_mlp_forward(rr_handle* h, const float* in, int32_t batch, float* ou
 
 rr_status rr_mlp_backward(rr_handle* h, const float* in, const float* dout, int32_t batch,
                           float* grads, rr_stream stream) {
+  MemScope mem_scope_(mem_of(h));
   RR_TRY(check_handle(h));
   Mlp& n = h->mlp;
   if (!n.w) return fail(RR_ERR_INVALID_ARG, "no network (rr_mlp_init)");
@@ -1926,12 +2369,13 @@ rr_status rr_mlp_backward(rr_handle* h, const float* in, const float* dout, int3
 
 rr_status rr_mlp_train(rr_handle* h, const float* in, const float* target, int64_t npairs,
                        const rr_mlp_train_opts* opts, float* loss_history, rr_stream stream) {
+  MemScope mem_scope_(mem_of(h));
   RR_TRY(check_handle(h));
   Mlp& n = h->mlp;
   if (!n.w) return fail(RR_ERR_INVALID_ARG, "no network (rr_mlp_init)");
   if (npairs < 1 || !in || !target) return fail(RR_ERR_INVALID_ARG, "need n >= 1 pairs");
-  rr_mlp_train_opts o{};
-  if (opts) o = *opts;
+  rr_mlp_train_opts o;
+  RR_TRY(read_opts(opts, &o));
   const int epochs = o.epochs > 0 ? o.epochs : 20;
   const int B = o.batch > 0 ? o.batch : 256;
   if (B > n.max_batch || npairs > (1LL << 31) - 1)
@@ -1981,10 +2425,13 @@ rr_status rr_mlp_train(rr_handle* h, const float* in, const float* target, int64
   return RR_OK;
 }
 
-rr_status rr_collect_pairs(rr_handle* h, const double* lambdas, int32_t n_solves,
-                           int32_t pairs_per_solve, int32_t every, const double* y, float* inputs,
-                           float* targets, int64_t* n_pairs, rr_stream stream) {
-  RR_TRY(check_sparse(h));
+namespace {
+// Pairs from solves driven by the algebraic cycle (V(1,1) PCG) or, with
+// `learned`, by the network itself (its flexible-CG solve, which visits the
+// residuals the network's own corrections leave).
+rr_status collect_pairs(rr_handle* h, bool learned, const double* lambdas, int32_t n_solves,
+                        int32_t pairs_per_solve, int32_t every, const double* y, float* inputs,
+                        float* targets, int64_t* n_pairs, rr_stream stream) {
   if (h->FC == 0) return fail(RR_ERR_INVALID_ARG, "no coarse level");
   if (n_solves < 0 || pairs_per_solve < 1 || every < 1 || !lambdas || !y || !inputs || !targets)
     return fail(RR_ERR_INVALID_ARG, "bad pair-collection arguments");
@@ -2005,7 +2452,11 @@ rr_status rr_collect_pairs(rr_handle* h, const double* lambdas, int32_t n_solves
     sv.lam = lambdas[i];
     sv.rhs = y;
     sv.wout = wtmp;
-    sv.op.precond = PK_VCYCLE;
+    sv.op.precond = learned ? PK_LEARNED : PK_VCYCLE;
+    if (learned) {
+      sv.op.krylov = RR_KRYLOV_FCG;
+      sv.op.fcg_m = 4;
+    }
     sv.op.tol = 1e-10;
     sv.op.max_iter = every * pairs_per_solve;
     sv.s = s;
@@ -2043,8 +2494,30 @@ rr_status rr_collect_pairs(rr_handle* h, const double* lambdas, int32_t n_solves
   if (n_pairs) *n_pairs = written;
   return RR_OK;
 }
+}  // namespace
+
+rr_status rr_collect_pairs(rr_handle* h, const double* lambdas, int32_t n_solves,
+                           int32_t pairs_per_solve, int32_t every, const double* y, float* inputs,
+                           float* targets, int64_t* n_pairs, rr_stream stream) {
+  MemScope mem_scope_(mem_of(h));
+  RR_TRY(check_sparse(h));
+  return collect_pairs(h, false, lambdas, n_solves, pairs_per_solve, every, y, inputs, targets, n_pairs,
+                       stream);
+}
+
+rr_status rr_collect_pairs_learned(rr_handle* h, const double* lambdas, int32_t n_solves,
+                                   int32_t pairs_per_solve, int32_t every, const double* y, float* inputs,
+                                   float* targets, int64_t* n_pairs, rr_stream stream) {
+  MemScope mem_scope_(mem_of(h));
+  RR_TRY(check_sparse(h));
+  if (!h->mlp.w || h->mlp.in != h->FC + 1 || h->mlp.out != h->FC)
+    return fail(RR_ERR_INVALID_ARG, "no network for this coarse level (rr_mlp_init)");
+  return collect_pairs(h, true, lambdas, n_solves, pairs_per_solve, every, y, inputs, targets, n_pairs,
+                       stream);
+}
 
 rr_status rr_smoother_weight(rr_handle* h, double lambda, double* omega) {
+  MemScope mem_scope_(mem_of(h));
   RR_TRY(check_handle(h));
   RR_TRY(check_lambda(lambda, false));
   if (!omega) return fail(RR_ERR_INVALID_ARG, "null omega");

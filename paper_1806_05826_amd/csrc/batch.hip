@@ -1,0 +1,421 @@
+// Many independent ridge problems (0/1 X, FP64) solved in one persistent
+// launch: every workgroup takes the next problem from a device queue (the
+// problems sorted by descending cost, so the longest start first), runs its
+// whole PCG solve with the two-level V(1,1) preconditioner (or Jacobi)
+// using workgroup barriers only, writes w and the problem's record, and
+// takes the next problem until the queue is empty.
+//
+// The operator q = X^T (X v) + lambda v of a problem runs out of LDS: the
+// gathered vector v (F <= 8192 features, 64 KB of FP64) sits in LDS, and the
+// rows are processed in chunks of kBU = 10240: the chunk's u = X v is formed
+// in LDS (80 KB), then every column adds the entries of its rows inside the
+// chunk (a column's CSC entries of chunk h start at csplit[h F + j]) into
+// t_j.  A group of lanes owns a row (G_row lanes, the problem's tuned value)
+// or a column (64, 16, 4 or 1 lanes by the column's length; the columns are
+// in descending-count order, so each class is a range), adds in a fixed
+// order and reduces with a fixed butterfly; the same group owns the same
+// column in every chunk, so t_j accumulates without atomics and every result
+// is bitwise reproducible.  Between operator applications the coarse
+// residual and correction live in the chunk buffer.
+#include <algorithm>
+#include <mutex>
+#include <numeric>
+
+#include "rr_device.h"
+
+namespace rr {
+
+constexpr int kBT = 1024;   // threads per workgroup
+static_assert(kBT == kSliceBlock, "the batched solver runs 1024-thread workgroups");
+
+// LDS: the gathered vector and the row chunk (or, between applications, the
+// coarse residual and correction)
+struct BatchLds {
+  double V[kBatchFMax];
+  double U[kBatchRows];
+  double red[kBT / 64];
+  int qslot;
+};
+
+__device__ inline double wg_sum(double v, double* red) { return block_sum_n<kBT>(v, red); }
+
+// sum over groups of G lanes (G a power of two <= 64), fixed butterfly
+template <int G>
+__device__ inline double group_sum(double s) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
+  return s;
+}
+
+// sum of vec[idx[k] - shift] over k = a + sub, a + sub + G, ... < z: a
+// lane's entries in batches of 16 index loads in flight (one workgroup per
+// CU streams the problem's indexes, so its memory-level parallelism is what
+// bounds it), two accumulators in a fixed order
+template <int G>
+__device__ inline double lane_gather(const int* __restrict__ idx, const double* vec, int a, int z,
+                                     int sub, int shift) {
+  constexpr int B = 16;
+  double s0 = 0.0, s1 = 0.0;
+  int k = a + sub;
+  for (; k + (B - 1) * G < z; k += B * G) {
+    int i[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) i[u] = idx[k + u * G];
+#pragma unroll
+    for (int u = 0; u < B; u += 2) {
+      s0 += vec[i[u] - shift];
+      s1 += vec[i[u + 1] - shift];
+    }
+  }
+  if (k < z) {   // the rest: fewer than 16 entries, loads issued together
+    int i[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) i[u] = (k + u * G < z) ? idx[k + u * G] : -1;
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+      if (i[u] >= 0) s0 += vec[i[u] - shift];
+  }
+  return s0 + s1;
+}
+
+// rows [r0, r1) of the chunk: U[i - r0] = sum_{j in row i} V[j], G lanes per row
+template <int G>
+__device__ inline void chunk_rows(const BatchProb& P, BatchLds& L, int r0, int r1) {
+  const int tid = threadIdx.x, sub = tid & (G - 1);
+  constexpr int per = kBT / G;
+  const int n = r1 - r0;
+  for (int base = 0; base < n; base += per) {   // the same trip count in every lane
+    const int i = r0 + base + tid / G;
+    double s = 0.0;
+    if (i < r1) s = lane_gather<G>(P.ci, L.V, P.rp[i], P.rp[i + 1], sub, 0);
+    s = group_sum<G>(s);
+    if (i < r1 && sub == 0) L.U[i - r0] = s;
+  }
+}
+
+// columns [c0, c1) over chunk h: t_j (+)= sum of U over the column's rows in
+// the chunk, G lanes per column
+template <int G>
+__device__ inline void chunk_cols(const BatchProb& P, const BatchLds& L, int h, int r0, int c0, int c1,
+                                  double* __restrict__ t) {
+  const int tid = threadIdx.x, sub = tid & (G - 1);
+  constexpr int per = kBT / G;
+  const int F = P.F;
+  for (int base = c0; base < c1; base += per) {
+    const int j = base + tid / G;
+    double s = 0.0;
+    if (j < c1)
+      s = lane_gather<G>(P.ri, L.U, P.csplit[(size_t)h * F + j], P.csplit[(size_t)(h + 1) * F + j], sub, r0);
+    s = group_sum<G>(s);
+    if (j < c1 && sub == 0) t[j] = (h == 0 ? 0.0 : t[j]) + s;
+  }
+}
+
+template <int G>
+__device__ inline void all_cols(const BatchProb& P, const BatchLds& L, int h, int r0, double* t) {
+  (void)G;
+  chunk_cols<64>(P, L, h, r0, 0, P.cls[0], t);
+  chunk_cols<16>(P, L, h, r0, P.cls[0], P.cls[1], t);
+  chunk_cols<4>(P, L, h, r0, P.cls[1], P.cls[2], t);
+  chunk_cols<1>(P, L, h, r0, P.cls[2], P.F, t);
+}
+
+// t = X^T (X V) with V already in LDS (and visible: the caller synchronised)
+__device__ inline void wg_gram(const BatchProb& P, BatchLds& L, double* __restrict__ t) {
+  for (int h = 0; h < P.nchunk; ++h) {
+    const int r0 = h * kBatchRows, r1 = min(P.N, r0 + kBatchRows);
+    switch (P.grow) {
+      case 1: chunk_rows<1>(P, L, r0, r1); break;
+      case 2: chunk_rows<2>(P, L, r0, r1); break;
+      case 4: chunk_rows<4>(P, L, r0, r1); break;
+      case 8: chunk_rows<8>(P, L, r0, r1); break;
+      case 16: chunk_rows<16>(P, L, r0, r1); break;
+      case 32: chunk_rows<32>(P, L, r0, r1); break;
+      default: chunk_rows<64>(P, L, r0, r1); break;
+    }
+    __syncthreads();
+    all_cols<1>(P, L, h, r0, t);
+    __syncthreads();
+  }
+}
+
+// t = X^T y for a caller vector y (rows of the chunk staged through U)
+__device__ inline void wg_rhs(const BatchProb& P, BatchLds& L, const double* __restrict__ y,
+                              double* __restrict__ t) {
+  for (int h = 0; h < P.nchunk; ++h) {
+    const int r0 = h * kBatchRows, r1 = min(P.N, r0 + kBatchRows);
+    for (int i = r0 + threadIdx.x; i < r1; i += kBT) L.U[i - r0] = y[i];
+    __syncthreads();
+    all_cols<1>(P, L, h, r0, t);
+    __syncthreads();
+  }
+}
+
+// z = B r: V(1,1) two-level cycle (kind 1) or Jacobi (kind 0); returns <r,z>
+__device__ inline double wg_precond(const BatchProb& P, BatchLds& L) {
+  const int F = P.F, tid = threadIdx.x;
+  const double lam = P.lam, om = P.omega;
+  if (P.kind == 0) {
+    double rz = 0.0;
+    for (int j = tid; j < F; j += kBT) {
+      const double zj = P.r[j] / (P.colnorm[j] + lam);
+      P.z[j] = zj;
+      rz += P.r[j] * zj;
+    }
+    return wg_sum(rz, L.red);
+  }
+  // e1 = w D^-1 r, into LDS and e1
+  for (int j = tid; j < F; j += kBT) {
+    const double e = (om * P.r[j]) / (P.colnorm[j] + lam);
+    L.V[j] = e;
+    P.e1[j] = e;
+  }
+  __syncthreads();
+  wg_gram(P, L, P.t);
+  // rho1 = r - (t + lam e1); c = P^T rho1 (cluster sums scaled by 1/sqrt(n_s)),
+  // 16 lanes per cluster, into U[0, FC)
+  {
+    const int sub = tid & 15;
+    for (int base = 0; base < P.FC; base += kBT / 16) {
+      const int l = base + tid / 16;
+      double s = 0.0;
+      if (l < P.FC) {
+        for (int k = P.coff[l] + sub; k < P.coff[l + 1]; k += 16) {
+          const int j = P.perm[k];
+          s += P.r[j] - (P.t[j] + lam * P.e1[j]);
+        }
+      }
+      s = group_sum<16>(s);
+      if (l < P.FC && sub == 0) L.U[l] = s * P.cscale[l];
+    }
+  }
+  __syncthreads();
+  // yc = A_c^-1 c, one wave per row, into U[FC, 2 FC)
+  {
+    const int wv = tid >> 6, lane = tid & 63;
+    const int fc = P.FC;
+    for (int row = wv; row < fc; row += kBT / 64) {
+      const double* a = P.Ainv + (size_t)row * fc;
+      double s0 = 0.0, s1 = 0.0;
+      int c = lane;
+      for (; c + 64 < fc; c += 128) {
+        s0 += a[c] * L.U[c];
+        s1 += a[c + 64] * L.U[c + 64];
+      }
+      if (c < fc) s0 += a[c] * L.U[c];
+      double s = s0 + s1;
+      s = group_sum<64>(s);
+      if (lane == 0) L.U[fc + row] = s;
+    }
+  }
+  __syncthreads();
+  // e2 = e1 + P yc, into LDS and z
+  for (int j = tid; j < F; j += kBT) {
+    const int l = P.labels[j];
+    const double e2 = P.e1[j] + P.cscale[l] * L.U[P.FC + l];
+    L.V[j] = e2;
+    P.z[j] = e2;
+  }
+  __syncthreads();
+  wg_gram(P, L, P.t);
+  // z = e2 + w D^-1 (r - (t + lam e2))
+  double rz = 0.0;
+  for (int j = tid; j < F; j += kBT) {
+    const double e2 = L.V[j], rj = P.r[j];
+    const double rho = rj - (P.t[j] + lam * e2);
+    const double zj = e2 + (om * rho) / (P.colnorm[j] + lam);
+    P.z[j] = zj;
+    rz += rj * zj;
+  }
+  return wg_sum(rz, L.red);
+}
+
+__device__ inline void solve_one(const BatchProb& P, BatchLds& L, BatchOut* out) {
+  const int F = P.F, tid = threadIdx.x;
+  const double lam = P.lam;
+  const long long t_begin = wall_clock64();
+  // b
+  if (P.rhs_is_b) {
+    for (int j = tid; j < F; j += kBT) P.b[j] = P.rhs[P.fperm[j]];
+  } else {
+    wg_rhs(P, L, P.rhs, P.b);
+  }
+  __syncthreads();
+  double bb = 0.0;
+  for (int j = tid; j < F; j += kBT) {
+    const double bj = P.b[j];
+    P.x[j] = 0.0;
+    P.r[j] = bj;
+    bb += bj * bj;
+  }
+  bb = wg_sum(bb, L.red);
+  int status = RR_ERR_NOT_CONVERGED, it = 0;
+  double rr = bb;
+  if (bb == 0.0) {
+    status = RR_OK;
+  } else {
+    double rz = wg_precond(P, L);
+    for (int j = tid; j < F; j += kBT) P.p[j] = P.z[j];
+    __syncthreads();
+    if (!finite_pos(rz)) status = RR_ERR_BREAKDOWN;
+    while (status == RR_ERR_NOT_CONVERGED && it < P.max_iter) {
+      // q = A p (t holds X^T X p), <p, q>
+      for (int j = tid; j < F; j += kBT) L.V[j] = P.p[j];
+      __syncthreads();
+      wg_gram(P, L, P.t);
+      double pq = 0.0;
+      for (int j = tid; j < F; j += kBT) pq += L.V[j] * (P.t[j] + lam * L.V[j]);
+      pq = wg_sum(pq, L.red);
+      if (!finite_pos(pq)) {
+        status = RR_ERR_BREAKDOWN;
+        break;
+      }
+      const double alpha = rz / pq;
+      double rn = 0.0;
+      for (int j = tid; j < F; j += kBT) {
+        const double pj = L.V[j];
+        P.x[j] += alpha * pj;
+        const double rj = P.r[j] - alpha * (P.t[j] + lam * pj);
+        P.r[j] = rj;
+        rn += rj * rj;
+      }
+      rr = wg_sum(rn, L.red);
+      ++it;
+      if (!(rr == rr)) {
+        status = RR_ERR_BREAKDOWN;
+        break;
+      }
+      if (rr <= P.tol2 * bb) {
+        status = RR_OK;
+        break;
+      }
+      const double rz_new = wg_precond(P, L);
+      if (!finite_pos(rz_new)) {
+        status = RR_ERR_BREAKDOWN;
+        break;
+      }
+      const double beta = rz_new / rz;
+      rz = rz_new;
+      for (int j = tid; j < F; j += kBT) P.p[j] = P.z[j] + beta * P.p[j];
+      __syncthreads();
+    }
+  }
+  // w in the caller's order; the true residual ||b - A x||
+  __syncthreads();
+  for (int j = tid; j < F; j += kBT) L.V[j] = P.x[j];
+  __syncthreads();
+  for (int j = tid; j < F; j += kBT) P.w[j] = P.x[P.finv[j]];
+  wg_gram(P, L, P.t);
+  double tr = 0.0;
+  for (int j = tid; j < F; j += kBT) {
+    const double res = P.b[j] - (P.t[j] + lam * L.V[j]);
+    tr += res * res;
+  }
+  tr = wg_sum(tr, L.red);
+  if (tid == 0) {
+    out->status = status;
+    out->iters = it;
+    out->relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    out->true_relres = bb > 0.0 ? sqrt(tr / bb) : 0.0;
+    out->t_begin = t_begin;
+    out->t_end = wall_clock64();
+  }
+  __syncthreads();
+}
+
+// Problems are taken in the order of `order` through the counter `queue`
+// (zeroed by the launch sequence); every workgroup leaves once the counter
+// has passed nprob, so the grid drains by itself.
+__global__ __launch_bounds__(kBT) void k_batch_solve(const BatchProb* __restrict__ probs,
+                                                     const int* __restrict__ order, int nprob,
+                                                     int* queue, BatchOut* __restrict__ out) {
+  __shared__ BatchLds L;
+  for (;;) {
+    if (threadIdx.x == 0) L.qslot = atomicAdd(queue, 1);
+    __syncthreads();
+    const int q = L.qslot;
+    __syncthreads();
+    if (q >= nprob) return;
+    const int pi = order[q];
+    solve_one(probs[pi], L, out + pi);
+  }
+}
+
+// one operator application per problem (autotuning and timing): t = X^T X v
+__global__ __launch_bounds__(kBT) void k_batch_gram(const BatchProb* __restrict__ probs, int nprob,
+                                                    const double* const* __restrict__ vin) {
+  __shared__ BatchLds L;
+  for (int pi = blockIdx.x; pi < nprob; pi += gridDim.x) {
+    const BatchProb& P = probs[pi];
+    for (int j = threadIdx.x; j < P.F; j += kBT) L.V[j] = vin[pi][j];
+    __syncthreads();
+    wg_gram(P, L, P.t);
+    __syncthreads();
+  }
+}
+
+__global__ void k_zero_int(int* p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
+void launch_batch_solve(const BatchProb* probs, const int* order, int nprob, int* queue, BatchOut* out,
+                        int grid, hipStream_t s) {
+  k_zero_int<<<1, 64, 0, s>>>(queue);
+  k_batch_solve<<<grid, kBT, 0, s>>>(probs, order, nprob, queue, out);
+}
+
+void launch_batch_gram(const BatchProb* probs, int nprob, const double* const* vin, int grid, hipStream_t s) {
+  k_batch_gram<<<grid, kBT, 0, s>>>(probs, nprob, vin);
+}
+
+// Setup of a 0/1 handle with F <= kBatchFMax: the CSC entry offsets of every
+// column at every row-chunk boundary and the column classes by length.
+rr_status build_batch_plan(BatchPlan& bp, const Sparse& X, hipStream_t s) {
+  free_batch_plan(bp);
+  if (!X.binary || X.F > kBatchFMax || X.F == 0) return RR_OK;
+  const int N = X.N, F = X.F;
+  std::vector<int> cp(F + 1), ri(std::max(1, X.nnz)), rp(N + 1);
+  RR_HIP(hipMemcpyAsync(cp.data(), X.col_ptr, sizeof(int) * (F + 1), hipMemcpyDeviceToHost, s));
+  RR_HIP(hipMemcpyAsync(rp.data(), X.row_ptr, sizeof(int) * (N + 1), hipMemcpyDeviceToHost, s));
+  if (X.nnz) RR_HIP(hipMemcpyAsync(ri.data(), X.row_idx, sizeof(int) * X.nnz, hipMemcpyDeviceToHost, s));
+  RR_HIP(hipStreamSynchronize(s));
+  const int nchunk = std::max(1, cdiv(N, kBatchRows));
+  std::vector<int> cs((size_t)(nchunk + 1) * F);
+  for (int j = 0; j < F; ++j) {
+    int k = cp[j];
+    for (int h = 0; h <= nchunk; ++h) {
+      const long long lim = std::min<long long>((long long)h * kBatchRows, N);
+      while (k < cp[j + 1] && ri[k] < lim) ++k;
+      cs[(size_t)h * F + j] = (h == nchunk) ? cp[j + 1] : k;
+    }
+  }
+  // classes: 64 lanes from 1024 entries, 16 from 256, 4 from 64, so a lane
+  // gets at least 16 entries (one batch of loads); the columns are in
+  // descending-count order, so each class is a prefix range
+  int cls[3] = {0, 0, 0};
+  const int thr[3] = {1024, 256, 64};
+  for (int c = 0; c < 3; ++c) {
+    int j = c ? cls[c - 1] : 0;
+    while (j < F && cp[j + 1] - cp[j] >= thr[c]) ++j;
+    cls[c] = j;
+  }
+  for (int j = 1; j < F; ++j)   // the classes assume the popularity order
+    if (cp[j + 1] - cp[j] > cp[j] - cp[j - 1]) return RR_OK;
+  const double avg = N > 0 ? (double)X.nnz / N : 0.0;
+  int g = 1;
+  while (g < 64 && 32.0 * g < avg) g *= 2;   // 16 to 32 entries per lane
+  bp.nchunk = nchunk;
+  bp.grow = g;
+  for (int c = 0; c < 3; ++c) bp.cls[c] = cls[c];
+  RR_HIP(dmalloc(&bp.csplit, sizeof(int) * cs.size()));
+  RR_HIP(hipMemcpyAsync(bp.csplit, cs.data(), sizeof(int) * cs.size(), hipMemcpyHostToDevice, s));
+  RR_HIP(hipStreamSynchronize(s));
+  return RR_OK;
+}
+
+void free_batch_plan(BatchPlan& bp) {
+  if (bp.csplit) (void)dev_free(bp.csplit);
+  bp = BatchPlan{};
+}
+
+}  // namespace rr

@@ -363,15 +363,17 @@ __global__ __launch_bounds__(kBlock) void k_fcg_update(
   if (sc->done) return;
   __shared__ double red[kBlock / 64];
   const double pq = sum_parts<kBlock>(parts_pq, n_pq, red);
-  if (!finite_pos(pq)) {
+  const double pr = sum_parts<kBlock>(parts_pr, n_pr, red);
+  if (!finite_pos(pq) || !(pr == pr) || pr == __builtin_inf() || pr == -__builtin_inf()) {
+    // under the learned correction the host falls back to the algebraic
+    // cycle; x and r keep the last good iterate
     if (is_block0_lead()) {
       sc->pq = pq;
-      sc->status = RR_ERR_BREAKDOWN;
+      sc->status = kind == PK_LEARNED ? kStatusFallback : RR_ERR_BREAKDOWN;
       sc->done = 1;
     }
     return;
   }
-  const double pr = sum_parts<kBlock>(parts_pr, n_pr, red);
   const double alpha = pr / pq;
   if (is_block0_lead()) {
     sc->pq = pq;

@@ -168,11 +168,11 @@ rr_status build_smoother_blocks(rr_handle* h, hipStream_t s) {
   if ((int)bperm.size() != F) return fail(RR_ERR_DEVICE, "internal: smoother blocks miss a feature");
   const int nblk = (int)boff.size() - 1;
   int *d_bid = nullptr, *d_bloc = nullptr;
-  RR_HIP(hipMalloc(&h->boff, sizeof(int) * (nblk + 1)));
-  RR_HIP(hipMalloc(&h->bperm, sizeof(int) * F));
-  RR_HIP(hipMalloc(&d_bid, sizeof(int) * F));
-  RR_HIP(hipMalloc(&d_bloc, sizeof(int) * F));
-  RR_HIP(hipMalloc(&h->bgram, sizeof(double) * (size_t)nblk * kBB));
+  RR_HIP(dmalloc(&h->boff, sizeof(int) * (nblk + 1)));
+  RR_HIP(dmalloc(&h->bperm, sizeof(int) * F));
+  RR_HIP(dmalloc(&d_bid, sizeof(int) * F));
+  RR_HIP(dmalloc(&d_bloc, sizeof(int) * F));
+  RR_HIP(dmalloc(&h->bgram, sizeof(double) * (size_t)nblk * kBB));
   RR_HIP(hipMemcpyAsync(h->boff, boff.data(), sizeof(int) * (nblk + 1), hipMemcpyHostToDevice, s));
   RR_HIP(hipMemcpyAsync(h->bperm, bperm.data(), sizeof(int) * F, hipMemcpyHostToDevice, s));
   RR_HIP(hipMemcpyAsync(d_bid, bid.data(), sizeof(int) * F, hipMemcpyHostToDevice, s));
@@ -180,12 +180,12 @@ rr_status build_smoother_blocks(rr_handle* h, hipStream_t s) {
   const long long nn = (long long)nblk * kBB;
   if (X.binary) {
     unsigned* Gi = nullptr;
-    RR_HIP(hipMalloc(&Gi, sizeof(unsigned) * nn));
+    RR_HIP(dmalloc(&Gi, sizeof(unsigned) * nn));
     RR_HIP(hipMemsetAsync(Gi, 0, sizeof(unsigned) * nn, s));
     k_block_gram_bin<<<cdiv(X.N, kBlock), kBlock, 0, s>>>(X.N, X.row_ptr, X.col_idx, d_bid, d_bloc, Gi);
     k_u32_to_f64<<<cdiv(nn, kBlock), kBlock, 0, s>>>(nn, Gi, h->bgram);
     RR_HIP(hipStreamSynchronize(s));
-    RR_HIP(hipFree(Gi));
+    RR_HIP(dev_free(Gi));
   } else {
     RR_HIP(hipMemsetAsync(h->bgram, 0, sizeof(double) * nn, s));
     k_block_gram_val<<<cdiv(X.N, kBlock), kBlock, 0, s>>>(X.N, X.row_ptr, X.col_idx, X.val, d_bid, d_bloc,
@@ -193,15 +193,15 @@ rr_status build_smoother_blocks(rr_handle* h, hipStream_t s) {
   }
   RR_HIP(hipStreamSynchronize(s));
   RR_HIP(hipGetLastError());
-  RR_HIP(hipFree(d_bid));
-  RR_HIP(hipFree(d_bloc));
+  RR_HIP(dev_free(d_bid));
+  RR_HIP(dev_free(d_bloc));
   h->nblk = nblk;
   return RR_OK;
 }
 
 rr_status block_factor(rr_handle* h, double lam, LambdaSlot& slot, hipStream_t s) {
   if (h->nblk == 0) return RR_OK;
-  if (!slot.Dinv) RR_HIP(hipMalloc(&slot.Dinv, sizeof(double) * (size_t)h->nblk * kBB));
+  if (!slot.Dinv) RR_HIP(dmalloc(&slot.Dinv, sizeof(double) * (size_t)h->nblk * kBB));
   RR_HIP(hipMemsetAsync(h->chol_flag, 0, sizeof(int), s));
   k_block_inv<<<h->nblk, 64, 0, s>>>(h->boff, h->bgram, lam, slot.Dinv, h->chol_flag);
   int bad = 0;

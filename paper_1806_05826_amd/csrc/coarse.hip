@@ -302,14 +302,14 @@ rr_status coarse_eigen(rr_handle* h, int* sweeps, hipStream_t s) {
   if (n <= 0) return fail(RR_ERR_INVALID_ARG, "no coarse level (n_clusters = 0)");
   const long long nn = (long long)n * n;
   const int m = n + (n & 1);
-  if (!h->eig_q) RR_HIP(hipMalloc(&h->eig_q, sizeof(double) * nn));
-  if (!h->eig_v) RR_HIP(hipMalloc(&h->eig_v, sizeof(double) * n));
+  if (!h->eig_q) RR_HIP(dmalloc(&h->eig_q, sizeof(double) * nn));
+  if (!h->eig_v) RR_HIP(dmalloc(&h->eig_v, sizeof(double) * n));
   double* A = h->chol_work;   // FC^2 scratch for the rotated K
   double2* cs = nullptr;
   double* parts = nullptr;
   constexpr int kOffBlocks = 256;
-  RR_HIP(hipMalloc(&cs, sizeof(double2) * (m / 2)));
-  RR_HIP(hipMalloc(&parts, sizeof(double) * 2 * kOffBlocks));
+  RR_HIP(dmalloc(&cs, sizeof(double2) * (m / 2)));
+  RR_HIP(dmalloc(&parts, sizeof(double) * 2 * kOffBlocks));
   RR_HIP(hipMemcpyAsync(A, h->K, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
   k_identity<<<cdiv(nn, kBlock), kBlock, 0, s>>>(n, h->eig_q);
   std::vector<double> hp(2 * kOffBlocks);
@@ -341,8 +341,8 @@ rr_status coarse_eigen(rr_handle* h, int* sweeps, hipStream_t s) {
   if (st == RR_OK && sw == kMaxJacobiSweeps) st = fail(RR_ERR_NOT_CONVERGED, "eigen: Jacobi sweeps did not converge");
   if (st == RR_OK) k_diag<<<cdiv(n, kBlock), kBlock, 0, s>>>(n, A, h->eig_v);
   (void)hipStreamSynchronize(s);
-  (void)hipFree(cs);
-  (void)hipFree(parts);
+  (void)dev_free(cs);
+  (void)dev_free(parts);
   RR_TRY(st);
   RR_HIP(hipGetLastError());
   *sweeps = sw;

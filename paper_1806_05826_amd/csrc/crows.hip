@@ -104,7 +104,7 @@ rr_status weighted_gram_from_labels(rr_handle* h, hipStream_t s) {
   const int FC = h->FC, N = h->X.N;
   const int FCp = (FC + 127) / 128 * 128, Np = (N + 127) / 128 * 128;
   const size_t bytes = sizeof(double) * (size_t)FCp * Np;
-  if (!h->wxc) RR_HIP(hipMalloc(&h->wxc, bytes));
+  if (!h->wxc) RR_HIP(dmalloc(&h->wxc, bytes));
   RR_HIP(hipMemsetAsync(h->wxc, 0, bytes, s));
   k_weighted_xc<<<cdiv(cr.nlayer, kCrThreads / 64), kCrThreads, 0, s>>>(cr.nlayer, cr.layer, cr.ent, cr.rowid,
                                                                         FC, Np, h->cscale, h->X.rw, h->wxc);
@@ -112,9 +112,9 @@ rr_status weighted_gram_from_labels(rr_handle* h, hipStream_t s) {
 }
 
 void free_cluster_rows(ClusterRows& cr) {
-  if (cr.layer) (void)hipFree(cr.layer);
-  if (cr.ent) (void)hipFree(cr.ent);
-  if (cr.rowid) (void)hipFree(cr.rowid);
+  if (cr.layer) (void)dev_free(cr.layer);
+  if (cr.ent) (void)dev_free(cr.ent);
+  if (cr.rowid) (void)dev_free(cr.rowid);
   cr = ClusterRows{};
 }
 
@@ -160,9 +160,9 @@ rr_status build_cluster_rows(rr_handle* h, hipStream_t s) {
       }
     }
   }
-  RR_HIP(hipMalloc(&cr.layer, sizeof(int2) * nlayer));
-  RR_HIP(hipMalloc(&cr.ent, sizeof(uint16_t) * total));
-  RR_HIP(hipMalloc(&cr.rowid, sizeof(int) * rowid.size()));
+  RR_HIP(dmalloc(&cr.layer, sizeof(int2) * nlayer));
+  RR_HIP(dmalloc(&cr.ent, sizeof(uint16_t) * total));
+  RR_HIP(dmalloc(&cr.rowid, sizeof(int) * rowid.size()));
   RR_HIP(hipMemcpyAsync(cr.layer, layer.data(), sizeof(int2) * nlayer, hipMemcpyHostToDevice, s));
   RR_HIP(hipMemcpyAsync(cr.ent, ent.data(), sizeof(uint16_t) * total, hipMemcpyHostToDevice, s));
   RR_HIP(hipMemcpyAsync(cr.rowid, rowid.data(), sizeof(int) * rowid.size(), hipMemcpyHostToDevice, s));

@@ -46,14 +46,14 @@ template <typename T>
 rr_status zalloc(T** p, size_t n) {
   *p = nullptr;
   if (n == 0) n = 1;
-  RR_HIP(hipMalloc((void**)p, n * sizeof(T)));
+  RR_HIP(dmalloc((void**)p, n * sizeof(T)));
   RR_HIP(hipMemset(*p, 0, n * sizeof(T)));
   return RR_OK;
 }
 
 template <typename T>
 void zfree(T*& p) {
-  if (p) (void)hipFree((void*)p);
+  if (p) (void)dev_free((void*)p);
   p = nullptr;
 }
 
@@ -780,7 +780,7 @@ rr_status ensure_dwork(rr_handle* h, int m) {
   pick_split(d.Fp / GB_M, d.Np, GB_K, &S, &kc, d.split_target[OP_BF16]);
   pb = std::max(pb, (size_t)S * fp * sizeof(float));
   W.part_bytes = pb;
-  RR_HIP(hipMalloc(&W.part, pb));
+  RR_HIP(dmalloc(&W.part, pb));
   const int fc = std::max(h->FC, 1);
   RR_TRY(zalloc(&W.c, (size_t)fc * need));
   RR_TRY(zalloc(&W.yc, (size_t)fc * need));
@@ -802,7 +802,7 @@ void dense_free_work(DenseWork& W) {
   zfree(W.u); zfree(W.uf); zfree(W.c); zfree(W.yc); zfree(W.parts);
   zfree(W.rz); zfree(W.pq); zfree(W.alpha); zfree(W.beta); zfree(W.rr); zfree(W.bb);
   zfree(W.done); zfree(W.iters); zfree(W.status); zfree(W.done_in); zfree(W.nactive);
-  if (W.part) (void)hipFree(W.part);
+  if (W.part) (void)dev_free(W.part);
   W.part = nullptr;
   if (W.nactive_host) (void)hipHostFree(W.nactive_host);
   W.nactive_host = nullptr;

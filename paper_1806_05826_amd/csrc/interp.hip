@@ -108,9 +108,9 @@ __global__ void k_perm_vals(int F, const int* __restrict__ perm, const double* _
 }  // namespace
 
 void free_interpolation(rr_handle* h) {
-  (void)hipFree(h->lsw);
-  (void)hipFree(h->lsw_perm);
-  (void)hipFree(h->pgram);
+  (void)dev_free(h->lsw);
+  (void)dev_free(h->lsw_perm);
+  (void)dev_free(h->pgram);
   h->lsw = h->lsw_perm = h->pgram = nullptr;
 }
 
@@ -128,23 +128,23 @@ rr_status set_interpolation(rr_handle* h, const double* V, int K, double beta, c
   double *pw = nullptr, *pw_perm = nullptr, *pgram = nullptr;
   int *rep_c = nullptr, *rep_int = nullptr, *bad = nullptr;
   auto release = [&]() {
-    (void)hipFree(Vi); (void)hipFree(eta); (void)hipFree(t); (void)hipFree(u);
-    (void)hipFree(den); (void)hipFree(rep_c); (void)hipFree(rep_int); (void)hipFree(bad);
+    (void)dev_free(Vi); (void)dev_free(eta); (void)dev_free(t); (void)dev_free(u);
+    (void)dev_free(den); (void)dev_free(rep_c); (void)dev_free(rep_int); (void)dev_free(bad);
   };
   auto drop_new = [&]() {
-    (void)hipFree(pw); (void)hipFree(pw_perm); (void)hipFree(pgram);
+    (void)dev_free(pw); (void)dev_free(pw_perm); (void)dev_free(pgram);
   };
-  bool ok = hipMalloc(&Vi, sizeof(double) * (size_t)K * F) == hipSuccess &&
-            hipMalloc(&eta, sizeof(double) * K) == hipSuccess &&
-            hipMalloc(&t, sizeof(double) * F) == hipSuccess &&
-            hipMalloc(&u, sizeof(double) * std::max(1, N)) == hipSuccess &&
-            hipMalloc(&den, sizeof(double) * fc) == hipSuccess &&
-            hipMalloc(&rep_c, sizeof(int) * fc) == hipSuccess &&
-            hipMalloc(&rep_int, sizeof(int) * fc) == hipSuccess &&
-            hipMalloc(&bad, sizeof(int)) == hipSuccess &&
-            hipMalloc(&pw, sizeof(double) * F) == hipSuccess &&
-            hipMalloc(&pw_perm, sizeof(double) * F) == hipSuccess &&
-            hipMalloc(&pgram, sizeof(double) * fc) == hipSuccess;
+  bool ok = dmalloc(&Vi, sizeof(double) * (size_t)K * F) == hipSuccess &&
+            dmalloc(&eta, sizeof(double) * K) == hipSuccess &&
+            dmalloc(&t, sizeof(double) * F) == hipSuccess &&
+            dmalloc(&u, sizeof(double) * std::max(1, N)) == hipSuccess &&
+            dmalloc(&den, sizeof(double) * fc) == hipSuccess &&
+            dmalloc(&rep_c, sizeof(int) * fc) == hipSuccess &&
+            dmalloc(&rep_int, sizeof(int) * fc) == hipSuccess &&
+            dmalloc(&bad, sizeof(int)) == hipSuccess &&
+            dmalloc(&pw, sizeof(double) * F) == hipSuccess &&
+            dmalloc(&pw_perm, sizeof(double) * F) == hipSuccess &&
+            dmalloc(&pgram, sizeof(double) * fc) == hipSuccess;
   if (!ok) {
     release();
     drop_new();
@@ -198,8 +198,16 @@ rr_status set_interpolation(rr_handle* h, const double* V, int K, double beta, c
   h->lsw = pw;
   h->lsw_perm = pw_perm;
   h->pgram = pgram;
-  // the Galerkin coarse Gram P^T X^T X P, one operator application per column
-  RR_TRY(build_coarse_gram_valued(h, s));
+  // the Galerkin coarse Gram P^T X^T X P, one operator application per
+  // column; if that fails, the handle goes back to the adjusted square-root
+  // average (whose K is rebuilt) rather than keep weights without their K
+  rr_status st = build_coarse_gram_valued(h, s);
+  if (st != RR_OK) {
+    const std::string msg = rr_last_error();
+    free_interpolation(h);
+    (void)build_coarse_gram(h, s);
+    return fail(st, msg);
+  }
   if (p_out) launch_gather(p_out, h->lsw, h->finv, F, s);
   RR_HIP(hipStreamSynchronize(s));
   RR_HIP(hipGetLastError());

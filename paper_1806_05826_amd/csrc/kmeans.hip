@@ -445,9 +445,9 @@ struct KmWork {
   int* d_heavy_feat = nullptr;
   int* d_heavy_hist = nullptr;
   ~KmWork() {
-    if (d_items) (void)hipFree(d_items);
-    if (d_heavy_feat) (void)hipFree(d_heavy_feat);
-    if (d_heavy_hist) (void)hipFree(d_heavy_hist);
+    if (d_items) (void)dev_free(d_items);
+    if (d_heavy_feat) (void)dev_free(d_heavy_feat);
+    if (d_heavy_hist) (void)dev_free(d_heavy_hist);
   }
 };
 
@@ -472,14 +472,14 @@ static rr_status make_items(rr_handle* h, KmWork& kw, int k, bool need_heavy, hi
       for (int r = a; r < b; r += chunk_rows) kw.items.push_back(Item{j, r, std::min(b, r + chunk_rows), hidx});
     }
   }
-  RR_HIP(hipMalloc(&kw.d_items, sizeof(Item) * std::max<size_t>(1, kw.items.size())));
+  RR_HIP(dmalloc(&kw.d_items, sizeof(Item) * std::max<size_t>(1, kw.items.size())));
   RR_HIP(hipMemcpyAsync(kw.d_items, kw.items.data(), sizeof(Item) * kw.items.size(),
                         hipMemcpyHostToDevice, s));
   if (!kw.heavy_feat.empty()) {
-    RR_HIP(hipMalloc(&kw.d_heavy_feat, sizeof(int) * kw.heavy_feat.size()));
+    RR_HIP(dmalloc(&kw.d_heavy_feat, sizeof(int) * kw.heavy_feat.size()));
     RR_HIP(hipMemcpyAsync(kw.d_heavy_feat, kw.heavy_feat.data(), sizeof(int) * kw.heavy_feat.size(),
                           hipMemcpyHostToDevice, s));
-    RR_HIP(hipMalloc(&kw.d_heavy_hist, sizeof(int) * kw.heavy_feat.size() * (size_t)k));
+    RR_HIP(dmalloc(&kw.d_heavy_hist, sizeof(int) * kw.heavy_feat.size() * (size_t)k));
     RR_HIP(hipMemsetAsync(kw.d_heavy_hist, 0, sizeof(int) * kw.heavy_feat.size() * (size_t)k, s));
   }
   RR_HIP(hipStreamSynchronize(s));
@@ -493,8 +493,7 @@ rr_status run_kmeans(rr_handle* h, int k, uint64_t seed, int max_iter, hipStream
   const int F = X.F, N = X.N;
   if (!X.binary) return fail(RR_ERR_UNSUPPORTED, "k-means on the GPU needs a binary X; pass labels_in");
   k = std::min(k, F);
-  if (two_hop_lds(k) + 8 * kBlock > 150 * 1024)
-    return fail(RR_ERR_UNSUPPORTED, "n_clusters too large for the LDS histogram (max ~18000)");
+  RR_TRY(check_coarse_size(k));
   // ---- seeding ----
   std::vector<unsigned long long> draws(k);
   uint64_t st_rng = seed;
@@ -505,13 +504,13 @@ rr_status run_kmeans(rr_handle* h, int k, uint64_t seed, int max_iter, hipStream
   SeedState* st = nullptr;
   unsigned* ticket = nullptr;
   const int nchunks = cdiv(F, kSeedChunk);
-  RR_HIP(hipMalloc(&d_draws, sizeof(unsigned long long) * k));
-  RR_HIP(hipMalloc(&d2, sizeof(long long) * F));
-  RR_HIP(hipMalloc(&chunk_sum, sizeof(long long) * nchunks));
-  RR_HIP(hipMalloc(&ind, sizeof(double) * N));
-  RR_HIP(hipMalloc(&gram, sizeof(double) * F));
-  RR_HIP(hipMalloc(&st, sizeof(SeedState)));
-  RR_HIP(hipMalloc(&ticket, sizeof(unsigned)));
+  RR_HIP(dmalloc(&d_draws, sizeof(unsigned long long) * k));
+  RR_HIP(dmalloc(&d2, sizeof(long long) * F));
+  RR_HIP(dmalloc(&chunk_sum, sizeof(long long) * nchunks));
+  RR_HIP(dmalloc(&ind, sizeof(double) * N));
+  RR_HIP(dmalloc(&gram, sizeof(double) * F));
+  RR_HIP(dmalloc(&st, sizeof(SeedState)));
+  RR_HIP(dmalloc(&ticket, sizeof(unsigned)));
   RR_HIP(hipMemsetAsync(ticket, 0, sizeof(unsigned), s));
   RR_HIP(hipMemsetAsync(st, 0, sizeof(SeedState), s));
   RR_HIP(hipMemcpyAsync(d_draws, draws.data(), sizeof(unsigned long long) * k, hipMemcpyHostToDevice, s));
@@ -535,24 +534,24 @@ rr_status run_kmeans(rr_handle* h, int k, uint64_t seed, int max_iter, hipStream
   RR_HIP(hipStreamSynchronize(s));
   const int nc = hst.n_centres;
   h->n_centres = nc;
-  RR_HIP(hipFree(d_draws));
-  RR_HIP(hipFree(d2));
-  RR_HIP(hipFree(chunk_sum));
-  RR_HIP(hipFree(ind));
-  RR_HIP(hipFree(gram));
-  RR_HIP(hipFree(st));
-  RR_HIP(hipFree(ticket));
+  RR_HIP(dev_free(d_draws));
+  RR_HIP(dev_free(d2));
+  RR_HIP(dev_free(chunk_sum));
+  RR_HIP(dev_free(ind));
+  RR_HIP(dev_free(gram));
+  RR_HIP(dev_free(st));
+  RR_HIP(dev_free(ticket));
 
   // ---- Lloyd ----
   KmWork kw;
   RR_TRY(make_items(h, kw, nc, true, s));
   int *lab = h->labels, *lab_new = nullptr, *n = nullptr, *s0 = nullptr, *changed = nullptr;
   unsigned long long* Q = nullptr;
-  RR_HIP(hipMalloc(&lab_new, sizeof(int) * F));
-  RR_HIP(hipMalloc(&n, sizeof(int) * nc));
-  RR_HIP(hipMalloc(&Q, sizeof(unsigned long long) * nc));
-  RR_HIP(hipMalloc(&s0, sizeof(int)));
-  RR_HIP(hipMalloc(&changed, sizeof(int)));
+  RR_HIP(dmalloc(&lab_new, sizeof(int) * F));
+  RR_HIP(dmalloc(&n, sizeof(int) * nc));
+  RR_HIP(dmalloc(&Q, sizeof(unsigned long long) * nc));
+  RR_HIP(dmalloc(&s0, sizeof(int)));
+  RR_HIP(dmalloc(&changed, sizeof(int)));
   k_init_labels<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, nc, h->centres, lab);
   k_set_centres<<<cdiv(nc, kBlock), kBlock, 0, s>>>(nc, h->centres, h->finv, lab);
   const int rows_per_block = 64;
@@ -586,11 +585,11 @@ rr_status run_kmeans(rr_handle* h, int k, uint64_t seed, int max_iter, hipStream
     std::swap(lab, lab_new);   // lab_new now points at the scratch buffer
   }
   RR_HIP(hipStreamSynchronize(s));
-  RR_HIP(hipFree(lab_new));
-  RR_HIP(hipFree(n));
-  RR_HIP(hipFree(Q));
-  RR_HIP(hipFree(s0));
-  RR_HIP(hipFree(changed));
+  RR_HIP(dev_free(lab_new));
+  RR_HIP(dev_free(n));
+  RR_HIP(dev_free(Q));
+  RR_HIP(dev_free(s0));
+  RR_HIP(dev_free(changed));
   return set_labels(h, nullptr, nc, s);
 }
 
@@ -601,13 +600,13 @@ rr_status set_labels(rr_handle* h, const int* labels_in, int nlab, hipStream_t s
   const int F = h->X.F;
   int* bad = nullptr;
   int *n = nullptr, *remap = nullptr, *fc = nullptr;
-  RR_HIP(hipMalloc(&bad, sizeof(int)));
+  RR_HIP(dmalloc(&bad, sizeof(int)));
   RR_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
   if (labels_in)
     k_check_labels<<<cdiv(F, kBlock), kBlock, 0, s>>>(F, nlab, labels_in, h->fperm, h->labels, bad);
-  RR_HIP(hipMalloc(&n, sizeof(int) * nlab));
-  RR_HIP(hipMalloc(&remap, sizeof(int) * nlab));
-  RR_HIP(hipMalloc(&fc, sizeof(int)));
+  RR_HIP(dmalloc(&n, sizeof(int) * nlab));
+  RR_HIP(dmalloc(&remap, sizeof(int) * nlab));
+  RR_HIP(dmalloc(&fc, sizeof(int)));
   RR_HIP(hipMemsetAsync(n, 0, sizeof(int) * nlab, s));
   int hbad = 0;
   RR_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -621,36 +620,36 @@ rr_status set_labels(rr_handle* h, const int* labels_in, int nlab, hipStream_t s
   RR_HIP(hipMemcpyAsync(&hfc, fc, sizeof(int), hipMemcpyDeviceToHost, s));
   RR_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
   RR_HIP(hipStreamSynchronize(s));
-  RR_HIP(hipFree(n));
-  RR_HIP(hipFree(remap));
-  RR_HIP(hipFree(fc));
-  RR_HIP(hipFree(bad));
+  RR_HIP(dev_free(n));
+  RR_HIP(dev_free(remap));
+  RR_HIP(dev_free(fc));
+  RR_HIP(dev_free(bad));
   if (hbad) return fail(RR_ERR_DEVICE, "internal: unassigned feature after clustering");
   h->FC = hfc;
-  RR_HIP(hipMalloc(&h->csize, sizeof(int) * hfc));
-  RR_HIP(hipMalloc(&h->cscale, sizeof(double) * hfc));
-  RR_HIP(hipMalloc(&h->perm, sizeof(int) * F));
-  RR_HIP(hipMalloc(&h->coff, sizeof(int) * (hfc + 1)));
+  RR_HIP(dmalloc(&h->csize, sizeof(int) * hfc));
+  RR_HIP(dmalloc(&h->cscale, sizeof(double) * hfc));
+  RR_HIP(dmalloc(&h->perm, sizeof(int) * F));
+  RR_HIP(dmalloc(&h->coff, sizeof(int) * (hfc + 1)));
   RR_HIP(hipMemsetAsync(h->csize, 0, sizeof(int) * hfc, s));
   k_count_members<<<std::min(1024, cdiv(F, kBlock)), kBlock, sizeof(int) * hfc, s>>>(F, hfc, h->labels, h->csize);
   k_scale<<<cdiv(hfc, kBlock), kBlock, 0, s>>>(hfc, h->csize, h->cscale);
   // perm: features sorted by cluster, stable
   int *keys_out = nullptr, *iota = nullptr;
-  RR_HIP(hipMalloc(&keys_out, sizeof(int) * F));
-  RR_HIP(hipMalloc(&iota, sizeof(int) * F));
+  RR_HIP(dmalloc(&keys_out, sizeof(int) * F));
+  RR_HIP(dmalloc(&iota, sizeof(int) * F));
   k_iota_f<<<cdiv(F, kBlock), kBlock, 0, s>>>(iota, F);
   size_t tmp_bytes = 0;
   unsigned end_bit = 1;
   while ((1ll << end_bit) < (long long)hfc) ++end_bit;
   RR_HIP(rocprim::radix_sort_pairs(nullptr, tmp_bytes, h->labels, keys_out, iota, h->perm, (size_t)F, 0u, end_bit, s));
   void* tmp = nullptr;
-  RR_HIP(hipMalloc(&tmp, std::max<size_t>(tmp_bytes, 1)));
+  RR_HIP(dmalloc(&tmp, std::max<size_t>(tmp_bytes, 1)));
   RR_HIP(rocprim::radix_sort_pairs(tmp, tmp_bytes, h->labels, keys_out, iota, h->perm, (size_t)F, 0u, end_bit, s));
   k_offsets<<<cdiv(hfc + 1, kBlock), kBlock, 0, s>>>(keys_out, F, hfc, h->coff);
   RR_HIP(hipStreamSynchronize(s));
-  RR_HIP(hipFree(tmp));
-  RR_HIP(hipFree(keys_out));
-  RR_HIP(hipFree(iota));
+  RR_HIP(dev_free(tmp));
+  RR_HIP(dev_free(keys_out));
+  RR_HIP(dev_free(iota));
   RR_TRY(build_merge_plan(h->restrict_plan, h->coff + 1, h->coff, hfc, F, s));
   return build_chunk_plan(h->restrict_plan, h->coff, hfc, s);
 }
@@ -661,20 +660,32 @@ rr_status build_coarse_gram(rr_handle* h, hipStream_t s) {
   const Sparse& X = h->X;
   const int fc = h->FC;
   if (!X.binary) return build_coarse_gram_valued(h, s);
+  RR_TRY(check_coarse_size(fc));   // before anything is allocated
   KmWork kw;
   RR_TRY(make_items(h, kw, fc, false, s));
   unsigned long long* StS = nullptr;
   const size_t nn = (size_t)fc * fc;
-  RR_HIP(hipMalloc(&StS, sizeof(unsigned long long) * nn));
-  RR_HIP(hipMemsetAsync(StS, 0, sizeof(unsigned long long) * nn, s));
+  RR_HIP(dmalloc(&StS, sizeof(unsigned long long) * nn));
+  hipError_t e = hipMemsetAsync(StS, 0, sizeof(unsigned long long) * nn, s);
+  if (e == hipSuccess) {
+    k_two_hop<MODE_GRAM><<<(int)kw.items.size(), kBlock, two_hop_lds(fc), s>>>(
+        fc, kw.d_items, X.row_ptr, X.col_idx, X.row_idx, h->labels, nullptr, nullptr, nullptr,
+        nullptr, nullptr, StS, nullptr);
+    k_gram_scale<<<cdiv((long long)nn, kBlock), kBlock, 0, s>>>(fc, StS, h->cscale, h->K);
+    e = hipStreamSynchronize(s);
+  }
+  (void)dev_free(StS);
+  RR_HIP(e);
+  return RR_OK;
+}
+
+// The exact integer Gram of 0/1 X keeps one histogram bin per cluster in
+// LDS (8 bytes each beside the block's reduction space): at most 18,944
+// clusters.
+rr_status check_coarse_size(int fc) {
   if (two_hop_lds(fc) + 8 * kBlock > 150 * 1024)
-    return fail(RR_ERR_UNSUPPORTED, "coarse size too large for the LDS histogram");
-  k_two_hop<MODE_GRAM><<<(int)kw.items.size(), kBlock, two_hop_lds(fc), s>>>(
-      fc, kw.d_items, X.row_ptr, X.col_idx, X.row_idx, h->labels, nullptr, nullptr, nullptr,
-      nullptr, nullptr, StS, nullptr);
-  k_gram_scale<<<cdiv((long long)nn, kBlock), kBlock, 0, s>>>(fc, StS, h->cscale, h->K);
-  RR_HIP(hipStreamSynchronize(s));
-  RR_HIP(hipFree(StS));
+    return fail(RR_ERR_UNSUPPORTED, "more than 18,944 clusters: too many for the LDS histogram of "
+                                    "the coarse Gram matrix");
   return RR_OK;
 }
 

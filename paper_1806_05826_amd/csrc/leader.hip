@@ -192,16 +192,16 @@ rr_status leader_follower(rr_handle* h, double tol, int* fc, hipStream_t s) {
   int *hist = nullptr, *touched = nullptr;
   unsigned long long* best = nullptr;
   LfState* st = nullptr;
-  RR_HIP(hipMalloc(&rl_cnt, sizeof(int) * std::max(1, N)));
-  RR_HIP(hipMalloc(&rl_ids, sizeof(int) * std::max(1, X.nnz)));
-  RR_HIP(hipMalloc(&lead_norm, sizeof(int) * F));
-  RR_HIP(hipMalloc(&winpos, sizeof(int) * F));
-  RR_HIP(hipMalloc(&wcnt, sizeof(int) * kLfWin));
-  RR_HIP(hipMalloc(&hist, sizeof(int) * (size_t)kLfWin * F));
-  RR_HIP(hipMalloc(&touched, sizeof(int) * (size_t)kLfWin * F));
-  RR_HIP(hipMalloc(&best, sizeof(unsigned long long) * kLfWin));
-  RR_HIP(hipMalloc(&st, sizeof(LfState)));
-  if (!h->centres) RR_HIP(hipMalloc(&h->centres, sizeof(int) * F));
+  RR_HIP(dmalloc(&rl_cnt, sizeof(int) * std::max(1, N)));
+  RR_HIP(dmalloc(&rl_ids, sizeof(int) * std::max(1, X.nnz)));
+  RR_HIP(dmalloc(&lead_norm, sizeof(int) * F));
+  RR_HIP(dmalloc(&winpos, sizeof(int) * F));
+  RR_HIP(dmalloc(&wcnt, sizeof(int) * kLfWin));
+  RR_HIP(dmalloc(&hist, sizeof(int) * (size_t)kLfWin * F));
+  RR_HIP(dmalloc(&touched, sizeof(int) * (size_t)kLfWin * F));
+  RR_HIP(dmalloc(&best, sizeof(unsigned long long) * kLfWin));
+  RR_HIP(dmalloc(&st, sizeof(LfState)));
+  if (!h->centres) RR_HIP(dmalloc(&h->centres, sizeof(int) * F));
   RR_HIP(hipMemsetAsync(rl_cnt, 0, sizeof(int) * std::max(1, N), s));
   RR_HIP(hipMemsetAsync(wcnt, 0, sizeof(int) * kLfWin, s));
   RR_HIP(hipMemsetAsync(hist, 0, sizeof(int) * (size_t)kLfWin * F, s));
@@ -243,8 +243,8 @@ rr_status leader_follower(rr_handle* h, double tol, int* fc, hipStream_t s) {
     k_lf_setpos<<<cdiv(nwin, kLfThreads), kLfThreads, 0, s>>>(t0, nwin, h->finv, winpos, 0);
   }
   (void)hipStreamSynchronize(s);
-  (void)hipFree(rl_cnt); (void)hipFree(rl_ids); (void)hipFree(lead_norm); (void)hipFree(winpos);
-  (void)hipFree(wcnt); (void)hipFree(hist); (void)hipFree(touched); (void)hipFree(best); (void)hipFree(st);
+  (void)dev_free(rl_cnt); (void)dev_free(rl_ids); (void)dev_free(lead_norm); (void)dev_free(winpos);
+  (void)dev_free(wcnt); (void)dev_free(hist); (void)dev_free(touched); (void)dev_free(best); (void)dev_free(st);
   RR_TRY(status);
   RR_HIP(hipGetLastError());
   *fc = hs.n_lead;

@@ -43,6 +43,35 @@ __global__ __launch_bounds__(kBlock) void k_ir_init(int F, const double* __restr
   }
 }
 
+// The FP32 cycle of an FP64 flexible-CG solve: r32 = (float) r, D32, and
+// the pre-smoothing step e1 = w D^-1 r in FP32 (skipped once the solve is done).
+__global__ __launch_bounds__(kBlock) void k_cycle_in(int F, const double* __restrict__ r64,
+                                                     const double* __restrict__ colnorm, double lam,
+                                                     double omega, IrVectors v, const int* done) {
+  if (is_done(done)) return;
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < F; j += gridDim.x * kBlock) {
+    const float rj = (float)r64[j];
+    const float Dj = (float)(colnorm[j] + lam);
+    v.r[j] = rj;
+    v.D[j] = Dj;
+    v.e1[j] = ((float)omega * rj) / Dj;
+  }
+}
+void launch_cycle_in(int F, const double* r64, const double* colnorm, double lam, double omega,
+                     const IrVectors& v, const int* done, hipStream_t s) {
+  k_cycle_in<<<vec_grid(F), kBlock, 0, s>>>(F, r64, colnorm, lam, omega, v, done);
+}
+
+// z = (double) z32
+__global__ __launch_bounds__(kBlock) void k_widen(int F, const float* __restrict__ z32,
+                                                  double* __restrict__ z, const int* done) {
+  if (is_done(done)) return;
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < F; j += gridDim.x * kBlock) z[j] = (double)z32[j];
+}
+void launch_widen(int F, const float* z32, double* z, const int* done, hipStream_t s) {
+  k_widen<<<vec_grid(F), kBlock, 0, s>>>(F, z32, z, done);
+}
+
 void launch_ir_init(int F, const double* r64, const double* colnorm, double lam, double omega,
                     int kind, const IrVectors& v, double* parts, hipStream_t s) {
   k_ir_init<<<vec_grid(F), kBlock, 0, s>>>(F, r64, colnorm, lam, omega, kind, v, parts);

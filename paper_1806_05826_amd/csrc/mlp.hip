@@ -165,14 +165,14 @@ void free_mlp(Mlp& n) {
                   (void*)n.z1, (void*)n.a1, (void*)n.z2, (void*)n.a2, (void*)n.y, (void*)n.dy32,
                   (void*)n.dy16, (void*)n.dz2, (void*)n.dz2b, (void*)n.dz1, (void*)n.dz1b,
                   (void*)n.err2, (void*)n.rows})
-    if (p) (void)hipFree(p);
+    if (p) (void)dev_free(p);
   n = Mlp{};
 }
 
 template <typename T>
 static rr_status mal(T** p, size_t n) {
   *p = nullptr;
-  hipError_t e = hipMalloc((void**)p, sizeof(T) * (n ? n : 1));
+  hipError_t e = dmalloc((void**)p, sizeof(T) * (n ? n : 1));
   if (e != hipSuccess) return fail(RR_ERR_DEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
   return RR_OK;
 }

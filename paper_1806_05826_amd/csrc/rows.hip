@@ -165,9 +165,9 @@ void launch_rows32(const RowPlan& rp, const float* v, float* u, const int* done,
 }
 
 void free_rows(RowPlan& rp) {
-  if (rp.layer) (void)hipFree(rp.layer);
-  if (rp.hidx) (void)hipFree(rp.hidx);
-  if (rp.cidx) (void)hipFree(rp.cidx);
+  if (rp.layer) (void)dev_free(rp.layer);
+  if (rp.hidx) (void)dev_free(rp.hidx);
+  if (rp.cidx) (void)dev_free(rp.cidx);
   rp = RowPlan{};
 }
 
@@ -258,9 +258,9 @@ rr_status build_rows(RowPlan& out, const std::vector<int>& ptr, const std::vecto
   out.hot_entries = hot;
   out.cold_entries = cold;
   out.idx_bytes = (long long)hidx.size() * 2 + (long long)cidx.size() * 4;
-  RR_HIP(hipMalloc(&out.layer, sizeof(int4) * lay.size()));
-  RR_HIP(hipMalloc(&out.hidx, sizeof(uint16_t) * hidx.size()));
-  RR_HIP(hipMalloc(&out.cidx, sizeof(int) * cidx.size()));
+  RR_HIP(dmalloc(&out.layer, sizeof(int4) * lay.size()));
+  RR_HIP(dmalloc(&out.hidx, sizeof(uint16_t) * hidx.size()));
+  RR_HIP(dmalloc(&out.cidx, sizeof(int) * cidx.size()));
   RR_HIP(hipMemcpyAsync(out.layer, lay.data(), sizeof(int4) * lay.size(), hipMemcpyHostToDevice, s));
   RR_HIP(hipMemcpyAsync(out.hidx, hidx.data(), sizeof(uint16_t) * hidx.size(), hipMemcpyHostToDevice, s));
   RR_HIP(hipMemcpyAsync(out.cidx, cidx.data(), sizeof(int) * cidx.size(), hipMemcpyHostToDevice, s));

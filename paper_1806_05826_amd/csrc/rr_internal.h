@@ -14,6 +14,38 @@
 
 namespace rr {
 
+// ---- device memory (alloc.hip) ---------------------------------------------
+// The memory context of a handle: where its device allocations come from.
+struct MemCtx {
+  enum Mode { kHip = 0, kHook = 1, kBump = 2, kCount = 3 };
+  Mode mode = kHip;
+  rr_alloc_fn alloc = nullptr;   // kHook: the caller's allocator
+  rr_free_fn free = nullptr;
+  void* ctx = nullptr;
+  char* base = nullptr;          // kBump: the caller's workspace
+  size_t cap = 0;
+  size_t used = 0;               // kBump / kCount: arena bytes taken
+  bool overflow = false;         // kBump: a request did not fit
+};
+// Makes m the calling thread's memory context for the scope's lifetime.
+class MemScope {
+ public:
+  explicit MemScope(MemCtx* m);
+  ~MemScope();
+  MemScope(const MemScope&) = delete;
+  MemScope& operator=(const MemScope&) = delete;
+ private:
+  MemCtx* saved_;
+};
+MemCtx default_mem();   // the caller's allocator when installed, else hipMalloc
+hipError_t dev_malloc(void** p, size_t bytes);
+hipError_t dev_free(void* p);
+template <typename T>
+inline hipError_t dmalloc(T** p, size_t bytes) {
+  return dev_malloc(reinterpret_cast<void**>(p), bytes);
+}
+
+
 constexpr int kBlock = 256;          // threads per block for streaming kernels
 constexpr int kMergeItems = 8;       // merge-path items per thread
 constexpr int kMergeTile = kBlock * kMergeItems;
@@ -67,6 +99,11 @@ struct StageArgs {
 
 // Window of previous directions of flexible CG (oldest first).
 constexpr int kMaxFcg = 16;
+// Internal status of a learned-correction solve whose flexible-CG step met a
+// non-finite or non-positive <p, A p> or a non-finite <p, r>: the host
+// switches the solve to the algebraic V(1,1) cycle and restarts the
+// flexible-CG history (never returned through the ABI).
+constexpr int kStatusFallback = 100;
 struct FcgWindow {
   const double* p[kMaxFcg];
   const double* ap[kMaxFcg];
@@ -146,17 +183,9 @@ struct MergePlan {
   int4* span = nullptr;    // device [nspan]: (segment, first block, last block, 0)
   double* head = nullptr;  // device [nblocks]
   double* tail = nullptr;  // device [nblocks]
-  // optional chunked form for sums without a dot product (the restriction):
-  // chunks of at most kChunk entries, (segment, first, end, partial slot or
-  // -1 when the chunk is its segment's only one); segments of several chunks
-  // (segment, first slot, slots, 0); the chunk partials (per work set)
-  int nchunk = 0, nfin = 0, ncpart = 0;
-  int4* chunk = nullptr;
-  int4* fin = nullptr;
-  double* cpart = nullptr;
-  // one-kernel form, used instead when no segment exceeds kOneSegMax
-  // entries: segments of up to kWaveSeg entries take one wave each, longer
-  // ones a whole block, (segment, first, end, 0) each
+  // one-kernel form for sums without a dot product (the restriction, built
+  // by build_chunk_plan): segments of up to kWaveSeg entries take one wave
+  // each, longer ones a whole block, (segment, first, end, 0) each
   int nwitem = 0, nbitem = 0;
   int4* witem = nullptr;
   int4* bitem = nullptr;
@@ -194,6 +223,32 @@ struct RowPlan {
   int* cidx = nullptr;        // cold lane streams (-1 = padding)
 };
 
+// Persistent batched solver (batch.hip): problems of at most kBatchFMax
+// features, rows in chunks of kBatchRows staged through LDS.
+constexpr int kBatchFMax = 8192;
+constexpr int kBatchRows = 10240;
+
+// Per-handle plan of the batched solver (0/1 X, F <= kBatchFMax).
+struct BatchPlan {
+  int nchunk = 0, grow = 1;   // row chunks; lanes per row
+  int cls[3] = {0, 0, 0};     // column classes: [0, cls0) 64 lanes, then 16, 4, 1
+  int* csplit = nullptr;      // [(nchunk + 1) * F] CSC entry of column j at chunk h's first row
+};
+
+// One problem of a persistent batched solve (device descriptor).
+struct BatchProb {
+  int N, F, FC, nchunk, grow, kind, rhs_is_b, max_iter, fixed;
+  int cls[3];
+  const int *rp, *ci, *ri, *csplit, *perm, *coff, *labels, *fperm, *finv;
+  const double *cscale, *Ainv, *colnorm, *rhs;
+  double lam, omega, tol2;
+  double *w, *x, *r, *p, *z, *e1, *b, *t;
+};
+struct BatchOut {
+  int status, iters;
+  double relres, true_relres;
+  long long t_begin, t_end;   // wall_clock64() around the problem's solve
+};
 // Autotuning record of the operator plans (see build_sell_plans): lanes per
 // row of the row pass (div_rows) and the column pass's lane-stream divisor.
 struct SellTuning {
@@ -218,6 +273,7 @@ struct Sparse {
   MergePlan csc_plan;       // segments = columns (merge-path form, valued X)
   RowPlan rows;             // u = X v   (0/1 X)
   SellPlan sell_csc;        // t = X^T u (0/1 X)
+  BatchPlan bplan;          // persistent batched solver (0/1 X, F <= kBatchFMax)
   int num_cu = 256;
 };
 
@@ -346,6 +402,7 @@ struct ClusterRows {
 
 struct rr_handle {
   int device = 0;
+  rr::MemCtx mem;               // where the handle's device memory comes from
   rr::Sparse X;
   int* fperm = nullptr;         // [F] internal feature -> caller's feature
   int* finv = nullptr;          // [F] caller's feature -> internal feature
@@ -472,6 +529,13 @@ void launch_rows(const RowPlan& rp, const double* v, double* u, const double* sc
 void launch_rows32(const RowPlan& rp, const float* v, float* u, const int* done, hipStream_t s,
                    const StageArgs* stage = nullptr);
 void free_rows(RowPlan& rp);
+rr_status build_batch_plan(BatchPlan& bp, const Sparse& X, hipStream_t s);
+void free_batch_plan(BatchPlan& bp);
+void launch_batch_solve(const BatchProb* probs, const int* order, int nprob, int* queue, BatchOut* out,
+                        int grid, hipStream_t s);
+void launch_batch_gram(const BatchProb* probs, int nprob, const double* const* vin, int grid, hipStream_t s);
+rr_status lanczos_prototypes(rr_handle* h, int n_proto, int steps, uint64_t seed, double* V, double* ev,
+                             hipStream_t s);
 rr_status build_rows(RowPlan& out, const std::vector<int>& ptr, const std::vector<int>& col, int N, int F,
                      int num_cu, int L, hipStream_t s);
 // More than kMaxParts block partials are first added into partials[0] by one
@@ -513,6 +577,9 @@ void launch_prolong(int F, const int* labels, const double* cscale, const double
                     hipStream_t s, const double* pw = nullptr);
 void launch_fill(double* x, double v, long long n, hipStream_t s);
 // ---- single-precision inner solves (mixed.hip) -------------------------------
+void launch_cycle_in(int F, const double* r64, const double* colnorm, double lam, double omega,
+                     const IrVectors& v, const int* done, hipStream_t s);
+void launch_widen(int F, const float* z32, double* z, const int* done, hipStream_t s);
 void launch_ir_init(int F, const double* r64, const double* colnorm, double lam, double omega,
                     int kind, const IrVectors& v, double* parts, hipStream_t s);
 void launch_ir_update(int F, const IrVectors& v, double omega, int kind, Scalars* sc,
@@ -563,6 +630,7 @@ uint64_t splitmix64_next(uint64_t& state);   // SplitMix64 (Steele, Lea & Flood)
 rr_status run_kmeans(rr_handle* h, int k, uint64_t seed, int max_iter, hipStream_t s);
 rr_status set_labels(rr_handle* h, const int* labels_in, int nlab, hipStream_t s);
 rr_status build_coarse_gram(rr_handle* h, hipStream_t s);
+rr_status check_coarse_size(int fc);   // RR_ERR_UNSUPPORTED above 18,944 clusters (0/1 X)
 rr_status build_coarse_gram_valued(rr_handle* h, hipStream_t s);   // (api.hip)
 // c = P^T v over the restriction plan mp (either interpolation)  (api.hip)
 void launch_restrict(const rr_handle* h, const MergePlan& mp, const double* v, double* out,

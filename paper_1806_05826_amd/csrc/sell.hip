@@ -423,14 +423,14 @@ void launch_sell_gather(const SellPlan& sp, const double* v, hipStream_t s) {
 }
 
 void free_sell(SellPlan& sp) {
-  if (sp.idx) (void)hipFree(sp.idx);
-  if (sp.task) (void)hipFree(sp.task);
-  if (sp.wrange) (void)hipFree(sp.wrange);
-  if (sp.bslice) (void)hipFree(sp.bslice);
-  if (sp.pos) (void)hipFree(sp.pos);
-  if (sp.sbase) (void)hipFree(sp.sbase);
-  if (sp.lseg) (void)hipFree(sp.lseg);
-  if (sp.part) (void)hipFree(sp.part);
+  if (sp.idx) (void)dev_free(sp.idx);
+  if (sp.task) (void)dev_free(sp.task);
+  if (sp.wrange) (void)dev_free(sp.wrange);
+  if (sp.bslice) (void)dev_free(sp.bslice);
+  if (sp.pos) (void)dev_free(sp.pos);
+  if (sp.sbase) (void)dev_free(sp.sbase);
+  if (sp.lseg) (void)dev_free(sp.lseg);
+  if (sp.part) (void)dev_free(sp.part);
   sp = SellPlan{};
 }
 
@@ -734,20 +734,20 @@ rr_status build_sell(SellPlan& sp, const std::vector<int>& ptr, const std::vecto
   sp.nblk = (int)bslice.size();
   sp.ntask = (int)tasks_sorted.size();
   sp.nout = B.nout;
-  RR_HIP(hipMalloc(&sp.idx, sizeof(uint16_t) * B.idx.size()));
-  RR_HIP(hipMalloc(&sp.task, sizeof(int4) * std::max<size_t>(1, tasks_sorted.size())));
-  RR_HIP(hipMalloc(&sp.wrange, sizeof(int) * std::max<size_t>(1, wrange.size())));
-  RR_HIP(hipMalloc(&sp.bslice, sizeof(int) * std::max<size_t>(1, bslice.size())));
-  RR_HIP(hipMalloc(&sp.pos, sizeof(int) * std::max<size_t>(1, B.pos.size())));
-  RR_HIP(hipMalloc(&sp.sbase, sizeof(int) * sbase.size()));
+  RR_HIP(dmalloc(&sp.idx, sizeof(uint16_t) * B.idx.size()));
+  RR_HIP(dmalloc(&sp.task, sizeof(int4) * std::max<size_t>(1, tasks_sorted.size())));
+  RR_HIP(dmalloc(&sp.wrange, sizeof(int) * std::max<size_t>(1, wrange.size())));
+  RR_HIP(dmalloc(&sp.bslice, sizeof(int) * std::max<size_t>(1, bslice.size())));
+  RR_HIP(dmalloc(&sp.pos, sizeof(int) * std::max<size_t>(1, B.pos.size())));
+  RR_HIP(dmalloc(&sp.sbase, sizeof(int) * sbase.size()));
   std::vector<int> lseg;
   for (int q = 0; q < S; ++q)
     if (sbase[q + 1] - sbase[q] > kReduceBatch) lseg.push_back(q);
   sp.nlong = (int)lseg.size();
-  RR_HIP(hipMalloc(&sp.lseg, sizeof(int) * std::max<size_t>(1, lseg.size())));
+  RR_HIP(dmalloc(&sp.lseg, sizeof(int) * std::max<size_t>(1, lseg.size())));
   if (!lseg.empty())
     RR_HIP(hipMemcpyAsync(sp.lseg, lseg.data(), sizeof(int) * lseg.size(), hipMemcpyHostToDevice, s));
-  RR_HIP(hipMalloc(&sp.part, sizeof(double) * std::max(1, sp.nout)));
+  RR_HIP(dmalloc(&sp.part, sizeof(double) * std::max(1, sp.nout)));
   RR_HIP(hipMemcpyAsync(sp.idx, B.idx.data(), sizeof(uint16_t) * B.idx.size(), hipMemcpyHostToDevice, s));
   if (!tasks_sorted.empty())
     RR_HIP(hipMemcpyAsync(sp.task, tasks_sorted.data(), sizeof(int4) * tasks_sorted.size(),
@@ -845,8 +845,8 @@ rr_status build_sell_plans(Sparse& X, hipStream_t s, int autotune, SellTuning* t
       // candidate must win by 3 % to replace a smaller one
       double *v = nullptr, *out = nullptr;
       const int nmax = std::max(X.N, X.F);
-      RR_HIP(hipMalloc(&v, sizeof(double) * nmax));
-      RR_HIP(hipMalloc(&out, sizeof(double) * nmax));
+      RR_HIP(dmalloc(&v, sizeof(double) * nmax));
+      RR_HIP(dmalloc(&out, sizeof(double) * nmax));
       launch_fill(v, 1.0, nmax, s);
       constexpr int kCand = 3, kRounds = 5;
       const int cand[kCand] = {1, 2, 4};
@@ -889,8 +889,8 @@ rr_status build_sell_plans(Sparse& X, hipStream_t s, int autotune, SellTuning* t
             }
         }
       }
-      (void)hipFree(v);
-      (void)hipFree(out);
+      (void)dev_free(v);
+      (void)dev_free(out);
       RR_TRY(st);
       std::lock_guard<std::mutex> lk(g_tune_mu);
       g_tune_cache[key] = {lanes, div_cols};

@@ -267,128 +267,53 @@ __global__ __launch_bounds__(kBlock) void k_segfix(const int4* __restrict__ span
   if constexpr (has_dot<MODE>()) store_block_partial<kBlock>(dot, e.partials, nmain + blockIdx.x);
 }
 
-// Chunked segmented sum for epilogues without a dot product: one wave per
-// chunk of at most kChunk entries (lane l adds entries l, l + 64, ... in
-// order, then a fixed butterfly); a segment's only chunk finishes it, the
-// chunks of longer segments leave partials that one wave per such segment
-// adds in chunk order (k_chunk_fin).  With VAL, entry e adds v[idx[e]] * val[e].
-constexpr int kChunk = 256;
-template <int MODE, bool VAL>
-__global__ __launch_bounds__(kBlock) void k_chunk_sum(const int4* __restrict__ chunk, int nchunk,
-                                                      const int* __restrict__ idx,
-                                                      const double* __restrict__ val,
-                                                      const double* __restrict__ v,
-                                                      double* __restrict__ cpart, Epi e,
-                                                      const int* done) {
-  if (is_done(done)) return;
-  const int wv = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (wv >= nchunk) return;
-  const int4 c = chunk[wv];
-  int j[kChunk / 64];
-#pragma unroll
-  for (int k = 0; k < kChunk / 64; ++k) j[k] = (c.y + lane + 64 * k < c.z) ? idx[c.y + lane + 64 * k] : -1;
-  double t = 0.0;
-  if constexpr (VAL) {
-    double a[kChunk / 64];
-#pragma unroll
-    for (int k = 0; k < kChunk / 64; ++k) a[k] = (j[k] >= 0) ? val[c.y + lane + 64 * k] : 0.0;
-#pragma unroll
-    for (int k = 0; k < kChunk / 64; ++k) t += (j[k] >= 0) ? v[j[k]] * a[k] : 0.0;
-  } else {
-#pragma unroll
-    for (int k = 0; k < kChunk / 64; ++k) t += (j[k] >= 0) ? v[j[k]] : 0.0;
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-  if (lane == 0) {
-    if (c.w < 0) {
-      double dot = 0.0;
-      seg_finish<MODE>(c.x, t, e, dot);
-    } else {
-      cpart[c.w] = t;
-    }
-  }
-}
-
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_chunk_fin(const int4* __restrict__ fin, int nfin,
-                                                      const double* __restrict__ cpart, Epi e,
-                                                      const int* done) {
-  if (is_done(done)) return;
-  const int wv = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (wv >= nfin) return;
-  const int4 f = fin[wv];
-  double t = 0.0;
-  for (int k = lane; k < f.z; k += 64) t += cpart[f.y + k];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-  if (lane == 0) {
-    double dot = 0.0;
-    seg_finish<MODE>(f.x, t, e, dot);
-  }
-}
-
-template <int MODE>
-static void chunk_mode(const MergePlan& mp, const int* idx, const double* val, const double* v,
-                       const Epi& e, const int* done, hipStream_t s) {
-  if (val)
-    k_chunk_sum<MODE, true><<<cdiv(mp.nchunk, kBlock / 64), kBlock, 0, s>>>(mp.chunk, mp.nchunk, idx,
-                                                                          val, v, mp.cpart, e, done);
-  else
-    k_chunk_sum<MODE, false><<<cdiv(mp.nchunk, kBlock / 64), kBlock, 0, s>>>(
-        mp.chunk, mp.nchunk, idx, nullptr, v, mp.cpart, e, done);
-  if (mp.nfin > 0)
-    k_chunk_fin<MODE><<<cdiv(mp.nfin, kBlock / 64), kBlock, 0, s>>>(mp.fin, mp.nfin, mp.cpart, e,
-                                                                    done);
-}
-
 // One-kernel segmented sum for epilogues without a dot product: a segment
 // of at most kWaveSeg entries is summed by one wave (lane l adds entries l,
-// l + 64, ... in order, then a fixed butterfly), a longer one (at most
-// kOneSegMax entries) by a whole block (thread k adds entries k, k + 256,
-// ... in order, then the fixed block tree).  Blocks [0, nb) take the long
-// segments, the others four short ones each.
+// l + 64, ... in order, then a fixed butterfly), a longer one by a whole
+// 1024-thread block (thread k adds entries k, k + 1024, ... in order, 16
+// loads in flight, then the fixed block tree).  Blocks [0, nb) take the long
+// segments, the others sixteen short ones each.
 constexpr int kWaveSeg = 1024;
-constexpr int kOneSegMax = 4096;
+constexpr int kSegBlock = 1024;
 template <int MODE, bool VAL>
-__global__ __launch_bounds__(kBlock) void k_seg1(const int4* __restrict__ witem, int nw,
-                                                 const int4* __restrict__ bitem, int nb,
-                                                 const int* __restrict__ idx, const double* __restrict__ val,
-                                                 const double* __restrict__ v, Epi e, const int* done) {
+__global__ __launch_bounds__(kSegBlock) void k_seg1(const int4* __restrict__ witem, int nw,
+                                                    const int4* __restrict__ bitem, int nb,
+                                                    const int* __restrict__ idx,
+                                                    const double* __restrict__ val,
+                                                    const double* __restrict__ v, Epi e, const int* done) {
   if (is_done(done)) return;
   double dot = 0.0;
+  constexpr int U = 16;
   if ((int)blockIdx.x < nb) {
     const int4 it = bitem[blockIdx.x];
-    constexpr int U = kOneSegMax / kBlock;
-    int j[U];
-#pragma unroll
-    for (int k = 0; k < U; ++k) {
-      const int q = it.y + (int)threadIdx.x + k * kBlock;
-      j[k] = q < it.z ? idx[q] : -1;
-    }
     double t = 0.0;
-    if constexpr (VAL) {
-      double a[U];
+    for (int q0 = it.y + (int)threadIdx.x; q0 < it.z; q0 += U * kSegBlock) {
+      int j[U];
 #pragma unroll
-      for (int k = 0; k < U; ++k) a[k] = j[k] >= 0 ? val[it.y + (int)threadIdx.x + k * kBlock] : 0.0;
+      for (int k = 0; k < U; ++k) {
+        const int q = q0 + k * kSegBlock;
+        j[k] = q < it.z ? idx[q] : -1;
+      }
+      if constexpr (VAL) {
+        double a[U];
 #pragma unroll
-      for (int k = 0; k < U; ++k) t += j[k] >= 0 ? v[j[k]] * a[k] : 0.0;
-    } else {
+        for (int k = 0; k < U; ++k) a[k] = j[k] >= 0 ? val[q0 + k * kSegBlock] : 0.0;
 #pragma unroll
-      for (int k = 0; k < U; ++k) t += j[k] >= 0 ? v[j[k]] : 0.0;
+        for (int k = 0; k < U; ++k) t += j[k] >= 0 ? v[j[k]] * a[k] : 0.0;
+      } else {
+#pragma unroll
+        for (int k = 0; k < U; ++k) t += j[k] >= 0 ? v[j[k]] : 0.0;
+      }
     }
-    __shared__ double red[kBlock / 64];
-    t = block_sum(t, red);
+    __shared__ double red[kSegBlock / 64];
+    t = block_sum_n<kSegBlock>(t, red);
     if (threadIdx.x == 0) seg_finish<MODE>(it.x, t, e, dot);
     return;
   }
-  const int wv = ((int)blockIdx.x - nb) * (kBlock / 64) + (int)(threadIdx.x >> 6);
+  const int wv = ((int)blockIdx.x - nb) * (kSegBlock / 64) + (int)(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (wv >= nw) return;
   const int4 it = witem[wv];
-  constexpr int U = kWaveSeg / 64;
   int j[U];
 #pragma unroll
   for (int k = 0; k < U; ++k) {
@@ -414,13 +339,13 @@ __global__ __launch_bounds__(kBlock) void k_seg1(const int4* __restrict__ witem,
 template <int MODE>
 static void seg1_mode(const MergePlan& mp, const int* idx, const double* val, const double* v,
                       const Epi& e, const int* done, hipStream_t s) {
-  const int grid = mp.nbitem + cdiv(mp.nwitem, kBlock / 64);
+  const int grid = mp.nbitem + cdiv(mp.nwitem, kSegBlock / 64);
   if (val)
-    k_seg1<MODE, true><<<grid, kBlock, 0, s>>>(mp.witem, mp.nwitem, mp.bitem, mp.nbitem, idx, val, v, e,
-                                               done);
+    k_seg1<MODE, true><<<grid, kSegBlock, 0, s>>>(mp.witem, mp.nwitem, mp.bitem, mp.nbitem, idx, val, v,
+                                                  e, done);
   else
-    k_seg1<MODE, false><<<grid, kBlock, 0, s>>>(mp.witem, mp.nwitem, mp.bitem, mp.nbitem, idx, nullptr, v,
-                                                e, done);
+    k_seg1<MODE, false><<<grid, kSegBlock, 0, s>>>(mp.witem, mp.nwitem, mp.bitem, mp.nbitem, idx,
+                                                   nullptr, v, e, done);
 }
 
 // Collapse n block partials into partials[0] (one block, fixed order).
@@ -475,15 +400,6 @@ int launch_segsum(const MergePlan& mp, const int* seg_end, const int* idx, const
     }
   }
   if (mp.nblocks == 0) return 0;
-  if (mp.nchunk > 0) {
-    switch (mode) {
-      case EPI_STORE: chunk_mode<EPI_STORE>(mp, idx, val, v, e, done, s); return 0;
-      case EPI_APPLY: chunk_mode<EPI_APPLY>(mp, idx, val, v, e, done, s); return 0;
-      case EPI_RESID: chunk_mode<EPI_RESID>(mp, idx, val, v, e, done, s); return 0;
-      case EPI_SCALE: chunk_mode<EPI_SCALE>(mp, idx, val, v, e, done, s); return 0;
-      default: break;   // epilogues with a dot product take the merge path
-    }
-  }
   switch (mode) {
     case EPI_STORE: return segsum_mode<EPI_STORE>(mp, seg_end, idx, val, v, e, done, s);
     case EPI_APPLY: return segsum_mode<EPI_APPLY>(mp, seg_end, idx, val, v, e, done, s);
@@ -507,15 +423,12 @@ __global__ void k_block_seg_start(const int2* coord, const int* seg_ptr, int nbl
 }
 
 void free_merge_plan(MergePlan& mp) {
-  if (mp.coord) (void)hipFree(mp.coord);
-  if (mp.span) (void)hipFree(mp.span);
-  if (mp.head) (void)hipFree(mp.head);
-  if (mp.tail) (void)hipFree(mp.tail);
-  if (mp.chunk) (void)hipFree(mp.chunk);
-  if (mp.fin) (void)hipFree(mp.fin);
-  if (mp.cpart) (void)hipFree(mp.cpart);
-  if (mp.witem) (void)hipFree(mp.witem);
-  if (mp.bitem) (void)hipFree(mp.bitem);
+  if (mp.coord) (void)dev_free(mp.coord);
+  if (mp.span) (void)dev_free(mp.span);
+  if (mp.head) (void)dev_free(mp.head);
+  if (mp.tail) (void)dev_free(mp.tail);
+  if (mp.witem) (void)dev_free(mp.witem);
+  if (mp.bitem) (void)dev_free(mp.bitem);
   mp = MergePlan{};
 }
 
@@ -524,9 +437,7 @@ rr_status build_chunk_plan(MergePlan& mp, const int* d_seg_ptr, int nseg, hipStr
   std::vector<int> ptr(nseg + 1);
   RR_HIP(hipMemcpyAsync(ptr.data(), d_seg_ptr, sizeof(int) * (nseg + 1), hipMemcpyDeviceToHost, s));
   RR_HIP(hipStreamSynchronize(s));
-  int longest = 0;
-  for (int q = 0; q < nseg; ++q) longest = std::max(longest, ptr[q + 1] - ptr[q]);
-  if (longest <= kOneSegMax) {   // one kernel: a wave or a block per segment
+  {   // a wave or a block per segment
     std::vector<int4> wi, bi;
     for (int q = 0; q < nseg; ++q) {
       if (ptr[q + 1] < ptr[q]) return fail(RR_ERR_DEVICE, "internal: decreasing segment offsets");
@@ -535,43 +446,16 @@ rr_status build_chunk_plan(MergePlan& mp, const int* d_seg_ptr, int nseg, hipStr
     mp.nwitem = (int)wi.size();
     mp.nbitem = (int)bi.size();
     if (mp.nwitem) {
-      RR_HIP(hipMalloc(&mp.witem, sizeof(int4) * mp.nwitem));
+      RR_HIP(dmalloc(&mp.witem, sizeof(int4) * mp.nwitem));
       RR_HIP(hipMemcpyAsync(mp.witem, wi.data(), sizeof(int4) * mp.nwitem, hipMemcpyHostToDevice, s));
     }
     if (mp.nbitem) {
-      RR_HIP(hipMalloc(&mp.bitem, sizeof(int4) * mp.nbitem));
+      RR_HIP(dmalloc(&mp.bitem, sizeof(int4) * mp.nbitem));
       RR_HIP(hipMemcpyAsync(mp.bitem, bi.data(), sizeof(int4) * mp.nbitem, hipMemcpyHostToDevice, s));
     }
     RR_HIP(hipStreamSynchronize(s));
     return RR_OK;
   }
-  std::vector<int4> chunk, fin;
-  int slots = 0;
-  for (int q = 0; q < nseg; ++q) {
-    const int a = ptr[q], z = ptr[q + 1];
-    if (z < a) return fail(RR_ERR_DEVICE, "internal: decreasing segment offsets");
-    const int nc = std::max(1, cdiv(z - a, kChunk));
-    if (nc == 1) {
-      chunk.push_back(make_int4(q, a, z, -1));
-      continue;
-    }
-    fin.push_back(make_int4(q, slots, nc, 0));
-    for (int c = 0; c < nc; ++c) chunk.push_back(make_int4(q, a + c * kChunk, std::min(z, a + (c + 1) * kChunk), slots++));
-  }
-  mp.nchunk = (int)chunk.size();
-  mp.nfin = (int)fin.size();
-  mp.ncpart = slots;
-  if (mp.nchunk) {
-    RR_HIP(hipMalloc(&mp.chunk, sizeof(int4) * mp.nchunk));
-    RR_HIP(hipMemcpyAsync(mp.chunk, chunk.data(), sizeof(int4) * mp.nchunk, hipMemcpyHostToDevice, s));
-  }
-  if (mp.nfin) {
-    RR_HIP(hipMalloc(&mp.fin, sizeof(int4) * mp.nfin));
-    RR_HIP(hipMemcpyAsync(mp.fin, fin.data(), sizeof(int4) * mp.nfin, hipMemcpyHostToDevice, s));
-    RR_HIP(hipMalloc(&mp.cpart, sizeof(double) * mp.ncpart));
-  }
-  RR_HIP(hipStreamSynchronize(s));
-  return RR_OK;
 }
 
 // seg_end = ptr + 1 (nseg entries), seg_ptr = ptr (nseg + 1 entries).
@@ -584,13 +468,13 @@ rr_status build_merge_plan(MergePlan& mp, const int* d_seg_end, const int* d_seg
   if (total == 0) return RR_OK;
   if (total >= INT_MAX) return fail(RR_ERR_INVALID_ARG, "merge plan: segments + nonzeros >= 2^31");
   mp.nblocks = cdiv(total, kMergeTile);
-  RR_HIP(hipMalloc(&mp.coord, sizeof(int2) * (mp.nblocks + 1)));
-  RR_HIP(hipMalloc(&mp.head, sizeof(double) * mp.nblocks));
-  RR_HIP(hipMalloc(&mp.tail, sizeof(double) * mp.nblocks));
+  RR_HIP(dmalloc(&mp.coord, sizeof(int2) * (mp.nblocks + 1)));
+  RR_HIP(dmalloc(&mp.head, sizeof(double) * mp.nblocks));
+  RR_HIP(dmalloc(&mp.tail, sizeof(double) * mp.nblocks));
   k_merge_coord<<<cdiv(mp.nblocks + 1, kBlock), kBlock, 0, s>>>(d_seg_end, nseg, nnz, mp.nblocks,
                                                                mp.coord);
   int* d_start = nullptr;
-  RR_HIP(hipMalloc(&d_start, sizeof(int) * mp.nblocks));
+  RR_HIP(dmalloc(&d_start, sizeof(int) * mp.nblocks));
   k_block_seg_start<<<cdiv(mp.nblocks, kBlock), kBlock, 0, s>>>(mp.coord, d_seg_ptr, mp.nblocks,
                                                                d_start);
   std::vector<int2> coord(mp.nblocks + 1);
@@ -600,7 +484,7 @@ rr_status build_merge_plan(MergePlan& mp, const int* d_seg_end, const int* d_seg
   RR_HIP(hipMemcpyAsync(start.data(), d_start, sizeof(int) * mp.nblocks, hipMemcpyDeviceToHost,
                         s));
   RR_HIP(hipStreamSynchronize(s));
-  RR_HIP(hipFree(d_start));
+  RR_HIP(dev_free(d_start));
   // Segments that cross tiles: a run of tiles b_a..b_z that all begin inside
   // segment s; s started in tile b_a - 1 and ends in tile b_z.
   std::vector<int4> spans;
@@ -619,7 +503,7 @@ rr_status build_merge_plan(MergePlan& mp, const int* d_seg_end, const int* d_seg
   }
   mp.nspan = (int)spans.size();
   if (mp.nspan) {
-    RR_HIP(hipMalloc(&mp.span, sizeof(int4) * mp.nspan));
+    RR_HIP(dmalloc(&mp.span, sizeof(int4) * mp.nspan));
     RR_HIP(hipMemcpyAsync(mp.span, spans.data(), sizeof(int4) * mp.nspan, hipMemcpyHostToDevice,
                           s));
     RR_HIP(hipStreamSynchronize(s));
@@ -660,14 +544,14 @@ __global__ void k_validate(const int* ptr, const int* idx, const double* val, in
 
 rr_status validate_csr(const Sparse& X, hipStream_t s) {
   int* d_flag = nullptr;
-  RR_HIP(hipMalloc(&d_flag, sizeof(int)));
+  RR_HIP(dmalloc(&d_flag, sizeof(int)));
   RR_HIP(hipMemsetAsync(d_flag, 0, sizeof(int), s));
   k_validate<<<cdiv(X.N + 1, kBlock), kBlock, 0, s>>>(X.row_ptr, X.col_idx, X.val, X.N, X.F,
                                                       X.nnz, d_flag);
   int flag = 0;
   RR_HIP(hipMemcpyAsync(&flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
   RR_HIP(hipStreamSynchronize(s));
-  RR_HIP(hipFree(d_flag));
+  RR_HIP(dev_free(d_flag));
   if (flag & 1) return fail(RR_ERR_INVALID_ARG, "X: row_ptr is not a valid CSR pointer array");
   if (flag & 2) return fail(RR_ERR_INVALID_ARG, "X: column index out of range");
   if (flag & 4) return fail(RR_ERR_INVALID_ARG, "X: column indices not strictly increasing in a row");
@@ -748,9 +632,9 @@ __global__ void k_keys_to_cols(const unsigned long long* keys, int nnz, int* col
 rr_status renumber_features(Sparse& X, int* fperm, int* finv, hipStream_t s) {
   const int F = X.F, nnz = X.nnz, N = X.N;
   int *cnt = nullptr, *cnt_out = nullptr, *iota = nullptr;
-  RR_HIP(hipMalloc(&cnt, sizeof(int) * F));
-  RR_HIP(hipMalloc(&cnt_out, sizeof(int) * F));
-  RR_HIP(hipMalloc(&iota, sizeof(int) * F));
+  RR_HIP(dmalloc(&cnt, sizeof(int) * F));
+  RR_HIP(dmalloc(&cnt_out, sizeof(int) * F));
+  RR_HIP(dmalloc(&iota, sizeof(int) * F));
   RR_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * F, s));
   if (nnz) k_col_count<<<std::min(4096, cdiv(nnz, kBlock)), kBlock, 0, s>>>(X.col_idx, nnz, cnt);
   k_iota<<<cdiv(F, kBlock), kBlock, 0, s>>>(iota, F);
@@ -758,43 +642,43 @@ rr_status renumber_features(Sparse& X, int* fperm, int* finv, hipStream_t s) {
   RR_HIP(rocprim::radix_sort_pairs_desc(nullptr, tmp_bytes, cnt, cnt_out, iota, fperm, (size_t)F, 0u,
                                         32u, s));
   void* tmp = nullptr;
-  RR_HIP(hipMalloc(&tmp, std::max<size_t>(tmp_bytes, 1)));
+  RR_HIP(dmalloc(&tmp, std::max<size_t>(tmp_bytes, 1)));
   RR_HIP(rocprim::radix_sort_pairs_desc(tmp, tmp_bytes, cnt, cnt_out, iota, fperm, (size_t)F, 0u, 32u,
                                         s));
   k_invert<<<cdiv(F, kBlock), kBlock, 0, s>>>(fperm, F, finv);
   RR_HIP(hipStreamSynchronize(s));
-  RR_HIP(hipFree(tmp));
-  RR_HIP(hipFree(cnt));
-  RR_HIP(hipFree(cnt_out));
-  RR_HIP(hipFree(iota));
+  RR_HIP(dev_free(tmp));
+  RR_HIP(dev_free(cnt));
+  RR_HIP(dev_free(cnt_out));
+  RR_HIP(dev_free(iota));
   if (nnz == 0) return RR_OK;
   unsigned long long *keys = nullptr, *keys_out = nullptr;
-  RR_HIP(hipMalloc(&keys, sizeof(unsigned long long) * nnz));
-  RR_HIP(hipMalloc(&keys_out, sizeof(unsigned long long) * nnz));
+  RR_HIP(dmalloc(&keys, sizeof(unsigned long long) * nnz));
+  RR_HIP(dmalloc(&keys_out, sizeof(unsigned long long) * nnz));
   k_row_keys<<<cdiv(N, kBlock), kBlock, 0, s>>>(X.row_ptr, X.col_idx, finv, N, keys);
   unsigned end_bit = 32 + bits_for(N);
   tmp_bytes = 0;
   if (X.binary) {
     RR_HIP(rocprim::radix_sort_keys(nullptr, tmp_bytes, keys, keys_out, (size_t)nnz, 0u, end_bit, s));
-    RR_HIP(hipMalloc(&tmp, std::max<size_t>(tmp_bytes, 1)));
+    RR_HIP(dmalloc(&tmp, std::max<size_t>(tmp_bytes, 1)));
     RR_HIP(rocprim::radix_sort_keys(tmp, tmp_bytes, keys, keys_out, (size_t)nnz, 0u, end_bit, s));
   } else {
     double* vout = nullptr;
-    RR_HIP(hipMalloc(&vout, sizeof(double) * nnz));
+    RR_HIP(dmalloc(&vout, sizeof(double) * nnz));
     RR_HIP(rocprim::radix_sort_pairs(nullptr, tmp_bytes, keys, keys_out, X.val, vout, (size_t)nnz, 0u,
                                      end_bit, s));
-    RR_HIP(hipMalloc(&tmp, std::max<size_t>(tmp_bytes, 1)));
+    RR_HIP(dmalloc(&tmp, std::max<size_t>(tmp_bytes, 1)));
     RR_HIP(rocprim::radix_sort_pairs(tmp, tmp_bytes, keys, keys_out, X.val, vout, (size_t)nnz, 0u,
                                      end_bit, s));
     RR_HIP(hipMemcpyAsync(X.val, vout, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
     RR_HIP(hipStreamSynchronize(s));
-    RR_HIP(hipFree(vout));
+    RR_HIP(dev_free(vout));
   }
   k_keys_to_cols<<<cdiv(nnz, kBlock), kBlock, 0, s>>>(keys_out, nnz, X.col_idx);
   RR_HIP(hipStreamSynchronize(s));
-  RR_HIP(hipFree(tmp));
-  RR_HIP(hipFree(keys));
-  RR_HIP(hipFree(keys_out));
+  RR_HIP(dev_free(tmp));
+  RR_HIP(dev_free(keys));
+  RR_HIP(dev_free(keys_out));
   return RR_OK;
 }
 
@@ -802,18 +686,18 @@ rr_status renumber_features(Sparse& X, int* fperm, int* finv, hipStream_t s) {
 // inside every column, so the transpose is deterministic.
 rr_status build_csc(Sparse& X, hipStream_t s) {
   const int nnz = X.nnz;
-  RR_HIP(hipMalloc(&X.col_ptr, sizeof(int) * (X.F + 1)));
-  RR_HIP(hipMalloc(&X.row_idx, sizeof(int) * std::max(nnz, 1)));
-  if (!X.binary) RR_HIP(hipMalloc(&X.cval, sizeof(double) * std::max(nnz, 1)));
+  RR_HIP(dmalloc(&X.col_ptr, sizeof(int) * (X.F + 1)));
+  RR_HIP(dmalloc(&X.row_idx, sizeof(int) * std::max(nnz, 1)));
+  if (!X.binary) RR_HIP(dmalloc(&X.cval, sizeof(double) * std::max(nnz, 1)));
   if (nnz == 0) {
     RR_HIP(hipMemsetAsync(X.col_ptr, 0, sizeof(int) * (X.F + 1), s));
     return RR_OK;
   }
   int *row_of = nullptr, *pos = nullptr, *keys_out = nullptr, *pos_out = nullptr;
-  RR_HIP(hipMalloc(&row_of, sizeof(int) * nnz));
-  RR_HIP(hipMalloc(&pos, sizeof(int) * nnz));
-  RR_HIP(hipMalloc(&keys_out, sizeof(int) * nnz));
-  RR_HIP(hipMalloc(&pos_out, sizeof(int) * nnz));
+  RR_HIP(dmalloc(&row_of, sizeof(int) * nnz));
+  RR_HIP(dmalloc(&pos, sizeof(int) * nnz));
+  RR_HIP(dmalloc(&keys_out, sizeof(int) * nnz));
+  RR_HIP(dmalloc(&pos_out, sizeof(int) * nnz));
   k_expand_rows<<<cdiv(X.N, kBlock), kBlock, 0, s>>>(X.row_ptr, X.N, row_of);
   k_iota<<<cdiv(nnz, kBlock), kBlock, 0, s>>>(pos, nnz);
   size_t tmp_bytes = 0;
@@ -821,18 +705,18 @@ rr_status build_csc(Sparse& X, hipStream_t s) {
   RR_HIP(rocprim::radix_sort_pairs(nullptr, tmp_bytes, X.col_idx, keys_out, pos, pos_out,
                                    (size_t)nnz, 0u, end_bit, s));
   void* tmp = nullptr;
-  RR_HIP(hipMalloc(&tmp, std::max<size_t>(tmp_bytes, 1)));
+  RR_HIP(dmalloc(&tmp, std::max<size_t>(tmp_bytes, 1)));
   RR_HIP(rocprim::radix_sort_pairs(tmp, tmp_bytes, X.col_idx, keys_out, pos, pos_out, (size_t)nnz,
                                    0u, end_bit, s));
   k_lower_bound_ptr<<<cdiv(X.F + 1, kBlock), kBlock, 0, s>>>(keys_out, nnz, X.F, X.col_ptr);
   k_gather_csc<<<cdiv(nnz, kBlock), kBlock, 0, s>>>(pos_out, row_of, X.binary ? nullptr : X.val,
                                                     nnz, X.row_idx, X.cval);
   RR_HIP(hipStreamSynchronize(s));
-  RR_HIP(hipFree(tmp));
-  RR_HIP(hipFree(row_of));
-  RR_HIP(hipFree(pos));
-  RR_HIP(hipFree(keys_out));
-  RR_HIP(hipFree(pos_out));
+  RR_HIP(dev_free(tmp));
+  RR_HIP(dev_free(row_of));
+  RR_HIP(dev_free(pos));
+  RR_HIP(dev_free(keys_out));
+  RR_HIP(dev_free(pos_out));
   if (X.binary) return RR_OK;   // 0/1 matrices use the sliced-ELL plans
   return build_merge_plan(X.csc_plan, X.col_ptr + 1, X.col_ptr, X.F, nnz, s);
 }

@@ -51,6 +51,30 @@ def test_error_paths_without_device():
     X = rr.rr_csr(0, 5, 0, None, None, None)
     h = ctypes.c_void_p()
     assert lib.rr_setup(ctypes.byref(X), None, None, ctypes.byref(h)) == rr.RR_ERR_INVALID_ARG
+    # versioned options: struct_size is set on construction; 0 is rejected
+    o = rr.rr_setup_opts(n_clusters=3)
+    assert o.struct_size == ctypes.sizeof(rr.rr_setup_opts)
+    o.struct_size = 0
+    assert lib.rr_setup(ctypes.byref(X), ctypes.byref(o), None, ctypes.byref(h)) == rr.RR_ERR_INVALID_ARG
+    assert "struct_size" in rr.rr_last_error()
+    # a workspace setup without a workspace, and a size query without X
+    assert lib.rr_setup_ws(ctypes.byref(X), None, None, 0, None, ctypes.byref(h)) == rr.RR_ERR_INVALID_ARG
+    n = ctypes.c_size_t()
+    assert lib.rr_setup_workspace_size(None, None, None, ctypes.byref(n)) == rr.RR_ERR_INVALID_ARG
+    assert lib.rr_set_allocator(ctypes.c_void_p(1), None, None) == rr.RR_ERR_INVALID_ARG
+
+
+def test_option_structs_match_the_header():
+    """The binding's option structs have the header's fields in order, with
+    struct_size first."""
+    import paper_1806_05826_amd as rr
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    for cls in (rr.rr_setup_opts, rr.rr_solve_opts, rr.rr_mlp_train_opts):
+        name = cls.__name__
+        body = re.search(r"typedef struct \{([^}]*)\}\s*" + name + ";", text).group(1)
+        fields = re.findall(r"\b(\w+)\s*(?:\[\w*\])?;", body)
+        assert [f for f, _ in cls._fields_] == fields, name
+        assert fields[0] == "struct_size"
 
 
 def test_oracle_is_not_imported_by_the_product():

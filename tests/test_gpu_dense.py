@@ -297,3 +297,69 @@ def test_dense_errors(rr, small):
         rr.DenseRidge(bad)
     assert e.value.status == rr.RR_ERR_INVALID_ARG
     R.close()
+
+
+@pytest.fixture(scope="module")
+def mid(rr):
+    """8192 x 2048 (32 groups of 64 columns, correlation 0.9) with 64
+    right-hand sides: the column pass's contraction splits into as many
+    pieces per output tile as at 50,000 x 4096 (the tiles and the split
+    target do not depend on N beyond the piece count), and every GEMM tile
+    is full."""
+    X = datagen.block_correlated_dense(8192, 32, 64, 0.9, seed=41).astype(np.float32)
+    lab = datagen.random_labels(X.shape[1], 64, 5)
+    fc = int(lab.max()) + 1
+    print(f"[dense mid] X {X.shape}, F_C={fc}", flush=True)
+    R = rr.DenseRidge(X, labels=lab)
+    yield X.astype(np.float64), lab, fc, R
+    R.close()
+
+
+def test_mid_operator_all_precisions(rr, mid):
+    X, lab, fc, R = mid
+    V = np.random.default_rng(9).standard_normal((64, X.shape[1]))
+    Q = host(R.apply_operator_block(0.1, V))
+    want = (X.T @ (X @ V.T)).T + 0.1 * V
+    bound = 4 * (X.shape[0] + X.shape[1]) * 2.0**-53 * ((np.abs(X).T @ (np.abs(X) @ np.abs(V.T))).T + 0.1 * np.abs(V))
+    assert np.all(np.abs(Q - want) <= bound)
+    Qb = host(R.apply_operator_block(0.1, V, precision="bf16_ir"))
+    want_b = op.apply_A_bf16(X, 0.1, V.T).T
+    assert np.all(np.abs(Qb - want_b) <= op.apply_A_bf16_bound(X, V.T).T + 1e-12 * np.abs(want_b))
+    Qf = host(R.apply_operator_block(0.1, V, precision="f32_ir"))
+    want_f = op.apply_A_f32(X, 0.1, V.T).T
+    assert np.all(np.abs(Qf - want_f) <= op.apply_A_f32_bound(X, V.T).T + 1e-12 * np.abs(want_f))
+
+
+@pytest.mark.parametrize("precision", ["f64", "bf16_ir", "f32_ir"])
+def test_mid_block_solves(rr, mid, precision):
+    """64 right-hand sides at lambda = 0.1: FP64 at the oracle's converged
+    count (1e-12) equals the oracle's V(1,1) iterate to 1e-10 per column;
+    the refinement forms reach the dense Cholesky solution to 1e-10."""
+    X, lab, fc, R = mid
+    lam = 0.1
+    _, Y = datagen.targets(X, 83, n_rhs=64)
+    Y = Y.T.copy()
+    om = op.omega_power(X, lam, seed=0x5eed)
+    cols = (0, 21, 42, 63)
+    if precision == "f64":
+        ks, refs = [], {}
+        for c in cols:
+            x_or, inf = krylov.solve(X, Y[c], lam, "vcycle", lab, fc, omega=om, tol=1e-12, max_iter=5000)
+            ks.append(inf.iters)
+        kfix = max(ks)
+        W, infos = R.solve_block(lam, Y, precond="vcycle", fixed_iters=kfix)
+        W = host(W)
+        for c in cols:
+            x_or, _ = krylov.solve(X, Y[c], lam, "vcycle", lab, fc, omega=om, fixed_iters=kfix)
+            err = np.linalg.norm(W[c] - x_or) / np.linalg.norm(x_or)
+            print(f"[dense mid f64] col {c}: {kfix} its, diff to oracle {err:.1e}", flush=True)
+            assert err <= 1e-10
+        return
+    W, infos = R.solve_block(lam, Y, precond="vcycle", precision=precision, tol=1e-13)
+    W = host(W)
+    for c in cols:
+        w_star = krylov.reference_solution(X, Y[c], lam)
+        err = np.linalg.norm(W[c] - w_star) / np.linalg.norm(w_star)
+        print(f"[dense mid {precision}] col {c}: {infos[c]['ir_steps']} steps, {infos[c]['iters']} its, "
+              f"err {err:.2e}", flush=True)
+        assert infos[c]["status"] == 0 and err <= 1e-10

@@ -128,6 +128,10 @@ def test_fullsize_solve(rr, big, solver_random_labels, lam):
         its.append(krylov.pcg(A, b, tl.vcycle, tol=1e-10, max_iter=2000)[1].iters)
     tl.coarse_correction = plain
     slack = 1 + int(0.02 * max(its))
+    print(f"[fullsize] lambda={lam}: GPU {info['iters']} iterations, oracle ensemble {sorted(its)} "
+          f"(spread {min(its)}..{max(its)}, band +-{slack})", flush=True)
+    if min(its) == max(its):   # no spread: the plain +-1 rule
+        assert abs(info["iters"] - its[0]) <= 1, (info["iters"], its)
     assert min(its) - slack <= info["iters"] <= max(its) + slack, (info["iters"], its)
     # oracle at equal iteration count once converged (1e-13)
     tl.D = D0
@@ -156,3 +160,61 @@ def test_fullsize_mixed_precision(rr, big, solver_random_labels, lam):
           f"iterations, residual {info['relres']:.1e}, error {err:.1e}", flush=True)
     assert info["status"] == 0 and info["ir_steps"] >= 2
     assert err <= 1e-10
+
+
+@pytest.fixture(scope="module")
+def kmeans_solver(rr, big):
+    R = rr.Ridge(big.X, n_clusters=1000, seed=5826)
+    lab = host(R.labels()).astype(np.int64)
+    return R, lab, R.info["n_coarse"]
+
+
+@pytest.mark.parametrize("lam", [1.0, 100.0])
+def test_fullsize_solve_on_kmeans_labels(rr, big, kmeans_solver, lam):
+    """The benchmark's aggregation (GPU k-means, k = 1000): at the oracle's
+    converged iteration count (relative residual 1e-13) the GPU iterate
+    equals the oracle's V(1,1) PCG iterate on the same labels to 1e-10, and
+    the natural-stop count at 1e-10 lies within one of the oracle's."""
+    R, lab, fc = kmeans_solver
+    print(f"[fullsize] k-means labels, lambda={lam}", flush=True)
+    omega = op.omega_gershgorin(big.X, lam)
+    tl = precond.TwoLevel(big.X, lam, lab, fc, omega)
+    A = lambda v: op.apply_A(big.X, lam, v)
+    b = op.rhs(big.X, big.y)
+    x_t, inf_t = krylov.pcg(A, b, tl.vcycle, tol=1e-13, max_iter=2000)
+    assert inf_t.status == krylov.OK
+    w, info = R.solve(lam, big.y, precond="vcycle", fixed_iters=inf_t.iters)
+    err = np.linalg.norm(host(w) - x_t) / np.linalg.norm(x_t)
+    k10 = next(k for k, h in enumerate(inf_t.history) if h <= 1e-10)
+    _, i10 = R.solve(lam, big.y, precond="vcycle", tol=1e-10, max_iter=2000)
+    print(f"[fullsize] k-means lambda={lam}: {inf_t.iters} iterations to 1e-13, error {err:.1e}; "
+          f"relres 1e-10 at {k10} (oracle) / {i10['iters']} (GPU)", flush=True)
+    assert err <= 1e-10
+    assert abs(i10["iters"] - k10) <= 1
+
+
+@pytest.mark.parametrize("lam", [1e-2, 100.0])
+def test_fullsize_fp32_cycle(rr, big, solver_random_labels, lam):
+    """FP64 flexible CG with the V(1,1) cycle in FP32 reaches the oracle's
+    FP64 solution (same aggregation, converged to 1e-14) to relative error
+    1e-10, the accuracy the plain FP64 path is measured at: it stops on the
+    error to that solution, which it must reach, and the error recomputed on
+    the host from the returned w confirms it.  (At equal residuals the two
+    cycles' iterates differ by up to kappa(A) times the residual: the FP32
+    cycle's coarse correction is less exact, so more of what remains lies in
+    the smallest eigenvalues' directions; a residual bar would not state the
+    accuracy reached.)"""
+    R, lab = solver_random_labels
+    print(f"[fullsize] FP32 cycle lambda={lam}", flush=True)
+    x_ref, inf_ref = krylov.solve(big.X, big.y, lam, "vcycle", lab, 1000, tol=1e-14, max_iter=3000)
+    assert inf_ref.status == krylov.OK
+    xr = torch.as_tensor(x_ref, dtype=torch.float64, device="cuda")
+    kw = dict(precond="vcycle", krylov="fcg", fcg_m=1, tol=1e-15, max_iter=3000, x_ref=xr, err_tol=1e-10)
+    w, info = R.solve(lam, big.y, precision="f32_cycle", **kw)
+    w64, i64 = R.solve(lam, big.y, **kw)
+    err = np.linalg.norm(host(w) - x_ref) / np.linalg.norm(x_ref)
+    err64 = np.linalg.norm(host(w64) - x_ref) / np.linalg.norm(x_ref)
+    print(f"[fullsize] FP32 cycle lambda={lam}: {info['iters']} iterations to error {err:.2e} "
+          f"(FP64 cycle: {i64['iters']} iterations, error {err64:.2e})", flush=True)
+    assert info["status"] == 0 and i64["status"] == 0
+    assert err <= 1e-10 and err64 <= 1e-10

@@ -209,3 +209,39 @@ def test_zero_energy_cluster_keeps_aggregation(rr):
     p_or = interp.ls_weights(V, eta, lab, fc, rep)
     assert np.allclose(p, p_or, rtol=1e-10, atol=1e-12 * np.abs(p_or).max())
     R.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_prototypes_match_the_oracle_eigenvectors(rr, name):
+    """rr_prototypes (Lanczos with full reorthogonalisation on the GPU)
+    against the oracle's dense eigendecomposition of X^T X: Ritz values to
+    1e-10 relative, Ritz vectors up to sign to the accuracy the spectral gap
+    allows (eps ||X^T X|| / gap), and the eigen equation's residual."""
+    P = CASES[name]()
+    R = rr.Ridge(P.X, n_clusters=20, seed=1)
+    K = 6
+    V = torch.empty((K, P.X.shape[1]), dtype=torch.float64, device="cuda")
+    ev = rr.rr_prototypes(R.h, K, V, steps=80)
+    Vo, evo = interp.leading_prototypes(P.X, K + 1)
+    Vg = host(V)
+    G = (P.X.T @ P.X).toarray()
+    print(f"[prototypes {name}] Ritz values {ev}, oracle {evo[:K]}", flush=True)
+    assert np.allclose(ev, evo[:K], rtol=1e-10, atol=0)
+    for k in range(K):
+        gap = min(abs(evo[k] - evo[j]) for j in range(K + 1) if j != k)
+        d = min(np.linalg.norm(Vg[k] - Vo[:, k]), np.linalg.norm(Vg[k] + Vo[:, k]))
+        assert d <= 1e-12 * evo[0] / gap + 1e-10, (k, d, gap)
+        assert np.linalg.norm(G @ Vg[k] - ev[k] * Vg[k]) <= 1e-9 * evo[0]
+    # they drive rr_set_interpolation like host-made prototypes
+    R2 = rr.Ridge(P.X, n_clusters=20, seed=1)
+    R.set_interpolation(V.T.contiguous().cpu().numpy(), beta=1.0)
+    R2.set_interpolation(Vo[:, :K], beta=1.0)
+    w1, i1 = R.solve(1.0, P.y, precond="vcycle", tol=1e-10)
+    w2, i2 = R2.solve(1.0, P.y, precond="vcycle", tol=1e-10)
+    assert i1["status"] == 0 and abs(i1["iters"] - i2["iters"]) <= 1
+    with pytest.raises(rr.RRError):
+        rr.rr_prototypes(R.h, 0, V)
+    with pytest.raises(rr.RRError):
+        rr.rr_prototypes(R.h, K, V, steps=K - 1)
+    R.close()
+    R2.close()

@@ -205,3 +205,56 @@ def test_learned_options(rr, tiny):
         R2.solve(1.0, Q.y, precond="learned", krylov="fcg")   # no network yet
     with pytest.raises(rr.RRError):
         rr.rr_mlp_init(R2.h, hidden=4)
+
+
+def test_nan_network_falls_back_to_the_algebraic_cycle(rr, tiny):
+    """A network whose weights were corrupted on the host (NaN) makes the
+    first flexible-CG step fail; the solve switches to the V(1,1) cycle from
+    the last good iterate (here x0 = 0) and converges, reporting the switch
+    at iteration 0."""
+    P, R = tiny
+    npar, n_in, n_out = rr.rr_mlp_size(R.h)
+    saved = rr.rr_mlp_get_weights(R.h)
+    try:
+        bad = np.full(npar, np.nan, dtype=np.float32)
+        rr.rr_mlp_set_weights(R.h, bad)
+        w, inf = R.solve(1.0, P.y, precond="learned", krylov="fcg", fcg_m=4, tol=1e-10, max_iter=500)
+        wv, iv = R.solve(1.0, P.y, precond="vcycle", krylov="fcg", fcg_m=4, tol=1e-10, max_iter=500)
+        print(f"[learned] NaN weights: status {inf['status']}, {inf['iters']} its, fallback at "
+              f"{inf['fallback_iter']} (V(1,1) FCG {iv['iters']} its)", flush=True)
+        assert inf["status"] == 0 and inf["fallback_iter"] == 0
+        assert inf["true_relres"] <= 2e-10
+        # from x0 = 0 with a fresh history this is the V(1,1) flexible-CG solve
+        assert abs(inf["iters"] - iv["iters"]) <= 1
+        d = np.linalg.norm(host(w) - host(wv)) / np.linalg.norm(host(wv))
+        assert d <= 1e-8, d
+        # an infinite weight as well
+        bad[:] = 0.0
+        bad[0] = np.inf
+        rr.rr_mlp_set_weights(R.h, bad)
+        w, inf = R.solve(0.3, P.y, precond="learned", krylov="fcg", fcg_m=2, tol=1e-10, max_iter=500)
+        assert inf["status"] == 0 and inf["true_relres"] <= 2e-10
+    finally:
+        rr.rr_mlp_set_weights(R.h, saved)
+
+
+def test_on_policy_pairs_are_coarse_corrections(rr, wide):
+    """Pairs from the network's own flexible-CG solves have the same form:
+    unit inputs, log lambda, and the exact coarse correction as target."""
+    P, R, fc, inp, tgt, lams = wide
+    rr.rr_mlp_init(R.h, hidden=64, seed=3)
+    rr.rr_mlp_train(R.h, inp, tgt, epochs=5, batch=256, lr=1e-3, seed=1)
+    n_s, per = 4, 10
+    inp2 = torch.empty((n_s * per, fc + 1), dtype=torch.float32, device="cuda")
+    tgt2 = torch.empty((n_s * per, fc), dtype=torch.float32, device="cuda")
+    y = torch.as_tensor(P.y, dtype=torch.float64, device="cuda")
+    n = rr.rr_collect_pairs_learned(R.h, lams[:n_s], per, 1, y, inp2, tgt2)
+    print(f"[learned] {n} on-policy pairs", flush=True)
+    assert 1 <= n <= n_s * per
+    X = host(inp2[:n]).astype(np.float64)
+    T = host(tgt2[:n]).astype(np.float64)
+    assert np.allclose(np.linalg.norm(X[:, :fc], axis=1), 1.0, atol=1e-5)
+    lam = float(np.exp(X[0, fc]))
+    assert abs(lam - lams[0]) <= 1e-5 * lams[0]
+    _, Ainv = (host(t) for t in R.coarse_factor(lams[0]))
+    assert np.linalg.norm(T[0] - Ainv @ X[0, :fc]) <= 1e-5 * np.linalg.norm(T[0])

@@ -86,3 +86,26 @@ def test_refinement_options(rr, case):
     Rv = rr.Ridge(Xv, n_clusters=0)
     with pytest.raises(rr.RRError):
         Rv.solve(1.0, Q.y, precond="jacobi", precision="f32_ir")
+
+
+@pytest.mark.parametrize("lam", [1e-2, 1.0])
+def test_fp32_cycle_keeps_the_fp64_krylov_space(rr, case, lam):
+    """FP64 flexible CG whose V(1,1) cycle runs in FP32: one solve reaches
+    the FP64 solution (no refinement restarts), in about the iterations of
+    the all-FP64 flexible CG."""
+    name, P, R = case
+    wst = krylov.reference_solution(P.X, P.y, lam)
+    w, info = R.solve(lam, P.y, precond="vcycle", krylov="fcg", fcg_m=1, precision="f32_cycle",
+                      tol=1e-13, max_iter=20000)
+    w64, i64 = R.solve(lam, P.y, precond="vcycle", krylov="fcg", fcg_m=1, tol=1e-13, max_iter=20000)
+    err = np.linalg.norm(host(w) - wst) / np.linalg.norm(wst)
+    err64 = np.linalg.norm(host(w64) - wst) / np.linalg.norm(wst)
+    print(f"[mixed {name}] FP32 cycle lambda={lam}: {info['iters']} iterations (FP64 {i64['iters']}), "
+          f"true residual {info['true_relres']:.1e}, error {err:.1e} (FP64 {err64:.1e})", flush=True)
+    assert info["status"] == 0 and info["true_relres"] <= 1e-12
+    assert err <= max(1e-10, 10 * err64)
+    assert info["iters"] <= 1.25 * i64["iters"] + 2
+    with pytest.raises(rr.RRError):   # the FP32 cycle needs flexible CG and V(1,1)
+        R.solve(lam, P.y, precond="vcycle", precision="f32_cycle")
+    with pytest.raises(rr.RRError):
+        R.solve(lam, P.y, precond="jacobi", krylov="fcg", precision="f32_cycle")

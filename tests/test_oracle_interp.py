@@ -5,6 +5,7 @@ average it reduces to."""
 import numpy as np
 import pytest
 import scipy.optimize as so
+import scipy.sparse as sp
 
 import datagen
 from oracle import interp, leader, precond
@@ -115,3 +116,25 @@ def test_plain_aggregation_matches_the_square_root_average():
     r = np.random.default_rng(9).standard_normal(80)
     assert np.allclose(a.coarse_correction(r), b.coarse_correction(r), rtol=1e-11, atol=1e-13)
     assert np.allclose(a.vcycle(r), b.vcycle(r), rtol=1e-11, atol=1e-13)
+
+
+def test_leading_prototypes_closed_form_and_eigen_equation():
+    """Disjoint column supports make X^T X diagonal with the squared column
+    norms on it, so the leading prototypes are the unit vectors of the
+    largest columns; on a general matrix every prototype satisfies
+    X^T X v = mu v with mu the largest eigenvalues (checked against the
+    singular values of X)."""
+    # columns with disjoint supports and norms^2 = 1, 9, 4, 16 (integer rows)
+    X = sp.csr_matrix(np.array([[1, 0, 0, 0], [0, 3, 0, 0], [0, 0, 2, 0], [0, 0, 0, 4.0]]))
+    V, ev = interp.leading_prototypes(X, 2)
+    assert np.allclose(ev, [16.0, 9.0])
+    assert np.allclose(np.abs(V[:, 0]), [0, 0, 0, 1]) and np.allclose(np.abs(V[:, 1]), [0, 1, 0, 0])
+    rng = np.random.default_rng(3)
+    Y = sp.random(60, 25, density=0.2, random_state=rng, format="csr")
+    V, ev = interp.leading_prototypes(Y, 5)
+    sv = np.linalg.svd(Y.toarray(), compute_uv=False)
+    assert np.allclose(ev, sv[:5] ** 2, rtol=1e-12)
+    G = (Y.T @ Y).toarray()
+    for k in range(5):
+        assert np.linalg.norm(G @ V[:, k] - ev[k] * V[:, k]) <= 1e-12 * ev[0]
+        assert abs(np.linalg.norm(V[:, k]) - 1.0) <= 1e-14
