@@ -435,6 +435,27 @@ rr_status rr_solve_batched(int32_t nprob, rr_handle* const* handles, const doubl
                            const double* const* rhs, double* const* w, const rr_solve_opts* opts,
                            rr_solve_info* info, rr_stream stream);
 
+/*
+ * rr_solve_batched_noalloc: rr_solve_batched with persistent = 1 for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  It allocates nothing:
+ * the problems' descriptors, launch order, records and queue counter live in
+ * a static device array of the library (about 570 KB per GPU, held until the
+ * process ends), so a call takes at most 2048 problems (more:
+ * RR_ERR_INVALID_ARG).  Every handle must already hold what its problems
+ * need: a handle listed k + 1 times needs k reserved work sets
+ * (rr_setup_opts.reserve_sets) and, for V(1,1), no more distinct lambdas
+ * than its lambda_slots (else RR_ERR_WORKSPACE).  The same restrictions as
+ * the persistent solve apply (0/1 X, at most 8192 features, FP64 PCG, V(1,1)
+ * or Jacobi).  The launch is never replayed from a graph (graph is ignored).
+ * All calls on one GPU share its array: calls that overlap on one GPU race,
+ * so a caller serialises them (the call returns only after its launch has
+ * finished).
+ */
+rr_status rr_solve_batched_noalloc(int32_t nprob, rr_handle* const* handles, const double* lambdas,
+                                   const double* const* rhs, double* const* w,
+                                   const rr_solve_opts* opts, rr_solve_info* info, rr_stream stream);
+
 /* Av = (X^T X + lambda I) v, v and Av device double[F] (lambda >= 0). */
 rr_status rr_apply_operator(rr_handle* h, double lambda, const double* v, double* Av,
                             rr_stream stream);

@@ -134,6 +134,7 @@ _SIGS = {
                                 C.POINTER(C.c_size_t)],
     "rr_set_allocator": [_P, _P, _P],
     "rr_prototypes": [_P, C.c_int32, C.c_int32, C.c_uint64, _P, _P, _P],
+    "rr_solve_batched_noalloc": [C.c_int32, _P, _P, _P, _P, C.POINTER(rr_solve_opts), _P, _P],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -435,6 +436,33 @@ def rr_solve_batched(handles, lams, rhs, ws, tol=0.0, max_iter=0, fixed_iters=0,
     st = _lib.rr_solve_batched(C.c_int32(n), C.cast(H, C.c_void_p), C.cast(L, C.c_void_p),
                                C.cast(Rp, C.c_void_p), C.cast(Wp, C.c_void_p), C.byref(o),
                                C.cast(infos, C.c_void_p), _stream(stream))
+    if st in raise_on:
+        raise RRError(st, rr_last_error())
+    return st, [{f: getattr(infos[i], f) for f, _ in rr_solve_info._fields_} for i in range(n)]
+
+
+def rr_solve_batched_noalloc(handles, lams, rhs, ws, tol=0.0, max_iter=0, fixed_iters=0,
+                             precond="vcycle", rhs_is_b=False, omega=0.0, stream=None,
+                             raise_on=(RR_ERR_INVALID_ARG, RR_ERR_DEVICE, RR_ERR_WORKSPACE,
+                                       RR_ERR_UNSUPPORTED)):
+    """The persistent batched solve with no device allocation (the
+    library's static scratch); returns (status, [info dict per problem])."""
+    n = len(handles)
+    if not (len(lams) == len(rhs) == len(ws) == n):
+        raise ValueError("handles, lams, rhs and ws must have equal lengths")
+    for t in list(rhs) + list(ws):
+        _dev_f64(t, None, "vector")
+    H = (C.c_void_p * max(n, 1))(*[C.c_void_p(h) for h in handles])
+    L = (C.c_double * max(n, 1))(*[float(x) for x in lams])
+    Rp = (C.c_void_p * max(n, 1))(*[_ptr(t) for t in rhs])
+    Wp = (C.c_void_p * max(n, 1))(*[_ptr(t) for t in ws])
+    o = rr_solve_opts(tol=float(tol), max_iter=int(max_iter), fixed_iters=int(fixed_iters),
+                      precond=PRECOND[precond] if isinstance(precond, str) else int(precond),
+                      rhs_is_b=1 if rhs_is_b else 0, omega=float(omega), persistent=1)
+    infos = (rr_solve_info * max(n, 1))()
+    st = _lib.rr_solve_batched_noalloc(C.c_int32(n), C.cast(H, C.c_void_p), C.cast(L, C.c_void_p),
+                                       C.cast(Rp, C.c_void_p), C.cast(Wp, C.c_void_p), C.byref(o),
+                                       C.cast(infos, C.c_void_p), _stream(stream))
     if st in raise_on:
         raise RRError(st, rr_last_error())
     return st, [{f: getattr(infos[i], f) for f, _ in rr_solve_info._fields_} for i in range(n)]

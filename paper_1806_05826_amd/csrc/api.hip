@@ -1483,7 +1483,7 @@ constexpr int kMaxSets = 8;
 
 rr_status solve_batched_persistent(int nprob, rr_handle* const* hs, const double* lams,
                                    const double* const* rhs, double* const* ws, const rr_solve_opts& op,
-                                   rr_solve_info* infos, hipStream_t caller);
+                                   rr_solve_info* infos, hipStream_t caller, bool noalloc = false);
 
 rr_status solve_batched_impl(int nprob, rr_handle* const* hs, const double* lams,
                              const double* const* rhs, double* const* ws, const rr_solve_opts* o,
@@ -1640,8 +1640,28 @@ rr_status batch_buffers(int dev, int n, BatchBuffers** out) {
 // problems taken longest first.
 rr_status solve_batched_persistent(int nprob, rr_handle* const* hs, const double* lams,
                                    const double* const* rhs, double* const* ws, const rr_solve_opts& op,
-                                   rr_solve_info* infos, hipStream_t caller) {
+                                   rr_solve_info* infos, hipStream_t caller, bool noalloc) {
   const double t0 = now_ms();
+  if (noalloc) {
+    // nothing may be allocated: every work set and coarse factor must exist
+    if (nprob > kStaticProblems)
+      return fail(RR_ERR_INVALID_ARG, "the allocation-free batched solve takes at most 2048 problems");
+    for (int i = 0; i < nprob; ++i) {
+      int k = 0, nl = 0;
+      for (int j = 0; j < i; ++j) k += (hs[j] == hs[i]);
+      if (k > (int)hs[i]->extra_sets.size())
+        return fail(RR_ERR_WORKSPACE, "a handle appears more often than its reserved work sets allow "
+                                      "(rr_setup_opts.reserve_sets)");
+      for (int j = 0; j < nprob; ++j) {
+        if (hs[j] != hs[i]) continue;
+        bool seen = false;
+        for (int q = 0; q < j; ++q) seen = seen || (hs[q] == hs[i] && lams[q] == lams[j]);
+        nl += !seen;
+      }
+      if (op.precond == RR_PRECOND_VCYCLE && nl > (int)hs[i]->slots.size())
+        return fail(RR_ERR_WORKSPACE, "more distinct lambdas on a handle than its lambda_slots");
+    }
+  }
   if (op.krylov != RR_KRYLOV_PCG || op.precision != RR_PREC_F64 || op.smoother != RR_SMOOTHER_POINT)
     return fail(RR_ERR_UNSUPPORTED, "the persistent batched solve runs FP64 PCG with the point smoother");
   if (op.precond != RR_PRECOND_VCYCLE && op.precond != RR_PRECOND_JACOBI)
@@ -1740,8 +1760,20 @@ rr_status solve_batched_persistent(int nprob, rr_handle* const* hs, const double
     cost[i] = (long long)X.nnz + X.N + X.F;
   }
   BatchBuffers* bb = nullptr;
+  BatchScratch scratch;
   std::unique_lock<std::mutex> lk(g_batch_mu);
-  if (res == RR_OK) res = batch_buffers(dev, nprob, &bb);
+  if (res == RR_OK) res = noalloc ? batch_scratch(&scratch) : batch_buffers(dev, nprob, &bb);
+  if (res == RR_OK && noalloc) {
+    // the static scratch stands in for the library's buffers; no graph
+    static BatchBuffers view;
+    view = BatchBuffers{};
+    view.probs = scratch.probs;
+    view.order = scratch.order;
+    view.out = scratch.out;
+    view.queue = scratch.queue;
+    view.cap = scratch.cap;
+    bb = &view;
+  }
   if (res == RR_OK) {
     std::vector<int> order(nprob);
     std::iota(order.begin(), order.end(), 0);
@@ -1752,7 +1784,7 @@ rr_status solve_batched_persistent(int nprob, rr_handle* const* hs, const double
     auto run = [&]() -> rr_status {
       RR_HIP(hipMemcpyAsync(bb->probs, pv.data(), sizeof(BatchProb) * nprob, hipMemcpyHostToDevice, caller));
       RR_HIP(hipMemcpyAsync(bb->order, order.data(), sizeof(int) * nprob, hipMemcpyHostToDevice, caller));
-      if (op.graph) {
+      if (op.graph && !noalloc) {
         if (!bb->exec || bb->graph_n != nprob || bb->graph_grid != grid) {
           if (bb->exec) (void)hipGraphExecDestroy(bb->exec);
           if (bb->graph) (void)hipGraphDestroy(bb->graph);
@@ -2024,6 +2056,24 @@ rr_status rr_solve_batched(int32_t nprob, rr_handle* const* handles, const doubl
   rr_status st = solve_batched_impl(nprob, handles, lambdas, rhs, w, &o, info, (hipStream_t)stream);
   for (int i = 0; st != RR_OK && i < nprob && handles; ++i) st = ws_status(handles[i], st);
   return st;
+}
+
+rr_status rr_solve_batched_noalloc(int32_t nprob, rr_handle* const* handles, const double* lambdas,
+                                   const double* const* rhs, double* const* w, const rr_solve_opts* opts,
+                                   rr_solve_info* info, rr_stream stream) {
+  g_last_error.clear();
+  rr_solve_opts o;
+  RR_TRY(read_opts(opts, &o));
+  if (nprob < 0) return fail(RR_ERR_INVALID_ARG, "nprob must be >= 0");
+  if (nprob == 0) return RR_OK;
+  if (!handles || !lambdas || !rhs || !w) return fail(RR_ERR_INVALID_ARG, "null batch array");
+  if (o.x_ref || o.residual_history)
+    return fail(RR_ERR_INVALID_ARG, "x_ref and residual_history are per-problem buffers: use rr_solve");
+  for (int i = 0; i < nprob; ++i) {
+    if (!handles[i]) return fail(RR_ERR_INVALID_ARG, "null handle in batch");
+    RR_TRY(check_sparse(handles[i]));
+  }
+  return solve_batched_persistent(nprob, handles, lambdas, rhs, w, o, info, (hipStream_t)stream, true);
 }
 
 rr_status rr_apply_operator(rr_handle* h, double lambda, const double* v, double* Av,

@@ -358,6 +358,39 @@ __global__ void k_zero_int(int* p) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
 }
 
+// Scratch of the allocation-free persistent solve: descriptors, order,
+// records and the queue counter of at most kStaticProblems problems, in one
+// file-scope device array per GPU (kept until the process ends).  Host code
+// must not pass the array's name to a kernel: it takes the device address
+// from hipGetSymbolAddress, once per device, with that device current.
+constexpr size_t kStaticProbBytes = (sizeof(BatchProb) * kStaticProblems + 255) / 256 * 256;
+constexpr size_t kStaticOrderBytes = (sizeof(int) * kStaticProblems + 255) / 256 * 256;
+constexpr size_t kStaticOutBytes = (sizeof(BatchOut) * kStaticProblems + 255) / 256 * 256;
+constexpr size_t kStaticScratchBytes = kStaticProbBytes + kStaticOrderBytes + kStaticOutBytes + 256;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+rr_status batch_scratch(BatchScratch* out) {
+  static std::mutex mu;
+  static unsigned char* ptrs[64] = {};
+  int dev = 0;
+  RR_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(RR_ERR_UNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ptrs[dev]) {
+    void* p = nullptr;
+    RR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(RR_ERR_DEVICE, "hipGetSymbolAddress returned no address");
+    ptrs[dev] = static_cast<unsigned char*>(p);
+  }
+  unsigned char* base = ptrs[dev];
+  out->probs = reinterpret_cast<BatchProb*>(base);
+  out->order = reinterpret_cast<int*>(base + kStaticProbBytes);
+  out->out = reinterpret_cast<BatchOut*>(base + kStaticProbBytes + kStaticOrderBytes);
+  out->queue = reinterpret_cast<int*>(base + kStaticProbBytes + kStaticOrderBytes + kStaticOutBytes);
+  out->cap = kStaticProblems;
+  return RR_OK;
+}
+
 void launch_batch_solve(const BatchProb* probs, const int* order, int nprob, int* queue, BatchOut* out,
                         int grid, hipStream_t s) {
   k_zero_int<<<1, 64, 0, s>>>(queue);

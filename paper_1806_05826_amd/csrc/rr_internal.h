@@ -249,6 +249,17 @@ struct BatchOut {
   double relres, true_relres;
   long long t_begin, t_end;   // wall_clock64() around the problem's solve
 };
+// The allocation-free persistent solve's buffers, in the library's static
+// device scratch of this GPU (batch.hip).
+constexpr int kStaticProblems = 2048;
+struct BatchScratch {
+  BatchProb* probs = nullptr;
+  int* order = nullptr;
+  BatchOut* out = nullptr;
+  int* queue = nullptr;
+  int cap = 0;
+};
+
 // Autotuning record of the operator plans (see build_sell_plans): lanes per
 // row of the row pass (div_rows) and the column pass's lane-stream divisor.
 struct SellTuning {
@@ -534,6 +545,7 @@ void free_batch_plan(BatchPlan& bp);
 void launch_batch_solve(const BatchProb* probs, const int* order, int nprob, int* queue, BatchOut* out,
                         int grid, hipStream_t s);
 void launch_batch_gram(const BatchProb* probs, int nprob, const double* const* vin, int grid, hipStream_t s);
+rr_status batch_scratch(BatchScratch* out);
 rr_status lanczos_prototypes(rr_handle* h, int n_proto, int steps, uint64_t seed, double* V, double* ev,
                              hipStream_t s);
 rr_status build_rows(RowPlan& out, const std::vector<int>& ptr, const std::vector<int>& col, int N, int F,
