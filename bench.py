@@ -429,6 +429,18 @@ def batched_uneven_section(rr, torch, dev, log, full=True):
     (st_p, inf_p), pers_ms = timed(lambda: rr.rr_solve_batched(hs, lams, rhs, ws, persistent=True,
                                                                graph=True, **kw))
     log(f"[bench batched] persistent launch: {pers_ms:.1f} ms")
+    hkw = dict(persistent="hybrid", graph=True, chunk=16, **kw)
+    rr.rr_solve_batched(hs, lams, rhs, ws, **hkw)
+    (st_h, inf_h), hyb_ms = timed(lambda: rr.rr_solve_batched(hs, lams, rhs, ws, **hkw))
+    # the caps of the hybrid form (as the library computes them): problems
+    # whose count passed their cap continued on the streams
+    cost = [n + d + z for n, d, z in shapes]
+    grid0 = min(n_problems, torch.cuda.get_device_properties(0).multi_processor_count)
+    bud = 256.0 * sum(cost) / grid0
+    caps = [max(16, int(np.ceil(bud / c))) for c in cost]
+    handed = sum(1 for i, inf in enumerate(inf_h) if inf["iters"] > caps[i])
+    log(f"[bench batched] hybrid launch + stream continuation: {hyb_ms:.1f} ms "
+        f"({handed} problems continued on the streams)")
     rr.rr_solve_batched(hs, lams, rhs, ws, chunk=16, graph=True, **kw)
     (st_g, inf_g), graph_ms = timed(lambda: rr.rr_solve_batched(hs, lams, rhs, ws, chunk=16, graph=True,
                                                                 **kw))
@@ -440,12 +452,14 @@ def batched_uneven_section(rr, torch, dev, log, full=True):
                     for h, lam, b, w in zip(hs, lams, rhs, ws)]
         seq()
         _, seq_ms = timed(seq)
-    ok = st_p == 0 and st_g == 0 and all(i["status"] == 0 for i in inf_p + inf_g)
+    ok = st_p == 0 and st_g == 0 and st_h == 0 and all(i["status"] == 0 for i in inf_p + inf_g + inf_h)
+    it_h = [i["iters"] for i in inf_h]
     it_p = [i["iters"] for i in inf_p]
     it_g = [i["iters"] for i in inf_g]
     # the two paths add in different orders: iteration counts at the natural
     # stop agree within 1 + 2 %
-    within_band = all(abs(a - b) <= 1 + 0.02 * b for a, b in zip(it_p, it_g))
+    within_band = all(abs(a - b) <= 1 + 0.02 * b for a, b in zip(it_p, it_g)) and \
+        all(abs(a - b) <= 1 + 0.02 * b for a, b in zip(it_h, it_g))
     for R in Rs:
         R.close()
     # the persistent launch's schedule: each problem's time on its workgroup
@@ -459,11 +473,13 @@ def batched_uneven_section(rr, torch, dev, log, full=True):
         + ", ".join(f"{busy[i]:.0f} ms ({it_p[i]} it, {shapes[i][0]}x{shapes[i][1]}, "
                     f"{shapes[i][2] / 1e6:.2f} M nnz)" for i in top))
     log(f"[bench batched] {n_problems} problems, {nnz / 1e6:.1f} M nnz (generated {gen_s:.1f} s, "
-        f"setup {setup_s:.1f} s): persistent {pers_ms:.1f} ms, stream+graphs {graph_ms:.1f} ms "
-        f"({graph_ms / pers_ms:.2f}x), all converged {ok}, iterations within 1 + 2 % {within_band}")
+        f"setup {setup_s:.1f} s): persistent {pers_ms:.1f} ms, hybrid {hyb_ms:.1f} ms, stream+graphs "
+        f"{graph_ms:.1f} ms (hybrid {graph_ms / hyb_ms:.2f}x of stream+graphs), all converged {ok}, "
+        f"iterations within 1 + 2 % {within_band}")
     out = {"problems": n_problems, "nnz": nnz, "n_range": list(n_range), "d_range": list(d_range),
            "tol": 1e-8, "setup_s": setup_s, "persistent_ms": pers_ms, "batched_graph_ms": graph_ms,
-           "persistent_vs_graph": graph_ms / pers_ms, "all_converged": ok,
+           "persistent_vs_graph": graph_ms / pers_ms, "hybrid_ms": hyb_ms,
+           "hybrid_vs_graph": graph_ms / hyb_ms, "hybrid_continued": handed, "all_converged": ok,
            "iterations_within_band": within_band, "total_iters": int(sum(it_p)),
            "max_iters": int(max(it_p)), "persistent_busy_fraction": util,
            "persistent_longest_ms": [busy[i] for i in top]}

@@ -81,7 +81,7 @@ class rr_solve_opts(_Versioned):
                 ("krylov", C.c_int32), ("fcg_m", C.c_int32), ("precision", C.c_int32),
                 ("graph", C.c_int32), ("inner_tol", C.c_double), ("smoother", C.c_int32),
                 ("rougher_steps", C.c_int32), ("rougher_jacobi", C.c_int32),
-                ("persistent", C.c_int32)]
+                ("persistent", C.c_int32), ("hybrid_iters", C.c_int32)]
 
 
 class rr_solve_info(C.Structure):
@@ -413,9 +413,11 @@ def rr_solve(h, lam, rhs, w, tol=0.0, max_iter=0, fixed_iters=0, precond="vcycle
 
 def rr_solve_batched(handles, lams, rhs, ws, tol=0.0, max_iter=0, fixed_iters=0, precond="vcycle",
                      rhs_is_b=False, omega=0.0, chunk=0, krylov="pcg", fcg_m=0, smoother="point",
-                     graph=False, persistent=False, stream=None,
+                     graph=False, persistent=False, hybrid_iters=0, stream=None,
                      raise_on=(RR_ERR_INVALID_ARG, RR_ERR_DEVICE, RR_ERR_UNSUPPORTED)):
-    """Batched solves; returns (status, [info dict per problem])."""
+    """Batched solves; returns (status, [info dict per problem]).  persistent:
+    False (work sets on streams), True (one persistent launch) or "hybrid"
+    (the launch with per-problem iteration caps, then the streams)."""
     n = len(handles)
     if not (len(lams) == len(rhs) == len(ws) == n):
         raise ValueError("handles, lams, rhs and ws must have equal lengths")
@@ -431,7 +433,8 @@ def rr_solve_batched(handles, lams, rhs, ws, tol=0.0, max_iter=0, fixed_iters=0,
                       krylov=KRYLOV[krylov] if isinstance(krylov, str) else int(krylov),
                       fcg_m=int(fcg_m), graph=1 if graph else 0,
                       smoother=SMOOTHER[smoother] if isinstance(smoother, str) else int(smoother),
-                      persistent=1 if persistent else 0)
+                      persistent=2 if persistent == "hybrid" else (1 if persistent else 0),
+                      hybrid_iters=int(hybrid_iters))
     infos = (rr_solve_info * max(n, 1))()
     st = _lib.rr_solve_batched(C.c_int32(n), C.cast(H, C.c_void_p), C.cast(L, C.c_void_p),
                                C.cast(Rp, C.c_void_p), C.cast(Wp, C.c_void_p), C.byref(o),

@@ -789,6 +789,13 @@ struct Solve {
   bool skip_check = false;   // no update since the last convergence check
   // precision RR_PREC_F32_CYCLE: the preconditioner's cycle runs in FP32
   bool cycle32 = false;
+  // continuation of a PCG solve left by the persistent kernel: the work set
+  // holds b, x, r and p of iteration `iter`, whose <r,z> is rz
+  struct Resume {
+    int iter;
+    double rz, bb, rr;
+  };
+  const Resume* resume = nullptr;
   rr_status precond(int tag, const StageArgs* st, int* nrz, double* snap_to = nullptr);
 
   rr_status begin();
@@ -889,6 +896,29 @@ rr_status Solve::begin() {
   }
   if (!std::isfinite(omega) || omega < 0.0) return fail(RR_ERR_INVALID_ARG, "omega must be finite and >= 0");
   launch_colnorm_diag(F, h->colnorm, lam, w.D, s);
+  if (resume) {
+    // the next iteration's update takes alpha = rz / <p, A p> and forms e1
+    // from the new r itself; the convergence checks resume at the first update
+    if (op.krylov != RR_KRYLOV_PCG || (kind != PK_VCYCLE && kind != PK_JACOBI) || op.x_ref ||
+        op.residual_history || block || w.X.rw)
+      return fail(RR_ERR_INVALID_ARG, "internal: only FP64 PCG solves with V(1,1) or Jacobi continue");
+    Scalars& hs = *w.sc_host;
+    std::memset(&hs, 0, sizeof(Scalars));
+    hs.bb = resume->bb;
+    hs.tol2 = tol * tol * resume->bb;
+    hs.limit = op.fixed_iters > 0 ? op.fixed_iters : max_iter;
+    hs.fixed = op.fixed_iters;
+    hs.status = RR_ERR_NOT_CONVERGED;
+    hs.rz = hs.rz_next = resume->rz;
+    hs.rr = resume->rr;
+    hs.iter = resume->iter;
+    RR_HIP(hipMemcpyAsync(w.sc, &hs, sizeof(Scalars), hipMemcpyHostToDevice, s));
+    pf.on = false;
+    two_level = kind == PK_VCYCLE;
+    stage = StageArgs{w.sc, w.parts.upd, w.parts.n_vec, nullptr, kind};
+    queued = resume->iter;
+    return RR_OK;
+  }
   if (op.rhs_is_b) {
     launch_gather(w.b, rhs, h->fperm, F, s);
   } else {
@@ -1502,6 +1532,7 @@ rr_status solve_batched_impl(int nprob, rr_handle* const* hs, const double* lams
     if (!hs[i]) return fail(RR_ERR_INVALID_ARG, "null handle in batch");
     RR_TRY(check_sparse(hs[i]));
   }
+  if (op.persistent < 0 || op.persistent > 2) return fail(RR_ERR_INVALID_ARG, "persistent must be 0, 1 or 2");
   if (op.persistent) return solve_batched_persistent(nprob, hs, lams, rhs, ws, op, infos, caller);
   std::vector<int> wave(nprob, 0), set(nprob, 0);
   int nwaves = 0;
@@ -1666,7 +1697,7 @@ rr_status solve_batched_persistent(int nprob, rr_handle* const* hs, const double
     return fail(RR_ERR_UNSUPPORTED, "the persistent batched solve runs FP64 PCG with the point smoother");
   if (op.precond != RR_PRECOND_VCYCLE && op.precond != RR_PRECOND_JACOBI)
     return fail(RR_ERR_UNSUPPORTED, "the persistent batched solve runs the V(1,1) or Jacobi preconditioner");
-  if (op.fixed_iters < 0 || op.max_iter < 0 || op.tol < 0)
+  if (op.fixed_iters < 0 || op.max_iter < 0 || op.tol < 0 || op.hybrid_iters < 0)
     return fail(RR_ERR_INVALID_ARG, "negative option");
   const double tol = op.tol > 0 ? op.tol : 1e-10;
   const int max_iter = op.fixed_iters > 0 ? op.fixed_iters : (op.max_iter > 0 ? op.max_iter : 10000);
@@ -1721,8 +1752,8 @@ rr_status solve_batched_persistent(int nprob, rr_handle* const* hs, const double
     P.max_iter = max_iter;
     P.fixed = op.fixed_iters > 0 ? 1 : 0;
     P.rp = X.row_ptr;
-    P.ci = X.col_idx;
-    P.ri = X.row_idx;
+    P.ci = X.bplan.ci16;
+    P.ri = X.bplan.ri16;
     P.csplit = X.bplan.csplit;
     P.perm = h->perm;
     P.coff = h->coff;
@@ -1781,6 +1812,23 @@ rr_status solve_batched_persistent(int nprob, rr_handle* const* hs, const double
     int ncu = 256;
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     const int grid = std::max(1, std::min(nprob, ncu));
+    if (op.persistent == 2 && !noalloc) {
+      // hybrid: a problem leaves the kernel after cap_i = B / cost_i
+      // iterations, B = hybrid_iters x (total cost / workgroups): the kernel
+      // then ends near the balanced time of hybrid_iters iterations per
+      // problem, and the few problems that need many more continue with
+      // the stream kernels, which spread one problem over the whole GPU.
+      // The caps depend on the sizes only, so results are reproducible.
+      constexpr int kMinCap = 16;
+      const double iters = op.hybrid_iters > 0 ? op.hybrid_iters : 256.0;
+      double tot = 0.0;
+      for (int i = 0; i < nprob; ++i) tot += (double)cost[i];
+      const double B = iters * tot / grid;
+      for (int i = 0; i < nprob; ++i) {
+        const double c = std::ceil(B / std::max<double>(1.0, (double)cost[i]));
+        pv[i].cap = c >= (double)pv[i].max_iter ? 0 : std::max(kMinCap, (int)c);
+      }
+    }
     auto run = [&]() -> rr_status {
       RR_HIP(hipMemcpyAsync(bb->probs, pv.data(), sizeof(BatchProb) * nprob, hipMemcpyHostToDevice, caller));
       RR_HIP(hipMemcpyAsync(bb->order, order.data(), sizeof(int) * nprob, hipMemcpyHostToDevice, caller));
@@ -1817,10 +1865,86 @@ rr_status solve_batched_persistent(int nprob, rr_handle* const* hs, const double
       RR_HIP(hipStreamSynchronize(caller));
       int clock_khz = 0;
       (void)hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev);
+      // problems that left the kernel at their cap: the PCG recurrence goes
+      // on from the work set's x, r, p and the recorded <r,z>, with the
+      // stream kernels (every problem on its work set's stream)
+      std::vector<rr_solve_info> cont(nprob);
+      std::vector<char> continued(nprob, 0);
+      {
+        std::vector<std::unique_ptr<Solve>> sv;
+        std::vector<std::unique_ptr<Solve::Resume>> rs;
+        std::vector<int> idx;
+        for (int i = 0; i < nprob && res == RR_OK; ++i) {
+          if (out[i].status != kStatusYield) continue;
+          rr_handle* h = hs[i];
+          int k = 0;
+          for (int j = 0; j < i; ++j) k += (hs[j] == h);
+          Work* w = nullptr;
+          {
+            MemScope ms(&h->mem);
+            res = get_work_set(h, k, &w);
+          }
+          if (res != RR_OK) break;
+          hipStream_t* st = (k == 0) ? &h->bstream : &w->stream;
+          if (!*st) RR_HIP(hipStreamCreateWithFlags(st, hipStreamNonBlocking));
+          std::unique_ptr<Solve::Resume> r(new Solve::Resume{out[i].iters, out[i].rz, out[i].bb,
+                                                             out[i].relres * out[i].relres * out[i].bb});
+          std::unique_ptr<Solve> x(new Solve());
+          x->h = h;
+          x->ws = w;
+          x->lam = lams[i];
+          x->rhs = rhs[i];
+          x->wout = ws[i];
+          x->op = op;
+          x->op.omega = pv[i].omega;
+          x->s = *st;
+          x->resume = r.get();
+          rs.push_back(std::move(r));
+          sv.push_back(std::move(x));
+          idx.push_back(i);
+        }
+        std::vector<rr_status> st(sv.size(), RR_OK);
+        for (size_t j = 0; j < sv.size(); ++j) {
+          MemScope ms(&sv[j]->h->mem);
+          st[j] = sv[j]->begin();
+        }
+        for (;;) {
+          bool active = false;
+          for (size_t j = 0; j < sv.size(); ++j)
+            if (st[j] == RR_OK && !sv[j]->done) {
+              MemScope ms(&sv[j]->h->mem);
+              st[j] = sv[j]->queue_chunk();
+              active = true;
+            }
+          if (!active) break;
+          for (size_t j = 0; j < sv.size(); ++j)
+            if (st[j] == RR_OK && !sv[j]->done) st[j] = sv[j]->poll();
+        }
+        for (size_t j = 0; j < sv.size(); ++j) {
+          rr_solve_info inf{};
+          if (st[j] == RR_OK) {
+            MemScope ms(&sv[j]->h->mem);
+            (void)sv[j]->finish(&inf);   // its status is in inf
+          } else {
+            (void)hipStreamSynchronize(sv[j]->s);
+            inf.status = st[j];
+          }
+          sv[j]->release();
+          cont[idx[j]] = inf;
+          continued[idx[j]] = 1;
+        }
+      }
       for (int i = 0; i < nprob; ++i) {
-        int st = out[i].status;
-        if (op.fixed_iters > 0 && st == RR_ERR_NOT_CONVERGED && out[i].iters == op.fixed_iters) st = RR_OK;
-        if (infos) {
+        int st = continued[i] ? cont[i].status : out[i].status;
+        if (!continued[i] && op.fixed_iters > 0 && st == RR_ERR_NOT_CONVERGED && out[i].iters == op.fixed_iters)
+          st = RR_OK;
+        const double kernel_ms =
+            clock_khz > 0 ? (double)(out[i].t_end - out[i].t_begin) / clock_khz : now_ms() - t0;
+        if (infos && continued[i]) {
+          rr_solve_info inf = cont[i];
+          inf.ms += kernel_ms;   // the problem's time in the kernel and after it
+          infos[i] = inf;
+        } else if (infos) {
           rr_solve_info inf{};
           inf.status = st;
           inf.iters = out[i].iters;
@@ -1828,14 +1952,18 @@ rr_status solve_batched_persistent(int nprob, rr_handle* const* hs, const double
           inf.relres = out[i].relres;
           inf.true_relres = out[i].true_relres;
           inf.omega = pv[i].omega;
-          // the problem's own time on its workgroup
-          inf.ms = clock_khz > 0 ? (double)(out[i].t_end - out[i].t_begin) / clock_khz : now_ms() - t0;
+          inf.ms = kernel_ms;   // the problem's own time on its workgroup
           inf.fallback_iter = -1;
           infos[i] = inf;
         }
-        if (st != RR_OK && res == RR_OK)
-          res = fail((rr_status)st, st == RR_ERR_NOT_CONVERGED ? "max_iter reached before the tolerance"
-                                                               : "breakdown: <p,Ap> or <r,z> not positive");
+        if (st != RR_OK && res == RR_OK) {
+          if (st == RR_ERR_NOT_CONVERGED)
+            res = fail(RR_ERR_NOT_CONVERGED, "max_iter reached before the tolerance");
+          else if (st == RR_ERR_BREAKDOWN)
+            res = fail(RR_ERR_BREAKDOWN, "breakdown: <p,Ap> or <r,z> not positive");
+          else
+            res = (rr_status)st;   // a continuation's own error; its message is kept
+        }
       }
     }
   }

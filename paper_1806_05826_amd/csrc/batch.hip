@@ -51,8 +51,8 @@ __device__ inline double group_sum(double s) {
 // lane's entries in batches of 16 index loads in flight (one workgroup per
 // CU streams the problem's indexes, so its memory-level parallelism is what
 // bounds it), two accumulators in a fixed order
-template <int G>
-__device__ inline double lane_gather(const int* __restrict__ idx, const double* vec, int a, int z,
+template <int G, typename I>
+__device__ inline double lane_gather(const I* __restrict__ idx, const double* vec, int a, int z,
                                      int sub, int shift) {
   constexpr int B = 16;
   double s0 = 0.0, s1 = 0.0;
@@ -70,7 +70,7 @@ __device__ inline double lane_gather(const int* __restrict__ idx, const double* 
   if (k < z) {   // the rest: fewer than 16 entries, loads issued together
     int i[B];
 #pragma unroll
-    for (int u = 0; u < B; ++u) i[u] = (k + u * G < z) ? idx[k + u * G] : -1;
+    for (int u = 0; u < B; ++u) i[u] = (k + u * G < z) ? (int)idx[k + u * G] : -1;
 #pragma unroll
     for (int u = 0; u < B; ++u)
       if (i[u] >= 0) s0 += vec[i[u] - shift];
@@ -105,7 +105,7 @@ __device__ inline void chunk_cols(const BatchProb& P, const BatchLds& L, int h, 
     const int j = base + tid / G;
     double s = 0.0;
     if (j < c1)
-      s = lane_gather<G>(P.ri, L.U, P.csplit[(size_t)h * F + j], P.csplit[(size_t)(h + 1) * F + j], sub, r0);
+      s = lane_gather<G>(P.ri, L.U, P.csplit[(size_t)h * F + j], P.csplit[(size_t)(h + 1) * F + j], sub, 0);
     s = group_sum<G>(s);
     if (j < c1 && sub == 0) t[j] = (h == 0 ? 0.0 : t[j]) + s;
   }
@@ -250,7 +250,7 @@ __device__ inline void solve_one(const BatchProb& P, BatchLds& L, BatchOut* out)
   }
   bb = wg_sum(bb, L.red);
   int status = RR_ERR_NOT_CONVERGED, it = 0;
-  double rr = bb;
+  double rr = bb, rz_keep = 0.0;
   if (bb == 0.0) {
     status = RR_OK;
   } else {
@@ -259,6 +259,11 @@ __device__ inline void solve_one(const BatchProb& P, BatchLds& L, BatchOut* out)
     __syncthreads();
     if (!finite_pos(rz)) status = RR_ERR_BREAKDOWN;
     while (status == RR_ERR_NOT_CONVERGED && it < P.max_iter) {
+      if (P.cap > 0 && it >= P.cap) {   // the host continues from x, r, p and rz
+        status = kStatusYield;
+        rz_keep = rz;
+        break;
+      }
       // q = A p (t holds X^T X p), <p, q>
       for (int j = tid; j < F; j += kBT) L.V[j] = P.p[j];
       __syncthreads();
@@ -299,6 +304,20 @@ __device__ inline void solve_one(const BatchProb& P, BatchLds& L, BatchOut* out)
       for (int j = tid; j < F; j += kBT) P.p[j] = P.z[j] + beta * P.p[j];
       __syncthreads();
     }
+  }
+  if (status == kStatusYield) {
+    if (tid == 0) {
+      out->status = status;
+      out->iters = it;
+      out->relres = sqrt(rr / bb);
+      out->true_relres = 0.0;
+      out->rz = rz_keep;
+      out->bb = bb;
+      out->t_begin = t_begin;
+      out->t_end = wall_clock64();
+    }
+    __syncthreads();
+    return;
   }
   // w in the caller's order; the true residual ||b - A x||
   __syncthreads();
@@ -440,14 +459,31 @@ rr_status build_batch_plan(BatchPlan& bp, const Sparse& X, hipStream_t s) {
   bp.nchunk = nchunk;
   bp.grow = g;
   for (int c = 0; c < 3; ++c) bp.cls[c] = cls[c];
+  // 16-bit index copies: column indices (< 8192) and row indices less the
+  // first row of their chunk (< 10240), half the index bytes per pass
+  const size_t nz = (size_t)std::max(1, X.nnz);
+  std::vector<int> ci(nz);
+  if (X.nnz) RR_HIP(hipMemcpyAsync(ci.data(), X.col_idx, sizeof(int) * X.nnz, hipMemcpyDeviceToHost, s));
+  RR_HIP(hipStreamSynchronize(s));
+  std::vector<uint16_t> c16(nz, 0), r16(nz, 0);
+  for (int k = 0; k < X.nnz; ++k) {
+    c16[k] = (uint16_t)ci[k];
+    r16[k] = (uint16_t)(ri[k] % kBatchRows);
+  }
   RR_HIP(dmalloc(&bp.csplit, sizeof(int) * cs.size()));
+  RR_HIP(dmalloc(&bp.ci16, sizeof(uint16_t) * nz));
+  RR_HIP(dmalloc(&bp.ri16, sizeof(uint16_t) * nz));
   RR_HIP(hipMemcpyAsync(bp.csplit, cs.data(), sizeof(int) * cs.size(), hipMemcpyHostToDevice, s));
+  RR_HIP(hipMemcpyAsync(bp.ci16, c16.data(), sizeof(uint16_t) * nz, hipMemcpyHostToDevice, s));
+  RR_HIP(hipMemcpyAsync(bp.ri16, r16.data(), sizeof(uint16_t) * nz, hipMemcpyHostToDevice, s));
   RR_HIP(hipStreamSynchronize(s));
   return RR_OK;
 }
 
 void free_batch_plan(BatchPlan& bp) {
   if (bp.csplit) (void)dev_free(bp.csplit);
+  if (bp.ci16) (void)dev_free(bp.ci16);
+  if (bp.ri16) (void)dev_free(bp.ri16);
   bp = BatchPlan{};
 }
 

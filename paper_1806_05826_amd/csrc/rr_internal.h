@@ -233,20 +233,28 @@ struct BatchPlan {
   int nchunk = 0, grow = 1;   // row chunks; lanes per row
   int cls[3] = {0, 0, 0};     // column classes: [0, cls0) 64 lanes, then 16, 4, 1
   int* csplit = nullptr;      // [(nchunk + 1) * F] CSC entry of column j at chunk h's first row
+  uint16_t* ci16 = nullptr;   // [nnz] CSR column indices (F <= 8192)
+  uint16_t* ri16 = nullptr;   // [nnz] CSC row indices less their chunk's first row
 };
 
 // One problem of a persistent batched solve (device descriptor).
 struct BatchProb {
   int N, F, FC, nchunk, grow, kind, rhs_is_b, max_iter, fixed;
+  int cap;   // > 0: leave the kernel at this iteration (the host continues the solve)
   int cls[3];
-  const int *rp, *ci, *ri, *csplit, *perm, *coff, *labels, *fperm, *finv;
+  const int *rp, *csplit, *perm, *coff, *labels, *fperm, *finv;
+  const uint16_t *ci, *ri;
   const double *cscale, *Ainv, *colnorm, *rhs;
   double lam, omega, tol2;
   double *w, *x, *r, *p, *z, *e1, *b, *t;
 };
+// status kStatusYield: the problem left at iteration `iters` with x, r, p
+// in its work set and <r,z> = rz, ||b||^2 = bb
+constexpr int kStatusYield = 101;
 struct BatchOut {
   int status, iters;
   double relres, true_relres;
+  double rz, bb;
   long long t_begin, t_end;   // wall_clock64() around the problem's solve
 };
 // The allocation-free persistent solve's buffers, in the library's static

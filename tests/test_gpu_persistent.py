@@ -10,7 +10,12 @@ oracle's PCG on the same aggregation at equal iteration counts to 1e-10
 once converged, and its iteration count at the natural stop matches
 rr_solve's within the natural-stop band (1 + 2 %).
 Results are bitwise reproducible from launch to launch and with the launch
-replayed from a HIP graph."""
+replayed from a HIP graph.
+
+The hybrid form (persistent = 2) caps every problem's iterations in the
+kernel (at least 16) and continues the same PCG recurrence with the stream
+kernels; with the smallest caps the problems here leave the kernel after 16
+to a few dozen iterations, so the same bars test the hand-over."""
 import numpy as np
 import pytest
 
@@ -56,7 +61,8 @@ def run(rr, probs, Rs, order, lams, **kw):
     rhs = [dev(probs[i][0].y) for i in order]
     ws = [torch.empty(probs[i][0].X.shape[1], dtype=torch.float64, device="cuda") for i in order]
     print(f"[persistent] {len(order)} problems {kw}", flush=True)
-    st, infos = rr.rr_solve_batched([Rs[i].h for i in order], lams, rhs, ws, persistent=True, **kw)
+    kw.setdefault("persistent", True)
+    st, infos = rr.rr_solve_batched([Rs[i].h for i in order], lams, rhs, ws, **kw)
     return st, [host(w) for w in ws], infos
 
 
@@ -180,3 +186,58 @@ def test_persistent_errors(rr, batch):
     st, _ = rr.rr_solve_batched([Rv.h], [1.0], [y], [w], persistent=True, precond="jacobi", raise_on=())
     assert st == 6
     Rv.close()
+
+
+@pytest.mark.parametrize("precond_kind", ["vcycle", "jacobi"])
+def test_hybrid_continues_the_recurrence(rr, batch, precond_kind):
+    probs, Rs = batch
+    order = list(range(len(probs)))
+    lams = [lam for _, lam in probs]
+    # hybrid_iters = 1: caps of 16 to a few dozen iterations, below the
+    # problems' counts
+    kw = dict(precond=precond_kind, persistent="hybrid", hybrid_iters=1, max_iter=5000)
+    st, ws, infos = run(rr, probs, Rs, order, lams, tol=1e-12, **kw)
+    assert st == 0
+    for j, i in enumerate(order):
+        P, lam, inf = probs[i][0], lams[j], infos[j]
+        assert inf["status"] == 0 and inf["relres"] <= 1e-12 and inf["iters"] > 16, (j, inf)
+        assert inf["true_relres"] <= 1e-11, (j, inf)
+        wst = krylov.reference_solution(P.X, P.y, lam)
+        G = (P.X.T @ P.X).toarray() + lam * np.eye(P.X.shape[1])
+        kappa = np.linalg.cond(G)
+        err = np.linalg.norm(ws[j] - wst) / np.linalg.norm(wst)
+        assert err <= 2 * kappa * 1e-12 + 1e-13, (j, err, kappa)
+    # reproducible from call to call
+    st, ws2, infos2 = run(rr, probs, Rs, order, lams, tol=1e-12, **kw)
+    assert st == 0
+    for j in range(len(order)):
+        assert np.array_equal(ws[j], ws2[j]) and infos[j]["iters"] == infos2[j]["iters"]
+    # iteration counts at the natural stop within 1 + 2 % of rr_solve's
+    st, _, infos = run(rr, probs, Rs, order, lams, tol=1e-10, **kw)
+    assert st == 0
+    for j, i in enumerate(order):
+        _, inf1 = Rs[i].solve(lams[j], probs[i][0].y, precond=precond_kind, tol=1e-10, max_iter=5000)
+        assert abs(infos[j]["iters"] - inf1["iters"]) <= 1 + 0.02 * inf1["iters"], (j, inf1, infos[j])
+
+
+def test_hybrid_fixed_iterations_match_oracle_pcg(rr, batch):
+    """At equal iteration counts the hybrid form's iterate (16 iterations in
+    the kernel, the rest on the streams) equals the oracle's V(1,1) PCG
+    iterate to 1e-10."""
+    probs, Rs = batch
+    order = [1, 4, len(probs) - 1]
+    lams = [probs[i][1] for i in order]
+    for i, lam in zip(order, lams):
+        P = probs[i][0]
+        labels = Rs[i].labels().cpu().numpy()
+        fc = int(labels.max()) + 1
+        omega = op.omega_gershgorin(P.X, lam)
+        B, _ = precond.make("vcycle", P.X, lam, labels, fc, omega)
+        b = op.rhs(P.X, P.y)
+        x, inf = krylov.pcg(lambda v: op.apply_A(P.X, lam, v), b, B, tol=1e-13, max_iter=5000)
+        assert inf.status == 0 and inf.iters > 16
+        st, ws, infos = run(rr, probs, Rs, [i], [lam], fixed_iters=inf.iters, precond="vcycle",
+                            persistent="hybrid", hybrid_iters=1)
+        assert st == 0 and infos[0]["iters"] == inf.iters
+        err = np.linalg.norm(ws[0] - x) / np.linalg.norm(x)
+        assert err <= 1e-10, (i, inf.iters, err)
