@@ -368,17 +368,17 @@ typedef struct {
                               graph when graph = 1): a workgroup runs a whole
                               PCG solve, problems taken longest first.  2
                               (hybrid): the same launch, but a problem leaves
-                              it after cap_i = hybrid_iters x (sum of costs /
-                              CUs) /
-                              cost_i iterations (cost = nnz + N + F; at least
-                              16) and its PCG recurrence continues, from the
-                              same x, r, p and <r,z>, with the stream kernels
-                              of rr_solve_batched; the caps depend on the
-                              sizes only, so results are reproducible.  0/1 X
+                              it after cap_i = hybrid_iters x (sum of costs
+                              / CUs) / cost_i iterations (cost = nnz + N + F;
+                              at least 16) and its PCG recurrence continues,
+                              from the same x, r, p and <r,z>, with the
+                              stream kernels of rr_solve_batched; the caps
+                              depend on the sizes only, so results are
+                              reproducible.  0/1 X
                               with at most 8192 features, FP64 PCG, V(1,1)
                               (n_coarse <= 5120) or Jacobi, point smoother,
                               no row weights or least-squares interpolation  */
-  int32_t hybrid_iters;    /* persistent = 2: the 256 of the cap formula; 0 -> 256 */
+  int32_t hybrid_iters;    /* persistent = 2: iterations of the cap formula; 0 -> 512 */
 } rr_solve_opts;
 
 typedef struct {

@@ -1820,7 +1820,7 @@ rr_status solve_batched_persistent(int nprob, rr_handle* const* hs, const double
       // the stream kernels, which spread one problem over the whole GPU.
       // The caps depend on the sizes only, so results are reproducible.
       constexpr int kMinCap = 16;
-      const double iters = op.hybrid_iters > 0 ? op.hybrid_iters : 256.0;
+      const double iters = op.hybrid_iters > 0 ? op.hybrid_iters : 512.0;
       double tot = 0.0;
       for (int i = 0; i < nprob; ++i) tot += (double)cost[i];
       const double B = iters * tot / grid;
