@@ -135,8 +135,11 @@ def valued_operator_section(rr, torch, dev, log, P):
     log(f"[bench valued] FP64-valued operator: {ms * 1e3:.1f} us per application, {gbs:.0f} GB/s "
         f"({gbs / HBM_PEAK_GBS:.3f} of HBM peak)")
     return {"apply_bytes": b, "apply_ms": ms, "apply_gbs": gbs, "frac": gbs / HBM_PEAK_GBS,
-            "kernels": "rr::k_csr (row groups) and the merge-path column pass (rr::k_segsum, "
-                       "rr::k_segfix)"}
+            "kernels": "rr::k_rows_val (row pass: hot values against the LDS slice of v, cold "
+                       "ones gathered), rr::k_sell_val<1> (sliced column gather with the values "
+                       "streamed beside the 16-bit indexes), rr::k_sell_reduce (column sums and "
+                       "epilogue), and the gathers between the caller's and the internal feature "
+                       "order"}
 
 
 def dense_section(rr, torch, dev, log):
@@ -404,7 +407,7 @@ def batched_uneven_section(rr, torch, dev, log, full=True):
     Rs, rhs, ws, lams = [], [], [], []
     for i, (P, lam) in enumerate(batch):
         k = int(min(800, max(8, -(-P.X.shape[1] // 10))))
-        Rs.append(rr.Ridge(P.X, n_clusters=k, seed=9))
+        Rs.append(rr.Ridge(P.X, n_clusters=k, seed=9, autotune=True))
         rhs.append(torch.as_tensor(P.y, dtype=torch.float64, device=dev))
         ws.append(torch.empty(P.X.shape[1], dtype=torch.float64, device=dev))
         lams.append(lam)
@@ -585,11 +588,11 @@ def main():
               f"against the {'oracle' if orc is not None else 'GPU'} reference",
               file=sys.stderr, flush=True)
 
-    def step(profile=False):
+    def step(profile=0):
         out = {}
         for lam in lams:
             st, inf = rr.rr_solve(R.h, lam, y, w, fixed_iters=calib[lam]["iters"],
-                                  precond="vcycle", profile=2 if profile else 0, chunk=16,
+                                  precond="vcycle", profile=profile, chunk=16,
                                   raise_on=(1, 2, 6))
             out[lam] = inf
         return out
@@ -610,24 +613,35 @@ def main():
                     raise_on=(1, 2, 6))
         err_final[lam] = float(torch.linalg.norm(w - wrefs[lam]) / torch.linalg.norm(wrefs[lam]))
     # kernel timing with HIP events recorded by the library on its stream
-    prof = step(profile=True)
+    prof = step(profile=2)
+    prof3 = step(profile=3)
     torch.cuda.synchronize()
+    # inside the timed solves: events around each pass (the gaps between
+    # kernels that the events force included)
     csc_ms = np.mean([prof[l]["csc_avg_ms"] for l in lams])
     csr_ms = np.mean([prof[l]["csr_avg_ms"] for l in lams])
+    # back-to-back launches on the solve's stream (20 each, HIP events around
+    # the batch): the row pass, the column gather, and the column gather with
+    # its reduction; the last two make one application, the kernels'
+    # durations the kernel trace reports
     gcsc_ms = np.mean([prof[l]["csc_gather_avg_ms"] for l in lams])
-    gcsr_ms = np.mean([prof[l]["csr_gather_avg_ms"] for l in lams])
+    gcsr_ms = np.mean([prof3[l]["csr_gather_avg_ms"] for l in lams])
+    col_ms = np.mean([prof3[l]["csc_gather_avg_ms"] for l in lams])
+    apply_ms = gcsr_ms + col_ms
     b_gather = column_gather_bytes(N, F, nnz)
     gbs_gather = b_gather / (gcsc_ms * 1e-3) / 1e9
     b_apply = apply_bytes(N, F, nnz)
-    gbs_op = b_apply / ((csc_ms + csr_ms) * 1e-3) / 1e9
+    gbs_op = b_apply / (apply_ms * 1e-3) / 1e9
     # the HBM-resident case: the same matrix with FP64 values stored both ways
     # (295 MB per application, more than the 256 MB Infinity Cache)
     valued = valued_operator_section(rr, torch, dev, log, P)
     if args.operator_only:
         print(json.dumps({"ms_per_step": ms_per_step, "per_lambda_iters": {str(l): calib[l]["iters"] for l in lams},
-                          "operator": {"apply_bytes": b_apply, "apply_ms": csr_ms + csc_ms,
-                                       "apply_gbs": gbs_op, "row_pass_ms": csr_ms,
-                                       "column_pass_ms": csc_ms, "column_gather_ms": gcsc_ms},
+                          "operator": {"apply_bytes": b_apply, "apply_ms": apply_ms,
+                                       "apply_gbs": gbs_op, "row_pass_ms": gcsr_ms,
+                                       "column_pass_ms": col_ms, "column_gather_ms": gcsc_ms,
+                                       "in_solve_row_pass_ms": csr_ms,
+                                       "in_solve_column_pass_ms": csc_ms},
                           "operator_valued_f64": valued}), flush=True)
         if args.calibrate_copy:
             calibration_copy(torch, dev)
@@ -769,6 +783,13 @@ def main():
     torch.cuda.synchronize()
     learned.update({"pairs": npairs, "train_s": time.perf_counter() - ta, "epochs": 60,
                     "loss_first": hist[0], "loss_last": hist[-1]})
+    # the fit: the network's relative error on its own training pairs (the
+    # targets are the coarse corrections in units of the coarse Jacobi step)
+    outp = torch.empty_like(tgt[:npairs])
+    rr.rr_mlp_forward(R.h, inp[:npairs].contiguous(), outp)
+    Tt = tgt[:npairs].double()
+    rel = (torch.linalg.norm(outp.double() - Tt, dim=1) / torch.linalg.norm(Tt, dim=1)).cpu().numpy()
+    learned["fit_relative_error"] = {"median": float(np.median(rel)), "p90": float(np.quantile(rel, 0.9))}
     def learned_solve():
         kw = dict(precond="learned", krylov="fcg", fcg_m=4)
         st, inf = rr.rr_solve(R.h, 1.0, y, w, tol=1e-10, max_iter=5000, chunk=8, raise_on=(1, 2, 6), **kw)
@@ -857,9 +878,9 @@ def main():
                      "cols_div": sinfo["tuned_cols_div"], "cached": sinfo["tune_cached"]},
         "kmeans_ms": sinfo["kmeans_ms"],
         "kmeans_passes": sinfo["kmeans_iters"],
-        "operator": {"apply_bytes": b_apply, "apply_ms": csr_ms + csc_ms, "apply_gbs": gbs_op,
-                     "row_pass_ms": csr_ms, "row_gather_ms": gcsr_ms,
-                     "column_pass_ms": csc_ms, "column_gather_ms": gcsc_ms},
+        "operator": {"apply_bytes": b_apply, "apply_ms": apply_ms, "apply_gbs": gbs_op,
+                     "row_pass_ms": gcsr_ms, "column_pass_ms": col_ms, "column_gather_ms": gcsc_ms,
+                     "in_solve_row_pass_ms": csr_ms, "in_solve_column_pass_ms": csc_ms},
         "compare_lambda1": compare,
         "batched_lambdas": batched,
         "mixed_precision": mixed,
@@ -874,9 +895,10 @@ def main():
                      "frac": gbs_op / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "one operator application q = X^T (X p) + lambda p (rr::k_rows row "
                                "pass, rr::k_sell<1> column gather, rr::k_sell_reduce<2> column sums "
-                               "and epilogue), HIP events on the solve's stream around each pass "
-                               "inside the timed solves",
-                     "bytes_per_launch": b_apply, "ms_per_launch": csr_ms + csc_ms,
+                               "and epilogue), HIP events on the solve's stream around 20 "
+                               "back-to-back launches of the row pass and of the column pass on "
+                               "each timed solve's final vectors",
+                     "bytes_per_launch": b_apply, "ms_per_launch": apply_ms,
                      "cache_resident": "the pattern's index arrays and vectors (about 60 MB) stay in "
                                        "the 256 MB Infinity Cache between passes; operator_valued_f64 "
                                        "is the HBM-resident case",

@@ -82,8 +82,9 @@ typedef enum {
                               per PCG iteration, SPD for w rho(D^-1 A) < 2)      */
   RR_PRECOND_ADDITIVE = 3, /* z = w D^-1 r + P A_c^-1 P^T r                      */
   RR_PRECOND_LEARNED = 4,  /* the VCYCLE cycle with its coarse solve replaced by
-                              the network: e2 = e1 + P (||r_c|| y), y its output
-                              for [r_c / ||r_c||, log lambda], r_c = P^T rho1
+                              the network: e2 = e1 + P yc, yc_s = ||r_c|| y_s /
+                              (K_ss + lambda), y its output for [r_c / ||r_c||,
+                              log lambda], r_c = P^T rho1, K = P^T X^T X P
                               (rr_mlp_init / rr_mlp_train); no coarse Cholesky
                               is applied; nonlinear, so flexible CG only; after
                               an iteration chunk that reduces ||r|| by less than
@@ -338,7 +339,8 @@ typedef struct {
   int32_t chunk;           /* iterations queued between host checks; 0 -> 8      */
   int32_t profile;         /* 1: time every operator pass with HIP events; 2: also
                               time 20 back-to-back launches of each sliced gather
-                              kernel on the final vectors (0/1 X)                */
+                              kernel on the final vectors; 3: the same with the
+                              column pass's reduction in the second loop       */
   int32_t krylov;          /* rr_krylov: PCG (default) or flexible CG           */
   int32_t fcg_m;           /* flexible CG: directions kept, 1..16; 0 -> 1.
                               Direction i is orthogonalized against the
@@ -400,9 +402,11 @@ typedef struct {
                               its epilogue                                       */
   int32_t csr_launches, csc_launches;
   double csr_gather_avg_ms;/* profile 1: of csr_avg_ms, the sliced gather kernel
-                              (0/1 X; the whole pass for valued X); profile 2:
-                              its back-to-back launch time                       */
-  double csc_gather_avg_ms;/* profile: the same for the column pass              */
+                              (0/1 X; the whole pass for valued X); profile 2
+                              and 3: its back-to-back launch time                */
+  double csc_gather_avg_ms;/* profile 1, 2: the same for the column gather;
+                              profile 3: the back-to-back time of the column
+                              gather with its reduction and epilogue            */
   int32_t fallback_iter;   /* RR_PRECOND_LEARNED: iteration at which the solve
                               fell back to the algebraic cycle, else -1          */
   int32_t pad_;
@@ -689,8 +693,10 @@ rr_status rr_mlp_train(rr_handle* h, const float* in, const float* target, int64
  * PCG solve of (X^T X + lambda I) w = X^T y (device y[N]) records the coarse
  * residual r_c = P^T rho1 that its cycle hands to the coarse solve, after
  * every `every`-th iteration, up to pairs_per_solve of them; pair q gets input
- * [r_c/||r_c||, log lambda] and target A_c(lambda)^-1 r_c / ||r_c|| (the
- * algebraic coarse correction).
+ * [r_c/||r_c||, log lambda] and target D_c A_c(lambda)^-1 r_c / ||r_c||, the
+ * algebraic coarse correction in units of the coarse Jacobi step (D_c =
+ * diag(A_c) = diag(K) + lambda I), so that targets are of order one whatever
+ * the scale of A_c (RR_PRECOND_LEARNED divides the output by D_c again).
  * inputs [n_solves * pairs_per_solve, F_C + 1] and targets [.., F_C] are
  * device FP32; *n_pairs receives the count written (solves that converge
  * early give fewer). */

@@ -29,12 +29,18 @@ __global__ void k_colnorm_binary(int F, const int* col_ptr, double* c) {
   if (j < F) c[j] = (double)(col_ptr[j + 1] - col_ptr[j]);
 }
 
-__global__ void k_colnorm_values(int F, const int* col_ptr, const double* cval, double* c) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+// ||x_j||^2 of a valued X: one wave per column (lane-strided sums, fixed
+// butterfly), so the long columns of a skewed X take no longer than a wave's
+// pass over them
+__global__ __launch_bounds__(kBlock) void k_colnorm_values(int F, const int* col_ptr, const double* cval,
+                                                           double* c) {
+  const int j = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (j >= F) return;
   double s = 0.0;
-  for (int e = col_ptr[j]; e < col_ptr[j + 1]; ++e) s += cval[e] * cval[e];
-  c[j] = s;
+  for (int e = col_ptr[j] + lane; e < col_ptr[j + 1]; e += 64) s += cval[e] * cval[e];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) c[j] = s;
 }
 
 __global__ void k_gather_int(int* dst, const int* src, const int* idx, int n) {
@@ -112,7 +118,7 @@ void free_work(Work& w) {
   if (w.extra) {
     dfree(w.X.sell_csc.part);
     dfree(w.X.csc_plan.head); dfree(w.X.csc_plan.tail);
-    dfree(w.rplan.head); dfree(w.rplan.tail);
+    dfree(w.rplan.head); dfree(w.rplan.tail); dfree(w.rplan.cpart);
   }
   w.graph.reset();
   if (w.graph.ev) (void)hipEventDestroy(w.graph.ev);
@@ -182,10 +188,11 @@ rr_status get_work_set(rr_handle* h, int k, Work** out) {
     w->X.sell_csc.part = nullptr;
     w->X.csc_plan.head = w->X.csc_plan.tail = nullptr;
     w->rplan.head = w->rplan.tail = nullptr;
+    w->rplan.cpart = nullptr;
     RR_TRY(alloc_work(*w, h->X.F, h->X.N, h->FC, h->npartials));
-    if (h->X.binary) {
-      RR_TRY(dalloc(&w->X.sell_csc.part, h->X.sell_csc.nout));
-    } else {
+    if (h->restrict_plan.ncpart > 0) RR_TRY(dalloc(&w->rplan.cpart, h->restrict_plan.ncpart));
+    if (h->X.sliced) RR_TRY(dalloc(&w->X.sell_csc.part, h->X.sell_csc.nout));
+    if (!h->X.binary) {
       RR_TRY(dalloc(&w->X.csc_plan.head, h->X.csc_plan.nblocks));
       RR_TRY(dalloc(&w->X.csc_plan.tail, h->X.csc_plan.nblocks));
     }
@@ -211,7 +218,7 @@ void destroy_handle(rr_handle* h) {
   free_cluster_rows(h->crow);
   dfree(h->colnorm); dfree(h->gersh); dfree(h->fperm); dfree(h->finv);
   dfree(h->labels); dfree(h->centres); dfree(h->csize); dfree(h->cscale);
-  dfree(h->perm); dfree(h->coff); dfree(h->K);
+  dfree(h->perm); dfree(h->cpos); dfree(h->coff); dfree(h->K);
   for (auto& s : h->slots) { dfree(s.L); dfree(s.Ainv); dfree(s.Dinv); }
   dfree(h->boff); dfree(h->bperm); dfree(h->bgram);
   dfree(h->eig_q); dfree(h->eig_v); dfree(h->rw); dfree(h->wxc);
@@ -280,7 +287,7 @@ rr_status setup_impl(const rr_csr* Xin, const rr_setup_opts* o, hipStream_t s, r
   {
     const double tt = now_ms();
     RR_TRY(build_sell_plans(X, s, (o && o->autotune) ? 1 : 0, &h->tuning));
-    RR_TRY(build_batch_plan(X.bplan, X, s));
+    RR_TRY(build_batch_plan(X.bplan, X, s, (o && o->autotune) ? 1 : 0));
     h->tune_ms = now_ms() - tt;
   }
   // column norms and Gershgorin row sums g = X^T (X 1)
@@ -289,7 +296,7 @@ rr_status setup_impl(const rr_csr* Xin, const rr_setup_opts* o, hipStream_t s, r
   if (X.binary)
     k_colnorm_binary<<<cdiv(X.F, kBlock), kBlock, 0, s>>>(X.F, X.col_ptr, h->colnorm);
   else
-    k_colnorm_values<<<cdiv(X.F, kBlock), kBlock, 0, s>>>(X.F, X.col_ptr, X.cval, h->colnorm);
+    k_colnorm_values<<<cdiv(X.F, kBlock / 64), kBlock, 0, s>>>(X.F, X.col_ptr, X.cval, h->colnorm);
   // work buffers for the Gershgorin pass (the full set is allocated below)
   Work& w = h->w;
   const int F = X.F, N = X.N;
@@ -704,14 +711,15 @@ rr_status precond_two_level(rr_handle* h, Work& w, Prof& pf, int tag, int kind, 
   e.p = w.e1;
   e.r = r;
   e.out = w.rho;
+  e.opos = h->cpos;   // rho1 in cluster order: the restriction reads it contiguously
   RR_TRY(op_csc(h, w, pf, tag, EPI_RESID, e, s));
   // e2 = e1 + P A_c^-1 P^T rho1 (learned: the network's coarse correction)
-  launch_restrict(h, w.rplan, w.rho, w.c, done, s);
+  launch_restrict_sorted(h, w.rplan, w.rho, w.c, done, s);
   if (snap) launch_copy_done(snap, w.c, h->FC, done, s);
   if (kind == PK_LEARNED) {
     launch_learned_in(h->FC, w.c, lam, h->mlp.xb, h->mlp_scale, done, s);
     mlp_forward(h->mlp, 1, s);
-    launch_learned_out(h->FC, h->mlp.y, h->mlp_scale, w.yc, done, s);
+    launch_learned_out(h->FC, h->mlp.y, h->mlp_scale, h->K, lam, w.yc, done, s);
   } else {
     launch_gemv(h->FC, sl.Ainv, w.c, w.yc, done, s);
   }
@@ -1185,7 +1193,7 @@ rr_status Solve::finish(rr_solve_info* info) {
     };
     acc(pf.csr, &inf.csr_avg_ms, &inf.csr_gather_avg_ms, &inf.csr_launches);
     acc(pf.csc, &inf.csc_avg_ms, &inf.csc_gather_avg_ms, &inf.csc_launches);
-    if (op.profile == 2 && h->X.binary) {
+    if ((op.profile == 2 || op.profile == 3) && h->X.sliced) {
       // back-to-back launches of each gather kernel on the final x and u = X x
       constexpr int kReps = 20;
       int ti = 0;
@@ -1195,7 +1203,15 @@ rr_status Solve::finish(rr_solve_info* info) {
       RR_HIP(hipEventRecord(ev[0], s));
       for (int i = 0; i < kReps; ++i) launch_rows(w.X.rows, w.x, w.u, nullptr, nullptr, s);
       RR_HIP(hipEventRecord(ev[1], s));
-      for (int i = 0; i < kReps; ++i) launch_sell_gather(w.X.sell_csc, w.u, s);
+      if (op.profile == 3) {   // the column pass with its reduction (q = X^T u + lambda x, <x, q>)
+        Epi e = base_epi(w, lam);
+        e.p = w.x;
+        e.out = w.q;
+        e.partials = w.parts.pq;
+        for (int i = 0; i < kReps; ++i) (void)launch_sell(w.X.sell_csc, w.u, EPI_APPLY_DOT, e, nullptr, s, nullptr, nullptr);
+      } else {
+        for (int i = 0; i < kReps; ++i) launch_sell_gather(w.X.sell_csc, w.u, s);
+      }
       RR_HIP(hipEventRecord(ev[2], s));
       RR_HIP(hipEventSynchronize(ev[2]));
       RR_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
@@ -1238,6 +1254,18 @@ void launch_restrict(const rr_handle* h, const MergePlan& mp, const double* v, d
   } else {
     er.scale = h->cscale;
     launch_segsum(mp, h->coff + 1, h->perm, nullptr, v, EPI_SCALE, er, done, s);
+  }
+}
+
+void launch_restrict_sorted(const rr_handle* h, const MergePlan& mp, const double* v, double* out,
+                            const int* done, hipStream_t s) {
+  Epi er{};
+  er.out = out;
+  if (h->lsw) {
+    launch_segsum(mp, h->coff + 1, nullptr, h->lsw_perm, v, EPI_STORE, er, done, s);
+  } else {
+    er.scale = h->cscale;
+    launch_segsum(mp, h->coff + 1, nullptr, nullptr, v, EPI_SCALE, er, done, s);
   }
 }
 
@@ -2657,7 +2685,7 @@ rr_status collect_pairs(rr_handle* h, bool learned, const double* lambdas, int32
       const int valid = std::min(pairs_per_solve, std::max(0, inf.iters - 1) / every);
       for (int q = 0; q < valid; ++q)
         launch_gemv(FC, sv.sl->Ainv, snap + (size_t)q * FC, ainv_rc + (size_t)q * FC, nullptr, s);
-      launch_make_pairs(FC, valid, snap, ainv_rc, lambdas[i], inputs + (size_t)written * (FC + 1),
+      launch_make_pairs(FC, valid, snap, ainv_rc, h->K, lambdas[i], inputs + (size_t)written * (FC + 1),
                         targets + (size_t)written * FC, s);
       written += valid;
       if (hipStreamSynchronize(s) != hipSuccess) res = fail(RR_ERR_DEVICE, "pair construction");

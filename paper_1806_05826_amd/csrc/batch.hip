@@ -18,8 +18,11 @@
 // is bitwise reproducible.  Between operator applications the coarse
 // residual and correction live in the chunk buffer.
 #include <algorithm>
+#include <cstring>
+#include <map>
 #include <mutex>
 #include <numeric>
+#include <string>
 
 #include "rr_device.h"
 
@@ -420,9 +423,50 @@ void launch_batch_gram(const BatchProb* probs, int nprob, const double* const* v
   k_batch_gram<<<grid, kBT, 0, s>>>(probs, nprob, vin);
 }
 
+namespace {
+// lanes per row of the persistent solve, tuned per shape bucket and device
+std::mutex g_btune_mu;
+std::map<std::string, int> g_btune;
+
+// Mean time of one operator application of this problem on one workgroup
+// (the persistent solve's situation) with `grow` lanes per row.
+rr_status time_batch_gram(const BatchPlan& bp, const Sparse& X, int grow, BatchProb* d_prob,
+                          const double* const* d_vin, double* t, hipStream_t s, float* ms) {
+  BatchProb P;
+  std::memset(&P, 0, sizeof(P));
+  P.N = X.N;
+  P.F = X.F;
+  P.nchunk = bp.nchunk;
+  P.grow = grow;
+  for (int c = 0; c < 3; ++c) P.cls[c] = bp.cls[c];
+  P.rp = X.row_ptr;
+  P.ci = bp.ci16;
+  P.ri = bp.ri16;
+  P.csplit = bp.csplit;
+  P.t = t;
+  RR_HIP(hipMemcpyAsync(d_prob, &P, sizeof(P), hipMemcpyHostToDevice, s));
+  hipEvent_t a, b;
+  RR_HIP(hipEventCreate(&a));
+  RR_HIP(hipEventCreate(&b));
+  constexpr int kReps = 3;
+  launch_batch_gram(d_prob, 1, d_vin, 1, s);
+  RR_HIP(hipEventRecord(a, s));
+  for (int i = 0; i < kReps; ++i) launch_batch_gram(d_prob, 1, d_vin, 1, s);
+  RR_HIP(hipEventRecord(b, s));
+  RR_HIP(hipEventSynchronize(b));
+  RR_HIP(hipEventElapsedTime(ms, a, b));
+  *ms /= kReps;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return RR_OK;
+}
+}  // namespace
+
 // Setup of a 0/1 handle with F <= kBatchFMax: the CSC entry offsets of every
 // column at every row-chunk boundary and the column classes by length.
-rr_status build_batch_plan(BatchPlan& bp, const Sparse& X, hipStream_t s) {
+// With autotune, the lanes per row come from timing half, once and twice the
+// default on one workgroup (cached per shape bucket and device).
+rr_status build_batch_plan(BatchPlan& bp, const Sparse& X, hipStream_t s, int autotune) {
   free_batch_plan(bp);
   if (!X.binary || X.F > kBatchFMax || X.F == 0) return RR_OK;
   const int N = X.N, F = X.F;
@@ -477,6 +521,58 @@ rr_status build_batch_plan(BatchPlan& bp, const Sparse& X, hipStream_t s) {
   RR_HIP(hipMemcpyAsync(bp.ci16, c16.data(), sizeof(uint16_t) * nz, hipMemcpyHostToDevice, s));
   RR_HIP(hipMemcpyAsync(bp.ri16, r16.data(), sizeof(uint16_t) * nz, hipMemcpyHostToDevice, s));
   RR_HIP(hipStreamSynchronize(s));
+  if (!autotune || X.nnz == 0) return RR_OK;
+  int dev = 0;
+  RR_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  RR_HIP(hipGetDeviceProperties(&prop, dev));
+  auto lg = [](long long v) { int b = 0; while ((1LL << b) < v) ++b; return b; };
+  const std::string key = std::string(prop.gcnArchName) + ":" + std::to_string(lg(N)) + ":" +
+                          std::to_string(lg(F)) + ":" + std::to_string(lg(X.nnz));
+  {
+    std::lock_guard<std::mutex> lk(g_btune_mu);
+    auto it = g_btune.find(key);
+    if (it != g_btune.end()) {
+      bp.grow = it->second;
+      bp.tuned = 2;
+      return RR_OK;
+    }
+  }
+  BatchProb* d_prob = nullptr;
+  double *v = nullptr, *t = nullptr;
+  const double** d_vin = nullptr;
+  rr_status st = RR_OK;
+  if (dmalloc(&d_prob, sizeof(BatchProb)) != hipSuccess || dmalloc(&v, sizeof(double) * F) != hipSuccess ||
+      dmalloc(&t, sizeof(double) * F) != hipSuccess || dmalloc(&d_vin, sizeof(double*)) != hipSuccess)
+    st = fail(RR_ERR_DEVICE, "out of device memory for the batched plan's tuning");
+  if (st == RR_OK) {
+    launch_fill(v, 1.0, F, s);
+    const double* hv = v;
+    if (hipMemcpyAsync(d_vin, &hv, sizeof(double*), hipMemcpyHostToDevice, s) != hipSuccess)
+      st = fail(RR_ERR_DEVICE, "tuning copy failed");
+  }
+  int best = g;
+  float best_ms = 1e30f;
+  for (int cand : {g, std::max(1, g / 2), std::min(64, 2 * g)}) {
+    if (st != RR_OK) break;
+    float ms = 0.f;
+    st = time_batch_gram(bp, X, cand, d_prob, d_vin, t, s, &ms);
+    // another value must win by 3 % over the default
+    if (st == RR_OK && (cand == g ? ms < best_ms : ms < 0.97f * best_ms)) {
+      best_ms = ms;
+      best = cand;
+    }
+  }
+  (void)hipStreamSynchronize(s);
+  (void)dev_free(d_prob);
+  (void)dev_free(v);
+  (void)dev_free(t);
+  (void)dev_free(d_vin);
+  RR_TRY(st);
+  bp.grow = best;
+  bp.tuned = 1;
+  std::lock_guard<std::mutex> lk(g_btune_mu);
+  g_btune[key] = best;
   return RR_OK;
 }
 

@@ -596,6 +596,11 @@ rr_status run_kmeans(rr_handle* h, int k, uint64_t seed, int max_iter, hipStream
 // Finalise an aggregation held in h->labels (or copied from labels_in):
 // drop empty clusters, renumber, sizes, scales, the cluster-sorted
 // permutation and its restriction plan.
+__global__ void k_inverse_perm(const int* __restrict__ perm, int F, int* __restrict__ inv) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < F) inv[perm[k]] = k;
+}
+
 rr_status set_labels(rr_handle* h, const int* labels_in, int nlab, hipStream_t s) {
   const int F = h->X.F;
   int* bad = nullptr;
@@ -646,6 +651,9 @@ rr_status set_labels(rr_handle* h, const int* labels_in, int nlab, hipStream_t s
   RR_HIP(dmalloc(&tmp, std::max<size_t>(tmp_bytes, 1)));
   RR_HIP(rocprim::radix_sort_pairs(tmp, tmp_bytes, h->labels, keys_out, iota, h->perm, (size_t)F, 0u, end_bit, s));
   k_offsets<<<cdiv(hfc + 1, kBlock), kBlock, 0, s>>>(keys_out, F, hfc, h->coff);
+  // cpos: the inverse of perm (where each feature sits in cluster order)
+  RR_HIP(dmalloc(&h->cpos, sizeof(int) * F));
+  k_inverse_perm<<<cdiv(F, kBlock), kBlock, 0, s>>>(h->perm, F, h->cpos);
   RR_HIP(hipStreamSynchronize(s));
   RR_HIP(dev_free(tmp));
   RR_HIP(dev_free(keys_out));

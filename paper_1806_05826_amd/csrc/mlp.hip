@@ -297,24 +297,29 @@ void launch_learned_in(int FC, const double* c, double lam, uint16_t* xb, double
   k_learned_in<<<1, kBlock, 0, s>>>(FC, c, log(lam), xb, scale, done);
 }
 
-// yc = ||c|| y (FP64)
+// yc_i = ||c|| y_i / (K_ii + lambda) (FP64): the network predicts the coarse
+// correction in units of the coarse Jacobi step, so that its outputs are of
+// order one whatever the scale of A_c
 __global__ void k_learned_out(int FC, const float* __restrict__ y, const double* __restrict__ scale,
-                              double* __restrict__ yc, const int* done) {
+                              const double* __restrict__ K, double lam, double* __restrict__ yc,
+                              const int* done) {
   if (is_done(done)) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < FC) yc[i] = *scale * (double)y[i];
+  if (i < FC) yc[i] = *scale * (double)y[i] / (K[(size_t)i * FC + i] + lam);
 }
 
-void launch_learned_out(int FC, const float* y, const double* scale, double* yc, const int* done,
-                        hipStream_t s) {
-  k_learned_out<<<cdiv(FC, kBlock), kBlock, 0, s>>>(FC, y, scale, yc, done);
+void launch_learned_out(int FC, const float* y, const double* scale, const double* K, double lam, double* yc,
+                        const int* done, hipStream_t s) {
+  k_learned_out<<<cdiv(FC, kBlock), kBlock, 0, s>>>(FC, y, scale, K, lam, yc, done);
 }
 
 // Training pairs from coarse residual snapshots: for pair q with r_c = S[q],
-// input [r_c/||r_c||, log lambda] and target A_c^-1 r_c / ||r_c||, where
+// input [r_c/||r_c||, log lambda] and target (K_ii + lambda) (A_c^-1 r_c)_i /
+// ||r_c|| (the coarse correction in units of the coarse Jacobi step), where
 // Ainv_rc[q] = A_c^-1 r_c has been formed already (one block per pair).
 __global__ __launch_bounds__(kBlock) void k_make_pairs(int FC, const double* __restrict__ S,
                                                        const double* __restrict__ Ainv_rc,
+                                                       const double* __restrict__ K, double lam,
                                                        double loglam, float* __restrict__ inputs,
                                                        float* __restrict__ targets) {
   const int q = blockIdx.x;
@@ -328,15 +333,15 @@ __global__ __launch_bounds__(kBlock) void k_make_pairs(int FC, const double* __r
   float* tg = targets + (size_t)q * FC;
   for (int i = threadIdx.x; i < FC; i += kBlock) {
     in[i] = (float)(rc[i] * inv);
-    tg[i] = (float)(Ainv_rc[(size_t)q * FC + i] * inv);
+    tg[i] = (float)(Ainv_rc[(size_t)q * FC + i] * inv * (K[(size_t)i * FC + i] + lam));
   }
   if (threadIdx.x == 0) in[FC] = (float)loglam;
 }
 
-void launch_make_pairs(int FC, int npairs, const double* S, const double* Ainv_rc, double lam,
+void launch_make_pairs(int FC, int npairs, const double* S, const double* Ainv_rc, const double* K, double lam,
                        float* inputs, float* targets, hipStream_t s) {
   if (npairs > 0)
-    k_make_pairs<<<npairs, kBlock, 0, s>>>(FC, S, Ainv_rc, log(lam), inputs, targets);
+    k_make_pairs<<<npairs, kBlock, 0, s>>>(FC, S, Ainv_rc, K, lam, log(lam), inputs, targets);
 }
 
 }  // namespace rr

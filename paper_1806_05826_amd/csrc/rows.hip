@@ -21,6 +21,10 @@
 // per wave; padding = W, the zero entry) and cold int32 feature indexes
 // (the same interleave, 16-byte loads; padding = -1).  The lanes of a row add
 // their sums in a fixed butterfly, so results are bitwise reproducible.
+//
+// A valued X streams each entry's FP64 value beside its index (hval, cval:
+// the same positions, 0 for padding; 16-byte loads of two values), so the
+// LDS slice serves the value-weighted sums as it serves the 0/1 ones.
 #include <algorithm>
 #include <climits>
 
@@ -125,6 +129,99 @@ __global__ __launch_bounds__(kSliceBlock) void k_rows(int nlayer, int N, const i
   }
 }
 
+// u_i = sum over row i of X_ij v_j for a valued X: the value streams are read
+// beside the index streams (batches of 4 hot and 2 cold index loads with
+// their values, all issued before the sums).
+constexpr int kHotBatchV = 4;
+constexpr int kColdBatchV = 2;
+
+template <int L>
+__global__ __launch_bounds__(kSliceBlock) void k_rows_val(int nlayer, int N, const int4* __restrict__ lay,
+                                                          const uint16_t* __restrict__ hidx,
+                                                          const double* __restrict__ hval,
+                                                          const int* __restrict__ cidx,
+                                                          const double* __restrict__ cval,
+                                                          const double* __restrict__ v, int F,
+                                                          double* __restrict__ u,
+                                                          const double* __restrict__ scale, const int* done,
+                                                          StageArgs stage) {
+  if (is_done(done)) return;
+  __shared__ __align__(16) double vs[kSliceRows + 1];
+  constexpr unsigned kPad = (unsigned)kSliceRows | ((unsigned)kSliceRows << 16);
+  const int lane = threadIdx.x & 63;
+  const int nw = gridDim.x * kSliceWaves;
+  int c = blockIdx.x * kSliceWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  fill_slice(vs, v, min(kSliceRows, F));
+  if (stage.sc) {   // convergence check of the preceding x/r update, under the slice copy
+    __shared__ double red_s[kSliceWaves];
+    double rz_unused;
+    if (stage_update<kSliceBlock>(stage, red_s, rz_unused)) {
+      __builtin_amdgcn_s_waitcnt(0);   // the slice copy lands before the workgroup ends
+      return;
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  const double2 z2 = make_double2(0.0, 0.0);
+  for (; c < nlayer; c += nw) {
+    const int4 d = lay[c];
+    // entry k of this lane: index at offset 256 (k / 4) + 4 lane + k % 4 of
+    // the layer's stream, value at the same offset of the value stream
+    const uint2* hp = reinterpret_cast<const uint2*>(hidx + d.x) + lane;
+    const double2* hv = reinterpret_cast<const double2*>(hval + d.x) + 2 * lane;
+    const int4* cp = reinterpret_cast<const int4*>(cidx + d.z) + lane;
+    const double2* cv = reinterpret_cast<const double2*>(cval + d.z) + 2 * lane;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int g = 0; g < d.y; g += 4 * kHotBatchV) {
+      uint2 q[kHotBatchV];
+      double2 w0[kHotBatchV], w1[kHotBatchV];
+#pragma unroll
+      for (int j = 0; j < kHotBatchV; ++j) {
+        const int G = g / 4 + j;
+        const bool in = 4 * G < d.y;
+        q[j] = in ? hp[G * 64] : make_uint2(kPad, kPad);
+        w0[j] = in ? hv[G * 128] : z2;
+        w1[j] = in ? hv[G * 128 + 1] : z2;
+      }
+#pragma unroll
+      for (int j = 0; j < kHotBatchV; ++j) {
+        a0 += vs[q[j].x & 0xffffu] * w0[j].x;
+        a1 += vs[q[j].x >> 16] * w0[j].y;
+        a2 += vs[q[j].y & 0xffffu] * w1[j].x;
+        a3 += vs[q[j].y >> 16] * w1[j].y;
+      }
+    }
+    double cs = 0.0;
+    for (int g = 0; g < d.w; g += 4 * kColdBatchV) {
+      int4 q[kColdBatchV];
+      double2 w0[kColdBatchV], w1[kColdBatchV];
+#pragma unroll
+      for (int j = 0; j < kColdBatchV; ++j) {
+        const int G = g / 4 + j;
+        const bool in = 4 * G < d.w;
+        q[j] = in ? cp[G * 64] : make_int4(-1, -1, -1, -1);
+        w0[j] = in ? cv[G * 128] : z2;
+        w1[j] = in ? cv[G * 128 + 1] : z2;
+      }
+      double x[4 * kColdBatchV];
+#pragma unroll
+      for (int j = 0; j < kColdBatchV; ++j) {
+        x[4 * j + 0] = q[j].x >= 0 ? v[q[j].x] * w0[j].x : 0.0;
+        x[4 * j + 1] = q[j].y >= 0 ? v[q[j].y] * w0[j].y : 0.0;
+        x[4 * j + 2] = q[j].z >= 0 ? v[q[j].z] * w1[j].x : 0.0;
+        x[4 * j + 3] = q[j].w >= 0 ? v[q[j].w] * w1[j].y : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < 4 * kColdBatchV; ++k) cs += x[k];
+    }
+    double sum = ((a0 + a1) + (a2 + a3)) + cs;
+    if constexpr (L >= 2) sum += __shfl_xor(sum, 1, 64);
+    if constexpr (L >= 4) sum += __shfl_xor(sum, 2, 64);
+    const int row = c * (64 / L) + lane / L;
+    if ((lane & (L - 1)) == 0 && row < N) u[row] = scale ? sum * scale[row] : sum;
+  }
+}
+
 template <typename T>
 static void rows_dispatch(const RowPlan& rp, const T* v, T* u, const double* scale, const int* done,
                           hipStream_t s, const StageArgs& st) {
@@ -144,11 +241,31 @@ static void rows_dispatch(const RowPlan& rp, const T* v, T* u, const double* sca
   }
 }
 
+static void rows_val_dispatch(const RowPlan& rp, const double* v, double* u, const double* scale,
+                              const int* done, hipStream_t s, const StageArgs& st) {
+  switch (rp.L) {
+    case 1:
+      k_rows_val<1><<<rp.nblk, kSliceBlock, 0, s>>>(rp.nlayer, rp.N, rp.layer, rp.hidx, rp.hval, rp.cidx,
+                                                    rp.cval, v, rp.F, u, scale, done, st);
+      break;
+    case 2:
+      k_rows_val<2><<<rp.nblk, kSliceBlock, 0, s>>>(rp.nlayer, rp.N, rp.layer, rp.hidx, rp.hval, rp.cidx,
+                                                    rp.cval, v, rp.F, u, scale, done, st);
+      break;
+    default:
+      k_rows_val<4><<<rp.nblk, kSliceBlock, 0, s>>>(rp.nlayer, rp.N, rp.layer, rp.hidx, rp.hval, rp.cidx,
+                                                    rp.cval, v, rp.F, u, scale, done, st);
+      break;
+  }
+}
+
 void launch_rows(const RowPlan& rp, const double* v, double* u, const double* scale, const int* done,
                  hipStream_t s, const StageArgs* stage) {
   StageArgs st{};
   if (stage) st = *stage;
-  if (rp.nblk > 0)
+  if (rp.nblk > 0 && rp.hval)
+    rows_val_dispatch(rp, v, u, scale, done, s, st);
+  else if (rp.nblk > 0)
     rows_dispatch<double>(rp, v, u, scale, done, s, st);
   else if (stage)
     launch_stage_update(*stage, s);
@@ -168,13 +285,15 @@ void free_rows(RowPlan& rp) {
   if (rp.layer) (void)dev_free(rp.layer);
   if (rp.hidx) (void)dev_free(rp.hidx);
   if (rp.cidx) (void)dev_free(rp.cidx);
+  if (rp.hval) (void)dev_free(rp.hval);
+  if (rp.cval) (void)dev_free(rp.cval);
   rp = RowPlan{};
 }
 
 // Host-side construction from the CSR (columns sorted inside every row, in
 // the popularity order).  Setup only.
 rr_status build_rows(RowPlan& out, const std::vector<int>& ptr, const std::vector<int>& col, int N, int F,
-                     int num_cu, int L, hipStream_t s) {
+                     int num_cu, int L, hipStream_t s, const std::vector<double>* val) {
   free_rows(out);
   if (L != 1 && L != 2 && L != 4) return fail(RR_ERR_DEVICE, "internal: lanes per row must be 1, 2 or 4");
   const int W = kSliceRows;
@@ -183,6 +302,7 @@ rr_status build_rows(RowPlan& out, const std::vector<int>& ptr, const std::vecto
   std::vector<int4> lay(std::max(1, nlayer));
   std::vector<uint16_t> hidx;
   std::vector<int> cidx;
+  std::vector<double> hv, cv;   // valued X: values at the indexes' positions
   long long hot = 0, cold = 0;
   std::vector<int> hc(64), cc(64);
   for (int c = 0; c < nlayer; ++c) {
@@ -212,6 +332,10 @@ rr_status build_rows(RowPlan& out, const std::vector<int>& ptr, const std::vecto
     lay[c] = make_int4((int)hoff, hm, (int)coff, cm);
     hidx.resize(hoff + (size_t)hm * 64, (uint16_t)W);
     cidx.resize(coff + (size_t)cm * 64, -1);
+    if (val) {
+      hv.resize(hidx.size(), 0.0);
+      cv.resize(cidx.size(), 0.0);
+    }
     for (int l = 0; l < 64; ++l) {
       const int i = c * rpl + l / L, sub = l % L;
       if (i >= N) continue;
@@ -220,13 +344,17 @@ rr_status build_rows(RowPlan& out, const std::vector<int>& ptr, const std::vecto
         const int j = col[k];
         if (j < W) {
           if (h % L == sub) {
-            hidx[hoff + (size_t)(hs / 4) * 256 + 4 * l + hs % 4] = (uint16_t)j;
+            const size_t at = hoff + (size_t)(hs / 4) * 256 + 4 * l + hs % 4;
+            hidx[at] = (uint16_t)j;
+            if (val) hv[at] = (*val)[k];
             ++hs;
           }
           ++h;
         } else {
           if (k2 % L == sub) {
-            cidx[coff + (size_t)(cs / 4) * 256 + 4 * l + cs % 4] = j;
+            const size_t at = coff + (size_t)(cs / 4) * 256 + 4 * l + cs % 4;
+            cidx[at] = j;
+            if (val) cv[at] = (*val)[k];
             ++cs;
           }
           ++k2;
@@ -249,6 +377,10 @@ rr_status build_rows(RowPlan& out, const std::vector<int>& ptr, const std::vecto
     if (q != -1 && (q < W || q >= F)) return fail(RR_ERR_DEVICE, "internal: row plan cold index out of range");
   if (hidx.empty()) hidx.resize(256, (uint16_t)W);
   if (cidx.empty()) cidx.resize(256, -1);
+  if (val) {
+    hv.resize(hidx.size(), 0.0);
+    cv.resize(cidx.size(), 0.0);
+  }
   out.N = N;
   out.F = F;
   out.W = W;
@@ -264,6 +396,13 @@ rr_status build_rows(RowPlan& out, const std::vector<int>& ptr, const std::vecto
   RR_HIP(hipMemcpyAsync(out.layer, lay.data(), sizeof(int4) * lay.size(), hipMemcpyHostToDevice, s));
   RR_HIP(hipMemcpyAsync(out.hidx, hidx.data(), sizeof(uint16_t) * hidx.size(), hipMemcpyHostToDevice, s));
   RR_HIP(hipMemcpyAsync(out.cidx, cidx.data(), sizeof(int) * cidx.size(), hipMemcpyHostToDevice, s));
+  if (val) {
+    RR_HIP(dmalloc(&out.hval, sizeof(double) * hv.size()));
+    RR_HIP(dmalloc(&out.cval, sizeof(double) * cv.size()));
+    RR_HIP(hipMemcpyAsync(out.hval, hv.data(), sizeof(double) * hv.size(), hipMemcpyHostToDevice, s));
+    RR_HIP(hipMemcpyAsync(out.cval, cv.data(), sizeof(double) * cv.size(), hipMemcpyHostToDevice, s));
+    out.idx_bytes += (long long)(hv.size() + cv.size()) * 8;
+  }
   RR_HIP(hipStreamSynchronize(s));
   return RR_OK;
 }

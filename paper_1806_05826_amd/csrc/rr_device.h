@@ -137,7 +137,7 @@ __device__ inline void seg_finish(int s, double t, const Epi& e, double& dot) {
     e.out[s] = q;
     dot += ps * q;
   } else if constexpr (MODE == EPI_RESID) {
-    e.out[s] = e.r[s] - (t + e.lam * e.p[s]);
+    e.out[e.opos ? e.opos[s] : s] = e.r[s] - (t + e.lam * e.p[s]);
   } else if constexpr (MODE == EPI_POST) {
     const double e2 = e.p[s];
     const double rs = e.r[s];

@@ -137,6 +137,7 @@ struct Epi {
   const int* labels;     // EPI_POST_P: cluster of every feature,
   const double* cscale;  // the prolongation's 1/sqrt(n_s)
   const double* yc;      // and the coarse correction
+  const int* opos;       // EPI_RESID: store segment s at opos[s] (cluster order), or at s
 };
 
 // Single-precision vectors of an inner solve of iterative refinement.
@@ -183,12 +184,14 @@ struct MergePlan {
   int4* span = nullptr;    // device [nspan]: (segment, first block, last block, 0)
   double* head = nullptr;  // device [nblocks]
   double* tail = nullptr;  // device [nblocks]
-  // one-kernel form for sums without a dot product (the restriction, built
-  // by build_chunk_plan): segments of up to kWaveSeg entries take one wave
-  // each, longer ones a whole block, (segment, first, end, 0) each
-  int nwitem = 0, nbitem = 0;
+  // wave-item form for sums without a dot product (the restriction, built
+  // by build_chunk_plan): witem (segment, first, end, chunk slot or -1), a
+  // segment of up to kWaveSeg entries per item, longer ones in chunks whose
+  // sums go to cpart; fitem (segment, first slot, chunks, 0) finishes those
+  int nwitem = 0, nfitem = 0, ncpart = 0;
   int4* witem = nullptr;
-  int4* bitem = nullptr;
+  int4* fitem = nullptr;
+  double* cpart = nullptr;   // device [ncpart] (each work set holds its own)
 };
 
 // Sliced-ELL plan of a segmented gather-sum out_s = sum_{e in s} v[g_e]
@@ -210,6 +213,7 @@ struct SellPlan {
   int* lseg = nullptr;        // [nlong] segments of more than 16 pieces (added by a wave each)
   int nlong = 0;
   double* part = nullptr;     // [nout] partial sums
+  double* val = nullptr;      // valued X: the entries' values beside idx (0 for padding)
 };
 
 // Row pass of 0/1 X without partial sums (rows.hip): layer c of 64 / L rows
@@ -221,6 +225,8 @@ struct RowPlan {
   int4* layer = nullptr;      // [nlayer] (hot offset, hot length, cold offset, cold length) per lane
   uint16_t* hidx = nullptr;   // hot lane streams (W = the zero entry)
   int* cidx = nullptr;        // cold lane streams (-1 = padding)
+  double* hval = nullptr;     // valued X: the entries' values beside hidx (0 for padding)
+  double* cval = nullptr;     // valued X: the entries' values beside cidx (0 for padding)
 };
 
 // Persistent batched solver (batch.hip): problems of at most kBatchFMax
@@ -235,6 +241,7 @@ struct BatchPlan {
   int* csplit = nullptr;      // [(nchunk + 1) * F] CSC entry of column j at chunk h's first row
   uint16_t* ci16 = nullptr;   // [nnz] CSR column indices (F <= 8192)
   uint16_t* ri16 = nullptr;   // [nnz] CSC row indices less their chunk's first row
+  int tuned = 0;              // grow: 0 from the rows' length, 1 timed here, 2 from the tuning cache
 };
 
 // One problem of a persistent batched solve (device descriptor).
@@ -293,6 +300,7 @@ struct Sparse {
   RowPlan rows;             // u = X v   (0/1 X)
   SellPlan sell_csc;        // t = X^T u (0/1 X)
   BatchPlan bplan;          // persistent batched solver (0/1 X, F <= kBatchFMax)
+  bool sliced = false;      // rows and sell_csc built: the operator runs the sliced passes
   int num_cu = 256;
 };
 
@@ -435,6 +443,7 @@ struct rr_handle {
   int* csize = nullptr;         // [FC]
   double* cscale = nullptr;     // [FC] 1/sqrt(n_s)
   int* perm = nullptr;          // [F] features sorted by cluster (stable)
+  int* cpos = nullptr;          // [F] inverse of perm: feature j sits at cpos[j]
   int* coff = nullptr;          // [FC+1] cluster offsets into perm
   rr::MergePlan restrict_plan;  // segments = clusters over perm
   ClusterRows crow;             // label table for the V(1,1) second row pass
@@ -548,7 +557,7 @@ void launch_rows(const RowPlan& rp, const double* v, double* u, const double* sc
 void launch_rows32(const RowPlan& rp, const float* v, float* u, const int* done, hipStream_t s,
                    const StageArgs* stage = nullptr);
 void free_rows(RowPlan& rp);
-rr_status build_batch_plan(BatchPlan& bp, const Sparse& X, hipStream_t s);
+rr_status build_batch_plan(BatchPlan& bp, const Sparse& X, hipStream_t s, int autotune);
 void free_batch_plan(BatchPlan& bp);
 void launch_batch_solve(const BatchProb* probs, const int* order, int nprob, int* queue, BatchOut* out,
                         int grid, hipStream_t s);
@@ -557,7 +566,7 @@ rr_status batch_scratch(BatchScratch* out);
 rr_status lanczos_prototypes(rr_handle* h, int n_proto, int steps, uint64_t seed, double* V, double* ev,
                              hipStream_t s);
 rr_status build_rows(RowPlan& out, const std::vector<int>& ptr, const std::vector<int>& col, int N, int F,
-                     int num_cu, int L, hipStream_t s);
+                     int num_cu, int L, hipStream_t s, const std::vector<double>* val = nullptr);
 // More than kMaxParts block partials are first added into partials[0] by one
 // block; returns the count the consumer should add.
 int collapse_parts(double* partials, int n, const int* done, hipStream_t s);
@@ -632,9 +641,9 @@ void mlp_backward(Mlp& n, int Bn, hipStream_t s);
 void mlp_adam(Mlp& n, float lr, hipStream_t s);
 void launch_learned_in(int FC, const double* c, double lam, uint16_t* xb, double* scale,
                        const int* done, hipStream_t s);
-void launch_learned_out(int FC, const float* y, const double* scale, double* yc, const int* done,
-                        hipStream_t s);
-void launch_make_pairs(int FC, int npairs, const double* S, const double* Ainv_rc, double lam,
+void launch_learned_out(int FC, const float* y, const double* scale, const double* K, double lam, double* yc,
+                        const int* done, hipStream_t s);
+void launch_make_pairs(int FC, int npairs, const double* S, const double* Ainv_rc, const double* K, double lam,
                        float* inputs, float* targets, hipStream_t s);
 
 // ---- coarse level (coarse.hip) ---------------------------------------------
@@ -655,6 +664,9 @@ rr_status build_coarse_gram_valued(rr_handle* h, hipStream_t s);   // (api.hip)
 // c = P^T v over the restriction plan mp (either interpolation)  (api.hip)
 void launch_restrict(const rr_handle* h, const MergePlan& mp, const double* v, double* out,
                      const int* done, hipStream_t s);
+// the same from v stored in cluster order (v[k] belongs to feature perm[k])
+void launch_restrict_sorted(const rr_handle* h, const MergePlan& mp, const double* v, double* out,
+                            const int* done, hipStream_t s);
 // least-squares interpolation weights from prototypes  (interp.hip)
 rr_status set_interpolation(rr_handle* h, const double* V, int nproto, double beta, const int* rep,
                             double* p_out, hipStream_t s);

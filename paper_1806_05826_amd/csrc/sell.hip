@@ -213,6 +213,140 @@ __global__ __launch_bounds__(kSliceBlock) void k_sell(const int* __restrict__ wr
   sell_body<double>(wrange, bslice, task, idx, v, gdim, W, out, done, stage);
 }
 
+// The passes of a valued X: every entry's FP64 value is streamed beside its
+// index (the same positions, 0 for padding) and multiplies the LDS value.
+// Lane tasks load 4 groups of 4 entries per batch (8-byte index loads and
+// 16-byte value loads), wave tasks 2 groups of 8 entries per lane; the sums
+// run in the same fixed orders as for 0/1 X.
+constexpr int kLaneUnrollV = 4;
+constexpr int kWaveUnrollV = 2;
+
+template <int PASS>
+__global__ __launch_bounds__(kSliceBlock) void k_sell_val(const int* __restrict__ wrange,
+                                                         const int* __restrict__ bslice,
+                                                         const int4* __restrict__ task,
+                                                         const uint16_t* __restrict__ idx,
+                                                         const double* __restrict__ val,
+                                                         const double* __restrict__ v, int gdim, int W,
+                                                         double* __restrict__ out, const int* done,
+                                                         StageArgs stage) {
+  if (is_done(done)) return;
+  __shared__ __align__(16) double vs[kSliceRows + 1];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int t0 = wrange[blockIdx.x * (kSliceWaves + 1) + w];
+  const int t1 = wrange[blockIdx.x * (kSliceWaves + 1) + w + 1];
+  int4 my = make_int4(0, 0, 0, 0);
+  if (t0 + lane < t1) my = task[t0 + lane];
+  const int g0 = bslice[blockIdx.x] * W;
+  fill_slice(vs, v + g0, min(W, gdim - g0));
+  if (stage.sc) {   // convergence check of the preceding x/r update, under the slice copy
+    __shared__ double red_s[kSliceWaves];
+    double rz_unused;
+    if (stage_update<kSliceBlock>(stage, red_s, rz_unused)) {
+      __builtin_amdgcn_s_waitcnt(0);   // the slice copy lands before the workgroup ends
+      return;
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  const double2 z2 = make_double2(0.0, 0.0);
+  for (int t = t0; t < t1; ++t) {
+    const int i = (t - t0) & 63;
+    if (i == 0 && t != t0) {
+      my = make_int4(0, 0, 0, 0);
+      if (t + lane < t1) my = task[t + lane];
+    }
+    const int kind = __builtin_amdgcn_readlane(my.x, i);
+    const int base = __builtin_amdgcn_readlane(my.y, i);
+    const int len = __builtin_amdgcn_readlane(my.z, i);
+    const int obase = __builtin_amdgcn_readlane(my.w, i);
+    if (kind == 0) {
+      // group g of lane l: entries 4 g .. 4 g + 3, indexes in one 8-byte
+      // load, values in two 16-byte loads
+      const uint2* p = reinterpret_cast<const uint2*>(idx + base) + lane;
+      const double2* pv = reinterpret_cast<const double2*>(val + base) + 2 * lane;
+      double* o = out + obase + lane;
+      double acc = 0.0;
+      const int ng = len / kLaneGroup;
+      auto add = [&](unsigned e, double x) {
+        acc += vs[e & kLocalMask] * x;
+        if (e & kEndFlag) {
+          *o = acc;
+          o += 64;
+          acc = 0.0;
+        }
+      };
+      for (int g = 0; g < ng; g += kLaneUnrollV) {
+        uint2 q[kLaneUnrollV];
+        double2 a[kLaneUnrollV], b[kLaneUnrollV];
+#pragma unroll
+        for (int j = 0; j < kLaneUnrollV; ++j) {
+          const bool in = g + j < ng;
+          q[j] = in ? p[(size_t)(g + j) * 64] : make_uint2(0u, 0u);
+          a[j] = in ? pv[(size_t)(g + j) * 128] : z2;
+          b[j] = in ? pv[(size_t)(g + j) * 128 + 1] : z2;
+        }
+#pragma unroll
+        for (int j = 0; j < kLaneUnrollV; ++j) {
+          if (g + j < ng) {
+            add(q[j].x & 0xffffu, a[j].x);
+            add(q[j].x >> 16, a[j].y);
+            add(q[j].y & 0xffffu, b[j].x);
+            add(q[j].y >> 16, b[j].y);
+          }
+        }
+      }
+    } else {
+      // groups of 512 entries: lane l reads 8 entries (one 16-byte index
+      // load, four 16-byte value loads) of each, then 64-entry tail groups
+      const uint4* p = reinterpret_cast<const uint4*>(idx) + base + lane;
+      const double2* pv = reinterpret_cast<const double2*>(val + (size_t)base * 8) + 4 * lane;
+      const int ng = len >> 4, nt = len & 15;
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int g = 0; g < ng; g += kWaveUnrollV) {
+        uint4 q[kWaveUnrollV];
+        double2 x[kWaveUnrollV][4];
+#pragma unroll
+        for (int j = 0; j < kWaveUnrollV; ++j) {
+          const bool in = g + j < ng;
+          q[j] = in ? p[(size_t)(g + j) * 64] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+          for (int h = 0; h < 4; ++h) x[j][h] = in ? pv[(size_t)(g + j) * 256 + h] : z2;
+        }
+#pragma unroll
+        for (int j = 0; j < kWaveUnrollV; ++j) {
+          if (g + j < ng) {
+            const unsigned wds[4] = {q[j].x, q[j].y, q[j].z, q[j].w};
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+              acc[(2 * h) & 3] += vs[wds[h] & kLocalMask] * x[j][h].x;
+              acc[(2 * h + 1) & 3] += vs[(wds[h] >> 16) & kLocalMask] * x[j][h].y;
+            }
+          }
+        }
+      }
+      if (nt > 0) {   // tail: up to 8 groups of 64 entries, one entry per lane each
+        const size_t tb = (size_t)base * 8 + (size_t)ng * 512 + lane;
+        unsigned q[8];
+        double x[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          q[j] = (j < nt) ? (unsigned)idx[tb + j * 64] : (unsigned)W;
+          x[j] = (j < nt) ? val[tb + j * 64] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (j < nt) acc[j & 3] += vs[q[j] & kLocalMask] * x[j];
+      }
+      double sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+      if (lane == 0) out[obase] = sum;
+    }
+  }
+}
+
 // The same passes over single-precision vectors (FP32 sums).
 template <int PASS>
 __global__ __launch_bounds__(kSliceBlock) void k_sell32(const int* __restrict__ wrange,
@@ -387,7 +521,10 @@ int launch_sell(const SellPlan& sp, const double* v, int mode, const Epi& e, con
   StageArgs st{};
   if (stage) st = *stage;
   if (sp.nblk > 0) {
-    if (sp.pass == 0)
+    if (sp.val)
+      k_sell_val<1><<<sp.nblk, kSliceBlock, 0, s>>>(sp.wrange, sp.bslice, sp.task, sp.idx, sp.val, v,
+                                                    sp.gdim, sp.W, sp.part, done, st);
+    else if (sp.pass == 0)
       k_sell<0><<<sp.nblk, kSliceBlock, 0, s>>>(sp.wrange, sp.bslice, sp.task, sp.idx, v, sp.gdim,
                                                sp.W, sp.part, done, st);
     else
@@ -414,7 +551,10 @@ int launch_sell(const SellPlan& sp, const double* v, int mode, const Epi& e, con
 void launch_sell_gather(const SellPlan& sp, const double* v, hipStream_t s) {
   if (sp.nblk == 0) return;
   const StageArgs st{};
-  if (sp.pass == 0)
+  if (sp.val)
+    k_sell_val<1><<<sp.nblk, kSliceBlock, 0, s>>>(sp.wrange, sp.bslice, sp.task, sp.idx, sp.val, v, sp.gdim,
+                                                  sp.W, sp.part, nullptr, st);
+  else if (sp.pass == 0)
     k_sell<0><<<sp.nblk, kSliceBlock, 0, s>>>(sp.wrange, sp.bslice, sp.task, sp.idx, v, sp.gdim,
                                              sp.W, sp.part, nullptr, st);
   else
@@ -431,6 +571,7 @@ void free_sell(SellPlan& sp) {
   if (sp.sbase) (void)dev_free(sp.sbase);
   if (sp.lseg) (void)dev_free(sp.lseg);
   if (sp.part) (void)dev_free(sp.part);
+  if (sp.val) (void)dev_free(sp.val);
   sp = SellPlan{};
 }
 
@@ -443,6 +584,8 @@ struct Pair {
 // Lane-task builder state: indexes, tasks, output positions.
 struct SellBuild {
   std::vector<uint16_t> idx;
+  std::vector<double> val;   // valued X: values at the indexes' positions (0 for padding)
+  bool valued = false;
   std::vector<int4> tasks;
   std::vector<long long> tcost;
   std::vector<int> tslice;
@@ -457,12 +600,14 @@ struct SellBuild {
 // at obase + 64 c + l.
 void emit_layer_task(SellBuild& B, const std::vector<std::vector<int>>& layers,
                      const std::vector<int>& llen, const std::vector<Pair>& pairs,
-                     const std::vector<int>& gidx, int g0, int W, int r) {
+                     const std::vector<int>& gidx, const std::vector<double>* gval, int g0, int W,
+                     int r) {
   int m = 0;
   for (int L : llen) m += L;
   m = (m + kLaneGroup - 1) / kLaneGroup * kLaneGroup;
   const size_t base = B.idx.size();   // a multiple of 64: every task fills whole 64-entry rows
   B.idx.resize(base + (size_t)m * 64, (uint16_t)W);
+  if (B.valued) B.val.resize(B.idx.size(), 0.0);
   auto at = [&](int k, int l) {
     return base + (size_t)(k / kLaneGroup) * 64 * kLaneGroup + (size_t)l * kLaneGroup + k % kLaneGroup;
   };
@@ -472,7 +617,10 @@ void emit_layer_task(SellBuild& B, const std::vector<std::vector<int>>& layers,
     for (int l = 0; l < 64; ++l) {
       if (l < (int)layers[c].size()) {
         const Pair& pa = pairs[layers[c][l]];
-        for (int e = 0; e < pa.len; ++e) B.idx[at(k0 + e, l)] = (uint16_t)(gidx[pa.start + e] - g0);
+        for (int e = 0; e < pa.len; ++e) {
+          B.idx[at(k0 + e, l)] = (uint16_t)(gidx[pa.start + e] - g0);
+          if (B.valued) B.val[at(k0 + e, l)] = (*gval)[pa.start + e];
+        }
         B.pos[layers[c][l]] = obase + (int)c * 64 + l;
       }
       B.idx[at(k0 + llen[c] - 1, l)] |= (uint16_t)kEndFlag;
@@ -490,7 +638,8 @@ void emit_layer_task(SellBuild& B, const std::vector<std::vector<int>>& layers,
 // Host-side construction from a segment-major pattern (ptr[S+1], gidx sorted
 // inside every segment).  Setup only.
 rr_status build_sell(SellPlan& sp, const std::vector<int>& ptr, const std::vector<int>& gidx,
-                     int S, int gdim, int num_cu, hipStream_t s, int target_div) {
+                     int S, int gdim, int num_cu, hipStream_t s, int target_div,
+                     const std::vector<double>* gval) {
   free_sell(sp);
   const int W = kSliceRows;
   const int R = std::max(1, cdiv(gdim, W));
@@ -562,6 +711,7 @@ rr_status build_sell(SellPlan& sp, const std::vector<int>& ptr, const std::vecto
   std::vector<std::vector<int>> small(R), heavy(R);
   for (int i = 0; i < (int)pairs.size(); ++i) (pairs[i].len > cmax ? heavy : small)[pslice[i]].push_back(i);
   SellBuild B;
+  B.valued = gval != nullptr;
   B.pos.assign(pairs.size(), -1);
   const uint16_t pad = (uint16_t)W;   // index of the zero entry
   auto by_len_desc = [&](int a, int b) {
@@ -571,12 +721,15 @@ rr_status build_sell(SellPlan& sp, const std::vector<int>& ptr, const std::vecto
     const int g0 = r * W;
     for (int i : heavy[r]) {
       while (B.idx.size() % 8) B.idx.push_back(pad);
+      if (B.valued) B.val.resize(B.idx.size(), 0.0);
       const int base16 = (int)(B.idx.size() / 8);
       const int len = pairs[i].len;
       const int ng = len / 512;                  // 512-entry groups (16-byte loads)
       const int nt = cdiv(len - ng * 512, 64);   // 64-entry tail groups (2-byte loads)
-      for (int k = 0; k < ng * 512 + nt * 64; ++k)
+      for (int k = 0; k < ng * 512 + nt * 64; ++k) {
         B.idx.push_back(k < len ? (uint16_t)(gidx[pairs[i].start + k] - g0) : pad);
+        if (B.valued) B.val.push_back(k < len ? (*gval)[pairs[i].start + k] : 0.0);
+      }
       B.pos[i] = B.nout++;
       B.tasks.push_back(make_int4(1, base16, ng * 16 + nt, B.pos[i]));
       B.tcost.push_back((long long)ng * 8 + nt + 8);
@@ -613,7 +766,7 @@ rr_status build_sell(SellPlan& sp, const std::vector<int>& ptr, const std::vecto
         layers.emplace_back(sm.begin() + 64 * c, sm.begin() + std::min<size_t>(sm.size(), 64 * c + 64));
         llen.push_back(pairs[sm[64 * c]].len);
       }
-      emit_layer_task(B, layers, llen, pairs, gidx, r * W, W, r);
+      emit_layer_task(B, layers, llen, pairs, gidx, gval, r * W, W, r);
     }
     return cnt;
   };
@@ -702,6 +855,7 @@ rr_status build_sell(SellPlan& sp, const std::vector<int>& ptr, const std::vecto
   }
   while (B.idx.size() % 8) B.idx.push_back(pad);
   if (B.idx.empty()) B.idx.resize(8, pad);
+  if (B.valued) B.val.resize(B.idx.size(), 0.0);
   // the kernel trusts the plan: check every access it will make
   for (const int4& t : tasks_sorted) {
     const size_t n16 = B.idx.size();
@@ -759,8 +913,12 @@ rr_status build_sell(SellPlan& sp, const std::vector<int>& ptr, const std::vecto
   if (!B.pos.empty())
     RR_HIP(hipMemcpyAsync(sp.pos, B.pos.data(), sizeof(int) * B.pos.size(), hipMemcpyHostToDevice, s));
   RR_HIP(hipMemcpyAsync(sp.sbase, sbase.data(), sizeof(int) * sbase.size(), hipMemcpyHostToDevice, s));
+  if (B.valued) {
+    RR_HIP(dmalloc(&sp.val, sizeof(double) * B.val.size()));
+    RR_HIP(hipMemcpyAsync(sp.val, B.val.data(), sizeof(double) * B.val.size(), hipMemcpyHostToDevice, s));
+  }
   RR_HIP(hipStreamSynchronize(s));
-  sp.idx_bytes = (long long)B.idx.size() * 2;
+  sp.idx_bytes = (long long)B.idx.size() * 2 + (long long)B.val.size() * 8;
   return RR_OK;
 }
 
@@ -809,14 +967,23 @@ std::map<std::string, std::pair<int, int>> g_tune_cache;
 }
 
 rr_status build_sell_plans(Sparse& X, hipStream_t s, int autotune, SellTuning* tuned) {
-  if (!X.binary) return RR_OK;   // valued matrices use the row-group / merge-path kernels
+  if (!X.binary && (X.N == 0 || X.nnz == 0)) return RR_OK;   // no entries: the generic kernels
   std::vector<int> rp(X.N + 1), ci(std::max(X.nnz, 1)), cp(X.F + 1), ri(std::max(X.nnz, 1));
+  std::vector<double> rv, cv;   // valued X: CSR and CSC values
   RR_HIP(hipMemcpyAsync(rp.data(), X.row_ptr, sizeof(int) * (X.N + 1), hipMemcpyDeviceToHost, s));
   RR_HIP(hipMemcpyAsync(cp.data(), X.col_ptr, sizeof(int) * (X.F + 1), hipMemcpyDeviceToHost, s));
   if (X.nnz) {
     RR_HIP(hipMemcpyAsync(ci.data(), X.col_idx, sizeof(int) * X.nnz, hipMemcpyDeviceToHost, s));
     RR_HIP(hipMemcpyAsync(ri.data(), X.row_idx, sizeof(int) * X.nnz, hipMemcpyDeviceToHost, s));
   }
+  if (!X.binary) {
+    rv.resize(X.nnz);
+    cv.resize(X.nnz);
+    RR_HIP(hipMemcpyAsync(rv.data(), X.val, sizeof(double) * X.nnz, hipMemcpyDeviceToHost, s));
+    RR_HIP(hipMemcpyAsync(cv.data(), X.cval, sizeof(double) * X.nnz, hipMemcpyDeviceToHost, s));
+  }
+  const std::vector<double>* rvp = X.binary ? nullptr : &rv;
+  const std::vector<double>* cvp = X.binary ? nullptr : &cv;
   RR_HIP(hipStreamSynchronize(s));
   // defaults: two lanes per row once rows average 16 entries or more
   int lanes = (X.N > 0 && (long long)X.nnz >= 16LL * X.N) ? 2 : 1, div_cols = 2;
@@ -827,7 +994,8 @@ rr_status build_sell_plans(Sparse& X, hipStream_t s, int autotune, SellTuning* t
     RR_HIP(hipGetDeviceProperties(&prop, dev));
     auto lg = [](long long v) { int b = 0; while ((1LL << b) < v) ++b; return b; };
     const std::string key = std::string(prop.gcnArchName) + ":" + std::to_string(lg(X.N)) + ":" +
-                            std::to_string(lg(X.F)) + ":" + std::to_string(lg(X.nnz));
+                            std::to_string(lg(X.F)) + ":" + std::to_string(lg(X.nnz)) +
+                            (X.binary ? ":01" : ":fp64");
     bool hit = false;
     {
       std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -855,8 +1023,8 @@ rr_status build_sell_plans(Sparse& X, hipStream_t s, int autotune, SellTuning* t
       float best[2][kCand];
       rr_status st = RR_OK;
       for (int c = 0; c < kCand && st == RR_OK; ++c) {
-        st = build_rows(rplans[c], rp, ci, X.N, X.F, X.num_cu, cand[c], s);
-        if (st == RR_OK) st = build_sell(cplans[c], cp, ri, X.F, X.N, X.num_cu, s, cand[c]);
+        st = build_rows(rplans[c], rp, ci, X.N, X.F, X.num_cu, cand[c], s, rvp);
+        if (st == RR_OK) st = build_sell(cplans[c], cp, ri, X.F, X.N, X.num_cu, s, cand[c], cvp);
         cplans[c].pass = 1;
         best[0][c] = best[1][c] = 1e30f;
       }
@@ -900,9 +1068,10 @@ rr_status build_sell_plans(Sparse& X, hipStream_t s, int autotune, SellTuning* t
     tuned->div_rows = lanes;
     tuned->div_cols = div_cols;
   }
-  RR_TRY(build_rows(X.rows, rp, ci, X.N, X.F, X.num_cu, lanes, s));
-  RR_TRY(build_sell(X.sell_csc, cp, ri, X.F, X.N, X.num_cu, s, div_cols));
+  RR_TRY(build_rows(X.rows, rp, ci, X.N, X.F, X.num_cu, lanes, s, rvp));
+  RR_TRY(build_sell(X.sell_csc, cp, ri, X.F, X.N, X.num_cu, s, div_cols, cvp));
   X.sell_csc.pass = 1;
+  X.sliced = true;
   return RR_OK;
 }
 

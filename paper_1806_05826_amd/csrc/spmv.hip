@@ -65,7 +65,7 @@ static void csr_dispatch(const Sparse& X, const double* v, double* u, const int*
 
 void launch_csr(const Sparse& X, const double* v, double* u, const int* done, hipStream_t s,
                 const StageArgs* stage, hipEvent_t mid) {
-  if (X.binary && X.N > 0) {
+  if (X.sliced && X.N > 0) {
     // u = D X v with row weights, applied as each row is finished
     launch_rows(X.rows, v, u, X.rw, done, s, stage);
     if (mid) (void)hipEventRecord(mid, s);
@@ -267,50 +267,26 @@ __global__ __launch_bounds__(kBlock) void k_segfix(const int4* __restrict__ span
   if constexpr (has_dot<MODE>()) store_block_partial<kBlock>(dot, e.partials, nmain + blockIdx.x);
 }
 
-// One-kernel segmented sum for epilogues without a dot product: a segment
-// of at most kWaveSeg entries is summed by one wave (lane l adds entries l,
-// l + 64, ... in order, then a fixed butterfly), a longer one by a whole
-// 1024-thread block (thread k adds entries k, k + 1024, ... in order, 16
-// loads in flight, then the fixed block tree).  Blocks [0, nb) take the long
-// segments, the others sixteen short ones each.
+// Segmented sums for epilogues without a dot product (the restriction): a
+// segment of at most kWaveSeg entries is one wave's item (lane l adds
+// entries l, l + 64, ... in order, 16 loads in flight, then a fixed
+// butterfly) and is finished in place; a longer one is cut into chunks of at
+// most kWaveSeg entries, each a wave item whose sum goes to cpart, and one
+// more wave per such segment (second kernel) adds its chunk sums in chunk
+// order and finishes it.  Entry q is v[idx[q]], or v[q] when v is already in
+// segment order (IDX false: one load, coalesced).
 constexpr int kWaveSeg = 1024;
 constexpr int kSegBlock = 1024;
-template <int MODE, bool VAL>
+template <int MODE, bool VAL, bool IDX>
 __global__ __launch_bounds__(kSegBlock) void k_seg1(const int4* __restrict__ witem, int nw,
-                                                    const int4* __restrict__ bitem, int nb,
                                                     const int* __restrict__ idx,
                                                     const double* __restrict__ val,
-                                                    const double* __restrict__ v, Epi e, const int* done) {
+                                                    const double* __restrict__ v, Epi e,
+                                                    double* __restrict__ cpart, const int* done) {
   if (is_done(done)) return;
-  double dot = 0.0;
   constexpr int U = 16;
-  if ((int)blockIdx.x < nb) {
-    const int4 it = bitem[blockIdx.x];
-    double t = 0.0;
-    for (int q0 = it.y + (int)threadIdx.x; q0 < it.z; q0 += U * kSegBlock) {
-      int j[U];
-#pragma unroll
-      for (int k = 0; k < U; ++k) {
-        const int q = q0 + k * kSegBlock;
-        j[k] = q < it.z ? idx[q] : -1;
-      }
-      if constexpr (VAL) {
-        double a[U];
-#pragma unroll
-        for (int k = 0; k < U; ++k) a[k] = j[k] >= 0 ? val[q0 + k * kSegBlock] : 0.0;
-#pragma unroll
-        for (int k = 0; k < U; ++k) t += j[k] >= 0 ? v[j[k]] * a[k] : 0.0;
-      } else {
-#pragma unroll
-        for (int k = 0; k < U; ++k) t += j[k] >= 0 ? v[j[k]] : 0.0;
-      }
-    }
-    __shared__ double red[kSegBlock / 64];
-    t = block_sum_n<kSegBlock>(t, red);
-    if (threadIdx.x == 0) seg_finish<MODE>(it.x, t, e, dot);
-    return;
-  }
-  const int wv = ((int)blockIdx.x - nb) * (kSegBlock / 64) + (int)(threadIdx.x >> 6);
+  static_assert(U * 64 == kWaveSeg, "a wave item is at most one batch per lane");
+  const int wv = (int)blockIdx.x * (kSegBlock / 64) + (int)(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (wv >= nw) return;
   const int4 it = witem[wv];
@@ -318,7 +294,7 @@ __global__ __launch_bounds__(kSegBlock) void k_seg1(const int4* __restrict__ wit
 #pragma unroll
   for (int k = 0; k < U; ++k) {
     const int q = it.y + lane + 64 * k;
-    j[k] = q < it.z ? idx[q] : -1;
+    j[k] = q < it.z ? (IDX ? idx[q] : q) : -1;
   }
   double t = 0.0;
   if constexpr (VAL) {
@@ -333,19 +309,54 @@ __global__ __launch_bounds__(kSegBlock) void k_seg1(const int4* __restrict__ wit
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-  if (lane == 0) seg_finish<MODE>(it.x, t, e, dot);
+  if (lane == 0) {
+    if (it.w < 0) {
+      double dot = 0.0;
+      seg_finish<MODE>(it.x, t, e, dot);
+    } else {
+      cpart[it.w] = t;
+    }
+  }
+}
+
+// fitem: (segment, first chunk sum, chunk count, 0); one wave each
+template <int MODE>
+__global__ __launch_bounds__(kSegBlock) void k_seg1_fin(const int4* __restrict__ fitem, int nf,
+                                                        const double* __restrict__ cpart, Epi e,
+                                                        const int* done) {
+  if (is_done(done)) return;
+  const int wv = (int)blockIdx.x * (kSegBlock / 64) + (int)(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (wv >= nf) return;
+  const int4 it = fitem[wv];
+  double t = 0.0;
+  for (int k = lane; k < it.z; k += 64) t += cpart[it.y + k];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+  if (lane == 0) {
+    double dot = 0.0;
+    seg_finish<MODE>(it.x, t, e, dot);
+  }
 }
 
 template <int MODE>
 static void seg1_mode(const MergePlan& mp, const int* idx, const double* val, const double* v,
                       const Epi& e, const int* done, hipStream_t s) {
-  const int grid = mp.nbitem + cdiv(mp.nwitem, kSegBlock / 64);
-  if (val)
-    k_seg1<MODE, true><<<grid, kSegBlock, 0, s>>>(mp.witem, mp.nwitem, mp.bitem, mp.nbitem, idx, val, v,
-                                                  e, done);
+  const int grid = cdiv(mp.nwitem, kSegBlock / 64);
+  if (val && idx)
+    k_seg1<MODE, true, true><<<grid, kSegBlock, 0, s>>>(mp.witem, mp.nwitem, idx, val, v, e, mp.cpart, done);
+  else if (idx)
+    k_seg1<MODE, false, true><<<grid, kSegBlock, 0, s>>>(mp.witem, mp.nwitem, idx, nullptr, v, e, mp.cpart,
+                                                         done);
+  else if (val)
+    k_seg1<MODE, true, false><<<grid, kSegBlock, 0, s>>>(mp.witem, mp.nwitem, nullptr, val, v, e, mp.cpart,
+                                                         done);
   else
-    k_seg1<MODE, false><<<grid, kSegBlock, 0, s>>>(mp.witem, mp.nwitem, mp.bitem, mp.nbitem, idx,
-                                                   nullptr, v, e, done);
+    k_seg1<MODE, false, false><<<grid, kSegBlock, 0, s>>>(mp.witem, mp.nwitem, nullptr, nullptr, v, e,
+                                                          mp.cpart, done);
+  if (mp.nfitem > 0)
+    k_seg1_fin<MODE><<<cdiv(mp.nfitem, kSegBlock / 64), kSegBlock, 0, s>>>(mp.fitem, mp.nfitem, mp.cpart, e,
+                                                                           done);
 }
 
 // Collapse n block partials into partials[0] (one block, fixed order).
@@ -384,7 +395,7 @@ int collapse_parts(double* partials, int n, const int* done, hipStream_t s) {
 
 int launch_csc(const Sparse& X, const double* u, int mode, const Epi& e, const int* done,
                hipStream_t s, hipEvent_t mid) {
-  if (X.binary) return launch_sell(X.sell_csc, u, mode, e, done, s, nullptr, mid);
+  if (X.sliced) return launch_sell(X.sell_csc, u, mode, e, done, s, nullptr, mid);
   const int n = launch_segsum(X.csc_plan, X.col_ptr + 1, X.row_idx, X.cval, u, mode, e, done, s);
   if (mid) (void)hipEventRecord(mid, s);
   return n;
@@ -392,13 +403,14 @@ int launch_csc(const Sparse& X, const double* u, int mode, const Epi& e, const i
 
 int launch_segsum(const MergePlan& mp, const int* seg_end, const int* idx, const double* val,
                   const double* v, int mode, const Epi& e, const int* done, hipStream_t s) {
-  if (mp.nwitem + mp.nbitem > 0) {
+  if (mp.nwitem > 0) {
     switch (mode) {
       case EPI_STORE: seg1_mode<EPI_STORE>(mp, idx, val, v, e, done, s); return 0;
       case EPI_SCALE: seg1_mode<EPI_SCALE>(mp, idx, val, v, e, done, s); return 0;
       default: break;
     }
   }
+  if (!idx) return 0;   // segment-ordered input: only the one-kernel form reads it
   if (mp.nblocks == 0) return 0;
   switch (mode) {
     case EPI_STORE: return segsum_mode<EPI_STORE>(mp, seg_end, idx, val, v, e, done, s);
@@ -428,34 +440,50 @@ void free_merge_plan(MergePlan& mp) {
   if (mp.head) (void)dev_free(mp.head);
   if (mp.tail) (void)dev_free(mp.tail);
   if (mp.witem) (void)dev_free(mp.witem);
-  if (mp.bitem) (void)dev_free(mp.bitem);
+  if (mp.fitem) (void)dev_free(mp.fitem);
+  if (mp.cpart) (void)dev_free(mp.cpart);
   mp = MergePlan{};
 }
 
-// The chunked form of a plan whose segments are seg_ptr[0..nseg] (setup only).
+// The wave-item form of a plan whose segments are seg_ptr[0..nseg] (setup
+// only): a wave per segment of up to kWaveSeg entries, longer ones in about
+// equal chunks of at most kWaveSeg entries plus a finishing wave.
 rr_status build_chunk_plan(MergePlan& mp, const int* d_seg_ptr, int nseg, hipStream_t s) {
   std::vector<int> ptr(nseg + 1);
   RR_HIP(hipMemcpyAsync(ptr.data(), d_seg_ptr, sizeof(int) * (nseg + 1), hipMemcpyDeviceToHost, s));
   RR_HIP(hipStreamSynchronize(s));
-  {   // a wave or a block per segment
-    std::vector<int4> wi, bi;
-    for (int q = 0; q < nseg; ++q) {
-      if (ptr[q + 1] < ptr[q]) return fail(RR_ERR_DEVICE, "internal: decreasing segment offsets");
-      (ptr[q + 1] - ptr[q] > kWaveSeg ? bi : wi).push_back(make_int4(q, ptr[q], ptr[q + 1], 0));
+  std::vector<int4> wi, fi;
+  int np = 0;
+  for (int q = 0; q < nseg; ++q) {
+    const int a = ptr[q], z = ptr[q + 1];
+    if (z < a) return fail(RR_ERR_DEVICE, "internal: decreasing segment offsets");
+    if (z - a <= kWaveSeg) {
+      wi.push_back(make_int4(q, a, z, -1));
+      continue;
     }
-    mp.nwitem = (int)wi.size();
-    mp.nbitem = (int)bi.size();
-    if (mp.nwitem) {
-      RR_HIP(dmalloc(&mp.witem, sizeof(int4) * mp.nwitem));
-      RR_HIP(hipMemcpyAsync(mp.witem, wi.data(), sizeof(int4) * mp.nwitem, hipMemcpyHostToDevice, s));
+    const int nc = cdiv(z - a, kWaveSeg);
+    fi.push_back(make_int4(q, np, nc, 0));
+    for (int c = 0; c < nc; ++c) {
+      const int c0 = a + (int)((long long)(z - a) * c / nc), c1 = a + (int)((long long)(z - a) * (c + 1) / nc);
+      wi.push_back(make_int4(q, c0, c1, np++));
     }
-    if (mp.nbitem) {
-      RR_HIP(dmalloc(&mp.bitem, sizeof(int4) * mp.nbitem));
-      RR_HIP(hipMemcpyAsync(mp.bitem, bi.data(), sizeof(int4) * mp.nbitem, hipMemcpyHostToDevice, s));
-    }
-    RR_HIP(hipStreamSynchronize(s));
-    return RR_OK;
   }
+  for (const int4& w : wi)
+    if (w.z - w.y > kWaveSeg || w.w >= np) return fail(RR_ERR_DEVICE, "internal: segment item out of range");
+  mp.nwitem = (int)wi.size();
+  mp.nfitem = (int)fi.size();
+  mp.ncpart = np;
+  if (mp.nwitem) {
+    RR_HIP(dmalloc(&mp.witem, sizeof(int4) * mp.nwitem));
+    RR_HIP(hipMemcpyAsync(mp.witem, wi.data(), sizeof(int4) * mp.nwitem, hipMemcpyHostToDevice, s));
+  }
+  if (mp.nfitem) {
+    RR_HIP(dmalloc(&mp.fitem, sizeof(int4) * mp.nfitem));
+    RR_HIP(hipMemcpyAsync(mp.fitem, fi.data(), sizeof(int4) * mp.nfitem, hipMemcpyHostToDevice, s));
+  }
+  if (np) RR_HIP(dmalloc(&mp.cpart, sizeof(double) * np));
+  RR_HIP(hipStreamSynchronize(s));
+  return RR_OK;
 }
 
 // seg_end = ptr + 1 (nseg entries), seg_ptr = ptr (nseg + 1 entries).

@@ -51,9 +51,10 @@ def batch(rr):
     big = datagen.sparse_problem(15_000, 3000, 40, seed=23)
     probs.append((big, 0.05))
     Rs = []
-    for P, _ in probs:
+    for i, (P, _) in enumerate(probs):
         k = int(min(800, max(8, -(-P.X.shape[1] // 10))))
-        Rs.append(rr.Ridge(P.X, n_clusters=k, seed=9))
+        # every other handle with its lanes per row timed at setup
+        Rs.append(rr.Ridge(P.X, n_clusters=k, seed=9, autotune=(i % 2 == 0)))
     return probs, Rs
 
 
