@@ -383,6 +383,44 @@ def test_real_valued_matrix(rr):
     assert np.linalg.norm(host(w) - x_t) <= 1e-10 * np.linalg.norm(x_t)
 
 
+def test_real_valued_operator_sliced_mid(rr):
+    """The valued operator's sliced passes past one LDS slice in both
+    directions: 40,000 x 30,000 (three row slices of the column pass, hot and
+    cold features in the row pass) with Zipf(1.1) columns and standard-normal
+    values, element by element against the oracle's operator; also with a
+    few empty rows and columns and ragged sizes."""
+    P = datagen.sparse_problem(40_000, 30_000, 30, seed=91)
+    X = P.X.tocsr().astype(np.float64)
+    rng = np.random.default_rng(92)
+    X.data = rng.standard_normal(X.nnz)
+    R = rr.Ridge(X, binary=False)
+    for lam in (0.0, 0.3):
+        v = rng.standard_normal(X.shape[1])
+        got = host(R.apply_operator(lam, v))
+        ref = op.apply_A(X, lam, v)
+        scale = np.abs(X).T @ (np.abs(X) @ np.abs(v)) + lam * np.abs(v)
+        err = np.max(np.abs(got - ref) / np.maximum(scale, 1e-300))
+        print(f"[valued mid] lambda={lam}: max error / |X|^T|X||v| = {err:.2e}", flush=True)
+        # both sides add up to a few thousand FP64 terms per output, in
+        # different orders: the gap is a few hundred units of rounding of
+        # |X|^T |X| |v| at most
+        assert err <= 1e-12
+    R.close()
+    # ragged: rows and columns with no entries, sizes off every tile
+    Y = X[:33_333, :29_999].tolil()
+    Y[100:140, :] = 0.0
+    Y[:, 5000:5100] = 0.0
+    Y = Y.tocsr()
+    Y.eliminate_zeros()
+    R = rr.Ridge(Y, binary=False)
+    v = rng.standard_normal(Y.shape[1])
+    got = host(R.apply_operator(1.0, v))
+    ref = op.apply_A(Y, 1.0, v)
+    scale = np.abs(Y).T @ (np.abs(Y) @ np.abs(v)) + np.abs(v)
+    assert np.max(np.abs(got - ref) / scale) <= 1e-12
+    R.close()
+
+
 @pytest.mark.parametrize("lam", [0.05, 0.7])
 def test_real_valued_two_level(rr, lam):
     """X with negative entries: smoother weight by power iteration, coarse
