@@ -714,13 +714,18 @@ rr_status precond_two_level(rr_handle* h, Work& w, Prof& pf, int tag, int kind, 
   e.opos = h->cpos;   // rho1 in cluster order: the restriction reads it contiguously
   RR_TRY(op_csc(h, w, pf, tag, EPI_RESID, e, s));
   // e2 = e1 + P A_c^-1 P^T rho1 (learned: the network's coarse correction)
-  launch_restrict_sorted(h, w.rplan, w.rho, w.c, done, s);
+  if (kind != PK_LEARNED && !snap && restrict_gemv_fusable(w.rplan, h->FC)) {
+    launch_restrict_gemv(w.rplan, w.rho, h->lsw ? h->lsw_perm : nullptr, h->lsw ? nullptr : h->cscale, w.c,
+                         h->FC, sl.Ainv, w.yc, done, s);
+  } else {
+    launch_restrict_sorted(h, w.rplan, w.rho, w.c, done, s);
+  }
   if (snap) launch_copy_done(snap, w.c, h->FC, done, s);
   if (kind == PK_LEARNED) {
     launch_learned_in(h->FC, w.c, lam, h->mlp.xb, h->mlp_scale, done, s);
     mlp_forward(h->mlp, 1, s);
     launch_learned_out(h->FC, h->mlp.y, h->mlp_scale, h->K, lam, w.yc, done, s);
-  } else {
+  } else if (snap || !restrict_gemv_fusable(w.rplan, h->FC)) {
     launch_gemv(h->FC, sl.Ainv, w.c, w.yc, done, s);
   }
   // z = e2 + w D^-1 (r - A e2), <r,z> -> beta; X e2 = X e1 + X P yc, where

@@ -664,6 +664,12 @@ rr_status build_coarse_gram_valued(rr_handle* h, hipStream_t s);   // (api.hip)
 // c = P^T v over the restriction plan mp (either interpolation)  (api.hip)
 void launch_restrict(const rr_handle* h, const MergePlan& mp, const double* v, double* out,
                      const int* done, hipStream_t s);
+// the restriction from cluster-ordered v and the coarse GEMV yc = Ainv c in two
+// kernels, the restriction's finishing step folded into the GEMV (c then holds
+// the short clusters' entries only); usable when restrict_gemv_fusable
+bool restrict_gemv_fusable(const MergePlan& mp, int n);
+void launch_restrict_gemv(const MergePlan& mp, const double* v_sorted, const double* val, const double* scale,
+                          double* c, int n, const double* Ainv, double* yc, const int* done, hipStream_t s);
 // the same from v stored in cluster order (v[k] belongs to feature perm[k])
 void launch_restrict_sorted(const rr_handle* h, const MergePlan& mp, const double* v, double* out,
                             const int* done, hipStream_t s);

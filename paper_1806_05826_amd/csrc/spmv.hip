@@ -339,6 +339,78 @@ __global__ __launch_bounds__(kSegBlock) void k_seg1_fin(const int4* __restrict__
   }
 }
 
+// The coarse GEMV y = A c of the V(1,1) cycle with the restriction's
+// finishing step folded in: every block copies c (n <= kGemvFinMax) into LDS
+// and forms the long clusters' entries itself from their chunk sums, in the
+// order and with the scaling of k_seg1_fin (so y is bitwise the same), then
+// one wave per row as in k_gemv.
+constexpr int kGemvFinMax = 4096;
+__global__ __launch_bounds__(kBlock) void k_gemv_fin(int n, const double* __restrict__ A,
+                                                     const double* __restrict__ c,
+                                                     const int4* __restrict__ fitem, int nf,
+                                                     const double* __restrict__ cpart,
+                                                     const double* __restrict__ scale, double* __restrict__ y,
+                                                     const int* done) {
+  if (is_done(done)) return;
+  __shared__ double xs[kGemvFinMax];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < n; i += kBlock) xs[i] = c[i];
+  __syncthreads();
+  for (int f = wv; f < nf; f += kBlock / 64) {
+    const int4 it = fitem[f];
+    double t = 0.0;
+    for (int k = lane; k < it.z; k += 64) t += cpart[it.y + k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+    if (lane == 0) xs[it.x] = scale ? t * scale[it.x] : t;
+  }
+  __syncthreads();
+  const int row = blockIdx.x * (kBlock / 64) + wv;
+  if (row >= n) return;
+  const double* a = A + (size_t)row * n;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int c0 = lane; c0 < n; c0 += 1024) {
+    double av[16], xv[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int q = c0 + 64 * k;
+      av[k] = q < n ? a[q] : 0.0;
+      xv[k] = q < n ? xs[q] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k & 3] += av[k] * xv[k];
+  }
+  double t = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+  if (lane == 0) y[row] = t;
+}
+
+bool restrict_gemv_fusable(const MergePlan& mp, int n) { return mp.nwitem > 0 && n > 0 && n <= kGemvFinMax; }
+
+void launch_restrict_gemv(const MergePlan& mp, const double* v_sorted, const double* val, const double* scale,
+                          double* c, int n, const double* Ainv, double* yc, const int* done, hipStream_t s) {
+  Epi e{};
+  e.out = c;
+  e.scale = scale;
+  const int grid = cdiv(mp.nwitem, kSegBlock / 64);
+  if (val) {
+    if (scale)
+      k_seg1<EPI_SCALE, true, false><<<grid, kSegBlock, 0, s>>>(mp.witem, mp.nwitem, nullptr, val, v_sorted, e,
+                                                               mp.cpart, done);
+    else
+      k_seg1<EPI_STORE, true, false><<<grid, kSegBlock, 0, s>>>(mp.witem, mp.nwitem, nullptr, val, v_sorted, e,
+                                                               mp.cpart, done);
+  } else {
+    if (scale)
+      k_seg1<EPI_SCALE, false, false><<<grid, kSegBlock, 0, s>>>(mp.witem, mp.nwitem, nullptr, nullptr, v_sorted,
+                                                                e, mp.cpart, done);
+    else
+      k_seg1<EPI_STORE, false, false><<<grid, kSegBlock, 0, s>>>(mp.witem, mp.nwitem, nullptr, nullptr, v_sorted,
+                                                                e, mp.cpart, done);
+  }
+  k_gemv_fin<<<cdiv(n, kBlock / 64), kBlock, 0, s>>>(n, Ainv, c, mp.fitem, mp.nfitem, mp.cpart, scale, yc, done);
+}
+
 template <int MODE>
 static void seg1_mode(const MergePlan& mp, const int* idx, const double* val, const double* v,
                       const Epi& e, const int* done, hipStream_t s) {
