@@ -142,10 +142,14 @@ typedef struct {
                               in increasing order                              */
   int32_t n_labels_in;
   int32_t lambda_slots;    /* coarse factors cached per handle; 0 -> 4          */
-  int32_t autotune;        /* 0/1 X: 1 chooses each sliced pass's lane-stream
+  int32_t autotune;        /* sparse X: 1 chooses each sliced pass's lane-stream
                               length among three candidates by timing them on
                               this device, cached per device and shape bucket
-                              (log2 of N, F, nnz) for the life of the process;
+                              (log2 of N, F, nnz) for the life of the process,
+                              and, for 0/1 X with F <= 8192, the persistent
+                              batched solve's lanes per row (the default, half
+                              and twice it, timed on one workgroup, cached the
+                              same way);
                               dense X: 1 chooses the split of the column pass's
                               contraction (the workgroups it aims at, one of
                               128..2048) per operator precision, timed on a
