@@ -47,6 +47,24 @@ def test_fullsize_operator_exact(rr, big):
     R.close()
 
 
+def test_fullsize_valued_operator(rr, big):
+    """The same pattern with standard-normal FP64 values (the HBM-resident
+    operator the benchmark times): every output against the oracle's
+    operator, relative to |X|^T |X| |v| (both sides add up to tens of
+    thousands of FP64 terms per output, in different orders)."""
+    X = big.X.tocsr().astype(np.float64)
+    X.data = np.random.default_rng(8).standard_normal(X.nnz)
+    R = rr.Ridge(X, binary=False)
+    v = np.random.default_rng(9).standard_normal(X.shape[1])
+    got = host(R.apply_operator(0.5, v))
+    ref = op.apply_A(X, 0.5, v)
+    scale = abs(X).T @ (abs(X) @ np.abs(v)) + 0.5 * np.abs(v)
+    err = np.max(np.abs(got - ref) / scale)
+    print(f"[fullsize] valued operator: max error / |X|^T|X||v| = {err:.2e}", flush=True)
+    assert err <= 1e-12
+    R.close()
+
+
 def test_fullsize_kmeans_fixed_point(rr, big):
     print("[fullsize] GPU k-means k=1000", flush=True)
     R = rr.Ridge(big.X, n_clusters=1000, seed=5826)

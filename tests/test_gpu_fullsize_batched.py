@@ -1,0 +1,76 @@
+"""Full-size parity of the 500-problem uneven batch (n in [500, 20,000],
+d in [200, 8000], density 1-5 %, lambda log-uniform in [1e-3, 10], 609 M
+nonzeros), in the launch configuration the benchmark times: handles set up
+with autotuned plans, the hybrid persistent solve (per-problem iteration
+caps in the kernel, then the stream kernels replayed from graphs),
+tolerance 1e-8.
+
+Sizes the oracle cannot solve one by one in seconds are checked through
+properties that hold at any size: for every problem the relative residual
+of the returned w, recomputed on the host with the oracle's operator, is
+within the tolerance; for a sample (the problem with the most iterations,
+the one with the most nonzeros, and three drawn at random) the error to
+the exact solution (dense Cholesky) is within kappa(A) times that
+residual."""
+import numpy as np
+import pytest
+
+import datagen
+from oracle import krylov, operator as op
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rr():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1806_05826_amd as rr
+    return rr
+
+
+def test_fullsize_batched_hybrid(rr):
+    print("[batched full] generating 500 problems", flush=True)
+    batch = datagen.batched_problems(500, seed=5826 + 4000, n_range=(500, 20_000), d_range=(200, 8_000),
+                                     workers=16)
+    Rs, rhs, ws, lams = [], [], [], []
+    for i, (P, lam) in enumerate(batch):
+        k = int(min(800, max(8, -(-P.X.shape[1] // 10))))
+        Rs.append(rr.Ridge(P.X, n_clusters=k, seed=9, autotune=True))
+        rhs.append(torch.as_tensor(P.y, dtype=torch.float64, device="cuda"))
+        ws.append(torch.empty(P.X.shape[1], dtype=torch.float64, device="cuda"))
+        lams.append(lam)
+        if (i + 1) % 100 == 0:
+            print(f"[batched full] set up {i + 1}", flush=True)
+    st, infos = rr.rr_solve_batched([R.h for R in Rs], lams, rhs, ws, tol=1e-8, precond="vcycle",
+                                    max_iter=5000, persistent="hybrid", graph=True, chunk=16)
+    assert st == 0 and all(i["status"] == 0 for i in infos)
+    W = [w.cpu().numpy() for w in ws]
+    worst = 0.0
+    for (P, lam), w in zip(batch, W):
+        b = op.rhs(P.X, P.y)
+        rel = np.linalg.norm(b - op.apply_A(P.X, lam, w)) / np.linalg.norm(b)
+        worst = max(worst, rel)
+    print(f"[batched full] largest relative residual of the returned w (host, oracle operator): {worst:.2e}",
+          flush=True)
+    # the solves stop on the recursive residual at 1e-8; the recomputed one
+    # may exceed it by rounding of the recurrence
+    assert worst <= 1.2e-8
+    its = [i["iters"] for i in infos]
+    nnz = [P.X.nnz for P, _ in batch]
+    rng = np.random.default_rng(7)
+    sample = sorted({int(np.argmax(its)), int(np.argmax(nnz)), *rng.choice(500, 3, replace=False).tolist()})
+    for j in sample:
+        P, lam = batch[j]
+        b = op.rhs(P.X, P.y)
+        G = (P.X.T @ P.X).toarray() + lam * np.eye(P.X.shape[1])
+        wst = np.linalg.solve(G, b)
+        ev = np.linalg.eigvalsh(G)
+        kappa = ev[-1] / ev[0]
+        rel = np.linalg.norm(b - op.apply_A(P.X, lam, W[j])) / np.linalg.norm(b)
+        err = np.linalg.norm(W[j] - wst) / np.linalg.norm(wst)
+        print(f"[batched full] problem {j} ({P.X.shape[0]} x {P.X.shape[1]}, {P.X.nnz} nnz, lambda {lam:.2e}, "
+              f"{its[j]} its): error {err:.2e}, kappa {kappa:.2e}, residual {rel:.2e}", flush=True)
+        assert err <= 1.01 * kappa * rel + 1e-13
+    for R in Rs:
+        R.close()
