@@ -259,7 +259,7 @@ typedef struct {
   double setup_ms;         /* wall time of rr_setup                            */
   double kmeans_ms;        /* of which clustering                              */
   double plan_ms;          /* of which building (and tuning) the pass plans    */
-  int32_t tuned_rows_div;  /* lanes per row of the row pass (1, 2 or 4)         */
+  int32_t tuned_rows_div;  /* lanes per row of the row pass (1, 2, 4, 8 or 16)  */
   int32_t tuned_cols_div;  /* lane-stream divisor of the sliced column pass    */
   int32_t tune_cached;     /* 1: autotune reused an earlier measurement        */
   int32_t dense;           /* 1 for a handle made by rr_setup_dense (nnz =

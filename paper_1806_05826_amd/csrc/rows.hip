@@ -124,6 +124,8 @@ __global__ __launch_bounds__(kSliceBlock) void k_rows(int nlayer, int N, const i
     T sum = ((a0 + a1) + (a2 + a3)) + cs;
     if constexpr (L >= 2) sum += __shfl_xor(sum, 1, 64);
     if constexpr (L >= 4) sum += __shfl_xor(sum, 2, 64);
+    if constexpr (L >= 8) sum += __shfl_xor(sum, 4, 64);
+    if constexpr (L >= 16) sum += __shfl_xor(sum, 8, 64);
     const int row = c * (64 / L) + lane / L;
     if ((lane & (L - 1)) == 0 && row < N) u[row] = scale ? (T)((double)sum * scale[row]) : sum;
   }
@@ -217,45 +219,47 @@ __global__ __launch_bounds__(kSliceBlock) void k_rows_val(int nlayer, int N, con
     double sum = ((a0 + a1) + (a2 + a3)) + cs;
     if constexpr (L >= 2) sum += __shfl_xor(sum, 1, 64);
     if constexpr (L >= 4) sum += __shfl_xor(sum, 2, 64);
+    if constexpr (L >= 8) sum += __shfl_xor(sum, 4, 64);
+    if constexpr (L >= 16) sum += __shfl_xor(sum, 8, 64);
     const int row = c * (64 / L) + lane / L;
     if ((lane & (L - 1)) == 0 && row < N) u[row] = scale ? sum * scale[row] : sum;
   }
+}
+
+template <typename T, int L>
+static void rows_launch(const RowPlan& rp, const T* v, T* u, const double* scale, const int* done,
+                        hipStream_t s, const StageArgs& st) {
+  k_rows<T, L><<<rp.nblk, kSliceBlock, 0, s>>>(rp.nlayer, rp.N, rp.layer, rp.hidx, rp.cidx, v, rp.F, u, scale,
+                                               done, st);
 }
 
 template <typename T>
 static void rows_dispatch(const RowPlan& rp, const T* v, T* u, const double* scale, const int* done,
                           hipStream_t s, const StageArgs& st) {
   switch (rp.L) {
-    case 1:
-      k_rows<T, 1><<<rp.nblk, kSliceBlock, 0, s>>>(rp.nlayer, rp.N, rp.layer, rp.hidx, rp.cidx, v, rp.F, u,
-                                                   scale, done, st);
-      break;
-    case 2:
-      k_rows<T, 2><<<rp.nblk, kSliceBlock, 0, s>>>(rp.nlayer, rp.N, rp.layer, rp.hidx, rp.cidx, v, rp.F, u,
-                                                   scale, done, st);
-      break;
-    default:
-      k_rows<T, 4><<<rp.nblk, kSliceBlock, 0, s>>>(rp.nlayer, rp.N, rp.layer, rp.hidx, rp.cidx, v, rp.F, u,
-                                                   scale, done, st);
-      break;
+    case 1: rows_launch<T, 1>(rp, v, u, scale, done, s, st); break;
+    case 2: rows_launch<T, 2>(rp, v, u, scale, done, s, st); break;
+    case 4: rows_launch<T, 4>(rp, v, u, scale, done, s, st); break;
+    case 8: rows_launch<T, 8>(rp, v, u, scale, done, s, st); break;
+    default: rows_launch<T, 16>(rp, v, u, scale, done, s, st); break;
   }
+}
+
+template <int L>
+static void rows_val_launch(const RowPlan& rp, const double* v, double* u, const double* scale,
+                            const int* done, hipStream_t s, const StageArgs& st) {
+  k_rows_val<L><<<rp.nblk, kSliceBlock, 0, s>>>(rp.nlayer, rp.N, rp.layer, rp.hidx, rp.hval, rp.cidx, rp.cval,
+                                                v, rp.F, u, scale, done, st);
 }
 
 static void rows_val_dispatch(const RowPlan& rp, const double* v, double* u, const double* scale,
                               const int* done, hipStream_t s, const StageArgs& st) {
   switch (rp.L) {
-    case 1:
-      k_rows_val<1><<<rp.nblk, kSliceBlock, 0, s>>>(rp.nlayer, rp.N, rp.layer, rp.hidx, rp.hval, rp.cidx,
-                                                    rp.cval, v, rp.F, u, scale, done, st);
-      break;
-    case 2:
-      k_rows_val<2><<<rp.nblk, kSliceBlock, 0, s>>>(rp.nlayer, rp.N, rp.layer, rp.hidx, rp.hval, rp.cidx,
-                                                    rp.cval, v, rp.F, u, scale, done, st);
-      break;
-    default:
-      k_rows_val<4><<<rp.nblk, kSliceBlock, 0, s>>>(rp.nlayer, rp.N, rp.layer, rp.hidx, rp.hval, rp.cidx,
-                                                    rp.cval, v, rp.F, u, scale, done, st);
-      break;
+    case 1: rows_val_launch<1>(rp, v, u, scale, done, s, st); break;
+    case 2: rows_val_launch<2>(rp, v, u, scale, done, s, st); break;
+    case 4: rows_val_launch<4>(rp, v, u, scale, done, s, st); break;
+    case 8: rows_val_launch<8>(rp, v, u, scale, done, s, st); break;
+    default: rows_val_launch<16>(rp, v, u, scale, done, s, st); break;
   }
 }
 
@@ -295,7 +299,8 @@ void free_rows(RowPlan& rp) {
 rr_status build_rows(RowPlan& out, const std::vector<int>& ptr, const std::vector<int>& col, int N, int F,
                      int num_cu, int L, hipStream_t s, const std::vector<double>* val) {
   free_rows(out);
-  if (L != 1 && L != 2 && L != 4) return fail(RR_ERR_DEVICE, "internal: lanes per row must be 1, 2 or 4");
+  if (L != 1 && L != 2 && L != 4 && L != 8 && L != 16)
+    return fail(RR_ERR_DEVICE, "internal: lanes per row must be 1, 2, 4, 8 or 16");
   const int W = kSliceRows;
   const int rpl = 64 / L;
   const int nlayer = cdiv(N, rpl);

@@ -279,8 +279,8 @@ struct BatchScratch {
 // row of the row pass (div_rows) and the column pass's lane-stream divisor.
 struct SellTuning {
   int div_rows = 2, div_cols = 2, cached = 0, n = 0;
-  int cand_div[6] = {}, cand_pass[6] = {};
-  float cand_ms[6] = {};
+  int cand_div[8] = {}, cand_pass[8] = {};
+  float cand_ms[8] = {};
 };
 
 // Sparse matrix stored both ways.

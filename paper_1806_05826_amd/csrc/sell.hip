@@ -985,8 +985,10 @@ rr_status build_sell_plans(Sparse& X, hipStream_t s, int autotune, SellTuning* t
   const std::vector<double>* rvp = X.binary ? nullptr : &rv;
   const std::vector<double>* cvp = X.binary ? nullptr : &cv;
   RR_HIP(hipStreamSynchronize(s));
-  // defaults: two lanes per row once rows average 16 entries or more
-  int lanes = (X.N > 0 && (long long)X.nnz >= 16LL * X.N) ? 2 : 1, div_cols = 2;
+  // defaults: two lanes per row once rows average 16 entries or more, four
+  // from 64, eight from 256
+  int lanes = 1, div_cols = 2;
+  for (int t = 16; lanes < 8 && X.N > 0 && (long long)X.nnz >= (long long)t * X.N; t *= 4) lanes *= 2;
   if (autotune) {
     int dev = 0;
     RR_HIP(hipGetDevice(&dev));
@@ -1016,40 +1018,50 @@ rr_status build_sell_plans(Sparse& X, hipStream_t s, int autotune, SellTuning* t
       RR_HIP(dmalloc(&v, sizeof(double) * nmax));
       RR_HIP(dmalloc(&out, sizeof(double) * nmax));
       launch_fill(v, 1.0, nmax, s);
-      constexpr int kCand = 3, kRounds = 5;
-      const int cand[kCand] = {1, 2, 4};
-      RowPlan rplans[kCand];
-      SellPlan cplans[kCand];
-      float best[2][kCand];
+      // lanes per row: 1, 2, 4, and 8 and 16 for rows of 64 entries or more
+      // on average (few long rows need more lanes than layers to fill the
+      // chip); column lane-stream divisors: 1, 2, 4
+      constexpr int kCandMax = 5, kCandCols = 3, kRounds = 5;
+      const int cand[kCandMax] = {1, 2, 4, 8, 16};
+      const int ncr = (X.N > 0 && (long long)X.nnz >= 64LL * X.N) ? 5 : 3;
+      RowPlan rplans[kCandMax];
+      SellPlan cplans[kCandCols];
+      float best[2][kCandMax];
       rr_status st = RR_OK;
-      for (int c = 0; c < kCand && st == RR_OK; ++c) {
-        st = build_rows(rplans[c], rp, ci, X.N, X.F, X.num_cu, cand[c], s, rvp);
-        if (st == RR_OK) st = build_sell(cplans[c], cp, ri, X.F, X.N, X.num_cu, s, cand[c], cvp);
-        cplans[c].pass = 1;
+      for (int c = 0; c < kCandMax && st == RR_OK; ++c) {
         best[0][c] = best[1][c] = 1e30f;
+        if (c < ncr) st = build_rows(rplans[c], rp, ci, X.N, X.F, X.num_cu, cand[c], s, rvp);
+        if (st == RR_OK && c < kCandCols) {
+          st = build_sell(cplans[c], cp, ri, X.F, X.N, X.num_cu, s, cand[c], cvp);
+          cplans[c].pass = 1;
+        }
       }
       for (int round = 0; round < kRounds && st == RR_OK; ++round)
-        for (int c = 0; c < kCand && st == RR_OK; ++c) {
+        for (int c = 0; c < kCandMax && st == RR_OK; ++c) {
           float ms = 0.f;
-          st = time_rows(rplans[c], v, out, 4, s, &ms);
-          best[0][c] = std::min(best[0][c], ms);
-          if (st == RR_OK) st = time_pass(cplans[c], v, out, 4, s, &ms);
-          best[1][c] = std::min(best[1][c], ms);
+          if (c < ncr) {
+            st = time_rows(rplans[c], v, out, 4, s, &ms);
+            best[0][c] = std::min(best[0][c], ms);
+          }
+          if (st == RR_OK && c < kCandCols) {
+            st = time_pass(cplans[c], v, out, 4, s, &ms);
+            best[1][c] = std::min(best[1][c], ms);
+          }
         }
-      for (int c = 0; c < kCand; ++c) {
+      for (int c = 0; c < kCandMax; ++c) {
         free_rows(rplans[c]);
-        free_sell(cplans[c]);
+        if (c < kCandCols) free_sell(cplans[c]);
       }
       if (st == RR_OK) {
         int pick[2] = {0, 0};
         for (int pass = 0; pass < 2; ++pass)
-          for (int c = 1; c < kCand; ++c)
+          for (int c = 1; c < (pass == 0 ? ncr : kCandCols); ++c)
             if (best[pass][c] < 0.97f * best[pass][pick[pass]]) pick[pass] = c;
         lanes = cand[pick[0]];
         div_cols = cand[pick[1]];
         if (tuned) {
-          for (int c = 0; c < kCand; ++c)
-            for (int pass = 0; pass < 2 && tuned->n < 6; ++pass) {
+          for (int pass = 0; pass < 2; ++pass)
+            for (int c = 0; c < (pass == 0 ? ncr : kCandCols) && tuned->n < 8; ++c) {
               tuned->cand_div[tuned->n] = cand[c];
               tuned->cand_pass[tuned->n] = pass;
               tuned->cand_ms[tuned->n] = best[pass][c];

@@ -1,5 +1,7 @@
-"""Autotuned sliced plans (rr_setup_opts.autotune): the tuner picks each
-pass's lane-stream divisor among {1, 2, 4} by timing, caches it per device
+"""Autotuned sliced plans (rr_setup_opts.autotune): the tuner picks the
+row pass's lanes per row among {1, 2, 4} (and 8, 16 for rows of 64 entries
+or more on average) and the column pass's lane-stream divisor among
+{1, 2, 4} by timing, caches it per device
 and shape bucket, and the tuned plans compute the same operator (bit-exact
 on integer vectors) and solve to the oracle's converged iterate."""
 import numpy as np
@@ -42,3 +44,25 @@ def test_autotune_choice_cache_and_results(rr):
     x_t, inf_t = krylov.solve(P.X, P.y, 1.0, "vcycle", lab, fc, tol=1e-13, max_iter=5000)
     w, info = R1.solve(1.0, P.y, precond="vcycle", fixed_iters=inf_t.iters)
     assert np.linalg.norm(host(w) - x_t) <= 1e-10 * np.linalg.norm(x_t)
+
+
+def test_long_rows_lanes(rr):
+    """Rows of about 300 entries: the default takes 8 lanes per row, the
+    tuner chooses among 1 to 16; both plans give the exact operator on an
+    integer vector, and the handle with the tuned plan solves to the
+    oracle's converged iterate."""
+    P = datagen.sparse_problem(3000, 6000, 300, seed=93)
+    v = np.random.default_rng(4).integers(-50, 50, P.X.shape[1]).astype(np.float64)
+    ref = op.apply_A(P.X, 0.0, v)
+    R0 = rr.Ridge(P.X)
+    assert R0.info["tuned_rows_div"] == 8
+    assert np.array_equal(host(R0.apply_operator(0.0, v)), ref)
+    R0.close()
+    R = rr.Ridge(P.X, autotune=True)
+    print(f"[autotune] long rows: {R.info['tuned_rows_div']} lanes per row", flush=True)
+    assert R.info["tuned_rows_div"] in (1, 2, 4, 8, 16)
+    assert np.array_equal(host(R.apply_operator(0.0, v)), ref)
+    x, inf = krylov.solve(P.X, P.y, 2.0, "jacobi", tol=1e-13)
+    w, info = R.solve(2.0, P.y, precond="jacobi", fixed_iters=inf.iters)
+    assert np.linalg.norm(host(w) - x) <= 1e-10 * np.linalg.norm(x)
+    R.close()
