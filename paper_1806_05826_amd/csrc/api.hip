@@ -119,6 +119,8 @@ void free_work(Work& w) {
     dfree(w.X.sell_csc.part);
     dfree(w.X.csc_plan.head); dfree(w.X.csc_plan.tail);
     dfree(w.rplan.head); dfree(w.rplan.tail); dfree(w.rplan.cpart);
+    dfree(w.xp_part);
+    dfree(w.xr.cpart);
   }
   w.graph.reset();
   if (w.graph.ev) (void)hipEventDestroy(w.graph.ev);
@@ -192,6 +194,10 @@ rr_status get_work_set(rr_handle* h, int k, Work** out) {
     RR_TRY(alloc_work(*w, h->X.F, h->X.N, h->FC, h->npartials));
     if (h->restrict_plan.ncpart > 0) RR_TRY(dalloc(&w->rplan.cpart, h->restrict_plan.ncpart));
     if (h->X.sliced) RR_TRY(dalloc(&w->X.sell_csc.part, h->X.sell_csc.nout));
+    w->xr = h->xp_restrict;
+    w->xr.cpart = nullptr;
+    if (h->xp.nblk > 0) RR_TRY(dalloc(&w->xp_part, h->xp.nout));
+    if (h->xp_restrict.ncpart > 0) RR_TRY(dalloc(&w->xr.cpart, h->xp_restrict.ncpart));
     if (!h->X.binary) {
       RR_TRY(dalloc(&w->X.csc_plan.head, h->X.csc_plan.nblocks));
       RR_TRY(dalloc(&w->X.csc_plan.tail, h->X.csc_plan.nblocks));
@@ -216,6 +222,8 @@ void destroy_handle(rr_handle* h) {
   free_batch_plan(X.bplan);
   free_merge_plan(h->restrict_plan);
   free_cluster_rows(h->crow);
+  free_sell(h->xp);
+  free_merge_plan(h->xp_restrict);
   dfree(h->colnorm); dfree(h->gersh); dfree(h->fperm); dfree(h->finv);
   dfree(h->labels); dfree(h->centres); dfree(h->csize); dfree(h->cscale);
   dfree(h->perm); dfree(h->cpos); dfree(h->coff); dfree(h->K);
@@ -362,6 +370,8 @@ rr_status setup_impl(const rr_csr* Xin, const rr_setup_opts* o, hipStream_t s, r
   RR_HIP(hipMemsetAsync(w.sc, 0, sizeof(Scalars), s));
   w.X = h->X;
   w.rplan = h->restrict_plan;
+  w.xp_part = h->xp.part;
+  w.xr = h->xp_restrict;
   RR_HIP(hipStreamSynchronize(s));
   RR_HIP(hipGetLastError());
   // buffers of later solves, reserved now so that those solves allocate
@@ -705,6 +715,31 @@ rr_status precond_two_level(rr_handle* h, Work& w, Prof& pf, int tag, int kind, 
   // (on the iteration that converges this is wasted work, nothing more)
   if (w.block)
     launch_block_smooth(h, sl.Dinv, omega, r, nullptr, nullptr, nullptr, w.e1, nullptr, done, s);
+  const bool label_rows = h->crow.nlayer > 0 && !h->lsw;
+  if (kind == PK_VCYCLE && label_rows && !w.block && !snap && h->X.binary && h->xp.nblk > 0 && w.xp_part &&
+      (w.xr.ncpart == 0 || w.xr.cpart) && restrict_gemv_fusable(w.xr, h->FC)) {
+    // P^T (r - A e1) = P^T (r - lam e1) - (X P)^T (X e1): the row pass's u
+    // goes straight to the column pass of X P (F_C segments), so the residual
+    // r - A e1 is never formed at the fine level
+    RR_TRY(op_csr(h, w, pf, tag, w.e1, s, stage));
+    SellPlan xp = h->xp;
+    xp.part = w.xp_part;
+    launch_sell_gather(xp, w.u, s, done);
+    launch_restrict_gemv_xp(w.xr, h->perm, r, w.e1, lam, h->cscale, xp, w.xp_part, w.c, h->FC, sl.Ainv, w.yc,
+                            done, s);
+    launch_cluster_rows(h, w.yc, w.X.rw, w.u, done, s);
+    Epi ep = base_epi(w, lam);
+    ep.p = w.e1;
+    ep.r = r;
+    ep.omega = omega;
+    ep.out = z;
+    ep.partials = w.parts.rz;
+    ep.labels = h->labels;
+    ep.cscale = h->cscale;
+    ep.yc = w.yc;
+    RR_TRY(op_csc(h, w, pf, tag, EPI_POST_P, ep, s, n_rz));
+    return RR_OK;
+  }
   // V(1,1): rho1 = r - A e1
   RR_TRY(op_csr(h, w, pf, tag, w.e1, s, stage));
   Epi e = base_epi(w, lam);
@@ -732,7 +767,6 @@ rr_status precond_two_level(rr_handle* h, Work& w, Prof& pf, int tag, int kind, 
   // u still holds X e1 (the label table carries the square-root-average P).
   // With the point smoother, e2 = e1 + P yc is formed inside the column
   // pass's epilogue, the only place that reads it.
-  const bool label_rows = h->crow.nlayer > 0 && !h->lsw;
   if (label_rows && !w.block && h->X.binary) {
     launch_cluster_rows(h, w.yc, w.X.rw, w.u, done, s);
     Epi ep = base_epi(w, lam);

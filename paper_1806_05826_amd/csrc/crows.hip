@@ -122,6 +122,8 @@ void free_cluster_rows(ClusterRows& cr) {
 rr_status build_cluster_rows(rr_handle* h, hipStream_t s) {
   ClusterRows& cr = h->crow;
   free_cluster_rows(cr);
+  free_sell(h->xp);
+  free_merge_plan(h->xp_restrict);
   const Sparse& X = h->X;
   const int N = X.N, F = X.F, FC = h->FC;
   if (!X.binary || FC < 1 || FC > kMaxCrClusters || N < 1) return RR_OK;
@@ -168,6 +170,11 @@ rr_status build_cluster_rows(rr_handle* h, hipStream_t s) {
   RR_HIP(hipMemcpyAsync(cr.rowid, rowid.data(), sizeof(int) * rowid.size(), hipMemcpyHostToDevice, s));
   RR_HIP(hipStreamSynchronize(s));
   cr.nlayer = nlayer;
+  // the column pass of X P, for the V(1,1) restriction from the row pass
+  if (X.sliced) {
+    RR_TRY(build_xp_plan(h->xp, rp, ci, lab, N, FC, X.num_cu, h->tuning.div_cols, s));
+    RR_TRY(build_xp_restrict(h->xp_restrict, h->xp, h->coff, FC, F, s));
+  }
   return RR_OK;
 }
 

@@ -138,6 +138,12 @@ struct Epi {
   const double* cscale;  // the prolongation's 1/sqrt(n_s)
   const double* yc;      // and the coarse correction
   const int* opos;       // EPI_RESID: store segment s at opos[s] (cluster order), or at s
+  // restriction from the row pass (k_seg1 with XP): cluster s subtracts its
+  // pieces xpart[xpos[q]], q in [xbase[s], xbase[s+1]), the partial sums of
+  // (X P)^T u over (cluster, row slice) pairs
+  const int* xbase;
+  const int* xpos;
+  const double* xpart;
 };
 
 // Single-precision vectors of an inner solve of iterative refinement.
@@ -363,6 +369,8 @@ struct Work {
   // different sets of one handle can run at the same time.
   Sparse X;
   MergePlan rplan;
+  double* xp_part = nullptr;      // partial sums of the X P column pass (this set's own)
+  MergePlan xr;                   // the X P restriction's items with this set's chunk sums
   bool extra = false;             // an additional set (owns those buffers)
   bool block = false;             // the running solve smooths with the block smoother
   int rsteps = 2;                 // CG steps of the rougher (RR_PRECOND_ROUGHER)
@@ -447,6 +455,8 @@ struct rr_handle {
   int* coff = nullptr;          // [FC+1] cluster offsets into perm
   rr::MergePlan restrict_plan;  // segments = clusters over perm
   ClusterRows crow;             // label table for the V(1,1) second row pass
+  rr::SellPlan xp;              // X's entries by cluster: column pass of X P (V(1,1) restriction)
+  rr::MergePlan xp_restrict;    // the restriction's wave items with xp (build_xp_restrict)
   double* K = nullptr;          // [FC*FC] coarse Gram
   double* rw = nullptr;         // [N] row weights (owned), null when unweighted
   double* wxc = nullptr;        // [FCp x Np] D^1/2 X P as rows, for the weighted coarse matrix
@@ -551,7 +561,13 @@ int sell_reduce_grid(const SellPlan& sp);
 int launch_sell32(const SellPlan& sp, float* part, const float* v, int mode, const Epi32& e,
                   const int* done, hipStream_t s, const StageArgs* stage = nullptr);
 // The gather kernel alone (partial sums only; no reduction, no epilogue).
-void launch_sell_gather(const SellPlan& sp, const double* v, hipStream_t s);
+void launch_sell_gather(const SellPlan& sp, const double* v, hipStream_t s, const int* done = nullptr);
+// The column pass of X P for 0/1 X: segment s = cluster s holds the rows of
+// every entry of X in a column of cluster s (rows ascending, repeated once
+// per entry), so the pass's pieces add up to ((X P)^T u)_s / P_js.  rp/ci:
+// X's CSR on the host, lab: the cluster of every feature.
+rr_status build_xp_plan(SellPlan& xp, const std::vector<int>& rp, const std::vector<int>& ci,
+                        const std::vector<int>& lab, int N, int FC, int num_cu, int div, hipStream_t s);
 void launch_rows(const RowPlan& rp, const double* v, double* u, const double* scale, const int* done,
                  hipStream_t s, const StageArgs* stage = nullptr);
 void launch_rows32(const RowPlan& rp, const float* v, float* u, const int* done, hipStream_t s,
@@ -670,6 +686,21 @@ void launch_restrict(const rr_handle* h, const MergePlan& mp, const double* v, d
 bool restrict_gemv_fusable(const MergePlan& mp, int n);
 void launch_restrict_gemv(const MergePlan& mp, const double* v_sorted, const double* val, const double* scale,
                           double* c, int n, const double* Ainv, double* yc, const int* done, hipStream_t s);
+// The restriction of r - A e1 and the coarse GEMV from the row pass's u = X e1
+// (V(1,1), 0/1 X, square-root-average P): launch_sell_gather of the X P plan
+// xp into xpart first; then c_s = P_js (sum_{j in s} (r_j - lam e1_j) - the
+// cluster's xp pieces) and yc = Ainv c, in two kernels.  mp: the plan of
+// build_xp_restrict (with this work set's cpart), perm: the cluster order;
+// usable when restrict_gemv_fusable(mp, n).
+void launch_restrict_gemv_xp(const MergePlan& mp, const int* perm, const double* r, const double* e1, double lam,
+                             const double* scale, const SellPlan& xp, const double* xpart, double* c, int n,
+                             const double* Ainv, double* yc, const int* done, hipStream_t s);
+// Wave items of that restriction (setup only): the restriction plan's items
+// over the clusters (offsets d_coff into the cluster order of F features),
+// except that a cluster with more than 128 X P pieces (or more than 1024
+// members) is finished from chunk sums, with extra items that sum its pieces
+// 512 at a time.
+rr_status build_xp_restrict(MergePlan& mp, const SellPlan& xp, const int* d_coff, int FC, int F, hipStream_t s);
 // the same from v stored in cluster order (v[k] belongs to feature perm[k])
 void launch_restrict_sorted(const rr_handle* h, const MergePlan& mp, const double* v, double* out,
                             const int* done, hipStream_t s);

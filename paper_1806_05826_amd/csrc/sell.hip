@@ -200,8 +200,8 @@ __device__ inline void sell_body(const int* __restrict__ wrange, const int* __re
   }
 }
 
-// PASS only names the instantiation (0: rows of X, 1: columns of X), so a
-// profiler reports the two operator passes apart.
+// PASS only names the instantiation (0: rows of X, 1: columns of X, 2: the
+// columns of X P), so a profiler reports the passes apart.
 template <int PASS>
 __global__ __launch_bounds__(kSliceBlock) void k_sell(const int* __restrict__ wrange,
                                                      const int* __restrict__ bslice,
@@ -548,18 +548,21 @@ int launch_sell(const SellPlan& sp, const double* v, int mode, const Epi& e, con
   return collapse_parts(e.partials, sell_reduce_grid(sp), done, s);
 }
 
-void launch_sell_gather(const SellPlan& sp, const double* v, hipStream_t s) {
+void launch_sell_gather(const SellPlan& sp, const double* v, hipStream_t s, const int* done) {
   if (sp.nblk == 0) return;
   const StageArgs st{};
   if (sp.val)
     k_sell_val<1><<<sp.nblk, kSliceBlock, 0, s>>>(sp.wrange, sp.bslice, sp.task, sp.idx, sp.val, v, sp.gdim,
-                                                  sp.W, sp.part, nullptr, st);
+                                                  sp.W, sp.part, done, st);
   else if (sp.pass == 0)
     k_sell<0><<<sp.nblk, kSliceBlock, 0, s>>>(sp.wrange, sp.bslice, sp.task, sp.idx, v, sp.gdim,
-                                             sp.W, sp.part, nullptr, st);
+                                             sp.W, sp.part, done, st);
+  else if (sp.pass == 2)
+    k_sell<2><<<sp.nblk, kSliceBlock, 0, s>>>(sp.wrange, sp.bslice, sp.task, sp.idx, v, sp.gdim,
+                                             sp.W, sp.part, done, st);
   else
     k_sell<1><<<sp.nblk, kSliceBlock, 0, s>>>(sp.wrange, sp.bslice, sp.task, sp.idx, v, sp.gdim,
-                                             sp.W, sp.part, nullptr, st);
+                                             sp.W, sp.part, done, st);
 }
 
 void free_sell(SellPlan& sp) {
@@ -919,6 +922,27 @@ rr_status build_sell(SellPlan& sp, const std::vector<int>& ptr, const std::vecto
   }
   RR_HIP(hipStreamSynchronize(s));
   sp.idx_bytes = (long long)B.idx.size() * 2 + (long long)B.val.size() * 8;
+  return RR_OK;
+}
+
+rr_status build_xp_plan(SellPlan& xp, const std::vector<int>& rp, const std::vector<int>& ci,
+                        const std::vector<int>& lab, int N, int FC, int num_cu, int div, hipStream_t s) {
+  free_sell(xp);
+  const int nnz = rp[N];
+  // cluster-major lists of X's entries: one pass over the rows in order
+  // leaves every cluster's rows ascending, as the slicing needs
+  std::vector<int> ptr(FC + 1, 0), rows(std::max(1, nnz));
+  for (int e = 0; e < nnz; ++e) {
+    const int c = lab[ci[e]];
+    if (c < 0 || c >= FC) return fail(RR_ERR_DEVICE, "internal: label out of range");
+    ++ptr[c + 1];
+  }
+  for (int c = 0; c < FC; ++c) ptr[c + 1] += ptr[c];
+  std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+  for (int i = 0; i < N; ++i)
+    for (int e = rp[i]; e < rp[i + 1]; ++e) rows[fill[lab[ci[e]]]++] = i;
+  RR_TRY(build_sell(xp, ptr, rows, FC, N, num_cu, s, div, nullptr));
+  xp.pass = 2;
   return RR_OK;
 }
 

@@ -275,14 +275,26 @@ __global__ __launch_bounds__(kBlock) void k_segfix(const int4* __restrict__ span
 // more wave per such segment (second kernel) adds its chunk sums in chunk
 // order and finishes it.  Entry q is v[idx[q]], or v[q] when v is already in
 // segment order (IDX false: one load, coalesced).
+// XP (with IDX, the plan of build_xp_restrict): entry q is r[j] - lam e1[j]
+// (Epi r, p, lam; j = idx[q]); an item that finishes cluster s subtracts the
+// sum of its X P column-pass pieces (at most kXpPieces, loaded ahead of the
+// entries), and a piece item (x = -1 - s) stores minus the sum of pieces
+// [y, z) (at most 512) in its chunk slot, so that cluster s gets
+// (P^T (r - lam e1) - (X P)^T u)_s / P_js = (P^T (r - A e1))_s / P_js with
+// u = X e1.  Pieces are added lane-strided, then by the fixed butterfly.
 constexpr int kWaveSeg = 1024;
-constexpr int kSegBlock = 1024;
-template <int MODE, bool VAL, bool IDX>
+constexpr int kSegBlock = 256;
+constexpr int kXpPieces = 128;       // pieces a finishing item adds itself
+constexpr int kXpPieceItem = 512;    // pieces of one piece item
+
+
+template <int MODE, bool VAL, bool IDX, bool XP = false>
 __global__ __launch_bounds__(kSegBlock) void k_seg1(const int4* __restrict__ witem, int nw,
                                                     const int* __restrict__ idx,
                                                     const double* __restrict__ val,
                                                     const double* __restrict__ v, Epi e,
                                                     double* __restrict__ cpart, const int* done) {
+  static_assert(!XP || (IDX && !VAL), "the X P form gathers r and e1 through the cluster order");
   if (is_done(done)) return;
   constexpr int U = 16;
   static_assert(U * 64 == kWaveSeg, "a wave item is at most one batch per lane");
@@ -290,14 +302,55 @@ __global__ __launch_bounds__(kSegBlock) void k_seg1(const int4* __restrict__ wit
   const int lane = threadIdx.x & 63;
   if (wv >= nw) return;
   const int4 it = witem[wv];
+  if constexpr (XP) {
+    if (it.x < 0) {   // piece item (wave-uniform)
+      constexpr int M = kXpPieceItem / 64;
+      int pp[M];
+      double pv[M];
+#pragma unroll
+      for (int m = 0; m < M; ++m) pp[m] = it.y + lane + 64 * m < it.z ? e.xpos[it.y + lane + 64 * m] : -1;
+#pragma unroll
+      for (int m = 0; m < M; ++m) pv[m] = pp[m] >= 0 ? e.xpart[pp[m]] : 0.0;
+      double c = 0.0;
+#pragma unroll
+      for (int m = 0; m < M; ++m) c += pv[m];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+      if (lane == 0) cpart[it.w] = -c;
+      return;
+    }
+  }
   int j[U];
 #pragma unroll
   for (int k = 0; k < U; ++k) {
     const int q = it.y + lane + 64 * k;
     j[k] = q < it.z ? (IDX ? idx[q] : q) : -1;
   }
+  constexpr int XM = kXpPieces / 64;
+  double xv[XM];
+#pragma unroll
+  for (int m = 0; m < XM; ++m) xv[m] = 0.0;
+  if constexpr (XP) {
+    if (it.w < 0) {   // this item finishes its cluster (wave-uniform)
+      const int q0 = e.xbase[it.x], q1 = e.xbase[it.x + 1];
+      int pp[XM];
+#pragma unroll
+      for (int m = 0; m < XM; ++m) pp[m] = q0 + lane + 64 * m < q1 ? e.xpos[q0 + lane + 64 * m] : -1;
+#pragma unroll
+      for (int m = 0; m < XM; ++m) xv[m] = pp[m] >= 0 ? e.xpart[pp[m]] : 0.0;
+    }
+  }
   double t = 0.0;
-  if constexpr (VAL) {
+  if constexpr (XP) {
+    double a[U], b[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      a[k] = j[k] >= 0 ? e.r[j[k]] : 0.0;
+      b[k] = j[k] >= 0 ? e.p[j[k]] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) t += a[k] - e.lam * b[k];
+  } else if constexpr (VAL) {
     double a[U];
 #pragma unroll
     for (int k = 0; k < U; ++k) a[k] = j[k] >= 0 ? val[it.y + lane + 64 * k] : 0.0;
@@ -309,6 +362,16 @@ __global__ __launch_bounds__(kSegBlock) void k_seg1(const int4* __restrict__ wit
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+  if constexpr (XP) {
+    if (it.w < 0) {
+      double c = 0.0;
+#pragma unroll
+      for (int m = 0; m < XM; ++m) c += xv[m];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+      t -= c;
+    }
+  }
   if (lane == 0) {
     if (it.w < 0) {
       double dot = 0.0;
@@ -345,7 +408,8 @@ __global__ __launch_bounds__(kSegBlock) void k_seg1_fin(const int4* __restrict__
 // order and with the scaling of k_seg1_fin (so y is bitwise the same), then
 // one wave per row as in k_gemv.
 constexpr int kGemvFinMax = 4096;
-__global__ __launch_bounds__(kBlock) void k_gemv_fin(int n, const double* __restrict__ A,
+constexpr int kGemvFinBlock = 256;
+__global__ __launch_bounds__(kGemvFinBlock) void k_gemv_fin(int n, const double* __restrict__ A,
                                                      const double* __restrict__ c,
                                                      const int4* __restrict__ fitem, int nf,
                                                      const double* __restrict__ cpart,
@@ -354,9 +418,9 @@ __global__ __launch_bounds__(kBlock) void k_gemv_fin(int n, const double* __rest
   if (is_done(done)) return;
   __shared__ double xs[kGemvFinMax];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int i = threadIdx.x; i < n; i += kBlock) xs[i] = c[i];
+  for (int i = threadIdx.x; i < n; i += kGemvFinBlock) xs[i] = c[i];
   __syncthreads();
-  for (int f = wv; f < nf; f += kBlock / 64) {
+  for (int f = wv; f < nf; f += kGemvFinBlock / 64) {
     const int4 it = fitem[f];
     double t = 0.0;
     for (int k = lane; k < it.z; k += 64) t += cpart[it.y + k];
@@ -365,7 +429,7 @@ __global__ __launch_bounds__(kBlock) void k_gemv_fin(int n, const double* __rest
     if (lane == 0) xs[it.x] = scale ? t * scale[it.x] : t;
   }
   __syncthreads();
-  const int row = blockIdx.x * (kBlock / 64) + wv;
+  const int row = blockIdx.x * (kGemvFinBlock / 64) + wv;
   if (row >= n) return;
   const double* a = A + (size_t)row * n;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -408,7 +472,25 @@ void launch_restrict_gemv(const MergePlan& mp, const double* v_sorted, const dou
       k_seg1<EPI_STORE, false, false><<<grid, kSegBlock, 0, s>>>(mp.witem, mp.nwitem, nullptr, nullptr, v_sorted,
                                                                 e, mp.cpart, done);
   }
-  k_gemv_fin<<<cdiv(n, kBlock / 64), kBlock, 0, s>>>(n, Ainv, c, mp.fitem, mp.nfitem, mp.cpart, scale, yc, done);
+  k_gemv_fin<<<cdiv(n, kGemvFinBlock / 64), kGemvFinBlock, 0, s>>>(n, Ainv, c, mp.fitem, mp.nfitem, mp.cpart, scale, yc, done);
+}
+
+void launch_restrict_gemv_xp(const MergePlan& mp, const int* perm, const double* r, const double* e1, double lam,
+                             const double* scale, const SellPlan& xp, const double* xpart, double* c, int n,
+                             const double* Ainv, double* yc, const int* done, hipStream_t s) {
+  Epi e{};
+  e.out = c;
+  e.scale = scale;
+  e.r = r;
+  e.p = e1;
+  e.lam = lam;
+  e.xbase = xp.sbase;
+  e.xpos = xp.pos;
+  e.xpart = xpart;
+  const int grid = cdiv(mp.nwitem, kSegBlock / 64);
+  k_seg1<EPI_SCALE, false, true, true><<<grid, kSegBlock, 0, s>>>(mp.witem, mp.nwitem, perm, nullptr, nullptr, e,
+                                                                  mp.cpart, done);
+  k_gemv_fin<<<cdiv(n, kGemvFinBlock / 64), kGemvFinBlock, 0, s>>>(n, Ainv, c, mp.fitem, mp.nfitem, mp.cpart, scale, yc, done);
 }
 
 template <int MODE>
@@ -549,6 +631,53 @@ rr_status build_chunk_plan(MergePlan& mp, const int* d_seg_ptr, int nseg, hipStr
     RR_HIP(dmalloc(&mp.witem, sizeof(int4) * mp.nwitem));
     RR_HIP(hipMemcpyAsync(mp.witem, wi.data(), sizeof(int4) * mp.nwitem, hipMemcpyHostToDevice, s));
   }
+  if (mp.nfitem) {
+    RR_HIP(dmalloc(&mp.fitem, sizeof(int4) * mp.nfitem));
+    RR_HIP(hipMemcpyAsync(mp.fitem, fi.data(), sizeof(int4) * mp.nfitem, hipMemcpyHostToDevice, s));
+  }
+  if (np) RR_HIP(dmalloc(&mp.cpart, sizeof(double) * np));
+  RR_HIP(hipStreamSynchronize(s));
+  return RR_OK;
+}
+
+rr_status build_xp_restrict(MergePlan& mp, const SellPlan& xp, const int* d_coff, int FC, int F, hipStream_t s) {
+  free_merge_plan(mp);
+  std::vector<int> ptr(FC + 1), sb(FC + 1);
+  RR_HIP(hipMemcpyAsync(ptr.data(), d_coff, sizeof(int) * (FC + 1), hipMemcpyDeviceToHost, s));
+  RR_HIP(hipMemcpyAsync(sb.data(), xp.sbase, sizeof(int) * (FC + 1), hipMemcpyDeviceToHost, s));
+  RR_HIP(hipStreamSynchronize(s));
+  if (xp.S != FC || ptr[0] != 0 || ptr[FC] != F || sb[0] != 0 || sb[FC] != xp.nitems)
+    return fail(RR_ERR_DEVICE, "internal: X P plan does not match the clusters");
+  std::vector<int4> wi, fi;
+  int np = 0;
+  for (int q = 0; q < FC; ++q) {
+    const int a = ptr[q], z = ptr[q + 1], p0 = sb[q], p1 = sb[q + 1];
+    if (z < a || p1 < p0) return fail(RR_ERR_DEVICE, "internal: decreasing segment offsets");
+    if (z - a <= kWaveSeg && p1 - p0 <= kXpPieces) {
+      wi.push_back(make_int4(q, a, z, -1));
+      continue;
+    }
+    const int nc = std::max(1, cdiv(z - a, kWaveSeg)), npc = cdiv(p1 - p0, kXpPieceItem);
+    fi.push_back(make_int4(q, np, nc + npc, 0));
+    for (int c = 0; c < nc; ++c) {
+      const int c0 = a + (int)((long long)(z - a) * c / nc), c1 = a + (int)((long long)(z - a) * (c + 1) / nc);
+      wi.push_back(make_int4(q, c0, c1, np++));
+    }
+    for (int c = 0; c < npc; ++c)
+      wi.push_back(make_int4(-1 - q, p0 + c * kXpPieceItem, std::min(p1, p0 + (c + 1) * kXpPieceItem), np++));
+  }
+  for (const int4& w : wi) {
+    const bool piece = w.x < 0;
+    const int lim = piece ? xp.nitems : F, len = piece ? kXpPieceItem : kWaveSeg;
+    if (w.y < 0 || w.z > lim || w.z - w.y > len || w.z < w.y || w.w >= np || (piece && w.w < 0))
+      return fail(RR_ERR_DEVICE, "internal: segment item out of range");
+  }
+  mp.nseg = FC;
+  mp.nwitem = (int)wi.size();
+  mp.nfitem = (int)fi.size();
+  mp.ncpart = np;
+  RR_HIP(dmalloc(&mp.witem, sizeof(int4) * std::max<size_t>(1, wi.size())));
+  if (!wi.empty()) RR_HIP(hipMemcpyAsync(mp.witem, wi.data(), sizeof(int4) * wi.size(), hipMemcpyHostToDevice, s));
   if (mp.nfitem) {
     RR_HIP(dmalloc(&mp.fitem, sizeof(int4) * mp.nfitem));
     RR_HIP(hipMemcpyAsync(mp.fitem, fi.data(), sizeof(int4) * mp.nfitem, hipMemcpyHostToDevice, s));

@@ -607,3 +607,42 @@ def test_tlfcg_needs_flexible_cg(rr, clustered):
     with pytest.raises(rr.RRError) as e:
         R.solve(1.0, P.y, precond="rougher")
     assert e.value.status == rr.RR_ERR_INVALID_ARG
+
+
+def test_vcycle_restriction_from_the_row_pass(rr):
+    """The V(1,1) cycle's restriction P^T (r - A e1), formed without the
+    fine-level residual as P^T (r - lam e1) - (X P)^T (X e1): a cluster of
+    14 dense features (hundreds of X P column-pass pieces, summed by piece
+    items), a cluster of 2000 members (finished from chunk sums) and 20 small
+    clusters.  B r and the converged solve against the oracle."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(61)
+    N, F, nd = 40_000, 3000, 14
+    rd, cd = np.nonzero(rng.random((N, nd)) < 0.9)
+    rs = np.repeat(np.arange(N), 10)
+    cs = rng.integers(nd, F, size=rs.size)
+    X = sp.csr_matrix((np.ones(rd.size + rs.size), (np.r_[rd, rs], np.r_[cd, cs])), shape=(N, F))
+    X.sum_duplicates()
+    X.data[:] = 1.0
+    lab = np.empty(F, dtype=np.int64)
+    lab[:12] = 0
+    lab[12:2012] = 1
+    lab[2012:] = 2 + np.arange(F - 2012) % 20
+    fc = 22
+    print(f"[xp restriction] N={N} F={F} nnz={X.nnz}", flush=True)
+    lam = 1.0
+    R = rr.Ridge(X, labels=lab)
+    omega = op.omega_gershgorin(X, lam)
+    B, _ = precond.make("vcycle", X, lam, lab, fc, omega)
+    r = rng.standard_normal(F)
+    z = host(R.apply_precond(lam, r, "vcycle"))
+    zr = B(r)
+    kappa_c = np.linalg.cond(coarse.coarse_matrix(X, lab, fc, lam))
+    err = np.linalg.norm(z - zr) / np.linalg.norm(zr)
+    print(f"[xp restriction] B r relative error {err:.2e}, bound {32 * kappa_c * 2**-52:.2e}", flush=True)
+    assert err <= 32 * kappa_c * 2**-52
+    y = rng.standard_normal(N)
+    x_t, inf_t = krylov.solve(X, y, lam, "vcycle", lab, fc, tol=1e-13, max_iter=2000)
+    w, info = R.solve(lam, y, precond="vcycle", fixed_iters=inf_t.iters)
+    assert np.linalg.norm(host(w) - x_t) <= 1e-10 * np.linalg.norm(x_t)
+    R.close()
