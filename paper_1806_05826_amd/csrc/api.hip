@@ -1065,7 +1065,7 @@ rr_status Solve::queue_chunk() {
     // changing state lives in device memory): capture them once per
     // signature, then replay
     GraphKey key{kind, lam, omega, sl ? sl->Ainv : nullptr, xref, op.residual_history, chunk,
-                 (sl && w.block) ? sl->Dinv : nullptr};
+                 (sl && w.block) ? sl->Dinv : nullptr, cycle32};
     // the legacy default stream cannot be captured: use the set's own
     // stream, ordered after and before the caller's with events
     hipStream_t gs = s;

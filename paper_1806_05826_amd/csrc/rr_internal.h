@@ -331,9 +331,11 @@ struct GraphKey {
   const double* history = nullptr;
   int chunk = 0;
   const double* dinv = nullptr;   // block smoother's inverses (null: point smoother)
+  bool cycle32 = false;           // the preconditioner's cycle in FP32
   bool operator==(const GraphKey& o) const {
     return kind == o.kind && lam == o.lam && omega == o.omega && ainv == o.ainv &&
-           xref == o.xref && history == o.history && chunk == o.chunk && dinv == o.dinv;
+           xref == o.xref && history == o.history && chunk == o.chunk && dinv == o.dinv &&
+           cycle32 == o.cycle32;
   }
 };
 struct ChunkGraph {
