@@ -50,34 +50,46 @@ __device__ inline double group_sum(double s) {
   return s;
 }
 
-// sum of vec[idx[k] - shift] over k = a + sub, a + sub + G, ... < z: a
-// lane's entries in batches of 16 index loads in flight (one workgroup per
-// CU streams the problem's indexes, so its memory-level parallelism is what
-// bounds it), two accumulators in a fixed order
-template <int G, typename I>
-__device__ inline double lane_gather(const I* __restrict__ idx, const double* vec, int a, int z,
-                                     int sub, int shift) {
+// sum of vec[idx[k]] over k in [a, z) by the G lanes of a group, lane sub
+// taking its share in a fixed order: the 4-aligned body [a4, z4) in groups
+// of four entries (one 8-byte load each; group q goes to lane q mod G, 16
+// loads, 64 entries, in flight per lane: one workgroup per CU streams the
+// problem's indexes, so the bytes it keeps in flight bound it), then the
+// unaligned head [a, a4) and tail [z4, z), one entry per lane; two
+// accumulators.  idx is 8-byte aligned.
+template <int G>
+__device__ inline double lane_gather(const uint16_t* __restrict__ idx, const double* vec, int a, int z,
+                                     int sub) {
   constexpr int B = 16;
   double s0 = 0.0, s1 = 0.0;
-  int k = a + sub;
-  for (; k + (B - 1) * G < z; k += B * G) {
-    int i[B];
+  const int a4 = min(z, (a + 3) & ~3);
+  const int z4 = max(a4, z & ~3);
+  const uint2* p = reinterpret_cast<const uint2*>(idx);
+  const int qz = z4 >> 2;
+  int q = (a4 >> 2) + sub;
+  auto add4 = [&](uint2 w) {
+    s0 += vec[w.x & 0xffffu];
+    s1 += vec[w.x >> 16];
+    s0 += vec[w.y & 0xffffu];
+    s1 += vec[w.y >> 16];
+  };
+  for (; q + (B - 1) * G < qz; q += B * G) {
+    uint2 w[B];
 #pragma unroll
-    for (int u = 0; u < B; ++u) i[u] = idx[k + u * G];
+    for (int u = 0; u < B; ++u) w[u] = p[q + u * G];
 #pragma unroll
-    for (int u = 0; u < B; u += 2) {
-      s0 += vec[i[u] - shift];
-      s1 += vec[i[u + 1] - shift];
-    }
+    for (int u = 0; u < B; ++u) add4(w[u]);
   }
-  if (k < z) {   // the rest: fewer than 16 entries, loads issued together
-    int i[B];
+  if (q < qz) {   // the rest: fewer than 16 groups, loads issued together
+    uint2 w[B];
 #pragma unroll
-    for (int u = 0; u < B; ++u) i[u] = (k + u * G < z) ? (int)idx[k + u * G] : -1;
+    for (int u = 0; u < B; ++u) w[u] = (q + u * G < qz) ? p[q + u * G] : make_uint2(0xffffffffu, 0xffffffffu);
 #pragma unroll
     for (int u = 0; u < B; ++u)
-      if (i[u] >= 0) s0 += vec[i[u] - shift];
+      if (w[u].x != 0xffffffffu) add4(w[u]);
   }
+  for (int k = a + sub; k < a4; k += G) s0 += vec[idx[k]];
+  for (int k = z4 + sub; k < z; k += G) s1 += vec[idx[k]];
   return s0 + s1;
 }
 
@@ -90,7 +102,7 @@ __device__ inline void chunk_rows(const BatchProb& P, BatchLds& L, int r0, int r
   for (int base = 0; base < n; base += per) {   // the same trip count in every lane
     const int i = r0 + base + tid / G;
     double s = 0.0;
-    if (i < r1) s = lane_gather<G>(P.ci, L.V, P.rp[i], P.rp[i + 1], sub, 0);
+    if (i < r1) s = lane_gather<G>(P.ci, L.V, P.rp[i], P.rp[i + 1], sub);
     s = group_sum<G>(s);
     if (i < r1 && sub == 0) L.U[i - r0] = s;
   }
@@ -108,7 +120,7 @@ __device__ inline void chunk_cols(const BatchProb& P, const BatchLds& L, int h, 
     const int j = base + tid / G;
     double s = 0.0;
     if (j < c1)
-      s = lane_gather<G>(P.ri, L.U, P.csplit[(size_t)h * F + j], P.csplit[(size_t)(h + 1) * F + j], sub, 0);
+      s = lane_gather<G>(P.ri, L.U, P.csplit[(size_t)h * F + j], P.csplit[(size_t)(h + 1) * F + j], sub);
     s = group_sum<G>(s);
     if (j < c1 && sub == 0) t[j] = (h == 0 ? 0.0 : t[j]) + s;
   }
@@ -517,6 +529,8 @@ rr_status build_batch_plan(BatchPlan& bp, const Sparse& X, hipStream_t s, int au
   RR_HIP(dmalloc(&bp.csplit, sizeof(int) * cs.size()));
   RR_HIP(dmalloc(&bp.ci16, sizeof(uint16_t) * nz));
   RR_HIP(dmalloc(&bp.ri16, sizeof(uint16_t) * nz));
+  if ((reinterpret_cast<uintptr_t>(bp.ci16) | reinterpret_cast<uintptr_t>(bp.ri16)) % 8)
+    return fail(RR_ERR_DEVICE, "internal: index copies not 8-byte aligned");
   RR_HIP(hipMemcpyAsync(bp.csplit, cs.data(), sizeof(int) * cs.size(), hipMemcpyHostToDevice, s));
   RR_HIP(hipMemcpyAsync(bp.ci16, c16.data(), sizeof(uint16_t) * nz, hipMemcpyHostToDevice, s));
   RR_HIP(hipMemcpyAsync(bp.ri16, r16.data(), sizeof(uint16_t) * nz, hipMemcpyHostToDevice, s));
