@@ -613,22 +613,24 @@ def test_vcycle_restriction_from_the_row_pass(rr):
     """The V(1,1) cycle's restriction P^T (r - A e1), formed without the
     fine-level residual as P^T (r - lam e1) - (X P)^T (X e1): a cluster of
     14 dense features (hundreds of X P column-pass pieces, summed by piece
-    items), a cluster of 2000 members (finished from chunk sums) and 20 small
-    clusters.  B r and the converged solve against the oracle."""
+    items), a cluster of 2000 members (finished from chunk sums), 20 small
+    clusters and one whose five features have no entries.  B r and the
+    converged solve against the oracle."""
     import scipy.sparse as sp
     rng = np.random.default_rng(61)
     N, F, nd = 40_000, 3000, 14
     rd, cd = np.nonzero(rng.random((N, nd)) < 0.9)
     rs = np.repeat(np.arange(N), 10)
-    cs = rng.integers(nd, F, size=rs.size)
+    cs = rng.integers(nd, F - 5, size=rs.size)
     X = sp.csr_matrix((np.ones(rd.size + rs.size), (np.r_[rd, rs], np.r_[cd, cs])), shape=(N, F))
     X.sum_duplicates()
     X.data[:] = 1.0
     lab = np.empty(F, dtype=np.int64)
     lab[:12] = 0
     lab[12:2012] = 1
-    lab[2012:] = 2 + np.arange(F - 2012) % 20
-    fc = 22
+    lab[2012:F - 5] = 2 + np.arange(F - 5 - 2012) % 20
+    lab[F - 5:] = 22
+    fc = 23
     print(f"[xp restriction] N={N} F={F} nnz={X.nnz}", flush=True)
     lam = 1.0
     R = rr.Ridge(X, labels=lab)
