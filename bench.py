@@ -311,6 +311,44 @@ def newton_section(rr, torch, dev, log, P, k, steps=5, beta=1.0):
     return {"steps": rows, "beta": beta, "tol": 1e-8}
 
 
+def tiny_section(rr, torch, dev, log, reps=20):
+    """The tiny plain-method workload (2000 x 500 binary, 2 % density,
+    Zipf(1.1) columns, lambda = 1, k-means k = 50): unpreconditioned CG
+    against Jacobi PCG and the two-level forms, each to relative residual
+    1e-10; iterations, time per solve (mean of `reps`, after one warm-up)
+    and the relative error against a dense Cholesky solve of the normal
+    equations (NumPy, FP64)."""
+    import numpy as np
+    import datagen
+    P = datagen.tiny_sparse()
+    lam = 1.0
+    Xd = P.X.toarray()
+    A = Xd.T @ Xd + lam * np.eye(Xd.shape[1])
+    L = np.linalg.cholesky(A)
+    wx = np.linalg.solve(L.T, np.linalg.solve(L, Xd.T @ P.y))
+    R = rr.Ridge(P.X, n_clusters=50, seed=5826)
+    y = torch.as_tensor(P.y, dtype=torch.float64, device=dev)
+    w = torch.empty(P.X.shape[1], dtype=torch.float64, device=dev)
+    out = {"workload": "binary 2000x500, 10 nnz/row, Zipf(1.1) columns, lambda=1, k-means k=50, "
+                       "stop at relative residual 1e-10",
+           "n_coarse": R.info["n_coarse"], "forms": {}}
+    for kind in ("none", "jacobi", "vcycle", "additive"):
+        rr.rr_solve(R.h, lam, y, w, tol=1e-10, max_iter=5000, precond=kind, raise_on=(1, 2, 6))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st, inf = rr.rr_solve(R.h, lam, y, w, tol=1e-10, max_iter=5000, precond=kind,
+                                  raise_on=(1, 2, 6))
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        err = float(np.linalg.norm(w.cpu().numpy() - wx) / np.linalg.norm(wx))
+        out["forms"][kind] = {"iters": inf["iters"], "ms": ms, "err": err,
+                              "true_relres": inf["true_relres"]}
+        log(f"[bench tiny] {kind}: {inf['iters']} iterations, {ms:.3f} ms, rel. error {err:.2e}")
+    R.close()
+    return out
+
+
 def leader_section(rr, torch, dev, log, P, R, tol=24.0):
     """Leader-follower aggregation (the paper's experiments' clustering) on
     the 200,000 x 100,000 workload at distance tolerance `tol`, against the
@@ -514,6 +552,8 @@ def main():
                     help="skip the dense many-rhs and batched uneven-problem sections")
     ap.add_argument("--dense-only", action="store_true",
                     help="run only the dense many-rhs section and print its JSON")
+    ap.add_argument("--tiny-only", action="store_true",
+                    help="run only the tiny plain-method section (CG against the two-level forms)")
     ap.add_argument("--operator-only", action="store_true",
                     help="run only the timed step at C2, the operator's timing and the FP64-valued "
                          "operator, and print their JSON (for profiler and counter runs)")
@@ -537,6 +577,9 @@ def main():
 
     if args.dense_only:
         print(json.dumps({"dense_many_rhs": dense_section(rr, torch, dev, log)}), flush=True)
+        return
+    if args.tiny_only:
+        print(json.dumps({"tiny_plain": tiny_section(rr, torch, dev, log)}), flush=True)
         return
     if args.batched_only:
         print(json.dumps({"batched_uneven": batched_uneven_section(rr, torch, dev, log,
@@ -839,6 +882,7 @@ def main():
     bayes = None if args.no_dense else bayes_section(rr, torch, dev, log, P, R, args.k)
     newton = None if args.no_dense else newton_section(rr, torch, dev, log, P, args.k)
     lf = None if args.no_dense else leader_section(rr, torch, dev, log, P, R)
+    tiny = None if args.no_dense else tiny_section(rr, torch, dev, log)
     dense = None if args.no_dense else dense_section(rr, torch, dev, log)
     uneven = None if args.no_dense else batched_uneven_section(rr, torch, dev, log,
                                                                full=not args.batched_small)
@@ -890,6 +934,7 @@ def main():
         "bayes_noise_injection": bayes,
         "newton_logistic": newton,
         "leader_follower": lf,
+        "tiny_plain": tiny,
         "operator_valued_f64": valued,
         "roofline": {"bound": "hbm", "achieved": gbs_op, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs_op / HBM_PEAK_GBS, "traffic": measured_traffic(),
