@@ -236,3 +236,47 @@ def test_fullsize_fp32_cycle(rr, big, solver_random_labels, lam):
           f"(FP64 cycle: {i64['iters']} iterations, error {err64:.2e})", flush=True)
     assert info["status"] == 0 and i64["status"] == 0
     assert err <= 1e-10 and err64 <= 1e-10
+
+
+def test_fullsize_leader_follower_rule(rr, big):
+    """Leader-follower clustering at the benchmark's tolerance (24): the
+    oracle's dense Gram matrix does not fit at this size, so the rule is
+    checked where it is defined, with exact integer distances: leaders are
+    created in feature order and each is at least the tolerance away from
+    every earlier leader; a follower joins the nearest earlier leader (the
+    first of equal ones), strictly inside the tolerance.  Checked on the
+    first 64 features, 256 drawn ones and 64 drawn leaders; then the V(1,1)
+    solve on this aggregation equals the oracle's at its converged count."""
+    tol = 24.0
+    R = rr.Ridge(big.X, lf_tolerance=tol)
+    fc = R.info["n_coarse"]
+    lab = host(R.labels()).astype(np.int64)
+    lead = host(R.centres())[:fc].astype(np.int64)
+    print(f"[fullsize] leader-follower tol {tol}: F_C {fc}", flush=True)
+    F = big.X.shape[1]
+    assert np.all(np.diff(lead) > 0) and lead[0] == 0
+    assert np.array_equal(lab[lead], np.arange(fc)) and lab.min() >= 0 and lab.max() < fc
+    Xc = sp.csc_matrix(big.X, dtype=np.int64)
+    c = np.asarray(Xc.sum(axis=0)).ravel()
+    rng = np.random.default_rng(17)
+    sample = np.unique(np.r_[np.arange(64), rng.choice(F, 256, replace=False), rng.choice(lead, 64)])
+    G = (Xc[:, sample].T @ Xc[:, lead]).toarray()   # exact integer inner products
+    for row, j in enumerate(sample):
+        k = int(np.searchsorted(lead, j))            # leaders created before j: lead[:k]
+        d2 = c[j] + c[lead[:k]] - 2 * G[row, :k]
+        if k < fc and lead[k] == j:                  # j leads cluster k
+            assert k == 0 or d2.min() >= tol * tol, (j, k)
+        else:
+            s = int(np.argmin(d2))
+            assert lab[j] == s and d2[s] < tol * tol, (j, lab[j], s)
+    lam = 1.0
+    omega = op.omega_gershgorin(big.X, lam)
+    tl = precond.TwoLevel(big.X, lam, lab, fc, omega)
+    A = lambda v: op.apply_A(big.X, lam, v)
+    x_t, inf_t = krylov.pcg(A, op.rhs(big.X, big.y), tl.vcycle, tol=1e-13, max_iter=2000)
+    assert inf_t.status == krylov.OK
+    w, info = R.solve(lam, big.y, precond="vcycle", fixed_iters=inf_t.iters)
+    err = np.linalg.norm(host(w) - x_t) / np.linalg.norm(x_t)
+    print(f"[fullsize] leader-follower solve: {inf_t.iters} iterations, error {err:.1e}", flush=True)
+    assert err <= 1e-10
+    R.close()
