@@ -280,3 +280,39 @@ def test_fullsize_leader_follower_rule(rr, big):
     print(f"[fullsize] leader-follower solve: {inf_t.iters} iterations, error {err:.1e}", flush=True)
     assert err <= 1e-10
     R.close()
+
+
+def test_fullsize_least_squares_interpolation(rr, big):
+    """Least-squares interpolation on the leader-follower aggregation at the
+    benchmark's tolerance, from 8 seeded prototype vectors: the weights p
+    against the oracle's at every feature, the coarse Gram matrix
+    P^T X^T X P against its definition (sparse products, exact for the
+    pattern, FP64 for the weights), and a solve on it to relative residual
+    1e-10 whose true residual the oracle's operator confirms."""
+    from oracle import interp
+    R = rr.Ridge(big.X, lf_tolerance=24.0, lambda_slots=2)
+    fc = R.info["n_coarse"]
+    lab = host(R.labels()).astype(np.int64)
+    F = big.X.shape[1]
+    V = np.random.default_rng(23).standard_normal((F, 8))
+    beta = 1.0
+    eta = interp.prototype_energies(big.X, V, beta)
+    p_or = interp.ls_weights(V, eta, lab, fc, interp.representatives(lab, fc))
+    p = host(R.set_interpolation(V, beta))
+    err_p = np.max(np.abs(p - p_or)) / np.max(np.abs(p_or))
+    print(f"[fullsize] least-squares weights: F_C {fc}, max error {err_p:.1e}", flush=True)
+    assert np.allclose(p, p_or, rtol=1e-10, atol=1e-12 * np.abs(p_or).max())
+    Pm = interp.ls_prolongation(lab, fc, p_or)
+    Xs = sp.csr_matrix(big.X, dtype=np.float64) @ Pm
+    Kref = (Xs.T @ Xs).toarray()
+    K = host(R.coarse_gram()).reshape(fc, fc)
+    assert np.allclose(K, Kref, rtol=1e-10, atol=1e-11 * np.abs(Kref).max())
+    lam = 1.0
+    w, info = R.solve(lam, big.y, precond="vcycle", tol=1e-10, max_iter=2000)
+    b = op.rhs(big.X, big.y)
+    wh = host(w)
+    rel = np.linalg.norm(b - op.apply_A(big.X, lam, wh)) / np.linalg.norm(b)
+    print(f"[fullsize] least-squares V(1,1): {info['iters']} iterations, true residual {rel:.1e}",
+          flush=True)
+    assert info["status"] == 0 and rel <= 2e-10
+    R.close()
