@@ -107,7 +107,7 @@ rr_status ws_status(const rr_handle* h, rr_status st) {
 
 void free_work(Work& w) {
   dfree(w.x); dfree(w.r); dfree(w.p); dfree(w.q); dfree(w.z); dfree(w.e1); dfree(w.e2);
-  dfree(w.rho); dfree(w.b); dfree(w.u); dfree(w.c); dfree(w.yc); dfree(w.partials);
+  dfree(w.rho); dfree(w.b); dfree(w.u); dfree(w.up); dfree(w.c); dfree(w.yc); dfree(w.partials);
   dfree(w.parts.dots);
   dfree(w.sc); dfree(w.D); dfree(w.vin); dfree(w.vout); dfree(w.xref);
   dfree(w.fcg_p); dfree(w.fcg_ap); dfree(w.fcg_paps);
@@ -134,7 +134,7 @@ rr_status alloc_work(Work& w, int F, int N, int FC, int np) {
   RR_TRY(dalloc(&w.x, F)); RR_TRY(dalloc(&w.r, F)); RR_TRY(dalloc(&w.p, F));
   RR_TRY(dalloc(&w.q, F)); RR_TRY(dalloc(&w.z, F)); RR_TRY(dalloc(&w.e1, F));
   RR_TRY(dalloc(&w.e2, F)); RR_TRY(dalloc(&w.rho, F)); RR_TRY(dalloc(&w.b, F));
-  RR_TRY(dalloc(&w.D, F)); RR_TRY(dalloc(&w.u, N));
+  RR_TRY(dalloc(&w.D, F)); RR_TRY(dalloc(&w.u, N)); RR_TRY(dalloc(&w.up, N));
   RR_TRY(dalloc(&w.vin, F)); RR_TRY(dalloc(&w.vout, F)); RR_TRY(dalloc(&w.xref, F));
   RR_TRY(dalloc(&w.sc, 1));
   RR_HIP(hipHostMalloc((void**)&w.sc_host, sizeof(Scalars), hipHostMallocDefault));
@@ -618,17 +618,26 @@ rr_status prof_pair(rr_handle* h, Prof& pf, int* idx) {
 }
 
 // Apply the operator pieces with optional event timing.
+// With pu, v holds z and the pass forms w.up = X z + beta w.up, X p of the
+// new direction (the column pass after it reads w.up and uses
+// EPI_APPLY_DOT_P).
 rr_status op_csr(rr_handle* h, Work& w, Prof& pf, int tag, const double* v, hipStream_t s,
-                 const StageArgs* stage = nullptr) {
+                 const StageArgs* stage = nullptr, const PUpd* pu = nullptr) {
   const int* done = &w.sc->done;
   if (!pf.on) {
-    launch_csr(w.X, v, w.u, done, s, stage);
+    if (pu)
+      launch_csr_pupd(w.X, v, w.up, done, s, *pu);
+    else
+      launch_csr(w.X, v, w.u, done, s, stage);
     return RR_OK;
   }
   int i;
   RR_TRY(prof_pair(h, pf, &i));
   RR_HIP(hipEventRecord(h->ev_pool[3 * i], s));
-  launch_csr(w.X, v, w.u, done, s, stage, h->ev_pool[3 * i + 1]);
+  if (pu)
+    launch_csr_pupd(w.X, v, w.up, done, s, *pu, h->ev_pool[3 * i + 1]);
+  else
+    launch_csr(w.X, v, w.u, done, s, stage, h->ev_pool[3 * i + 1]);
   RR_HIP(hipEventRecord(h->ev_pool[3 * i + 2], s));
   pf.csr.push_back({i, tag});
   return RR_OK;
@@ -636,17 +645,18 @@ rr_status op_csr(rr_handle* h, Work& w, Prof& pf, int tag, const double* v, hipS
 
 // *nparts receives the count of block partials a dot-product epilogue left.
 rr_status op_csc(rr_handle* h, Work& w, Prof& pf, int tag, int mode, const Epi& e, hipStream_t s,
-                 int* nparts = nullptr) {
+                 int* nparts = nullptr, const double* uin = nullptr) {
   const int* done = &w.sc->done;
+  const double* u = uin ? uin : w.u;
   if (!pf.on) {
-    const int n = launch_csc(w.X, w.u, mode, e, done, s);
+    const int n = launch_csc(w.X, u, mode, e, done, s);
     if (nparts) *nparts = n;
     return RR_OK;
   }
   int i;
   RR_TRY(prof_pair(h, pf, &i));
   RR_HIP(hipEventRecord(h->ev_pool[3 * i], s));
-  const int n = launch_csc(w.X, w.u, mode, e, done, s, h->ev_pool[3 * i + 1]);
+  const int n = launch_csc(w.X, u, mode, e, done, s, h->ev_pool[3 * i + 1]);
   if (nparts) *nparts = n;
   RR_HIP(hipEventRecord(h->ev_pool[3 * i + 2], s));
   pf.csc.push_back({i, tag});
@@ -834,6 +844,13 @@ struct Solve {
   int fallback_iter = -1;
   int fcg_base = 0;
   bool skip_check = false;   // no update since the last convergence check
+  // PCG with a two-level preconditioner: the direction update p = z + beta p
+  // is left to the next iteration (pu_pending): its row pass forms
+  // X p = X z + beta X p from the previous direction's X p, and its column
+  // reduction writes p; beta's partials are the preconditioner's <r,z>
+  // partials (pu_n of them)
+  bool pu_fold = false, pu_pending = false;
+  int pu_n = 0;
   // precision RR_PREC_F32_CYCLE: the preconditioner's cycle runs in FP32
   bool cycle32 = false;
   // continuation of a PCG solve left by the persistent kernel: the work set
@@ -1007,7 +1024,15 @@ rr_status Solve::begin() {
   } else if (two_level) {
     int nrz = 0;
     RR_TRY(precond_two_level(h, w, pf, -1, kind, lam, omega, *sl, w.r, w.z, nullptr, &nrz, s));
-    launch_pupdate(F, w.p, w.z, w.sc, w.parts.rz, nrz, 1, nullptr, s);
+    // the first direction p = z: sc->rz is still 0, so the folded update
+    // takes beta = 0
+    pu_fold = csr_pupd_ok(w.X);
+    if (pu_fold) {
+      pu_pending = true;
+      pu_n = nrz;
+    } else {
+      launch_pupdate(F, w.p, w.z, w.sc, w.parts.rz, nrz, 1, nullptr, s);
+    }
   } else {
     launch_pupdate(F, w.p, w.z, w.sc, w.parts.init + 2 * nv, nv, 1, nullptr, s);
   }
@@ -1065,7 +1090,7 @@ rr_status Solve::queue_chunk() {
     // changing state lives in device memory): capture them once per
     // signature, then replay
     GraphKey key{kind, lam, omega, sl ? sl->Ainv : nullptr, xref, op.residual_history, chunk,
-                 (sl && w.block) ? sl->Dinv : nullptr, cycle32};
+                 (sl && w.block) ? sl->Dinv : nullptr, cycle32, pu_fold ? pu_n : -1};
     // the legacy default stream cannot be captured: use the set's own
     // stream, ordered after and before the caller's with events
     hipStream_t gs = s;
@@ -1110,13 +1135,22 @@ rr_status Solve::queue_chunk() {
 
 rr_status Solve::queue_chunk_eager(Work& w, int F) {
   for (int c = 0; c < chunk; ++c, ++queued) {
-    RR_TRY(op_csr(h, w, pf, queued, w.p, s));
     Epi e = base_epi(w, lam);
     e.p = w.p;
     e.out = w.q;
     e.partials = w.parts.pq;
     int npq = 0;
-    RR_TRY(op_csc(h, w, pf, queued, EPI_APPLY_DOT, e, s, &npq));
+    if (pu_pending) {   // X p = X z + beta X p, then p = z + beta p in the reduction
+      const PUpd pu{w.parts.rz, pu_n, w.sc};
+      RR_TRY(op_csr(h, w, pf, queued, w.z, s, nullptr, &pu));
+      e.r = w.z;
+      e.pnew = w.p;
+      RR_TRY(op_csc(h, w, pf, queued, EPI_APPLY_DOT_P, e, s, &npq, w.up));
+      pu_pending = false;
+    } else {
+      RR_TRY(op_csr(h, w, pf, queued, w.p, s));
+      RR_TRY(op_csc(h, w, pf, queued, EPI_APPLY_DOT, e, s, &npq));
+    }
     launch_pcg_update(F, w.x, w.r, w.p, w.q, w.z, w.e1, w.D, xref, omega, kind, w.sc,
                       w.parts.pq, npq, w.parts.upd, s);
     if (two_level) {
@@ -1126,7 +1160,12 @@ rr_status Solve::queue_chunk_eager(Work& w, int F) {
         sp = snap + (size_t)(snap_queued++) * h->FC;
       RR_TRY(precond_two_level(h, w, pf, 100000000 + queued, kind, lam, omega, *sl, w.r, w.z,
                                &stage, &nrz, s, sp));
-      launch_pupdate(F, w.p, w.z, w.sc, w.parts.rz, nrz, 0, nullptr, s);
+      if (pu_fold) {
+        pu_pending = true;
+        pu_n = nrz;
+      } else {
+        launch_pupdate(F, w.p, w.z, w.sc, w.parts.rz, nrz, 0, nullptr, s);
+      }
     } else {
       launch_pupdate(F, w.p, w.z, w.sc, nullptr, 0, 0, &stage, s);
     }

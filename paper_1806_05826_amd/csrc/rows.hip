@@ -35,13 +35,21 @@ namespace rr {
 constexpr int kHotBatch = 8;    // 8-byte hot index loads (4 entries each) per batch
 constexpr int kColdBatch = 2;   // 16-byte cold index loads (4 entries each) per batch
 
-template <typename T, int L>
+// PU (FP64 only): v holds z and u holds X p of the previous direction; the
+// pass writes u = X z + beta u, the new direction's X p, with the PCG
+// update's beta = <r,z>_new / sc->rz (0 while sc->rz is 0: the first
+// direction; u is then not read), <r,z>_new the sum of pu.parts[0, pu.n).
+// Every workgroup adds the partials itself while its slice copy is in
+// flight; workgroup 0 stores beta and <r,z>_new, and a non-finite or
+// non-positive <r,z>_new ends the solve as a breakdown.
+template <typename T, int L, bool PU = false>
 __global__ __launch_bounds__(kSliceBlock) void k_rows(int nlayer, int N, const int4* __restrict__ lay,
                                                       const uint16_t* __restrict__ hidx,
                                                       const int* __restrict__ cidx,
                                                       const T* __restrict__ v, int F, T* __restrict__ u,
                                                       const double* __restrict__ scale, const int* done,
-                                                      StageArgs stage) {
+                                                      StageArgs stage, PUpd pu = PUpd{}) {
+  static_assert(!PU || sizeof(T) == 8, "the folded direction update is FP64");
   if (is_done(done)) return;
   __shared__ __align__(16) T vs[kSliceRows + 1];
   constexpr unsigned kPad = (unsigned)kSliceRows | ((unsigned)kSliceRows << 16);
@@ -64,6 +72,25 @@ __global__ __launch_bounds__(kSliceBlock) void k_rows(int nlayer, int N, const i
   bool have = c < nlayer;
   if (have) load_first();   // in flight during the slice copy
   fill_slice(vs, v, min(kSliceRows, F));
+  T beta = T(0);
+  if constexpr (PU) {   // beta under the slice copy
+    __shared__ double red_p[kSliceWaves];
+    const double rz_new = sum_parts<kSliceBlock>(pu.parts, pu.n, red_p);
+    if (!finite_pos(rz_new)) {   // the same value in every thread of every workgroup
+      if (is_block0_lead()) {
+        pu.sc->status = RR_ERR_BREAKDOWN;
+        pu.sc->done = 1;
+      }
+      __builtin_amdgcn_s_waitcnt(0);   // the slice copy lands before the workgroup ends
+      return;
+    }
+    const double rz_old = pu.sc->rz;
+    beta = rz_old == 0.0 ? 0.0 : rz_new / rz_old;
+    if (is_block0_lead()) {
+      pu.sc->rz_next = rz_new;
+      pu.sc->beta = beta;
+    }
+  }
   if (stage.sc) {   // convergence check of the preceding x/r update, under the slice copy
     __shared__ double red_s[kSliceWaves];
     double rz_unused;
@@ -127,7 +154,13 @@ __global__ __launch_bounds__(kSliceBlock) void k_rows(int nlayer, int N, const i
     if constexpr (L >= 8) sum += __shfl_xor(sum, 4, 64);
     if constexpr (L >= 16) sum += __shfl_xor(sum, 8, 64);
     const int row = c * (64 / L) + lane / L;
-    if ((lane & (L - 1)) == 0 && row < N) u[row] = scale ? (T)((double)sum * scale[row]) : sum;
+    if ((lane & (L - 1)) == 0 && row < N) {
+      T o = scale ? (T)((double)sum * scale[row]) : sum;
+      if constexpr (PU) {
+        if (beta != T(0)) o += beta * u[row];
+      }
+      u[row] = o;
+    }
   }
 }
 
@@ -273,6 +306,24 @@ void launch_rows(const RowPlan& rp, const double* v, double* u, const double* sc
     rows_dispatch<double>(rp, v, u, scale, done, s, st);
   else if (stage)
     launch_stage_update(*stage, s);
+}
+
+template <int L>
+static void rows_pu_launch(const RowPlan& rp, const double* z, double* up, const double* scale, const int* done,
+                           hipStream_t s, const PUpd& pu) {
+  k_rows<double, L, true><<<rp.nblk, kSliceBlock, 0, s>>>(rp.nlayer, rp.N, rp.layer, rp.hidx, rp.cidx, z, rp.F,
+                                                          up, scale, done, StageArgs{}, pu);
+}
+
+void launch_rows_pupd(const RowPlan& rp, const double* z, double* up, const double* scale, const int* done,
+                      hipStream_t s, const PUpd& pu) {
+  switch (rp.L) {
+    case 1: rows_pu_launch<1>(rp, z, up, scale, done, s, pu); break;
+    case 2: rows_pu_launch<2>(rp, z, up, scale, done, s, pu); break;
+    case 4: rows_pu_launch<4>(rp, z, up, scale, done, s, pu); break;
+    case 8: rows_pu_launch<8>(rp, z, up, scale, done, s, pu); break;
+    default: rows_pu_launch<16>(rp, z, up, scale, done, s, pu); break;
+  }
 }
 
 void launch_rows32(const RowPlan& rp, const float* v, float* u, const int* done, hipStream_t s,

@@ -136,6 +136,12 @@ __device__ inline void seg_finish(int s, double t, const Epi& e, double& dot) {
     const double q = t + e.lam * ps;
     e.out[s] = q;
     dot += ps * q;
+  } else if constexpr (MODE == EPI_APPLY_DOT_P) {
+    const double ps = e.r[s] + e.sc->beta * e.p[s];
+    e.pnew[s] = ps;
+    const double q = t + e.lam * ps;
+    e.out[s] = q;
+    dot += ps * q;
   } else if constexpr (MODE == EPI_RESID) {
     e.out[e.opos ? e.opos[s] : s] = e.r[s] - (t + e.lam * e.p[s]);
   } else if constexpr (MODE == EPI_POST) {
@@ -164,7 +170,8 @@ __device__ inline void seg_finish(int s, double t, const Epi& e, double& dot) {
 
 template <int MODE>
 constexpr bool has_dot() {
-  return MODE == EPI_APPLY_DOT || MODE == EPI_POST || MODE == EPI_POST_P || MODE == EPI_TRUE;
+  return MODE == EPI_APPLY_DOT || MODE == EPI_APPLY_DOT_P || MODE == EPI_POST || MODE == EPI_POST_P ||
+         MODE == EPI_TRUE;
 }
 
 // The epilogue's dot product leaves one partial per block (consumed by the

@@ -97,6 +97,17 @@ struct StageArgs {
   int kind;
 };
 
+// The PCG direction update p = z + beta p folded into the next iteration:
+// beta = <r,z>_new / sc->rz (0 while sc->rz is 0: the first direction), with
+// <r,z>_new the sum of parts[0, n).  The row pass forms X p = X z + beta X p
+// (launch_rows_pupd, X p of the previous direction kept in its output), and
+// the column reduction that follows (EPI_APPLY_DOT_P) writes p itself.
+struct PUpd {
+  const double* parts;
+  int n;
+  Scalars* sc;
+};
+
 // Window of previous directions of flexible CG (oldest first).
 constexpr int kMaxFcg = 16;
 // Internal status of a learned-correction solve whose flexible-CG step met a
@@ -120,7 +131,8 @@ enum EpiMode {
   EPI_POST = 4,       // rho = r - (t + lam e2); z = e2 + w rho / D; <r,z> -> beta
   EPI_TRUE = 5,       // res = r - (t + lam x); <res,res> -> true_rr
   EPI_SCALE = 6,      // out[s] = t * scale[s]
-  EPI_POST_P = 7      // EPI_POST with e2 = e1 + P yc formed in place (p = e1)
+  EPI_POST_P = 7,     // EPI_POST with e2 = e1 + P yc formed in place (p = e1)
+  EPI_APPLY_DOT_P = 8 // p = z + beta p (z in r, beta in sc, written to pnew), then EPI_APPLY_DOT
 };
 
 struct Epi {
@@ -144,6 +156,7 @@ struct Epi {
   const int* xbase;
   const int* xpos;
   const double* xpart;
+  double* pnew;          // EPI_APPLY_DOT_P: where the updated direction goes (p itself)
 };
 
 // Single-precision vectors of an inner solve of iterative refinement.
@@ -332,10 +345,11 @@ struct GraphKey {
   int chunk = 0;
   const double* dinv = nullptr;   // block smoother's inverses (null: point smoother)
   bool cycle32 = false;           // the preconditioner's cycle in FP32
+  int pu_n = -1;                  // direction update folded into the next iteration: its partials
   bool operator==(const GraphKey& o) const {
     return kind == o.kind && lam == o.lam && omega == o.omega && ainv == o.ainv &&
            xref == o.xref && history == o.history && chunk == o.chunk && dinv == o.dinv &&
-           cycle32 == o.cycle32;
+           cycle32 == o.cycle32 && pu_n == o.pu_n;
   }
 };
 struct ChunkGraph {
@@ -358,6 +372,7 @@ struct Work {
   double *D = nullptr;            // Jacobi diagonal at the current lambda
   double *vin = nullptr, *vout = nullptr, *xref = nullptr;  // boundary permutation buffers
   double *u = nullptr;            // [N]
+  double *up = nullptr;           // [N] X p of the current direction (folded direction update)
   double *c = nullptr, *yc = nullptr;   // [FC]
   double *partials = nullptr;     // reduction partials
   int npartials = 0;
@@ -539,6 +554,12 @@ void free_merge_plan(MergePlan& mp);
 // (before its segment reduction); elsewhere after the whole pass.
 void launch_csr(const Sparse& X, const double* v, double* u, const int* done, hipStream_t s,
                 const StageArgs* stage = nullptr, hipEvent_t mid = nullptr);
+// up = X z + beta up (with row weights D: D X z + beta up), beta formed from
+// pu as the PCG direction update takes it: X p of the new direction from X p
+// of the previous one (0/1 X with the row-pass plan only: csr_pupd_ok).
+bool csr_pupd_ok(const Sparse& X);
+void launch_csr_pupd(const Sparse& X, const double* z, double* up, const int* done, hipStream_t s,
+                     const PUpd& pu, hipEvent_t mid = nullptr);
 // Column-segment reduction t_s = sum_e v[idx[e]] (* val[e]) with epilogue `mode`.
 // Epilogues with a dot product leave block partials in e.partials; the
 // return value is their count (0 for the other modes).
@@ -572,6 +593,8 @@ rr_status build_xp_plan(SellPlan& xp, const std::vector<int>& rp, const std::vec
                         const std::vector<int>& lab, int N, int FC, int num_cu, int div, hipStream_t s);
 void launch_rows(const RowPlan& rp, const double* v, double* u, const double* scale, const int* done,
                  hipStream_t s, const StageArgs* stage = nullptr);
+void launch_rows_pupd(const RowPlan& rp, const double* z, double* up, const double* scale, const int* done,
+                      hipStream_t s, const PUpd& pu);
 void launch_rows32(const RowPlan& rp, const float* v, float* u, const int* done, hipStream_t s,
                    const StageArgs* stage = nullptr);
 void free_rows(RowPlan& rp);

@@ -538,13 +538,16 @@ int launch_sell(const SellPlan& sp, const double* v, int mode, const Epi& e, con
     case EPI_STORE: sell_reduce_mode<EPI_STORE>(sp, e, done, s); break;
     case EPI_APPLY: sell_reduce_mode<EPI_APPLY>(sp, e, done, s); break;
     case EPI_APPLY_DOT: sell_reduce_mode<EPI_APPLY_DOT>(sp, e, done, s); break;
+    case EPI_APPLY_DOT_P: sell_reduce_mode<EPI_APPLY_DOT_P>(sp, e, done, s); break;
     case EPI_RESID: sell_reduce_mode<EPI_RESID>(sp, e, done, s); break;
     case EPI_POST: sell_reduce_mode<EPI_POST>(sp, e, done, s); break;
     case EPI_POST_P: sell_reduce_mode<EPI_POST_P>(sp, e, done, s); break;
     case EPI_TRUE: sell_reduce_mode<EPI_TRUE>(sp, e, done, s); break;
     case EPI_SCALE: sell_reduce_mode<EPI_SCALE>(sp, e, done, s); break;
   }
-  if (mode != EPI_APPLY_DOT && mode != EPI_POST && mode != EPI_POST_P && mode != EPI_TRUE) return 0;
+  if (mode != EPI_APPLY_DOT && mode != EPI_APPLY_DOT_P && mode != EPI_POST && mode != EPI_POST_P &&
+      mode != EPI_TRUE)
+    return 0;
   return collapse_parts(e.partials, sell_reduce_grid(sp), done, s);
 }
 

@@ -87,6 +87,14 @@ void launch_csr(const Sparse& X, const double* v, double* u, const int* done, hi
   if (mid) (void)hipEventRecord(mid, s);
 }
 
+bool csr_pupd_ok(const Sparse& X) { return X.sliced && X.N > 0 && X.rows.nblk > 0 && !X.rows.hval; }
+
+void launch_csr_pupd(const Sparse& X, const double* z, double* up, const int* done, hipStream_t s,
+                     const PUpd& pu, hipEvent_t mid) {
+  launch_rows_pupd(X.rows, z, up, X.rw, done, s, pu);
+  if (mid) (void)hipEventRecord(mid, s);
+}
+
 // ---------------------------------------------------------------------------
 // Merge-path segmented gather-sum.  The merged list holds, for every
 // segment, its nonzeros followed by an end marker.  Tile b covers merged
