@@ -171,7 +171,8 @@ rr_status build_cluster_rows(rr_handle* h, hipStream_t s) {
   RR_HIP(hipStreamSynchronize(s));
   cr.nlayer = nlayer;
   // the column pass of X P, for the V(1,1) restriction from the row pass
-  if (X.sliced) {
+  // (only where the restriction's finishing step fits the coarse GEMV)
+  if (X.sliced && restrict_gemv_fusable(h->restrict_plan, FC)) {
     RR_TRY(build_xp_plan(h->xp, rp, ci, lab, N, FC, X.num_cu, h->tuning.div_cols, s));
     RR_TRY(build_xp_restrict(h->xp_restrict, h->xp, h->coff, FC, F, s));
   }
