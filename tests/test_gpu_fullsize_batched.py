@@ -72,5 +72,19 @@ def test_fullsize_batched_hybrid(rr):
         print(f"[batched full] problem {j} ({P.X.shape[0]} x {P.X.shape[1]}, {P.X.nnz} nnz, lambda {lam:.2e}, "
               f"{its[j]} its): error {err:.2e}, kappa {kappa:.2e}, residual {rel:.2e}", flush=True)
         assert err <= 1.01 * kappa * rel + 1e-13
+    # the problem with the most iterations once more on its own through
+    # rr_solve, whose PCG folds the direction update into the next
+    # iteration (X p updated recursively over thousands of iterations): its
+    # returned w meets the tolerance on the recomputed residual, in an
+    # iteration count within 2 % of the hybrid form's
+    j = int(np.argmax(its))
+    P, lam = batch[j]
+    w1, i1 = Rs[j].solve(lam, P.y, precond="vcycle", tol=1e-8, max_iter=5000)
+    b = op.rhs(P.X, P.y)
+    rel = np.linalg.norm(b - op.apply_A(P.X, lam, w1.cpu().numpy())) / np.linalg.norm(b)
+    print(f"[batched full] problem {j} alone: {i1['iters']} its (batched {its[j]}), residual {rel:.2e}",
+          flush=True)
+    assert i1["status"] == 0 and rel <= 1.2e-8
+    assert abs(i1["iters"] - its[j]) <= 1 + 0.02 * its[j]
     for R in Rs:
         R.close()
