@@ -620,15 +620,16 @@ rr_status prof_pair(rr_handle* h, Prof& pf, int* idx) {
 // Apply the operator pieces with optional event timing.
 // With pu, v holds z and the pass forms w.up = X z + beta w.up, X p of the
 // new direction (the column pass after it reads w.up and uses
-// EPI_APPLY_DOT_P).
+// EPI_APPLY_DOT_P).  Without, the pass writes uout (w.u by default).
 rr_status op_csr(rr_handle* h, Work& w, Prof& pf, int tag, const double* v, hipStream_t s,
-                 const StageArgs* stage = nullptr, const PUpd* pu = nullptr) {
+                 const StageArgs* stage = nullptr, const PUpd* pu = nullptr, double* uout = nullptr) {
   const int* done = &w.sc->done;
+  double* u = uout ? uout : w.u;
   if (!pf.on) {
     if (pu)
       launch_csr_pupd(w.X, v, w.up, done, s, *pu);
     else
-      launch_csr(w.X, v, w.u, done, s, stage);
+      launch_csr(w.X, v, u, done, s, stage);
     return RR_OK;
   }
   int i;
@@ -637,7 +638,7 @@ rr_status op_csr(rr_handle* h, Work& w, Prof& pf, int tag, const double* v, hipS
   if (pu)
     launch_csr_pupd(w.X, v, w.up, done, s, *pu, h->ev_pool[3 * i + 1]);
   else
-    launch_csr(w.X, v, w.u, done, s, stage, h->ev_pool[3 * i + 1]);
+    launch_csr(w.X, v, u, done, s, stage, h->ev_pool[3 * i + 1]);
   RR_HIP(hipEventRecord(h->ev_pool[3 * i + 2], s));
   pf.csr.push_back({i, tag});
   return RR_OK;
@@ -981,6 +982,10 @@ rr_status Solve::begin() {
     two_level = kind == PK_VCYCLE;
     stage = StageArgs{w.sc, w.parts.upd, w.parts.n_vec, nullptr, kind};
     queued = resume->iter;
+    // p is ready: the first iteration applies A to it and keeps X p, the
+    // later ones fold their direction updates
+    pu_fold = two_level && csr_pupd_ok(w.X);
+    pu_pending = false;
     return RR_OK;
   }
   if (op.rhs_is_b) {
@@ -1085,7 +1090,9 @@ rr_status Solve::queue_chunk() {
     }
     return RR_OK;
   }
-  if (op.graph && !pf.on && !snap) {
+  // (a chunk that begins without a pending folded update, a continued
+  // solve's first, runs eagerly: the captured chunk begins with one)
+  if (op.graph && !pf.on && !snap && (pu_pending || !pu_fold)) {
     // the chunk's launches are the same for every chunk of this solve (all
     // changing state lives in device memory): capture them once per
     // signature, then replay
@@ -1147,6 +1154,9 @@ rr_status Solve::queue_chunk_eager(Work& w, int F) {
       e.pnew = w.p;
       RR_TRY(op_csc(h, w, pf, queued, EPI_APPLY_DOT_P, e, s, &npq, w.up));
       pu_pending = false;
+    } else if (pu_fold) {   // p ready (a continued solve): X p kept for the next direction
+      RR_TRY(op_csr(h, w, pf, queued, w.p, s, nullptr, nullptr, w.up));
+      RR_TRY(op_csc(h, w, pf, queued, EPI_APPLY_DOT, e, s, &npq, w.up));
     } else {
       RR_TRY(op_csr(h, w, pf, queued, w.p, s));
       RR_TRY(op_csc(h, w, pf, queued, EPI_APPLY_DOT, e, s, &npq));
